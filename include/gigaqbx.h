@@ -1,0 +1,181 @@
+/*
+ * gigaqbx.h -- C ABI of the MI355X (gfx950) QBX-coupled FMM for 2-D Laplace layer potentials.
+ *
+ * Method: Wala & Kloeckner, "A Fast Algorithm with Error Bounds for Quadrature by Expansion".
+ * The library evaluates the QBX approximation (Sec. 2.1, eq. (qbx)) of the single-layer potential
+ * (Sec. 1, eq. (slp-definition)) and double-layer potential (eq. (dlp-definition)) at targets that
+ * are associated with QBX expansion centers, accelerated by the GIGAQBX FMM (Sec. 4, Algorithm
+ * Stages 1-8) on a quadtree with target confinement regions and the modified interaction lists
+ * (Sec. 4.3, Definitions 1-9).
+ *
+ * General conventions
+ *   - Every call returns a gq_status; nothing is thrown across the ABI. On failure the context
+ *     keeps a message retrievable with gq_last_error().
+ *   - Points and vectors are (n, 2) row-major interleaved (x, y) FP64 arrays. Complex values are
+ *     (re, im) FP64 pairs.
+ *   - The caller owns every input and output pointer; the library owns its internal workspace
+ *     (device memory it allocates at gq_build and frees at gq_destroy).
+ *   - Potentials include the -1/(2 pi) factor of eqs. (slp-definition)/(dlp-definition).
+ *   - A context is bound to one device and one HIP stream; calls on one context must not overlap.
+ *     Device work is enqueued on the context's stream and is asynchronous unless stated.
+ *   - A context created with device = -1 is host-only: it builds the tree and lists (Stage 1 and
+ *     Sec. 4.3) and exposes them for inspection, but cannot evaluate.
+ */
+#ifndef GIGAQBX_H
+#define GIGAQBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gq_ctx gq_ctx;
+
+typedef enum {
+  GQ_OK = 0,
+  GQ_EINVAL = -1,  /* invalid argument (null pointer, bad size, non-finite coordinate, ...)   */
+  GQ_ENOMEM = -2,  /* host or device allocation failed                                        */
+  GQ_EHIP = -3,    /* a HIP runtime call failed (message names it)                            */
+  GQ_ESTATE = -4,  /* call out of order (evaluate before build, host-only context, ...)       */
+  GQ_EUNSUP = -5   /* valid request this build does not support (order too high, ...)         */
+} gq_status;
+
+/* Layer-potential kinds. GQ_S_MINUS_D evaluates S(dens1) - D(dens2), the left side of Green's
+ * formula used as the accuracy test in Sec. 5.1. */
+enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3 };
+
+/* Where the geometry arrays passed to gq_set_geometry live. */
+enum { GQ_MEM_HOST = 0, GQ_MEM_DEVICE = 1 };
+
+/* Arithmetic of the box expansions (P2M, M2M, M2L, L2L). */
+enum { GQ_FP64 = 0, GQ_MIXED_FP32 = 1 };
+
+typedef struct {
+  int p_qbx;              /* QBX expansion order (Sec. 4.1), 0..GQ_MAX_P_QBX                   */
+  int p_fmm;              /* FMM expansion order (Sec. 4.1), 1..GQ_MAX_P_FMM                   */
+  int n_max;              /* subdivide a box owning more than n_max eligible particles (Stage 1) */
+  int count_mode;         /* 0: sources + eligible centers count towards n_max (Sec. 4.3);
+                             1: sources only                                                    */
+  double t_f;             /* target confinement factor, 0 <= t_f < 1 (Sec. 4.3.1); 0.9 typical  */
+  int w3far_min_sources;  /* Remark 1: a List-3-far box with fewer sources is evaluated directly
+                             through its leaves; 0 disables                                     */
+  int precision;          /* GQ_FP64 or GQ_MIXED_FP32                                           */
+  int max_levels;         /* depth guard for coincident particles (not in the paper); <= 28     */
+} gq_params;
+
+#define GQ_MAX_P_QBX 20
+#define GQ_MAX_P_FMM 63
+
+/* Fill *p with the defaults: p_qbx 12, p_fmm 30, n_max 64, count_mode 0, t_f 0.9,
+ * w3far_min_sources 15, GQ_FP64, max_levels 24. */
+gq_status gq_default_params(gq_params *p);
+
+/* Create a context on HIP device `device` (>= 0) using `hip_stream` (a hipStream_t, may be NULL for
+ * the default stream; borrowed, not owned), or a host-only context with device = -1. */
+gq_status gq_create(gq_ctx **out, int device, void *hip_stream);
+
+/* Release the context and all device workspace. Synchronises the context's stream first. */
+gq_status gq_destroy(gq_ctx *ctx);
+
+/* Replace the stream later calls enqueue on (borrowed). */
+gq_status gq_set_stream(gq_ctx *ctx, void *hip_stream);
+
+/*
+ * Geometry (Sec. 4.2 inputs (a) and (d), Sec. 2.2.2 center placement), copied into the context:
+ *   src_xy  (n_src, 2)  quadrature nodes y_i
+ *   src_nrm (n_src, 2)  unit normals n_i (outward for the sign conventions of eq. (dlp))
+ *   src_w   (n_src)     quadrature weights including the arclength element
+ *   ctr_xy  (n_ctr, 2)  QBX expansion centers, ctr_r (n_ctr) their radii (> 0)
+ *   tgt_xy  (n_tgt, 2)  targets; tgt_ctr (n_tgt, 2) int32 indices of the one or two centers
+ *                       whose expansions are averaged for the target; -1 marks an unused slot.
+ *                       Every target needs at least one center.
+ * mem says whether all pointers are host (GQ_MEM_HOST) or device (GQ_MEM_DEVICE) memory on the
+ * context's device. The call returns after the copy; the arrays may be freed afterwards. It
+ * invalidates any previous build. Non-finite coordinates or radii give GQ_EINVAL.
+ */
+gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src_xy,
+                          const double *src_nrm, const double *src_w, int64_t n_ctr,
+                          const double *ctr_xy, const double *ctr_r, int64_t n_tgt,
+                          const double *tgt_xy, const int32_t *tgt_ctr);
+
+/*
+ * Stage 1 and Sec. 4.3: build the quadtree (root square covering every particle and every whole
+ * QBX disk; a center stays in a box when its disk does not fit the child's target confinement
+ * region), sort particles into tree order, build Lists 1, 2, 3-close/far, 4-close/far, and upload
+ * tree, lists and translation tables to the device. Synchronous. Invalid parameters give
+ * GQ_EINVAL, orders above the compiled maxima GQ_EUNSUP.
+ */
+gq_status gq_build(gq_ctx *ctx, const gq_params *params);
+
+/*
+ * Evaluate, by the GIGAQBX FMM (Algorithm Stages 2-8 plus evaluation of the QBX expansions at
+ * the targets), n_dens independent potentials:
+ *   kind GQ_S:          out[j] = S dens1[j]
+ *   kind GQ_D:          out[j] = D dens1[j]
+ *   kind GQ_S_MINUS_D:  out[j] = S dens1[j] - D dens2[j]
+ * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
+ * caller's source order; out is a device array (n_dens, n_tgt) with row stride ld_out in the
+ * caller's target order. dens2 must be NULL unless kind is GQ_S_MINUS_D. Enqueued on the
+ * context's stream; inputs must stay valid and outputs untouched until the stream passes the
+ * call. Requires a successful gq_build on a device context (else GQ_ESTATE).
+ */
+gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                  const double *dens2, int64_t ld2, double *out, int64_t ld_out);
+
+/*
+ * Same contract as gq_eval, computed by unaccelerated QBX on the GPU: every center's expansion
+ * (eq. (qbx)) is formed from all sources directly, without tree or lists (needs only
+ * gq_set_geometry and gq_build for the orders). O(n_ctr n_src) work; for checking and small
+ * problems.
+ */
+gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
+                         int64_t ld1, const double *dens2, int64_t ld2, double *out,
+                         int64_t ld_out);
+
+/* Sizes of the tree and lists after gq_build (Sec. 4.3, and the stage costs of Table 2). */
+typedef struct {
+  int64_t n_src, n_ctr, n_tgt;
+  int64_t n_boxes, n_levels, n_leaves, n_target_boxes;
+  int64_t n_suspended_centers;   /* centers owned by non-leaf boxes                      */
+  int64_t n_list1, n_list2, n_list3_close, n_list3_far, n_list4_close, n_list4_far;
+  int64_t near_pairs;            /* (center, source) pairs evaluated directly             */
+  int64_t list3_far_pairs;       /* (center, box) multipole-to-QBX-local pairs            */
+  int64_t list4_far_sources;     /* (box, source) pairs formed into box locals            */
+  int64_t max_list2, max_list4, max_list4_close, max_list4_far;
+  double root_lo[2];
+  double root_side;
+  double build_ms;               /* host time of the last gq_build                        */
+} gq_stats;
+
+gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);
+
+/*
+ * Copy one tree or list array to host memory `dst` (may be NULL to query the element count,
+ * which is always written to *count). Element types:
+ *   GQ_TREE_BOX_LEVEL, GQ_TREE_BOX_PARENT       int32  (n_boxes)      parent -1 for the root
+ *   GQ_TREE_BOX_CHILD                           int32  (n_boxes, 4)   quadrant x + 2 y, -1 none
+ *   GQ_TREE_BOX_IJ                              int64  (n_boxes, 2)   integer coordinates at level
+ *   GQ_TREE_BOX_SRC_RANGE, GQ_TREE_BOX_CTR_RANGE int64 (n_boxes, 2)   [begin, end) in tree order;
+ *                                               sources: whole subtree; centers: owned ones
+ *   GQ_TREE_SRC_ORDER, GQ_TREE_CTR_ORDER        int64  (n_src | n_ctr) caller index at each
+ *                                               tree-order position
+ *   GQ_LIST*_START                              int64  (n_boxes + 1)  CSR row starts
+ *   GQ_LIST*                                    int32  (entries)      box indices
+ */
+enum {
+  GQ_TREE_BOX_LEVEL = 1, GQ_TREE_BOX_PARENT, GQ_TREE_BOX_CHILD, GQ_TREE_BOX_IJ,
+  GQ_TREE_BOX_SRC_RANGE, GQ_TREE_BOX_CTR_RANGE, GQ_TREE_SRC_ORDER, GQ_TREE_CTR_ORDER,
+  GQ_LIST1_START, GQ_LIST1, GQ_LIST2_START, GQ_LIST2, GQ_LIST3C_START, GQ_LIST3C,
+  GQ_LIST3F_START, GQ_LIST3F, GQ_LIST4C_START, GQ_LIST4C, GQ_LIST4F_START, GQ_LIST4F
+};
+gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count);
+
+/* Message describing the last failure on this context (or on creation, with ctx NULL). */
+const char *gq_last_error(gq_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIGAQBX_H */

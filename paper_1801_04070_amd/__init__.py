@@ -1,0 +1,176 @@
+"""MI355X-native GIGAQBX: QBX-coupled FMM for 2-D Laplace layer potentials (HIP, gfx950).
+
+The compute path is the C-ABI library ``libgigaqbx.so`` (``include/gigaqbx.h``); this module only
+marshals arguments to it. PyTorch supplies device memory and the HIP stream. There is no CPU
+fallback: importing :class:`QBXFMM` on a device context without the built library raises.
+
+Functions with the ABI's names (``gq_create`` ... ``gq_last_error``) are re-exported from the
+loaded library; :class:`QBXFMM` wraps a context for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64, GQ_MIXED_FP32,
+                   gq_params, gq_stats)
+
+__all__ = ["QBXFMM", "GQError", "library", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "default_params"]
+
+_L = None
+
+
+def library():
+    """The loaded C library (raises ImportError if it is not built)."""
+    global _L
+    if _L is None:
+        _L = _lib.load()
+    return _L
+
+
+def __getattr__(name):
+    if name in _lib.EXPORTED:
+        return getattr(library(), name)
+    raise AttributeError(name)
+
+
+class GQError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def default_params(**kw) -> gq_params:
+    p = gq_params()
+    library().gq_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor or numpy array."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class QBXFMM:
+    """One library context. ``device=-1`` gives a host-only context (tree and lists only)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._L = library()
+        self.device = device
+        h = C.c_void_p()
+        if device >= 0:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            sp = C.c_void_p(stream.cuda_stream)
+        else:
+            sp = None
+        st = self._L.gq_create(C.byref(h), device, sp)
+        if st != 0:
+            raise GQError(st, self._L.gq_last_error(None).decode())
+        self._h = h
+        self.n_src = self.n_ctr = self.n_tgt = 0
+
+    def _check(self, st):
+        if st != 0:
+            raise GQError(st, self._L.gq_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._L.gq_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._check(self._L.gq_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def set_geometry(self, src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy, tgt_ctr):
+        """Arrays are host numpy (float64 / int32) or device torch tensors (all of one kind)."""
+        arrs = [src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy, tgt_ctr]
+        if all(isinstance(a, np.ndarray) for a in arrs):
+            mem = GQ_MEM_HOST
+            arrs = [np.ascontiguousarray(a, dtype=np.int32 if i == 6 else np.float64)
+                    for i, a in enumerate(arrs)]
+        else:
+            mem = GQ_MEM_DEVICE
+            arrs = [a.contiguous() for a in arrs]
+        self._keep = arrs
+        src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy, tgt_ctr = arrs
+        self.n_src, self.n_ctr, self.n_tgt = len(src_w), len(ctr_r), tgt_xy.shape[0]
+        self._check(self._L.gq_set_geometry(
+            self._h, mem, self.n_src, _ptr(src_xy), _ptr(src_nrm), _ptr(src_w), self.n_ctr,
+            _ptr(ctr_xy), _ptr(ctr_r), self.n_tgt, _ptr(tgt_xy), _ptr(tgt_ctr)))
+        self._keep = None
+
+    def set_geometry_from(self, geom):
+        """Geometry object with the fields of ``gq_inputs.Geometry`` (host arrays)."""
+        self.set_geometry(geom.src_xy, geom.src_nrm, geom.src_w, geom.ctr_xy, geom.ctr_r,
+                          geom.tgt_xy, geom.tgt_ctr)
+
+    def build(self, params: gq_params | None = None, **kw) -> dict:
+        p = params if params is not None else default_params(**kw)
+        self._check(self._L.gq_build(self._h, C.byref(p)))
+        self.params = p
+        return self.stats()
+
+    def stats(self) -> dict:
+        s = gq_stats()
+        self._check(self._L.gq_get_stats(self._h, C.byref(s)))
+        d = {name: getattr(s, name) for name, _ in gq_stats._fields_}
+        d["root_lo"] = tuple(s.root_lo)
+        return d
+
+    _TREE_TYPES = {
+        _lib.GQ_TREE_BOX_LEVEL: (np.int32, 1), _lib.GQ_TREE_BOX_PARENT: (np.int32, 1),
+        _lib.GQ_TREE_BOX_CHILD: (np.int32, 4), _lib.GQ_TREE_BOX_IJ: (np.int64, 2),
+        _lib.GQ_TREE_BOX_SRC_RANGE: (np.int64, 2), _lib.GQ_TREE_BOX_CTR_RANGE: (np.int64, 2),
+        _lib.GQ_TREE_SRC_ORDER: (np.int64, 1), _lib.GQ_TREE_CTR_ORDER: (np.int64, 1),
+    }
+
+    def tree_array(self, what: int) -> np.ndarray:
+        n = C.c_int64()
+        self._check(self._L.gq_get_tree_array(self._h, what, None, C.byref(n)))
+        if what in self._TREE_TYPES:
+            dt, w = self._TREE_TYPES[what]
+        else:
+            dt, w = (np.int64, 1) if what % 2 == 1 else (np.int32, 1)
+        out = np.empty(n.value, dtype=dt)
+        self._check(self._L.gq_get_tree_array(self._h, what, out.ctypes.data, C.byref(n)))
+        return out.reshape(-1, w) if w > 1 else out
+
+    def lists(self) -> dict:
+        """All interaction lists as {name: (starts, entries)}."""
+        names = {"list1": _lib.GQ_LIST1_START, "list2": _lib.GQ_LIST2_START,
+                 "list3c": _lib.GQ_LIST3C_START, "list3f": _lib.GQ_LIST3F_START,
+                 "list4c": _lib.GQ_LIST4C_START, "list4f": _lib.GQ_LIST4F_START}
+        return {k: (self.tree_array(v), self.tree_array(v + 1)) for k, v in names.items()}
+
+    def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
+        """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or
+        (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt)."""
+        import torch
+        squeeze = dens1.dim() == 1
+        d1 = dens1.reshape(-1, dens1.shape[-1]).contiguous()
+        d2 = None if dens2 is None else dens2.reshape(-1, dens2.shape[-1]).contiguous()
+        n_dens = d1.shape[0]
+        if out is None:
+            out = torch.empty((n_dens, self.n_tgt), dtype=torch.float64, device=d1.device)
+        fn = self._L.gq_eval_direct if direct else self._L.gq_eval
+        self._check(fn(self._h, kind, n_dens, _ptr(d1), d1.stride(0), _ptr(d2),
+                       0 if d2 is None else d2.stride(0), _ptr(out), out.stride(0)))
+        return out[0] if squeeze else out

@@ -1,0 +1,67 @@
+"""ctypes declarations of the C ABI in ``include/gigaqbx.h`` (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgigaqbx.so")
+
+GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EHIP, GQ_ESTATE, GQ_EUNSUP = 0, -1, -2, -3, -4, -5
+GQ_S, GQ_D, GQ_S_MINUS_D = 1, 2, 3
+GQ_MEM_HOST, GQ_MEM_DEVICE = 0, 1
+GQ_FP64, GQ_MIXED_FP32 = 0, 1
+GQ_MAX_P_QBX, GQ_MAX_P_FMM = 20, 63
+
+(GQ_TREE_BOX_LEVEL, GQ_TREE_BOX_PARENT, GQ_TREE_BOX_CHILD, GQ_TREE_BOX_IJ, GQ_TREE_BOX_SRC_RANGE,
+ GQ_TREE_BOX_CTR_RANGE, GQ_TREE_SRC_ORDER, GQ_TREE_CTR_ORDER, GQ_LIST1_START, GQ_LIST1,
+ GQ_LIST2_START, GQ_LIST2, GQ_LIST3C_START, GQ_LIST3C, GQ_LIST3F_START, GQ_LIST3F,
+ GQ_LIST4C_START, GQ_LIST4C, GQ_LIST4F_START, GQ_LIST4F) = range(1, 21)
+
+STATUS_NAMES = {0: "GQ_OK", -1: "GQ_EINVAL", -2: "GQ_ENOMEM", -3: "GQ_EHIP", -4: "GQ_ESTATE",
+                -5: "GQ_EUNSUP"}
+
+
+class gq_params(C.Structure):
+    _fields_ = [("p_qbx", C.c_int), ("p_fmm", C.c_int), ("n_max", C.c_int),
+                ("count_mode", C.c_int), ("t_f", C.c_double), ("w3far_min_sources", C.c_int),
+                ("precision", C.c_int), ("max_levels", C.c_int)]
+
+
+class gq_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_src", "n_ctr", "n_tgt", "n_boxes", "n_levels", "n_leaves", "n_target_boxes",
+        "n_suspended_centers", "n_list1", "n_list2", "n_list3_close", "n_list3_far",
+        "n_list4_close", "n_list4_far", "near_pairs", "list3_far_pairs", "list4_far_sources",
+        "max_list2", "max_list4", "max_list4_close", "max_list4_far")] + [
+        ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double)]
+
+
+EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
+            "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
+            "gq_last_error"]
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"HIP library {path} is not built; run `python -c 'import __graft_entry__ as g; "
+            "g.build()'` (or `python -m paper_1801_04070_amd.build`) first")
+    L = C.CDLL(path)
+    vp, dp, ip, i64, i32 = C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int
+    L.gq_default_params.argtypes = [C.POINTER(gq_params)]
+    L.gq_create.argtypes = [C.POINTER(C.c_void_p), i32, vp]
+    L.gq_destroy.argtypes = [vp]
+    L.gq_set_stream.argtypes = [vp, vp]
+    L.gq_set_geometry.argtypes = [vp, i32, i64, dp, dp, dp, i64, dp, dp, i64, dp, ip]
+    L.gq_build.argtypes = [vp, C.POINTER(gq_params)]
+    L.gq_eval.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64]
+    L.gq_eval_direct.argtypes = L.gq_eval.argtypes
+    L.gq_get_stats.argtypes = [vp, C.POINTER(gq_stats)]
+    L.gq_get_tree_array.argtypes = [vp, i32, vp, C.POINTER(C.c_int64)]
+    L.gq_last_error.argtypes = [vp]
+    L.gq_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name != "gq_last_error":
+            getattr(L, name).restype = C.c_int
+    return L

@@ -1,0 +1,455 @@
+// C-ABI implementation (host side): argument checking, geometry and tree upload, evaluation
+// orchestration. Every step of an evaluation runs in the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "context.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+gq_status fail(gq_ctx *ctx, gq_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+#define GQ_HIP(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, GQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+void free_device(gq_ctx *ctx) {
+  if (ctx->device >= 0) {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (void *p : ctx->allocations) (void)hipFree(p);
+  }
+  ctx->allocations.clear();
+  ctx->d = gq::DevBuffers();
+  ctx->built = false;
+}
+
+template <typename T>
+gq_status upload(gq_ctx *ctx, T *&dst, const void *src, size_t count) {
+  dst = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(ctx, GQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  ctx->allocations.push_back(p);
+  if (src && count) {
+    e = hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  dst = static_cast<T *>(p);
+  return GQ_OK;
+}
+
+template <typename T>
+gq_status alloc(gq_ctx *ctx, T *&dst, size_t count) {
+  return upload<T>(ctx, dst, nullptr, count);
+}
+
+std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
+  std::vector<int32_t> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (int32_t)v[i];
+  return o;
+}
+
+#define GQ_TRY(expr)                 \
+  do {                               \
+    gq_status s_ = (expr);           \
+    if (s_ != GQ_OK) return s_;      \
+  } while (0)
+
+gq_status upload_all(gq_ctx *ctx) {
+  const gq::Tree &t = ctx->tree;
+  auto &d = ctx->d;
+  const int64_t ns = ctx->ns, nc = ctx->nc, nt = ctx->nt, nb = t.n_boxes();
+  // sources in tree order
+  {
+    std::vector<double> xy(2 * ns), nrm(2 * ns), w(ns);
+    std::vector<int32_t> perm(ns);
+    for (int64_t i = 0; i < ns; ++i) {
+      int64_t o = t.src_order[i];
+      xy[2 * i] = ctx->src_xy[2 * o]; xy[2 * i + 1] = ctx->src_xy[2 * o + 1];
+      nrm[2 * i] = ctx->src_nrm[2 * o]; nrm[2 * i + 1] = ctx->src_nrm[2 * o + 1];
+      w[i] = ctx->src_w[o];
+      perm[i] = (int32_t)o;
+    }
+    GQ_TRY(upload(ctx, d.sxy, xy.data(), ns));
+    GQ_TRY(upload(ctx, d.snrm, nrm.data(), ns));
+    GQ_TRY(upload(ctx, d.sw, w.data(), ns));
+    GQ_TRY(upload(ctx, d.sperm, perm.data(), ns));
+  }
+  // centers in tree order, center -> target slots
+  {
+    std::vector<double> xy(2 * nc), r(nc);
+    std::vector<int64_t> inv(nc);
+    for (int64_t k = 0; k < nc; ++k) {
+      int64_t o = t.ctr_order[k];
+      inv[o] = k;
+      xy[2 * k] = ctx->ctr_xy[2 * o]; xy[2 * k + 1] = ctx->ctr_xy[2 * o + 1];
+      r[k] = ctx->ctr_r[o];
+    }
+    std::vector<int32_t> start(nc + 1, 0), slot;
+    for (int64_t tg = 0; tg < nt; ++tg)
+      for (int s = 0; s < 2; ++s)
+        if (ctx->tgt_ctr[2 * tg + s] >= 0) start[inv[ctx->tgt_ctr[2 * tg + s]] + 1]++;
+    for (int64_t k = 0; k < nc; ++k) start[k + 1] += start[k];
+    slot.assign(start[nc], 0);
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int64_t tg = 0; tg < nt; ++tg)
+      for (int s = 0; s < 2; ++s)
+        if (ctx->tgt_ctr[2 * tg + s] >= 0)
+          slot[fill[inv[ctx->tgt_ctr[2 * tg + s]]]++] = (int32_t)(2 * tg + s);
+    GQ_TRY(upload(ctx, d.cxy, xy.data(), nc));
+    GQ_TRY(upload(ctx, d.cr, r.data(), nc));
+    GQ_TRY(upload(ctx, d.cbox, t.ctr_box.data(), nc));
+    GQ_TRY(upload(ctx, d.c2t_start, start.data(), nc + 1));
+    GQ_TRY(upload(ctx, d.c2t_slot, slot.data(), slot.size()));
+    GQ_TRY(upload(ctx, d.txy, ctx->tgt_xy.data(), nt));
+    GQ_TRY(upload(ctx, d.tctr, ctx->tgt_ctr.data(), 2 * nt));
+  }
+  // boxes
+  {
+    std::vector<double> bc(2 * nb);
+    std::vector<int8_t> quad(nb, 0);
+    std::vector<int32_t> s0(nb), s1(nb), leaves, tboxes, istb(nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+      bc[2 * b] = t.cx[b]; bc[2 * b + 1] = t.cy[b];
+      quad[b] = (int8_t)((t.bi[b] & 1) + 2 * (t.bj[b] & 1));
+      s0[b] = (int32_t)t.src_begin[b]; s1[b] = (int32_t)t.src_end[b];
+      if (t.is_leaf(b)) leaves.push_back((int32_t)b);
+      if (t.has_tgt[b]) { tboxes.push_back((int32_t)b); istb[b] = 1; }
+    }
+    ctx->n_tboxes = (int64_t)tboxes.size();
+    GQ_TRY(upload(ctx, d.bc, bc.data(), nb));
+    GQ_TRY(upload(ctx, d.blevel, t.level.data(), nb));
+    GQ_TRY(upload(ctx, d.bparent, t.parent.data(), nb));
+    GQ_TRY(upload(ctx, d.bchild, t.child.data(), 4 * nb));
+    GQ_TRY(upload(ctx, d.bsrc0, s0.data(), nb));
+    GQ_TRY(upload(ctx, d.bsrc1, s1.data(), nb));
+    GQ_TRY(upload(ctx, d.bquad, quad.data(), nb));
+    GQ_TRY(upload(ctx, d.leaves, leaves.data(), leaves.size()));
+    GQ_TRY(upload(ctx, d.tboxes, tboxes.data(), tboxes.size()));
+    GQ_TRY(upload(ctx, d.is_tbox, istb.data(), nb));
+    std::vector<double> side(t.n_levels), iside(t.n_levels), lside(t.n_levels);
+    for (int l = 0; l < t.n_levels; ++l) {
+      side[l] = std::ldexp(t.side, -l);
+      iside[l] = 1.0 / side[l];
+      lside[l] = std::log(side[l]);
+    }
+    GQ_TRY(upload(ctx, d.level_side, side.data(), side.size()));
+    GQ_TRY(upload(ctx, d.level_inv_side, iside.data(), iside.size()));
+    GQ_TRY(upload(ctx, d.level_log_side, lside.data(), lside.size()));
+  }
+  // lists
+  GQ_TRY(upload(ctx, d.v_start, to_i32(t.list2.start).data(), nb + 1));
+  GQ_TRY(upload(ctx, d.v_idx, t.list2.idx.data(), t.list2.idx.size()));
+  GQ_TRY(upload(ctx, d.v_off, t.list2_offset.data(), t.list2_offset.size()));
+  GQ_TRY(upload(ctx, d.wf_start, to_i32(t.list3f.start).data(), nb + 1));
+  GQ_TRY(upload(ctx, d.wf_idx, t.list3f.idx.data(), t.list3f.idx.size()));
+  GQ_TRY(upload(ctx, d.xf_start, to_i32(t.list4f.start).data(), nb + 1));
+  GQ_TRY(upload(ctx, d.xf_idx, t.list4f.idx.data(), t.list4f.idx.size()));
+  GQ_TRY(upload(ctx, d.near_row, to_i32(t.near_row).data(), nb + 1));
+  GQ_TRY(upload(ctx, d.near_lo, to_i32(t.near_lo).data(), t.near_lo.size()));
+  GQ_TRY(upload(ctx, d.near_hi, to_i32(t.near_hi).data(), t.near_hi.size()));
+  // tables
+  const gq::Tables &tb = ctx->tables;
+  const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
+  GQ_TRY(upload(ctx, d.m2m, tb.m2m.data(), tb.m2m.size() / 2));
+  GQ_TRY(upload(ctx, d.l2l, tb.l2l.data(), tb.l2l.size() / 2));
+  GQ_TRY(upload(ctx, d.m2lb, tb.m2l_b.data(), tb.m2l_b.size()));
+  GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
+  GQ_TRY(upload(ctx, d.ologabs, tb.ologabs.data(), tb.ologabs.size()));
+  {
+    const int NB = 2 * tb.p + 2;
+    auto C = [&](int n, int k) { return (k < 0 || k > n || n >= NB) ? 0.0 : tb.binom[(size_t)n * NB + k]; };
+    std::vector<double> l2q((size_t)P1 * (PQ + 1)), m2q((size_t)(PQ + 1) * P1);
+    for (int k = 0; k < P1; ++k)
+      for (int m = 0; m <= PQ; ++m) l2q[(size_t)k * (PQ + 1) + m] = C(k, m);
+    for (int m = 0; m <= PQ; ++m)
+      for (int k = 0; k < P1; ++k) m2q[(size_t)m * P1 + k] = k == 0 ? 0.0 : C(m + k - 1, k - 1);
+    GQ_TRY(upload(ctx, d.l2q_binom, l2q.data(), l2q.size()));
+    GQ_TRY(upload(ctx, d.m2q_binom, m2q.data(), m2q.size()));
+  }
+  // workspace
+  GQ_TRY(alloc(ctx, d.sq, ns));
+  GQ_TRY(alloc(ctx, d.sdip, ns));
+  GQ_TRY(alloc(ctx, d.M, (size_t)nb * P1));
+  GQ_TRY(alloc(ctx, d.L, (size_t)nb * P1));
+  GQ_TRY(alloc(ctx, d.tv, 2 * nt));
+  return GQ_OK;
+}
+
+bool finite_all(const std::vector<double> &v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                      const double *dens2, int64_t ld2, double *out, int64_t ld_out, bool direct) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context cannot evaluate");
+  if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_eval before a successful gq_build");
+  if (kind < GQ_S || kind > GQ_S_MINUS_D) return fail(ctx, GQ_EINVAL, "unknown kind");
+  if (n_dens < 0) return fail(ctx, GQ_EINVAL, "n_dens < 0");
+  if (n_dens == 0) return GQ_OK;
+  if (!dens1 || !out) return fail(ctx, GQ_EINVAL, "null density or output");
+  if ((kind == GQ_S_MINUS_D) != (dens2 != nullptr))
+    return fail(ctx, GQ_EINVAL, "dens2 must be given exactly for GQ_S_MINUS_D");
+  if (ld1 < ctx->ns || (dens2 && ld2 < ctx->ns) || ld_out < ctx->nt)
+    return fail(ctx, GQ_EINVAL, "leading dimension smaller than the row length");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  for (int64_t j = 0; j < n_dens; ++j) {
+    hipError_t e = gq::run_eval(ctx, kind, dens1 + j * ld1, dens2 ? dens2 + j * ld2 : nullptr,
+                                out + j * ld_out, direct);
+    if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  return GQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gq_status gq_default_params(gq_params *p) {
+  if (!p) return GQ_EINVAL;
+  p->p_qbx = 12;
+  p->p_fmm = 30;
+  p->n_max = 64;
+  p->count_mode = 0;
+  p->t_f = 0.9;
+  p->w3far_min_sources = 15;
+  p->precision = GQ_FP64;
+  p->max_levels = 24;
+  return GQ_OK;
+}
+
+gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
+  if (!out) return fail(nullptr, GQ_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (device < -1) return fail(nullptr, GQ_EINVAL, "device must be >= -1");
+  if (device >= 0) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device >= n)
+      return fail(nullptr, GQ_EHIP, std::string("no HIP device ") + std::to_string(device));
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, GQ_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  }
+  gq_ctx *ctx = new (std::nothrow) gq_ctx();
+  if (!ctx) return fail(nullptr, GQ_ENOMEM, "context allocation failed");
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  gq_default_params(&ctx->params);
+  *out = ctx;
+  return GQ_OK;
+}
+
+gq_status gq_destroy(gq_ctx *ctx) {
+  if (!ctx) return GQ_OK;
+  if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+  free_device(ctx);
+  delete ctx;
+  return GQ_OK;
+}
+
+gq_status gq_set_stream(gq_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return GQ_OK;
+}
+
+gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src_xy,
+                          const double *src_nrm, const double *src_w, int64_t n_ctr,
+                          const double *ctr_xy, const double *ctr_r, int64_t n_tgt,
+                          const double *tgt_xy, const int32_t *tgt_ctr) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "mem must be GQ_MEM_HOST or GQ_MEM_DEVICE");
+  if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
+  if (n_src <= 0 || n_ctr <= 0 || n_tgt < 0) return fail(ctx, GQ_EINVAL, "need n_src > 0, n_ctr > 0, n_tgt >= 0");
+  if (n_src >= (int64_t(1) << 31) || n_ctr >= (int64_t(1) << 31) || 2 * n_tgt >= (int64_t(1) << 31))
+    return fail(ctx, GQ_EUNSUP, "sizes beyond 2^31 are not supported");
+  if (!src_xy || !src_nrm || !src_w || !ctr_xy || !ctr_r || (n_tgt > 0 && (!tgt_xy || !tgt_ctr)))
+    return fail(ctx, GQ_EINVAL, "null geometry pointer");
+  free_device(ctx);
+  ctx->have_geom = false;
+  ctx->ns = n_src; ctx->nc = n_ctr; ctx->nt = n_tgt;
+  try {
+    ctx->src_xy.resize(2 * n_src); ctx->src_nrm.resize(2 * n_src); ctx->src_w.resize(n_src);
+    ctx->ctr_xy.resize(2 * n_ctr); ctx->ctr_r.resize(n_ctr);
+    ctx->tgt_xy.resize(2 * n_tgt); ctx->tgt_ctr.resize(2 * n_tgt);
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, GQ_ENOMEM, "host copy of the geometry");
+  }
+  struct { void *dst; const void *src; size_t bytes; } cp[] = {
+      {ctx->src_xy.data(), src_xy, sizeof(double) * 2 * n_src},
+      {ctx->src_nrm.data(), src_nrm, sizeof(double) * 2 * n_src},
+      {ctx->src_w.data(), src_w, sizeof(double) * n_src},
+      {ctx->ctr_xy.data(), ctr_xy, sizeof(double) * 2 * n_ctr},
+      {ctx->ctr_r.data(), ctr_r, sizeof(double) * n_ctr},
+      {ctx->tgt_xy.data(), tgt_xy, sizeof(double) * 2 * n_tgt},
+      {ctx->tgt_ctr.data(), tgt_ctr, sizeof(int32_t) * 2 * n_tgt}};
+  for (auto &c : cp) {
+    if (!c.bytes) continue;
+    if (mem == GQ_MEM_HOST) std::memcpy(c.dst, c.src, c.bytes);
+    else GQ_HIP(ctx, hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost));
+  }
+  if (!finite_all(ctx->src_xy) || !finite_all(ctx->src_nrm) || !finite_all(ctx->src_w) ||
+      !finite_all(ctx->ctr_xy) || !finite_all(ctx->ctr_r) || !finite_all(ctx->tgt_xy))
+    return fail(ctx, GQ_EINVAL, "non-finite geometry value");
+  for (double r : ctx->ctr_r)
+    if (!(r > 0)) return fail(ctx, GQ_EINVAL, "center radius must be positive");
+  for (int64_t t = 0; t < n_tgt; ++t) {
+    int used = 0;
+    for (int s = 0; s < 2; ++s) {
+      int32_t c = ctx->tgt_ctr[2 * t + s];
+      if (c < -1 || c >= n_ctr) return fail(ctx, GQ_EINVAL, "target-center index out of range");
+      used += c >= 0;
+    }
+    if (!used) return fail(ctx, GQ_EUNSUP, "every target needs at least one QBX center");
+  }
+  ctx->have_geom = true;
+  return GQ_OK;
+}
+
+gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!params) return fail(ctx, GQ_EINVAL, "null params");
+  if (!ctx->have_geom) return fail(ctx, GQ_ESTATE, "gq_build before gq_set_geometry");
+  const gq_params &p = *params;
+  if (p.p_qbx < 0 || p.p_fmm < 1) return fail(ctx, GQ_EINVAL, "orders must satisfy p_qbx >= 0, p_fmm >= 1");
+  if (p.p_fmm > GQ_MAX_P_FMM) return fail(ctx, GQ_EUNSUP, "p_fmm above GQ_MAX_P_FMM");
+  if (!gq::pq_supported(p.p_qbx)) return fail(ctx, GQ_EUNSUP, "p_qbx has no compiled kernel in this build");
+  if (p.precision != GQ_FP64) return fail(ctx, GQ_EUNSUP, "only GQ_FP64 is supported in this build");
+  if (p.count_mode != 0 && p.count_mode != 1) return fail(ctx, GQ_EINVAL, "count_mode must be 0 or 1");
+  if (p.w3far_min_sources < 0) return fail(ctx, GQ_EINVAL, "w3far_min_sources must be >= 0");
+  free_device(ctx);
+  ctx->params = p;
+  ctx->pq_bucket = p.p_qbx;
+  auto t0 = std::chrono::steady_clock::now();
+  gq::TreeParams tp;
+  tp.n_max = p.n_max; tp.count_mode = p.count_mode; tp.t_f = p.t_f;
+  tp.w3far_min_sources = p.w3far_min_sources; tp.max_levels = p.max_levels;
+  std::string msg;
+  try {
+    msg = gq::build_tree(ctx->tree, ctx->ns, ctx->src_xy.data(), ctx->nc, ctx->ctr_xy.data(),
+                         ctx->ctr_r.data(), tp);
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, GQ_ENOMEM, "host allocation during tree build");
+  }
+  if (!msg.empty()) return fail(ctx, GQ_EINVAL, msg);
+  gq::build_tables(ctx->tables, p.p_fmm);
+  if (ctx->device >= 0) {
+    GQ_HIP(ctx, hipSetDevice(ctx->device));
+    gq_status st = upload_all(ctx);
+    if (st != GQ_OK) {
+      free_device(ctx);
+      return st;
+    }
+  }
+  ctx->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ctx->built = true;
+  return GQ_OK;
+}
+
+gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                  const double *dens2, int64_t ld2, double *out, int64_t ld_out) {
+  return eval_common(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, false);
+}
+
+gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                         const double *dens2, int64_t ld2, double *out, int64_t ld_out) {
+  return eval_common(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, true);
+}
+
+gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!out) return fail(ctx, GQ_EINVAL, "null output");
+  if (!ctx->built) return fail(ctx, GQ_ESTATE, "no tree built");
+  const gq::Tree &t = ctx->tree;
+  std::memset(out, 0, sizeof(*out));
+  out->n_src = ctx->ns; out->n_ctr = ctx->nc; out->n_tgt = ctx->nt;
+  out->n_boxes = t.n_boxes(); out->n_levels = t.n_levels; out->n_leaves = t.n_leaves;
+  out->n_target_boxes = t.n_target_boxes; out->n_suspended_centers = t.n_suspended;
+  out->n_list1 = (int64_t)t.list1.idx.size(); out->n_list2 = (int64_t)t.list2.idx.size();
+  out->n_list3_close = (int64_t)t.list3c.idx.size(); out->n_list3_far = (int64_t)t.list3f.idx.size();
+  out->n_list4_close = (int64_t)t.list4c.idx.size(); out->n_list4_far = (int64_t)t.list4f.idx.size();
+  out->near_pairs = t.near_pairs; out->list3_far_pairs = t.list3f_pairs;
+  out->list4_far_sources = t.list4f_sources;
+  for (int64_t b = 0; b < t.n_boxes(); ++b) {
+    out->max_list2 = std::max(out->max_list2, t.list2.row_size(b));
+    out->max_list4_close = std::max(out->max_list4_close, t.list4c.row_size(b));
+    out->max_list4_far = std::max(out->max_list4_far, t.list4f.row_size(b));
+  }
+  out->max_list4 = 0;
+  out->root_lo[0] = t.lo[0]; out->root_lo[1] = t.lo[1]; out->root_side = t.side;
+  out->build_ms = ctx->build_ms;
+  return GQ_OK;
+}
+
+gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!count) return fail(ctx, GQ_EINVAL, "null count");
+  if (!ctx->built) return fail(ctx, GQ_ESTATE, "no tree built");
+  const gq::Tree &t = ctx->tree;
+  const void *src = nullptr;
+  size_t n = 0, esz = 0;
+  std::vector<int64_t> tmp;
+  auto pairs = [&](const std::vector<int64_t> &a, const std::vector<int64_t> &b) {
+    tmp.resize(2 * a.size());
+    for (size_t i = 0; i < a.size(); ++i) { tmp[2 * i] = a[i]; tmp[2 * i + 1] = b[i]; }
+    src = tmp.data(); n = tmp.size(); esz = 8;
+  };
+  const gq::Csr *csr = nullptr;
+  bool starts = false;
+  switch (what) {
+    case GQ_TREE_BOX_LEVEL: src = t.level.data(); n = t.level.size(); esz = 4; break;
+    case GQ_TREE_BOX_PARENT: src = t.parent.data(); n = t.parent.size(); esz = 4; break;
+    case GQ_TREE_BOX_CHILD: src = t.child.data(); n = t.child.size(); esz = 4; break;
+    case GQ_TREE_BOX_IJ: pairs(t.bi, t.bj); break;
+    case GQ_TREE_BOX_SRC_RANGE: pairs(t.src_begin, t.src_end); break;
+    case GQ_TREE_BOX_CTR_RANGE: pairs(t.ctr_begin, t.ctr_end); break;
+    case GQ_TREE_SRC_ORDER: src = t.src_order.data(); n = t.src_order.size(); esz = 8; break;
+    case GQ_TREE_CTR_ORDER: src = t.ctr_order.data(); n = t.ctr_order.size(); esz = 8; break;
+    case GQ_LIST1_START: starts = true; /* fallthrough */
+    case GQ_LIST1: csr = &t.list1; break;
+    case GQ_LIST2_START: starts = true; /* fallthrough */
+    case GQ_LIST2: csr = &t.list2; break;
+    case GQ_LIST3C_START: starts = true; /* fallthrough */
+    case GQ_LIST3C: csr = &t.list3c; break;
+    case GQ_LIST3F_START: starts = true; /* fallthrough */
+    case GQ_LIST3F: csr = &t.list3f; break;
+    case GQ_LIST4C_START: starts = true; /* fallthrough */
+    case GQ_LIST4C: csr = &t.list4c; break;
+    case GQ_LIST4F_START: starts = true; /* fallthrough */
+    case GQ_LIST4F: csr = &t.list4f; break;
+    default: return fail(ctx, GQ_EINVAL, "unknown tree array");
+  }
+  if (csr) {
+    if (starts) { src = csr->start.data(); n = csr->start.size(); esz = 8; }
+    else { src = csr->idx.data(); n = csr->idx.size(); esz = 4; }
+  }
+  *count = (int64_t)n;
+  if (dst && n) std::memcpy(dst, src, n * esz);
+  return GQ_OK;
+}
+
+const char *gq_last_error(gq_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

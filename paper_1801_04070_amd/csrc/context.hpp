@@ -1,0 +1,79 @@
+// Library context: host copies of the geometry, the host tree/lists, and every device buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gigaqbx.h"
+#include "tables.hpp"
+#include "tree.hpp"
+
+namespace gq {
+
+// Device buffers. Sources and centers are stored in tree order (see tree.hpp); every box
+// array has one entry per box in breadth-first order.
+struct DevBuffers {
+  // sources (tree order)
+  double2 *sxy = nullptr, *snrm = nullptr;
+  double *sw = nullptr;
+  int32_t *sperm = nullptr;          // caller index of each tree-order source
+  // centers (tree order) and their targets
+  double2 *cxy = nullptr;
+  double *cr = nullptr;
+  int32_t *cbox = nullptr;           // owning box
+  int32_t *c2t_start = nullptr;      // CSR center -> target slots (slot = 2 * target + column)
+  int32_t *c2t_slot = nullptr;
+  // targets (caller order)
+  double2 *txy = nullptr;
+  int32_t *tctr = nullptr;           // (n_tgt, 2) association as given
+  // boxes
+  double2 *bc = nullptr;             // centers
+  int32_t *blevel = nullptr, *bparent = nullptr, *bchild = nullptr;
+  int32_t *bsrc0 = nullptr, *bsrc1 = nullptr;
+  int8_t *bquad = nullptr;           // quadrant of the box within its parent
+  int32_t *leaves = nullptr;         // leaf boxes
+  int32_t *tboxes = nullptr;         // target-or-ancestor boxes
+  int32_t *is_tbox = nullptr;        // per box: 1 if target-or-ancestor
+  double *level_side = nullptr, *level_inv_side = nullptr, *level_log_side = nullptr;
+  // lists
+  int32_t *v_start = nullptr, *v_idx = nullptr, *v_off = nullptr;
+  int32_t *wf_start = nullptr, *wf_idx = nullptr;
+  int32_t *xf_start = nullptr, *xf_idx = nullptr;
+  int32_t *near_row = nullptr, *near_lo = nullptr, *near_hi = nullptr;
+  // tables
+  double2 *m2m = nullptr, *l2l = nullptr, *opow = nullptr;
+  double *m2lb = nullptr, *ologabs = nullptr;
+  double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
+  double *m2q_binom = nullptr;       // [PQB + 1][P1]  C(m + k - 1, k - 1)
+  // workspace
+  double *sq = nullptr;              // per-source charge  w * sigma
+  double2 *sdip = nullptr;           // per-source dipole  w * tau * n
+  double2 *M = nullptr, *L = nullptr;
+  double *tv = nullptr;              // per target slot values
+};
+
+}  // namespace gq
+
+struct gq_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // geometry (caller order, host copies)
+  int64_t ns = 0, nc = 0, nt = 0;
+  std::vector<double> src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy;
+  std::vector<int32_t> tgt_ctr;
+  bool have_geom = false, built = false;
+
+  gq_params params{};
+  gq::Tree tree;
+  gq::Tables tables;
+  int pq_bucket = 0;                 // compiled QBX order used by the kernels
+  int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
+  gq::DevBuffers d;
+  std::vector<void *> allocations;   // every device allocation, freed together
+  double build_ms = 0;
+};

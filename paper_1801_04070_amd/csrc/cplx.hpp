@@ -1,0 +1,47 @@
+// Complex FP64/FP32 helpers for device code (values stored as double2 / float2 = (re, im)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gq {
+
+__host__ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__host__ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__host__ __device__ __forceinline__ double2 cscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+// a + s * b with real s
+__host__ __device__ __forceinline__ double2 caxpy(double s, double2 b, double2 a) {
+  return make_double2(fma(s, b.x, a.x), fma(s, b.y, a.y));
+}
+// a + b * c (complex)
+__host__ __device__ __forceinline__ double2 cfma(double2 b, double2 c, double2 a) {
+  return make_double2(fma(b.x, c.x, fma(-b.y, c.y, a.x)), fma(b.x, c.y, fma(b.y, c.x, a.y)));
+}
+__host__ __device__ __forceinline__ double2 cinv(double2 a) {
+  double s = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * s, -a.y * s);
+}
+// z^n for n >= 0 by binary powering
+__host__ __device__ __forceinline__ double2 cpowi(double2 z, int n) {
+  double2 r = make_double2(1.0, 0.0);
+  while (n > 0) {
+    if (n & 1) r = cmul(r, z);
+    z = cmul(z, z);
+    n >>= 1;
+  }
+  return r;
+}
+
+__host__ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+}  // namespace gq

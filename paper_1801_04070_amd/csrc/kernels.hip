@@ -1,0 +1,499 @@
+// HIP kernels (gfx950) for the GIGAQBX FMM stages and direct QBX.
+//
+// Expansion scaling (see tables.hpp): box multipoles are stored as a_k / s^k and box locals as
+// b_k s^k with s the box side; QBX local coefficients of a center of radius r are stored as
+// alpha_m r^m, so the QBX expansion is evaluated at the target as sum_m alpha_m ((x - c)/r)^m.
+//
+// Kinds (template KIND): 1 = single layer (charges q = w sigma), 2 = double layer (dipoles
+// w tau n), 3 = S(sigma) - D(tau). With z = y - c the source contributions are
+//   charge:  alpha_0 += q log|z|,   alpha_m += -q / (m z^m)        (eq. (local), eq. (qbx))
+//   dipole:  alpha_m += d / z^(m+1),  d = w tau n                    (Re(n/(y - x)) kernel)
+// and the multipole of a box about c_b (eq. (multipole)):
+//   charge:  a_0 += q,  a_k += -q z^k / k;   dipole: a_k += -d z^(k-1).
+#include "context.hpp"
+#include "cplx.hpp"
+#include "kernels.hpp"
+
+namespace gq {
+
+namespace {
+
+constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
+
+// ------------------------------------------------------------------------------------------
+// Source strengths in tree order: q = w sigma, dipole d = w tau n (with the minus sign of S - D).
+template <int KIND>
+__global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const double *__restrict__ sw,
+                         const double2 *__restrict__ snrm, const double *__restrict__ d1,
+                         const double *__restrict__ d2, double *__restrict__ sq,
+                         double2 *__restrict__ sdip) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int32_t o = sperm[i];
+  const double w = sw[i];
+  if (KIND == 1) sq[i] = w * d1[o];
+  if (KIND == 2) sdip[i] = cscale(snrm[i], w * d1[o]);
+  if (KIND == 3) {
+    sq[i] = w * d1[o];
+    sdip[i] = cscale(snrm[i], -w * d2[o]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 2a, P2M for leaf boxes: one work-group per leaf, lane k computes coefficient k.
+template <int KIND>
+__global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
+                                            const double2 *__restrict__ bc,
+                                            const int32_t *__restrict__ blevel,
+                                            const int32_t *__restrict__ bsrc0,
+                                            const int32_t *__restrict__ bsrc1,
+                                            const double *__restrict__ level_inv_side,
+                                            const double2 *__restrict__ sxy,
+                                            const double *__restrict__ sq,
+                                            const double2 *__restrict__ sdip, int P1,
+                                            double2 *__restrict__ M) {
+  const int32_t b = leaves[blockIdx.x];
+  const int k = threadIdx.x;
+  if (k >= P1) return;
+  const double2 c = bc[b];
+  const double is = level_inv_side[blevel[b]];
+  double2 acc = make_double2(0.0, 0.0);
+  const double ik = k > 0 ? 1.0 / k : 0.0;
+  for (int32_t s = bsrc0[b]; s < bsrc1[b]; ++s) {
+    const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+    if (k == 0) {
+      if (KIND & 1) acc.x += sq[s];
+      continue;
+    }
+    const double2 pk1 = cpowi(y, k - 1);
+    if (KIND & 1) acc = caxpy(-sq[s] * ik, cmul(pk1, y), acc);
+    if (KIND & 2) acc = cfma(cscale(sdip[s], -is), pk1, acc);
+  }
+  M[(int64_t)b * P1 + k] = acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 2b, M2M for the non-leaf boxes of one level: parent_m = sum_q sum_k T_q[m][k] child_k.
+__global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restrict__ bchild,
+                                            const double2 *__restrict__ T, int P1,
+                                            double2 *__restrict__ M) {
+  const int32_t b = box0 + blockIdx.x;
+  const int m = threadIdx.x;
+  if (m >= P1) return;
+  const int32_t *ch = bchild + 4 * (int64_t)b;
+  if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf: formed by P2M
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < 4; ++q) {
+    if (ch[q] < 0) continue;
+    const double2 *Tq = T + ((int64_t)q * P1 + m) * P1;
+    const double2 *Mc = M + (int64_t)ch[q] * P1;
+    for (int k = 0; k <= m; ++k) acc = cfma(Tq[k], Mc[k], acc);
+  }
+  M[(int64_t)b * P1 + m] = acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One work-group per
+// target-or-ancestor box; lane m computes coefficient m.
+template <int KIND>
+__global__ void __launch_bounds__(64) k_far_local(
+    const int32_t *__restrict__ tboxes, const double2 *__restrict__ bc,
+    const int32_t *__restrict__ blevel, const double *__restrict__ level_inv_side,
+    const double *__restrict__ level_log_side, const int32_t *__restrict__ v_start,
+    const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
+    const int32_t *__restrict__ xf_start, const int32_t *__restrict__ xf_idx,
+    const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
+    const double2 *__restrict__ M, const double *__restrict__ Bm, const double2 *__restrict__ opow,
+    const double *__restrict__ ologabs, const double2 *__restrict__ sxy,
+    const double *__restrict__ sq, const double2 *__restrict__ sdip, int P1,
+    double2 *__restrict__ L) {
+  __shared__ double2 X[64];
+  const int32_t b = tboxes[blockIdx.x];
+  const int m = threadIdx.x;
+  const int lev = blevel[b];
+  const double logs = level_log_side[lev];
+  double2 acc = make_double2(0.0, 0.0);
+  // M2L: beta_m = o^-m sum_k B[m][k] (a_k o^-k), plus a_0 log|s o| in beta_0
+  for (int32_t j = v_start[b]; j < v_start[b + 1]; ++j) {
+    const int32_t d = v_idx[j];
+    const double2 *op = opow + (int64_t)v_off[j] * P1;
+    __syncthreads();
+    if (m < P1) X[m] = cmul(M[(int64_t)d * P1 + m], op[m]);
+    __syncthreads();
+    if (m < P1) {
+      double2 s = make_double2(0.0, 0.0);
+      const double *Brow = Bm + (int64_t)m * P1;
+      for (int k = 0; k < P1; ++k) s = caxpy(Brow[k], X[k], s);
+      acc = cfma(s, op[m], acc);
+      if (m == 0) acc.x += X[0].x * (logs + ologabs[v_off[j]]);
+    }
+  }
+  if (m >= P1) return;
+  // P2L (eq. (local) about c_b) for the sources of List 4 far boxes
+  const double2 c = bc[b];
+  const double is = level_inv_side[lev];
+  const double im = m > 0 ? 1.0 / m : 0.0;
+  for (int32_t j = xf_start[b]; j < xf_start[b + 1]; ++j) {
+    const int32_t d = xf_idx[j];
+    for (int32_t s = bsrc0[d]; s < bsrc1[d]; ++s) {
+      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+      const double2 inv = cinv(y);
+      const double2 pw = cpowi(inv, m);
+      if (KIND & 1) {
+        const double q = sq[s];
+        if (m == 0) acc.x += q * (logs + 0.5 * log(y.x * y.x + y.y * y.y));
+        else acc = caxpy(-q * im, pw, acc);
+      }
+      if (KIND & 2) acc = cfma(cscale(sdip[s], is), cmul(pw, inv), acc);
+    }
+  }
+  L[(int64_t)b * P1 + m] = acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 7, L2L for the target-or-ancestor boxes of one level: child_m += sum_k T_q[m][k] parent_k.
+__global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restrict__ bparent,
+                                            const int8_t *__restrict__ bquad,
+                                            const int32_t *__restrict__ is_tbox,
+                                            const double2 *__restrict__ T, int P1,
+                                            double2 *__restrict__ L) {
+  const int32_t b = box0 + blockIdx.x;
+  const int m = threadIdx.x;
+  if (m >= P1 || !is_tbox[b]) return;
+  const int32_t p = bparent[b];
+  const double2 *Tq = T + ((int64_t)bquad[b] * P1 + m) * P1;
+  const double2 *Lp = L + (int64_t)p * P1;
+  double2 acc = L[(int64_t)b * P1 + m];
+  for (int k = m; k < P1; ++k) acc = cfma(Tq[k], Lp[k], acc);
+  L[(int64_t)b * P1 + m] = acc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Near-field accumulation of one source into a center's QBX coefficients (P2QBXL).
+// z = (y - c)/r. Charge part accumulates acc_m = sum q z^-m (m >= 1), normalised by -1/m later.
+template <int KIND, int PQ>
+struct NearAcc {
+  double2 a[PQ + 1];   // KIND 1: a_m = sum q z^-m (m>=1); KIND 2/3: final scaled coefficients
+  double logsum;       // sum q log|z|
+  double qsum;         // sum q
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) a[m] = make_double2(0.0, 0.0);
+    logsum = 0.0;
+    qsum = 0.0;
+  }
+  __device__ __forceinline__ void add(double2 z, double q, double2 dr) {
+    const double r2 = z.x * z.x + z.y * z.y;
+    const double ir2 = 1.0 / r2;
+    const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
+    if (KIND == 1) {
+      logsum = fma(q, log(r2), logsum);
+      qsum += q;
+      double2 pw = inv;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+        a[m] = caxpy(q, pw, a[m]);
+        if (m < PQ) pw = cmul(pw, inv);
+      }
+    } else if (KIND == 2) {
+      double2 pw = cmul(dr, inv);
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) {
+        a[m] = cadd(a[m], pw);
+        if (m < PQ) pw = cmul(pw, inv);
+      }
+    } else {
+      logsum = fma(q, log(r2), logsum);
+      qsum += q;
+      const double2 e = cmul(dr, inv);
+      a[0] = cadd(a[0], e);
+      double2 pw = inv;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+        const double2 coef = make_double2(fma(-q, 1.0 / m, e.x), e.y);
+        a[m] = cfma(pw, coef, a[m]);
+        if (m < PQ) pw = cmul(pw, inv);
+      }
+    }
+  }
+  // Add the finished near-field coefficients into alpha (scaled by r^m), given log r.
+  __device__ __forceinline__ void finish(double2 *alpha, double logr) const {
+    if (KIND & 1) alpha[0].x += 0.5 * logsum + qsum * logr;
+    if (KIND == 1) {
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[m], alpha[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], a[m]);
+    }
+  }
+};
+
+// QBX expansion of a center evaluated at its targets (QBXL2P), written to the target slots.
+template <int PQ>
+__device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, const double2 *alpha,
+                                             const int32_t *__restrict__ c2t_start,
+                                             const int32_t *__restrict__ c2t_slot,
+                                             const double2 *__restrict__ txy, double *__restrict__ tv) {
+  const double ir = 1.0 / r;
+  for (int32_t g = c2t_start[c]; g < c2t_start[c + 1]; ++g) {
+    const int32_t slot = c2t_slot[g];
+    const double2 x = txy[slot >> 1];
+    const double2 z = make_double2((x.x - cc.x) * ir, (x.y - cc.y) * ir);
+    double2 s = alpha[PQ];
+#pragma unroll
+    for (int m = PQ - 1; m >= 0; --m) s = cfma(s, z, alpha[m]);
+    tv[slot] = -kInv2Pi * s.x;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stages 3, 5, 6a, 8 per center: L2QBXL (box local -> center), M2QBXL (List 3 far multipoles ->
+// center), P2QBXL (List 1, 3 close, 4 close sources -> center), then QBXL2P at its targets.
+// One thread per center (tree order, so a wave covers centers of a few neighbouring boxes).
+template <int KIND, int PQ>
+__global__ void __launch_bounds__(256) k_qbx_center(
+    int32_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const int32_t *__restrict__ cbox, const double2 *__restrict__ bc,
+    const int32_t *__restrict__ blevel, const double *__restrict__ level_side,
+    const double2 *__restrict__ L, const double2 *__restrict__ M, int P1,
+    const double *__restrict__ l2q_binom, const double *__restrict__ m2q_binom,
+    const int32_t *__restrict__ wf_start, const int32_t *__restrict__ wf_idx,
+    const int32_t *__restrict__ near_row, const int32_t *__restrict__ near_lo,
+    const int32_t *__restrict__ near_hi, const double2 *__restrict__ sxy,
+    const double *__restrict__ sq, const double2 *__restrict__ sdip,
+    const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
+    const double2 *__restrict__ txy, double *__restrict__ tv) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double2 cc = cxy[c];
+  const double r = cr[c];
+  const int32_t b = cbox[c];
+  double2 alpha[PQ + 1];
+
+  // L2QBXL: alpha_m = (r/s)^m sum_{k>=m} C(k,m) b_k t^(k-m), t = (c - c_b)/s  (Horner in t)
+  {
+    const double s = level_side[blevel[b]];
+    const double is = 1.0 / s;
+    const double2 t = make_double2((cc.x - bc[b].x) * is, (cc.y - bc[b].y) * is);
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+    const double2 *Lb = L + (int64_t)b * P1;
+    for (int k = P1 - 1; k >= 0; --k) {
+      const double2 bk = Lb[k];
+      const double *Ck = l2q_binom + (int64_t)k * (PQ + 1);
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m)
+        if (m <= k) alpha[m] = caxpy(Ck[m], bk, cmul(alpha[m], t));
+    }
+    const double rs = r * is;
+    double f = rs;
+#pragma unroll
+    for (int m = 1; m <= PQ; ++m) {
+      alpha[m] = cscale(alpha[m], f);
+      f *= rs;
+    }
+  }
+
+  // M2QBXL over List 3 far: alpha_m += (-r/y)^m [-a_0/m + sum_k C(m+k-1,k-1) a_k (s_d/y)^k],
+  // alpha_0 += a_0 log|y| + sum_k a_k (s_d/y)^k, y = c - c_d          (eq. (m2l), corrected)
+  for (int32_t j = wf_start[b]; j < wf_start[b + 1]; ++j) {
+    const int32_t d = wf_idx[j];
+    const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
+    const double2 iy = cinv(y);
+    const double2 w = cscale(iy, level_side[blevel[d]]);
+    const double2 u = cscale(iy, -r);
+    const double2 *Md = M + (int64_t)d * P1;
+    const double a0 = Md[0].x;
+    alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
+    {
+      double2 pm = u;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+        alpha[m] = caxpy(-a0 / m, pm, alpha[m]);
+        pm = cmul(pm, u);
+      }
+    }
+    double2 wk = make_double2(1.0, 0.0);
+    for (int k = 1; k < P1; ++k) {
+      wk = cmul(wk, w);
+      double2 P = cmul(Md[k], wk);
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) {
+        alpha[m] = caxpy(m2q_binom[m * P1 + k], P, alpha[m]);
+        P = cmul(P, u);
+      }
+    }
+  }
+
+  // P2QBXL over the merged near-field source ranges
+  {
+    NearAcc<KIND, PQ> acc;
+    acc.zero();
+    const double ir = 1.0 / r;
+    for (int32_t g = near_row[b]; g < near_row[b + 1]; ++g) {
+      for (int32_t s = near_lo[g]; s < near_hi[g]; ++s) {
+        const double2 z = make_double2((sxy[s].x - cc.x) * ir, (sxy[s].y - cc.y) * ir);
+        acc.add(z, (KIND & 1) ? sq[s] : 0.0,
+                (KIND & 2) ? cscale(sdip[s], ir) : make_double2(0.0, 0.0));
+      }
+    }
+    acc.finish(alpha, log(r));
+  }
+  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
+}
+
+// ------------------------------------------------------------------------------------------
+// Direct (unaccelerated) QBX: every center takes every source, staged through LDS tiles.
+template <int KIND, int PQ>
+__global__ void __launch_bounds__(256) k_direct(
+    int32_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr, int32_t ns,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, const int32_t *__restrict__ c2t_start,
+    const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
+    double *__restrict__ tv) {
+  __shared__ double2 ts[256];
+  __shared__ double tq[256];
+  __shared__ double2 td[256];
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = c < nc;
+  const double2 cc = active ? cxy[c] : make_double2(0.0, 0.0);
+  const double r = active ? cr[c] : 1.0;
+  const double ir = 1.0 / r;
+  NearAcc<KIND, PQ> acc;
+  acc.zero();
+  for (int32_t base = 0; base < ns; base += 256) {
+    const int32_t n = min(256, ns - base);
+    __syncthreads();
+    if ((int32_t)threadIdx.x < n) {
+      ts[threadIdx.x] = sxy[base + threadIdx.x];
+      if (KIND & 1) tq[threadIdx.x] = sq[base + threadIdx.x];
+      if (KIND & 2) td[threadIdx.x] = sdip[base + threadIdx.x];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int32_t j = 0; j < n; ++j) {
+      const double2 z = make_double2((ts[j].x - cc.x) * ir, (ts[j].y - cc.y) * ir);
+      acc.add(z, (KIND & 1) ? tq[j] : 0.0, (KIND & 2) ? cscale(td[j], ir) : make_double2(0.0, 0.0));
+    }
+  }
+  if (!active) return;
+  double2 alpha[PQ + 1];
+#pragma unroll
+  for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+  acc.finish(alpha, log(r));
+  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
+}
+
+// ------------------------------------------------------------------------------------------
+// Average the target slots into the caller's output row.
+__global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const double *__restrict__ tv,
+                           double *__restrict__ out) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double s = 0.0;
+  int n = 0;
+  if (tctr[2 * t] >= 0) { s += tv[2 * t]; n++; }
+  if (tctr[2 * t + 1] >= 0) { s += tv[2 * t + 1]; n++; }
+  out[t] = n == 2 ? 0.5 * s : s;
+}
+
+template <int KIND>
+hipError_t launch_gather(gq_ctx *ctx, const double *d1, const double *d2) {
+  const int32_t ns = (int32_t)ctx->ns;
+  hipLaunchKernelGGL(k_gather<KIND>, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, ns,
+                     ctx->d.sperm, ctx->d.sw, ctx->d.snrm, d1, d2, ctx->d.sq, ctx->d.sdip);
+  return hipGetLastError();
+}
+
+template <int KIND, int PQ>
+hipError_t launch_fmm(gq_ctx *ctx) {
+  auto &d = ctx->d;
+  auto &t = ctx->tree;
+  const int P1 = ctx->params.p_fmm + 1;
+  const hipStream_t st = ctx->stream;
+  const int32_t nleaf = (int32_t)t.n_leaves;
+  if (nleaf > 0)
+    hipLaunchKernelGGL(k_p2m<KIND>, dim3(nleaf), dim3(64), 0, st, d.leaves, d.bc, d.blevel, d.bsrc0,
+                       d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, d.M);
+  for (int l = t.n_levels - 2; l >= 0; --l) {
+    const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+    if (nb > 0) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m, P1, d.M);
+  }
+  const int32_t ntb = (int32_t)ctx->n_tboxes;
+  if (ntb > 0)
+    hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
+                       d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
+                       d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2lb, d.opow, d.ologabs, d.sxy, d.sq,
+                       d.sdip, P1, d.L);
+  for (int l = 1; l < t.n_levels; ++l) {
+    const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+    if (nb > 0)
+      hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
+                         d.l2l, P1, d.L);
+  }
+  const int32_t nc = (int32_t)ctx->nc;
+  hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, st, nc, d.cxy,
+                     d.cr, d.cbox, d.bc, d.blevel, d.level_side, d.L, d.M, P1, d.l2q_binom,
+                     d.m2q_binom, d.wf_start, d.wf_idx, d.near_row, d.near_lo, d.near_hi, d.sxy,
+                     d.sq, d.sdip, d.c2t_start, d.c2t_slot, d.txy, d.tv);
+  return hipGetLastError();
+}
+
+template <int KIND, int PQ>
+hipError_t launch_direct(gq_ctx *ctx) {
+  auto &d = ctx->d;
+  const int32_t nc = (int32_t)ctx->nc;
+  hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, ctx->stream, nc,
+                     d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip, d.c2t_start, d.c2t_slot,
+                     d.txy, d.tv);
+  return hipGetLastError();
+}
+
+template <int PQ>
+hipError_t dispatch_kind(gq_ctx *ctx, int kind, bool direct) {
+  switch (kind) {
+    case 1: return direct ? launch_direct<1, PQ>(ctx) : launch_fmm<1, PQ>(ctx);
+    case 2: return direct ? launch_direct<2, PQ>(ctx) : launch_fmm<2, PQ>(ctx);
+    case 3: return direct ? launch_direct<3, PQ>(ctx) : launch_fmm<3, PQ>(ctx);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool pq_supported(int pq) {
+  switch (pq) {
+#define GQ_CASE(P) case P:
+    GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+    return true;
+  }
+  return false;
+}
+
+hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, double *out,
+                    bool direct) {
+  hipError_t e;
+  switch (kind) {
+    case 1: e = launch_gather<1>(ctx, d1, d2); break;
+    case 2: e = launch_gather<2>(ctx, d1, d2); break;
+    case 3: e = launch_gather<3>(ctx, d1, d2); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (ctx->pq_bucket) {
+#define GQ_CASE(P) \
+  case P: e = dispatch_kind<P>(ctx, kind, direct); break;
+    GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int32_t nt = (int32_t)ctx->nt;
+  hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256), dim3(256), 0, ctx->stream, nt, ctx->d.tctr,
+                     ctx->d.tv, out);
+  return hipGetLastError();
+}
+
+}  // namespace gq

@@ -1,0 +1,94 @@
+// Fixed translation tables for scaled expansions (see tables.hpp for the scaling and the reading
+// of eq. (m2l)). Computed once per FMM order in long double and rounded to FP64.
+#include "tables.hpp"
+
+#include <cmath>
+#include <complex>
+
+namespace gq {
+
+using cld = std::complex<long double>;
+
+void build_tables(Tables &t, int p) {
+  t = Tables();
+  t.p = p;
+  const int P1 = p + 1;
+  const int NB = 2 * p + 2;
+  t.binom.assign((size_t)NB * NB, 0.0);
+  std::vector<long double> pas((size_t)NB * NB, 0.0L);
+  for (int n = 0; n < NB; ++n) {
+    pas[(size_t)n * NB] = 1.0L;
+    for (int k = 1; k <= n; ++k)
+      pas[(size_t)n * NB + k] = pas[(size_t)(n - 1) * NB + k - 1] + (k <= n - 1 ? pas[(size_t)(n - 1) * NB + k] : 0.0L);
+  }
+  for (size_t i = 0; i < pas.size(); ++i) t.binom[i] = (double)pas[i];
+  auto C = [&](int n, int k) -> long double {
+    if (k < 0 || n < 0 || k > n) return 0.0L;
+    return pas[(size_t)n * NB + k];
+  };
+  auto cpow = [](cld z, int n) {
+    cld r(1.0L, 0.0L);
+    for (int i = 0; i < n; ++i) r *= z;
+    return r;
+  };
+
+  t.m2m.assign((size_t)4 * P1 * P1 * 2, 0.0);
+  t.l2l.assign((size_t)4 * P1 * P1 * 2, 0.0);
+  for (int q = 0; q < 4; ++q) {
+    const long double sx = (q & 1) ? 0.5L : -0.5L, sy = (q & 2) ? 0.5L : -0.5L;
+    // child center - parent center = s_child * u, u = (sx, sy)
+    const cld u(sx, sy);
+    const cld mv = u;  // -v with v = (parent - child)/s_child = -u
+    double *M = &t.m2m[(size_t)q * P1 * P1 * 2];
+    double *L = &t.l2l[(size_t)q * P1 * P1 * 2];
+    // M2M, eq. (m2m) with y = parent - child: alpha_m = -a_0 (-y)^m/m + sum_k C(m-1,k-1) a_k (-y)^(m-k)
+    for (int m = 0; m <= p; ++m) {
+      const long double s = std::pow(2.0L, -(long double)m);
+      for (int k = 0; k <= m; ++k) {
+        cld val;
+        if (m == 0) val = (k == 0) ? cld(1.0L) : cld(0.0L);
+        else if (k == 0) val = -cpow(mv, m) * (s / (long double)m);
+        else val = cpow(mv, m - k) * (C(m - 1, k - 1) * s);
+        M[((size_t)m * P1 + k) * 2] = (double)val.real();
+        M[((size_t)m * P1 + k) * 2 + 1] = (double)val.imag();
+      }
+    }
+    // L2L, eq. (l2l) with y = child - parent: beta_m = sum_{k>=m} C(k,m) b_k y^(k-m)
+    for (int m = 0; m <= p; ++m)
+      for (int k = m; k <= p; ++k) {
+        cld val = cpow(u, k - m) * (C(k, m) * std::pow(2.0L, -(long double)k));
+        L[((size_t)m * P1 + k) * 2] = (double)val.real();
+        L[((size_t)m * P1 + k) * 2 + 1] = (double)val.imag();
+      }
+  }
+
+  // M2L factor B, eq. (m2l) with the corrected sign of the a_0 term
+  t.m2l_b.assign((size_t)P1 * P1, 0.0);
+  for (int m = 0; m <= p; ++m)
+    for (int k = 0; k <= p; ++k) {
+      long double v;
+      if (m == 0) v = (k == 0) ? 0.0L : 1.0L;
+      else if (k == 0) v = ((m % 2) ? 1.0L : -1.0L) / (long double)m;
+      else v = ((m % 2) ? -1.0L : 1.0L) * C(m + k - 1, k - 1);
+      t.m2l_b[(size_t)m * P1 + k] = (double)v;
+    }
+
+  t.opow.assign((size_t)121 * P1 * 2, 0.0);
+  t.ologabs.assign(121, 0.0);
+  for (int i = 0; i < 11; ++i)
+    for (int j = 0; j < 11; ++j) {
+      const int oi = i * 11 + j;
+      const long double ox = i - 5, oy = j - 5;
+      if (std::max(std::fabs(ox), std::fabs(oy)) < 3) continue;  // never a List-2 offset
+      const cld inv = 1.0L / cld(ox, oy);
+      cld pw(1.0L);
+      for (int k = 0; k <= p; ++k) {
+        t.opow[((size_t)oi * P1 + k) * 2] = (double)pw.real();
+        t.opow[((size_t)oi * P1 + k) * 2 + 1] = (double)pw.imag();
+        pw *= inv;
+      }
+      t.ologabs[oi] = (double)(0.5L * std::log(ox * ox + oy * oy));
+    }
+}
+
+}  // namespace gq

@@ -1,0 +1,232 @@
+"""Tree and interaction lists (Stage 1, Sec. 4.3) checked by brute force on the host.
+
+Runs through a host-only library context (no GPU): the builder is the library's own C++.
+Checks, for every box that owns centers, that the sources reaching its centers through
+  direct evaluation      List 1 U List 3 close U List 4 close (leaf sources),
+  multipole -> QBX local List 3 far (subtree sources),
+  box local expansions   List 2 and List 4 far of the box and all its ancestors
+partition the source set exactly once; that every list entry satisfies its defining predicate
+(Definitions 1-9); the list-size bounds of Sec. 4.6 (|List 2| <= 75, |List 4 close| <= 42,
+|List 4 far| <= 63); and that every owned center's disk lies inside its box's target
+confinement region.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gq_inputs as gi
+from paper_1801_04070_amd import QBXFMM, _lib
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+def _build(geom, **kw):
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(geom)
+    stats = q.build(**kw)
+    T = {
+        "level": q.tree_array(_lib.GQ_TREE_BOX_LEVEL),
+        "parent": q.tree_array(_lib.GQ_TREE_BOX_PARENT),
+        "child": q.tree_array(_lib.GQ_TREE_BOX_CHILD),
+        "ij": q.tree_array(_lib.GQ_TREE_BOX_IJ),
+        "src": q.tree_array(_lib.GQ_TREE_BOX_SRC_RANGE),
+        "ctr": q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE),
+        "src_order": q.tree_array(_lib.GQ_TREE_SRC_ORDER),
+        "ctr_order": q.tree_array(_lib.GQ_TREE_CTR_ORDER),
+    }
+    T.update(q.lists())
+    T["stats"] = stats
+    lo = np.array(stats["root_lo"])
+    side = stats["root_side"] / 2.0 ** T["level"]
+    T["half"] = 0.5 * side
+    T["center"] = lo[None, :] + (T["ij"] + 0.5) * side[:, None]
+    T["leaf"] = (T["child"] < 0).all(axis=1)
+    return q, T
+
+
+def _row(T, name, b):
+    st, ix = T[name]
+    return ix[st[b]:st[b + 1]]
+
+
+def _linf(T, a, b):
+    return np.abs(T["center"][a] - T["center"][b]).max()
+
+
+def _adjacent(T, a, b):
+    return _linf(T, a, b) <= T["half"][a] + T["half"][b] * (1 + 1e-15) + 1e-300
+
+
+def _ancestors(T, b):
+    out = []
+    while b >= 0:
+        out.append(b)
+        b = T["parent"][b]
+    return out
+
+
+GEOMS = {
+    "c1": lambda: gi.starfish_c1(),
+    "three_stars": lambda: gi.random_stars(n_curves=3, panels_per_curve=40, seed=4, box=8.0),
+    "circle_small_boxes": lambda: gi.unit_circle(48),
+}
+
+
+def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15):
+    q, T = _build(geom, p_qbx=8, p_fmm=10, t_f=t_f, n_max=n_max, count_mode=count_mode,
+                  w3far_min_sources=w3)
+    nb = len(T["level"])
+    ns = geom.n_src
+    src = T["src"]
+    # ---- particles: orders are permutations, box ranges consistent ----
+    assert np.array_equal(np.sort(T["src_order"]), np.arange(ns))
+    assert np.array_equal(np.sort(T["ctr_order"]), np.arange(geom.n_ctr))
+    assert src[0, 0] == 0 and src[0, 1] == ns
+    for b in range(nb):
+        kids = [c for c in T["child"][b] if c >= 0]
+        if kids:
+            # non-leaf boxes own no sources: the subtree range is the union of the children's
+            assert sum(src[c, 1] - src[c, 0] for c in kids) == src[b, 1] - src[b, 0]
+    # every source lies in its leaf's closed square; every owned center disk fits the TCR
+    xy = geom.src_xy[T["src_order"]]
+    cxy = geom.ctr_xy[T["ctr_order"]]
+    cr = geom.ctr_r[T["ctr_order"]]
+    for b in range(nb):
+        s0, s1 = src[b]
+        if T["leaf"][b] and s1 > s0:
+            d = np.abs(xy[s0:s1] - T["center"][b]).max()
+            assert d <= T["half"][b] * (1 + 1e-12)
+        c0, c1 = T["ctr"][b]
+        if c1 > c0 and b != 0:
+            reach = np.abs(cxy[c0:c1] - T["center"][b]).max(axis=1) + cr[c0:c1]
+            assert (reach <= T["half"][b] * (1 + t_f) * (1 + 1e-12)).all()
+    # subdivision rule: a leaf owns at most n_max particles eligible for children (sources, and
+    # centers whose disk would fit the TCR of the child containing them), unless at max depth
+    for b in range(nb):
+        if T["leaf"][b]:
+            c0, c1 = T["ctr"][b]
+            hc = 0.5 * T["half"][b]
+            quad = (cxy[c0:c1] >= T["center"][b]).astype(float) * 2 - 1
+            chc = T["center"][b] + quad * hc
+            elig = (np.abs(cxy[c0:c1] - chc).max(axis=1) + cr[c0:c1] <= hc * (1 + t_f)).sum()
+            cnt = (src[b, 1] - src[b, 0]) + (elig if count_mode == 0 else 0)
+            assert cnt <= n_max or T["level"][b] == T["stats"]["n_levels"] - 1
+    # ---- exact-once coverage and predicates for every box owning centers ----
+    tf1 = 1 + t_f
+    counts = {"list2": 0, "list4c": 0, "list4f": 0}
+    for b in range(nb):
+        for name in counts:
+            counts[name] = max(counts[name], len(_row(T, name, b)))
+        if T["ctr"][b, 1] == T["ctr"][b, 0]:
+            continue
+        ranges = []
+        for name in ("list1", "list3c", "list4c"):
+            for d in _row(T, name, b):
+                assert T["leaf"][d], name
+                ranges.append(tuple(src[d]))
+        for d in _row(T, "list3f", b):
+            ranges.append(tuple(src[d]))
+        for w in _ancestors(T, b):
+            for d in _row(T, "list2", w):
+                ranges.append(tuple(src[d]))
+            for d in _row(T, "list4f", w):
+                ranges.append(tuple(src[d]))
+        ranges = sorted(r for r in ranges if r[1] > r[0])
+        assert ranges[0][0] == 0 and ranges[-1][1] == ns, "coverage does not span all sources"
+        for r0, r1 in zip(ranges[:-1], ranges[1:]):
+            assert r0[1] == r1[0], f"box {b}: gap or overlap between source ranges {r0} {r1}"
+        # predicates
+        for d in _row(T, "list1", b):
+            assert _adjacent(T, b, d)
+        for d in _row(T, "list3f", b):
+            assert _linf(T, d, b) >= 3 * T["half"][d] + T["half"][b] * tf1 * (1 - 1e-12)
+            assert not _adjacent(T, b, d) and T["level"][d] > T["level"][b]
+        if w3 == 0:
+            for d in _row(T, "list3c", b):
+                assert _linf(T, d, b) < 3 * T["half"][d] + T["half"][b] * tf1
+                assert not _adjacent(T, b, d)
+        for d in _row(T, "list4c", b):
+            assert _linf(T, d, b) < 3 * T["half"][b] * tf1 + T["half"][d]
+    for b in range(nb):
+        for d in _row(T, "list2", b):
+            assert T["level"][d] == T["level"][b]
+            assert np.abs(T["ij"][d] - T["ij"][b]).max() in (3, 4, 5)  # 2-well-separated
+        for d in _row(T, "list4f", b):
+            assert _linf(T, d, b) >= 3 * T["half"][b] * tf1 + T["half"][d] * (1 - 1e-12)
+            assert T["leaf"][d] and T["level"][d] <= T["level"][b]
+            assert not _adjacent(T, b, d)
+    return T, counts
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+@pytest.mark.parametrize("count_mode", [0, 1])
+def test_lists_partition_sources(name, count_mode):
+    _check_tree(GEOMS[name](), count_mode=count_mode)
+
+
+@pytest.mark.parametrize("t_f", [0.0, 0.5, 0.9])
+@pytest.mark.parametrize("n_max", [8, 32])
+def test_lists_partition_deep_trees(t_f, n_max):
+    # small n_max forces deep adaptive trees with many suspended centers
+    _check_tree(gi.random_stars(n_curves=2, panels_per_curve=24, seed=9, box=6.0), t_f=t_f,
+                n_max=n_max, w3=0)
+
+
+def test_remark1_demotion_keeps_partition():
+    T0, _ = _check_tree(gi.starfish_c1(), n_max=16, w3=0)
+    T1, _ = _check_tree(gi.starfish_c1(), n_max=16, w3=15)
+    assert len(T1["list3f"][1]) <= len(T0["list3f"][1])
+
+
+def test_list_size_bounds():
+    with open(GOLDEN) as f:
+        const = json.load(f)
+    for name in GEOMS:
+        _, counts = _check_tree(GEOMS[name]())
+        assert counts["list2"] <= const["max_list2"]["value"]
+        assert counts["list4c"] <= const["max_list4_close"]["value"]
+        assert counts["list4f"] <= const["max_list4_far"]["value"]
+
+
+def test_root_square_is_dyadic_and_covers_disks():
+    g = gi.starfish_c1()
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(g)
+    s = q.build(p_qbx=8, p_fmm=10)
+    side = s["root_side"]
+    assert side == 2.0 ** round(np.log2(side))
+    lo = np.array(s["root_lo"])
+    assert (g.ctr_xy - g.ctr_r[:, None] >= lo).all()
+    assert (g.ctr_xy + g.ctr_r[:, None] < lo + side).all()
+
+
+def test_error_paths_host_context():
+    from paper_1801_04070_amd import GQError
+    g = gi.starfish_c1()
+    q = QBXFMM(device=-1)
+    with pytest.raises(GQError) as e:
+        q.build(p_qbx=8, p_fmm=10)
+    assert e.value.status == _lib.GQ_ESTATE
+    bad = g.src_xy.copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(GQError) as e:
+        q.set_geometry(bad, g.src_nrm, g.src_w, g.ctr_xy, g.ctr_r, g.tgt_xy, g.tgt_ctr)
+    assert e.value.status == _lib.GQ_EINVAL
+    q.set_geometry_from(g)
+    with pytest.raises(GQError) as e:
+        q.build(p_qbx=8, p_fmm=10, n_max=0)
+    assert e.value.status == _lib.GQ_EINVAL
+    with pytest.raises(GQError) as e:
+        q.build(p_qbx=8, p_fmm=99)
+    assert e.value.status == _lib.GQ_EUNSUP
+    # coincident particles stop at the depth guard instead of recursing forever
+    n = 200
+    same = np.zeros((n, 2))
+    nrm = np.tile([1.0, 0.0], (n, 1))
+    q2 = QBXFMM(device=-1)
+    q2.set_geometry(same, nrm, np.ones(n), np.array([[0.5, 0.0]]), np.array([0.1]),
+                    np.zeros((1, 2)), np.array([[0, -1]], np.int32))
+    s = q2.build(p_qbx=8, p_fmm=10, n_max=8, max_levels=12)
+    assert s["n_levels"] == 12
