@@ -142,6 +142,8 @@ typedef struct {
   int64_t near_pairs;            /* (center, source) pairs evaluated directly             */
   int64_t list3_far_pairs;       /* (center, box) multipole-to-QBX-local pairs            */
   int64_t list4_far_sources;     /* (box, source) pairs formed into box locals            */
+  int64_t near_sources;          /* sum over boxes owning centers of their direct sources  */
+  int64_t n_local_boxes;         /* target-or-ancestor boxes (boxes with a local expansion) */
   int64_t max_list2, max_list4, max_list4_close, max_list4_far;
   double root_lo[2];
   double root_side;
@@ -170,6 +172,28 @@ enum {
   GQ_LIST3F_START, GQ_LIST3F, GQ_LIST4C_START, GQ_LIST4C, GQ_LIST4F_START, GQ_LIST4F
 };
 gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count);
+
+/*
+ * Per-stage device timing for profiling. When enabled, every evaluation records a HIP event pair
+ * on the context's stream around each stage; gq_get_stage_times synchronises the stream, adds
+ * the elapsed times since the last query into ms[(kind - 1) * GQ_N_STAGES + stage] (caller
+ * arrays of 3 * GQ_N_STAGES doubles / int64 counts), and clears the records. Disabled by default.
+ */
+enum {
+  GQ_STAGE_GATHER = 0,   /* densities -> per-source strengths in tree order                */
+  GQ_STAGE_P2M,          /* Stage 2a                                                        */
+  GQ_STAGE_M2M,          /* Stage 2b (all levels)                                           */
+  GQ_STAGE_M2L_P2L,      /* Stages 4 and 6b: box locals from List 2 and List 4 far          */
+  GQ_STAGE_L2L,          /* Stage 7 (all levels)                                            */
+  GQ_STAGE_NEAR,         /* Stages 3, 5a, 6a: direct sources -> QBX centers (P2QBXL)        */
+  GQ_STAGE_M2QBXL,       /* Stage 5b: List 3 far multipoles -> QBX centers                  */
+  GQ_STAGE_QBX_CENTER,   /* Stage 8 per center (L2QBXL) and evaluation at the targets      */
+  GQ_STAGE_FINALIZE,     /* average of the one or two center values per target              */
+  GQ_STAGE_DIRECT,       /* unaccelerated QBX (gq_eval_direct)                              */
+  GQ_N_STAGES
+};
+gq_status gq_set_profiling(gq_ctx *ctx, int enable);
+gq_status gq_get_stage_times(gq_ctx *ctx, double *ms, int64_t *count);
 
 /* Message describing the last failure on this context (or on creation, with ctx NULL). */
 const char *gq_last_error(gq_ctx *ctx);

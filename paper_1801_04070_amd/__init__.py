@@ -160,6 +160,23 @@ class QBXFMM:
                  "list4c": _lib.GQ_LIST4C_START, "list4f": _lib.GQ_LIST4F_START}
         return {k: (self.tree_array(v), self.tree_array(v + 1)) for k, v in names.items()}
 
+    def set_profiling(self, enable: bool = True):
+        self._check(self._L.gq_set_profiling(self._h, int(enable)))
+
+    def stage_times(self) -> dict:
+        """{(kind, stage_name): (total_ms, launches)} since the last call (synchronises)."""
+        n = 3 * _lib.GQ_N_STAGES
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        self._check(self._L.gq_get_stage_times(self._h, ms, cnt))
+        out = {}
+        for k in range(3):
+            for s, name in enumerate(_lib.GQ_STAGE_NAMES):
+                i = k * _lib.GQ_N_STAGES + s
+                if cnt[i]:
+                    out[(k + 1, name)] = (ms[i], cnt[i])
+        return out
+
     def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
         """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or
         (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt)."""

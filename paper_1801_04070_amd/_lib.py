@@ -33,13 +33,18 @@ class gq_stats(C.Structure):
         "n_src", "n_ctr", "n_tgt", "n_boxes", "n_levels", "n_leaves", "n_target_boxes",
         "n_suspended_centers", "n_list1", "n_list2", "n_list3_close", "n_list3_far",
         "n_list4_close", "n_list4_far", "near_pairs", "list3_far_pairs", "list4_far_sources",
+        "near_sources", "n_local_boxes",
         "max_list2", "max_list4", "max_list4_close", "max_list4_far")] + [
         ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double)]
 
 
+GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",
+                  "finalize", "direct"]
+GQ_N_STAGES = len(GQ_STAGE_NAMES)
+
 EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
-            "gq_last_error"]
+            "gq_set_profiling", "gq_get_stage_times", "gq_last_error"]
 
 
 def load(path: str = LIB_PATH):
@@ -59,6 +64,8 @@ def load(path: str = LIB_PATH):
     L.gq_eval_direct.argtypes = L.gq_eval.argtypes
     L.gq_get_stats.argtypes = [vp, C.POINTER(gq_stats)]
     L.gq_get_tree_array.argtypes = [vp, i32, vp, C.POINTER(C.c_int64)]
+    L.gq_set_profiling.argtypes = [vp, i32]
+    L.gq_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.gq_last_error.argtypes = [vp]
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:

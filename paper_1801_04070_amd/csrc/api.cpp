@@ -72,6 +72,82 @@ std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
     if (s_ != GQ_OK) return s_;      \
   } while (0)
 
+// Direct-interaction work (Stages 3, 5a, 6a) and multipole-to-QBX-local work (Stage 5b) are split
+// into items of one wavefront each: a box, one chunk of its direct sources (at most kNearChunk)
+// or of its List 3 far boxes (at most kFarChunk), and a block of n_cl of its centers. The wave
+// runs n_cl centers x (64 / n_cl) slices over the chunk; n_cl is the power of two minimising a
+// simple cost model (per-element work + slice reduction + fixed cost per wave). Each (center,
+// chunk) result goes to its own row; the rows of a box are laid out [chunk][center], direct
+// chunks first.
+constexpr int kNearChunk = 1024;
+constexpr int kFarChunk = 16;
+
+int pick_lg(int64_t nc, int64_t len, double elem_cost) {
+  int best_lg = 0;
+  double best = 1e300;
+  for (int lg = 0; lg <= 6; ++lg) {
+    const int64_t ncl = int64_t(1) << lg, nsl = 64 >> lg;
+    const double waves = (double)((nc + ncl - 1) / ncl);
+    const double cost = waves * ((double)((len + nsl - 1) / nsl) * elem_cost + (6 - lg) * 60.0 + 150.0);
+    if (cost <= best) { best = cost; best_lg = lg; }
+  }
+  return best_lg;
+}
+
+gq_status upload_near_work(gq_ctx *ctx) {
+  const gq::Tree &t = ctx->tree;
+  auto &d = ctx->d;
+  const int64_t nb = t.n_boxes();
+  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems;
+  int64_t rows = 0;
+  auto emit = [](std::vector<int32_t> &out, int64_t off, int64_t clen, int64_t ctr0, int64_t row0,
+                 int64_t nc, int lg) {
+    const int64_t ncl = int64_t(1) << lg;
+    for (int64_t cb = 0; cb < nc; cb += ncl) {
+      const int32_t item[8] = {(int32_t)off, (int32_t)clen, (int32_t)(ctr0 + cb), (int32_t)(row0 + cb),
+                               (int32_t)std::min<int64_t>(ncl, nc - cb), lg, 0, 0};
+      out.insert(out.end(), item, item + 8);
+    }
+  };
+  for (int64_t b = 0; b < nb; ++b) {
+    bctr0[b] = (int32_t)t.ctr_begin[b];
+    bctr1[b] = (int32_t)t.ctr_end[b];
+    const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
+    if (nc == 0) continue;
+    const int64_t off = (int64_t)src.size();
+    for (int64_t g = t.near_row[b]; g < t.near_row[b + 1]; ++g)
+      for (int64_t s = t.near_lo[g]; s < t.near_hi[g]; ++s) src.push_back((int32_t)s);
+    const int64_t len = (int64_t)src.size() - off;
+    const int64_t nchunks = (len + kNearChunk - 1) / kNearChunk;
+    const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
+    const int64_t fchunks = (wlen + kFarChunk - 1) / kFarChunk;
+    base[b] = (int32_t)rows;
+    nch[b] = (int32_t)(nchunks + fchunks);
+    for (int64_t j = 0; j < nchunks; ++j) {
+      const int64_t c0 = j * kNearChunk, clen = std::min<int64_t>(kNearChunk, len - c0);
+      emit(items, off + c0, clen, t.ctr_begin[b], rows + j * nc, nc, pick_lg(nc, clen, 120.0));
+    }
+    for (int64_t j = 0; j < fchunks; ++j) {
+      const int64_t c0 = j * kFarChunk, clen = std::min<int64_t>(kFarChunk, wlen - c0);
+      emit(fitems, woff + c0, clen, t.ctr_begin[b], rows + (nchunks + j) * nc, nc,
+           pick_lg(nc, clen, 2400.0));
+    }
+    rows += (nchunks + fchunks) * nc;
+  }
+  ctx->n_near_items = (int64_t)items.size() / 8;
+  ctx->n_far_items = (int64_t)fitems.size() / 8;
+  ctx->n_near_rows = rows;
+  GQ_TRY(upload(ctx, d.near_src, src.data(), src.size()));
+  GQ_TRY(upload(ctx, d.near_items, items.data(), items.size() / 4));
+  GQ_TRY(upload(ctx, d.far_items, fitems.data(), fitems.size() / 4));
+  GQ_TRY(upload(ctx, d.bctr0, bctr0.data(), nb));
+  GQ_TRY(upload(ctx, d.bctr1, bctr1.data(), nb));
+  GQ_TRY(upload(ctx, d.part_base, base.data(), nb));
+  GQ_TRY(upload(ctx, d.n_chunks, nch.data(), nb));
+  GQ_TRY(alloc(ctx, d.anear, (size_t)std::max<int64_t>(rows, 1) * (ctx->pq_bucket + 1)));
+  return GQ_OK;
+}
+
 gq_status upload_all(gq_ctx *ctx) {
   const gq::Tree &t = ctx->tree;
   auto &d = ctx->d;
@@ -162,9 +238,7 @@ gq_status upload_all(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.wf_idx, t.list3f.idx.data(), t.list3f.idx.size()));
   GQ_TRY(upload(ctx, d.xf_start, to_i32(t.list4f.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.xf_idx, t.list4f.idx.data(), t.list4f.idx.size()));
-  GQ_TRY(upload(ctx, d.near_row, to_i32(t.near_row).data(), nb + 1));
-  GQ_TRY(upload(ctx, d.near_lo, to_i32(t.near_lo).data(), t.near_lo.size()));
-  GQ_TRY(upload(ctx, d.near_hi, to_i32(t.near_hi).data(), t.near_hi.size()));
+  GQ_TRY(upload_near_work(ctx));
   // tables
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
@@ -174,7 +248,7 @@ gq_status upload_all(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
   GQ_TRY(upload(ctx, d.ologabs, tb.ologabs.data(), tb.ologabs.size()));
   {
-    const int NB = 2 * tb.p + 2;
+    const int NB = tb.nbinom;
     auto C = [&](int n, int k) { return (k < 0 || k > n || n >= NB) ? 0.0 : tb.binom[(size_t)n * NB + k]; };
     std::vector<double> l2q((size_t)P1 * (PQ + 1)), m2q((size_t)(PQ + 1) * P1);
     for (int k = 0; k < P1; ++k)
@@ -261,7 +335,15 @@ gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
 
 gq_status gq_destroy(gq_ctx *ctx) {
   if (!ctx) return GQ_OK;
-  if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &r : ctx->prof) {
+      ctx->event_pool.push_back(r.a);
+      ctx->event_pool.push_back(r.b);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  }
   free_device(ctx);
   delete ctx;
   return GQ_OK;
@@ -352,7 +434,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
     return fail(ctx, GQ_ENOMEM, "host allocation during tree build");
   }
   if (!msg.empty()) return fail(ctx, GQ_EINVAL, msg);
-  gq::build_tables(ctx->tables, p.p_fmm);
+  gq::build_tables(ctx->tables, p.p_fmm, p.p_qbx);
   if (ctx->device >= 0) {
     GQ_HIP(ctx, hipSetDevice(ctx->device));
     gq_status st = upload_all(ctx);
@@ -390,6 +472,8 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   out->n_list4_close = (int64_t)t.list4c.idx.size(); out->n_list4_far = (int64_t)t.list4f.idx.size();
   out->near_pairs = t.near_pairs; out->list3_far_pairs = t.list3f_pairs;
   out->list4_far_sources = t.list4f_sources;
+  out->near_sources = t.near_sources;
+  out->n_local_boxes = t.n_local_boxes;
   for (int64_t b = 0; b < t.n_boxes(); ++b) {
     out->max_list2 = std::max(out->max_list2, t.list2.row_size(b));
     out->max_list4_close = std::max(out->max_list4_close, t.list4c.row_size(b));
@@ -446,6 +530,36 @@ gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count) {
   *count = (int64_t)n;
   if (dst && n) std::memcpy(dst, src, n * esz);
   return GQ_OK;
+}
+
+gq_status gq_set_profiling(gq_ctx *ctx, int enable) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context");
+  ctx->profiling = enable != 0;
+  return GQ_OK;
+}
+
+gq_status gq_get_stage_times(gq_ctx *ctx, double *ms, int64_t *count) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!ms || !count) return fail(ctx, GQ_EINVAL, "null output");
+  if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 3 * GQ_N_STAGES; ++i) { ms[i] = 0.0; count[i] = 0; }
+  gq_status st = GQ_OK;
+  for (auto &r : ctx->prof) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      ms[r.slot] += t;
+      count[r.slot] += 1;
+    } else {
+      st = fail(ctx, GQ_EHIP, "hipEventElapsedTime failed");
+    }
+    ctx->event_pool.push_back(r.a);
+    ctx->event_pool.push_back(r.b);
+  }
+  ctx->prof.clear();
+  return st;
 }
 
 const char *gq_last_error(gq_ctx *ctx) {

@@ -42,7 +42,14 @@ struct DevBuffers {
   int32_t *v_start = nullptr, *v_idx = nullptr, *v_off = nullptr;
   int32_t *wf_start = nullptr, *wf_idx = nullptr;
   int32_t *xf_start = nullptr, *xf_idx = nullptr;
-  int32_t *near_row = nullptr, *near_lo = nullptr, *near_hi = nullptr;
+  // direct (near-field) work: expanded source lists, balanced work items, partial-row layout
+  int32_t *near_src = nullptr;       // per box owning centers: its direct sources (tree order)
+  int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
+  int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
+  int32_t *bctr0 = nullptr, *bctr1 = nullptr;   // owned center range per box
+  int32_t *part_base = nullptr;      // first near row of each box
+  int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
+  double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
   double2 *m2m = nullptr, *l2l = nullptr, *opow = nullptr;
   double *m2lb = nullptr, *ologabs = nullptr;
@@ -73,7 +80,15 @@ struct gq_ctx {
   gq::Tables tables;
   int pq_bucket = 0;                 // compiled QBX order used by the kernels
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
+  int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   gq::DevBuffers d;
   std::vector<void *> allocations;   // every device allocation, freed together
   double build_ms = 0;
+
+  // stage profiling (HIP events on the context stream)
+  bool profiling = false;
+  int cur_kind = 1;
+  struct ProfRecord { int slot; hipEvent_t a, b; };
+  std::vector<ProfRecord> prof;
+  std::vector<hipEvent_t> event_pool;
 };

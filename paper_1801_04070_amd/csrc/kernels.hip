@@ -248,8 +248,146 @@ __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, co
 }
 
 // ------------------------------------------------------------------------------------------
-// Stages 3, 5, 6a, 8 per center: L2QBXL (box local -> center), M2QBXL (List 3 far multipoles ->
-// center), P2QBXL (List 1, 3 close, 4 close sources -> center), then QBXL2P at its targets.
+// Stages 3, 5a, 6a: P2QBXL from the direct sources (List 1, List 3 close, List 4 close) of a box
+// into its centers. One wavefront per work item (box, source chunk, block of n_cl centers): lane
+// = (center, slice) with 64/n_cl slices striding over the chunk's sources, then a fixed-order
+// xor-shuffle reduction over the slices. The result row holds the scaled coefficients.
+template <int KIND, int PQ>
+__global__ void __launch_bounds__(256) k_near(
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, double2 *__restrict__ anear) {
+  const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= n_items) return;  // uniform per wavefront
+  const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x, lg = i1.y;
+  const int nsl = 64 >> lg;
+  const int cl = lane >> (6 - lg);
+  const int sl = lane & (nsl - 1);
+  const bool active = cl < n_ctr;
+  const int32_t c = ctr_first + (active ? cl : 0);
+  const double2 cc = cxy[c];
+  const double r = cr[c];
+  const double ir = 1.0 / r;
+  NearAcc<KIND, PQ> acc;
+  acc.zero();
+  if (active) {
+    for (int32_t k = sl; k < len; k += nsl) {
+      const int32_t s = near_src[off + k];
+      const double2 z = make_double2((sxy[s].x - cc.x) * ir, (sxy[s].y - cc.y) * ir);
+      acc.add(z, (KIND & 1) ? sq[s] : 0.0,
+              (KIND & 2) ? cscale(sdip[s], ir) : make_double2(0.0, 0.0));
+    }
+  }
+  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      acc.a[m].x += __shfl_xor(acc.a[m].x, o, 64);
+      acc.a[m].y += __shfl_xor(acc.a[m].y, o, 64);
+    }
+    if (KIND & 1) {
+      acc.logsum += __shfl_xor(acc.logsum, o, 64);
+      acc.qsum += __shfl_xor(acc.qsum, o, 64);
+    }
+  }
+  if (active && sl == 0) {
+    double2 alpha[PQ + 1];
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+    acc.finish(alpha, log(r));
+    double2 *row = anear + (int64_t)(row_first + cl) * (PQ + 1);
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 5b, M2QBXL: the multipole of a List 3 far box d taken to the QBX local expansion of a
+// center c (eq. (m2l) with the corrected a_0 sign, truncated at order PQ), y = c - c_d:
+//   alpha_0 += a_0 log|y| + sum_k a_k (s_d/y)^k
+//   alpha_m += (-r/y)^m [-a_0/m + sum_k C(m+k-1,k-1) a_k (s_d/y)^k]
+template <int PQ>
+__device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r, int32_t d,
+                                           const double2 *__restrict__ bc,
+                                           const int32_t *__restrict__ blevel,
+                                           const double *__restrict__ level_side,
+                                           const double2 *__restrict__ M, int P1,
+                                           const double *__restrict__ m2q_binom) {
+  const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
+  const double2 iy = cinv(y);
+  const double2 w = cscale(iy, level_side[blevel[d]]);
+  const double2 u = cscale(iy, -r);
+  const double2 *Md = M + (int64_t)d * P1;
+  const double a0 = Md[0].x;
+  alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
+  {
+    double2 pm = u;
+#pragma unroll
+    for (int m = 1; m <= PQ; ++m) {
+      alpha[m] = caxpy(-a0 / m, pm, alpha[m]);
+      pm = cmul(pm, u);
+    }
+  }
+  double2 wk = make_double2(1.0, 0.0);
+  for (int k = 1; k < P1; ++k) {
+    wk = cmul(wk, w);
+    double2 P = cmul(Md[k], wk);
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      alpha[m] = caxpy(m2q_binom[m * P1 + k], P, alpha[m]);
+      P = cmul(P, u);
+    }
+  }
+}
+
+// Work items for Stage 5b, same item layout and lane mapping as k_near, the slices striding over
+// the chunk's List 3 far boxes.
+template <int PQ>
+__global__ void __launch_bounds__(256) k_m2qbxl(
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
+    const double *__restrict__ level_side, const double2 *__restrict__ M, int P1,
+    const double *__restrict__ m2q_binom, double2 *__restrict__ anear) {
+  const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= n_items) return;  // uniform per wavefront
+  const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x, lg = i1.y;
+  const int nsl = 64 >> lg;
+  const int cl = lane >> (6 - lg);
+  const int sl = lane & (nsl - 1);
+  const bool active = cl < n_ctr;
+  const int32_t c = ctr_first + (active ? cl : 0);
+  const double2 cc = cxy[c];
+  const double r = cr[c];
+  double2 alpha[PQ + 1];
+#pragma unroll
+  for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+  if (active)
+    for (int32_t e = sl; e < len; e += nsl)
+      m2qbxl_add<PQ>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1, m2q_binom);
+  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      alpha[m].x += __shfl_xor(alpha[m].x, o, 64);
+      alpha[m].y += __shfl_xor(alpha[m].y, o, 64);
+    }
+  }
+  if (active && sl == 0) {
+    double2 *row = anear + (int64_t)(row_first + cl) * (PQ + 1);
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 8 per center: L2QBXL (box local -> center), plus the direct and List 3 far rows from
+// k_near and k_m2qbxl, then QBXL2P at its targets.
 // One thread per center (tree order, so a wave covers centers of a few neighbouring boxes).
 template <int KIND, int PQ>
 __global__ void __launch_bounds__(256) k_qbx_center(
@@ -258,10 +396,9 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const int32_t *__restrict__ blevel, const double *__restrict__ level_side,
     const double2 *__restrict__ L, const double2 *__restrict__ M, int P1,
     const double *__restrict__ l2q_binom, const double *__restrict__ m2q_binom,
-    const int32_t *__restrict__ wf_start, const int32_t *__restrict__ wf_idx,
-    const int32_t *__restrict__ near_row, const int32_t *__restrict__ near_lo,
-    const int32_t *__restrict__ near_hi, const double2 *__restrict__ sxy,
-    const double *__restrict__ sq, const double2 *__restrict__ sdip,
+    const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
+    const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_chunks,
+    const double2 *__restrict__ anear,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv) {
   const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -295,50 +432,16 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     }
   }
 
-  // M2QBXL over List 3 far: alpha_m += (-r/y)^m [-a_0/m + sum_k C(m+k-1,k-1) a_k (s_d/y)^k],
-  // alpha_0 += a_0 log|y| + sum_k a_k (s_d/y)^k, y = c - c_d          (eq. (m2l), corrected)
-  for (int32_t j = wf_start[b]; j < wf_start[b + 1]; ++j) {
-    const int32_t d = wf_idx[j];
-    const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
-    const double2 iy = cinv(y);
-    const double2 w = cscale(iy, level_side[blevel[d]]);
-    const double2 u = cscale(iy, -r);
-    const double2 *Md = M + (int64_t)d * P1;
-    const double a0 = Md[0].x;
-    alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
-    {
-      double2 pm = u;
-#pragma unroll
-      for (int m = 1; m <= PQ; ++m) {
-        alpha[m] = caxpy(-a0 / m, pm, alpha[m]);
-        pm = cmul(pm, u);
-      }
-    }
-    double2 wk = make_double2(1.0, 0.0);
-    for (int k = 1; k < P1; ++k) {
-      wk = cmul(wk, w);
-      double2 P = cmul(Md[k], wk);
-#pragma unroll
-      for (int m = 0; m <= PQ; ++m) {
-        alpha[m] = caxpy(m2q_binom[m * P1 + k], P, alpha[m]);
-        P = cmul(P, u);
-      }
-    }
-  }
-
-  // P2QBXL over the merged near-field source ranges
+  // direct (P2QBXL) and List 3 far (M2QBXL) rows of this center, in chunk order
   {
-    NearAcc<KIND, PQ> acc;
-    acc.zero();
-    const double ir = 1.0 / r;
-    for (int32_t g = near_row[b]; g < near_row[b + 1]; ++g) {
-      for (int32_t s = near_lo[g]; s < near_hi[g]; ++s) {
-        const double2 z = make_double2((sxy[s].x - cc.x) * ir, (sxy[s].y - cc.y) * ir);
-        acc.add(z, (KIND & 1) ? sq[s] : 0.0,
-                (KIND & 2) ? cscale(sdip[s], ir) : make_double2(0.0, 0.0));
-      }
+    const int32_t nbc = bctr1[b] - bctr0[b];
+    const int32_t loc = c - bctr0[b];
+    const int32_t nch = n_chunks[b];
+    for (int32_t j = 0; j < nch; ++j) {
+      const double2 *row = anear + (int64_t)(part_base[b] + j * nbc + loc) * (PQ + 1);
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], row[m]);
     }
-    acc.finish(alpha, log(r));
   }
   eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
 }
@@ -398,8 +501,41 @@ __global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const d
   out[t] = n == 2 ? 0.5 * s : s;
 }
 
+// Records a HIP event pair around one stage when the context profiles (see gq_set_profiling).
+class StageTimer {
+ public:
+  StageTimer(gq_ctx *ctx, int stage) : ctx_(ctx) {
+    if (!ctx->profiling) return;
+    slot_ = (ctx->cur_kind - 1) * GQ_N_STAGES + stage;
+    a_ = take(ctx);
+    if (a_) (void)hipEventRecord(a_, ctx->stream);
+  }
+  ~StageTimer() {
+    if (!ctx_->profiling || !a_) return;
+    hipEvent_t b = take(ctx_);
+    if (!b) return;
+    (void)hipEventRecord(b, ctx_->stream);
+    ctx_->prof.push_back({slot_, a_, b});
+  }
+
+ private:
+  static hipEvent_t take(gq_ctx *ctx) {
+    if (!ctx->event_pool.empty()) {
+      hipEvent_t e = ctx->event_pool.back();
+      ctx->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+  }
+  gq_ctx *ctx_;
+  int slot_ = 0;
+  hipEvent_t a_ = nullptr;
+};
+
 template <int KIND>
 hipError_t launch_gather(gq_ctx *ctx, const double *d1, const double *d2) {
+  StageTimer st_(ctx, GQ_STAGE_GATHER);
   const int32_t ns = (int32_t)ctx->ns;
   hipLaunchKernelGGL(k_gather<KIND>, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, ns,
                      ctx->d.sperm, ctx->d.sw, ctx->d.snrm, d1, d2, ctx->d.sq, ctx->d.sdip);
@@ -412,31 +548,57 @@ hipError_t launch_fmm(gq_ctx *ctx) {
   auto &t = ctx->tree;
   const int P1 = ctx->params.p_fmm + 1;
   const hipStream_t st = ctx->stream;
+  const int32_t nitems = (int32_t)ctx->n_near_items;
+  if (nitems > 0) {
+    StageTimer st_(ctx, GQ_STAGE_NEAR);
+    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3((nitems + 3) / 4), dim3(256), 0, st, nitems,
+                       d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear);
+  }
   const int32_t nleaf = (int32_t)t.n_leaves;
-  if (nleaf > 0)
+  if (nleaf > 0) {
+    StageTimer st_(ctx, GQ_STAGE_P2M);
     hipLaunchKernelGGL(k_p2m<KIND>, dim3(nleaf), dim3(64), 0, st, d.leaves, d.bc, d.blevel, d.bsrc0,
                        d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, d.M);
-  for (int l = t.n_levels - 2; l >= 0; --l) {
-    const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-    if (nb > 0) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m, P1, d.M);
+  }
+  {
+    StageTimer st_(ctx, GQ_STAGE_M2M);
+    for (int l = t.n_levels - 2; l >= 0; --l) {
+      const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+      if (nb > 0) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m, P1, d.M);
+    }
   }
   const int32_t ntb = (int32_t)ctx->n_tboxes;
-  if (ntb > 0)
+  if (ntb > 0) {
+    StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
     hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
                        d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2lb, d.opow, d.ologabs, d.sxy, d.sq,
                        d.sdip, P1, d.L);
-  for (int l = 1; l < t.n_levels; ++l) {
-    const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-    if (nb > 0)
-      hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
-                         d.l2l, P1, d.L);
+  }
+  {
+    StageTimer st_(ctx, GQ_STAGE_L2L);
+    for (int l = 1; l < t.n_levels; ++l) {
+      const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+      if (nb > 0)
+        hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
+                           d.l2l, P1, d.L);
+    }
+  }
+  const int32_t nfi = (int32_t)ctx->n_far_items;
+  if (nfi > 0) {
+    StageTimer st_(ctx, GQ_STAGE_M2QBXL);
+    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4), dim3(256), 0, st, nfi, d.far_items,
+                       d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, d.M, P1, d.m2q_binom,
+                       d.anear);
   }
   const int32_t nc = (int32_t)ctx->nc;
-  hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, st, nc, d.cxy,
-                     d.cr, d.cbox, d.bc, d.blevel, d.level_side, d.L, d.M, P1, d.l2q_binom,
-                     d.m2q_binom, d.wf_start, d.wf_idx, d.near_row, d.near_lo, d.near_hi, d.sxy,
-                     d.sq, d.sdip, d.c2t_start, d.c2t_slot, d.txy, d.tv);
+  {
+    StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
+    hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, st, nc,
+                       d.cxy, d.cr, d.cbox, d.bc, d.blevel, d.level_side, d.L, d.M, P1,
+                       d.l2q_binom, d.m2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
+                       d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv);
+  }
   return hipGetLastError();
 }
 
@@ -444,6 +606,7 @@ template <int KIND, int PQ>
 hipError_t launch_direct(gq_ctx *ctx) {
   auto &d = ctx->d;
   const int32_t nc = (int32_t)ctx->nc;
+  StageTimer st_(ctx, GQ_STAGE_DIRECT);
   hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, ctx->stream, nc,
                      d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip, d.c2t_start, d.c2t_slot,
                      d.txy, d.tv);
@@ -475,6 +638,7 @@ bool pq_supported(int pq) {
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, double *out,
                     bool direct) {
   hipError_t e;
+  ctx->cur_kind = kind;
   switch (kind) {
     case 1: e = launch_gather<1>(ctx, d1, d2); break;
     case 2: e = launch_gather<2>(ctx, d1, d2); break;
@@ -491,6 +655,7 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, d
   }
   if (e != hipSuccess) return e;
   const int32_t nt = (int32_t)ctx->nt;
+  StageTimer st_(ctx, GQ_STAGE_FINALIZE);
   hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256), dim3(256), 0, ctx->stream, nt, ctx->d.tctr,
                      ctx->d.tv, out);
   return hipGetLastError();

@@ -2,6 +2,7 @@
 // of eq. (m2l)). Computed once per FMM order in long double and rounded to FP64.
 #include "tables.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 
@@ -9,11 +10,12 @@ namespace gq {
 
 using cld = std::complex<long double>;
 
-void build_tables(Tables &t, int p) {
+void build_tables(Tables &t, int p, int max_pq) {
   t = Tables();
   t.p = p;
   const int P1 = p + 1;
-  const int NB = 2 * p + 2;
+  const int NB = std::max(2 * p + 2, p + max_pq + 2);
+  t.nbinom = NB;
   t.binom.assign((size_t)NB * NB, 0.0);
   std::vector<long double> pas((size_t)NB * NB, 0.0L);
   for (int n = 0; n < NB; ++n) {

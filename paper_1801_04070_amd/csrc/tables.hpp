@@ -25,9 +25,11 @@ struct Tables {
   std::vector<double> m2l_b;      // [P1][P1] real B
   std::vector<double> opow;       // [121][P1] complex: o^-k for o = (i - 5) + (j - 5) i, index i*11+j
   std::vector<double> ologabs;    // [121] log|o|
-  std::vector<double> binom;      // [2 p + 2][2 p + 2] Pascal triangle C(n, k)
+  int nbinom = 0;                 // rows of the Pascal triangle
+  std::vector<double> binom;      // [nbinom][nbinom] Pascal triangle C(n, k)
 };
 
-void build_tables(Tables &t, int p);
+// Tables for FMM order p; the Pascal triangle covers C(n, k) for n < p + max_pq + 2 as well.
+void build_tables(Tables &t, int p, int max_pq);
 
 }  // namespace gq

@@ -198,6 +198,7 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
   for (int64_t b = 0; b < nb; ++b) {
     t.n_leaves += t.is_leaf(b);
     t.n_target_boxes += t.ctr_end[b] > t.ctr_begin[b];
+    t.n_local_boxes += t.has_tgt[b];
     if (!t.is_leaf(b)) t.n_suspended += t.ctr_end[b] - t.ctr_begin[b];
   }
 
@@ -394,6 +395,7 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
         else { t.near_lo.push_back(r.first); t.near_hi.push_back(r.second); }
       }
       t.near_pairs += nown * nsrc;
+      t.near_sources += nsrc;
       t.list3f_pairs += nown * (int64_t)Wf[b].size();
     }
     for (int32_t d : Xf[b]) t.list4f_sources += t.n_src_subtree(d);

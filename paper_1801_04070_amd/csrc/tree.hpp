@@ -64,7 +64,8 @@ struct Tree {
 
   // Statistics.
   int64_t n_leaves = 0, n_target_boxes = 0, n_suspended = 0;
-  int64_t near_pairs = 0, list3f_pairs = 0, list4f_sources = 0;
+  int64_t near_pairs = 0, list3f_pairs = 0, list4f_sources = 0, near_sources = 0;
+  int64_t n_local_boxes = 0;
 
   int64_t n_boxes() const { return (int64_t)level.size(); }
   bool is_leaf(int64_t b) const {

@@ -1,0 +1,112 @@
+"""Algorithmic work per kernel launch, from the tree/list statistics.
+
+Counting convention (floating-point operations of the method's formulas, not of the generated
+code): complex multiply 6, complex add 2, real x complex multiply-add 4, complex multiply-add
+8, real multiply-add 2, reciprocal / division / logarithm 1 each. Source-to-expansion steps use
+the power recurrences of eqs. (multipole)/(local); translations use the factored forms
+(M2L: diag(o^-m) B diag(o^-k); L2QBXL: repeated Horner).
+
+Bytes are the algorithmic HBM traffic of one launch: each operand the kernel must read once and
+each result it writes once (source records 24 B for charges, 32 B for dipoles, 40 B for both;
+complex coefficients 16 B).
+"""
+from __future__ import annotations
+
+MI355X_PEAKS = {
+    "fp64_vector_tflops": 78.6,   # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+    "fp32_vector_tflops": 157.3,
+    "fp64_mfma_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+
+
+def _near_pair_flops(kind: int, q: int) -> int:
+    # z = (y - c)/r (4), 1/z (6); charge: log|z| term (3), q-1 powers (6 each), q accumulations (4)
+    f = 4 + 6
+    if kind & 1:
+        f += 3 + 6 * (q - 1) + 4 * q
+    if kind & 2:
+        # e = d/z (6), q powers (6 each), q+1 complex adds (2)
+        f += 6 + 6 * q + 2 * (q + 1)
+    return f
+
+
+def _m2qbxl_flops(q: int, p: int) -> int:
+    # y, 1/y, w = s/y, u = -r/y, log|y|; a_0 terms; a_k w^k; sum_k C(m+k-1,k-1) T_k for all m;
+    # output scaling by u^m and accumulation
+    return 16 + 10 * q + 12 * p + 4 * (q + 1) * p + 6 * q + 8 * (q + 1)
+
+
+def _l2qbxl_flops(q: int, p: int) -> int:
+    horner = sum(p - m for m in range(q + 1) if p - m > 0)
+    return 4 + 8 * horner + 8 * q
+
+
+def _qbxl2p_flops(q: int) -> int:
+    return 5 + 8 * q
+
+
+def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> dict:
+    """Algorithmic flops and HBM bytes of one launch of each stage for one density."""
+    q, p = p_qbx, p_fmm
+    P1, Q1 = p + 1, q + 1
+    src_rec = {1: 24, 2: 32, 3: 40}[kind]
+    row = Q1 * 16
+    n_rows_near = stats["n_ctr"]  # at least one direct row per center
+    out = {}
+    out["near"] = {
+        "flops": stats["near_pairs"] * _near_pair_flops(kind, q),
+        "bytes": stats["near_sources"] * (src_rec + 4) + stats["n_ctr"] * 24 + n_rows_near * row,
+        "bound": "alu"}
+    out["m2qbxl"] = {
+        "flops": stats["list3_far_pairs"] * _m2qbxl_flops(q, p),
+        "bytes": stats["n_list3_far"] * (P1 * 16 + 20) + stats["list3_far_pairs"] // 8 * row,
+        "bound": "alu"}
+    out["qbx_center"] = {
+        "flops": stats["n_ctr"] * _l2qbxl_flops(q, p) + n_slots * _qbxl2p_flops(q),
+        "bytes": stats["n_ctr"] * (24 + 4 + row) + stats["n_target_boxes"] * P1 * 16
+                 + n_slots * 24,
+        "bound": "alu"}
+    per_pair = 6 * P1 + 4 * P1 * P1 + 8 * P1
+    p2l = 4 + 6 + 6 * p + 4 * P1 + 3
+    out["m2l_p2l"] = {
+        "flops": stats["n_list2"] * per_pair + stats["list4_far_sources"] * p2l,
+        "bytes": stats["n_list2"] * (P1 * 16 + 8) + stats["n_local_boxes"] * P1 * 16,
+        "bound": "alu"}
+    tri = P1 * (P1 + 1) // 2
+    out["m2m"] = {"flops": (stats["n_boxes"] - 1) * tri * 8,
+                  "bytes": 2 * stats["n_boxes"] * P1 * 16, "bound": "alu"}
+    out["l2l"] = {"flops": max(stats["n_local_boxes"] - 1, 0) * tri * 8,
+                  "bytes": 2 * stats["n_local_boxes"] * P1 * 16, "bound": "alu"}
+    p2m = 4 + (10 * p if kind & 1 else 0) + (8 * p if kind & 2 else 0)
+    out["p2m"] = {"flops": stats["n_src"] * p2m,
+                  "bytes": stats["n_src"] * src_rec + stats["n_leaves"] * P1 * 16, "bound": "alu"}
+    out["gather"] = {"flops": stats["n_src"] * 3, "bytes": stats["n_src"] * (8 + 8 + 16 + 4 + src_rec - 16),
+                     "bound": "hbm"}
+    out["finalize"] = {"flops": stats["n_tgt"] * 2, "bytes": stats["n_tgt"] * (16 + 8 + 8), "bound": "hbm"}
+    return out
+
+
+def center_kernel(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> dict:
+    """Flops and bytes of one launch of the per-center kernel (Stages 3, 5, 6a, 8 + QBXL2P)."""
+    q, p = p_qbx, p_fmm
+    flops = (stats["near_pairs"] * _near_pair_flops(kind, q)
+             + stats["list3_far_pairs"] * _m2qbxl_flops(q, p)
+             + stats["n_ctr"] * _l2qbxl_flops(q, p)
+             + n_slots * _qbxl2p_flops(q))
+    src_rec = {1: 24, 2: 32, 3: 40}[kind]
+    nbytes = (stats["n_ctr"] * (16 + 8 + 4 + 8)          # center xy, r, box, target-slot index
+              + n_slots * (16 + 8)                        # target xy, slot value written
+              + stats["n_target_boxes"] * (p + 1) * 16    # box local read once per box
+              + stats["n_list3_far"] * (p + 1) * 16       # List 3 far multipoles per box entry
+              + stats["near_sources"] * src_rec)     # near sources, once per target box
+    return {"flops": flops, "bytes": nbytes}
+
+
+def m2l_kernel(stats: dict, kind: int, p_fmm: int) -> dict:
+    P1 = p_fmm + 1
+    per_pair = 6 * P1 + 4 * P1 * P1 + 8 * P1
+    p2l = 4 + 6 + 6 * p_fmm + 4 * P1 + 3
+    flops = stats["n_list2"] * per_pair + stats["list4_far_sources"] * p2l
+    nbytes = stats["n_list2"] * (P1 * 16 + 8) + stats["n_local_boxes"] * P1 * 16
+    return {"flops": flops, "bytes": nbytes}
