@@ -242,9 +242,10 @@ gq_status upload_all(gq_ctx *ctx) {
   // tables
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
-  GQ_TRY(upload(ctx, d.m2m, tb.m2m.data(), tb.m2m.size() / 2));
-  GQ_TRY(upload(ctx, d.l2l, tb.l2l.data(), tb.l2l.size() / 2));
-  GQ_TRY(upload(ctx, d.m2lb, tb.m2l_b.data(), tb.m2l_b.size()));
+  GQ_TRY(upload(ctx, d.m2m_rt, tb.m2m_rt.data(), tb.m2m_rt.size()));
+  GQ_TRY(upload(ctx, d.l2l_rt, tb.l2l_rt.data(), tb.l2l_rt.size()));
+  GQ_TRY(upload(ctx, d.omega, tb.omega.data(), tb.omega.size() / 2));
+  GQ_TRY(upload(ctx, d.m2l_bt, tb.m2l_bt.data(), tb.m2l_bt.size()));
   GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
   GQ_TRY(upload(ctx, d.ologabs, tb.ologabs.data(), tb.ologabs.size()));
   {
@@ -328,6 +329,15 @@ gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
   if (!ctx) return fail(nullptr, GQ_ENOMEM, "context allocation failed");
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (device >= 0) {
+    // default-priority, non-blocking side stream; events carry the fork/join dependencies
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+      gq_destroy(ctx);
+      return fail(nullptr, GQ_EHIP, "stream/event creation failed");
+    }
+  }
   gq_default_params(&ctx->params);
   *out = ctx;
   return GQ_OK;
@@ -343,8 +353,14 @@ gq_status gq_destroy(gq_ctx *ctx) {
       ctx->event_pool.push_back(r.b);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   }
   free_device(ctx);
+  if (ctx->device >= 0) {
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  }
   delete ctx;
   return GQ_OK;
 }

@@ -51,8 +51,8 @@ struct DevBuffers {
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
-  double2 *m2m = nullptr, *l2l = nullptr, *opow = nullptr;
-  double *m2lb = nullptr, *ologabs = nullptr;
+  double2 *opow = nullptr, *omega = nullptr;
+  double *m2m_rt = nullptr, *l2l_rt = nullptr, *m2l_bt = nullptr, *ologabs = nullptr;
   double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
   double *m2q_binom = nullptr;       // [PQB + 1][P1]  C(m + k - 1, k - 1)
   // workspace
@@ -66,7 +66,9 @@ struct DevBuffers {
 
 struct gq_ctx {
   int device = -1;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // caller's stream (borrowed)
+  hipStream_t side = nullptr;        // library stream for work that overlaps the tree passes
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
 
   // geometry (caller order, host copies)

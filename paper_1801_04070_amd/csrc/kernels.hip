@@ -73,28 +73,49 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 2b, M2M for the non-leaf boxes of one level: parent_m = sum_q sum_k T_q[m][k] child_k.
+// Stage 2b, M2M for the non-leaf boxes of one level (eq. (m2m), factored through the real matrix
+// Rm, see tables.hpp): parent_m = sum_q w_q^m sum_k Rm[m][k] (w_q^-k child_q,k).
 __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restrict__ bchild,
-                                            const double2 *__restrict__ T, int P1,
+                                            const double *__restrict__ Rt,
+                                            const double2 *__restrict__ omega, int P1,
                                             double2 *__restrict__ M) {
+  __shared__ double2 X[4][64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
-  if (m >= P1) return;
   const int32_t *ch = bchild + 4 * (int64_t)b;
-  if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf: formed by P2M
-  double2 acc = make_double2(0.0, 0.0);
+  if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf (uniform per block)
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (ch[q] < 0) continue;
-    const double2 *Tq = T + ((int64_t)q * P1 + m) * P1;
-    const double2 *Mc = M + (int64_t)ch[q] * P1;
-    for (int k = 0; k <= m; ++k) acc = cfma(Tq[k], Mc[k], acc);
+    double2 x = make_double2(0.0, 0.0);
+    if (ch[q] >= 0 && m < P1) {
+      const double2 w = omega[q * 8 + (m & 7)];
+      x = cmul(M[(int64_t)ch[q] * P1 + m], make_double2(w.x, -w.y));
+    }
+    X[q][m] = x;
   }
-  M[(int64_t)b * P1 + m] = acc;
+  __syncthreads();
+  if (m >= P1) return;
+  double2 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int k = 0; k <= m; ++k) {
+    const double r = Rt[k * P1 + m];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q][k], acc[q]);
+  }
+  double2 out = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
+  M[(int64_t)b * P1 + m] = out;
 }
 
 // ------------------------------------------------------------------------------------------
 // Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One work-group per
-// target-or-ancestor box; lane m computes coefficient m.
+// target-or-ancestor box; lane m computes coefficient m. M2L (eq. (m2l), corrected a_0 sign)
+// in factored form beta_m = o^-m sum_k B[m][k] (a_k o^-k) (+ a_0 log|s o| in beta_0), register-
+// blocked over batches of kM2LBatch pairs so each B element is read once per batch.
+constexpr int kM2LBatch = 8;
+
 template <int KIND>
 __global__ void __launch_bounds__(64) k_far_local(
     const int32_t *__restrict__ tboxes, const double2 *__restrict__ bc,
@@ -103,29 +124,49 @@ __global__ void __launch_bounds__(64) k_far_local(
     const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
     const int32_t *__restrict__ xf_start, const int32_t *__restrict__ xf_idx,
     const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
-    const double2 *__restrict__ M, const double *__restrict__ Bm, const double2 *__restrict__ opow,
+    const double2 *__restrict__ M, const double *__restrict__ Bt, const double2 *__restrict__ opow,
     const double *__restrict__ ologabs, const double2 *__restrict__ sxy,
     const double *__restrict__ sq, const double2 *__restrict__ sdip, int P1,
     double2 *__restrict__ L) {
-  __shared__ double2 X[64];
+  __shared__ double2 X[kM2LBatch][64];
+  __shared__ int32_t offs[kM2LBatch];
   const int32_t b = tboxes[blockIdx.x];
   const int m = threadIdx.x;
   const int lev = blevel[b];
   const double logs = level_log_side[lev];
   double2 acc = make_double2(0.0, 0.0);
-  // M2L: beta_m = o^-m sum_k B[m][k] (a_k o^-k), plus a_0 log|s o| in beta_0
-  for (int32_t j = v_start[b]; j < v_start[b + 1]; ++j) {
-    const int32_t d = v_idx[j];
-    const double2 *op = opow + (int64_t)v_off[j] * P1;
+  const int32_t v0 = v_start[b], v1 = v_start[b + 1];
+  for (int32_t j0 = v0; j0 < v1; j0 += kM2LBatch) {
+    const int nbat = min(kM2LBatch, (int)(v1 - j0));
     __syncthreads();
-    if (m < P1) X[m] = cmul(M[(int64_t)d * P1 + m], op[m]);
+#pragma unroll
+    for (int p = 0; p < kM2LBatch; ++p) {
+      double2 x = make_double2(0.0, 0.0);
+      if (p < nbat && m < P1) {
+        const int32_t oi = v_off[j0 + p];
+        x = cmul(M[(int64_t)v_idx[j0 + p] * P1 + m], opow[(int64_t)oi * P1 + m]);
+        if (m == 0) offs[p] = oi;
+      }
+      X[p][m] = x;
+    }
     __syncthreads();
     if (m < P1) {
-      double2 s = make_double2(0.0, 0.0);
-      const double *Brow = Bm + (int64_t)m * P1;
-      for (int k = 0; k < P1; ++k) s = caxpy(Brow[k], X[k], s);
-      acc = cfma(s, op[m], acc);
-      if (m == 0) acc.x += X[0].x * (logs + ologabs[v_off[j]]);
+      double2 Y[kM2LBatch];
+#pragma unroll
+      for (int p = 0; p < kM2LBatch; ++p) Y[p] = make_double2(0.0, 0.0);
+      for (int k = 0; k < P1; ++k) {
+        const double bk = Bt[k * P1 + m];
+#pragma unroll
+        for (int p = 0; p < kM2LBatch; ++p) Y[p] = caxpy(bk, X[p][k], Y[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < kM2LBatch; ++p) {
+        if (p < nbat) {
+          const int32_t oi = offs[p];
+          acc = cfma(Y[p], opow[(int64_t)oi * P1 + m], acc);
+          if (m == 0) acc.x += X[p][0].x * (logs + ologabs[oi]);
+        }
+      }
     }
   }
   if (m >= P1) return;
@@ -151,21 +192,27 @@ __global__ void __launch_bounds__(64) k_far_local(
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 7, L2L for the target-or-ancestor boxes of one level: child_m += sum_k T_q[m][k] parent_k.
+// Stage 7, L2L for the target-or-ancestor boxes of one level (eq. (l2l), factored through the
+// real matrix Rl): child_m += w_q^-m sum_{k>=m} Rl[m][k] (w_q^k parent_k).
 __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restrict__ bparent,
                                             const int8_t *__restrict__ bquad,
                                             const int32_t *__restrict__ is_tbox,
-                                            const double2 *__restrict__ T, int P1,
+                                            const double *__restrict__ Rt,
+                                            const double2 *__restrict__ omega, int P1,
                                             double2 *__restrict__ L) {
+  __shared__ double2 X[64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
-  if (m >= P1 || !is_tbox[b]) return;
+  if (!is_tbox[b]) return;  // uniform per block
   const int32_t p = bparent[b];
-  const double2 *Tq = T + ((int64_t)bquad[b] * P1 + m) * P1;
-  const double2 *Lp = L + (int64_t)p * P1;
-  double2 acc = L[(int64_t)b * P1 + m];
-  for (int k = m; k < P1; ++k) acc = cfma(Tq[k], Lp[k], acc);
-  L[(int64_t)b * P1 + m] = acc;
+  const int q = bquad[b];
+  if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
+  __syncthreads();
+  if (m >= P1) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
+  const double2 w = omega[q * 8 + (m & 7)];
+  L[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -252,15 +299,19 @@ __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, co
 // into its centers. One wavefront per work item (box, source chunk, block of n_cl centers): lane
 // = (center, slice) with 64/n_cl slices striding over the chunk's sources, then a fixed-order
 // xor-shuffle reduction over the slices. The result row holds the scaled coefficients.
+constexpr int kNearBatch = 128;  // sources staged in LDS per step
+
 template <int KIND, int PQ>
-__global__ void __launch_bounds__(256) k_near(
+__global__ void __launch_bounds__(64) k_near(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, double2 *__restrict__ anear) {
-  const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (w >= n_items) return;  // uniform per wavefront
+  __shared__ double2 t_xy[kNearBatch];
+  __shared__ double t_q[(KIND & 1) ? kNearBatch : 1];
+  __shared__ double2 t_d[(KIND & 2) ? kNearBatch : 1];
+  const int32_t w = (int32_t)blockIdx.x;  // one wavefront per work-group and per item
+  const int lane = threadIdx.x;
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
   const int n_ctr = i1.x, lg = i1.y;
@@ -274,12 +325,25 @@ __global__ void __launch_bounds__(256) k_near(
   const double ir = 1.0 / r;
   NearAcc<KIND, PQ> acc;
   acc.zero();
-  if (active) {
-    for (int32_t k = sl; k < len; k += nsl) {
-      const int32_t s = near_src[off + k];
-      const double2 z = make_double2((sxy[s].x - cc.x) * ir, (sxy[s].y - cc.y) * ir);
-      acc.add(z, (KIND & 1) ? sq[s] : 0.0,
-              (KIND & 2) ? cscale(sdip[s], ir) : make_double2(0.0, 0.0));
+  for (int32_t base = 0; base < len; base += kNearBatch) {
+    const int nb = min(kNearBatch, (int)(len - base));
+    __syncthreads();
+#pragma unroll
+    for (int j = lane; j < kNearBatch; j += 64) {
+      if (j < nb) {
+        const int32_t s = near_src[off + base + j];
+        t_xy[j] = sxy[s];
+        if (KIND & 1) t_q[j] = sq[s];
+        if (KIND & 2) t_d[j] = sdip[s];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < nb; j += nsl) {
+        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
+        acc.add(z, (KIND & 1) ? t_q[j] : 0.0,
+                (KIND & 2) ? cscale(t_d[j], ir) : make_double2(0.0, 0.0));
+      }
     }
   }
   for (int o = nsl >> 1; o >= 1; o >>= 1) {
@@ -322,24 +386,25 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
   const double2 u = cscale(iy, -r);
   const double2 *Md = M + (int64_t)d * P1;
   const double a0 = Md[0].x;
-  alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
-  {
-    double2 pm = u;
+  // V_m = -a_0/m + sum_k C(m+k-1,k-1) a_k w^k  (V_0 without the log term)
+  double2 V[PQ + 1];
+  V[0] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int m = 1; m <= PQ; ++m) {
-      alpha[m] = caxpy(-a0 / m, pm, alpha[m]);
-      pm = cmul(pm, u);
-    }
-  }
+  for (int m = 1; m <= PQ; ++m) V[m] = make_double2(-a0 / m, 0.0);
   double2 wk = make_double2(1.0, 0.0);
   for (int k = 1; k < P1; ++k) {
     wk = cmul(wk, w);
-    double2 P = cmul(Md[k], wk);
+    const double2 T = cmul(Md[k], wk);
 #pragma unroll
-    for (int m = 0; m <= PQ; ++m) {
-      alpha[m] = caxpy(m2q_binom[m * P1 + k], P, alpha[m]);
-      P = cmul(P, u);
-    }
+    for (int m = 0; m <= PQ; ++m) V[m] = caxpy(m2q_binom[m * P1 + k], T, V[m]);
+  }
+  alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
+  alpha[0] = cadd(alpha[0], V[0]);
+  double2 pm = u;
+#pragma unroll
+  for (int m = 1; m <= PQ; ++m) {
+    alpha[m] = cfma(pm, V[m], alpha[m]);
+    pm = cmul(pm, u);
   }
 }
 
@@ -504,17 +569,18 @@ __global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const d
 // Records a HIP event pair around one stage when the context profiles (see gq_set_profiling).
 class StageTimer {
  public:
-  StageTimer(gq_ctx *ctx, int stage) : ctx_(ctx) {
+  StageTimer(gq_ctx *ctx, int stage, hipStream_t s) : ctx_(ctx), s_(s) {
     if (!ctx->profiling) return;
     slot_ = (ctx->cur_kind - 1) * GQ_N_STAGES + stage;
     a_ = take(ctx);
-    if (a_) (void)hipEventRecord(a_, ctx->stream);
+    if (a_) (void)hipEventRecord(a_, s_);
   }
+  StageTimer(gq_ctx *ctx, int stage) : StageTimer(ctx, stage, ctx->stream) {}
   ~StageTimer() {
     if (!ctx_->profiling || !a_) return;
     hipEvent_t b = take(ctx_);
     if (!b) return;
-    (void)hipEventRecord(b, ctx_->stream);
+    (void)hipEventRecord(b, s_);
     ctx_->prof.push_back({slot_, a_, b});
   }
 
@@ -529,6 +595,7 @@ class StageTimer {
     return hipEventCreate(&e) == hipSuccess ? e : nullptr;
   }
   gq_ctx *ctx_;
+  hipStream_t s_;
   int slot_ = 0;
   hipEvent_t a_ = nullptr;
 };
@@ -548,12 +615,20 @@ hipError_t launch_fmm(gq_ctx *ctx) {
   auto &t = ctx->tree;
   const int P1 = ctx->params.p_fmm + 1;
   const hipStream_t st = ctx->stream;
+  // The direct-interaction kernel needs only the source strengths: it runs on the side stream
+  // while the upward pass, M2L, List 3 far and the downward pass proceed on the caller's stream.
   const int32_t nitems = (int32_t)ctx->n_near_items;
+  hipError_t e = hipEventRecord(ctx->ev_fork, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  if (e != hipSuccess) return e;
   if (nitems > 0) {
-    StageTimer st_(ctx, GQ_STAGE_NEAR);
-    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3((nitems + 3) / 4), dim3(256), 0, st, nitems,
+    StageTimer st_(ctx, GQ_STAGE_NEAR, ctx->side);
+    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems), dim3(64), 0, ctx->side, nitems,
                        d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear);
   }
+  e = hipEventRecord(ctx->ev_join, ctx->side);
+  if (e != hipSuccess) return e;
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
@@ -564,7 +639,9 @@ hipError_t launch_fmm(gq_ctx *ctx) {
     StageTimer st_(ctx, GQ_STAGE_M2M);
     for (int l = t.n_levels - 2; l >= 0; --l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-      if (nb > 0) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m, P1, d.M);
+      if (nb > 0)
+        hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m_rt, d.omega, P1,
+                           d.M);
     }
   }
   const int32_t ntb = (int32_t)ctx->n_tboxes;
@@ -572,7 +649,7 @@ hipError_t launch_fmm(gq_ctx *ctx) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
     hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
-                       d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2lb, d.opow, d.ologabs, d.sxy, d.sq,
+                       d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2l_bt, d.opow, d.ologabs, d.sxy, d.sq,
                        d.sdip, P1, d.L);
   }
   {
@@ -581,7 +658,7 @@ hipError_t launch_fmm(gq_ctx *ctx) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
         hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
-                           d.l2l, P1, d.L);
+                           d.l2l_rt, d.omega, P1, d.L);
     }
   }
   const int32_t nfi = (int32_t)ctx->n_far_items;
@@ -592,6 +669,8 @@ hipError_t launch_fmm(gq_ctx *ctx) {
                        d.anear);
   }
   const int32_t nc = (int32_t)ctx->nc;
+  e = hipStreamWaitEvent(st, ctx->ev_join, 0);
+  if (e != hipSuccess) return e;
   {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
     hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, st, nc,

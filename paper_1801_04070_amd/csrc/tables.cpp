@@ -64,6 +64,37 @@ void build_tables(Tables &t, int p, int max_pq) {
       }
   }
 
+  // factored shifts (see tables.hpp): |u| = 2^-1/2 for every quadrant
+  {
+    const long double au = std::sqrt(0.5L);
+    t.m2m_rt.assign((size_t)P1 * P1, 0.0);
+    t.l2l_rt.assign((size_t)P1 * P1, 0.0);
+    for (int m = 0; m <= p; ++m) {
+      const long double s = std::pow(2.0L, -(long double)m);
+      for (int k = 0; k <= m; ++k) {
+        long double v;
+        if (m == 0) v = (k == 0) ? 1.0L : 0.0L;
+        else if (k == 0) v = -std::pow(au, (long double)m) * s / (long double)m;
+        else v = C(m - 1, k - 1) * std::pow(au, (long double)(m - k)) * s;
+        t.m2m_rt[(size_t)k * P1 + m] = (double)v;
+      }
+      for (int k = m; k <= p; ++k)
+        t.l2l_rt[(size_t)k * P1 + m] =
+            (double)(C(k, m) * std::pow(2.0L, -(long double)k) * std::pow(au, (long double)(k - m)));
+    }
+    t.omega.assign(4 * 8 * 2, 0.0);
+    for (int q = 0; q < 4; ++q) {
+      const cld u((q & 1) ? 0.5L : -0.5L, (q & 2) ? 0.5L : -0.5L);
+      const cld w = u / std::abs(u);
+      cld pw(1.0L);
+      for (int j = 0; j < 8; ++j) {
+        t.omega[(q * 8 + j) * 2] = (double)pw.real();
+        t.omega[(q * 8 + j) * 2 + 1] = (double)pw.imag();
+        pw *= w;
+      }
+    }
+  }
+
   // M2L factor B, eq. (m2l) with the corrected sign of the a_0 term
   t.m2l_b.assign((size_t)P1 * P1, 0.0);
   for (int m = 0; m <= p; ++m)
@@ -74,6 +105,9 @@ void build_tables(Tables &t, int p, int max_pq) {
       else v = ((m % 2) ? -1.0L : 1.0L) * C(m + k - 1, k - 1);
       t.m2l_b[(size_t)m * P1 + k] = (double)v;
     }
+  t.m2l_bt.assign((size_t)P1 * P1, 0.0);
+  for (int m = 0; m <= p; ++m)
+    for (int k = 0; k <= p; ++k) t.m2l_bt[(size_t)k * P1 + m] = t.m2l_b[(size_t)m * P1 + k];
 
   t.opow.assign((size_t)121 * P1 * 2, 0.0);
   t.ologabs.assign(121, 0.0);
