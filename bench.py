@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=64, help="densities of the batched variant")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -164,6 +165,43 @@ def main():
 
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
     gpu_out = out.cpu().numpy()
+
+    # batched variant: 64 seeded densities in one call per kind (a block right-hand-side batch)
+    variants = {}
+    if args.batch > 1:
+        nb = args.batch
+        hb = np.stack([gi.fourier_density(geom, seed=100 + j) for j in range(nb)])
+        db = torch.as_tensor(hb, dtype=torch.float64, device="cuda:0")
+        ob = torch.empty((2, nb, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+
+        def bstep():
+            q.eval(GQ_S, db, out=ob[0])
+            q.eval(GQ_D, db, out=ob[1])
+
+        bsteps = max(2, args.steps // 4)
+        for _ in range(max(1, args.warmup)):
+            bstep()
+        torch.cuda.synchronize()
+        q.stage_times()
+        q.set_profiling(True)
+        start.record()
+        for _ in range(bsteps):
+            bstep()
+        stop.record()
+        torch.cuda.synchronize()
+        bms = start.elapsed_time(stop) / bsteps
+        bstages = {}
+        for (kind, name), (ms, cnt) in q.stage_times().items():
+            bstages[name] = round(bstages.get(name, 0.0) + ms / bsteps, 3)
+        q.set_profiling(False)
+        variants[f"batched_{nb}"] = {
+            "value": round(2 * nb * geom.n_tgt / (bms * 1e-3), 1), "unit": "targets/s",
+            "ms_per_step": round(bms, 4), "steps": bsteps,
+            "workload": f"same geometry, {nb} seeded densities per call, S and D",
+            "vs_plain": round(2 * nb * geom.n_tgt / (bms * 1e-3) / value, 3),
+            "stage_ms_per_step": bstages}
+        log(f"bench: batched {nb}: {bms:.3f} ms/step")
+        batched_out = (ob[0, nb - 1].cpu().numpy(), ob[1, nb - 1].cpu().numpy(), hb[nb - 1])
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -177,6 +215,7 @@ def main():
                    "list2_pairs": stats["n_list2"], "near_pairs": stats["near_pairs"],
                    "list3_far_pairs": stats["list3_far_pairs"],
                    "build_ms": round(stats["build_ms"], 1)},
+        "variants": variants,
         "stage_ms_per_step": breakdown,
         "stage_tflops": stage_rates,
         "roofline": roofline,
@@ -188,6 +227,12 @@ def main():
         result["parity"] = parity
         if max(parity["S"], parity["D"]) > GATE:
             result["parity"]["status"] = "FAILED"
+        if variants:
+            _, bpar = cpu_baseline(geom, batched_out[2], batched_out[:2], args.cpu_budget / 4)
+            key = next(iter(variants))
+            variants[key]["parity"] = bpar
+            if max(bpar["S"], bpar["D"]) > GATE:
+                variants[key]["parity"]["status"] = "FAILED"
     print(json.dumps(result), flush=True)
 
 

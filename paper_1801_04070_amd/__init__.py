@@ -182,8 +182,14 @@ class QBXFMM:
         (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt)."""
         import torch
         squeeze = dens1.dim() == 1
-        d1 = dens1.reshape(-1, dens1.shape[-1]).contiguous()
-        d2 = None if dens2 is None else dens2.reshape(-1, dens2.shape[-1]).contiguous()
+
+        def rows(t):
+            # keep a row-strided 2-D view (unit stride along a row), else copy
+            t = t.reshape(-1, t.shape[-1]) if t.dim() == 1 else t
+            return t if t.stride(-1) == 1 else t.contiguous()
+
+        d1 = rows(dens1)
+        d2 = None if dens2 is None else rows(dens2)
         n_dens = d1.shape[0]
         if out is None:
             out = torch.empty((n_dens, self.n_tgt), dtype=torch.float64, device=d1.device)

@@ -29,7 +29,20 @@ gq_status fail(gq_ctx *ctx, gq_status st, const std::string &msg) {
       return fail(ctx, GQ_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
+void free_workspace(gq_ctx *ctx) {
+  if (ctx->device >= 0) {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    for (void *p : ctx->ws_allocations) (void)hipFree(p);
+  }
+  ctx->ws_allocations.clear();
+  ctx->ws_batch = 0;
+  ctx->d.sq = nullptr; ctx->d.sdip = nullptr; ctx->d.M = nullptr; ctx->d.L = nullptr;
+  ctx->d.anear = nullptr; ctx->d.tv = nullptr;
+}
+
 void free_device(gq_ctx *ctx) {
+  free_workspace(ctx);
   if (ctx->device >= 0) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (void *p : ctx->allocations) (void)hipFree(p);
@@ -56,8 +69,14 @@ gq_status upload(gq_ctx *ctx, T *&dst, const void *src, size_t count) {
 }
 
 template <typename T>
-gq_status alloc(gq_ctx *ctx, T *&dst, size_t count) {
-  return upload<T>(ctx, dst, nullptr, count);
+gq_status alloc_ws(gq_ctx *ctx, T *&dst, size_t count) {
+  dst = nullptr;
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return fail(ctx, GQ_ENOMEM, std::string("hipMalloc (workspace): ") + hipGetErrorString(e));
+  ctx->ws_allocations.push_back(p);
+  dst = static_cast<T *>(p);
+  return GQ_OK;
 }
 
 std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
@@ -144,8 +163,43 @@ gq_status upload_near_work(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.bctr1, bctr1.data(), nb));
   GQ_TRY(upload(ctx, d.part_base, base.data(), nb));
   GQ_TRY(upload(ctx, d.n_chunks, nch.data(), nb));
-  GQ_TRY(alloc(ctx, d.anear, (size_t)std::max<int64_t>(rows, 1) * (ctx->pq_bucket + 1)));
   return GQ_OK;
+}
+
+// Schedules of the levels above the cut for the single-work-group upward (M2M) and downward
+// (L2L) passes. The cut is the first level with at least kCutBoxes non-leaf boxes; the levels
+// below it run one launch per level.
+constexpr int kCutBoxes = 64;
+
+void build_schedules(gq_ctx *ctx) {
+  const gq::Tree &t = ctx->tree;
+  const int L = t.n_levels;
+  int cut = std::max(L - 1, 0);
+  for (int l = 0; l < L; ++l) {
+    int64_t nonleaf = 0;
+    for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) nonleaf += !t.is_leaf(b);
+    if (nonleaf >= kCutBoxes) { cut = l; break; }
+  }
+  auto build = [&](gq::TreeSchedule &S, bool up) {
+    S = gq::TreeSchedule();
+    S.cut_level = cut;
+    S.blk.push_back(0);
+    S.stage.push_back(0);
+    bool any = false;
+    for (int i = 0; i < L; ++i) {
+      const int l = up ? L - 1 - i : i;
+      // upward: non-leaf boxes of levels < cut (deepest first); downward: boxes with targets
+      // below them at levels 1..cut (top first)
+      if (up ? l >= cut : (l > cut || l < 1)) continue;
+      const size_t before = S.box.size();
+      for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
+        if (up ? !t.is_leaf(b) : (bool)t.has_tgt[b]) S.box.push_back((int32_t)b);
+      if (S.box.size() > before) { S.stage.push_back((int32_t)S.box.size()); any = true; }
+    }
+    if (any) { S.blk.push_back((int32_t)S.stage.size() - 1); S.has_top = true; }
+  };
+  build(ctx->up, true);
+  build(ctx->down, false);
 }
 
 gq_status upload_all(gq_ctx *ctx) {
@@ -239,6 +293,13 @@ gq_status upload_all(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.xf_start, to_i32(t.list4f.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.xf_idx, t.list4f.idx.data(), t.list4f.idx.size()));
   GQ_TRY(upload_near_work(ctx));
+  build_schedules(ctx);
+  GQ_TRY(upload(ctx, d.up_blk, ctx->up.blk.data(), ctx->up.blk.size()));
+  GQ_TRY(upload(ctx, d.up_stage, ctx->up.stage.data(), ctx->up.stage.size()));
+  GQ_TRY(upload(ctx, d.up_box, ctx->up.box.data(), ctx->up.box.size()));
+  GQ_TRY(upload(ctx, d.dn_blk, ctx->down.blk.data(), ctx->down.blk.size()));
+  GQ_TRY(upload(ctx, d.dn_stage, ctx->down.stage.data(), ctx->down.stage.size()));
+  GQ_TRY(upload(ctx, d.dn_box, ctx->down.box.data(), ctx->down.box.size()));
   // tables
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
@@ -259,12 +320,23 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.l2q_binom, l2q.data(), l2q.size()));
     GQ_TRY(upload(ctx, d.m2q_binom, m2q.data(), m2q.size()));
   }
-  // workspace
-  GQ_TRY(alloc(ctx, d.sq, ns));
-  GQ_TRY(alloc(ctx, d.sdip, ns));
-  GQ_TRY(alloc(ctx, d.M, (size_t)nb * P1));
-  GQ_TRY(alloc(ctx, d.L, (size_t)nb * P1));
-  GQ_TRY(alloc(ctx, d.tv, 2 * nt));
+  return GQ_OK;
+}
+
+// Per-density buffers (strengths, box expansions, center rows, target slots) for nd densities;
+// grows on demand (synchronising the context's streams before freeing the old buffers).
+gq_status ensure_workspace(gq_ctx *ctx, int nd) {
+  if (nd <= ctx->ws_batch) return GQ_OK;
+  free_workspace(ctx);
+  auto &d = ctx->d;
+  const size_t n = (size_t)nd, P1 = ctx->params.p_fmm + 1, nb = ctx->tree.n_boxes();
+  GQ_TRY(alloc_ws(ctx, d.sq, n * ctx->ns));
+  GQ_TRY(alloc_ws(ctx, d.sdip, n * ctx->ns));
+  GQ_TRY(alloc_ws(ctx, d.M, n * nb * P1));
+  GQ_TRY(alloc_ws(ctx, d.L, n * nb * P1));
+  GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->pq_bucket + 1)));
+  GQ_TRY(alloc_ws(ctx, d.tv, n * 2 * ctx->nt));
+  ctx->ws_batch = nd;
   return GQ_OK;
 }
 
@@ -288,9 +360,12 @@ gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1
   if (ld1 < ctx->ns || (dens2 && ld2 < ctx->ns) || ld_out < ctx->nt)
     return fail(ctx, GQ_EINVAL, "leading dimension smaller than the row length");
   GQ_HIP(ctx, hipSetDevice(ctx->device));
-  for (int64_t j = 0; j < n_dens; ++j) {
-    hipError_t e = gq::run_eval(ctx, kind, dens1 + j * ld1, dens2 ? dens2 + j * ld2 : nullptr,
-                                out + j * ld_out, direct);
+  const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
+  GQ_TRY(ensure_workspace(ctx, batch));
+  for (int64_t j = 0; j < n_dens; j += batch) {
+    const int nd = (int)std::min<int64_t>(batch, n_dens - j);
+    hipError_t e = gq::run_eval(ctx, kind, dens1 + j * ld1, ld1, dens2 ? dens2 + j * ld2 : nullptr,
+                                ld2, out + j * ld_out, ld_out, nd, direct);
     if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
   }
   return GQ_OK;
@@ -333,7 +408,8 @@ gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
     // default-priority, non-blocking side stream; events carry the fork/join dependencies
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_up, hipEventDisableTiming) != hipSuccess) {
       gq_destroy(ctx);
       return fail(nullptr, GQ_EHIP, "stream/event creation failed");
     }
@@ -359,6 +435,7 @@ gq_status gq_destroy(gq_ctx *ctx) {
   if (ctx->device >= 0) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
   }
   delete ctx;

@@ -25,10 +25,15 @@ constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 template <int KIND>
 __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const double *__restrict__ sw,
                          const double2 *__restrict__ snrm, const double *__restrict__ d1,
-                         const double *__restrict__ d2, double *__restrict__ sq,
-                         double2 *__restrict__ sdip) {
+                         int64_t ld1, const double *__restrict__ d2, int64_t ld2,
+                         double *__restrict__ sq, double2 *__restrict__ sdip) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
+  const int64_t jd = blockIdx.y;  // density of the batch
+  d1 += jd * ld1;
+  if (KIND == 3) d2 += jd * ld2;
+  sq += jd * ns;
+  sdip += jd * ns;
   const int32_t o = sperm[i];
   const double w = sw[i];
   if (KIND == 1) sq[i] = w * d1[o];
@@ -40,7 +45,8 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 2a, P2M for leaf boxes: one work-group per leaf, lane k computes coefficient k.
+// Stage 2a, P2M for leaf boxes: one work-group per leaf, the leaf's sources staged in LDS, lane k
+// computes coefficient k.
 template <int KIND>
 __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ bc,
@@ -51,25 +57,45 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ sxy,
                                             const double *__restrict__ sq,
                                             const double2 *__restrict__ sdip, int P1,
-                                            double2 *__restrict__ M) {
+                                            double2 *__restrict__ M, int64_t src_st,
+                                            int64_t box_st) {
+  __shared__ double2 t_y[64];
+  __shared__ double t_q[(KIND & 1) ? 64 : 1];
+  __shared__ double2 t_d[(KIND & 2) ? 64 : 1];
   const int32_t b = leaves[blockIdx.x];
   const int k = threadIdx.x;
-  if (k >= P1) return;
+  const int64_t jd = blockIdx.y;
+  sq += jd * src_st;
+  sdip += jd * src_st;
+  M += jd * box_st;
   const double2 c = bc[b];
   const double is = level_inv_side[blevel[b]];
-  double2 acc = make_double2(0.0, 0.0);
   const double ik = k > 0 ? 1.0 / k : 0.0;
-  for (int32_t s = bsrc0[b]; s < bsrc1[b]; ++s) {
-    const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-    if (k == 0) {
-      if (KIND & 1) acc.x += sq[s];
-      continue;
+  double2 acc = make_double2(0.0, 0.0);
+  const int32_t s0 = bsrc0[b], s1 = bsrc1[b];
+  for (int32_t base = s0; base < s1; base += 64) {
+    const int n = min(64, (int)(s1 - base));
+    __syncthreads();
+    if (k < n) {
+      const int32_t s = base + k;
+      t_y[k] = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+      if (KIND & 1) t_q[k] = sq[s];
+      if (KIND & 2) t_d[k] = cscale(sdip[s], -is);
     }
-    const double2 pk1 = cpowi(y, k - 1);
-    if (KIND & 1) acc = caxpy(-sq[s] * ik, cmul(pk1, y), acc);
-    if (KIND & 2) acc = cfma(cscale(sdip[s], -is), pk1, acc);
+    __syncthreads();
+    if (k < P1) {
+      for (int j = 0; j < n; ++j) {
+        if (k == 0) {
+          if (KIND & 1) acc.x += t_q[j];
+          continue;
+        }
+        const double2 pk1 = cpowi(t_y[j], k - 1);
+        if (KIND & 1) acc = caxpy(-t_q[j] * ik, cmul(pk1, t_y[j]), acc);
+        if (KIND & 2) acc = cfma(t_d[j], pk1, acc);
+      }
+    }
   }
-  M[(int64_t)b * P1 + k] = acc;
+  if (k < P1) M[(int64_t)b * P1 + k] = acc;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -78,10 +104,11 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
 __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restrict__ bchild,
                                             const double *__restrict__ Rt,
                                             const double2 *__restrict__ omega, int P1,
-                                            double2 *__restrict__ M) {
+                                            double2 *__restrict__ M, int64_t box_st) {
   __shared__ double2 X[4][64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
+  M += (int64_t)blockIdx.y * box_st;
   const int32_t *ch = bchild + 4 * (int64_t)b;
   if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf (uniform per block)
 #pragma unroll
@@ -127,10 +154,17 @@ __global__ void __launch_bounds__(64) k_far_local(
     const double2 *__restrict__ M, const double *__restrict__ Bt, const double2 *__restrict__ opow,
     const double *__restrict__ ologabs, const double2 *__restrict__ sxy,
     const double *__restrict__ sq, const double2 *__restrict__ sdip, int P1,
-    double2 *__restrict__ L) {
+    double2 *__restrict__ L, int64_t src_st, int64_t box_st) {
   __shared__ double2 X[kM2LBatch][64];
   __shared__ int32_t offs[kM2LBatch];
   const int32_t b = tboxes[blockIdx.x];
+  {
+    const int64_t jd = blockIdx.y;
+    M += jd * box_st;
+    L += jd * box_st;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+  }
   const int m = threadIdx.x;
   const int lev = blevel[b];
   const double logs = level_log_side[lev];
@@ -199,11 +233,12 @@ __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restr
                                             const int32_t *__restrict__ is_tbox,
                                             const double *__restrict__ Rt,
                                             const double2 *__restrict__ omega, int P1,
-                                            double2 *__restrict__ L) {
+                                            double2 *__restrict__ L, int64_t box_st) {
   __shared__ double2 X[64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
   if (!is_tbox[b]) return;  // uniform per block
+  L += (int64_t)blockIdx.y * box_st;
   const int32_t p = bparent[b];
   const int q = bquad[b];
   if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
@@ -213,6 +248,77 @@ __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restr
   for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
   const double2 w = omega[q * 8 + (m & 7)];
   L[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Stages 2b and 7 for the sparse levels above a cut level in a single work-group (the levels
+// below the cut, which hold most boxes, use one k_m2m / k_l2l launch per level). The schedule is a
+// range of stages, each a list of boxes whose inputs are complete; the wavefronts take the boxes
+// of a stage in rounds, lane m producing coefficient m.
+constexpr int kSchedMaxP1 = GQ_MAX_P_FMM + 1;
+
+template <bool UP>
+__global__ void __launch_bounds__(1024) k_tree_sched(
+    int32_t blk0, const int32_t *__restrict__ blk_stage, const int32_t *__restrict__ stage_box,
+    const int32_t *__restrict__ sched_box, const int32_t *__restrict__ bchild,
+    const int32_t *__restrict__ bparent, const int8_t *__restrict__ bquad,
+    const double *__restrict__ Rt, const double2 *__restrict__ omega, int P1,
+    double2 *__restrict__ E, int64_t box_st) {
+  // LDS: the real shift matrix (P1 x P1, k-major) and, per wavefront, its box's inputs already
+  // multiplied by the unit factors (UP: 4 children x w_q^-k; down: the parent x w_q^k).
+  extern __shared__ double lds[];
+  double *sR = lds;
+  double2 *sX = reinterpret_cast<double2 *>(lds + P1 * P1);
+  E += (int64_t)blockIdx.y * box_st;
+  const int32_t blk = blk0 + blockIdx.x;
+  const int wave = threadIdx.x >> 6, m = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x; i < P1 * P1; i += blockDim.x) sR[i] = Rt[i];
+  double2 *X = sX + wave * (UP ? 4 : 1) * kSchedMaxP1;
+  for (int32_t st = blk_stage[blk]; st < blk_stage[blk + 1]; ++st) {
+    // rounds of nw boxes: every wavefront runs the same number of rounds (barriers stay uniform)
+    for (int32_t i0 = stage_box[st]; i0 < stage_box[st + 1]; i0 += nw) {
+      const int32_t i = i0 + wave;
+      const bool has = i < stage_box[st + 1];
+      const int32_t b = has ? sched_box[i] : 0;
+      __syncthreads();
+      if (has && m < P1) {
+        if (UP) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int32_t ch = bchild[4 * (int64_t)b + q];
+            const double2 w = omega[q * 8 + (m & 7)];
+            X[q * kSchedMaxP1 + m] = ch < 0 ? make_double2(0.0, 0.0)
+                                            : cmul(E[(int64_t)ch * P1 + m], make_double2(w.x, -w.y));
+          }
+        } else {
+          X[m] = cmul(E[(int64_t)bparent[b] * P1 + m], omega[bquad[b] * 8 + (m & 7)]);
+        }
+      }
+      __syncthreads();
+      if (has && m < P1) {
+        if (UP) {
+          double2 acc[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+          for (int k = 0; k <= m; ++k) {
+            const double r = sR[k * P1 + m];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q * kSchedMaxP1 + k], acc[q]);
+          }
+          double2 out = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
+          E[(int64_t)b * P1 + m] = out;
+        } else {
+          double2 acc = make_double2(0.0, 0.0);
+          for (int k = m; k < P1; ++k) acc = caxpy(sR[k * P1 + m], X[k], acc);
+          const double2 w = omega[bquad[b] * 8 + (m & 7)];
+          E[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, E[(int64_t)b * P1 + m]);
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -306,12 +412,19 @@ __global__ void __launch_bounds__(64) k_near(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
-    const double2 *__restrict__ sdip, double2 *__restrict__ anear) {
+    const double2 *__restrict__ sdip, double2 *__restrict__ anear, int64_t src_st,
+    int64_t row_st) {
   __shared__ double2 t_xy[kNearBatch];
   __shared__ double t_q[(KIND & 1) ? kNearBatch : 1];
   __shared__ double2 t_d[(KIND & 2) ? kNearBatch : 1];
   const int32_t w = (int32_t)blockIdx.x;  // one wavefront per work-group and per item
   const int lane = threadIdx.x;
+  {
+    const int64_t jd = blockIdx.y;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+    anear += jd * row_st;
+  }
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
   const int n_ctr = i1.x, lg = i1.y;
@@ -416,10 +529,13 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_side, const double2 *__restrict__ M, int P1,
-    const double *__restrict__ m2q_binom, double2 *__restrict__ anear) {
+    const double *__restrict__ m2q_binom, double2 *__restrict__ anear, int64_t box_st,
+    int64_t row_st) {
   const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= n_items) return;  // uniform per wavefront
+  M += (int64_t)blockIdx.y * box_st;
+  anear += (int64_t)blockIdx.y * row_st;
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
   const int n_ctr = i1.x, lg = i1.y;
@@ -465,9 +581,17 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_chunks,
     const double2 *__restrict__ anear,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
-    const double2 *__restrict__ txy, double *__restrict__ tv) {
+    const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
+    int64_t tv_st) {
   const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  {
+    const int64_t jd = blockIdx.y;
+    L += jd * box_st;
+    M += jd * box_st;
+    anear += jd * row_st;
+    tv += jd * tv_st;
+  }
   const double2 cc = cxy[c];
   const double r = cr[c];
   const int32_t b = cbox[c];
@@ -519,8 +643,14 @@ __global__ void __launch_bounds__(256) k_direct(
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, const int32_t *__restrict__ c2t_start,
     const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
-    double *__restrict__ tv) {
+    double *__restrict__ tv, int64_t src_st, int64_t tv_st) {
   __shared__ double2 ts[256];
+  {
+    const int64_t jd = blockIdx.y;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+    tv += jd * tv_st;
+  }
   __shared__ double tq[256];
   __shared__ double2 td[256];
   const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -556,9 +686,11 @@ __global__ void __launch_bounds__(256) k_direct(
 // ------------------------------------------------------------------------------------------
 // Average the target slots into the caller's output row.
 __global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const double *__restrict__ tv,
-                           double *__restrict__ out) {
+                           double *__restrict__ out, int64_t tv_st, int64_t ld_out) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
+  tv += (int64_t)blockIdx.y * tv_st;
+  out += (int64_t)blockIdx.y * ld_out;
   double s = 0.0;
   int n = 0;
   if (tctr[2 * t] >= 0) { s += tv[2 * t]; n++; }
@@ -600,21 +732,39 @@ class StageTimer {
   hipEvent_t a_ = nullptr;
 };
 
+// Dynamic LDS of k_tree_sched: the shift matrix plus per-wavefront inputs.
+size_t sched_lds(int P1, int threads, bool up) {
+  return sizeof(double) * P1 * P1 + sizeof(double2) * (threads / 64) * (up ? 4 : 1) * kSchedMaxP1;
+}
+
+// Per-density strides of the batched buffers (elements).
+struct Strides {
+  int64_t src, box, row, tv;
+};
+
+Strides strides(const gq_ctx *ctx) {
+  const int64_t P1 = ctx->params.p_fmm + 1;
+  return {ctx->ns, ctx->tree.n_boxes() * P1, ctx->n_near_rows * (ctx->pq_bucket + 1), 2 * ctx->nt};
+}
+
 template <int KIND>
-hipError_t launch_gather(gq_ctx *ctx, const double *d1, const double *d2) {
+hipError_t launch_gather(gq_ctx *ctx, const double *d1, int64_t ld1, const double *d2,
+                         int64_t ld2, int nd) {
   StageTimer st_(ctx, GQ_STAGE_GATHER);
   const int32_t ns = (int32_t)ctx->ns;
-  hipLaunchKernelGGL(k_gather<KIND>, dim3((ns + 255) / 256), dim3(256), 0, ctx->stream, ns,
-                     ctx->d.sperm, ctx->d.sw, ctx->d.snrm, d1, d2, ctx->d.sq, ctx->d.sdip);
+  hipLaunchKernelGGL(k_gather<KIND>, dim3((ns + 255) / 256, nd), dim3(256), 0, ctx->stream, ns,
+                     ctx->d.sperm, ctx->d.sw, ctx->d.snrm, d1, ld1, d2, ld2, ctx->d.sq,
+                     ctx->d.sdip);
   return hipGetLastError();
 }
 
 template <int KIND, int PQ>
-hipError_t launch_fmm(gq_ctx *ctx) {
+hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   auto &d = ctx->d;
   auto &t = ctx->tree;
   const int P1 = ctx->params.p_fmm + 1;
   const hipStream_t st = ctx->stream;
+  const Strides S = strides(ctx);
   // The direct-interaction kernel needs only the source strengths: it runs on the side stream
   // while the upward pass, M2L, List 3 far and the downward pass proceed on the caller's stream.
   const int32_t nitems = (int32_t)ctx->n_near_items;
@@ -624,80 +774,98 @@ hipError_t launch_fmm(gq_ctx *ctx) {
   if (e != hipSuccess) return e;
   if (nitems > 0) {
     StageTimer st_(ctx, GQ_STAGE_NEAR, ctx->side);
-    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems), dim3(64), 0, ctx->side, nitems,
-                       d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear);
+    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems, nd), dim3(64), 0, ctx->side, nitems,
+                       d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear, S.src,
+                       S.row);
   }
-  e = hipEventRecord(ctx->ev_join, ctx->side);
-  if (e != hipSuccess) return e;
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    hipLaunchKernelGGL(k_p2m<KIND>, dim3(nleaf), dim3(64), 0, st, d.leaves, d.bc, d.blevel, d.bsrc0,
-                       d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, d.M);
+    hipLaunchKernelGGL(k_p2m<KIND>, dim3(nleaf, nd), dim3(64), 0, st, d.leaves, d.bc, d.blevel,
+                       d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, d.M, S.src,
+                       S.box);
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    for (int l = t.n_levels - 2; l >= 0; --l) {
+    const TreeSchedule &u = ctx->up;
+    for (int l = t.n_levels - 2; l >= u.cut_level; --l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
-        hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(64), 0, st, b0, d.bchild, d.m2m_rt, d.omega, P1,
-                           d.M);
+        hipLaunchKernelGGL(k_m2m, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, d.m2m_rt, d.omega,
+                           P1, d.M, S.box);
     }
+    if (u.has_top)
+      hipLaunchKernelGGL(k_tree_sched<true>, dim3(1, nd), dim3(kTopThreads),
+                         sched_lds(P1, kTopThreads, true), st, 0, d.up_blk, d.up_stage, d.up_box,
+                         d.bchild, d.bparent, d.bquad, d.m2m_rt, d.omega, P1, d.M, S.box);
   }
+  e = hipEventRecord(ctx->ev_up, st);
+  if (e != hipSuccess) return e;
+  // List 3 far multipoles -> centers on the side stream, once the upward pass is complete
+  e = hipStreamWaitEvent(ctx->side, ctx->ev_up, 0);
+  if (e != hipSuccess) return e;
+  const int32_t nfi = (int32_t)ctx->n_far_items;
+  if (nfi > 0) {
+    StageTimer st_(ctx, GQ_STAGE_M2QBXL, ctx->side);
+    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4, nd), dim3(256), 0, ctx->side, nfi,
+                       d.far_items, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, d.M, P1,
+                       d.m2q_binom, d.anear, S.box, S.row);
+  }
+  e = hipEventRecord(ctx->ev_join, ctx->side);
+  if (e != hipSuccess) return e;
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
+    hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
                        d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2l_bt, d.opow, d.ologabs, d.sxy, d.sq,
-                       d.sdip, P1, d.L);
+                       d.sdip, P1, d.L, S.src, S.box);
   }
   {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    for (int l = 1; l < t.n_levels; ++l) {
+    const TreeSchedule &dn = ctx->down;
+    if (dn.has_top)
+      hipLaunchKernelGGL(k_tree_sched<false>, dim3(1, nd), dim3(kTopThreads),
+                         sched_lds(P1, kTopThreads, false), st, 0, d.dn_blk, d.dn_stage, d.dn_box,
+                         d.bchild, d.bparent, d.bquad, d.l2l_rt, d.omega, P1, d.L, S.box);
+    for (int l = dn.cut_level + 1; l < t.n_levels; ++l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
-        hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
-                           d.l2l_rt, d.omega, P1, d.L);
+        hipLaunchKernelGGL(k_l2l, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
+                           d.l2l_rt, d.omega, P1, d.L, S.box);
     }
-  }
-  const int32_t nfi = (int32_t)ctx->n_far_items;
-  if (nfi > 0) {
-    StageTimer st_(ctx, GQ_STAGE_M2QBXL);
-    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4), dim3(256), 0, st, nfi, d.far_items,
-                       d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, d.M, P1, d.m2q_binom,
-                       d.anear);
   }
   const int32_t nc = (int32_t)ctx->nc;
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;
   {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
-    hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, st, nc,
+    hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256, nd), dim3(256), 0, st, nc,
                        d.cxy, d.cr, d.cbox, d.bc, d.blevel, d.level_side, d.L, d.M, P1,
                        d.l2q_binom, d.m2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
-                       d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv);
+                       d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
   }
   return hipGetLastError();
 }
 
 template <int KIND, int PQ>
-hipError_t launch_direct(gq_ctx *ctx) {
+hipError_t launch_direct(gq_ctx *ctx, int nd) {
   auto &d = ctx->d;
   const int32_t nc = (int32_t)ctx->nc;
+  const Strides S = strides(ctx);
   StageTimer st_(ctx, GQ_STAGE_DIRECT);
-  hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((nc + 255) / 256), dim3(256), 0, ctx->stream, nc,
-                     d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip, d.c2t_start, d.c2t_slot,
-                     d.txy, d.tv);
+  hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((nc + 255) / 256, nd), dim3(256), 0, ctx->stream,
+                     nc, d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip, d.c2t_start,
+                     d.c2t_slot, d.txy, d.tv, S.src, S.tv);
   return hipGetLastError();
 }
 
 template <int PQ>
-hipError_t dispatch_kind(gq_ctx *ctx, int kind, bool direct) {
+hipError_t dispatch_kind(gq_ctx *ctx, int kind, bool direct, int nd) {
   switch (kind) {
-    case 1: return direct ? launch_direct<1, PQ>(ctx) : launch_fmm<1, PQ>(ctx);
-    case 2: return direct ? launch_direct<2, PQ>(ctx) : launch_fmm<2, PQ>(ctx);
-    case 3: return direct ? launch_direct<3, PQ>(ctx) : launch_fmm<3, PQ>(ctx);
+    case 1: return direct ? launch_direct<1, PQ>(ctx, nd) : launch_fmm<1, PQ>(ctx, nd);
+    case 2: return direct ? launch_direct<2, PQ>(ctx, nd) : launch_fmm<2, PQ>(ctx, nd);
+    case 3: return direct ? launch_direct<3, PQ>(ctx, nd) : launch_fmm<3, PQ>(ctx, nd);
   }
   return hipErrorInvalidValue;
 }
@@ -714,20 +882,20 @@ bool pq_supported(int pq) {
   return false;
 }
 
-hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, double *out,
-                    bool direct) {
+hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
+                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct) {
   hipError_t e;
   ctx->cur_kind = kind;
   switch (kind) {
-    case 1: e = launch_gather<1>(ctx, d1, d2); break;
-    case 2: e = launch_gather<2>(ctx, d1, d2); break;
-    case 3: e = launch_gather<3>(ctx, d1, d2); break;
+    case 1: e = launch_gather<1>(ctx, d1, ld1, d2, ld2, nd); break;
+    case 2: e = launch_gather<2>(ctx, d1, ld1, d2, ld2, nd); break;
+    case 3: e = launch_gather<3>(ctx, d1, ld1, d2, ld2, nd); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
   switch (ctx->pq_bucket) {
 #define GQ_CASE(P) \
-  case P: e = dispatch_kind<P>(ctx, kind, direct); break;
+  case P: e = dispatch_kind<P>(ctx, kind, direct, nd); break;
     GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
     default: return hipErrorInvalidValue;
@@ -735,8 +903,8 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, d
   if (e != hipSuccess) return e;
   const int32_t nt = (int32_t)ctx->nt;
   StageTimer st_(ctx, GQ_STAGE_FINALIZE);
-  hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256), dim3(256), 0, ctx->stream, nt, ctx->d.tctr,
-                     ctx->d.tv, out);
+  hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
+                     ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out);
   return hipGetLastError();
 }
 

@@ -12,8 +12,15 @@ namespace gq {
 
 bool pq_supported(int pq);
 
-// One density: gather strengths, run the FMM stages (or direct QBX), write out[0..n_tgt).
-hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, const double *d2, double *out,
-                    bool direct);
+// Threads of the single work-group covering the tree levels above the cut.
+constexpr int kTopThreads = 512;
+
+// Maximum densities per launch (the batch dimension of every kernel's grid).
+constexpr int kMaxDensBatch = 64;
+
+// nd densities (rows of d1/d2 with strides ld1/ld2): gather strengths, run the FMM stages (or
+// direct QBX), write nd output rows of n_tgt values with stride ld_out.
+hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
+                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct);
 
 }  // namespace gq

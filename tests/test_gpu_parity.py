@@ -167,3 +167,26 @@ def test_empty_batch_and_errors(c1):
     with pytest.raises(GQError) as e:
         _ctx(c1, p_qbx=7, p_fmm=15)  # no compiled kernel for this order
     assert e.value.status == _lib.GQ_EUNSUP
+
+
+def test_density_batches_match_single_evaluations(c1):
+    """70 densities (two launches of the batch dimension), padded row strides, S - D kind: each
+    row equals the single-density evaluation bitwise and the oracle within the gate."""
+    q, _ = _ctx(c1, p_qbx=8, p_fmm=30)
+    n, pad = 70, 7
+    rng = np.random.default_rng(3)
+    d1 = torch.zeros((n, c1.n_src + pad), dtype=torch.float64, device="cuda:0")
+    d2 = torch.zeros((n, c1.n_src + pad), dtype=torch.float64, device="cuda:0")
+    h1 = np.stack([gi.fourier_density(c1, seed=int(s)) for s in rng.integers(0, 10**6, n)])
+    h2 = np.stack([gi.fourier_density(c1, seed=int(s)) for s in rng.integers(0, 10**6, n)])
+    d1[:, :c1.n_src] = _dev(h1)
+    d2[:, :c1.n_src] = _dev(h2)
+    out = torch.full((n, c1.n_tgt + pad), np.nan, dtype=torch.float64, device="cuda:0")
+    q.eval(3, d1[:, :c1.n_src], d2[:, :c1.n_src], out=out[:, :c1.n_tgt])
+    res = out.cpu().numpy()
+    assert np.isnan(res[:, c1.n_tgt:]).all(), "wrote outside the output rows"
+    for j in (0, 33, 63, 64, 69):
+        single = q.eval(3, _dev(h1[j]), _dev(h2[j])).cpu().numpy()
+        assert np.array_equal(single, res[j, :c1.n_tgt])
+    ref = oracle.qbx_eval(c1, 3, h1[69], h2[69], p_qbx=8)
+    assert _rel(res[69, :c1.n_tgt], ref) < 1e-10
