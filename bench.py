@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--batch", type=int, default=64, help="densities of the batched variant")
+    ap.add_argument("--overlap", type=int, default=1, choices=(0, 1),
+                    help="run direct and List 3 far work on a second stream")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -110,7 +112,7 @@ def main():
     q = QBXFMM(device=0)
     q.set_geometry_from(geom)
     stats = q.build(p_qbx=p_qbx, p_fmm=p_fmm, n_max=64, count_mode=0, t_f=0.9,
-                    w3far_min_sources=15)
+                    w3far_min_sources=15, overlap=args.overlap)
     dens = torch.as_tensor(dens_h, dtype=torch.float64, device="cuda:0")
     out = torch.empty((2, geom.n_tgt), dtype=torch.float64, device="cuda:0")
 
@@ -213,7 +215,7 @@ def main():
                    "n_ctr": geom.n_ctr, "p_qbx": p_qbx, "p_fmm": p_fmm,
                    "boxes": stats["n_boxes"], "levels": stats["n_levels"],
                    "list2_pairs": stats["n_list2"], "near_pairs": stats["near_pairs"],
-                   "list3_far_pairs": stats["list3_far_pairs"],
+                   "list3_far_pairs": stats["list3_far_pairs"], "overlap": args.overlap,
                    "build_ms": round(stats["build_ms"], 1)},
         "variants": variants,
         "stage_ms_per_step": breakdown,

@@ -62,13 +62,15 @@ typedef struct {
                              through its leaves; 0 disables                                     */
   int precision;          /* GQ_FP64 or GQ_MIXED_FP32                                           */
   int max_levels;         /* depth guard for coincident particles (not in the paper); <= 28     */
+  int overlap;            /* 1: direct and List 3 far work on a second stream, overlapping the
+                             tree passes; 0: everything on the caller's stream                  */
 } gq_params;
 
 #define GQ_MAX_P_QBX 20
 #define GQ_MAX_P_FMM 63
 
 /* Fill *p with the defaults: p_qbx 12, p_fmm 30, n_max 64, count_mode 0, t_f 0.9,
- * w3far_min_sources 15, GQ_FP64, max_levels 24. */
+ * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1. */
 gq_status gq_default_params(gq_params *p);
 
 /* Create a context on HIP device `device` (>= 0) using `hip_stream` (a hipStream_t, may be NULL for

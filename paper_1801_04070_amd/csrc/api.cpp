@@ -166,42 +166,6 @@ gq_status upload_near_work(gq_ctx *ctx) {
   return GQ_OK;
 }
 
-// Schedules of the levels above the cut for the single-work-group upward (M2M) and downward
-// (L2L) passes. The cut is the first level with at least kCutBoxes non-leaf boxes; the levels
-// below it run one launch per level.
-constexpr int kCutBoxes = 64;
-
-void build_schedules(gq_ctx *ctx) {
-  const gq::Tree &t = ctx->tree;
-  const int L = t.n_levels;
-  int cut = std::max(L - 1, 0);
-  for (int l = 0; l < L; ++l) {
-    int64_t nonleaf = 0;
-    for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) nonleaf += !t.is_leaf(b);
-    if (nonleaf >= kCutBoxes) { cut = l; break; }
-  }
-  auto build = [&](gq::TreeSchedule &S, bool up) {
-    S = gq::TreeSchedule();
-    S.cut_level = cut;
-    S.blk.push_back(0);
-    S.stage.push_back(0);
-    bool any = false;
-    for (int i = 0; i < L; ++i) {
-      const int l = up ? L - 1 - i : i;
-      // upward: non-leaf boxes of levels < cut (deepest first); downward: boxes with targets
-      // below them at levels 1..cut (top first)
-      if (up ? l >= cut : (l > cut || l < 1)) continue;
-      const size_t before = S.box.size();
-      for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
-        if (up ? !t.is_leaf(b) : (bool)t.has_tgt[b]) S.box.push_back((int32_t)b);
-      if (S.box.size() > before) { S.stage.push_back((int32_t)S.box.size()); any = true; }
-    }
-    if (any) { S.blk.push_back((int32_t)S.stage.size() - 1); S.has_top = true; }
-  };
-  build(ctx->up, true);
-  build(ctx->down, false);
-}
-
 gq_status upload_all(gq_ctx *ctx) {
   const gq::Tree &t = ctx->tree;
   auto &d = ctx->d;
@@ -293,13 +257,7 @@ gq_status upload_all(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.xf_start, to_i32(t.list4f.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.xf_idx, t.list4f.idx.data(), t.list4f.idx.size()));
   GQ_TRY(upload_near_work(ctx));
-  build_schedules(ctx);
-  GQ_TRY(upload(ctx, d.up_blk, ctx->up.blk.data(), ctx->up.blk.size()));
-  GQ_TRY(upload(ctx, d.up_stage, ctx->up.stage.data(), ctx->up.stage.size()));
-  GQ_TRY(upload(ctx, d.up_box, ctx->up.box.data(), ctx->up.box.size()));
-  GQ_TRY(upload(ctx, d.dn_blk, ctx->down.blk.data(), ctx->down.blk.size()));
-  GQ_TRY(upload(ctx, d.dn_stage, ctx->down.stage.data(), ctx->down.stage.size()));
-  GQ_TRY(upload(ctx, d.dn_box, ctx->down.box.data(), ctx->down.box.size()));
+
   // tables
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
@@ -385,6 +343,7 @@ gq_status gq_default_params(gq_params *p) {
   p->w3far_min_sources = 15;
   p->precision = GQ_FP64;
   p->max_levels = 24;
+  p->overlap = 1;
   return GQ_OK;
 }
 
@@ -512,6 +471,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.precision != GQ_FP64) return fail(ctx, GQ_EUNSUP, "only GQ_FP64 is supported in this build");
   if (p.count_mode != 0 && p.count_mode != 1) return fail(ctx, GQ_EINVAL, "count_mode must be 0 or 1");
   if (p.w3far_min_sources < 0) return fail(ctx, GQ_EINVAL, "w3far_min_sources must be >= 0");
+  if (p.overlap != 0 && p.overlap != 1) return fail(ctx, GQ_EINVAL, "overlap must be 0 or 1");
   free_device(ctx);
   ctx->params = p;
   ctx->pq_bucket = p.p_qbx;

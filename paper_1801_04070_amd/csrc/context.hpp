@@ -50,9 +50,6 @@ struct DevBuffers {
   int32_t *part_base = nullptr;      // first near row of each box
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
-  // scheduled upward (M2M) and downward (L2L) passes, see TreeSchedule
-  int32_t *up_blk = nullptr, *up_stage = nullptr, *up_box = nullptr;
-  int32_t *dn_blk = nullptr, *dn_stage = nullptr, *dn_box = nullptr;
   // tables
   double2 *opow = nullptr, *omega = nullptr;
   double *m2m_rt = nullptr, *l2l_rt = nullptr, *m2l_bt = nullptr, *ologabs = nullptr;
@@ -63,14 +60,6 @@ struct DevBuffers {
   double2 *sdip = nullptr;           // per-source dipole  w * tau * n
   double2 *M = nullptr, *L = nullptr;
   double *tv = nullptr;              // per target slot values
-};
-
-// Single-work-group schedule of the levels above the cut of a tree pass: stages
-// [blk[0], blk[1]), stage s is the box list box[stage[s] .. stage[s+1]).
-struct TreeSchedule {
-  bool has_top = false;
-  int cut_level = 0;
-  std::vector<int32_t> blk, stage, box;
 };
 
 }  // namespace gq
@@ -94,7 +83,6 @@ struct gq_ctx {
   int pq_bucket = 0;                 // compiled QBX order used by the kernels
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
-  gq::TreeSchedule up, down;
   gq::DevBuffers d;
   std::vector<void *> allocations;   // tree, list and table allocations, freed together
   std::vector<void *> ws_allocations;  // per-density workspace, sized for ws_batch densities

@@ -137,13 +137,19 @@ __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restr
 }
 
 // ------------------------------------------------------------------------------------------
-// Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One work-group per
-// target-or-ancestor box; lane m computes coefficient m. M2L (eq. (m2l), corrected a_0 sign)
-// in factored form beta_m = o^-m sum_k B[m][k] (a_k o^-k) (+ a_0 log|s o| in beta_0), register-
-// blocked over batches of kM2LBatch pairs so each B element is read once per batch.
-constexpr int kM2LBatch = 8;
+// Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One wavefront per
+// target-or-ancestor box.
+//
+// M2L (eq. (m2l), corrected a_0 sign) in factored form beta_m = o^-m sum_k B[m][k] (a_k o^-k)
+// (+ a_0 log|s o| in beta_0) on the matrix cores: the fixed real matrix B is the A operand of
+// v_mfma_f64_16x16x4f64 (RT row tiles x 4 RT k-steps, held in registers for the whole box), and a
+// batch of 8 List 2 pairs gives the 16 real columns (re/im of a_k o^-k per pair) of the B operand.
+// The 16 x 16 results are scaled by o^-m per pair and summed over the pairs with xor shuffles
+// inside each 16-lane group. Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, D[g + 4 v][j] in element v of lane j + 16 g.
+typedef double gq_d4 __attribute__((ext_vector_type(4)));
 
-template <int KIND>
+template <int KIND, int RT>
 __global__ void __launch_bounds__(64) k_far_local(
     const int32_t *__restrict__ tboxes, const double2 *__restrict__ bc,
     const int32_t *__restrict__ blevel, const double *__restrict__ level_inv_side,
@@ -155,8 +161,8 @@ __global__ void __launch_bounds__(64) k_far_local(
     const double *__restrict__ ologabs, const double2 *__restrict__ sxy,
     const double *__restrict__ sq, const double2 *__restrict__ sdip, int P1,
     double2 *__restrict__ L, int64_t src_st, int64_t box_st) {
-  __shared__ double2 X[kM2LBatch][64];
-  __shared__ int32_t offs[kM2LBatch];
+  constexpr int KS = 4 * RT;
+  __shared__ double2 Ls[16 * RT];
   const int32_t b = tboxes[blockIdx.x];
   {
     const int64_t jd = blockIdx.y;
@@ -165,63 +171,120 @@ __global__ void __launch_bounds__(64) k_far_local(
     sq += jd * src_st;
     sdip += jd * src_st;
   }
-  const int m = threadIdx.x;
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, c16 = lane & 15;
   const int lev = blevel[b];
   const double logs = level_log_side[lev];
-  double2 acc = make_double2(0.0, 0.0);
-  const int32_t v0 = v_start[b], v1 = v_start[b + 1];
-  for (int32_t j0 = v0; j0 < v1; j0 += kM2LBatch) {
-    const int nbat = min(kM2LBatch, (int)(v1 - j0));
-    __syncthreads();
+  double A[RT][KS];
 #pragma unroll
-    for (int p = 0; p < kM2LBatch; ++p) {
-      double2 x = make_double2(0.0, 0.0);
-      if (p < nbat && m < P1) {
-        const int32_t oi = v_off[j0 + p];
-        x = cmul(M[(int64_t)v_idx[j0 + p] * P1 + m], opow[(int64_t)oi * P1 + m]);
-        if (m == 0) offs[p] = oi;
-      }
-      X[p][m] = x;
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + c16, k = 4 * ks + g;
+      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : 0.0;
     }
-    __syncthreads();
-    if (m < P1) {
-      double2 Y[kM2LBatch];
+  double2 Lacc[RT][4];
 #pragma unroll
-      for (int p = 0; p < kM2LBatch; ++p) Y[p] = make_double2(0.0, 0.0);
-      for (int k = 0; k < P1; ++k) {
-        const double bk = Bt[k * P1 + m];
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int p = 0; p < kM2LBatch; ++p) Y[p] = caxpy(bk, X[p][k], Y[p]);
+    for (int v = 0; v < 4; ++v) Lacc[rt][v] = make_double2(0.0, 0.0);
+  double logsum0 = 0.0;
+  const int pr = c16 >> 1, comp = c16 & 1;
+  const int32_t v0 = v_start[b], v1 = v_start[b + 1];
+  for (int32_t j0 = v0; j0 < v1; j0 += 8) {
+    const int nbat = min(8, (int)(v1 - j0));
+    const bool pv = pr < nbat;
+    const int32_t d = pv ? v_idx[j0 + pr] : 0;
+    const int32_t oi = pv ? v_off[j0 + pr] : 0;
+    const double2 *Md = M + (int64_t)d * P1;
+    const double2 *op = opow + (int64_t)oi * P1;
+    double Bf[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g;
+      double x = 0.0;
+      if (pv && k < P1) {
+        const double2 mk = Md[k], ok = op[k];
+        x = comp ? fma(mk.x, ok.y, mk.y * ok.x) : fma(mk.x, ok.x, -mk.y * ok.y);
       }
+      Bf[ks] = x;
+    }
+    gq_d4 C[RT];
 #pragma unroll
-      for (int p = 0; p < kM2LBatch; ++p) {
-        if (p < nbat) {
-          const int32_t oi = offs[p];
-          acc = cfma(Y[p], opow[(int64_t)oi * P1 + m], acc);
-          if (m == 0) acc.x += X[p][0].x * (logs + ologabs[oi]);
+    for (int rt = 0; rt < RT; ++rt) {
+      C[rt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        C[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[rt][ks], Bf[ks], C[rt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + g + 4 * v;
+        const double y = C[rt][v];
+        const double yo = __shfl_xor(y, 1, 64);
+        double2 contrib = make_double2(0.0, 0.0);
+        if (pv && !comp && m < P1) contrib = cmul(make_double2(y, yo), op[m]);
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
+          contrib.x += __shfl_xor(contrib.x, o, 64);
+          contrib.y += __shfl_xor(contrib.y, o, 64);
+        }
+        Lacc[rt][v] = cadd(Lacc[rt][v], contrib);
+      }
+    // a_0 log|s o| of pair `lane` of the batch
+    if (lane < nbat)
+      logsum0 += M[(int64_t)v_idx[j0 + lane] * P1].x * (logs + ologabs[v_off[j0 + lane]]);
+  }
+  // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) logsum0 += __shfl_xor(logsum0, o, 64);
+  if (c16 == 0) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ls[16 * rt + g + 4 * v] = Lacc[rt][v];
+  }
+  __syncthreads();
+  // P2L (eq. (local) about c_b) for the sources of List 4 far boxes, 16 sources at a time: lane
+  // j < 16 forms source j's contributions to every coefficient with a running power of 1/y and
+  // stores them in LDS; lane m then sums column m.
+  __shared__ double2 Pc[16][16 * RT];
+  const int m = lane;
+  double2 acc = m < P1 ? Ls[m] : make_double2(0.0, 0.0);
+  if (m == 0) acc.x += logsum0;
+  const double2 c = bc[b];
+  const double is = level_inv_side[lev];
+  for (int32_t j = xf_start[b]; j < xf_start[b + 1]; ++j) {
+    const int32_t dd = xf_idx[j];
+    for (int32_t s0 = bsrc0[dd]; s0 < bsrc1[dd]; s0 += 16) {
+      const int n = min(16, (int)(bsrc1[dd] - s0));
+      __syncthreads();
+      if (lane < n) {
+        const int32_t s = s0 + lane;
+        const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+        const double2 inv = cinv(y);
+        const double q = (KIND & 1) ? sq[s] : 0.0;
+        const double2 dl = (KIND & 2) ? cscale(sdip[s], is) : make_double2(0.0, 0.0);
+        // coefficient 0: q log|s y| + d/y;  coefficient k: -q y^-k / k + d y^-(k+1)
+        double2 pw = inv;
+        double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
+        if (KIND & 1) c0.x += q * (logs + 0.5 * log(y.x * y.x + y.y * y.y));
+        Pc[lane][0] = c0;
+        for (int k = 1; k < P1; ++k) {
+          double2 ck = (KIND & 1) ? cscale(pw, -q / k) : make_double2(0.0, 0.0);
+          pw = cmul(pw, inv);
+          if (KIND & 2) ck = cfma(dl, pw, ck);
+          Pc[lane][k] = ck;
         }
       }
+      __syncthreads();
+      if (m < P1)
+        for (int jj = 0; jj < n; ++jj) acc = cadd(acc, Pc[jj][m]);
     }
   }
   if (m >= P1) return;
-  // P2L (eq. (local) about c_b) for the sources of List 4 far boxes
-  const double2 c = bc[b];
-  const double is = level_inv_side[lev];
-  const double im = m > 0 ? 1.0 / m : 0.0;
-  for (int32_t j = xf_start[b]; j < xf_start[b + 1]; ++j) {
-    const int32_t d = xf_idx[j];
-    for (int32_t s = bsrc0[d]; s < bsrc1[d]; ++s) {
-      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-      const double2 inv = cinv(y);
-      const double2 pw = cpowi(inv, m);
-      if (KIND & 1) {
-        const double q = sq[s];
-        if (m == 0) acc.x += q * (logs + 0.5 * log(y.x * y.x + y.y * y.y));
-        else acc = caxpy(-q * im, pw, acc);
-      }
-      if (KIND & 2) acc = cfma(cscale(sdip[s], is), cmul(pw, inv), acc);
-    }
-  }
   L[(int64_t)b * P1 + m] = acc;
 }
 
@@ -248,77 +311,6 @@ __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restr
   for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
   const double2 w = omega[q * 8 + (m & 7)];
   L[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
-}
-
-// ------------------------------------------------------------------------------------------
-// Stages 2b and 7 for the sparse levels above a cut level in a single work-group (the levels
-// below the cut, which hold most boxes, use one k_m2m / k_l2l launch per level). The schedule is a
-// range of stages, each a list of boxes whose inputs are complete; the wavefronts take the boxes
-// of a stage in rounds, lane m producing coefficient m.
-constexpr int kSchedMaxP1 = GQ_MAX_P_FMM + 1;
-
-template <bool UP>
-__global__ void __launch_bounds__(1024) k_tree_sched(
-    int32_t blk0, const int32_t *__restrict__ blk_stage, const int32_t *__restrict__ stage_box,
-    const int32_t *__restrict__ sched_box, const int32_t *__restrict__ bchild,
-    const int32_t *__restrict__ bparent, const int8_t *__restrict__ bquad,
-    const double *__restrict__ Rt, const double2 *__restrict__ omega, int P1,
-    double2 *__restrict__ E, int64_t box_st) {
-  // LDS: the real shift matrix (P1 x P1, k-major) and, per wavefront, its box's inputs already
-  // multiplied by the unit factors (UP: 4 children x w_q^-k; down: the parent x w_q^k).
-  extern __shared__ double lds[];
-  double *sR = lds;
-  double2 *sX = reinterpret_cast<double2 *>(lds + P1 * P1);
-  E += (int64_t)blockIdx.y * box_st;
-  const int32_t blk = blk0 + blockIdx.x;
-  const int wave = threadIdx.x >> 6, m = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int i = threadIdx.x; i < P1 * P1; i += blockDim.x) sR[i] = Rt[i];
-  double2 *X = sX + wave * (UP ? 4 : 1) * kSchedMaxP1;
-  for (int32_t st = blk_stage[blk]; st < blk_stage[blk + 1]; ++st) {
-    // rounds of nw boxes: every wavefront runs the same number of rounds (barriers stay uniform)
-    for (int32_t i0 = stage_box[st]; i0 < stage_box[st + 1]; i0 += nw) {
-      const int32_t i = i0 + wave;
-      const bool has = i < stage_box[st + 1];
-      const int32_t b = has ? sched_box[i] : 0;
-      __syncthreads();
-      if (has && m < P1) {
-        if (UP) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int32_t ch = bchild[4 * (int64_t)b + q];
-            const double2 w = omega[q * 8 + (m & 7)];
-            X[q * kSchedMaxP1 + m] = ch < 0 ? make_double2(0.0, 0.0)
-                                            : cmul(E[(int64_t)ch * P1 + m], make_double2(w.x, -w.y));
-          }
-        } else {
-          X[m] = cmul(E[(int64_t)bparent[b] * P1 + m], omega[bquad[b] * 8 + (m & 7)]);
-        }
-      }
-      __syncthreads();
-      if (has && m < P1) {
-        if (UP) {
-          double2 acc[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
-          for (int k = 0; k <= m; ++k) {
-            const double r = sR[k * P1 + m];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q * kSchedMaxP1 + k], acc[q]);
-          }
-          double2 out = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
-          E[(int64_t)b * P1 + m] = out;
-        } else {
-          double2 acc = make_double2(0.0, 0.0);
-          for (int k = m; k < P1; ++k) acc = caxpy(sR[k * P1 + m], X[k], acc);
-          const double2 w = omega[bquad[b] * 8 + (m & 7)];
-          E[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, E[(int64_t)b * P1 + m]);
-        }
-      }
-    }
-    __syncthreads();
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -486,37 +478,42 @@ __global__ void __launch_bounds__(64) k_near(
 // center c (eq. (m2l) with the corrected a_0 sign, truncated at order PQ), y = c - c_d:
 //   alpha_0 += a_0 log|y| + sum_k a_k (s_d/y)^k
 //   alpha_m += (-r/y)^m [-a_0/m + sum_k C(m+k-1,k-1) a_k (s_d/y)^k]
+//
+// The binomial-weighted sums V_m = sum_k C(m+k-1, k-1) T_k, T_k = a_k (s_d/y)^k, are formed without
+// binomials: since C(m+k-1, m) = sum_{j<=k} C(m+j-2, m-1), V_m is the (m+1)-fold suffix sum of T.
+// Walking k downwards with running sums S_0 += T_k, S_1 += S_0, ..., S_PQ += S_{PQ-1} leaves
+// V_m = S_m. The powers w^k are produced downwards from w^p by multiplications with 1/w.
 template <int PQ>
 __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r, int32_t d,
                                            const double2 *__restrict__ bc,
                                            const int32_t *__restrict__ blevel,
                                            const double *__restrict__ level_side,
-                                           const double2 *__restrict__ M, int P1,
-                                           const double *__restrict__ m2q_binom) {
+                                           const double2 *__restrict__ M, int P1) {
   const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
   const double2 iy = cinv(y);
-  const double2 w = cscale(iy, level_side[blevel[d]]);
+  const double sd = level_side[blevel[d]];
+  const double2 w = cscale(iy, sd);
+  const double2 iw = make_double2(y.x / sd, y.y / sd);
   const double2 u = cscale(iy, -r);
   const double2 *Md = M + (int64_t)d * P1;
   const double a0 = Md[0].x;
-  // V_m = -a_0/m + sum_k C(m+k-1,k-1) a_k w^k  (V_0 without the log term)
-  double2 V[PQ + 1];
-  V[0] = make_double2(0.0, 0.0);
+  double2 S[PQ + 1];
 #pragma unroll
-  for (int m = 1; m <= PQ; ++m) V[m] = make_double2(-a0 / m, 0.0);
-  double2 wk = make_double2(1.0, 0.0);
-  for (int k = 1; k < P1; ++k) {
-    wk = cmul(wk, w);
-    const double2 T = cmul(Md[k], wk);
+  for (int m = 0; m <= PQ; ++m) S[m] = make_double2(0.0, 0.0);
+  double2 wk = cpowi(w, P1 - 1);
+  for (int k = P1 - 1; k >= 1; --k) {
+    S[0] = cfma(Md[k], wk, S[0]);
 #pragma unroll
-    for (int m = 0; m <= PQ; ++m) V[m] = caxpy(m2q_binom[m * P1 + k], T, V[m]);
+    for (int m = 1; m <= PQ; ++m) S[m] = cadd(S[m], S[m - 1]);
+    wk = cmul(wk, iw);
   }
+  // alpha_0 += a_0 log|y| + V_0;  alpha_m += u^m (V_m - a_0/m)
   alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
-  alpha[0] = cadd(alpha[0], V[0]);
+  alpha[0] = cadd(alpha[0], S[0]);
   double2 pm = u;
 #pragma unroll
   for (int m = 1; m <= PQ; ++m) {
-    alpha[m] = cfma(pm, V[m], alpha[m]);
+    alpha[m] = cfma(pm, make_double2(S[m].x - a0 / m, S[m].y), alpha[m]);
     pm = cmul(pm, u);
   }
 }
@@ -551,7 +548,7 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   if (active)
     for (int32_t e = sl; e < len; e += nsl)
-      m2qbxl_add<PQ>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1, m2q_binom);
+      m2qbxl_add<PQ>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1);
   for (int o = nsl >> 1; o >= 1; o >>= 1) {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -732,11 +729,6 @@ class StageTimer {
   hipEvent_t a_ = nullptr;
 };
 
-// Dynamic LDS of k_tree_sched: the shift matrix plus per-wavefront inputs.
-size_t sched_lds(int P1, int threads, bool up) {
-  return sizeof(double) * P1 * P1 + sizeof(double2) * (threads / 64) * (up ? 4 : 1) * kSchedMaxP1;
-}
-
 // Per-density strides of the batched buffers (elements).
 struct Strides {
   int64_t src, box, row, tv;
@@ -766,15 +758,17 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   const hipStream_t st = ctx->stream;
   const Strides S = strides(ctx);
   // The direct-interaction kernel needs only the source strengths: it runs on the side stream
-  // while the upward pass, M2L, List 3 far and the downward pass proceed on the caller's stream.
+  // while the upward pass, M2L, List 3 far and the downward pass proceed on the caller's stream
+  // (without overlap both "streams" are the caller's stream and the events order nothing new).
+  const hipStream_t side = ctx->params.overlap ? ctx->side : st;
   const int32_t nitems = (int32_t)ctx->n_near_items;
   hipError_t e = hipEventRecord(ctx->ev_fork, st);
   if (e != hipSuccess) return e;
-  e = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   if (e != hipSuccess) return e;
   if (nitems > 0) {
-    StageTimer st_(ctx, GQ_STAGE_NEAR, ctx->side);
-    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems, nd), dim3(64), 0, ctx->side, nitems,
+    StageTimer st_(ctx, GQ_STAGE_NEAR, side);
+    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems, nd), dim3(64), 0, side, nitems,
                        d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear, S.src,
                        S.row);
   }
@@ -787,48 +781,40 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    const TreeSchedule &u = ctx->up;
-    for (int l = t.n_levels - 2; l >= u.cut_level; --l) {
+    for (int l = t.n_levels - 2; l >= 0; --l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
         hipLaunchKernelGGL(k_m2m, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, d.m2m_rt, d.omega,
                            P1, d.M, S.box);
     }
-    if (u.has_top)
-      hipLaunchKernelGGL(k_tree_sched<true>, dim3(1, nd), dim3(kTopThreads),
-                         sched_lds(P1, kTopThreads, true), st, 0, d.up_blk, d.up_stage, d.up_box,
-                         d.bchild, d.bparent, d.bquad, d.m2m_rt, d.omega, P1, d.M, S.box);
   }
   e = hipEventRecord(ctx->ev_up, st);
   if (e != hipSuccess) return e;
   // List 3 far multipoles -> centers on the side stream, once the upward pass is complete
-  e = hipStreamWaitEvent(ctx->side, ctx->ev_up, 0);
+  e = hipStreamWaitEvent(side, ctx->ev_up, 0);
   if (e != hipSuccess) return e;
   const int32_t nfi = (int32_t)ctx->n_far_items;
   if (nfi > 0) {
-    StageTimer st_(ctx, GQ_STAGE_M2QBXL, ctx->side);
-    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4, nd), dim3(256), 0, ctx->side, nfi,
+    StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
+    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4, nd), dim3(256), 0, side, nfi,
                        d.far_items, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, d.M, P1,
                        d.m2q_binom, d.anear, S.box, S.row);
   }
-  e = hipEventRecord(ctx->ev_join, ctx->side);
+  e = hipEventRecord(ctx->ev_join, side);
   if (e != hipSuccess) return e;
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    hipLaunchKernelGGL(k_far_local<KIND>, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
+    auto kern = P1 <= 16 ? k_far_local<KIND, 1> : P1 <= 32 ? k_far_local<KIND, 2>
+              : P1 <= 48 ? k_far_local<KIND, 3> : k_far_local<KIND, 4>;
+    hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
                        d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2l_bt, d.opow, d.ologabs, d.sxy, d.sq,
                        d.sdip, P1, d.L, S.src, S.box);
   }
   {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    const TreeSchedule &dn = ctx->down;
-    if (dn.has_top)
-      hipLaunchKernelGGL(k_tree_sched<false>, dim3(1, nd), dim3(kTopThreads),
-                         sched_lds(P1, kTopThreads, false), st, 0, d.dn_blk, d.dn_stage, d.dn_box,
-                         d.bchild, d.bparent, d.bquad, d.l2l_rt, d.omega, P1, d.L, S.box);
-    for (int l = dn.cut_level + 1; l < t.n_levels; ++l) {
+    for (int l = 1; l < t.n_levels; ++l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
         hipLaunchKernelGGL(k_l2l, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,

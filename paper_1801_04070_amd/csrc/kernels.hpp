@@ -12,8 +12,6 @@ namespace gq {
 
 bool pq_supported(int pq);
 
-// Threads of the single work-group covering the tree levels above the cut.
-constexpr int kTopThreads = 512;
 
 // Maximum densities per launch (the batch dimension of every kernel's grid).
 constexpr int kMaxDensBatch = 64;
