@@ -265,6 +265,16 @@ gq_status upload_all(gq_ctx *ctx) {
   GQ_TRY(upload(ctx, d.l2l_rt, tb.l2l_rt.data(), tb.l2l_rt.size()));
   GQ_TRY(upload(ctx, d.omega, tb.omega.data(), tb.omega.size() / 2));
   GQ_TRY(upload(ctx, d.m2l_bt, tb.m2l_bt.data(), tb.m2l_bt.size()));
+  if (ctx->params.precision == GQ_MIXED_FP32) {
+    auto f32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
+    const std::vector<float> rm = f32(tb.m2m_rt), rl = f32(tb.l2l_rt), bt = f32(tb.m2l_bt),
+                             om = f32(tb.omega), op = f32(tb.opow);
+    GQ_TRY(upload(ctx, d.m2m_rt_f, rm.data(), rm.size()));
+    GQ_TRY(upload(ctx, d.l2l_rt_f, rl.data(), rl.size()));
+    GQ_TRY(upload(ctx, d.m2l_bt_f, bt.data(), bt.size()));
+    GQ_TRY(upload(ctx, d.omega_f, om.data(), om.size() / 2));
+    GQ_TRY(upload(ctx, d.opow_f, op.data(), op.size() / 2));
+  }
   GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
   GQ_TRY(upload(ctx, d.ologabs, tb.ologabs.data(), tb.ologabs.size()));
   {
@@ -468,7 +478,8 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.p_qbx < 0 || p.p_fmm < 1) return fail(ctx, GQ_EINVAL, "orders must satisfy p_qbx >= 0, p_fmm >= 1");
   if (p.p_fmm > GQ_MAX_P_FMM) return fail(ctx, GQ_EUNSUP, "p_fmm above GQ_MAX_P_FMM");
   if (!gq::pq_supported(p.p_qbx)) return fail(ctx, GQ_EUNSUP, "p_qbx has no compiled kernel in this build");
-  if (p.precision != GQ_FP64) return fail(ctx, GQ_EUNSUP, "only GQ_FP64 is supported in this build");
+  if (p.precision != GQ_FP64 && p.precision != GQ_MIXED_FP32)
+    return fail(ctx, GQ_EINVAL, "precision must be GQ_FP64 or GQ_MIXED_FP32");
   if (p.count_mode != 0 && p.count_mode != 1) return fail(ctx, GQ_EINVAL, "count_mode must be 0 or 1");
   if (p.w3far_min_sources < 0) return fail(ctx, GQ_EINVAL, "w3far_min_sources must be >= 0");
   if (p.overlap != 0 && p.overlap != 1) return fail(ctx, GQ_EINVAL, "overlap must be 0 or 1");

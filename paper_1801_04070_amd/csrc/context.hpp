@@ -53,6 +53,9 @@ struct DevBuffers {
   // tables
   double2 *opow = nullptr, *omega = nullptr;
   double *m2m_rt = nullptr, *l2l_rt = nullptr, *m2l_bt = nullptr, *ologabs = nullptr;
+  // the same tables rounded to FP32 for the mixed-precision box expansions
+  float *m2m_rt_f = nullptr, *l2l_rt_f = nullptr, *m2l_bt_f = nullptr;
+  float2 *omega_f = nullptr, *opow_f = nullptr;
   double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
   double *m2q_binom = nullptr;       // [PQB + 1][P1]  C(m + k - 1, k - 1)
   // workspace

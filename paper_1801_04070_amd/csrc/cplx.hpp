@@ -40,8 +40,37 @@ __host__ __device__ __forceinline__ double2 cpowi(double2 z, int n) {
   return r;
 }
 
-__host__ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+// FP32 overloads, used by the box-expansion kernels of the mixed-precision path.
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__host__ __device__ __forceinline__ float2 caxpy(float s, float2 b, float2 a) {
+  return make_float2(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y));
+}
+__host__ __device__ __forceinline__ float2 cfma(float2 b, float2 c, float2 a) {
+  return make_float2(fmaf(b.x, c.x, fmaf(-b.y, c.y, a.x)), fmaf(b.x, c.y, fmaf(b.y, c.x, a.y)));
+}
+
+// Storage conversions between FP64 arithmetic and the expansion storage type.
+__host__ __device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__host__ __device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+template <typename V> __host__ __device__ __forceinline__ V from_d2(double2 a);
+template <> __host__ __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <> __host__ __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+  return make_float2((float)a.x, (float)a.y);
+}
+template <typename V> struct Scalar;
+template <> struct Scalar<double2> { using T = double; };
+template <> struct Scalar<float2> { using T = float; };
+template <typename V> __host__ __device__ __forceinline__ V mk2(double x, double y);
+template <> __host__ __device__ __forceinline__ double2 mk2<double2>(double x, double y) {
+  return make_double2(x, y);
+}
+template <> __host__ __device__ __forceinline__ float2 mk2<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
 }
 
 }  // namespace gq

@@ -47,7 +47,7 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 // ------------------------------------------------------------------------------------------
 // Stage 2a, P2M for leaf boxes: one work-group per leaf, the leaf's sources staged in LDS, lane k
 // computes coefficient k.
-template <int KIND>
+template <int KIND, typename E>
 __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ bc,
                                             const int32_t *__restrict__ blevel,
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ sxy,
                                             const double *__restrict__ sq,
                                             const double2 *__restrict__ sdip, int P1,
-                                            double2 *__restrict__ M, int64_t src_st,
+                                            E *__restrict__ M, int64_t src_st,
                                             int64_t box_st) {
   __shared__ double2 t_y[64];
   __shared__ double t_q[(KIND & 1) ? 64 : 1];
@@ -95,17 +95,18 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
       }
     }
   }
-  if (k < P1) M[(int64_t)b * P1 + k] = acc;
+  if (k < P1) M[(int64_t)b * P1 + k] = from_d2<E>(acc);
 }
 
 // ------------------------------------------------------------------------------------------
 // Stage 2b, M2M for the non-leaf boxes of one level (eq. (m2m), factored through the real matrix
 // Rm, see tables.hpp): parent_m = sum_q w_q^m sum_k Rm[m][k] (w_q^-k child_q,k).
+template <typename E>
 __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restrict__ bchild,
-                                            const double *__restrict__ Rt,
-                                            const double2 *__restrict__ omega, int P1,
-                                            double2 *__restrict__ M, int64_t box_st) {
-  __shared__ double2 X[4][64];
+                                            const typename Scalar<E>::T *__restrict__ Rt,
+                                            const E *__restrict__ omega, int P1,
+                                            E *__restrict__ M, int64_t box_st) {
+  __shared__ E X[4][64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
   M += (int64_t)blockIdx.y * box_st;
@@ -113,24 +114,24 @@ __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restr
   if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf (uniform per block)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    double2 x = make_double2(0.0, 0.0);
+    E x = mk2<E>(0.0, 0.0);
     if (ch[q] >= 0 && m < P1) {
-      const double2 w = omega[q * 8 + (m & 7)];
-      x = cmul(M[(int64_t)ch[q] * P1 + m], make_double2(w.x, -w.y));
+      const E w = omega[q * 8 + (m & 7)];
+      x = cmul(M[(int64_t)ch[q] * P1 + m], mk2<E>(w.x, -w.y));
     }
     X[q][m] = x;
   }
   __syncthreads();
   if (m >= P1) return;
-  double2 acc[4];
+  E acc[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int q = 0; q < 4; ++q) acc[q] = mk2<E>(0.0, 0.0);
   for (int k = 0; k <= m; ++k) {
-    const double r = Rt[k * P1 + m];
+    const auto r = Rt[k * P1 + m];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q][k], acc[q]);
   }
-  double2 out = make_double2(0.0, 0.0);
+  E out = mk2<E>(0.0, 0.0);
 #pragma unroll
   for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
   M[(int64_t)b * P1 + m] = out;
@@ -148,8 +149,27 @@ __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restr
 // inside each 16-lane group. Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane
 // i + 16 k, B[k][j] in lane j + 16 k, D[g + 4 v][j] in element v of lane j + 16 g.
 typedef double gq_d4 __attribute__((ext_vector_type(4)));
+typedef float gq_f4 __attribute__((ext_vector_type(4)));
 
-template <int KIND, int RT>
+// One 16x16x4 matrix-core step in the expansion precision, and the output row held in element v of
+// a lane of 16-lane group g (FP64: g + 4 v, FP32: 4 g + v).
+__device__ __forceinline__ gq_d4 mfma16(double a, double b, gq_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ gq_f4 mfma16(float a, float b, gq_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename R> struct Mfma16;
+template <> struct Mfma16<double> {
+  using Acc = gq_d4;
+  static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+template <> struct Mfma16<float> {
+  using Acc = gq_f4;
+  static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+
+template <int KIND, int RT, typename E>
 __global__ void __launch_bounds__(64) k_far_local(
     const int32_t *__restrict__ tboxes, const double2 *__restrict__ bc,
     const int32_t *__restrict__ blevel, const double *__restrict__ level_inv_side,
@@ -157,10 +177,13 @@ __global__ void __launch_bounds__(64) k_far_local(
     const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
     const int32_t *__restrict__ xf_start, const int32_t *__restrict__ xf_idx,
     const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
-    const double2 *__restrict__ M, const double *__restrict__ Bt, const double2 *__restrict__ opow,
-    const double *__restrict__ ologabs, const double2 *__restrict__ sxy,
-    const double *__restrict__ sq, const double2 *__restrict__ sdip, int P1,
-    double2 *__restrict__ L, int64_t src_st, int64_t box_st) {
+    const E *__restrict__ M, const typename Scalar<E>::T *__restrict__ Bt,
+    const E *__restrict__ opow, const double *__restrict__ ologabs,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, int P1, E *__restrict__ L, int64_t src_st,
+    int64_t box_st) {
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
   __shared__ double2 Ls[16 * RT];
   const int32_t b = tboxes[blockIdx.x];
@@ -175,13 +198,13 @@ __global__ void __launch_bounds__(64) k_far_local(
   const int g = lane >> 4, c16 = lane & 15;
   const int lev = blevel[b];
   const double logs = level_log_side[lev];
-  double A[RT][KS];
+  R A[RT][KS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int i = 16 * rt + c16, k = 4 * ks + g;
-      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : 0.0;
+      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
     }
   double2 Lacc[RT][4];
 #pragma unroll
@@ -196,36 +219,35 @@ __global__ void __launch_bounds__(64) k_far_local(
     const bool pv = pr < nbat;
     const int32_t d = pv ? v_idx[j0 + pr] : 0;
     const int32_t oi = pv ? v_off[j0 + pr] : 0;
-    const double2 *Md = M + (int64_t)d * P1;
-    const double2 *op = opow + (int64_t)oi * P1;
-    double Bf[KS];
+    const E *Md = M + (int64_t)d * P1;
+    const E *op = opow + (int64_t)oi * P1;
+    R Bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + g;
-      double x = 0.0;
+      R x = R(0);
       if (pv && k < P1) {
-        const double2 mk = Md[k], ok = op[k];
-        x = comp ? fma(mk.x, ok.y, mk.y * ok.x) : fma(mk.x, ok.x, -mk.y * ok.y);
+        const E mk = Md[k], ok = op[k];
+        x = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
       }
       Bf[ks] = x;
     }
-    gq_d4 C[RT];
+    Acc C[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      C[rt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+      C[rt] = Acc{R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        C[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[rt][ks], Bf[ks], C[rt], 0, 0, 0);
+      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = 16 * rt + g + 4 * v;
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
         const double y = C[rt][v];
         const double yo = __shfl_xor(y, 1, 64);
         double2 contrib = make_double2(0.0, 0.0);
-        if (pv && !comp && m < P1) contrib = cmul(make_double2(y, yo), op[m]);
+        if (pv && !comp && m < P1) contrib = cmul(make_double2(y, yo), to_d2(op[m]));
 #pragma unroll
         for (int o = 8; o >= 1; o >>= 1) {
           contrib.x += __shfl_xor(contrib.x, o, 64);
@@ -235,7 +257,7 @@ __global__ void __launch_bounds__(64) k_far_local(
       }
     // a_0 log|s o| of pair `lane` of the batch
     if (lane < nbat)
-      logsum0 += M[(int64_t)v_idx[j0 + lane] * P1].x * (logs + ologabs[v_off[j0 + lane]]);
+      logsum0 += (double)M[(int64_t)v_idx[j0 + lane] * P1].x * (logs + ologabs[v_off[j0 + lane]]);
   }
   // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
 #pragma unroll
@@ -244,7 +266,7 @@ __global__ void __launch_bounds__(64) k_far_local(
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Ls[16 * rt + g + 4 * v] = Lacc[rt][v];
+      for (int v = 0; v < 4; ++v) Ls[16 * rt + Mfma16<R>::row(g, v)] = Lacc[rt][v];
   }
   __syncthreads();
   // P2L (eq. (local) about c_b) for the sources of List 4 far boxes, 16 sources at a time: lane
@@ -285,19 +307,20 @@ __global__ void __launch_bounds__(64) k_far_local(
     }
   }
   if (m >= P1) return;
-  L[(int64_t)b * P1 + m] = acc;
+  L[(int64_t)b * P1 + m] = from_d2<E>(acc);
 }
 
 // ------------------------------------------------------------------------------------------
 // Stage 7, L2L for the target-or-ancestor boxes of one level (eq. (l2l), factored through the
 // real matrix Rl): child_m += w_q^-m sum_{k>=m} Rl[m][k] (w_q^k parent_k).
+template <typename E>
 __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restrict__ bparent,
                                             const int8_t *__restrict__ bquad,
                                             const int32_t *__restrict__ is_tbox,
-                                            const double *__restrict__ Rt,
-                                            const double2 *__restrict__ omega, int P1,
-                                            double2 *__restrict__ L, int64_t box_st) {
-  __shared__ double2 X[64];
+                                            const typename Scalar<E>::T *__restrict__ Rt,
+                                            const E *__restrict__ omega, int P1,
+                                            E *__restrict__ L, int64_t box_st) {
+  __shared__ E X[64];
   const int32_t b = box0 + blockIdx.x;
   const int m = threadIdx.x;
   if (!is_tbox[b]) return;  // uniform per block
@@ -307,10 +330,10 @@ __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restr
   if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
   __syncthreads();
   if (m >= P1) return;
-  double2 acc = make_double2(0.0, 0.0);
+  E acc = mk2<E>(0.0, 0.0);
   for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
-  const double2 w = omega[q * 8 + (m & 7)];
-  L[(int64_t)b * P1 + m] = cfma(make_double2(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
+  const E w = omega[q * 8 + (m & 7)];
+  L[(int64_t)b * P1 + m] = cfma(mk2<E>(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -483,26 +506,26 @@ __global__ void __launch_bounds__(64) k_near(
 // binomials: since C(m+k-1, m) = sum_{j<=k} C(m+j-2, m-1), V_m is the (m+1)-fold suffix sum of T.
 // Walking k downwards with running sums S_0 += T_k, S_1 += S_0, ..., S_PQ += S_{PQ-1} leaves
 // V_m = S_m. The powers w^k are produced downwards from w^p by multiplications with 1/w.
-template <int PQ>
+template <int PQ, typename E>
 __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r, int32_t d,
                                            const double2 *__restrict__ bc,
                                            const int32_t *__restrict__ blevel,
                                            const double *__restrict__ level_side,
-                                           const double2 *__restrict__ M, int P1) {
+                                           const E *__restrict__ M, int P1) {
   const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
   const double2 iy = cinv(y);
   const double sd = level_side[blevel[d]];
   const double2 w = cscale(iy, sd);
   const double2 iw = make_double2(y.x / sd, y.y / sd);
   const double2 u = cscale(iy, -r);
-  const double2 *Md = M + (int64_t)d * P1;
+  const E *Md = M + (int64_t)d * P1;
   const double a0 = Md[0].x;
   double2 S[PQ + 1];
 #pragma unroll
   for (int m = 0; m <= PQ; ++m) S[m] = make_double2(0.0, 0.0);
   double2 wk = cpowi(w, P1 - 1);
   for (int k = P1 - 1; k >= 1; --k) {
-    S[0] = cfma(Md[k], wk, S[0]);
+    S[0] = cfma(to_d2(Md[k]), wk, S[0]);
 #pragma unroll
     for (int m = 1; m <= PQ; ++m) S[m] = cadd(S[m], S[m - 1]);
     wk = cmul(wk, iw);
@@ -520,13 +543,13 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
 
 // Work items for Stage 5b, same item layout and lane mapping as k_near, the slices striding over
 // the chunk's List 3 far boxes.
-template <int PQ>
+template <int PQ, typename E>
 __global__ void __launch_bounds__(256) k_m2qbxl(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
-    const double *__restrict__ level_side, const double2 *__restrict__ M, int P1,
-    const double *__restrict__ m2q_binom, double2 *__restrict__ anear, int64_t box_st,
+    const double *__restrict__ level_side, const E *__restrict__ M, int P1,
+    double2 *__restrict__ anear, int64_t box_st,
     int64_t row_st) {
   const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
@@ -548,7 +571,7 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   if (active)
     for (int32_t e = sl; e < len; e += nsl)
-      m2qbxl_add<PQ>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1);
+      m2qbxl_add<PQ, E>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1);
   for (int o = nsl >> 1; o >= 1; o >>= 1) {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -567,13 +590,12 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
 // Stage 8 per center: L2QBXL (box local -> center), plus the direct and List 3 far rows from
 // k_near and k_m2qbxl, then QBXL2P at its targets.
 // One thread per center (tree order, so a wave covers centers of a few neighbouring boxes).
-template <int KIND, int PQ>
+template <int KIND, int PQ, typename E>
 __global__ void __launch_bounds__(256) k_qbx_center(
     int32_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const int32_t *__restrict__ cbox, const double2 *__restrict__ bc,
     const int32_t *__restrict__ blevel, const double *__restrict__ level_side,
-    const double2 *__restrict__ L, const double2 *__restrict__ M, int P1,
-    const double *__restrict__ l2q_binom, const double *__restrict__ m2q_binom,
+    const E *__restrict__ L, int P1, const double *__restrict__ l2q_binom,
     const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
     const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_chunks,
     const double2 *__restrict__ anear,
@@ -585,7 +607,6 @@ __global__ void __launch_bounds__(256) k_qbx_center(
   {
     const int64_t jd = blockIdx.y;
     L += jd * box_st;
-    M += jd * box_st;
     anear += jd * row_st;
     tv += jd * tv_st;
   }
@@ -601,9 +622,9 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const double2 t = make_double2((cc.x - bc[b].x) * is, (cc.y - bc[b].y) * is);
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
-    const double2 *Lb = L + (int64_t)b * P1;
+    const E *Lb = L + (int64_t)b * P1;
     for (int k = P1 - 1; k >= 0; --k) {
-      const double2 bk = Lb[k];
+      const double2 bk = to_d2(Lb[k]);
       const double *Ck = l2q_binom + (int64_t)k * (PQ + 1);
 #pragma unroll
       for (int m = 0; m <= PQ; ++m)
@@ -750,10 +771,29 @@ hipError_t launch_gather(gq_ctx *ctx, const double *d1, int64_t ld1, const doubl
   return hipGetLastError();
 }
 
-template <int KIND, int PQ>
-hipError_t launch_fmm(gq_ctx *ctx, int nd) {
+// Translation tables in the expansion precision.
+template <typename E> struct ExpTables;
+template <> struct ExpTables<double2> {
+  const double *m2m_rt, *l2l_rt, *m2l_bt;
+  const double2 *omega, *opow;
+  explicit ExpTables(const DevBuffers &d)
+      : m2m_rt(d.m2m_rt), l2l_rt(d.l2l_rt), m2l_bt(d.m2l_bt), omega(d.omega), opow(d.opow) {}
+};
+template <> struct ExpTables<float2> {
+  const float *m2m_rt, *l2l_rt, *m2l_bt;
+  const float2 *omega, *opow;
+  explicit ExpTables(const DevBuffers &d)
+      : m2m_rt(d.m2m_rt_f), l2l_rt(d.l2l_rt_f), m2l_bt(d.m2l_bt_f), omega(d.omega_f),
+        opow(d.opow_f) {}
+};
+
+template <int KIND, int PQ, typename E>
+hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   auto &d = ctx->d;
   auto &t = ctx->tree;
+  const ExpTables<E> X(d);
+  E *M = reinterpret_cast<E *>(d.M);
+  E *L = reinterpret_cast<E *>(d.L);
   const int P1 = ctx->params.p_fmm + 1;
   const hipStream_t st = ctx->stream;
   const Strides S = strides(ctx);
@@ -775,17 +815,17 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    hipLaunchKernelGGL(k_p2m<KIND>, dim3(nleaf, nd), dim3(64), 0, st, d.leaves, d.bc, d.blevel,
-                       d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, d.M, S.src,
-                       S.box);
+    hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64), 0, st, d.leaves, d.bc,
+                       d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
+                       S.src, S.box);
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
     for (int l = t.n_levels - 2; l >= 0; --l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
-        hipLaunchKernelGGL(k_m2m, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, d.m2m_rt, d.omega,
-                           P1, d.M, S.box);
+        hipLaunchKernelGGL(k_m2m<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, X.m2m_rt, X.omega,
+                           P1, M, S.box);
     }
   }
   e = hipEventRecord(ctx->ev_up, st);
@@ -796,29 +836,29 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   const int32_t nfi = (int32_t)ctx->n_far_items;
   if (nfi > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
-    hipLaunchKernelGGL((k_m2qbxl<PQ>), dim3((nfi + 3) / 4, nd), dim3(256), 0, side, nfi,
-                       d.far_items, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, d.M, P1,
-                       d.m2q_binom, d.anear, S.box, S.row);
+    hipLaunchKernelGGL((k_m2qbxl<PQ, E>), dim3((nfi + 3) / 4, nd), dim3(256), 0, side, nfi,
+                       d.far_items, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, M, P1,
+                       d.anear, S.box, S.row);
   }
   e = hipEventRecord(ctx->ev_join, side);
   if (e != hipSuccess) return e;
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    auto kern = P1 <= 16 ? k_far_local<KIND, 1> : P1 <= 32 ? k_far_local<KIND, 2>
-              : P1 <= 48 ? k_far_local<KIND, 3> : k_far_local<KIND, 4>;
+    auto kern = P1 <= 16 ? k_far_local<KIND, 1, E> : P1 <= 32 ? k_far_local<KIND, 2, E>
+              : P1 <= 48 ? k_far_local<KIND, 3, E> : k_far_local<KIND, 4, E>;
     hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
-                       d.xf_idx, d.bsrc0, d.bsrc1, d.M, d.m2l_bt, d.opow, d.ologabs, d.sxy, d.sq,
-                       d.sdip, P1, d.L, S.src, S.box);
+                       d.xf_idx, d.bsrc0, d.bsrc1, M, X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq,
+                       d.sdip, P1, L, S.src, S.box);
   }
   {
     StageTimer st_(ctx, GQ_STAGE_L2L);
     for (int l = 1; l < t.n_levels; ++l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
-        hipLaunchKernelGGL(k_l2l, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad, d.is_tbox,
-                           d.l2l_rt, d.omega, P1, d.L, S.box);
+        hipLaunchKernelGGL(k_l2l<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad,
+                           d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
     }
   }
   const int32_t nc = (int32_t)ctx->nc;
@@ -826,12 +866,18 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
   if (e != hipSuccess) return e;
   {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
-    hipLaunchKernelGGL((k_qbx_center<KIND, PQ>), dim3((nc + 255) / 256, nd), dim3(256), 0, st, nc,
-                       d.cxy, d.cr, d.cbox, d.bc, d.blevel, d.level_side, d.L, d.M, P1,
-                       d.l2q_binom, d.m2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
-                       d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
+    hipLaunchKernelGGL((k_qbx_center<KIND, PQ, E>), dim3((nc + 255) / 256, nd), dim3(256), 0, st,
+                       nc, d.cxy, d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, P1, d.l2q_binom,
+                       d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear, d.c2t_start,
+                       d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
   }
   return hipGetLastError();
+}
+
+template <int KIND, int PQ>
+hipError_t launch_fmm(gq_ctx *ctx, int nd) {
+  return ctx->params.precision == GQ_MIXED_FP32 ? launch_fmm_t<KIND, PQ, float2>(ctx, nd)
+                                                : launch_fmm_t<KIND, PQ, double2>(ctx, nd);
 }
 
 template <int KIND, int PQ>

@@ -190,3 +190,35 @@ def test_density_batches_match_single_evaluations(c1):
         assert np.array_equal(single, res[j, :c1.n_tgt])
     ref = oracle.qbx_eval(c1, 3, h1[69], h2[69], p_qbx=8)
     assert _rel(res[69, :c1.n_tgt], ref) < 1e-10
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_mixed_precision_c1(c1, kind):
+    """FP32 box expansions (P2M, M2M, M2L on FP32 matrix cores, L2L) with power-of-two level
+    scaling at p_fmm = 16 against the FP64 oracle: gate 1e-6."""
+    from paper_1801_04070_amd import GQ_MIXED_FP32
+    mu, mu2 = _densities(c1, 0)
+    q, _ = _ctx(c1, p_qbx=8, p_fmm=16, precision=GQ_MIXED_FP32)
+    gpu = _run(q, kind, mu, mu2)
+    ref = oracle.qbx_eval(c1, kind, mu, mu2 if kind == 3 else None, p_qbx=8)
+    err = _rel(gpu, ref)
+    print(f"C1 mixed kind={kind} rel_err={err:.3e}")
+    assert err < 1e-6
+
+
+def test_mixed_and_high_order_c2_sampled():
+    """Full-size workload: FP32 expansions at p_fmm = 16 (gate 1e-6) and all-FP64 at p_fmm = 40
+    (gate 1e-12) against the oracle at sampled targets."""
+    from paper_1801_04070_amd import GQ_MIXED_FP32
+    g = gi.config_geometry("c2")
+    mu, _ = _densities(g, 4)
+    rng = np.random.default_rng(9)
+    idx = np.sort(rng.choice(g.n_tgt, 128, replace=False))
+    ref = oracle.qbx_eval(g, 1, mu, None, p_qbx=12, tgt_xy=g.tgt_xy[idx], tgt_ctr=g.tgt_ctr[idx])
+    q, _ = _ctx(g, p_qbx=12, p_fmm=16, precision=GQ_MIXED_FP32)
+    err32 = _rel(_run(q, 1, mu, None)[idx], ref)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=40)
+    err64 = _rel(_run(q, 1, mu, None)[idx], ref)
+    print(f"C2 mixed p16 rel_err={err32:.3e}  fp64 p40 rel_err={err64:.3e}")
+    assert err32 < 1e-6
+    assert err64 < 1e-12
