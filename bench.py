@@ -1,19 +1,26 @@
 """Throughput of the GIGAQBX FMM hot path on one MI355X.
 
-Workload (default): 16 random star curves, 8192 panels x 16 Gauss-Legendre nodes = 131072
-sources, two QBX centers per node (radius = half the panel arclength), 131072 on-surface targets,
+Headline workload: 16 random star curves, 8192 panels x 16 Gauss-Legendre nodes = 131072 sources,
+two QBX centers per node (radius = half the panel arclength), 131072 on-surface targets,
 p_qbx = 12, p_fmm = 30, n_max = 64, t_f = 0.9, FP64. One step evaluates the single-layer and the
 double-layer potential of a Fourier-mode density (all FMM stages, densities resident in HBM);
 targets/s = 2 x 131072 / step time. Tree and list build is excluded and reported as build_ms.
 
+Variants on the same geometry (reported under "variants", each with its own error against the
+FP64 oracle at sampled targets):
+  batched_64      64 densities per call (a block of right-hand sides), FP64, p_fmm 30
+  mixed_fp32_p16  FP32 box expansions at p_fmm 16 (tolerance 1e-6)
+  fp64_p16        all-FP64 at p_fmm 16, the equal-accuracy reference for mixed_fp32_p16
+  fp64_p40        all-FP64 at p_fmm 40 (tolerance 1e-12)
+
 The JSON line also carries:
   roofline      the dominant kernel's achieved rate (algorithmic flops per launch / average launch
-                time from HIP events recorded on the library's stream during the timed steps)
+                time from HIP events recorded on the library's streams during the timed steps)
                 against the FP64 vector peak;
   cpu_baseline  the CPU oracle (direct QBX, FP64) timed on a bounded sample of the same targets
-                on this host, whose values also give the GPU-vs-oracle error of this run.
+                on this host; the same oracle values give the GPU-vs-oracle error of this run.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-variants]
        python bench.py --copy-mib 256      (plain copy kernel, for HBM counter calibration)
 """
 from __future__ import annotations
@@ -49,14 +56,50 @@ def copy_calibration(mib: int, reps: int = 5):
     log(f"copy calibration: {reps} copies of {mib} MiB")
 
 
-def cpu_baseline(geom, dens, gpu_out, budget_s: float):
-    """Oracle on a bounded sample of targets: throughput on this host and GPU parity there."""
+class Timer:
+    """Times K steps with events on torch's current stream (the library's stream)."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def run(self, q, step, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        q.stage_times()
+        q.set_profiling(True)
+        torch.cuda.synchronize()
+        self.a.record()
+        for _ in range(steps):
+            step()
+        self.b.record()
+        torch.cuda.synchronize()
+        ms = self.a.elapsed_time(self.b) / steps
+        stages = q.stage_times()
+        q.set_profiling(False)
+        return ms, stages
+
+
+def per_stage(stages, steps):
+    agg = {}
+    for (kind, name), (ms, cnt) in stages.items():
+        agg.setdefault(name, [0.0, 0])
+        agg[name][0] += ms
+        agg[name][1] += cnt
+    return agg, {k: round(v[0] / steps, 4) for k, v in agg.items()}
+
+
+def oracle_sample(geom, dens, budget_s: float, seed=123):
+    """Oracle values (S and D) at a bounded random sample of targets, and the time it took."""
     import numpy as np
     import oracle
     from paper_1801_04070_amd import GQ_D, GQ_S
 
-    rng = np.random.default_rng(123)
-    order = rng.permutation(geom.n_tgt)
+    order = np.random.default_rng(seed).permutation(geom.n_tgt)
     probe = order[:16]
     t0 = time.perf_counter()
     oracle.qbx_eval(geom, GQ_S, dens, p_qbx=12, tgt_xy=geom.tgt_xy[probe], tgt_ctr=geom.tgt_ctr[probe])
@@ -69,12 +112,15 @@ def cpu_baseline(geom, dens, gpu_out, budget_s: float):
     ref_d = oracle.qbx_eval(geom, GQ_D, dens, p_qbx=12, tgt_xy=geom.tgt_xy[idx],
                             tgt_ctr=geom.tgt_ctr[idx])
     dt = time.perf_counter() - t0
-    err_s = float(np.abs(gpu_out[0][idx] - ref_s).max() / np.abs(ref_s).max())
-    err_d = float(np.abs(gpu_out[1][idx] - ref_d).max() / np.abs(ref_d).max())
-    cpu = {"value": 2 * n / dt, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
-           "sample": f"{n} random on-surface targets of the same workload, S and D, direct QBX "
-                     f"(FP64, compensated sums, OpenMP over targets); {dt:.1f} s"}
-    return cpu, {"S": err_s, "D": err_d, "n_sampled_targets": n, "gate": GATE}
+    return {"idx": idx, "S": ref_s, "D": ref_d, "seconds": dt, "threads": oracle.num_threads()}
+
+
+def rel_errors(sample, out_s, out_d):
+    import numpy as np
+    i = sample["idx"]
+    es = float(np.abs(out_s[i] - sample["S"]).max() / np.abs(sample["S"]).max())
+    ed = float(np.abs(out_d[i] - sample["D"]).max() / np.abs(sample["D"]).max())
+    return {"S": es, "D": ed, "n_sampled_targets": int(len(i))}
 
 
 def main():
@@ -83,6 +129,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--batch", type=int, default=64, help="densities of the batched variant")
@@ -103,51 +150,39 @@ def main():
         return
 
     import gq_inputs as gi
-    from paper_1801_04070_amd import GQ_D, GQ_S, QBXFMM, perfmodel
+    from paper_1801_04070_amd import GQ_D, GQ_MIXED_FP32, GQ_S, QBXFMM, perfmodel
 
     p_qbx, p_fmm = 12, 30
-    log("bench: building C2 workload (16 stars, 131072 sources)")
+    log("bench: building the 16-star workload (131072 sources)")
     geom = gi.config_geometry("c2")
     dens_h = gi.fourier_density(geom, seed=2)
-    q = QBXFMM(device=0)
-    q.set_geometry_from(geom)
-    stats = q.build(p_qbx=p_qbx, p_fmm=p_fmm, n_max=64, count_mode=0, t_f=0.9,
-                    w3far_min_sources=15, overlap=args.overlap)
     dens = torch.as_tensor(dens_h, dtype=torch.float64, device="cuda:0")
-    out = torch.empty((2, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+    timer = Timer()
 
-    def step():
-        q.eval(GQ_S, dens, out=out[0:1])
-        q.eval(GQ_D, dens, out=out[1:2])
+    def context(**kw):
+        q = QBXFMM(device=0)
+        q.set_geometry_from(geom)
+        params = dict(p_qbx=p_qbx, p_fmm=p_fmm, n_max=64, count_mode=0, t_f=0.9,
+                      w3far_min_sources=15, overlap=args.overlap)
+        params.update(kw)
+        return q, q.build(**params)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    q.stage_times()
-    q.set_profiling(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        step()
-    stop.record()
-    torch.cuda.synchronize()
-    ms_per_step = start.elapsed_time(stop) / args.steps
-    stages = q.stage_times()
-    q.set_profiling(False)
-    log(f"bench: {args.steps} steps, {ms_per_step:.3f} ms/step")
+    def sd_step(q, d, out):
+        def step():
+            q.eval(GQ_S, d, out=out[0])
+            q.eval(GQ_D, d, out=out[1])
+        return step
 
-    # dominant kernel and its roofline: algorithmic work per launch / average launch time
-    per_stage = {}
-    for (kind, name), (ms, cnt) in stages.items():
-        per_stage.setdefault(name, [0.0, 0])
-        per_stage[name][0] += ms
-        per_stage[name][1] += cnt
-    breakdown = {k: round(v[0] / args.steps, 4) for k, v in per_stage.items()}
+    # ---- headline: plain FP64 ----
+    q, stats = context()
+    out = torch.empty((2, 1, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+    ms_per_step, stages = timer.run(q, sd_step(q, dens, out), args.steps, args.warmup)
+    log(f"bench: plain {args.steps} steps, {ms_per_step:.3f} ms/step")
+    agg, breakdown = per_stage(stages, args.steps)
     n_slots = int((geom.tgt_ctr >= 0).sum())
     work = {k: perfmodel.stage_work(stats, k, p_qbx, p_fmm, n_slots) for k in (GQ_S, GQ_D)}
-    dom = max(per_stage, key=lambda n: per_stage[n][0])
-    ms_dom, n_dom = per_stage[dom]
+    dom = max(agg, key=lambda n: agg[n][0])
+    ms_dom, n_dom = agg[dom]
     avg_ms = ms_dom / n_dom
     flops = (work[GQ_S][dom]["flops"] + work[GQ_D][dom]["flops"]) / 2
     nbytes = (work[GQ_S][dom]["bytes"] + work[GQ_D][dom]["bytes"]) / 2
@@ -160,50 +195,46 @@ def main():
                 "algorithmic_bytes_per_launch": int(nbytes),
                 "achieved_hbm_gbs": round(nbytes / (avg_ms * 1e-3) / 1e9, 1)}
     stage_rates = {}
-    for name, (ms, cnt) in per_stage.items():
+    for name, (ms, cnt) in agg.items():
         if name in work[GQ_S] and cnt:
             f = (work[GQ_S][name]["flops"] + work[GQ_D][name]["flops"]) / 2
             stage_rates[name] = round(f / (ms / cnt * 1e-3) / 1e12, 3)
-
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
-    gpu_out = out.cpu().numpy()
+    plain_out = out[:, 0].cpu().numpy()
+    q.close()
 
-    # batched variant: 64 seeded densities in one call per kind (a block right-hand-side batch)
+    # ---- variants ----
     variants = {}
-    if args.batch > 1:
-        nb = args.batch
-        hb = np.stack([gi.fourier_density(geom, seed=100 + j) for j in range(nb)])
-        db = torch.as_tensor(hb, dtype=torch.float64, device="cuda:0")
-        ob = torch.empty((2, nb, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+    outputs = {}
+    if not args.no_variants:
+        def variant(name, workload, nd=1, **kw):
+            qv, _ = context(**kw)
+            if nd == 1:
+                dv = dens
+            else:
+                hb = np.stack([gi.fourier_density(geom, seed=100 + j) for j in range(nd)])
+                dv = torch.as_tensor(hb, dtype=torch.float64, device="cuda:0")
+                outputs[name + "_density"] = hb[nd - 1]
+            ov = torch.empty((2, nd, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+            steps = max(2, args.steps // 4) if nd > 1 else args.steps
+            ms, st = timer.run(qv, sd_step(qv, dv, ov), steps, max(1, args.warmup))
+            _, bd = per_stage(st, steps)
+            v = 2 * nd * geom.n_tgt / (ms * 1e-3)
+            variants[name] = {"value": round(v, 1), "unit": "targets/s", "ms_per_step": round(ms, 4),
+                              "steps": steps, "workload": workload,
+                              "vs_plain": round(v / value, 3), "stage_ms_per_step": bd}
+            outputs[name] = ov[:, nd - 1].cpu().numpy()
+            qv.close()
+            log(f"bench: {name}: {ms:.3f} ms/step")
 
-        def bstep():
-            q.eval(GQ_S, db, out=ob[0])
-            q.eval(GQ_D, db, out=ob[1])
+        variant(f"batched_{args.batch}", f"{args.batch} seeded densities per call, S and D, FP64, "
+                "p_fmm 30", nd=args.batch)
+        variant("mixed_fp32_p16", "FP32 box expansions (FP32 matrix-core M2L), p_fmm 16, "
+                "tolerance 1e-6", p_fmm=16, precision=GQ_MIXED_FP32)
+        variant("fp64_p16", "all FP64, p_fmm 16 (equal-accuracy reference for mixed_fp32_p16)",
+                p_fmm=16)
+        variant("fp64_p40", "all FP64, p_fmm 40, tolerance 1e-12", p_fmm=40)
 
-        bsteps = max(2, args.steps // 4)
-        for _ in range(max(1, args.warmup)):
-            bstep()
-        torch.cuda.synchronize()
-        q.stage_times()
-        q.set_profiling(True)
-        start.record()
-        for _ in range(bsteps):
-            bstep()
-        stop.record()
-        torch.cuda.synchronize()
-        bms = start.elapsed_time(stop) / bsteps
-        bstages = {}
-        for (kind, name), (ms, cnt) in q.stage_times().items():
-            bstages[name] = round(bstages.get(name, 0.0) + ms / bsteps, 3)
-        q.set_profiling(False)
-        variants[f"batched_{nb}"] = {
-            "value": round(2 * nb * geom.n_tgt / (bms * 1e-3), 1), "unit": "targets/s",
-            "ms_per_step": round(bms, 4), "steps": bsteps,
-            "workload": f"same geometry, {nb} seeded densities per call, S and D",
-            "vs_plain": round(2 * nb * geom.n_tgt / (bms * 1e-3) / value, 3),
-            "stage_ms_per_step": bstages}
-        log(f"bench: batched {nb}: {bms:.3f} ms/step")
-        batched_out = (ob[0, nb - 1].cpu().numpy(), ob[1, nb - 1].cpu().numpy(), hb[nb - 1])
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -224,17 +255,34 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
-        cpu, parity = cpu_baseline(geom, dens_h, gpu_out, args.cpu_budget)
-        result["cpu_baseline"] = cpu
-        result["parity"] = parity
-        if max(parity["S"], parity["D"]) > GATE:
-            result["parity"]["status"] = "FAILED"
-        if variants:
-            _, bpar = cpu_baseline(geom, batched_out[2], batched_out[:2], args.cpu_budget / 4)
-            key = next(iter(variants))
-            variants[key]["parity"] = bpar
-            if max(bpar["S"], bpar["D"]) > GATE:
-                variants[key]["parity"]["status"] = "FAILED"
+        smp = oracle_sample(geom, dens_h, args.cpu_budget)
+        n = len(smp["idx"])
+        result["cpu_baseline"] = {
+            "value": round(2 * n / smp["seconds"], 2), "unit": "targets/s",
+            "cores": smp["threads"], "kind": "oracle",
+            "sample": f"{n} random on-surface targets of the same workload, S and D, direct QBX "
+                      f"(FP64, compensated sums, OpenMP over targets); {smp['seconds']:.1f} s"}
+        par = rel_errors(smp, plain_out[0], plain_out[1])
+        par["gate"] = GATE
+        if max(par["S"], par["D"]) > GATE:
+            par["status"] = "FAILED"
+        result["parity"] = par
+        gates = {"mixed_fp32_p16": 1e-6, "fp64_p16": 1e-6, "fp64_p40": 1e-12}
+        for name, gate in gates.items():
+            if name in outputs:
+                e = rel_errors(smp, outputs[name][0], outputs[name][1])
+                e["gate"] = gate
+                if max(e["S"], e["D"]) > gate:
+                    e["status"] = "FAILED"
+                variants[name]["parity"] = e
+        bname = f"batched_{args.batch}"
+        if bname in outputs:
+            smp_b = oracle_sample(geom, outputs[bname + "_density"], args.cpu_budget / 4, seed=7)
+            e = rel_errors(smp_b, outputs[bname][0], outputs[bname][1])
+            e["gate"] = GATE
+            if max(e["S"], e["D"]) > GATE:
+                e["status"] = "FAILED"
+            variants[bname]["parity"] = e
     print(json.dumps(result), flush=True)
 
 
