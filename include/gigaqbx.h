@@ -139,6 +139,20 @@ gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
                          int64_t ld1, const double *dens2, int64_t ld2, double *out,
                          int64_t ld_out);
 
+/*
+ * Per-center QBX orders (the truncation order p of eq. (qbx) may differ between centers; Sec. 4.1
+ * chooses it from the truncation error, which depends on the local geometry). orders[c] (n_ctr
+ * int32, caller order, host or device memory per mem; NULL restores the uniform p_qbx) must lie in
+ * 0..p_qbx of the last gq_build. Every box then runs at the smallest compiled order that is at
+ * least the largest order of its centers, and the direct, List 3 far and center work is regrouped
+ * by order. Synchronous. Call after gq_build; a new gq_build resets to the uniform order.
+ */
+gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders);
+
+/* Copy the QBX order used by each box (n_boxes int32, breadth-first box order) to host memory
+ * `dst` (NULL to query the count, always written to *count). */
+gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
+
 /* Sizes of the tree and lists after gq_build (Sec. 4.3, and the stage costs of Table 2). */
 typedef struct {
   int64_t n_src, n_ctr, n_tgt;

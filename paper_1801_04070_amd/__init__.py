@@ -160,6 +160,26 @@ class QBXFMM:
                  "list4c": _lib.GQ_LIST4C_START, "list4f": _lib.GQ_LIST4F_START}
         return {k: (self.tree_array(v), self.tree_array(v + 1)) for k, v in names.items()}
 
+    def set_qbx_orders(self, orders):
+        """Per-center QBX orders (caller order), or None for the uniform build order."""
+        if orders is None:
+            self._check(self._L.gq_set_qbx_orders(self._h, GQ_MEM_HOST, None))
+            return
+        if isinstance(orders, np.ndarray):
+            o = np.ascontiguousarray(orders, dtype=np.int32)
+            self._check(self._L.gq_set_qbx_orders(self._h, GQ_MEM_HOST, o.ctypes.data))
+        else:
+            import torch
+            o = orders.to(torch.int32).contiguous()
+            self._check(self._L.gq_set_qbx_orders(self._h, GQ_MEM_DEVICE, o.data_ptr()))
+
+    def box_orders(self) -> np.ndarray:
+        n = C.c_int64()
+        self._check(self._L.gq_get_box_orders(self._h, None, C.byref(n)))
+        out = np.empty(n.value, dtype=np.int32)
+        self._check(self._L.gq_get_box_orders(self._h, out.ctypes.data, C.byref(n)))
+        return out
+
     def set_profiling(self, enable: bool = True):
         self._check(self._L.gq_set_profiling(self._h, int(enable)))
 

@@ -44,7 +44,8 @@ GQ_N_STAGES = len(GQ_STAGE_NAMES)
 
 EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
-            "gq_set_profiling", "gq_get_stage_times", "gq_last_error"]
+            "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
+            "gq_last_error"]
 
 
 def load(path: str = LIB_PATH):
@@ -64,6 +65,8 @@ def load(path: str = LIB_PATH):
     L.gq_eval_direct.argtypes = L.gq_eval.argtypes
     L.gq_get_stats.argtypes = [vp, C.POINTER(gq_stats)]
     L.gq_get_tree_array.argtypes = [vp, i32, vp, C.POINTER(C.c_int64)]
+    L.gq_set_qbx_orders.argtypes = [vp, i32, vp]
+    L.gq_get_box_orders.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.gq_set_profiling.argtypes = [vp, i32]
     L.gq_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.gq_last_error.argtypes = [vp]

@@ -46,8 +46,10 @@ void free_device(gq_ctx *ctx) {
   if (ctx->device >= 0) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (void *p : ctx->allocations) (void)hipFree(p);
+    for (void *p : ctx->nw_allocations) (void)hipFree(p);
   }
   ctx->allocations.clear();
+  ctx->nw_allocations.clear();
   ctx->d = gq::DevBuffers();
   ctx->built = false;
 }
@@ -113,11 +115,17 @@ int pick_lg(int64_t nc, int64_t len, double elem_cost) {
   return best_lg;
 }
 
+// Work of the per-center stages grouped by QBX order: every box runs at its own order (the
+// largest order among its centers, default the build's p_qbx), and the items, rows and centers of
+// each compiled order form one contiguous range so that each order is one kernel launch.
 gq_status upload_near_work(gq_ctx *ctx) {
   const gq::Tree &t = ctx->tree;
   auto &d = ctx->d;
   const int64_t nb = t.n_boxes();
-  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems;
+  for (void *p : ctx->nw_allocations) (void)hipFree(p);
+  ctx->nw_allocations.clear();
+  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
+  std::vector<int64_t> box_src_off(nb, 0), box_src_len(nb, 0);
   int64_t rows = 0;
   auto emit = [](std::vector<int32_t> &out, int64_t off, int64_t clen, int64_t ctr0, int64_t row0,
                  int64_t nc, int lg) {
@@ -128,42 +136,72 @@ gq_status upload_near_work(gq_ctx *ctx) {
       out.insert(out.end(), item, item + 8);
     }
   };
+  // direct source lists and row layout (independent of the orders)
   for (int64_t b = 0; b < nb; ++b) {
     bctr0[b] = (int32_t)t.ctr_begin[b];
     bctr1[b] = (int32_t)t.ctr_end[b];
     const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
     if (nc == 0) continue;
-    const int64_t off = (int64_t)src.size();
+    box_src_off[b] = (int64_t)src.size();
     for (int64_t g = t.near_row[b]; g < t.near_row[b + 1]; ++g)
       for (int64_t s = t.near_lo[g]; s < t.near_hi[g]; ++s) src.push_back((int32_t)s);
-    const int64_t len = (int64_t)src.size() - off;
-    const int64_t nchunks = (len + kNearChunk - 1) / kNearChunk;
-    const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
+    box_src_len[b] = (int64_t)src.size() - box_src_off[b];
+    const int64_t nchunks = (box_src_len[b] + kNearChunk - 1) / kNearChunk;
+    const int64_t wlen = t.list3f.start[b + 1] - t.list3f.start[b];
     const int64_t fchunks = (wlen + kFarChunk - 1) / kFarChunk;
     base[b] = (int32_t)rows;
     nch[b] = (int32_t)(nchunks + fchunks);
-    for (int64_t j = 0; j < nchunks; ++j) {
-      const int64_t c0 = j * kNearChunk, clen = std::min<int64_t>(kNearChunk, len - c0);
-      emit(items, off + c0, clen, t.ctr_begin[b], rows + j * nc, nc, pick_lg(nc, clen, 120.0));
-    }
-    for (int64_t j = 0; j < fchunks; ++j) {
-      const int64_t c0 = j * kFarChunk, clen = std::min<int64_t>(kFarChunk, wlen - c0);
-      emit(fitems, woff + c0, clen, t.ctr_begin[b], rows + (nchunks + j) * nc, nc,
-           pick_lg(nc, clen, 2400.0));
-    }
     rows += (nchunks + fchunks) * nc;
+  }
+  // items and centers, grouped by order
+  ctx->buckets.clear();
+  for (int pq : ctx->pq_values) {
+    gq::OrderBucket bk;
+    bk.pq = pq;
+    bk.near0 = (int64_t)items.size() / 8;
+    bk.far0 = (int64_t)fitems.size() / 8;
+    bk.ctr0 = (int64_t)clist.size();
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
+      if (nc == 0 || ctx->box_pq[b] != pq) continue;
+      const int64_t len = box_src_len[b];
+      const int64_t nchunks = (len + kNearChunk - 1) / kNearChunk;
+      for (int64_t j = 0; j < nchunks; ++j) {
+        const int64_t c0 = j * kNearChunk, clen = std::min<int64_t>(kNearChunk, len - c0);
+        emit(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
+             pick_lg(nc, clen, 10.0 * pq));
+      }
+      const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
+      for (int64_t j = 0; j * kFarChunk < wlen; ++j) {
+        const int64_t c0 = j * kFarChunk, clen = std::min<int64_t>(kFarChunk, wlen - c0);
+        emit(fitems, woff + c0, clen, t.ctr_begin[b], base[b] + (nchunks + j) * nc, nc,
+             pick_lg(nc, clen, 200.0 * pq));
+      }
+      for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) clist.push_back((int32_t)c);
+    }
+    bk.near1 = (int64_t)items.size() / 8;
+    bk.far1 = (int64_t)fitems.size() / 8;
+    bk.ctr1 = (int64_t)clist.size();
+    if (bk.ctr1 > bk.ctr0) ctx->buckets.push_back(bk);
   }
   ctx->n_near_items = (int64_t)items.size() / 8;
   ctx->n_far_items = (int64_t)fitems.size() / 8;
   ctx->n_near_rows = rows;
-  GQ_TRY(upload(ctx, d.near_src, src.data(), src.size()));
-  GQ_TRY(upload(ctx, d.near_items, items.data(), items.size() / 4));
-  GQ_TRY(upload(ctx, d.far_items, fitems.data(), fitems.size() / 4));
-  GQ_TRY(upload(ctx, d.bctr0, bctr0.data(), nb));
-  GQ_TRY(upload(ctx, d.bctr1, bctr1.data(), nb));
-  GQ_TRY(upload(ctx, d.part_base, base.data(), nb));
-  GQ_TRY(upload(ctx, d.n_chunks, nch.data(), nb));
-  return GQ_OK;
+  // these buffers live in nw_allocations (re-uploaded when the orders change)
+  std::vector<void *> saved;
+  saved.swap(ctx->allocations);
+  gq_status st = GQ_OK;
+  if (st == GQ_OK) st = upload(ctx, d.near_src, src.data(), src.size());
+  if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.bctr0, bctr0.data(), nb);
+  if (st == GQ_OK) st = upload(ctx, d.bctr1, bctr1.data(), nb);
+  if (st == GQ_OK) st = upload(ctx, d.part_base, base.data(), nb);
+  if (st == GQ_OK) st = upload(ctx, d.n_chunks, nch.data(), nb);
+  if (st == GQ_OK) st = upload(ctx, d.ctr_list, clist.data(), clist.size());
+  ctx->nw_allocations.swap(ctx->allocations);
+  ctx->allocations.swap(saved);
+  return st;
 }
 
 gq_status upload_all(gq_ctx *ctx) {
@@ -260,7 +298,7 @@ gq_status upload_all(gq_ctx *ctx) {
 
   // tables
   const gq::Tables &tb = ctx->tables;
-  const int P1 = ctx->params.p_fmm + 1, PQ = ctx->pq_bucket;
+  const int P1 = ctx->params.p_fmm + 1, PQ = ctx->params.p_qbx;
   GQ_TRY(upload(ctx, d.m2m_rt, tb.m2m_rt.data(), tb.m2m_rt.size()));
   GQ_TRY(upload(ctx, d.l2l_rt, tb.l2l_rt.data(), tb.l2l_rt.size()));
   GQ_TRY(upload(ctx, d.omega, tb.omega.data(), tb.omega.size() / 2));
@@ -302,7 +340,7 @@ gq_status ensure_workspace(gq_ctx *ctx, int nd) {
   GQ_TRY(alloc_ws(ctx, d.sdip, n * ctx->ns));
   GQ_TRY(alloc_ws(ctx, d.M, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.L, n * nb * P1));
-  GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->pq_bucket + 1)));
+  GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1)));
   GQ_TRY(alloc_ws(ctx, d.tv, n * 2 * ctx->nt));
   ctx->ws_batch = nd;
   return GQ_OK;
@@ -485,7 +523,8 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.overlap != 0 && p.overlap != 1) return fail(ctx, GQ_EINVAL, "overlap must be 0 or 1");
   free_device(ctx);
   ctx->params = p;
-  ctx->pq_bucket = p.p_qbx;
+  ctx->pq_values.clear();
+  for (int q : gq::compiled_pq()) if (q <= p.p_qbx) ctx->pq_values.push_back(q);
   auto t0 = std::chrono::steady_clock::now();
   gq::TreeParams tp;
   tp.n_max = p.n_max; tp.count_mode = p.count_mode; tp.t_f = p.t_f;
@@ -499,6 +538,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   }
   if (!msg.empty()) return fail(ctx, GQ_EINVAL, msg);
   gq::build_tables(ctx->tables, p.p_fmm, p.p_qbx);
+  ctx->box_pq.assign(ctx->tree.n_boxes(), p.p_qbx);
   if (ctx->device >= 0) {
     GQ_HIP(ctx, hipSetDevice(ctx->device));
     gq_status st = upload_all(ctx);
@@ -593,6 +633,48 @@ gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count) {
   }
   *count = (int64_t)n;
   if (dst && n) std::memcpy(dst, src, n * esz);
+  return GQ_OK;
+}
+
+gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_set_qbx_orders before a successful gq_build");
+  if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "bad mem");
+  if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
+  const gq::Tree &t = ctx->tree;
+  std::vector<int32_t> ord(ctx->nc, ctx->params.p_qbx);
+  if (orders) {
+    if (mem == GQ_MEM_HOST) std::memcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc);
+    else GQ_HIP(ctx, hipMemcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc, hipMemcpyDeviceToHost));
+  }
+  std::vector<int32_t> bp(t.n_boxes(), -1);
+  for (int64_t k = 0; k < ctx->nc; ++k) {
+    const int32_t q = ord[t.ctr_order[k]];
+    if (q < 0 || q > ctx->params.p_qbx) return fail(ctx, GQ_EINVAL, "order outside 0..p_qbx");
+    bp[t.ctr_box[k]] = std::max(bp[t.ctr_box[k]], q);
+  }
+  for (int64_t b = 0; b < t.n_boxes(); ++b) {
+    int q = ctx->params.p_qbx;  // smallest compiled order >= the box's largest center order
+    for (int c : ctx->pq_values)
+      if (c >= bp[b]) { q = c; break; }
+    bp[b] = q;
+  }
+  ctx->box_pq = bp;
+  if (ctx->device >= 0) {
+    GQ_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->side) GQ_HIP(ctx, hipStreamSynchronize(ctx->side));
+    gq_status st = upload_near_work(ctx);
+    if (st != GQ_OK) return st;
+  }
+  return GQ_OK;
+}
+
+gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!ctx->built || !count) return fail(ctx, GQ_ESTATE, "no tree built or null count");
+  *count = (int64_t)ctx->box_pq.size();
+  if (dst) std::memcpy(dst, ctx->box_pq.data(), sizeof(int32_t) * ctx->box_pq.size());
   return GQ_OK;
 }
 

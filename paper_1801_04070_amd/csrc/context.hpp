@@ -49,6 +49,7 @@ struct DevBuffers {
   int32_t *bctr0 = nullptr, *bctr1 = nullptr;   // owned center range per box
   int32_t *part_base = nullptr;      // first near row of each box
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
+  int32_t *ctr_list = nullptr;       // tree-order centers grouped by order
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
   double2 *opow = nullptr, *omega = nullptr;
@@ -63,6 +64,12 @@ struct DevBuffers {
   double2 *sdip = nullptr;           // per-source dipole  w * tau * n
   double2 *M = nullptr, *L = nullptr;
   double *tv = nullptr;              // per target slot values
+};
+
+// Per-order ranges of the work lists (items of k_near / k_m2qbxl, centers of k_qbx_center).
+struct OrderBucket {
+  int pq = 0;
+  int64_t near0 = 0, near1 = 0, far0 = 0, far1 = 0, ctr0 = 0, ctr1 = 0;
 };
 
 }  // namespace gq
@@ -83,7 +90,10 @@ struct gq_ctx {
   gq_params params{};
   gq::Tree tree;
   gq::Tables tables;
-  int pq_bucket = 0;                 // compiled QBX order used by the kernels
+  std::vector<int> pq_values;        // compiled QBX orders <= params.p_qbx, ascending
+  std::vector<int32_t> box_pq;       // QBX order of each box (largest order of its centers)
+  std::vector<gq::OrderBucket> buckets;  // per order: item and center ranges
+  std::vector<void *> nw_allocations;    // direct / List 3 far work, re-uploaded on order changes
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   gq::DevBuffers d;

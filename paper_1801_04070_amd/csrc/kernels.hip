@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(64) k_near(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
-    const double2 *__restrict__ sdip, double2 *__restrict__ anear, int64_t src_st,
+    const double2 *__restrict__ sdip, double2 *__restrict__ anear, int rs, int64_t src_st,
     int64_t row_st) {
   __shared__ double2 t_xy[kNearBatch];
   __shared__ double t_q[(KIND & 1) ? kNearBatch : 1];
@@ -490,7 +490,7 @@ __global__ void __launch_bounds__(64) k_near(
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
     acc.finish(alpha, log(r));
-    double2 *row = anear + (int64_t)(row_first + cl) * (PQ + 1);
+    double2 *row = anear + (int64_t)(row_first + cl) * rs;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
   }
@@ -549,8 +549,7 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_side, const E *__restrict__ M, int P1,
-    double2 *__restrict__ anear, int64_t box_st,
-    int64_t row_st) {
+    double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st) {
   const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (w >= n_items) return;  // uniform per wavefront
@@ -580,7 +579,7 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
     }
   }
   if (active && sl == 0) {
-    double2 *row = anear + (int64_t)(row_first + cl) * (PQ + 1);
+    double2 *row = anear + (int64_t)(row_first + cl) * rs;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
   }
@@ -592,7 +591,8 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
 // One thread per center (tree order, so a wave covers centers of a few neighbouring boxes).
 template <int KIND, int PQ, typename E>
 __global__ void __launch_bounds__(256) k_qbx_center(
-    int32_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    int32_t nc, const int32_t *__restrict__ clist, int rs, int ls,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const int32_t *__restrict__ cbox, const double2 *__restrict__ bc,
     const int32_t *__restrict__ blevel, const double *__restrict__ level_side,
     const E *__restrict__ L, int P1, const double *__restrict__ l2q_binom,
@@ -602,8 +602,9 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
     int64_t tv_st) {
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
+  const int32_t ic = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ic >= nc) return;
+  const int32_t c = clist[ic];
   {
     const int64_t jd = blockIdx.y;
     L += jd * box_st;
@@ -625,7 +626,7 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const E *Lb = L + (int64_t)b * P1;
     for (int k = P1 - 1; k >= 0; --k) {
       const double2 bk = to_d2(Lb[k]);
-      const double *Ck = l2q_binom + (int64_t)k * (PQ + 1);
+      const double *Ck = l2q_binom + (int64_t)k * ls;
 #pragma unroll
       for (int m = 0; m <= PQ; ++m)
         if (m <= k) alpha[m] = caxpy(Ck[m], bk, cmul(alpha[m], t));
@@ -645,7 +646,7 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const int32_t loc = c - bctr0[b];
     const int32_t nch = n_chunks[b];
     for (int32_t j = 0; j < nch; ++j) {
-      const double2 *row = anear + (int64_t)(part_base[b] + j * nbc + loc) * (PQ + 1);
+      const double2 *row = anear + (int64_t)(part_base[b] + j * nbc + loc) * rs;
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], row[m]);
     }
@@ -757,7 +758,8 @@ struct Strides {
 
 Strides strides(const gq_ctx *ctx) {
   const int64_t P1 = ctx->params.p_fmm + 1;
-  return {ctx->ns, ctx->tree.n_boxes() * P1, ctx->n_near_rows * (ctx->pq_bucket + 1), 2 * ctx->nt};
+  return {ctx->ns, ctx->tree.n_boxes() * P1, ctx->n_near_rows * (ctx->params.p_qbx + 1),
+          2 * ctx->nt};
 }
 
 template <int KIND>
@@ -787,7 +789,44 @@ template <> struct ExpTables<float2> {
         opow(d.opow_f) {}
 };
 
+// The three per-order stages of one order bucket.
 template <int KIND, int PQ, typename E>
+void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
+                        const Strides &S) {
+  auto &d = ctx->d;
+  const int32_t n = (int32_t)(bk.near1 - bk.near0);
+  if (n > 0)
+    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(n, nd), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
+                       d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
+                       ctx->params.p_qbx + 1, S.src, S.row);
+}
+
+template <int PQ, typename E>
+void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
+                          const Strides &S, const E *M) {
+  auto &d = ctx->d;
+  const int32_t n = (int32_t)(bk.far1 - bk.far0);
+  if (n > 0)
+    hipLaunchKernelGGL((k_m2qbxl<PQ, E>), dim3((n + 3) / 4, nd), dim3(256), 0, s, n,
+                       d.far_items + 2 * bk.far0, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel,
+                       d.level_side, M, ctx->params.p_fmm + 1, d.anear, ctx->params.p_qbx + 1,
+                       S.box, S.row);
+}
+
+template <int KIND, int PQ, typename E>
+void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
+                          const Strides &S, const E *L) {
+  auto &d = ctx->d;
+  const int32_t n = (int32_t)(bk.ctr1 - bk.ctr0);
+  if (n > 0)
+    hipLaunchKernelGGL((k_qbx_center<KIND, PQ, E>), dim3((n + 255) / 256, nd), dim3(256), 0, s, n,
+                       d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
+                       d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
+                       d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear,
+                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
+}
+
+template <int KIND, typename E>
 hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   auto &d = ctx->d;
   auto &t = ctx->tree;
@@ -801,16 +840,20 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   // while the upward pass, M2L, List 3 far and the downward pass proceed on the caller's stream
   // (without overlap both "streams" are the caller's stream and the events order nothing new).
   const hipStream_t side = ctx->params.overlap ? ctx->side : st;
-  const int32_t nitems = (int32_t)ctx->n_near_items;
   hipError_t e = hipEventRecord(ctx->ev_fork, st);
   if (e != hipSuccess) return e;
   e = hipStreamWaitEvent(side, ctx->ev_fork, 0);
   if (e != hipSuccess) return e;
-  if (nitems > 0) {
+  {
     StageTimer st_(ctx, GQ_STAGE_NEAR, side);
-    hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(nitems, nd), dim3(64), 0, side, nitems,
-                       d.near_items, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear, S.src,
-                       S.row);
+    for (const OrderBucket &bk : ctx->buckets) {
+      switch (bk.pq) {
+#define GQ_CASE(P) \
+  case P: launch_near_bucket<KIND, P, E>(ctx, bk, nd, side, S); break;
+        GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+      }
+    }
   }
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
@@ -833,12 +876,16 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   // List 3 far multipoles -> centers on the side stream, once the upward pass is complete
   e = hipStreamWaitEvent(side, ctx->ev_up, 0);
   if (e != hipSuccess) return e;
-  const int32_t nfi = (int32_t)ctx->n_far_items;
-  if (nfi > 0) {
+  if (ctx->n_far_items > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
-    hipLaunchKernelGGL((k_m2qbxl<PQ, E>), dim3((nfi + 3) / 4, nd), dim3(256), 0, side, nfi,
-                       d.far_items, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel, d.level_side, M, P1,
-                       d.anear, S.box, S.row);
+    for (const OrderBucket &bk : ctx->buckets) {
+      switch (bk.pq) {
+#define GQ_CASE(P) \
+  case P: launch_m2qbxl_bucket<P, E>(ctx, bk, nd, side, S, M); break;
+        GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+      }
+    }
   }
   e = hipEventRecord(ctx->ev_join, side);
   if (e != hipSuccess) return e;
@@ -861,23 +908,26 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
                            d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
     }
   }
-  const int32_t nc = (int32_t)ctx->nc;
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;
   {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
-    hipLaunchKernelGGL((k_qbx_center<KIND, PQ, E>), dim3((nc + 255) / 256, nd), dim3(256), 0, st,
-                       nc, d.cxy, d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, P1, d.l2q_binom,
-                       d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear, d.c2t_start,
-                       d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
+    for (const OrderBucket &bk : ctx->buckets) {
+      switch (bk.pq) {
+#define GQ_CASE(P) \
+  case P: launch_center_bucket<KIND, P, E>(ctx, bk, nd, st, S, L); break;
+        GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+      }
+    }
   }
   return hipGetLastError();
 }
 
-template <int KIND, int PQ>
+template <int KIND>
 hipError_t launch_fmm(gq_ctx *ctx, int nd) {
-  return ctx->params.precision == GQ_MIXED_FP32 ? launch_fmm_t<KIND, PQ, float2>(ctx, nd)
-                                                : launch_fmm_t<KIND, PQ, double2>(ctx, nd);
+  return ctx->params.precision == GQ_MIXED_FP32 ? launch_fmm_t<KIND, float2>(ctx, nd)
+                                                : launch_fmm_t<KIND, double2>(ctx, nd);
 }
 
 template <int KIND, int PQ>
@@ -893,16 +943,25 @@ hipError_t launch_direct(gq_ctx *ctx, int nd) {
 }
 
 template <int PQ>
-hipError_t dispatch_kind(gq_ctx *ctx, int kind, bool direct, int nd) {
+hipError_t dispatch_direct(gq_ctx *ctx, int kind, int nd) {
   switch (kind) {
-    case 1: return direct ? launch_direct<1, PQ>(ctx, nd) : launch_fmm<1, PQ>(ctx, nd);
-    case 2: return direct ? launch_direct<2, PQ>(ctx, nd) : launch_fmm<2, PQ>(ctx, nd);
-    case 3: return direct ? launch_direct<3, PQ>(ctx, nd) : launch_fmm<3, PQ>(ctx, nd);
+    case 1: return launch_direct<1, PQ>(ctx, nd);
+    case 2: return launch_direct<2, PQ>(ctx, nd);
+    case 3: return launch_direct<3, PQ>(ctx, nd);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
+
+const std::vector<int> &compiled_pq() {
+  static const std::vector<int> v = {
+#define GQ_CASE(P) P,
+      GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+  };
+  return v;
+}
 
 bool pq_supported(int pq) {
   switch (pq) {
@@ -925,12 +984,21 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const 
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  switch (ctx->pq_bucket) {
+  if (direct) {
+    switch (ctx->params.p_qbx) {
 #define GQ_CASE(P) \
-  case P: e = dispatch_kind<P>(ctx, kind, direct, nd); break;
-    GQ_PQ_LIST(GQ_CASE)
+  case P: e = dispatch_direct<P>(ctx, kind, nd); break;
+      GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (kind) {
+      case 1: e = launch_fmm<1>(ctx, nd); break;
+      case 2: e = launch_fmm<2>(ctx, nd); break;
+      case 3: e = launch_fmm<3>(ctx, nd); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   const int32_t nt = (int32_t)ctx->nt;

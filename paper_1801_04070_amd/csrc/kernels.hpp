@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 struct gq_ctx;
 
 // QBX orders with compiled center kernels (the per-center coefficient arrays live in registers).
@@ -11,6 +13,9 @@ struct gq_ctx;
 namespace gq {
 
 bool pq_supported(int pq);
+
+// The compiled QBX orders, ascending.
+const std::vector<int> &compiled_pq();
 
 
 // Maximum densities per launch (the batch dimension of every kernel's grid).

@@ -222,3 +222,38 @@ def test_mixed_and_high_order_c2_sampled():
     print(f"C2 mixed p16 rel_err={err32:.3e}  fp64 p40 rel_err={err64:.3e}")
     assert err32 < 1e-6
     assert err64 < 1e-12
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_per_center_orders_match_oracle(kind):
+    """Per-center QBX orders: every box runs at the smallest compiled order covering its centers;
+    each target's value is the average of its two one-sided values at their centers' orders."""
+    from paper_1801_04070_amd import _lib
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    mu, _ = _densities(g, 6)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=30)
+    uniform = _run(q, kind, mu, None)
+    orders = np.random.default_rng(0).choice([3, 4, 6, 8, 12], size=g.n_ctr).astype(np.int32)
+    q.set_qbx_orders(orders)
+    bo = q.box_orders()
+    rng_c = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    order_c = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    eff = np.empty(g.n_ctr, np.int64)
+    for b, (c0, c1) in enumerate(rng_c):
+        eff[order_c[c0:c1]] = bo[b]
+    assert (eff >= orders).all() and set(np.unique(eff)) <= {4, 6, 8, 10, 12, 16}
+    gpu = _run(q, kind, mu, None)
+    ref = np.zeros(g.n_tgt)
+    for col in (0, 1):
+        cidx = g.tgt_ctr[:, col]
+        for p in np.unique(eff[cidx]):
+            sel = np.nonzero(eff[cidx] == p)[0]
+            tc = np.full((len(sel), 2), -1, np.int32)
+            tc[:, 0] = cidx[sel]
+            ref[sel] += 0.5 * oracle.qbx_eval(g, kind, mu, p_qbx=int(p), tgt_xy=g.tgt_xy[sel],
+                                               tgt_ctr=tc)
+    err = _rel(gpu, ref)
+    print(f"per-center orders kind={kind} rel_err={err:.3e}")
+    assert err < 1e-10
+    q.set_qbx_orders(None)
+    assert np.array_equal(_run(q, kind, mu, None), uniform)

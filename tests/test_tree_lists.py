@@ -230,3 +230,25 @@ def test_error_paths_host_context():
                     np.zeros((1, 2)), np.array([[0, -1]], np.int32))
     s = q2.build(p_qbx=8, p_fmm=10, n_max=8, max_levels=12)
     assert s["n_levels"] == 12
+
+
+def test_box_orders_from_center_orders():
+    """gq_set_qbx_orders: each box gets the smallest compiled order >= its centers' largest."""
+    g = gi.starfish_c1()
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(g)
+    q.build(p_qbx=12, p_fmm=10)
+    assert (q.box_orders() == 12).all()
+    orders = np.random.default_rng(1).integers(0, 13, size=g.n_ctr).astype(np.int32)
+    q.set_qbx_orders(orders)
+    bo = q.box_orders()
+    rng_c = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    order_c = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    compiled = [4, 6, 8, 10, 12]
+    for b, (c0, c1) in enumerate(rng_c):
+        if c1 > c0:
+            need = orders[order_c[c0:c1]].max()
+            assert bo[b] == min(c for c in compiled if c >= need)
+    from paper_1801_04070_amd import GQError
+    with pytest.raises(GQError):
+        q.set_qbx_orders(np.full(g.n_ctr, 13, np.int32))
