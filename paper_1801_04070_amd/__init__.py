@@ -31,7 +31,7 @@ def library():
 
 
 def __getattr__(name):
-    if name in _lib.EXPORTED:
+    if name in _lib.EXPORTED or name in _lib.EXPORTED_MLP:
         return getattr(library(), name)
     raise AttributeError(name)
 

@@ -48,6 +48,11 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_last_error"]
 
 
+EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
+                "gq_mlp_get_params", "gq_mlp_forward", "gq_mlp_gradients", "gq_mlp_train_step",
+                "gq_mlp_last_error"]
+
+
 def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(
@@ -73,5 +78,20 @@ def load(path: str = LIB_PATH):
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:
         if name != "gq_last_error":
+            getattr(L, name).restype = C.c_int
+    # include/gigaqbx_mlp.h
+    L.gq_mlp_create.argtypes = [C.POINTER(C.c_void_p), i32, vp, i32, i32, i32, C.c_uint64]
+    L.gq_mlp_destroy.argtypes = [vp]
+    L.gq_mlp_param_count.argtypes = [vp]
+    L.gq_mlp_param_count.restype = C.c_int64
+    L.gq_mlp_set_params.argtypes = [vp, vp]
+    L.gq_mlp_get_params.argtypes = [vp, vp]
+    L.gq_mlp_forward.argtypes = [vp, i64, vp, vp]
+    L.gq_mlp_gradients.argtypes = [vp, i64, vp, vp, vp, vp, C.POINTER(C.c_float)]
+    L.gq_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, C.c_float, C.POINTER(C.c_float)]
+    L.gq_mlp_last_error.argtypes = [vp]
+    L.gq_mlp_last_error.restype = C.c_char_p
+    for name in EXPORTED_MLP:
+        if name not in ("gq_mlp_last_error", "gq_mlp_param_count"):
             getattr(L, name).restype = C.c_int
     return L
