@@ -84,6 +84,27 @@ class Timer:
         return ms, stages
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` (mean over its template instances) from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have changed since
+    the counters were taken."""
+    from paper_1801_04070_amd import profsummary
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_c2.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except OSError:
+        return None, "no counter summary"
+    if t.get("kernel_sources_sha256") != profsummary.sources_sha256():
+        return None, "kernel sources changed since the counters were taken"
+    ks = [d for k, d in t["kernels"].items() if k.startswith(kernel + "<") or k == kernel]
+    if not ks:
+        return None, "kernel not in the counter summary"
+    n = sum(d["dispatches"] for d in ks)
+    return (round(sum(d["hbm_bytes"] * d["dispatches"] for d in ks) / n),
+            "profiles/hbm_traffic_c2.json (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+
+
 def per_stage(stages, steps):
     agg = {}
     for (kind, name), (ms, cnt) in stages.items():
@@ -194,6 +215,7 @@ def main():
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops),
                 "algorithmic_bytes_per_launch": int(nbytes),
                 "achieved_hbm_gbs": round(nbytes / (avg_ms * 1e-3) / 1e9, 1)}
+    roofline["traffic"], roofline["traffic_source"] = measured_traffic(KERNEL_OF_STAGE[dom])
     stage_rates = {}
     for name, (ms, cnt) in agg.items():
         if name in work[GQ_S] and cnt:

@@ -7,7 +7,8 @@ include the arclength element, unit outward normals, QBX centers placed at y -/+
 target-to-center association for on-surface targets, densities, and harmonic test fields.
 
 Both the CPU oracle's callers and the GPU library's callers take their inputs from here; neither
-the oracle nor the library imports this module.
+the oracle nor the library's compute path imports this module (the offline trainer of the
+order-prediction network draws its training geometries from here).
 
 Random numbers come from numpy's PCG64 generator (``numpy.random.default_rng(seed)``), so every
 workload is reproducible from its seed.
@@ -28,6 +29,7 @@ Conventions
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import copy
 import math
 
 import numpy as np
@@ -131,10 +133,23 @@ def _discretize_curve(curve: StarCurve, n_panels: int, order: int, radius_factor
     return th, xy, nrm, w, plen_node
 
 
-def discretize(curves, n_panels, order: int = 16, radius_factor: float = 0.5) -> Geometry:
-    """Discretise curves into ``n_panels`` (int or per-curve list) Gauss panels of ``order`` nodes."""
+def discretize(curves, n_panels, order: int = 16, radius_factor: float = 0.5,
+               src_order: int | None = None) -> Geometry:
+    """Discretise curves into ``n_panels`` (int or per-curve list) Gauss panels of ``order`` nodes.
+
+    With ``src_order`` the source quadrature is upsampled (Sec. 2: geometry and density are
+    taken to p_quad nodes per panel for QBX): sources are the ``src_order``-node Gauss rule on
+    the same panels, while centers and targets stay at the ``order`` nodes."""
     if np.isscalar(n_panels):
         n_panels = [int(n_panels)] * len(curves)
+    if src_order is not None and src_order != order:
+        g = discretize(curves, n_panels, order, radius_factor)
+        f = discretize(curves, n_panels, src_order, radius_factor)
+        g.src_xy, g.src_nrm, g.src_w = f.src_xy, f.src_nrm, f.src_w
+        g.theta, g.curve_id, g.panel_id = f.theta, f.curve_id, f.panel_id
+        g.panel_len = f.panel_len
+        g.geom_offsets = f.geom_offsets
+        return g
     parts = [_discretize_curve(c, p, order, radius_factor) for c, p in zip(curves, n_panels)]
     th = np.concatenate([p[0] for p in parts])
     xy = np.concatenate([p[1] for p in parts])
@@ -226,7 +241,7 @@ def ragged_star_batch(n_geoms=32, seed=200, min_nodes=1024, max_nodes=65536, ord
 
 
 def wavy_lattice(nx=8, ny=8, panels_per_curve=1024, seed=300, order=16, radius_factor=0.5,
-                 gap_in_radii=4.0):
+                 gap_in_radii=4.0, src_order=None):
     """Wavy closed curves on an nx x ny lattice, spaced so neighbours nearly touch.
 
     r = 1 + a cos(k theta + phi), k ~ U{8..16}, a ~ U(0.05, 0.15); the lattice pitch leaves a
@@ -244,7 +259,48 @@ def wavy_lattice(nx=8, ny=8, panels_per_curve=1024, seed=300, order=16, radius_f
             a, k, ph = specs[j * nx + i]
             curves.append(StarCurve(cx=1.2 + i * pitch, cy=1.2 + j * pitch, R=1.0, amp=a,
                                     arms=k, phase=ph))
-    return discretize(curves, panels_per_curve, order, radius_factor)
+    return discretize(curves, panels_per_curve, order, radius_factor, src_order)
+
+
+def per_center_targets(geom: Geometry) -> Geometry:
+    """Copy of ``geom`` (as made by ``discretize``: target i is the node of centers 2i, 2i+1)
+    with one target per center: center c evaluates at its own node alone."""
+    g = copy.copy(geom)
+    n = geom.tgt_xy.shape[0]
+    g.tgt_xy = np.repeat(geom.tgt_xy, 2, axis=0)
+    g.tgt_ctr = np.stack([np.arange(2 * n, dtype=np.int32), np.full(2 * n, -1, np.int32)], axis=1)
+    return g
+
+
+def order_training_geometry(seed: int, order: int = 16, radius_factor: float = 0.5,
+                            src_order: int = 64):
+    """A 2 x 2 lattice of random stars and a charge point x0 between them.
+
+    Per geometry: panels per curve ~ U{64..512}; per curve k ~ U{3..16} arms with amplitude
+    a ~ U(0.05, min(0.3, 2.4 / k)); the gap between neighbouring outer circles is drawn
+    log-uniformly from 2.5 to 40 expansion radii, so some pairs of curves nearly touch. x0 sits
+    near the middle of the lattice, outside every curve (harmonic field for Green's formula).
+    Sources are upsampled to ``src_order`` nodes per panel.
+    """
+    rng = np.random.default_rng(seed)
+    panels = int(rng.integers(64, 513))
+    specs = []
+    for _ in range(4):
+        k = int(rng.integers(3, 17))
+        specs.append((float(rng.uniform(0.05, min(0.3, 2.4 / k))), k,
+                      float(rng.uniform(0, 2 * np.pi))))
+    amax = max(a for a, _, _ in specs)
+    perim = 2 * np.pi * max(math.hypot(1 + a, a * k) for a, k, _ in specs)
+    rmax_ctr = radius_factor * perim / panels
+    gap = float(np.exp(rng.uniform(np.log(2.5), np.log(40.0)))) * rmax_ctr
+    pitch = 2 * (1 + amax) + gap
+    curves = [StarCurve(cx=i * pitch, cy=j * pitch, R=1.0, amp=a, arms=k, phase=ph)
+              for (a, k, ph), (i, j) in zip(specs, [(0, 0), (1, 0), (0, 1), (1, 1)])]
+    geom = discretize(curves, panels, order, radius_factor, src_order)
+    while True:
+        x0 = np.array([0.5 * pitch, 0.5 * pitch]) + rng.uniform(-0.3, 0.3, 2) * pitch
+        if all(math.hypot(x0[0] - c.cx, x0[1] - c.cy) > 1 + c.amp + 0.05 for c in curves):
+            return geom, x0
 
 
 def point_charge_field(points: np.ndarray, normals: np.ndarray, x0):
@@ -257,9 +313,11 @@ def point_charge_field(points: np.ndarray, normals: np.ndarray, x0):
 
 
 def green_test_field(geom: Geometry, x0):
-    """Densities for Green's formula S(du/dn) - D(u): returns (sigma=du/dn, tau=u, u)."""
+    """Densities for Green's formula S(du/dn) - D(u) with u = log|x - x0|: returns
+    (sigma = du/dn at the sources, tau = u at the sources, u at the targets)."""
     u, dudn = point_charge_field(geom.src_xy, geom.src_nrm, x0)
-    return dudn, u, u
+    d = geom.tgt_xy - np.asarray(x0, dtype=np.float64)[None, :]
+    return dudn, u, 0.5 * np.log(np.einsum("ij,ij->i", d, d))
 
 
 def config_geometry(name: str) -> Geometry:

@@ -92,10 +92,17 @@ gq_status gq_set_stream(gq_ctx *ctx, void *hip_stream);
  *   src_xy  (n_src, 2)  quadrature nodes y_i
  *   src_nrm (n_src, 2)  unit normals n_i (outward for the sign conventions of eq. (dlp))
  *   src_w   (n_src)     quadrature weights including the arclength element
- *   ctr_xy  (n_ctr, 2)  QBX expansion centers, ctr_r (n_ctr) their radii (> 0)
+ *   ctr_xy  (n_ctr, 2)  QBX expansion centers, ctr_r (n_ctr) their radii (> 0); n_ctr may be
+ *                       0 when every target is a conventional one
  *   tgt_xy  (n_tgt, 2)  targets; tgt_ctr (n_tgt, 2) int32 indices of the one or two centers
  *                       whose expansions are averaged for the target; -1 marks an unused slot.
- *                       Every target needs at least one center.
+ *                       A target with both slots -1 is a conventional (off-surface) target:
+ *                       it gets the plain point value of the layer potential (direct sum over
+ *                       its near sources, multipole-to-point over List 3 far, its box's local
+ *                       expansion: Stages 3a, 5b and 8a) through an internal center at the
+ *                       target with radius 2^-40 of the particles' extent, appended after the
+ *                       caller's centers (indices >= n_ctr in the tree arrays). Such a target
+ *                       must not coincide with a source node.
  * mem says whether all pointers are host (GQ_MEM_HOST) or device (GQ_MEM_DEVICE) memory on the
  * context's device. The call returns after the copy; the arrays may be freed afterwards. It
  * invalidates any previous build. Non-finite coordinates or radii give GQ_EINVAL.
@@ -132,7 +139,8 @@ gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, in
 /*
  * Same contract as gq_eval, computed by unaccelerated QBX on the GPU: every center's expansion
  * (eq. (qbx)) is formed from all sources directly, without tree or lists (needs only
- * gq_set_geometry and gq_build for the orders). O(n_ctr n_src) work; for checking and small
+ * gq_set_geometry and gq_build for the orders). Each center uses the same order as in gq_eval
+ * (its box's order after gq_set_qbx_orders). O(n_ctr n_src) work; for checking and small
  * problems.
  */
 gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
@@ -168,6 +176,7 @@ typedef struct {
   double root_lo[2];
   double root_side;
   double build_ms;               /* host time of the last gq_build                        */
+  int64_t n_point_targets;       /* conventional targets (each with an internal center)   */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);

@@ -41,6 +41,9 @@ gq_status gq_mlp_destroy(gq_mlp *net);
 /* Number of FP32 parameters. */
 int64_t gq_mlp_param_count(const gq_mlp *net);
 
+/* Layer sizes given at creation (any output pointer may be NULL). */
+gq_status gq_mlp_shape(const gq_mlp *net, int *n_in, int *n_hidden, int *n_out);
+
 /* Copy the FP32 master parameters from / to host memory (synchronous); set also resets Adam. */
 gq_status gq_mlp_set_params(gq_mlp *net, const float *host_params);
 gq_status gq_mlp_get_params(gq_mlp *net, float *host_params);
@@ -60,6 +63,39 @@ gq_status gq_mlp_train_step(gq_mlp *net, int64_t n, const float *x, const float 
                             const float *w, float lr, float *loss);
 
 const char *gq_mlp_last_error(gq_mlp *net);
+
+/* The HIP stream the network's work is enqueued on (as given to gq_mlp_create). */
+void *gq_mlp_stream(const gq_mlp *net);
+
+/* ---- per-center features and order prediction (uses a built gq_ctx) ---------------------- */
+
+#define GQ_N_FEATURES 8
+
+/* Geometry features of every center, from the sources within four expansion radii r of it
+ * (tree walk over the leaf boxes that meet that disk). Written as FP32 to the device array feat
+ * (n_ctr x GQ_N_FEATURES, the caller's center order):
+ *   0: arc length (sum of quadrature weights) within 2 r, over 4 r
+ *   1: arc length within 4 r, over 8 r
+ *   2: distance to the nearest source node, over r
+ *   3: log2(r / mean node spacing within 4 r)
+ *   4: |sum of w n| / sum of w within 4 r  (1 for one straight piece of curve)
+ *   5: weighted standard deviation of (y - c).n / r within 4 r  (curvature)
+ *   6: weighted mean of (y - c).n / r within 4 r  (about +1 interior side, -1 exterior side)
+ *   7: distance to the nearest source whose normal faces against that of the nearest node,
+ *      over 4 r (1 when there is none inside the disk: no opposite sheet of curve nearby)
+ * Needs a successful gq_build on a device context (else GQ_ESTATE). Synchronous. */
+gq_status gq_center_features(gq_ctx *ctx, float *feat);
+
+/* Per-center QBX orders from the network: features -> network -> predicted log10 QBX error
+ * e_j = out_scale * y_j + out_shift for each candidate order cand[j] (n_cand ascending host
+ * values in 0..p_qbx; the network's n_out must equal n_cand). Each center takes the smallest
+ * candidate with e_j + margin <= log10_tol, else the largest candidate (the fallback for
+ * centers the network cannot place, and for non-finite predictions). Orders go to the device
+ * array `orders` (n_ctr int32, caller order); with apply != 0 they are then passed to
+ * gq_set_qbx_orders. Temporary device buffers are allocated and freed here. Synchronous. */
+gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n_cand,
+                            double out_scale, double out_shift, double log10_tol, double margin,
+                            int32_t *orders, int apply);
 
 #ifdef __cplusplus
 }

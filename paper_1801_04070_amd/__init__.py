@@ -26,6 +26,12 @@ def library():
     """The loaded C library (raises ImportError if it is not built)."""
     global _L
     if _L is None:
+        # torch first: the library then binds to the HIP runtime torch already loaded, so device
+        # pointers, streams and the device list are shared by one runtime in the process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _L = _lib.load()
     return _L
 

@@ -12,6 +12,7 @@ GQ_S, GQ_D, GQ_S_MINUS_D = 1, 2, 3
 GQ_MEM_HOST, GQ_MEM_DEVICE = 0, 1
 GQ_FP64, GQ_MIXED_FP32 = 0, 1
 GQ_MAX_P_QBX, GQ_MAX_P_FMM = 20, 63
+GQ_N_FEATURES = 8
 
 (GQ_TREE_BOX_LEVEL, GQ_TREE_BOX_PARENT, GQ_TREE_BOX_CHILD, GQ_TREE_BOX_IJ, GQ_TREE_BOX_SRC_RANGE,
  GQ_TREE_BOX_CTR_RANGE, GQ_TREE_SRC_ORDER, GQ_TREE_CTR_ORDER, GQ_LIST1_START, GQ_LIST1,
@@ -35,7 +36,8 @@ class gq_stats(C.Structure):
         "n_list4_close", "n_list4_far", "near_pairs", "list3_far_pairs", "list4_far_sources",
         "near_sources", "n_local_boxes",
         "max_list2", "max_list4", "max_list4_close", "max_list4_far")] + [
-        ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double)]
+        ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double),
+        ("n_point_targets", C.c_int64)]
 
 
 GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",
@@ -50,7 +52,8 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
                 "gq_mlp_get_params", "gq_mlp_forward", "gq_mlp_gradients", "gq_mlp_train_step",
-                "gq_mlp_last_error"]
+                "gq_mlp_last_error", "gq_mlp_shape", "gq_mlp_stream", "gq_center_features",
+                "gq_orders_predict"]
 
 
 def load(path: str = LIB_PATH):
@@ -91,7 +94,13 @@ def load(path: str = LIB_PATH):
     L.gq_mlp_train_step.argtypes = [vp, i64, vp, vp, vp, C.c_float, C.POINTER(C.c_float)]
     L.gq_mlp_last_error.argtypes = [vp]
     L.gq_mlp_last_error.restype = C.c_char_p
+    L.gq_mlp_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.gq_mlp_stream.argtypes = [vp]
+    L.gq_mlp_stream.restype = C.c_void_p
+    L.gq_center_features.argtypes = [vp, vp]
+    L.gq_orders_predict.argtypes = [vp, vp, vp, i32, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, vp, i32]
     for name in EXPORTED_MLP:
-        if name not in ("gq_mlp_last_error", "gq_mlp_param_count"):
+        if name not in ("gq_mlp_last_error", "gq_mlp_param_count", "gq_mlp_stream"):
             getattr(L, name).restype = C.c_int
     return L

@@ -23,7 +23,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
              "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 
-HIP_SOURCES = ["kernels.hip", "api.cpp", "mlp.hip"]
+HIP_SOURCES = ["kernels.hip", "api.cpp", "mlp.hip", "orders.hip"]
 CXX_SOURCES = ["tree.cpp", "tables.cpp"]
 
 

@@ -228,9 +228,11 @@ gq_status upload_all(gq_ctx *ctx) {
   {
     std::vector<double> xy(2 * nc), r(nc);
     std::vector<int64_t> inv(nc);
+    std::vector<int32_t> cperm(nc);
     for (int64_t k = 0; k < nc; ++k) {
       int64_t o = t.ctr_order[k];
       inv[o] = k;
+      cperm[k] = (int32_t)o;
       xy[2 * k] = ctx->ctr_xy[2 * o]; xy[2 * k + 1] = ctx->ctr_xy[2 * o + 1];
       r[k] = ctx->ctr_r[o];
     }
@@ -247,6 +249,7 @@ gq_status upload_all(gq_ctx *ctx) {
           slot[fill[inv[ctx->tgt_ctr[2 * tg + s]]]++] = (int32_t)(2 * tg + s);
     GQ_TRY(upload(ctx, d.cxy, xy.data(), nc));
     GQ_TRY(upload(ctx, d.cr, r.data(), nc));
+    GQ_TRY(upload(ctx, d.cperm, cperm.data(), nc));
     GQ_TRY(upload(ctx, d.cbox, t.ctr_box.data(), nc));
     GQ_TRY(upload(ctx, d.c2t_start, start.data(), nc + 1));
     GQ_TRY(upload(ctx, d.c2t_slot, slot.data(), slot.size()));
@@ -462,14 +465,16 @@ gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "mem must be GQ_MEM_HOST or GQ_MEM_DEVICE");
   if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
-  if (n_src <= 0 || n_ctr <= 0 || n_tgt < 0) return fail(ctx, GQ_EINVAL, "need n_src > 0, n_ctr > 0, n_tgt >= 0");
+  if (n_src <= 0 || n_ctr < 0 || n_tgt < 0) return fail(ctx, GQ_EINVAL, "need n_src > 0, n_ctr >= 0, n_tgt >= 0");
   if (n_src >= (int64_t(1) << 31) || n_ctr >= (int64_t(1) << 31) || 2 * n_tgt >= (int64_t(1) << 31))
     return fail(ctx, GQ_EUNSUP, "sizes beyond 2^31 are not supported");
-  if (!src_xy || !src_nrm || !src_w || !ctr_xy || !ctr_r || (n_tgt > 0 && (!tgt_xy || !tgt_ctr)))
+  if (!src_xy || !src_nrm || !src_w || (n_ctr > 0 && (!ctr_xy || !ctr_r)) ||
+      (n_tgt > 0 && (!tgt_xy || !tgt_ctr)))
     return fail(ctx, GQ_EINVAL, "null geometry pointer");
   free_device(ctx);
   ctx->have_geom = false;
   ctx->ns = n_src; ctx->nc = n_ctr; ctx->nt = n_tgt;
+  ctx->nc_user = n_ctr; ctx->n_pt = 0;
   try {
     ctx->src_xy.resize(2 * n_src); ctx->src_nrm.resize(2 * n_src); ctx->src_w.resize(n_src);
     ctx->ctr_xy.resize(2 * n_ctr); ctx->ctr_r.resize(n_ctr);
@@ -495,6 +500,7 @@ gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src
     return fail(ctx, GQ_EINVAL, "non-finite geometry value");
   for (double r : ctx->ctr_r)
     if (!(r > 0)) return fail(ctx, GQ_EINVAL, "center radius must be positive");
+  std::vector<int64_t> point_targets;
   for (int64_t t = 0; t < n_tgt; ++t) {
     int used = 0;
     for (int s = 0; s < 2; ++s) {
@@ -502,8 +508,35 @@ gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src
       if (c < -1 || c >= n_ctr) return fail(ctx, GQ_EINVAL, "target-center index out of range");
       used += c >= 0;
     }
-    if (!used) return fail(ctx, GQ_EUNSUP, "every target needs at least one QBX center");
+    if (!used) point_targets.push_back(t);
   }
+  if (!point_targets.empty()) {
+    const int64_t n_pt = (int64_t)point_targets.size();
+    if (n_ctr + n_pt >= (int64_t(1) << 31)) return fail(ctx, GQ_EUNSUP, "too many centers and point targets");
+    // internal radius: 2^-40 of the extent of all particles, far below any quadrature scale
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    auto grow = [&](const std::vector<double> &xy) {
+      for (size_t i = 0; i + 1 < xy.size(); i += 2)
+        for (int a = 0; a < 2; ++a) { lo[a] = std::min(lo[a], xy[i + a]); hi[a] = std::max(hi[a], xy[i + a]); }
+    };
+    grow(ctx->src_xy); grow(ctx->ctr_xy); grow(ctx->tgt_xy);
+    const double ext = std::max(hi[0] - lo[0], hi[1] - lo[1]);
+    const double r_pt = std::ldexp(ext > 0 ? ext : 1.0, -40);
+    try {
+      ctx->ctr_xy.resize(2 * (n_ctr + n_pt)); ctx->ctr_r.resize(n_ctr + n_pt);
+    } catch (const std::bad_alloc &) {
+      return fail(ctx, GQ_ENOMEM, "host copy of the point-target centers");
+    }
+    for (int64_t j = 0; j < n_pt; ++j) {
+      const int64_t t = point_targets[j], c = n_ctr + j;
+      ctx->ctr_xy[2 * c] = ctx->tgt_xy[2 * t]; ctx->ctr_xy[2 * c + 1] = ctx->tgt_xy[2 * t + 1];
+      ctx->ctr_r[c] = r_pt;
+      ctx->tgt_ctr[2 * t] = (int32_t)c;
+    }
+    ctx->n_pt = n_pt;
+    ctx->nc = n_ctr + n_pt;
+  }
+  if (ctx->nc == 0) return fail(ctx, GQ_EINVAL, "need at least one center or point target");
   ctx->have_geom = true;
   return GQ_OK;
 }
@@ -568,7 +601,8 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "no tree built");
   const gq::Tree &t = ctx->tree;
   std::memset(out, 0, sizeof(*out));
-  out->n_src = ctx->ns; out->n_ctr = ctx->nc; out->n_tgt = ctx->nt;
+  out->n_src = ctx->ns; out->n_ctr = ctx->nc_user; out->n_tgt = ctx->nt;
+  out->n_point_targets = ctx->n_pt;
   out->n_boxes = t.n_boxes(); out->n_levels = t.n_levels; out->n_leaves = t.n_leaves;
   out->n_target_boxes = t.n_target_boxes; out->n_suspended_centers = t.n_suspended;
   out->n_list1 = (int64_t)t.list1.idx.size(); out->n_list2 = (int64_t)t.list2.idx.size();
@@ -644,9 +678,11 @@ gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders) {
   const gq::Tree &t = ctx->tree;
   std::vector<int32_t> ord(ctx->nc, ctx->params.p_qbx);
   if (orders) {
-    if (mem == GQ_MEM_HOST) std::memcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc);
-    else GQ_HIP(ctx, hipMemcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc, hipMemcpyDeviceToHost));
+    if (mem == GQ_MEM_HOST) std::memcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc_user);
+    else GQ_HIP(ctx, hipMemcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc_user, hipMemcpyDeviceToHost));
   }
+  // point targets need only the constant term: lowest compiled order, never raising a box's
+  for (int64_t c = ctx->nc_user; c < ctx->nc; ++c) ord[c] = ctx->pq_values.front();
   std::vector<int32_t> bp(t.n_boxes(), -1);
   for (int64_t k = 0; k < ctx->nc; ++k) {
     const int32_t q = ord[t.ctr_order[k]];

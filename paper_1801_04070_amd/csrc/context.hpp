@@ -23,6 +23,7 @@ struct DevBuffers {
   // centers (tree order) and their targets
   double2 *cxy = nullptr;
   double *cr = nullptr;
+  int32_t *cperm = nullptr;          // caller index of each tree-order center
   int32_t *cbox = nullptr;           // owning box
   int32_t *c2t_start = nullptr;      // CSR center -> target slots (slot = 2 * target + column)
   int32_t *c2t_slot = nullptr;
@@ -83,6 +84,11 @@ struct gq_ctx {
 
   // geometry (caller order, host copies)
   int64_t ns = 0, nc = 0, nt = 0;
+  // Conventional (point) targets: a target that lists no center gets an internal center at its
+  // own position with a tiny radius, appended after the caller's nc_user centers. At the target
+  // itself only the constant term of that center's expansion survives, which is the plain point
+  // value (direct sum + M2P + L2P).
+  int64_t nc_user = 0, n_pt = 0;
   std::vector<double> src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy;
   std::vector<int32_t> tgt_ctr;
   bool have_geom = false, built = false;

@@ -655,10 +655,12 @@ __global__ void __launch_bounds__(256) k_qbx_center(
 }
 
 // ------------------------------------------------------------------------------------------
-// Direct (unaccelerated) QBX: every center takes every source, staged through LDS tiles.
+// Direct (unaccelerated) QBX: every center of one order bucket (clist, n) takes every source,
+// staged through LDS tiles.
 template <int KIND, int PQ>
 __global__ void __launch_bounds__(256) k_direct(
-    int32_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr, int32_t ns,
+    int32_t nc, const int32_t *__restrict__ clist, const double2 *__restrict__ cxy,
+    const double *__restrict__ cr, int32_t ns,
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, const int32_t *__restrict__ c2t_start,
     const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
@@ -672,8 +674,9 @@ __global__ void __launch_bounds__(256) k_direct(
   }
   __shared__ double tq[256];
   __shared__ double2 td[256];
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = c < nc;
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = i < nc;
+  const int32_t c = active ? clist[i] : 0;
   const double2 cc = active ? cxy[c] : make_double2(0.0, 0.0);
   const double r = active ? cr[c] : 1.0;
   const double ir = 1.0 / r;
@@ -931,25 +934,30 @@ hipError_t launch_fmm(gq_ctx *ctx, int nd) {
 }
 
 template <int KIND, int PQ>
-hipError_t launch_direct(gq_ctx *ctx, int nd) {
+void launch_direct(gq_ctx *ctx, const OrderBucket &bk, int nd, const Strides &S) {
   auto &d = ctx->d;
-  const int32_t nc = (int32_t)ctx->nc;
-  const Strides S = strides(ctx);
-  StageTimer st_(ctx, GQ_STAGE_DIRECT);
-  hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((nc + 255) / 256, nd), dim3(256), 0, ctx->stream,
-                     nc, d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip, d.c2t_start,
-                     d.c2t_slot, d.txy, d.tv, S.src, S.tv);
-  return hipGetLastError();
+  const int32_t n = (int32_t)(bk.ctr1 - bk.ctr0);
+  if (n > 0)
+    hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((n + 255) / 256, nd), dim3(256), 0, ctx->stream,
+                       n, d.ctr_list + bk.ctr0, d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip,
+                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.src, S.tv);
 }
 
-template <int PQ>
-hipError_t dispatch_direct(gq_ctx *ctx, int kind, int nd) {
-  switch (kind) {
-    case 1: return launch_direct<1, PQ>(ctx, nd);
-    case 2: return launch_direct<2, PQ>(ctx, nd);
-    case 3: return launch_direct<3, PQ>(ctx, nd);
+// Direct QBX at each center's box order (the same effective orders as the FMM path).
+template <int KIND>
+hipError_t dispatch_direct(gq_ctx *ctx, int nd) {
+  const Strides S = strides(ctx);
+  StageTimer st_(ctx, GQ_STAGE_DIRECT);
+  for (const OrderBucket &bk : ctx->buckets) {
+    switch (bk.pq) {
+#define GQ_CASE(P) \
+  case P: launch_direct<KIND, P>(ctx, bk, nd, S); break;
+      GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+      default: return hipErrorInvalidValue;
+    }
   }
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -985,11 +993,10 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const 
   }
   if (e != hipSuccess) return e;
   if (direct) {
-    switch (ctx->params.p_qbx) {
-#define GQ_CASE(P) \
-  case P: e = dispatch_direct<P>(ctx, kind, nd); break;
-      GQ_PQ_LIST(GQ_CASE)
-#undef GQ_CASE
+    switch (kind) {
+      case 1: e = dispatch_direct<1>(ctx, nd); break;
+      case 2: e = dispatch_direct<2>(ctx, nd); break;
+      case 3: e = dispatch_direct<3>(ctx, nd); break;
       default: return hipErrorInvalidValue;
     }
   } else {

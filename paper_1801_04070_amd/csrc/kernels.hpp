@@ -8,7 +8,7 @@
 struct gq_ctx;
 
 // QBX orders with compiled center kernels (the per-center coefficient arrays live in registers).
-#define GQ_PQ_LIST(X) X(4) X(6) X(8) X(10) X(12) X(16)
+#define GQ_PQ_LIST(X) X(4) X(6) X(8) X(10) X(12) X(16) X(20)
 
 namespace gq {
 

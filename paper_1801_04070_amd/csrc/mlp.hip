@@ -398,6 +398,14 @@ gq_status gq_mlp_destroy(gq_mlp *net) {
 
 int64_t gq_mlp_param_count(const gq_mlp *net) { return net ? net->np : 0; }
 
+gq_status gq_mlp_shape(const gq_mlp *net, int *n_in, int *n_hidden, int *n_out) {
+  if (!net) return GQ_EINVAL;
+  if (n_in) *n_in = net->n_in;
+  if (n_hidden) *n_hidden = net->n_h;
+  if (n_out) *n_out = net->n_out;
+  return GQ_OK;
+}
+
 gq_status gq_mlp_set_params(gq_mlp *net, const float *host_params) {
   if (!net || !host_params) return mfail(net, GQ_EINVAL, "null argument");
   GQ_MLP_HIP(net, hipSetDevice(net->device));
@@ -476,5 +484,7 @@ gq_status gq_mlp_train_step(gq_mlp *net, int64_t n, const float *x, const float 
 }
 
 const char *gq_mlp_last_error(gq_mlp *net) { return net ? net->err.c_str() : "null network"; }
+
+void *gq_mlp_stream(const gq_mlp *net) { return net ? static_cast<void *>(net->stream) : nullptr; }
 
 }  // extern "C"

@@ -6,6 +6,8 @@ with alpha = (t_f + sqrt 2)/(6 - sqrt 2) = 0.5046 at t_f = 0.9; the paper observ
 error about two orders of magnitude below the bound. Gates: 1e-10 at p_fmm = 30, 1e-7 at
 p_fmm = 15; direct QBX on the GPU differs from the oracle by summation order only (1e-12).
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -241,7 +243,7 @@ def test_per_center_orders_match_oracle(kind):
     eff = np.empty(g.n_ctr, np.int64)
     for b, (c0, c1) in enumerate(rng_c):
         eff[order_c[c0:c1]] = bo[b]
-    assert (eff >= orders).all() and set(np.unique(eff)) <= {4, 6, 8, 10, 12, 16}
+    assert (eff >= orders).all() and set(np.unique(eff)) <= {4, 6, 8, 10, 12, 16, 20}
     gpu = _run(q, kind, mu, None)
     ref = np.zeros(g.n_tgt)
     for col in (0, 1):
@@ -255,5 +257,34 @@ def test_per_center_orders_match_oracle(kind):
     err = _rel(gpu, ref)
     print(f"per-center orders kind={kind} rel_err={err:.3e}")
     assert err < 1e-10
+    # the direct path uses the same effective orders
+    assert _rel(_run(q, kind, mu, None, direct=True), ref) < 1e-12
     q.set_qbx_orders(None)
     assert np.array_equal(_run(q, kind, mu, None), uniform)
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_point_targets_match_oracle(kind):
+    """Conventional (off-surface) targets next to QBX targets in one evaluation: point values
+    (direct sum + M2P + L2P) against the oracle's plain sum of point potentials, QBX targets
+    against the oracle's QBX."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=96, seed=21, box=10.0)
+    mu, mu2 = _densities(g, 9)
+    rng = np.random.default_rng(kind)
+    pts = rng.uniform(g.src_xy.min(0) - 0.5, g.src_xy.max(0) + 0.5, size=(3000, 2))
+    d = np.sqrt(((pts[:, None, :] - g.src_xy[None, ::7, :]) ** 2).sum(-1)).min(1)
+    pts = pts[d > 1e-2][:2000]
+    e = copy.copy(g)
+    e.tgt_xy = np.concatenate([g.tgt_xy, pts])
+    e.tgt_ctr = np.concatenate([g.tgt_ctr, np.full((len(pts), 2), -1, np.int32)])
+    q, stats = _ctx(e, p_qbx=12, p_fmm=30)
+    assert stats["n_point_targets"] == len(pts)
+    d2 = mu2 if kind == 3 else None
+    for direct, tol in ((False, 1e-10), (True, 1e-12)):
+        gpu = _run(q, kind, mu, mu2, direct=direct)
+        n = g.n_tgt
+        ref_pt = oracle.point_potential(g, kind, mu, d2, tgt_xy=pts)
+        ref_q = oracle.qbx_eval(g, kind, mu, d2, p_qbx=12)
+        e_pt, e_q = _rel(gpu[n:], ref_pt), _rel(gpu[:n], ref_q)
+        print(f"point targets kind={kind} direct={direct} rel_err={e_pt:.3e} qbx={e_q:.3e}")
+        assert e_pt < tol and e_q < tol

@@ -10,6 +10,7 @@ partition the source set exactly once; that every list entry satisfies its defin
 |List 4 far| <= 63); and that every owned center's disk lies inside its box's target
 confinement region.
 """
+import copy
 import json
 import os
 
@@ -252,3 +253,64 @@ def test_box_orders_from_center_orders():
     from paper_1801_04070_amd import GQError
     with pytest.raises(GQError):
         q.set_qbx_orders(np.full(g.n_ctr, 13, np.int32))
+
+
+def _with_point_targets(g, n_pt=300, seed=4):
+    """Add conventional targets (both center slots -1) off the curve and around it."""
+    rng = np.random.default_rng(seed)
+    lo, hi = g.src_xy.min(0) - 0.3, g.src_xy.max(0) + 0.3
+    pts = rng.uniform(lo, hi, size=(n_pt, 2))
+    tgt_xy = np.concatenate([g.tgt_xy, pts])
+    tgt_ctr = np.concatenate([g.tgt_ctr, np.full((n_pt, 2), -1, np.int32)])
+    return pts, tgt_xy, tgt_ctr
+
+
+def test_point_targets_match_explicit_tiny_centers():
+    """A target with no center gets an internal center of radius 2^-40 * extent at its position,
+    numbered after the caller's centers: the same tree as passing those centers explicitly."""
+    g = gi.random_stars(n_curves=2, panels_per_curve=24, seed=9, box=6.0)
+    pts, tgt_xy, tgt_ctr = _with_point_targets(g)
+    q = QBXFMM(device=-1)
+    q.set_geometry(g.src_xy, g.src_nrm, g.src_w, g.ctr_xy, g.ctr_r, tgt_xy, tgt_ctr)
+    s = q.build(p_qbx=8, p_fmm=10, n_max=16)
+    assert s["n_point_targets"] == len(pts) and s["n_ctr"] == g.n_ctr
+    allxy = np.concatenate([g.src_xy, g.ctr_xy, tgt_xy])
+    ext = (allxy.max(0) - allxy.min(0)).max()
+    r_pt = np.ldexp(ext, -40)
+    e = copy.copy(g)
+    e.ctr_xy = np.concatenate([g.ctr_xy, pts])
+    e.ctr_r = np.concatenate([g.ctr_r, np.full(len(pts), r_pt)])
+    tc = tgt_ctr.copy()
+    tc[len(g.tgt_xy):, 0] = g.n_ctr + np.arange(len(pts))
+    e.tgt_xy, e.tgt_ctr = tgt_xy, tc
+    q2 = QBXFMM(device=-1)
+    q2.set_geometry_from(e)
+    q2.build(p_qbx=8, p_fmm=10, n_max=16)
+    for what in range(_lib.GQ_TREE_BOX_LEVEL, _lib.GQ_LIST4F + 1):
+        assert np.array_equal(q.tree_array(what), q2.tree_array(what)), what
+    T, _ = _check_tree(e, n_max=16)
+    # every point target's center sits in a leaf that contains it
+    owner = np.empty(e.n_ctr, np.int64)
+    rng_c = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    order_c = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    for b, (c0, c1) in enumerate(rng_c):
+        owner[order_c[c0:c1]] = b
+    assert all(T["leaf"][owner[g.n_ctr + j]] for j in range(len(pts)))
+    # orders: point-target centers never raise a box's order
+    q.set_qbx_orders(np.full(g.n_ctr, 4, np.int32))
+    bo = q.box_orders()
+    assert (bo[rng_c[:, 1] > rng_c[:, 0]] == 4).all()
+
+
+def test_point_targets_only():
+    g = gi.starfish_c1()
+    pts = np.array([[0.0, 0.0], [3.0, 1.0], [0.2, -0.1]])
+    q = QBXFMM(device=-1)
+    q.set_geometry(g.src_xy, g.src_nrm, g.src_w, np.zeros((0, 2)), np.zeros(0), pts,
+                   np.full((3, 2), -1, np.int32))
+    s = q.build(p_qbx=4, p_fmm=10)
+    assert s["n_ctr"] == 0 and s["n_point_targets"] == 3
+    from paper_1801_04070_amd import GQError
+    with pytest.raises(GQError):
+        q.set_geometry(g.src_xy, g.src_nrm, g.src_w, np.zeros((0, 2)), np.zeros(0),
+                       np.zeros((0, 2)), np.zeros((0, 2), np.int32))
