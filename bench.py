@@ -12,6 +12,9 @@ FP64 oracle at sampled targets):
   mixed_fp32_p16  FP32 box expansions at p_fmm 16 (tolerance 1e-6)
   fp64_p16        all-FP64 at p_fmm 16, the equal-accuracy reference for mixed_fp32_p16
   fp64_p40        all-FP64 at p_fmm 40 (tolerance 1e-12)
+  learned_orders  per-center QBX orders from the shipped network on an 8 x 8 lattice of nearly
+                  touching wavy curves (1048576 targets), against the smallest uniform order
+                  meeting the same tolerance (1e-10, true error via Green's formula)
 
 The JSON line also carries:
   roofline      the dominant kernel's achieved rate (algorithmic flops per launch / average launch
@@ -103,6 +106,80 @@ def measured_traffic(kernel: str):
     n = sum(d["dispatches"] for d in ks)
     return (round(sum(d["hbm_bytes"] * d["dispatches"] for d in ks) / n),
             "profiles/hbm_traffic_c2.json (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
+
+
+def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30):
+    """Learned per-center QBX orders against the smallest uniform order meeting the tolerance.
+
+    Workload: 8 x 8 lattice of wavy curves (seed 300) whose neighbours nearly touch (gap of four
+    expansion radii), 1024 panels x 16 nodes each = 1048576 on-surface targets and 2097152
+    centers, sources upsampled to 64 nodes per panel (4194304 sources). One step evaluates Green's
+    formula S(du/dn) - D(u), u = log|x - x0| with x0 outside the lattice; the exact value at the
+    targets is u / 2, so every error here is the true error relative to max |u|."""
+    import numpy as np
+    import torch
+    import gq_inputs as gi
+    from paper_1801_04070_amd import GQ_S_MINUS_D, QBXFMM, learned
+    model = learned.load_default()
+    if model is None:
+        return {"status": "no shipped order model"}
+    g = gi.wavy_lattice(nx=8, ny=8, panels_per_curve=1024, seed=300, gap_in_radii=4.0,
+                        src_order=64)
+    lo, hi = g.src_xy.min(0), g.src_xy.max(0)
+    x0 = (lo[0] - 0.7, 0.3 * lo[1] + 0.7 * hi[1])
+    sig, tau, u = gi.green_test_field(g, x0)
+    q = QBXFMM(0)
+    q.set_geometry_from(g)
+    t0 = time.perf_counter()
+    stats = q.build(p_qbx=max(model.candidates), p_fmm=p_fmm)
+    build_s = time.perf_counter() - t0
+    d1 = torch.as_tensor(sig, device="cuda:0")
+    d2 = torch.as_tensor(tau, device="cuda:0")
+    out = torch.empty((1, g.n_tgt), dtype=torch.float64, device="cuda:0")
+    scale = float(np.abs(u).max())
+    half_u = torch.as_tensor(0.5 * u, device="cuda:0")
+
+    def step():
+        q.eval(GQ_S_MINUS_D, d1, d2, out=out)
+
+    def log10_err():
+        step()
+        return float(torch.log10((out[0] - half_u).abs().max() / scale))
+
+    uniform = {}
+    p_u = None
+    for p in model.candidates:
+        q.set_qbx_orders(np.full(g.n_ctr, p, np.int32))
+        uniform[p] = round(log10_err(), 2)
+        if uniform[p] <= log10_tol:
+            p_u = p
+            break
+    if p_u is None:
+        return {"status": "no uniform candidate order meets the tolerance", "uniform": uniform}
+    ms_u, st_u = timer.run(q, step, steps, warmup)
+    t0 = time.perf_counter()
+    orders = learned.choose_orders(q, log10_tol, model)
+    torch.cuda.synchronize()
+    choose_s = time.perf_counter() - t0
+    e_l = round(log10_err(), 2)
+    ms_l, st_l = timer.run(q, step, steps, warmup)
+    hist = torch.bincount(orders.long(), minlength=max(model.candidates) + 1).cpu().numpy()
+    _, bd_u = per_stage(st_u, steps)
+    _, bd_l = per_stage(st_l, steps)
+    q.close()
+    v_u = g.n_tgt / (ms_u * 1e-3)
+    v_l = g.n_tgt / (ms_l * 1e-3)
+    return {"value": round(v_l, 1), "unit": "targets/s", "ms_per_step": round(ms_l, 4),
+            "uniform_value": round(v_u, 1), "uniform_ms_per_step": round(ms_u, 4),
+            "speedup_vs_uniform": round(v_l / v_u, 3), "log10_tol": log10_tol,
+            "p_uniform": p_u, "uniform_log10_err": uniform, "learned_log10_err": e_l,
+            "status": "ok" if e_l <= log10_tol else "FAILED",
+            "learned_order_histogram": {int(p): int(hist[p]) for p in model.candidates},
+            "choose_orders_s": round(choose_s, 3), "build_s": round(build_s, 1),
+            "stage_ms_per_step_uniform": bd_u, "stage_ms_per_step_learned": bd_l,
+            "steps": steps, "p_fmm": p_fmm,
+            "workload": "8x8 wavy lattice (gap 4 radii), 1048576 targets, 2097152 centers, "
+                        "4194304 upsampled sources, Green's formula, FP64"}
 
 
 def per_stage(stages, steps):
@@ -256,6 +333,10 @@ def main():
         variant("fp64_p16", "all FP64, p_fmm 16 (equal-accuracy reference for mixed_fp32_p16)",
                 p_fmm=16)
         variant("fp64_p40", "all FP64, p_fmm 40, tolerance 1e-12", p_fmm=40)
+        log("bench: learned orders on the wavy lattice")
+        variants["learned_orders"] = learned_variant(timer, max(2, args.steps // 4),
+                                                     max(1, args.warmup))
+        log(f"bench: learned orders: {variants['learned_orders'].get('speedup_vs_uniform')}x")
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,

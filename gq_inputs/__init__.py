@@ -278,9 +278,10 @@ def order_training_geometry(seed: int, order: int = 16, radius_factor: float = 0
 
     Per geometry: panels per curve ~ U{64..512}; per curve k ~ U{3..16} arms with amplitude
     a ~ U(0.05, min(0.3, 2.4 / k)); the gap between neighbouring outer circles is drawn
-    log-uniformly from 2.5 to 40 expansion radii, so some pairs of curves nearly touch. x0 sits
-    near the middle of the lattice, outside every curve (harmonic field for Green's formula).
-    Sources are upsampled to ``src_order`` nodes per panel.
+    log-uniformly from 2.5 to 40 expansion radii, so some pairs of curves nearly touch. The
+    charge point x0 (harmonic field for Green's formula) lies outside the lattice, 0.3 to 2 away
+    from its bounding box, so that the density is smooth on the scale of the panels and the QBX
+    error is governed by the geometry. Sources are upsampled to ``src_order`` nodes per panel.
     """
     rng = np.random.default_rng(seed)
     panels = int(rng.integers(64, 513))
@@ -297,10 +298,16 @@ def order_training_geometry(seed: int, order: int = 16, radius_factor: float = 0
     curves = [StarCurve(cx=i * pitch, cy=j * pitch, R=1.0, amp=a, arms=k, phase=ph)
               for (a, k, ph), (i, j) in zip(specs, [(0, 0), (1, 0), (0, 1), (1, 1)])]
     geom = discretize(curves, panels, order, radius_factor, src_order)
-    while True:
-        x0 = np.array([0.5 * pitch, 0.5 * pitch]) + rng.uniform(-0.3, 0.3, 2) * pitch
-        if all(math.hypot(x0[0] - c.cx, x0[1] - c.cy) > 1 + c.amp + 0.05 for c in curves):
-            return geom, x0
+    lo = geom.src_xy.min(axis=0)
+    hi = geom.src_xy.max(axis=0)
+    side = int(rng.integers(0, 4))
+    dist = float(rng.uniform(0.3, 2.0))
+    t = float(rng.uniform(0.0, 1.0))
+    if side < 2:   # left / right of the box
+        x0 = np.array([lo[0] - dist if side == 0 else hi[0] + dist, lo[1] + t * (hi[1] - lo[1])])
+    else:          # below / above
+        x0 = np.array([lo[0] + t * (hi[0] - lo[0]), lo[1] - dist if side == 2 else hi[1] + dist])
+    return geom, x0
 
 
 def point_charge_field(points: np.ndarray, normals: np.ndarray, x0):

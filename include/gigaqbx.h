@@ -161,6 +161,23 @@ gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders);
  * `dst` (NULL to query the count, always written to *count). */
 gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
 
+/*
+ * HIP graph of one evaluation, for small problems where kernel launches dominate (a build of the
+ * 1024-source starfish runs about 15 launches per kind). gq_graph_create validates like gq_eval,
+ * sizes the workspace, then captures exactly the gq_eval call with these arguments (pointers
+ * are baked in) on a library-owned stream; nothing is computed. gq_graph_launch enqueues one
+ * replay on the context's current stream. A graph becomes stale (GQ_ESTATE on launch) once the
+ * context's buffers change: gq_set_geometry, gq_build, gq_set_qbx_orders, or a gq_eval with more
+ * densities per batch than any before. Stage profiling must be off while capturing (GQ_ESTATE).
+ * Replays and eager calls on one context share its workspace: they must not run concurrently.
+ */
+typedef struct gq_graph gq_graph;
+gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
+                          int64_t ld1, const double *dens2, int64_t ld2, double *out,
+                          int64_t ld_out, gq_graph **graph);
+gq_status gq_graph_launch(gq_graph *graph);
+gq_status gq_graph_destroy(gq_graph *graph);
+
 /* Sizes of the tree and lists after gq_build (Sec. 4.3, and the stage costs of Table 2). */
 typedef struct {
   int64_t n_src, n_ctr, n_tgt;

@@ -89,13 +89,14 @@ gq_status gq_center_features(gq_ctx *ctx, float *feat);
 /* Per-center QBX orders from the network: features -> network -> predicted log10 QBX error
  * e_j = out_scale * y_j + out_shift for each candidate order cand[j] (n_cand ascending host
  * values in 0..p_qbx; the network's n_out must equal n_cand). Each center takes the smallest
- * candidate with e_j + margin <= log10_tol, else the largest candidate (the fallback for
- * centers the network cannot place, and for non-finite predictions). Orders go to the device
- * array `orders` (n_ctr int32, caller order); with apply != 0 they are then passed to
- * gq_set_qbx_orders. Temporary device buffers are allocated and freed here. Synchronous. */
+ * candidate with e_j + margins[j] <= log10_tol (margins: n_cand host values, NULL for zeros),
+ * else the largest candidate (the fallback for centers the network cannot place, and for
+ * non-finite predictions). Orders go to the device array `orders` (n_ctr int32, caller order);
+ * with apply != 0 they are then passed to gq_set_qbx_orders. Temporary device buffers are
+ * allocated and freed here. Synchronous. */
 gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n_cand,
-                            double out_scale, double out_shift, double log10_tol, double margin,
-                            int32_t *orders, int apply);
+                            double out_scale, double out_shift, double log10_tol,
+                            const double *margins, int32_t *orders, int apply);
 
 #ifdef __cplusplus
 }

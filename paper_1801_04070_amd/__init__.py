@@ -203,6 +203,23 @@ class QBXFMM:
                     out[(k + 1, name)] = (ms[i], cnt[i])
         return out
 
+    def graph(self, kind: int, dens1, dens2=None, out=None):
+        """Capture ``eval(kind, dens1, dens2, out)`` into a HIP graph (see gq_graph_create);
+        returns (EvalGraph, out). The tensors must stay alive while the graph is used."""
+        import torch
+        d1 = dens1.reshape(-1, dens1.shape[-1]) if dens1.dim() == 1 else dens1
+        d2 = None if dens2 is None else (dens2.reshape(-1, dens2.shape[-1]) if dens2.dim() == 1
+                                         else dens2)
+        if d1.stride(-1) != 1 or (d2 is not None and d2.stride(-1) != 1):
+            raise ValueError("densities must have unit stride along a row")
+        if out is None:
+            out = torch.empty((d1.shape[0], self.n_tgt), dtype=torch.float64, device=d1.device)
+        h = C.c_void_p()
+        self._check(self._L.gq_graph_create(self._h, kind, d1.shape[0], _ptr(d1), d1.stride(0),
+                                            _ptr(d2), 0 if d2 is None else d2.stride(0),
+                                            _ptr(out), out.stride(0), C.byref(h)))
+        return EvalGraph(self, h, (d1, d2, out)), out
+
     def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
         """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or
         (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt)."""
@@ -223,3 +240,24 @@ class QBXFMM:
         self._check(fn(self._h, kind, n_dens, _ptr(d1), d1.stride(0), _ptr(d2),
                        0 if d2 is None else d2.stride(0), _ptr(out), out.stride(0)))
         return out[0] if squeeze else out
+
+
+class EvalGraph:
+    """A captured evaluation; ``launch()`` replays it on the context's stream."""
+
+    def __init__(self, fmm: QBXFMM, handle, keep):
+        self._fmm, self._h, self._keep = fmm, handle, keep
+
+    def launch(self):
+        self._fmm._check(self._fmm._L.gq_graph_launch(self._h))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._fmm._L.gq_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -47,7 +47,7 @@ GQ_N_STAGES = len(GQ_STAGE_NAMES)
 EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
-            "gq_last_error"]
+            "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_last_error"]
 
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
@@ -77,6 +77,9 @@ def load(path: str = LIB_PATH):
     L.gq_get_box_orders.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.gq_set_profiling.argtypes = [vp, i32]
     L.gq_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.gq_graph_create.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64, C.POINTER(C.c_void_p)]
+    L.gq_graph_launch.argtypes = [vp]
+    L.gq_graph_destroy.argtypes = [vp]
     L.gq_last_error.argtypes = [vp]
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -98,8 +101,8 @@ def load(path: str = LIB_PATH):
     L.gq_mlp_stream.argtypes = [vp]
     L.gq_mlp_stream.restype = C.c_void_p
     L.gq_center_features.argtypes = [vp, vp]
-    L.gq_orders_predict.argtypes = [vp, vp, vp, i32, C.c_double, C.c_double, C.c_double,
-                                    C.c_double, vp, i32]
+    L.gq_orders_predict.argtypes = [vp, vp, vp, i32, C.c_double, C.c_double, C.c_double, vp,
+                                    vp, i32]
     for name in EXPORTED_MLP:
         if name not in ("gq_mlp_last_error", "gq_mlp_param_count", "gq_mlp_stream"):
             getattr(L, name).restype = C.c_int

@@ -30,6 +30,7 @@ gq_status fail(gq_ctx *ctx, gq_status st, const std::string &msg) {
   } while (0)
 
 void free_workspace(gq_ctx *ctx) {
+  ctx->generation++;
   if (ctx->device >= 0) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
@@ -43,6 +44,7 @@ void free_workspace(gq_ctx *ctx) {
 
 void free_device(gq_ctx *ctx) {
   free_workspace(ctx);
+  ctx->generation++;
   if (ctx->device >= 0) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (void *p : ctx->allocations) (void)hipFree(p);
@@ -124,6 +126,7 @@ gq_status upload_near_work(gq_ctx *ctx) {
   const int64_t nb = t.n_boxes();
   for (void *p : ctx->nw_allocations) (void)hipFree(p);
   ctx->nw_allocations.clear();
+  ctx->generation++;
   std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
   std::vector<int64_t> box_src_off(nb, 0), box_src_len(nb, 0);
   int64_t rows = 0;
@@ -355,8 +358,22 @@ bool finite_all(const std::vector<double> &v) {
   return true;
 }
 
-gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
-                      const double *dens2, int64_t ld2, double *out, int64_t ld_out, bool direct) {
+gq_status launch_batches(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                         const double *dens2, int64_t ld2, double *out, int64_t ld_out,
+                         bool direct) {
+  const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
+  for (int64_t j = 0; j < n_dens; j += batch) {
+    const int nd = (int)std::min<int64_t>(batch, n_dens - j);
+    hipError_t e = gq::run_eval(ctx, kind, dens1 + j * ld1, ld1, dens2 ? dens2 + j * ld2 : nullptr,
+                                ld2, out + j * ld_out, ld_out, nd, direct);
+    if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  return GQ_OK;
+}
+
+gq_status check_eval_args(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
+                          int64_t ld1, const double *dens2, int64_t ld2, const double *out,
+                          int64_t ld_out) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context cannot evaluate");
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_eval before a successful gq_build");
@@ -368,16 +385,17 @@ gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1
     return fail(ctx, GQ_EINVAL, "dens2 must be given exactly for GQ_S_MINUS_D");
   if (ld1 < ctx->ns || (dens2 && ld2 < ctx->ns) || ld_out < ctx->nt)
     return fail(ctx, GQ_EINVAL, "leading dimension smaller than the row length");
+  return GQ_OK;
+}
+
+gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                      const double *dens2, int64_t ld2, double *out, int64_t ld_out, bool direct) {
+  GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
+  if (n_dens == 0) return GQ_OK;
   GQ_HIP(ctx, hipSetDevice(ctx->device));
   const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
   GQ_TRY(ensure_workspace(ctx, batch));
-  for (int64_t j = 0; j < n_dens; j += batch) {
-    const int nd = (int)std::min<int64_t>(batch, n_dens - j);
-    hipError_t e = gq::run_eval(ctx, kind, dens1 + j * ld1, ld1, dens2 ? dens2 + j * ld2 : nullptr,
-                                ld2, out + j * ld_out, ld_out, nd, direct);
-    if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-  }
-  return GQ_OK;
+  return launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, direct);
 }
 
 }  // namespace
@@ -440,6 +458,7 @@ gq_status gq_destroy(gq_ctx *ctx) {
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   }
   free_device(ctx);
   if (ctx->device >= 0) {
@@ -593,6 +612,78 @@ gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, in
 gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
                          const double *dens2, int64_t ld2, double *out, int64_t ld_out) {
   return eval_common(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, true);
+}
+
+struct gq_graph {
+  gq_ctx *ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t generation = 0;
+};
+
+gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                          const double *dens2, int64_t ld2, double *out, int64_t ld_out,
+                          gq_graph **graph) {
+  if (!graph) return fail(ctx, GQ_EINVAL, "null graph output");
+  *graph = nullptr;
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (n_dens <= 0) return fail(ctx, GQ_EINVAL, "a graph needs n_dens >= 1");
+  GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
+  if (ctx->profiling) return fail(ctx, GQ_ESTATE, "disable stage profiling before capturing a graph");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  gq_status st = GQ_OK;
+  GQ_TRY(ensure_workspace(ctx, (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch)));
+  if (!ctx->capture) GQ_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  // capture on the library's own stream (the caller's may be the null stream, which cannot be
+  // captured); the side stream joins through the fork/join events
+  if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  hipStream_t saved = ctx->stream;
+  ctx->stream = ctx->capture;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, false);
+    e = hipStreamEndCapture(ctx->capture, &g);
+  }
+  ctx->stream = saved;
+  if (e != hipSuccess || st != GQ_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != GQ_OK ? st : fail(ctx, GQ_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  gq_graph *h = new (std::nothrow) gq_graph();
+  if (!h) {
+    (void)hipGraphDestroy(g);
+    return fail(ctx, GQ_ENOMEM, "graph handle");
+  }
+  h->ctx = ctx;
+  h->graph = g;
+  h->generation = ctx->generation;
+  e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete h;
+    return fail(ctx, GQ_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *graph = h;
+  return GQ_OK;
+}
+
+gq_status gq_graph_launch(gq_graph *graph) {
+  if (!graph || !graph->ctx) return GQ_EINVAL;
+  gq_ctx *ctx = graph->ctx;
+  if (graph->generation != ctx->generation)
+    return fail(ctx, GQ_ESTATE, "graph is stale: the context's buffers changed since capture");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  GQ_HIP(ctx, hipGraphLaunch(graph->exec, ctx->stream));
+  return GQ_OK;
+}
+
+gq_status gq_graph_destroy(gq_graph *graph) {
+  if (!graph) return GQ_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return GQ_OK;
 }
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {

@@ -108,6 +108,10 @@ struct gq_ctx {
   int ws_batch = 0;
   double build_ms = 0;
 
+  // bumped whenever device buffers a captured graph refers to are freed or replaced
+  uint64_t generation = 0;
+  hipStream_t capture = nullptr;     // library stream used only to capture evaluation graphs
+
   // stage profiling (HIP events on the context stream)
   bool profiling = false;
   int cur_kind = 1;

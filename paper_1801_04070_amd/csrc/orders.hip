@@ -105,17 +105,18 @@ __global__ void __launch_bounds__(256) k_center_features(
   if (!ok) *overflow = 1;  // vector store; only ever set to 1
 }
 
-// orders[c] = smallest candidate whose predicted log10 error (scale y + shift) plus the margin is
-// at most log10_tol; the largest candidate otherwise (also for a non-finite prediction).
+// orders[c] = smallest candidate j whose predicted log10 error (scale y_j + shift) is at most
+// limit[j] (the tolerance less that candidate's margin); the largest candidate otherwise (also
+// for non-finite predictions).
 __global__ void k_choose_orders(int64_t n, int n_out, const float *__restrict__ y, float scale,
-                                float shift, float limit, const int32_t *__restrict__ cand,
-                                int32_t *__restrict__ orders) {
+                                float shift, const float *__restrict__ limit,
+                                const int32_t *__restrict__ cand, int32_t *__restrict__ orders) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   int32_t q = cand[n_out - 1];
   for (int j = 0; j < n_out; ++j) {
     const float e = fmaf(scale, y[c * n_out + j], shift);
-    if (e == e && e <= limit) { q = cand[j]; break; }
+    if (e == e && e <= limit[j]) { q = cand[j]; break; }
   }
   orders[c] = q;
 }
@@ -164,8 +165,8 @@ gq_status gq_center_features(gq_ctx *ctx, float *feat) {
 }
 
 gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n_cand,
-                            double out_scale, double out_shift, double log10_tol, double margin,
-                            int32_t *orders, int apply) {
+                            double out_scale, double out_shift, double log10_tol,
+                            const double *margins, int32_t *orders, int apply) {
   if (!ctx) return GQ_EINVAL;
   if (!net || !cand || n_cand < 1 || !orders) return ofail(ctx, GQ_EINVAL, "null argument or no candidates");
   int n_in = 0, n_out = 0;
@@ -176,21 +177,28 @@ gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n
   for (int j = 0; j < n_cand; ++j)
     if (cand[j] < 0 || cand[j] > ctx->params.p_qbx || (j && cand[j] <= cand[j - 1]))
       return ofail(ctx, GQ_EINVAL, "candidate orders must ascend within 0..p_qbx");
-  if (!std::isfinite(out_scale) || !std::isfinite(out_shift) || !std::isfinite(log10_tol) ||
-      !std::isfinite(margin))
-    return ofail(ctx, GQ_EINVAL, "non-finite scale, shift, tolerance or margin");
+  if (!std::isfinite(out_scale) || !std::isfinite(out_shift) || !std::isfinite(log10_tol))
+    return ofail(ctx, GQ_EINVAL, "non-finite scale, shift or tolerance");
+  std::vector<float> limit(n_cand);
+  for (int j = 0; j < n_cand; ++j) {
+    const double m = margins ? margins[j] : 0.0;
+    if (!std::isfinite(m)) return ofail(ctx, GQ_EINVAL, "non-finite margin");
+    limit[j] = (float)(log10_tol - m);
+  }
   const int64_t nc = ctx->nc_user;
   if (nc == 0) return apply ? gq_set_qbx_orders(ctx, GQ_MEM_DEVICE, nullptr) : GQ_OK;
   GQ_ORD_HIP(ctx, hipSetDevice(ctx->device));
-  float *feat = nullptr, *y = nullptr;
+  float *feat = nullptr, *y = nullptr, *dlimit = nullptr;
   int32_t *dcand = nullptr;
   gq_status st = GQ_OK;
   if (hipMalloc(&feat, sizeof(float) * nc * GQ_N_FEATURES) != hipSuccess ||
       hipMalloc(&y, sizeof(float) * nc * n_cand) != hipSuccess ||
-      hipMalloc(&dcand, sizeof(int32_t) * n_cand) != hipSuccess)
+      hipMalloc(&dcand, sizeof(int32_t) * n_cand) != hipSuccess ||
+      hipMalloc(&dlimit, sizeof(float) * n_cand) != hipSuccess)
     st = ofail(ctx, GQ_ENOMEM, "hipMalloc (order prediction)");
-  if (st == GQ_OK && hipMemcpy(dcand, cand, sizeof(int32_t) * n_cand, hipMemcpyHostToDevice) != hipSuccess)
-    st = ofail(ctx, GQ_EHIP, "hipMemcpy (candidates)");
+  if (st == GQ_OK && (hipMemcpy(dcand, cand, sizeof(int32_t) * n_cand, hipMemcpyHostToDevice) != hipSuccess ||
+                      hipMemcpy(dlimit, limit.data(), sizeof(float) * n_cand, hipMemcpyHostToDevice) != hipSuccess))
+    st = ofail(ctx, GQ_EHIP, "hipMemcpy (candidates, limits)");
   if (st == GQ_OK) st = gq_center_features(ctx, feat);
   // the network runs on its own stream: gq_center_features returned after its stream drained
   if (st == GQ_OK) {
@@ -200,8 +208,7 @@ gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n
   if (st == GQ_OK) {
     hipStream_t ns = static_cast<hipStream_t>(gq_mlp_stream(net));
     hipLaunchKernelGGL(k_choose_orders, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, ns, nc,
-                       n_cand, y, (float)out_scale, (float)out_shift, (float)(log10_tol - margin),
-                       dcand, orders);
+                       n_cand, y, (float)out_scale, (float)out_shift, dlimit, dcand, orders);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(ns);
     if (e != hipSuccess) st = ofail(ctx, GQ_EHIP, std::string("order choice: ") + hipGetErrorString(e));
@@ -209,6 +216,7 @@ gq_status gq_orders_predict(gq_ctx *ctx, gq_mlp *net, const int32_t *cand, int n
   (void)hipFree(feat);
   (void)hipFree(y);
   (void)hipFree(dcand);
+  (void)hipFree(dlimit);
   if (st == GQ_OK && apply) st = gq_set_qbx_orders(ctx, GQ_MEM_DEVICE, orders);
   return st;
 }

@@ -12,13 +12,14 @@ module marshals arguments, and its trainer drives the library's own kernels:
 
 * training data: for random 2 x 2 lattices of stars (``gq_inputs.order_training_geometry``,
   sources upsampled to 64 Gauss nodes per 16-node panel, as QBX needs) the library's FMM
-  (p_fmm 40) evaluates Green's formula S(du/dn) - D(u) for u = log|x - x0| (x0 outside every
-  curve, often close to one), one target per center at its own node, at every candidate order.
+  (p_fmm 40) evaluates Green's formula S(du/dn) - D(u) for u = log|x - x0| (x0 outside the
+  lattice), one target per center at its own node, at every candidate order.
   The exact one-sided limits are u on the interior side and 0 on the exterior side, so the
   label of (center, order) is the log10 of its true error relative to max |u| at the targets;
 * training: Adam on the weighted squared error of the scaled log10 errors;
-* calibration: the margin is the smallest one for which, on held-out geometries, no center's
-  chosen order exceeds the tolerance (checked at log10 tolerances -6, -8 and -10).
+* calibration: per candidate order j and tolerance, the margin m_j is the smallest (in steps of
+  0.05) for which no held-out center with prediction_j + m_j <= tol has a true error above the
+  tolerance (calibrated at log10 tolerances -8, -10 and -12).
 """
 from __future__ import annotations
 
@@ -35,9 +36,9 @@ WEIGHTS = os.path.join(HERE, "data", "order_mlp.npz")
 
 CANDIDATES = (4, 6, 8, 10, 12, 16)
 OUT_SCALE, OUT_SHIFT = 4.0, -10.0      # predicted log10 error = OUT_SCALE * y + OUT_SHIFT
-LOG10_FLOOR = -16.0
+LOG10_FLOOR = -13.0                    # labels below 1e-13 carry only rounding noise
 N_HIDDEN = 64
-CAL_TOLS = (-6.0, -8.0, -10.0)
+CAL_TOLS = (-8.0, -10.0, -12.0)
 
 
 def center_features(fmm: QBXFMM):
@@ -68,7 +69,8 @@ class OrderModel:
         meta = json.loads(str(z["meta"]))
         return cls(z["params"], int(z["n_hidden"]), tuple(z["candidates"].tolist()),
                    float(z["out_scale"]), float(z["out_shift"]),
-                   {float(k): float(v) for k, v in meta.pop("margins").items()}, meta)
+                   {float(k): [float(x) for x in v] for k, v in meta.pop("margins").items()},
+                   meta)
 
     def save(self, path: str = WEIGHTS) -> None:
         os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -86,31 +88,32 @@ class OrderModel:
             self._nets[device] = net
         return self._nets[device]
 
-    def margin(self, log10_tol: float) -> float:
-        """Calibrated margin at this tolerance, else the largest calibrated one (1 if none)."""
+    def margin(self, log10_tol: float) -> list:
+        """Per-candidate margins calibrated at this tolerance; for another tolerance those of the
+        nearest calibrated one at or below it (the tightest if none is below)."""
+        n = len(self.candidates)
         if not self.margins:
-            return 1.0
-        for k, v in self.margins.items():
-            if abs(k - log10_tol) < 1e-6:
-                return v
-        return max(self.margins.values())
+            return [1.0] * n
+        ks = sorted(self.margins)
+        below = [k for k in ks if k <= log10_tol + 1e-9]
+        return list(self.margins[below[-1] if below else ks[0]])
 
     def predict_log10_errors(self, fmm: QBXFMM):
         """(n_ctr, n_candidates) FP32 device tensor of predicted log10 QBX errors."""
         y = self.network(fmm.device).forward(center_features(fmm))
         return y * self.out_scale + self.out_shift
 
-    def choose_orders(self, fmm: QBXFMM, log10_tol: float, margin: float | None = None,
-                      apply: bool = True):
+    def choose_orders(self, fmm: QBXFMM, log10_tol: float, margin=None, apply: bool = True):
         """Per-center orders (int32 device tensor); applied to ``fmm`` unless apply=False."""
         import torch
-        m = self.margin(log10_tol) if margin is None else float(margin)
+        m = np.asarray(self.margin(log10_tol) if margin is None else
+                       np.broadcast_to(margin, (len(self.candidates),)), dtype=np.float64).copy()
         net = self.network(fmm.device)
         cand = np.array(self.candidates, np.int32)
         out = torch.empty(fmm.n_ctr, dtype=torch.int32, device=f"cuda:{fmm.device}")
         fmm._check(fmm._L.gq_orders_predict(fmm._h, net._h, cand.ctypes.data, len(cand),
-                                            self.out_scale, self.out_shift, float(log10_tol), m,
-                                            _ptr(out), int(apply)))
+                                            self.out_scale, self.out_shift, float(log10_tol),
+                                            m.ctypes.data, _ptr(out), int(apply)))
         return out
 
 
@@ -178,25 +181,49 @@ def dataset(seeds, device: int = 0, log=None):
     return torch.cat(xs), torch.cat(ts)
 
 
-def calibrate(pred, true, tols=CAL_TOLS, candidates=CANDIDATES):
-    """Smallest margin (0.05 steps) with no held-out center whose chosen order misses the
-    tolerance, among centers whose largest candidate order meets it."""
-    import torch
+def calibrate(pred, true, tols=CAL_TOLS, step=0.05, max_margin=6.0):
+    """Per-candidate margins: for each tolerance and order j the smallest m (multiple of `step`)
+    such that no held-out row with pred_j + m <= tol has true_j > tol."""
     out = {}
     for tol in tols:
-        ok_at_max = true[:, -1] <= tol
-        p, t = pred[ok_at_max], true[ok_at_max]
-        m = 0.0
-        while m < 6.0:
-            fits = p + m <= tol
-            first = torch.where(fits.any(1), fits.float().argmax(1),
-                                torch.full_like(fits[:, 0], len(candidates) - 1, dtype=torch.long))
-            miss = t.gather(1, first[:, None])[:, 0] > tol
-            if not bool(miss.any()):
-                break
-            m += 0.05
-        out[float(tol)] = round(m, 2)
+        ms = []
+        for j in range(pred.shape[1]):
+            p, t = pred[:, j], true[:, j]
+            m = 0.0
+            while m < max_margin:
+                sel = p + m <= tol
+                if not bool((t[sel] > tol).any()):
+                    break
+                m = round(m + step, 10)
+            ms.append(round(m, 2))
+        out[float(tol)] = ms
     return out
+
+
+def choice_report(pred, true, margins, candidates=CANDIDATES):
+    """On held-out rows, per tolerance: among rows whose largest candidate meets the tolerance,
+    the miss rate and worst log10 error of the chosen orders; the share of rows no candidate can
+    meet; the mean chosen order, the mean of the smallest order that truly meets the tolerance,
+    and the smallest uniform order whose worst error meets it."""
+    import torch
+    cand = torch.tensor(candidates, device=pred.device)
+    rep = {}
+    for tol, m in margins.items():
+        fits = pred + torch.tensor(m, device=pred.device) <= tol
+        last = torch.full_like(fits[:, 0], len(candidates) - 1, dtype=torch.long)
+        j = torch.where(fits.any(1), fits.float().argmax(1), last)
+        err = true.gather(1, j[:, None])[:, 0]
+        ok = true <= tol
+        best = torch.where(ok.any(1), ok.float().argmax(1), last)
+        feas = ok[:, -1]
+        uni = [c for c, col in zip(candidates, true.T) if bool((col[feas] <= tol).all())]
+        rep[str(tol)] = {"miss_rate": float((err[feas] > tol).float().mean()),
+                         "worst_log10_err": round(float(err[feas].max()), 2),
+                         "infeasible_rate": float((~feas).float().mean()),
+                         "mean_order": round(float(cand[j].float().mean()), 3),
+                         "mean_best_order": round(float(cand[best].float().mean()), 3),
+                         "uniform_order": uni[0] if uni else None}
+    return rep
 
 
 def train(train_seeds=range(1000, 1180), val_seeds=range(1180, 1200), steps: int = 4000,
@@ -228,11 +255,12 @@ def train(train_seeds=range(1000, 1180), val_seeds=range(1180, 1200), steps: int
     model = OrderModel(net.get_params(), N_HIDDEN, CANDIDATES, OUT_SCALE, OUT_SHIFT)
     pv = net.forward(xv) * OUT_SCALE + OUT_SHIFT
     model.margins = calibrate(pv, ev)
+    choice = choice_report(pv, ev, model.margins)
     rmse = ((pv - ev) ** 2).mean(0).sqrt().tolist()
     report = {"train_rows": int(n), "val_rows": int(xv.shape[0]), "steps": steps,
               "batch": batch, "lr": lr, "seconds_data": round(t_data, 1),
               "seconds_train": round(t_train, 1), "val_rmse_log10": [round(v, 3) for v in rmse],
-              "margins": model.margins, "loss_history": hist,
+              "margins": model.margins, "validation_choice": choice, "loss_history": hist,
               "train_seeds": [int(min(train_seeds)), int(max(train_seeds))],
               "val_seeds": [int(min(val_seeds)), int(max(val_seeds))]}
     model.meta = {k: v for k, v in report.items() if k != "loss_history"}

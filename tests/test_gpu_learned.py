@@ -1,0 +1,91 @@
+"""Learned per-center QBX orders: the shipped network against uniform orders on held-out geometry.
+
+Geometry: a 3 x 3 lattice of wavy curves (seed 301, not a training seed) whose neighbours nearly
+touch (gap of three expansion radii), 16-node panels with sources upsampled to 64 nodes. Field:
+Green's formula S(du/dn) - D(u) for u = log|x - x0| with x0 outside the lattice, so the exact value
+at each on-surface target (average of the two one-sided limits) is u / 2. Errors are relative to
+max |u| over the targets, FMM at p_fmm 30 (its own error is far below the tolerance).
+
+The gain: the learned orders meet the tolerance while their mean effective order (each center
+runs at its box's order) is below the smallest uniform order that meets it.
+"""
+import numpy as np
+import pytest
+
+import gq_inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+LOG10_TOLS = (-10.0, -12.0)
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    from paper_1801_04070_amd import QBXFMM
+    g = gi.wavy_lattice(nx=3, ny=3, panels_per_curve=128, seed=301, gap_in_radii=3.0,
+                        src_order=64)
+    lo, hi = g.src_xy.min(0), g.src_xy.max(0)
+    x0 = np.array([lo[0] - 0.7, 0.3 * lo[1] + 0.7 * hi[1]])   # outside the lattice
+    sig, tau, u = gi.green_test_field(g, x0)
+    q = QBXFMM(0)
+    q.set_geometry_from(g)
+    q.build(p_qbx=16, p_fmm=30)
+    d1 = torch.from_numpy(sig).cuda()
+    d2 = torch.from_numpy(tau).cuda()
+    return g, q, d1, d2, u
+
+
+def _err(q, d1, d2, u):
+    v = q.eval(3, d1, d2).cpu().numpy()
+    return float(np.log10(np.abs(v - 0.5 * u).max() / np.abs(u).max()))
+
+
+def _effective_orders(q):
+    from paper_1801_04070_amd import _lib
+    bo = q.box_orders()
+    rng = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    order = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    eff = np.empty(len(order), np.int64)
+    for b, (c0, c1) in enumerate(rng):
+        eff[order[c0:c1]] = bo[b]
+    return eff
+
+
+@pytest.mark.parametrize("log10_tol", LOG10_TOLS)
+def test_learned_orders_meet_tolerance_below_uniform_cost(case, log10_tol):
+    from paper_1801_04070_amd import learned
+    g, q, d1, d2, u = case
+    model = learned.load_default()
+    assert model is not None, "the shipped order model is missing"
+    errs = {}
+    for p in model.candidates:
+        q.set_qbx_orders(np.full(g.n_ctr, p, np.int32))
+        errs[p] = _err(q, d1, d2, u)
+    print("uniform log10 errors:", errs)
+    meeting = [p for p in model.candidates if errs[p] <= log10_tol]
+    assert meeting, errs
+    p_uni = meeting[0]
+    orders = learned.choose_orders(q, log10_tol, model).cpu().numpy()
+    e_learned = _err(q, d1, d2, u)
+    eff = _effective_orders(q)[:g.n_ctr]
+    print(f"uniform p={p_uni}; learned: log10 err {e_learned:.2f}, mean center order "
+          f"{orders.mean():.2f}, mean effective order {eff.mean():.2f}, "
+          f"histogram {np.bincount(orders, minlength=17)[list(model.candidates)]}")
+    assert e_learned <= log10_tol
+    assert eff.mean() < p_uni
+
+
+def test_fallback_to_uniform_orders(case):
+    """A model whose candidates exceed the build's p_qbx is not used: uniform build order."""
+    from paper_1801_04070_amd import learned
+    g, q, d1, d2, u = case
+    model = learned.load_default()
+    assert model is not None
+    too_high = learned.OrderModel(model.params, model.n_hidden, (4, 6, 8, 10, 12, 20),
+                                  model.out_scale, model.out_shift, model.margins)
+    q.set_qbx_orders(np.full(g.n_ctr, 4, np.int32))
+    assert learned.choose_orders(q, LOG10_TOLS[0], too_high) is None
+    from paper_1801_04070_amd import _lib
+    rng = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    assert (q.box_orders()[rng[:, 1] > rng[:, 0]] == 16).all()

@@ -51,13 +51,13 @@ def _constant_net(levels):
 
 
 def _predict(fmm, net, cand, scale, shift, tol, margin, apply=0):
-    import ctypes as C
     import torch
     from paper_1801_04070_amd import _ptr
     out = torch.empty(fmm.n_ctr, dtype=torch.int32, device="cuda:0")
     c = np.asarray(cand, np.int32)
+    m = np.broadcast_to(np.asarray(margin, np.float64), (len(c),)).copy()
     st = fmm._L.gq_orders_predict(fmm._h, net._h, c.ctypes.data, len(c), scale, shift, tol,
-                                  margin, _ptr(out), apply)
+                                  m.ctypes.data, _ptr(out), apply)
     return st, out.cpu().numpy()
 
 
@@ -71,6 +71,9 @@ def test_order_choice_rule():
                               (-20.0, 0.0, 16), (0.0, 0.0, 4)]:
         st, o = _predict(fmm, net, cand, 2.0, -10.0, tol, margin)
         assert st == 0 and np.all(o == want), (tol, margin, o[:4])
+    # per-candidate margins: 8 and 10 need a wider margin than 12 -> 12 at tolerance -9
+    st, o = _predict(fmm, net, cand, 2.0, -10.0, -9.0, [0.0, 0.0, 4.0, 2.0, 0.5, 0.0])
+    assert st == 0 and np.all(o == 12)
     # non-finite predictions fall back to the largest candidate
     net_nan = _constant_net([float("nan")] * 6)
     st, o = _predict(fmm, net_nan, cand, 2.0, -10.0, -6.0, 0.0)
@@ -96,6 +99,8 @@ def test_order_choice_errors():
     assert _predict(fmm, _constant_net([0.0] * 5), (4, 6, 8, 10, 12, 12), 1.0, 0.0, -6.0,
                     0.0)[0] == -1
     assert _predict(fmm, net, (2, 4, 6, 8, 10, 12), 1.0, float("inf"), -6.0, 0.0)[0] == -1
+    assert _predict(fmm, net, (2, 4, 6, 8, 10, 12), 1.0, 0.0, -6.0,
+                    [0, 0, float("nan"), 0, 0, 0])[0] == -1
     # the context is still usable after the rejected calls
     ones = torch.ones(g.src_w.shape[0], dtype=torch.float64, device="cuda:0")
     assert torch.isfinite(fmm.eval(GQ_S, ones)).all()

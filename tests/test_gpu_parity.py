@@ -288,3 +288,30 @@ def test_point_targets_match_oracle(kind):
         e_pt, e_q = _rel(gpu[n:], ref_pt), _rel(gpu[:n], ref_q)
         print(f"point targets kind={kind} direct={direct} rel_err={e_pt:.3e} qbx={e_q:.3e}")
         assert e_pt < tol and e_q < tol
+
+
+@pytest.mark.parametrize("kind", [1, 3])
+def test_graph_replays_match_eager(c1, kind):
+    """A captured evaluation replayed several times, with other eager evaluations (sharing the
+    workspace) and host synchronisations between replays, reproduces the eager result exactly."""
+    mu, mu2 = _densities(c1, 4)
+    q, _ = _ctx(c1, p_qbx=8, p_fmm=20)
+    d1 = _dev(np.stack([mu, 2 * mu]))
+    d2 = _dev(np.stack([mu2, -mu2])) if kind == 3 else None
+    eager = q.eval(kind, d1, d2).cpu().numpy()
+    g, out = q.graph(kind, d1, d2)
+    other = _dev(gi.fourier_density(c1, seed=77))
+    for rep in range(4):
+        out.fill_(float("nan"))
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), rep
+        # eager work between replays, on the same workspace
+        q.eval(1, other)
+        torch.cuda.synchronize()
+    # the graph goes stale when the buffers change
+    q.set_qbx_orders(np.full(c1.n_ctr, 4, np.int32))
+    from paper_1801_04070_amd import GQError
+    with pytest.raises(GQError):
+        g.launch()
+    g.close()
