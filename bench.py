@@ -12,9 +12,13 @@ FP64 oracle at sampled targets):
   mixed_fp32_p16  FP32 box expansions at p_fmm 16 (tolerance 1e-6)
   fp64_p16        all-FP64 at p_fmm 16, the equal-accuracy reference for mixed_fp32_p16
   fp64_p40        all-FP64 at p_fmm 40 (tolerance 1e-12)
-  learned_orders  per-center QBX orders from the shipped network on an 8 x 8 lattice of nearly
-                  touching wavy curves (1048576 targets), against the smallest uniform order
-                  meeting the same tolerance (1e-10, true error via Green's formula)
+  ragged_32       32 independent stars (1024..65536 nodes) in one batched context (one forest)
+                  against 32 contexts evaluated one after another
+  graph           the headline step replayed from captured HIP graphs
+  learned_orders_1e-10, _1e-12
+                  per-center QBX orders from the shipped network on an 8 x 8 lattice of nearly
+                  touching wavy curves (196608 targets), against the smallest uniform order
+                  meeting the same tolerance (true error via Green's formula)
 
 The JSON line also carries:
   roofline      the dominant kernel's achieved rate (algorithmic flops per launch / average launch
@@ -86,6 +90,18 @@ class Timer:
         q.set_profiling(False)
         return ms, stages
 
+    def run_plain(self, step, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        self.a.record()
+        for _ in range(steps):
+            step()
+        self.b.record()
+        torch.cuda.synchronize()
+        return self.a.elapsed_time(self.b) / steps
+
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` (mean over its template instances) from the committed
@@ -108,14 +124,70 @@ def measured_traffic(kernel: str):
             "profiles/hbm_traffic_c2.json (FETCH_SIZE + WRITE_SIZE, copy-calibrated)")
 
 
-def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30):
+def ragged_variant(timer, steps, warmup, n_geoms=32, p_qbx=12, p_fmm=30):
+    """32 separate star geometries with log-uniform node counts 1024..65536 (seed 200): one
+    batched context (a forest: every stage launched once for all geometries) against one context
+    per geometry evaluated one after another. One step: S and D of one density per geometry."""
+    import numpy as np
+    import torch
+    import gq_inputs as gi
+    from paper_1801_04070_amd import GQ_D, GQ_S, QBXFMM
+    geoms = gi.ragged_star_batch(n_geoms=n_geoms, seed=200)
+    dens = [gi.fourier_density(g, seed=200 + i) for i, g in enumerate(geoms)]
+    kw = dict(p_qbx=p_qbx, p_fmm=p_fmm)
+    qb = QBXFMM(0)
+    qb.set_geometry_batch(geoms)
+    t0 = time.perf_counter()
+    qb.build(**kw)
+    build_s = time.perf_counter() - t0
+    db = torch.as_tensor(np.concatenate(dens), device="cuda:0")
+    ob = torch.empty((2, 1, qb.n_tgt), dtype=torch.float64, device="cuda:0")
+
+    def step_b():
+        qb.eval(GQ_S, db, out=ob[0])
+        qb.eval(GQ_D, db, out=ob[1])
+
+    ms_b, st_b = timer.run(qb, step_b, steps, warmup)
+    _, bd = per_stage(st_b, steps)
+    sep = []
+    for g, d in zip(geoms, dens):
+        q = QBXFMM(0)
+        q.set_geometry_from(g)
+        q.build(**kw)
+        dd = torch.as_tensor(d, device="cuda:0")
+        sep.append((q, dd, torch.empty((2, 1, g.n_tgt), dtype=torch.float64, device="cuda:0")))
+
+    def step_s():
+        for q, dd, o in sep:
+            q.eval(GQ_S, dd, out=o[0])
+            q.eval(GQ_D, dd, out=o[1])
+
+    ms_s = timer.run_plain(step_s, steps, warmup)
+    ref = torch.cat([o[:, 0] for _, _, o in sep], dim=1)
+    diff = float((ob[:, 0] - ref).abs().max() / ref.abs().max())
+    n_t = qb.n_tgt
+    for q, _, _ in sep:
+        q.close()
+    qb.close()
+    return {"value": round(2 * n_t / (ms_b * 1e-3), 1), "unit": "targets/s",
+            "ms_per_step": round(ms_b, 4), "separate_ms_per_step": round(ms_s, 4),
+            "separate_value": round(2 * n_t / (ms_s * 1e-3), 1),
+            "speedup_vs_separate": round(ms_s / ms_b, 3), "max_rel_diff_vs_separate": diff,
+            "n_geoms": n_geoms, "n_tgt": n_t, "build_s": round(build_s, 2), "steps": steps,
+            "stage_ms_per_step": bd,
+            "workload": f"{n_geoms} stars, 1024..65536 nodes each (log-uniform, seed 200), "
+                        f"{n_t} targets, S and D, FP64, p_qbx {p_qbx}, p_fmm {p_fmm}"}
+
+
+def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192):
     """Learned per-center QBX orders against the smallest uniform order meeting the tolerance.
 
     Workload: 8 x 8 lattice of wavy curves (seed 300) whose neighbours nearly touch (gap of four
-    expansion radii), 1024 panels x 16 nodes each = 1048576 on-surface targets and 2097152
-    centers, sources upsampled to 64 nodes per panel (4194304 sources). One step evaluates Green's
-    formula S(du/dn) - D(u), u = log|x - x0| with x0 outside the lattice; the exact value at the
-    targets is u / 2, so every error here is the true error relative to max |u|."""
+    expansion radii), `panels` panels x 16 nodes per curve (192: 196608 on-surface targets and
+    393216 centers), sources upsampled to 64 nodes per panel (786432 sources). One step evaluates
+    Green's formula S(du/dn) - D(u), u = log|x - x0| with x0 outside the lattice; the exact value
+    at the targets is u / 2, so every error here is the true error relative to max |u|. (At 1024
+    panels per curve the uniform order 4 already reaches 1e-12, leaving no order to save.)"""
     import numpy as np
     import torch
     import gq_inputs as gi
@@ -123,7 +195,7 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30):
     model = learned.load_default()
     if model is None:
         return {"status": "no shipped order model"}
-    g = gi.wavy_lattice(nx=8, ny=8, panels_per_curve=1024, seed=300, gap_in_radii=4.0,
+    g = gi.wavy_lattice(nx=8, ny=8, panels_per_curve=panels, seed=300, gap_in_radii=4.0,
                         src_order=64)
     lo, hi = g.src_xy.min(0), g.src_xy.max(0)
     x0 = (lo[0] - 0.7, 0.3 * lo[1] + 0.7 * hi[1])
@@ -178,8 +250,9 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30):
             "choose_orders_s": round(choose_s, 3), "build_s": round(build_s, 1),
             "stage_ms_per_step_uniform": bd_u, "stage_ms_per_step_learned": bd_l,
             "steps": steps, "p_fmm": p_fmm,
-            "workload": "8x8 wavy lattice (gap 4 radii), 1048576 targets, 2097152 centers, "
-                        "4194304 upsampled sources, Green's formula, FP64"}
+            "workload": f"8x8 wavy lattice (gap 4 radii), {panels} panels per curve, "
+                        f"{g.n_tgt} targets, {g.n_ctr} centers, {g.n_src} upsampled sources, "
+                        "Green's formula, FP64"}
 
 
 def per_stage(stages, steps):
@@ -300,10 +373,27 @@ def main():
             stage_rates[name] = round(f / (ms / cnt * 1e-3) / 1e12, 3)
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
     plain_out = out[:, 0].cpu().numpy()
+    # the same step replayed from HIP graphs (one per kind): no per-kernel host launch cost
+    g_s, _ = q.graph(GQ_S, dens, out=out[0])
+    g_d, _ = q.graph(GQ_D, dens, out=out[1])
+
+    def graph_step():
+        g_s.launch()
+        g_d.launch()
+
+    ms_graph = timer.run_plain(graph_step, args.steps, args.warmup)
+    graph_same = bool(np.array_equal(out[:, 0].cpu().numpy(), plain_out))
+    log(f"bench: graph replay {ms_graph:.3f} ms/step (identical: {graph_same})")
+    g_s.close()
+    g_d.close()
     q.close()
 
     # ---- variants ----
-    variants = {}
+    variants = {"graph": {"value": round(2 * geom.n_tgt / (ms_graph * 1e-3), 1),
+                          "unit": "targets/s", "ms_per_step": round(ms_graph, 4),
+                          "steps": args.steps, "vs_plain": round(ms_per_step / ms_graph, 3),
+                          "identical_to_plain": graph_same,
+                          "workload": "the headline step replayed from two captured HIP graphs"}}
     outputs = {}
     if not args.no_variants:
         def variant(name, workload, nd=1, **kw):
@@ -333,10 +423,15 @@ def main():
         variant("fp64_p16", "all FP64, p_fmm 16 (equal-accuracy reference for mixed_fp32_p16)",
                 p_fmm=16)
         variant("fp64_p40", "all FP64, p_fmm 40, tolerance 1e-12", p_fmm=40)
-        log("bench: learned orders on the wavy lattice")
-        variants["learned_orders"] = learned_variant(timer, max(2, args.steps // 4),
-                                                     max(1, args.warmup))
-        log(f"bench: learned orders: {variants['learned_orders'].get('speedup_vs_uniform')}x")
+        log("bench: ragged batch of 32 geometries")
+        variants["ragged_32"] = ragged_variant(timer, args.steps, args.warmup)
+        log(f"bench: ragged batch: {variants['ragged_32']['speedup_vs_separate']}x vs separate")
+        for tol in (-10.0, -12.0):
+            name = f"learned_orders_1e{int(tol)}"
+            log(f"bench: learned orders on the wavy lattice, tolerance 1e{int(tol)}")
+            variants[name] = learned_variant(timer, max(2, args.steps // 4), max(1, args.warmup),
+                                             log10_tol=tol)
+            log(f"bench: {name}: {variants[name].get('speedup_vs_uniform')}x")
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,

@@ -113,6 +113,24 @@ gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src
                           const double *tgt_xy, const int32_t *tgt_ctr);
 
 /*
+ * Several independent geometries in one context (a ragged batch): every stage then runs once
+ * over the work of all geometries, with no interaction between them. The arrays are the
+ * geometries' arrays concatenated; src_off, ctr_off, tgt_off (host, n_geom + 1 each, starting at
+ * 0 and ending at n_src, n_ctr, n_tgt) give each geometry's first source, center and target, and
+ * every geometry needs at least one source. tgt_ctr holds center indices local to the target's
+ * geometry (-1 unused; both -1: conventional target of that geometry). gq_build builds one tree
+ * per geometry (host threads) and merges them into one forest; densities and outputs of gq_eval
+ * are concatenated in the same order. Tree arrays then describe the forest: boxes are numbered
+ * depth-major over all trees and GQ_TREE_BOX_LEVEL holds a per-(tree, depth) level index;
+ * gq_stats' root fields describe the first geometry's root. Other arguments as gq_set_geometry.
+ */
+gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int64_t *src_off,
+                                const int64_t *ctr_off, const int64_t *tgt_off, int64_t n_src,
+                                const double *src_xy, const double *src_nrm, const double *src_w,
+                                int64_t n_ctr, const double *ctr_xy, const double *ctr_r,
+                                int64_t n_tgt, const double *tgt_xy, const int32_t *tgt_ctr);
+
+/*
  * Stage 1 and Sec. 4.3: build the quadtree (root square covering every particle and every whole
  * QBX disk; a center stays in a box when its disk does not fit the child's target confinement
  * region), sort particles into tree order, build Lists 1, 2, 3-close/far, 4-close/far, and upload

@@ -123,6 +123,26 @@ class QBXFMM:
             _ptr(ctr_xy), _ptr(ctr_r), self.n_tgt, _ptr(tgt_xy), _ptr(tgt_ctr)))
         self._keep = None
 
+    def set_geometry_batch(self, geoms):
+        """Several independent geometries (objects with the fields of ``gq_inputs.Geometry``,
+        host arrays, tgt_ctr local to each geometry) in one context; outputs and densities are
+        concatenated in the same order."""
+        cat = lambda name, dt: np.ascontiguousarray(
+            np.concatenate([getattr(g, name) for g in geoms]), dtype=dt)
+        off = lambda n: np.concatenate([[0], np.cumsum([n(g) for g in geoms])]).astype(np.int64)
+        so = off(lambda g: len(g.src_w))
+        co = off(lambda g: len(g.ctr_r))
+        to = off(lambda g: g.tgt_xy.shape[0])
+        arrs = [cat("src_xy", np.float64), cat("src_nrm", np.float64), cat("src_w", np.float64),
+                cat("ctr_xy", np.float64).reshape(-1, 2), cat("ctr_r", np.float64),
+                cat("tgt_xy", np.float64).reshape(-1, 2), cat("tgt_ctr", np.int32).reshape(-1, 2)]
+        self.n_src, self.n_ctr, self.n_tgt = int(so[-1]), int(co[-1]), int(to[-1])
+        self.geom_offsets = {"src": so, "ctr": co, "tgt": to}
+        self._check(self._L.gq_set_geometry_batch(
+            self._h, GQ_MEM_HOST, len(geoms), so.ctypes.data, co.ctypes.data, to.ctypes.data,
+            self.n_src, *[_ptr(a) for a in arrs[:3]], self.n_ctr, _ptr(arrs[3]), _ptr(arrs[4]),
+            self.n_tgt, _ptr(arrs[5]), _ptr(arrs[6])))
+
     def set_geometry_from(self, geom):
         """Geometry object with the fields of ``gq_inputs.Geometry`` (host arrays)."""
         self.set_geometry(geom.src_xy, geom.src_nrm, geom.src_w, geom.ctr_xy, geom.ctr_r,

@@ -45,6 +45,7 @@ GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "q
 GQ_N_STAGES = len(GQ_STAGE_NAMES)
 
 EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
+            "gq_set_geometry_batch",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_last_error"]
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH):
     L.gq_destroy.argtypes = [vp]
     L.gq_set_stream.argtypes = [vp, vp]
     L.gq_set_geometry.argtypes = [vp, i32, i64, dp, dp, dp, i64, dp, dp, i64, dp, ip]
+    L.gq_set_geometry_batch.argtypes = [vp, i32, i64, vp, vp, vp, i64, dp, dp, dp, i64, dp, dp,
+                                        i64, dp, ip]
     L.gq_build.argtypes = [vp, C.POINTER(gq_params)]
     L.gq_eval.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64]
     L.gq_eval_direct.argtypes = L.gq_eval.argtypes

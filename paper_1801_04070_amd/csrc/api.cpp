@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "context.hpp"
 #include "kernels.hpp"
@@ -282,9 +284,12 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.leaves, leaves.data(), leaves.size()));
     GQ_TRY(upload(ctx, d.tboxes, tboxes.data(), tboxes.size()));
     GQ_TRY(upload(ctx, d.is_tbox, istb.data(), nb));
-    std::vector<double> side(t.n_levels), iside(t.n_levels), lside(t.n_levels);
-    for (int l = 0; l < t.n_levels; ++l) {
-      side[l] = std::ldexp(t.side, -l);
+    // box sides per level (a forest: per virtual level, one per tree and depth)
+    std::vector<double> side = t.level_side_table;
+    if (side.empty())
+      for (int l = 0; l < t.n_levels; ++l) side.push_back(std::ldexp(t.side, -l));
+    std::vector<double> iside(side.size()), lside(side.size());
+    for (size_t l = 0; l < side.size(); ++l) {
       iside[l] = 1.0 / side[l];
       lside[l] = std::log(side[l]);
     }
@@ -398,6 +403,160 @@ gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1
   return launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, direct);
 }
 
+// Shared by gq_set_geometry (n_geom = 1, null offsets) and gq_set_geometry_batch.
+gq_status set_geometry_impl(gq_ctx *ctx, int mem, int64_t n_geom, const int64_t *src_off,
+                            const int64_t *ctr_off, const int64_t *tgt_off, int64_t n_src,
+                            const double *src_xy, const double *src_nrm, const double *src_w,
+                            int64_t n_ctr, const double *ctr_xy, const double *ctr_r,
+                            int64_t n_tgt, const double *tgt_xy, const int32_t *tgt_ctr) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "mem must be GQ_MEM_HOST or GQ_MEM_DEVICE");
+  if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
+  if (n_src <= 0 || n_ctr < 0 || n_tgt < 0) return fail(ctx, GQ_EINVAL, "need n_src > 0, n_ctr >= 0, n_tgt >= 0");
+  if (n_src >= (int64_t(1) << 31) || n_ctr >= (int64_t(1) << 31) || 2 * n_tgt >= (int64_t(1) << 31))
+    return fail(ctx, GQ_EUNSUP, "sizes beyond 2^31 are not supported");
+  if (!src_xy || !src_nrm || !src_w || (n_ctr > 0 && (!ctr_xy || !ctr_r)) ||
+      (n_tgt > 0 && (!tgt_xy || !tgt_ctr)))
+    return fail(ctx, GQ_EINVAL, "null geometry pointer");
+  // geometry offsets (host): start at 0, non-decreasing, end at the totals, >= 1 source each
+  std::vector<int64_t> so{0, n_src}, co{0, n_ctr}, to{0, n_tgt};
+  if (n_geom != 1 || src_off) {
+    if (n_geom < 1 || !src_off || !ctr_off || !tgt_off) return fail(ctx, GQ_EINVAL, "need n_geom >= 1 and three offset arrays");
+    so.assign(src_off, src_off + n_geom + 1);
+    co.assign(ctr_off, ctr_off + n_geom + 1);
+    to.assign(tgt_off, tgt_off + n_geom + 1);
+    if (so[0] || co[0] || to[0] || so[n_geom] != n_src || co[n_geom] != n_ctr || to[n_geom] != n_tgt)
+      return fail(ctx, GQ_EINVAL, "offsets must start at 0 and end at the totals");
+    for (int64_t k = 0; k < n_geom; ++k)
+      if (so[k + 1] <= so[k] || co[k + 1] < co[k] || to[k + 1] < to[k])
+        return fail(ctx, GQ_EINVAL, "offsets must increase (every geometry needs a source)");
+  }
+  free_device(ctx);
+  ctx->have_geom = false;
+  ctx->ns = n_src; ctx->nc = n_ctr; ctx->nt = n_tgt;
+  ctx->nc_user = n_ctr; ctx->n_pt = 0;
+  ctx->n_geom = n_geom;
+  ctx->geom_src_off = so; ctx->geom_ctr_off = co; ctx->geom_tgt_off = to;
+  ctx->pt_geom.clear();
+  try {
+    ctx->src_xy.resize(2 * n_src); ctx->src_nrm.resize(2 * n_src); ctx->src_w.resize(n_src);
+    ctx->ctr_xy.resize(2 * n_ctr); ctx->ctr_r.resize(n_ctr);
+    ctx->tgt_xy.resize(2 * n_tgt); ctx->tgt_ctr.resize(2 * n_tgt);
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, GQ_ENOMEM, "host copy of the geometry");
+  }
+  struct { void *dst; const void *src; size_t bytes; } cp[] = {
+      {ctx->src_xy.data(), src_xy, sizeof(double) * 2 * n_src},
+      {ctx->src_nrm.data(), src_nrm, sizeof(double) * 2 * n_src},
+      {ctx->src_w.data(), src_w, sizeof(double) * n_src},
+      {ctx->ctr_xy.data(), ctr_xy, sizeof(double) * 2 * n_ctr},
+      {ctx->ctr_r.data(), ctr_r, sizeof(double) * n_ctr},
+      {ctx->tgt_xy.data(), tgt_xy, sizeof(double) * 2 * n_tgt},
+      {ctx->tgt_ctr.data(), tgt_ctr, sizeof(int32_t) * 2 * n_tgt}};
+  for (auto &c : cp) {
+    if (!c.bytes) continue;
+    if (mem == GQ_MEM_HOST) std::memcpy(c.dst, c.src, c.bytes);
+    else GQ_HIP(ctx, hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost));
+  }
+  if (!finite_all(ctx->src_xy) || !finite_all(ctx->src_nrm) || !finite_all(ctx->src_w) ||
+      !finite_all(ctx->ctr_xy) || !finite_all(ctx->ctr_r) || !finite_all(ctx->tgt_xy))
+    return fail(ctx, GQ_EINVAL, "non-finite geometry value");
+  for (double r : ctx->ctr_r)
+    if (!(r > 0)) return fail(ctx, GQ_EINVAL, "center radius must be positive");
+  // target -> center indices: local to the target's geometry in a batch, made global here
+  std::vector<int64_t> point_targets;
+  std::vector<int32_t> point_geom;
+  for (int64_t k = 0; k < n_geom; ++k) {
+    const int64_t nck = co[k + 1] - co[k];
+    for (int64_t t = to[k]; t < to[k + 1]; ++t) {
+      int used = 0;
+      for (int s = 0; s < 2; ++s) {
+        int32_t &c = ctx->tgt_ctr[2 * t + s];
+        if (c < -1 || c >= nck) return fail(ctx, GQ_EINVAL, "target-center index out of range");
+        if (c >= 0) {
+          c = (int32_t)(c + co[k]);
+          ++used;
+        }
+      }
+      if (!used) {
+        point_targets.push_back(t);
+        point_geom.push_back((int32_t)k);
+      }
+    }
+  }
+  if (!point_targets.empty()) {
+    const int64_t n_pt = (int64_t)point_targets.size();
+    if (n_ctr + n_pt >= (int64_t(1) << 31)) return fail(ctx, GQ_EUNSUP, "too many centers and point targets");
+    // internal radius: 2^-40 of the extent of all particles, far below any quadrature scale
+    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+    auto grow = [&](const std::vector<double> &xy) {
+      for (size_t i = 0; i + 1 < xy.size(); i += 2)
+        for (int a = 0; a < 2; ++a) { lo[a] = std::min(lo[a], xy[i + a]); hi[a] = std::max(hi[a], xy[i + a]); }
+    };
+    grow(ctx->src_xy); grow(ctx->ctr_xy); grow(ctx->tgt_xy);
+    const double ext = std::max(hi[0] - lo[0], hi[1] - lo[1]);
+    const double r_pt = std::ldexp(ext > 0 ? ext : 1.0, -40);
+    try {
+      ctx->ctr_xy.resize(2 * (n_ctr + n_pt)); ctx->ctr_r.resize(n_ctr + n_pt);
+    } catch (const std::bad_alloc &) {
+      return fail(ctx, GQ_ENOMEM, "host copy of the point-target centers");
+    }
+    for (int64_t j = 0; j < n_pt; ++j) {
+      const int64_t t = point_targets[j], c = n_ctr + j;
+      ctx->ctr_xy[2 * c] = ctx->tgt_xy[2 * t]; ctx->ctr_xy[2 * c + 1] = ctx->tgt_xy[2 * t + 1];
+      ctx->ctr_r[c] = r_pt;
+      ctx->tgt_ctr[2 * t] = (int32_t)c;
+    }
+    ctx->n_pt = n_pt;
+    ctx->nc = n_ctr + n_pt;
+    ctx->pt_geom = point_geom;
+  }
+  if (ctx->nc == 0) return fail(ctx, GQ_EINVAL, "need at least one center or point target");
+  ctx->have_geom = true;
+  return GQ_OK;
+}
+
+// One tree per geometry (threads over geometries), merged into a forest.
+std::string build_forest(gq_ctx *ctx, const gq::TreeParams &tp) {
+  const int64_t K = ctx->n_geom;
+  std::vector<std::vector<int64_t>> cglob(K);
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t c = ctx->geom_ctr_off[k]; c < ctx->geom_ctr_off[k + 1]; ++c) cglob[k].push_back(c);
+  for (int64_t j = 0; j < ctx->n_pt; ++j) cglob[ctx->pt_geom[j]].push_back(ctx->nc_user + j);
+  std::vector<gq::Tree> trees(K);
+  std::vector<std::string> msg(K);
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    std::vector<double> cxy, cr;
+    for (int64_t k; (k = next.fetch_add(1)) < K;) {
+      cxy.resize(2 * cglob[k].size());
+      cr.resize(cglob[k].size());
+      for (size_t i = 0; i < cglob[k].size(); ++i) {
+        const int64_t c = cglob[k][i];
+        cxy[2 * i] = ctx->ctr_xy[2 * c]; cxy[2 * i + 1] = ctx->ctr_xy[2 * c + 1];
+        cr[i] = ctx->ctr_r[c];
+      }
+      const int64_t s0 = ctx->geom_src_off[k];
+      try {
+        msg[k] = gq::build_tree(trees[k], ctx->geom_src_off[k + 1] - s0, ctx->src_xy.data() + 2 * s0,
+                                (int64_t)cr.size(), cxy.data(), cr.data(), tp);
+      } catch (const std::bad_alloc &) {
+        msg[k] = "host allocation during tree build";
+      }
+    }
+  };
+  const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>(K, std::max(1u, std::thread::hardware_concurrency())));
+  std::vector<std::thread> pool;
+  for (int i = 1; i < nthr; ++i) pool.emplace_back(work);
+  work();
+  for (auto &th : pool) th.join();
+  for (int64_t k = 0; k < K; ++k)
+    if (!msg[k].empty()) return "geometry " + std::to_string(k) + ": " + msg[k];
+  std::vector<int64_t> sbase(ctx->geom_src_off.begin(), ctx->geom_src_off.end() - 1);
+  gq::merge_forest(trees, sbase, cglob, ctx->tree);
+  return "";
+}
+
 }  // namespace
 
 extern "C" {
@@ -481,83 +640,18 @@ gq_status gq_set_geometry(gq_ctx *ctx, int mem, int64_t n_src, const double *src
                           const double *src_nrm, const double *src_w, int64_t n_ctr,
                           const double *ctr_xy, const double *ctr_r, int64_t n_tgt,
                           const double *tgt_xy, const int32_t *tgt_ctr) {
-  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
-  if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "mem must be GQ_MEM_HOST or GQ_MEM_DEVICE");
-  if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
-  if (n_src <= 0 || n_ctr < 0 || n_tgt < 0) return fail(ctx, GQ_EINVAL, "need n_src > 0, n_ctr >= 0, n_tgt >= 0");
-  if (n_src >= (int64_t(1) << 31) || n_ctr >= (int64_t(1) << 31) || 2 * n_tgt >= (int64_t(1) << 31))
-    return fail(ctx, GQ_EUNSUP, "sizes beyond 2^31 are not supported");
-  if (!src_xy || !src_nrm || !src_w || (n_ctr > 0 && (!ctr_xy || !ctr_r)) ||
-      (n_tgt > 0 && (!tgt_xy || !tgt_ctr)))
-    return fail(ctx, GQ_EINVAL, "null geometry pointer");
-  free_device(ctx);
-  ctx->have_geom = false;
-  ctx->ns = n_src; ctx->nc = n_ctr; ctx->nt = n_tgt;
-  ctx->nc_user = n_ctr; ctx->n_pt = 0;
-  try {
-    ctx->src_xy.resize(2 * n_src); ctx->src_nrm.resize(2 * n_src); ctx->src_w.resize(n_src);
-    ctx->ctr_xy.resize(2 * n_ctr); ctx->ctr_r.resize(n_ctr);
-    ctx->tgt_xy.resize(2 * n_tgt); ctx->tgt_ctr.resize(2 * n_tgt);
-  } catch (const std::bad_alloc &) {
-    return fail(ctx, GQ_ENOMEM, "host copy of the geometry");
-  }
-  struct { void *dst; const void *src; size_t bytes; } cp[] = {
-      {ctx->src_xy.data(), src_xy, sizeof(double) * 2 * n_src},
-      {ctx->src_nrm.data(), src_nrm, sizeof(double) * 2 * n_src},
-      {ctx->src_w.data(), src_w, sizeof(double) * n_src},
-      {ctx->ctr_xy.data(), ctr_xy, sizeof(double) * 2 * n_ctr},
-      {ctx->ctr_r.data(), ctr_r, sizeof(double) * n_ctr},
-      {ctx->tgt_xy.data(), tgt_xy, sizeof(double) * 2 * n_tgt},
-      {ctx->tgt_ctr.data(), tgt_ctr, sizeof(int32_t) * 2 * n_tgt}};
-  for (auto &c : cp) {
-    if (!c.bytes) continue;
-    if (mem == GQ_MEM_HOST) std::memcpy(c.dst, c.src, c.bytes);
-    else GQ_HIP(ctx, hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost));
-  }
-  if (!finite_all(ctx->src_xy) || !finite_all(ctx->src_nrm) || !finite_all(ctx->src_w) ||
-      !finite_all(ctx->ctr_xy) || !finite_all(ctx->ctr_r) || !finite_all(ctx->tgt_xy))
-    return fail(ctx, GQ_EINVAL, "non-finite geometry value");
-  for (double r : ctx->ctr_r)
-    if (!(r > 0)) return fail(ctx, GQ_EINVAL, "center radius must be positive");
-  std::vector<int64_t> point_targets;
-  for (int64_t t = 0; t < n_tgt; ++t) {
-    int used = 0;
-    for (int s = 0; s < 2; ++s) {
-      int32_t c = ctx->tgt_ctr[2 * t + s];
-      if (c < -1 || c >= n_ctr) return fail(ctx, GQ_EINVAL, "target-center index out of range");
-      used += c >= 0;
-    }
-    if (!used) point_targets.push_back(t);
-  }
-  if (!point_targets.empty()) {
-    const int64_t n_pt = (int64_t)point_targets.size();
-    if (n_ctr + n_pt >= (int64_t(1) << 31)) return fail(ctx, GQ_EUNSUP, "too many centers and point targets");
-    // internal radius: 2^-40 of the extent of all particles, far below any quadrature scale
-    double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
-    auto grow = [&](const std::vector<double> &xy) {
-      for (size_t i = 0; i + 1 < xy.size(); i += 2)
-        for (int a = 0; a < 2; ++a) { lo[a] = std::min(lo[a], xy[i + a]); hi[a] = std::max(hi[a], xy[i + a]); }
-    };
-    grow(ctx->src_xy); grow(ctx->ctr_xy); grow(ctx->tgt_xy);
-    const double ext = std::max(hi[0] - lo[0], hi[1] - lo[1]);
-    const double r_pt = std::ldexp(ext > 0 ? ext : 1.0, -40);
-    try {
-      ctx->ctr_xy.resize(2 * (n_ctr + n_pt)); ctx->ctr_r.resize(n_ctr + n_pt);
-    } catch (const std::bad_alloc &) {
-      return fail(ctx, GQ_ENOMEM, "host copy of the point-target centers");
-    }
-    for (int64_t j = 0; j < n_pt; ++j) {
-      const int64_t t = point_targets[j], c = n_ctr + j;
-      ctx->ctr_xy[2 * c] = ctx->tgt_xy[2 * t]; ctx->ctr_xy[2 * c + 1] = ctx->tgt_xy[2 * t + 1];
-      ctx->ctr_r[c] = r_pt;
-      ctx->tgt_ctr[2 * t] = (int32_t)c;
-    }
-    ctx->n_pt = n_pt;
-    ctx->nc = n_ctr + n_pt;
-  }
-  if (ctx->nc == 0) return fail(ctx, GQ_EINVAL, "need at least one center or point target");
-  ctx->have_geom = true;
-  return GQ_OK;
+  return set_geometry_impl(ctx, mem, 1, nullptr, nullptr, nullptr, n_src, src_xy, src_nrm, src_w,
+                           n_ctr, ctr_xy, ctr_r, n_tgt, tgt_xy, tgt_ctr);
+}
+
+gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int64_t *src_off,
+                                const int64_t *ctr_off, const int64_t *tgt_off, int64_t n_src,
+                                const double *src_xy, const double *src_nrm, const double *src_w,
+                                int64_t n_ctr, const double *ctr_xy, const double *ctr_r,
+                                int64_t n_tgt, const double *tgt_xy, const int32_t *tgt_ctr) {
+  if (!src_off) return fail(ctx, GQ_EINVAL, "null offsets");
+  return set_geometry_impl(ctx, mem, n_geom, src_off, ctr_off, tgt_off, n_src, src_xy, src_nrm,
+                           src_w, n_ctr, ctr_xy, ctr_r, n_tgt, tgt_xy, tgt_ctr);
 }
 
 gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
@@ -583,8 +677,11 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   tp.w3far_min_sources = p.w3far_min_sources; tp.max_levels = p.max_levels;
   std::string msg;
   try {
-    msg = gq::build_tree(ctx->tree, ctx->ns, ctx->src_xy.data(), ctx->nc, ctx->ctr_xy.data(),
-                         ctx->ctr_r.data(), tp);
+    if (ctx->n_geom > 1)
+      msg = build_forest(ctx, tp);
+    else
+      msg = gq::build_tree(ctx->tree, ctx->ns, ctx->src_xy.data(), ctx->nc, ctx->ctr_xy.data(),
+                           ctx->ctr_r.data(), tp);
   } catch (const std::bad_alloc &) {
     return fail(ctx, GQ_ENOMEM, "host allocation during tree build");
   }

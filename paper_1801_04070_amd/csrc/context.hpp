@@ -89,6 +89,12 @@ struct gq_ctx {
   // itself only the constant term of that center's expansion survives, which is the plain point
   // value (direct sum + M2P + L2P).
   int64_t nc_user = 0, n_pt = 0;
+  // Independent geometries in one context (gq_set_geometry_batch): caller-order offsets of each
+  // geometry's sources, centers and targets (n_geom + 1 each), and the geometry of every
+  // internal point-target center. n_geom = 1 for gq_set_geometry.
+  int64_t n_geom = 1;
+  std::vector<int64_t> geom_src_off, geom_ctr_off, geom_tgt_off;
+  std::vector<int32_t> pt_geom;
   std::vector<double> src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy;
   std::vector<int32_t> tgt_ctr;
   bool have_geom = false, built = false;

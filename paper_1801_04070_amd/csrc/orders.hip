@@ -24,13 +24,13 @@ constexpr int kStack = 96;  // tree depth <= 28: a depth-first walk holds at mos
 // f(s) with the tree-order source index. Returns false if the stack would overflow (no source
 // is skipped silently: the caller flags the center).
 template <typename F>
-__device__ bool walk_disk(double2 x, double R, const double2 *__restrict__ bc,
+__device__ bool walk_disk(int32_t root, double2 x, double R, const double2 *__restrict__ bc,
                           const int32_t *__restrict__ blevel, const int32_t *__restrict__ bchild,
                           const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
                           const double *__restrict__ level_side, F &&f) {
   int32_t stack[kStack];
   int sp = 0;
-  stack[sp++] = 0;
+  stack[sp++] = root;
   const double R2 = R * R;
   while (sp > 0) {
     const int32_t b = stack[--sp];
@@ -55,7 +55,8 @@ __device__ bool walk_disk(double2 x, double R, const double2 *__restrict__ bc,
 // One thread per tree-order center; writes GQ_N_FEATURES FP32 values at the caller's index.
 __global__ void __launch_bounds__(256) k_center_features(
     int64_t nc, const double2 *__restrict__ cxy, const double *__restrict__ cr,
-    const int32_t *__restrict__ cperm, const double2 *__restrict__ bc,
+    const int32_t *__restrict__ cperm, const int32_t *__restrict__ cbox,
+    const int32_t *__restrict__ bparent, const double2 *__restrict__ bc,
     const int32_t *__restrict__ blevel, const int32_t *__restrict__ bchild,
     const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
     const double *__restrict__ level_side, const double2 *__restrict__ sxy,
@@ -65,10 +66,13 @@ __global__ void __launch_bounds__(256) k_center_features(
   if (k >= nc || cperm[k] >= nc_user) return;  // internal point-target centers have no row
   const double2 x = cxy[k];
   const double r = cr[k], R = 4.0 * r;
+  // the root of this center's own tree (a context may hold several independent geometries)
+  int32_t root = cbox[k];
+  for (int guard = 0; guard < kStack && bparent[root] >= 0; ++guard) root = bparent[root];
   // pass 1: nearest source and its normal
   double dmin2 = 1e300;
   double2 n0 = make_double2(0.0, 0.0);
-  bool ok = walk_disk(x, R, bc, blevel, bchild, bsrc0, bsrc1, level_side, [&](int32_t s) {
+  bool ok = walk_disk(root, x, R, bc, blevel, bchild, bsrc0, bsrc1, level_side, [&](int32_t s) {
     const double2 y = sxy[s];
     const double d2 = (y.x - x.x) * (y.x - x.x) + (y.y - x.y) * (y.y - x.y);
     if (d2 < dmin2) { dmin2 = d2; n0 = snrm[s]; }
@@ -76,7 +80,7 @@ __global__ void __launch_bounds__(256) k_center_features(
   // pass 2: arc length, node count, normal coherence, normal offsets, opposite-facing sheet
   double a2 = 0.0, a4 = 0.0, cnt = 0.0, nx = 0.0, ny = 0.0, o1 = 0.0, o2 = 0.0;
   double sheet2 = R * R;
-  ok &= walk_disk(x, R, bc, blevel, bchild, bsrc0, bsrc1, level_side, [&](int32_t s) {
+  ok &= walk_disk(root, x, R, bc, blevel, bchild, bsrc0, bsrc1, level_side, [&](int32_t s) {
     const double2 y = sxy[s], n = snrm[s];
     const double ex = y.x - x.x, ey = y.y - x.y, d2 = ex * ex + ey * ey;
     if (d2 >= R * R) return;
@@ -151,7 +155,8 @@ gq_status gq_center_features(gq_ctx *ctx, float *feat) {
   const gq::DevBuffers &d = ctx->d;
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_center_features, dim3((unsigned)((ctx->nc + 255) / 256)), dim3(256), 0,
-                       ctx->stream, ctx->nc, d.cxy, d.cr, d.cperm, d.bc, d.blevel, d.bchild, d.bsrc0,
+                       ctx->stream, ctx->nc, d.cxy, d.cr, d.cperm, d.cbox, d.bparent, d.bc,
+                       d.blevel, d.bchild, d.bsrc0,
                        d.bsrc1, d.level_side, d.sxy, d.snrm, d.sw, feat, ctx->nc_user, flag);
     e = hipGetLastError();
   }

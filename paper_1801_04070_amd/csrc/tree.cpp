@@ -404,4 +404,111 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
   return "";
 }
 
+void merge_forest(const std::vector<Tree> &trees, const std::vector<int64_t> &src_base,
+                  const std::vector<std::vector<int64_t>> &ctr_global, Tree &f) {
+  f = Tree();
+  const size_t K = trees.size();
+  int depth = 0;
+  for (const Tree &t : trees) depth = std::max(depth, t.n_levels);
+  f.n_levels = depth;
+  f.lo[0] = trees.empty() ? 0.0 : trees[0].lo[0];
+  f.lo[1] = trees.empty() ? 0.0 : trees[0].lo[1];
+  f.side = trees.empty() ? 1.0 : trees[0].side;
+  // virtual levels: tree k, depth l -> vbase[k] + l
+  std::vector<int32_t> vbase(K + 1, 0);
+  for (size_t k = 0; k < K; ++k) vbase[k + 1] = vbase[k] + trees[k].n_levels;
+  f.level_side_table.resize(vbase[K]);
+  for (size_t k = 0; k < K; ++k)
+    for (int l = 0; l < trees[k].n_levels; ++l)
+      f.level_side_table[vbase[k] + l] = std::ldexp(trees[k].side, -l);
+  // new box numbering, depth-major
+  std::vector<std::vector<int32_t>> map(K);
+  std::vector<std::pair<int, int64_t>> order;  // (tree, old box) in new order
+  f.level_start.assign(depth + 1, 0);
+  for (int l = 0; l < depth; ++l) {
+    f.level_start[l] = (int64_t)order.size();
+    for (size_t k = 0; k < K; ++k) {
+      const Tree &t = trees[k];
+      if (l >= t.n_levels) continue;
+      for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) order.push_back({(int)k, b});
+    }
+  }
+  f.level_start[depth] = (int64_t)order.size();
+  for (size_t k = 0; k < K; ++k) map[k].assign(trees[k].n_boxes(), -1);
+  for (size_t i = 0; i < order.size(); ++i) map[order[i].first][order[i].second] = (int32_t)i;
+  const int64_t nb = (int64_t)order.size();
+  f.root_of_level.resize(vbase[K]);
+  for (size_t k = 0; k < K; ++k)
+    for (int l = 0; l < trees[k].n_levels; ++l) f.root_of_level[vbase[k] + l] = map[k][0];
+  // particle offsets in the merged tree order
+  std::vector<int64_t> sbase(K + 1, 0), cbase(K + 1, 0);
+  for (size_t k = 0; k < K; ++k) {
+    sbase[k + 1] = sbase[k] + (int64_t)trees[k].src_order.size();
+    cbase[k + 1] = cbase[k] + (int64_t)trees[k].ctr_order.size();
+  }
+  for (size_t k = 0; k < K; ++k) {
+    for (int64_t s : trees[k].src_order) f.src_order.push_back(src_base[k] + s);
+    for (int64_t c : trees[k].ctr_order) f.ctr_order.push_back(ctr_global[k][c]);
+    for (int32_t b : trees[k].ctr_box) f.ctr_box.push_back(map[k][b]);
+  }
+  f.level.resize(nb); f.parent.resize(nb); f.child.resize(4 * nb); f.bi.resize(nb); f.bj.resize(nb);
+  f.cx.resize(nb); f.cy.resize(nb); f.src_begin.resize(nb); f.src_end.resize(nb);
+  f.ctr_begin.resize(nb); f.ctr_end.resize(nb); f.has_tgt.resize(nb);
+  auto remap_csr = [&](Csr Tree::*field, Csr &out) {
+    out.start.assign(nb + 1, 0);
+    out.idx.clear();
+    for (int64_t i = 0; i < nb; ++i) {
+      const Tree &t = trees[order[i].first];
+      const Csr &c = t.*field;
+      const int64_t b = order[i].second;
+      out.start[i] = (int64_t)out.idx.size();
+      if (!c.start.empty())
+        for (int64_t e = c.start[b]; e < c.start[b + 1]; ++e)
+          out.idx.push_back(map[order[i].first][c.idx[e]]);
+    }
+    out.start[nb] = (int64_t)out.idx.size();
+  };
+  f.near_row.assign(nb + 1, 0);
+  for (int64_t i = 0; i < nb; ++i) {
+    const int k = order[i].first;
+    const Tree &t = trees[k];
+    const int64_t b = order[i].second;
+    f.level[i] = vbase[k] + t.level[b];
+    f.parent[i] = t.parent[b] < 0 ? -1 : map[k][t.parent[b]];
+    for (int q = 0; q < 4; ++q) {
+      const int32_t c = t.child[4 * b + q];
+      f.child[4 * i + q] = c < 0 ? -1 : map[k][c];
+    }
+    f.bi[i] = t.bi[b]; f.bj[i] = t.bj[b]; f.cx[i] = t.cx[b]; f.cy[i] = t.cy[b];
+    f.src_begin[i] = sbase[k] + t.src_begin[b]; f.src_end[i] = sbase[k] + t.src_end[b];
+    f.ctr_begin[i] = cbase[k] + t.ctr_begin[b]; f.ctr_end[i] = cbase[k] + t.ctr_end[b];
+    f.has_tgt[i] = t.has_tgt[b];
+    f.near_row[i] = (int64_t)f.near_lo.size();
+    for (int64_t g = t.near_row[b]; g < t.near_row[b + 1]; ++g) {
+      f.near_lo.push_back(sbase[k] + t.near_lo[g]);
+      f.near_hi.push_back(sbase[k] + t.near_hi[g]);
+    }
+  }
+  f.near_row[nb] = (int64_t)f.near_lo.size();
+  remap_csr(&Tree::list1, f.list1);
+  remap_csr(&Tree::list2, f.list2);
+  remap_csr(&Tree::list3c, f.list3c);
+  remap_csr(&Tree::list3f, f.list3f);
+  remap_csr(&Tree::list4c, f.list4c);
+  remap_csr(&Tree::list4f, f.list4f);
+  // List 2 offsets follow the V entries of each box in the new row order
+  for (int64_t i = 0; i < nb; ++i) {
+    const Tree &t = trees[order[i].first];
+    const int64_t b = order[i].second;
+    for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e)
+      f.list2_offset.push_back(t.list2_offset[e]);
+  }
+  for (const Tree &t : trees) {
+    f.n_leaves += t.n_leaves; f.n_target_boxes += t.n_target_boxes; f.n_suspended += t.n_suspended;
+    f.near_pairs += t.near_pairs; f.list3f_pairs += t.list3f_pairs;
+    f.list4f_sources += t.list4f_sources; f.near_sources += t.near_sources;
+    f.n_local_boxes += t.n_local_boxes;
+  }
+}
+
 }  // namespace gq

@@ -62,6 +62,13 @@ struct Tree {
   std::vector<int64_t> near_row;                // n_boxes + 1
   std::vector<int64_t> near_lo, near_hi;        // ranges
 
+  // Forests (several independent geometries in one context): box levels are then "virtual"
+  // levels, an index into level_side_table (one entry per (tree, depth)); level_start and
+  // n_levels stay indexed by depth, so the boxes of one depth of every tree are contiguous.
+  // Empty for a single tree, whose level l has side side / 2^l.
+  std::vector<double> level_side_table;
+  std::vector<int32_t> root_of_level;           // forests: root box of each virtual level's tree
+
   // Statistics.
   int64_t n_leaves = 0, n_target_boxes = 0, n_suspended = 0;
   int64_t near_pairs = 0, list3f_pairs = 0, list4f_sources = 0, near_sources = 0;
@@ -79,5 +86,12 @@ struct Tree {
 // else an error message.
 std::string build_tree(Tree &t, int64_t ns, const double *src_xy, int64_t nc, const double *ctr_xy,
                        const double *ctr_r, const TreeParams &p);
+
+// Merge independent trees into one forest. Tree k's sources are the caller's sources
+// src_base[k] + (its local indices); its centers map through ctr_global[k] (local -> caller
+// index). Boxes are renumbered depth-major across trees (depth, then tree, then the tree's own
+// order); sources and centers keep each tree's order, trees one after another.
+void merge_forest(const std::vector<Tree> &trees, const std::vector<int64_t> &src_base,
+                  const std::vector<std::vector<int64_t>> &ctr_global, Tree &out);
 
 }  // namespace gq

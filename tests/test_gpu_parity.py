@@ -315,3 +315,54 @@ def test_graph_replays_match_eager(c1, kind):
     with pytest.raises(GQError):
         g.launch()
     g.close()
+
+
+def test_ragged_batch_matches_separate_contexts():
+    """Independent geometries of very different sizes, overlapping in space, in one context:
+    each geometry's potentials equal those of its own context (same trees, same work items),
+    also with conventional targets, per-center orders and batched densities."""
+    geoms = gi.ragged_star_batch(n_geoms=6, seed=200, min_nodes=256, max_nodes=16384)
+    g2 = copy.copy(geoms[2])
+    pts = np.array([[0.1, 0.2], [3.0, -1.0], [0.5, 0.5]])
+    g2.tgt_xy = np.concatenate([g2.tgt_xy, pts])
+    g2.tgt_ctr = np.concatenate([g2.tgt_ctr, np.full((3, 2), -1, np.int32)])
+    geoms[2] = g2
+    from paper_1801_04070_amd import QBXFMM
+    kw = dict(p_qbx=12, p_fmm=30)
+    qb = QBXFMM(0)
+    qb.set_geometry_batch(geoms)
+    qb.build(**kw)
+    dens = [np.stack([gi.fourier_density(g, seed=40 + i), gi.fourier_density(g, seed=90 + i)])
+            for i, g in enumerate(geoms)]
+    dens2 = [np.stack([gi.fourier_density(g, seed=140 + i)] * 2) for i, g in enumerate(geoms)]
+    db = _dev(np.concatenate(dens, axis=1))
+    db2 = _dev(np.concatenate(dens2, axis=1))
+    rng = np.random.default_rng(5)
+    orders = [rng.choice([4, 6, 8, 12], size=g.n_ctr).astype(np.int32) for g in geoms]
+    for kind in (1, 2, 3):
+        for use_orders in (False, True):
+            qb.set_qbx_orders(np.concatenate(orders) if use_orders else None)
+            out = qb.eval(kind, db, db2 if kind == 3 else None).cpu().numpy()
+            t0 = 0
+            for i, g in enumerate(geoms):
+                q = QBXFMM(0)
+                q.set_geometry_from(g)
+                q.build(**kw)
+                if use_orders:
+                    q.set_qbx_orders(orders[i])
+                ref = q.eval(kind, _dev(dens[i]), _dev(dens2[i]) if kind == 3 else None)
+                ref = ref.cpu().numpy()
+                part = out[:, t0:t0 + g.n_tgt]
+                err = np.abs(part - ref).max() / np.abs(ref).max()
+                assert err <= 1e-14, (kind, use_orders, i, err)
+                t0 += g.n_tgt
+    # features: each center walks its own geometry's tree only
+    from paper_1801_04070_amd.learned import center_features
+    fb = center_features(qb).cpu().numpy()
+    c0 = 0
+    for g in geoms:
+        q = QBXFMM(0)
+        q.set_geometry_from(g)
+        q.build(**kw)
+        np.testing.assert_array_equal(fb[c0:c0 + g.n_ctr], center_features(q).cpu().numpy())
+        c0 += g.n_ctr

@@ -314,3 +314,75 @@ def test_point_targets_only():
     with pytest.raises(GQError):
         q.set_geometry(g.src_xy, g.src_nrm, g.src_w, np.zeros((0, 2)), np.zeros(0),
                        np.zeros((0, 2)), np.zeros((0, 2), np.int32))
+
+
+def _boxes_by_tree(q):
+    """Per forest box: (tree root, depth, i, j); roots found by following parents."""
+    par = q.tree_array(_lib.GQ_TREE_BOX_PARENT)
+    ij = q.tree_array(_lib.GQ_TREE_BOX_IJ)
+    out = []
+    for b in range(len(par)):
+        d, r = 0, b
+        while par[r] >= 0:
+            r = par[r]
+            d += 1
+        out.append((r, d, int(ij[b, 0]), int(ij[b, 1])))
+    return out
+
+
+def test_forest_matches_separate_trees():
+    """A batch of geometries (two of them overlapping in space) builds the same trees and lists
+    as separate contexts, renumbered: boxes by (depth, i, j) within each tree, particles offset."""
+    geoms = [gi.starfish_c1(), gi.unit_circle(24),
+             gi.random_stars(n_curves=2, panels_per_curve=24, seed=9, box=6.0),
+             gi.discretize([gi.StarCurve(amp=0.2, arms=3)], 40)]
+    pts, tgt_xy, tgt_ctr = _with_point_targets(geoms[2], n_pt=50)
+    g2 = copy.copy(geoms[2])
+    g2.tgt_xy, g2.tgt_ctr = tgt_xy, tgt_ctr
+    geoms[2] = g2
+    kw = dict(p_qbx=8, p_fmm=10, n_max=16)
+    qf = QBXFMM(device=-1)
+    qf.set_geometry_batch(geoms)
+    sf = qf.build(**kw)
+    singles = []
+    for g in geoms:
+        q = QBXFMM(device=-1)
+        q.set_geometry_from(g)
+        singles.append((q, q.build(**kw)))
+    for key in ("n_boxes", "n_leaves", "n_list1", "n_list2", "n_list3_close", "n_list3_far",
+                "n_list4_close", "n_list4_far", "near_pairs", "n_point_targets"):
+        assert sf[key] == sum(s[key] for _, s in singles), key
+    fb = _boxes_by_tree(qf)
+    roots = sorted({r for r, *_ in fb})
+    assert len(roots) == len(geoms)
+    so = np.concatenate([[0], np.cumsum([len(g.src_w) for g in geoms])])
+    co = np.concatenate([[0], np.cumsum([len(g.ctr_r) for g in geoms])])
+    f_src, f_ctr = qf.tree_array(_lib.GQ_TREE_SRC_ORDER), qf.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    f_lists = qf.lists()
+    s_pos = c_pos = 0
+    n_user = co[-1]
+    pt_seen = 0
+    for k, (q, st) in enumerate(singles):
+        ns, nc_all = len(geoms[k].src_w), st["n_ctr"] + st["n_point_targets"]
+        assert np.array_equal(f_src[s_pos:s_pos + ns], q.tree_array(_lib.GQ_TREE_SRC_ORDER) + so[k])
+        c_single = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+        want = np.where(c_single < st["n_ctr"], c_single + co[k],
+                        n_user + pt_seen + (c_single - st["n_ctr"]))
+        assert np.array_equal(f_ctr[c_pos:c_pos + nc_all], want)
+        s_pos += ns
+        c_pos += nc_all
+        pt_seen += st["n_point_targets"]
+        # lists, keyed by (depth, i, j) inside tree k
+        sb = _boxes_by_tree(q)
+        # roots are the first boxes of the depth-major numbering, in geometry order
+        key_f = {b: (d, i, j) for b, (r, d, i, j) in enumerate(fb) if r == roots[k]}
+        inv_f = {v: b for b, v in key_f.items()}
+        s_lists = q.lists()
+        for name in f_lists:
+            fs, fi = f_lists[name]
+            ss, si = s_lists[name]
+            for b, (_, d, i, j) in enumerate(sb):
+                fbx = inv_f[(d, i, j)]
+                got = sorted(key_f[e] for e in fi[fs[fbx]:fs[fbx + 1]])
+                exp = sorted(sb[e][1:] for e in si[ss[b]:ss[b + 1]])
+                assert got == exp, (name, k, b)
