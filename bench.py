@@ -3,18 +3,20 @@
 Headline workload: 16 random star curves, 8192 panels x 16 Gauss-Legendre nodes = 131072 sources,
 two QBX centers per node (radius = half the panel arclength), 131072 on-surface targets,
 p_qbx = 12, p_fmm = 30, n_max = 64, t_f = 0.9, FP64. One step evaluates the single-layer and the
-double-layer potential of a Fourier-mode density (all FMM stages, densities resident in HBM);
+double-layer potential of a Fourier-mode density (all FMM stages, densities resident in HBM) with
+one gq_eval(GQ_S_AND_D) call, which runs the two kinds concurrently on two stream pairs;
 targets/s = 2 x 131072 / step time. Tree and list build is excluded and reported as build_ms.
 
 Variants on the same geometry (reported under "variants", each with its own error against the
 FP64 oracle at sampled targets):
+  graph           S and D replayed from two captured HIP graphs
+  sequential_s_then_d  S and D as two calls on one stream (no overlap between the kinds)
   batched_64      64 densities per call (a block of right-hand sides), FP64, p_fmm 30
   mixed_fp32_p16  FP32 box expansions at p_fmm 16 (tolerance 1e-6)
   fp64_p16        all-FP64 at p_fmm 16, the equal-accuracy reference for mixed_fp32_p16
   fp64_p40        all-FP64 at p_fmm 40 (tolerance 1e-12)
   ragged_32       32 independent stars (1024..65536 nodes) in one batched context (one forest)
                   against 32 contexts evaluated one after another
-  graph           the headline step replayed from captured HIP graphs
   learned_orders_1e-10, _1e-12
                   per-center QBX orders from the shipped network on an 8 x 8 lattice of nearly
                   touching wavy curves (196608 targets), against the smallest uniform order
@@ -147,8 +149,9 @@ def ragged_variant(timer, steps, warmup, n_geoms=32, p_qbx=12, p_fmm=30):
         qb.eval(GQ_S, db, out=ob[0])
         qb.eval(GQ_D, db, out=ob[1])
 
-    ms_b, st_b = timer.run(qb, step_b, steps, warmup)
-    _, bd = per_stage(st_b, steps)
+    ms_b = timer.run_plain(step_b, steps, warmup)
+    _, st_b = timer.run(qb, step_b, min(steps, 5), 1)
+    _, bd = per_stage(st_b, min(steps, 5))
     sep = []
     for g, d in zip(geoms, dens):
         q = QBXFMM(0)
@@ -228,13 +231,15 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192)
             break
     if p_u is None:
         return {"status": "no uniform candidate order meets the tolerance", "uniform": uniform}
-    ms_u, st_u = timer.run(q, step, steps, warmup)
+    ms_u = timer.run_plain(step, steps, warmup)
+    _, st_u = timer.run(q, step, steps, 1)
     t0 = time.perf_counter()
     orders = learned.choose_orders(q, log10_tol, model)
     torch.cuda.synchronize()
     choose_s = time.perf_counter() - t0
     e_l = round(log10_err(), 2)
-    ms_l, st_l = timer.run(q, step, steps, warmup)
+    ms_l = timer.run_plain(step, steps, warmup)
+    _, st_l = timer.run(q, step, steps, 1)
     hist = torch.bincount(orders.long(), minlength=max(model.candidates) + 1).cpu().numpy()
     _, bd_u = per_stage(st_u, steps)
     _, bd_l = per_stage(st_l, steps)
@@ -306,6 +311,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="densities of the batched variant")
     ap.add_argument("--overlap", type=int, default=1, choices=(0, 1),
                     help="run direct and List 3 far work on a second stream")
+    ap.add_argument("--near-chunk", type=int, default=0, help="direct sources per work item")
+    ap.add_argument("--far-chunk", type=int, default=0, help="List 3 far boxes per work item")
+    ap.add_argument("--far-ppl", type=int, default=0, help="List 3 far pairs per lane")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -321,7 +329,7 @@ def main():
         return
 
     import gq_inputs as gi
-    from paper_1801_04070_amd import GQ_D, GQ_MIXED_FP32, GQ_S, QBXFMM, perfmodel
+    from paper_1801_04070_amd import GQ_D, GQ_MIXED_FP32, GQ_S, GQ_S_AND_D, QBXFMM, perfmodel
 
     p_qbx, p_fmm = 12, 30
     log("bench: building the 16-star workload (131072 sources)")
@@ -334,21 +342,27 @@ def main():
         q = QBXFMM(device=0)
         q.set_geometry_from(geom)
         params = dict(p_qbx=p_qbx, p_fmm=p_fmm, n_max=64, count_mode=0, t_f=0.9,
-                      w3far_min_sources=15, overlap=args.overlap)
+                      w3far_min_sources=15, overlap=args.overlap, near_chunk=args.near_chunk,
+                      far_chunk=args.far_chunk, far_pairs_per_lane=args.far_ppl)
         params.update(kw)
         return q, q.build(**params)
 
     def sd_step(q, d, out):
+        # S and D of the same densities in one call (the library runs the kinds concurrently);
+        # out rows: S of every density, then D of every density
         def step():
-            q.eval(GQ_S, d, out=out[0])
-            q.eval(GQ_D, d, out=out[1])
+            q.eval(GQ_S_AND_D, d, out=out)
         return step
 
     # ---- headline: plain FP64 ----
     q, stats = context()
-    out = torch.empty((2, 1, geom.n_tgt), dtype=torch.float64, device="cuda:0")
-    ms_per_step, stages = timer.run(q, sd_step(q, dens, out), args.steps, args.warmup)
+    out = torch.empty((2, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+    # timed without stage events (they cost launches of their own); the stage breakdown and the
+    # roofline come from a second timed region of the same steps with the ABI's stage profiling
+    ms_per_step = timer.run_plain(sd_step(q, dens, out), args.steps, args.warmup)
     log(f"bench: plain {args.steps} steps, {ms_per_step:.3f} ms/step")
+    ms_profiled, stages = timer.run(q, sd_step(q, dens, out), args.steps, 1)
+    log(f"bench: with stage profiling {ms_profiled:.3f} ms/step")
     agg, breakdown = per_stage(stages, args.steps)
     n_slots = int((geom.tgt_ctr >= 0).sum())
     work = {k: perfmodel.stage_work(stats, k, p_qbx, p_fmm, n_slots) for k in (GQ_S, GQ_D)}
@@ -360,6 +374,8 @@ def main():
     peak = perfmodel.MI355X_PEAKS["fp64_vector_tflops"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom] + " (S and D launches)",
+                "timed_region": f"{args.steps} profiled steps (stage events on), "
+                                f"{ms_profiled:.4f} ms/step",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
                 "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops),
@@ -372,20 +388,31 @@ def main():
             f = (work[GQ_S][name]["flops"] + work[GQ_D][name]["flops"]) / 2
             stage_rates[name] = round(f / (ms / cnt * 1e-3) / 1e12, 3)
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
-    plain_out = out[:, 0].cpu().numpy()
-    # the same step replayed from HIP graphs (one per kind): no per-kernel host launch cost
-    g_s, _ = q.graph(GQ_S, dens, out=out[0])
-    g_d, _ = q.graph(GQ_D, dens, out=out[1])
+    plain_out = out.cpu().numpy()
+    # S and D replayed from two captured HIP graphs (no per-kernel host launch cost; the
+    # combined kind cannot be captured, so the kinds run one after the other here)
+    g_s, _ = q.graph(GQ_S, dens, out=out[0:1])
+    g_d, _ = q.graph(GQ_D, dens, out=out[1:2])
 
     def graph_step():
         g_s.launch()
         g_d.launch()
 
     ms_graph = timer.run_plain(graph_step, args.steps, args.warmup)
-    graph_same = bool(np.array_equal(out[:, 0].cpu().numpy(), plain_out))
+    graph_same = bool(np.array_equal(out.cpu().numpy(), plain_out))
     log(f"bench: graph replay {ms_graph:.3f} ms/step (identical: {graph_same})")
     g_s.close()
     g_d.close()
+    # S then D as two calls on one stream (no concurrency between the kinds)
+    out_seq = torch.empty_like(out)
+
+    def seq_step():
+        q.eval(GQ_S, dens, out=out_seq[0:1])
+        q.eval(GQ_D, dens, out=out_seq[1:2])
+
+    ms_seq = timer.run_plain(seq_step, args.steps, args.warmup)
+    seq_same = bool(np.array_equal(out_seq.cpu().numpy(), plain_out))
+    log(f"bench: S then D sequential {ms_seq:.3f} ms/step (identical: {seq_same})")
     q.close()
 
     # ---- variants ----
@@ -393,7 +420,13 @@ def main():
                           "unit": "targets/s", "ms_per_step": round(ms_graph, 4),
                           "steps": args.steps, "vs_plain": round(ms_per_step / ms_graph, 3),
                           "identical_to_plain": graph_same,
-                          "workload": "the headline step replayed from two captured HIP graphs"}}
+                          "workload": "S and D replayed from two captured HIP graphs"},
+                "sequential_s_then_d": {"value": round(2 * geom.n_tgt / (ms_seq * 1e-3), 1),
+                                        "unit": "targets/s", "ms_per_step": round(ms_seq, 4),
+                                        "steps": args.steps,
+                                        "vs_plain": round(ms_per_step / ms_seq, 3),
+                                        "identical_to_plain": seq_same,
+                                        "workload": "S then D as two calls on one stream"}}
     outputs = {}
     if not args.no_variants:
         def variant(name, workload, nd=1, **kw):
@@ -404,15 +437,16 @@ def main():
                 hb = np.stack([gi.fourier_density(geom, seed=100 + j) for j in range(nd)])
                 dv = torch.as_tensor(hb, dtype=torch.float64, device="cuda:0")
                 outputs[name + "_density"] = hb[nd - 1]
-            ov = torch.empty((2, nd, geom.n_tgt), dtype=torch.float64, device="cuda:0")
+            ov = torch.empty((2 * nd, geom.n_tgt), dtype=torch.float64, device="cuda:0")
             steps = max(2, args.steps // 4) if nd > 1 else args.steps
-            ms, st = timer.run(qv, sd_step(qv, dv, ov), steps, max(1, args.warmup))
-            _, bd = per_stage(st, steps)
+            ms = timer.run_plain(sd_step(qv, dv, ov), steps, max(1, args.warmup))
+            _, st = timer.run(qv, sd_step(qv, dv, ov), min(steps, 5), 1)
+            _, bd = per_stage(st, min(steps, 5))
             v = 2 * nd * geom.n_tgt / (ms * 1e-3)
             variants[name] = {"value": round(v, 1), "unit": "targets/s", "ms_per_step": round(ms, 4),
                               "steps": steps, "workload": workload,
                               "vs_plain": round(v / value, 3), "stage_ms_per_step": bd}
-            outputs[name] = ov[:, nd - 1].cpu().numpy()
+            outputs[name] = ov[[nd - 1, 2 * nd - 1]].cpu().numpy()
             qv.close()
             log(f"bench: {name}: {ms:.3f} ms/step")
 

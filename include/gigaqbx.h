@@ -42,8 +42,9 @@ typedef enum {
 } gq_status;
 
 /* Layer-potential kinds. GQ_S_MINUS_D evaluates S(dens1) - D(dens2), the left side of Green's
- * formula used as the accuracy test in Sec. 5.1. */
-enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3 };
+ * formula used as the accuracy test in Sec. 5.1. GQ_S_AND_D evaluates both S(dens1) and
+ * D(dens1) (two output rows per density). */
+enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3, GQ_S_AND_D = 4 };
 
 /* Where the geometry arrays passed to gq_set_geometry live. */
 enum { GQ_MEM_HOST = 0, GQ_MEM_DEVICE = 1 };
@@ -68,13 +69,17 @@ typedef struct {
   int max_levels;         /* depth guard for coincident particles (not in the paper); <= 28     */
   int overlap;            /* 1: direct and List 3 far work on a second stream, overlapping the
                              tree passes; 0: everything on the caller's stream                  */
+  int near_chunk;         /* direct sources per work item (one wavefront), 0: 1024             */
+  int far_chunk;          /* List 3 far boxes per work item (1..32), 0: 16                      */
+  int far_pairs_per_lane; /* (center, List 3 far box) pairs per lane in an item (default 1);
+                             0: a cost model of per-element and per-wave work                  */
 } gq_params;
 
 #define GQ_MAX_P_QBX 20
 #define GQ_MAX_P_FMM 63
 
 /* Fill *p with the defaults: p_qbx 12, p_fmm 30, n_max 64, count_mode 0, t_f 0.9,
- * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1. */
+ * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1, work-item shapes 0 (defaults). */
 gq_status gq_default_params(gq_params *p);
 
 /* Create a context on HIP device `device` (>= 0) using `hip_stream` (a hipStream_t, may be NULL for
@@ -145,9 +150,13 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params);
  *   kind GQ_S:          out[j] = S dens1[j]
  *   kind GQ_D:          out[j] = D dens1[j]
  *   kind GQ_S_MINUS_D:  out[j] = S dens1[j] - D dens2[j]
+ *   kind GQ_S_AND_D:    out[j] = S dens1[j] and out[n_dens + j] = D dens1[j]; the two kinds
+ *                       run concurrently (separate library streams and workspace halves), so
+ *                       one kind's latency-bound tree passes overlap the other's bulk kernels
  * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
- * caller's source order; out is a device array (n_dens, n_tgt) with row stride ld_out in the
- * caller's target order. dens2 must be NULL unless kind is GQ_S_MINUS_D. Enqueued on the
+ * caller's source order; out is a device array (n_dens, n_tgt) (GQ_S_AND_D: 2 n_dens rows)
+ * with row stride ld_out in the caller's target order. dens2 must be NULL unless kind is
+ * GQ_S_MINUS_D. Enqueued on the
  * context's stream; inputs must stay valid and outputs untouched until the stream passes the
  * call. Requires a successful gq_build on a device context (else GQ_ESTATE).
  */
@@ -187,6 +196,7 @@ gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
  * replay on the context's current stream. A graph becomes stale (GQ_ESTATE on launch) once the
  * context's buffers change: gq_set_geometry, gq_build, gq_set_qbx_orders, or a gq_eval with more
  * densities per batch than any before. Stage profiling must be off while capturing (GQ_ESTATE).
+ * GQ_S_AND_D cannot be captured (GQ_EUNSUP): capture GQ_S and GQ_D as two graphs.
  * Replays and eager calls on one context share its workspace: they must not run concurrently.
  */
 typedef struct gq_graph gq_graph;

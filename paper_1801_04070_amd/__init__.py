@@ -14,10 +14,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64, GQ_MIXED_FP32,
-                   gq_params, gq_stats)
+from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64,
+                   GQ_MIXED_FP32, gq_params, gq_stats)
 
-__all__ = ["QBXFMM", "GQError", "library", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "default_params"]
+__all__ = ["QBXFMM", "GQError", "library", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "GQ_S_AND_D",
+           "default_params"]
 
 _L = None
 
@@ -233,7 +234,8 @@ class QBXFMM:
         if d1.stride(-1) != 1 or (d2 is not None and d2.stride(-1) != 1):
             raise ValueError("densities must have unit stride along a row")
         if out is None:
-            out = torch.empty((d1.shape[0], self.n_tgt), dtype=torch.float64, device=d1.device)
+            rows = d1.shape[0] * (2 if kind == GQ_S_AND_D else 1)
+            out = torch.empty((rows, self.n_tgt), dtype=torch.float64, device=d1.device)
         h = C.c_void_p()
         self._check(self._L.gq_graph_create(self._h, kind, d1.shape[0], _ptr(d1), d1.stride(0),
                                             _ptr(d2), 0 if d2 is None else d2.stride(0),
@@ -242,7 +244,8 @@ class QBXFMM:
 
     def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
         """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or
-        (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt)."""
+        (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt); for GQ_S_AND_D
+        (2 n_dens, n_tgt), the S rows first."""
         import torch
         squeeze = dens1.dim() == 1
 
@@ -255,11 +258,12 @@ class QBXFMM:
         d2 = None if dens2 is None else rows(dens2)
         n_dens = d1.shape[0]
         if out is None:
-            out = torch.empty((n_dens, self.n_tgt), dtype=torch.float64, device=d1.device)
+            rows = n_dens * (2 if kind == GQ_S_AND_D else 1)
+            out = torch.empty((rows, self.n_tgt), dtype=torch.float64, device=d1.device)
         fn = self._L.gq_eval_direct if direct else self._L.gq_eval
         self._check(fn(self._h, kind, n_dens, _ptr(d1), d1.stride(0), _ptr(d2),
                        0 if d2 is None else d2.stride(0), _ptr(out), out.stride(0)))
-        return out[0] if squeeze else out
+        return out[0] if squeeze and kind != GQ_S_AND_D else out
 
 
 class EvalGraph:

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgigaqbx.so")
 
 GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EHIP, GQ_ESTATE, GQ_EUNSUP = 0, -1, -2, -3, -4, -5
-GQ_S, GQ_D, GQ_S_MINUS_D = 1, 2, 3
+GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D = 1, 2, 3, 4
 GQ_MEM_HOST, GQ_MEM_DEVICE = 0, 1
 GQ_FP64, GQ_MIXED_FP32 = 0, 1
 GQ_MAX_P_QBX, GQ_MAX_P_FMM = 20, 63
@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "GQ_OK", -1: "GQ_EINVAL", -2: "GQ_ENOMEM", -3: "GQ_EHIP", -4:
 class gq_params(C.Structure):
     _fields_ = [("p_qbx", C.c_int), ("p_fmm", C.c_int), ("n_max", C.c_int),
                 ("count_mode", C.c_int), ("t_f", C.c_double), ("w3far_min_sources", C.c_int),
-                ("precision", C.c_int), ("max_levels", C.c_int), ("overlap", C.c_int)]
+                ("precision", C.c_int), ("max_levels", C.c_int), ("overlap", C.c_int),
+                ("near_chunk", C.c_int), ("far_chunk", C.c_int), ("far_pairs_per_lane", C.c_int)]
 
 
 class gq_stats(C.Structure):

@@ -36,6 +36,8 @@ void free_workspace(gq_ctx *ctx) {
   if (ctx->device >= 0) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->main2) (void)hipStreamSynchronize(ctx->main2);
+    if (ctx->side2) (void)hipStreamSynchronize(ctx->side2);
     for (void *p : ctx->ws_allocations) (void)hipFree(p);
   }
   ctx->ws_allocations.clear();
@@ -104,7 +106,7 @@ std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
 // simple cost model (per-element work + slice reduction + fixed cost per wave). Each (center,
 // chunk) result goes to its own row; the rows of a box are laid out [chunk][center], direct
 // chunks first.
-constexpr int kNearChunk = 1024;
+constexpr int kNearChunk = 1024;   // defaults of gq_params.near_chunk / far_chunk
 constexpr int kFarChunk = 16;
 
 int pick_lg(int64_t nc, int64_t len, double elem_cost) {
@@ -132,6 +134,18 @@ gq_status upload_near_work(gq_ctx *ctx) {
   std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
   std::vector<int64_t> box_src_off(nb, 0), box_src_len(nb, 0);
   int64_t rows = 0;
+  const int64_t near_chunk = ctx->params.near_chunk > 0 ? ctx->params.near_chunk : kNearChunk;
+  const int64_t far_chunk = ctx->params.far_chunk > 0 ? ctx->params.far_chunk : kFarChunk;
+  ctx->far_chunk = (int)far_chunk;
+  const int far_ppl = ctx->params.far_pairs_per_lane;
+  // List 3 far items: with far_ppl > 0 the fewest slices that keep each lane at <= far_ppl
+  // boxes (short serial chains, many waves); else the cost model
+  auto far_lg = [&](int64_t nc, int64_t clen, int pq) {
+    if (far_ppl <= 0) return pick_lg(nc, clen, 200.0 * pq);
+    for (int lg = 6; lg > 0; --lg)
+      if ((clen + (64 >> lg) - 1) / (64 >> lg) <= far_ppl) return lg;
+    return 0;
+  };
   auto emit = [](std::vector<int32_t> &out, int64_t off, int64_t clen, int64_t ctr0, int64_t row0,
                  int64_t nc, int lg) {
     const int64_t ncl = int64_t(1) << lg;
@@ -151,9 +165,9 @@ gq_status upload_near_work(gq_ctx *ctx) {
     for (int64_t g = t.near_row[b]; g < t.near_row[b + 1]; ++g)
       for (int64_t s = t.near_lo[g]; s < t.near_hi[g]; ++s) src.push_back((int32_t)s);
     box_src_len[b] = (int64_t)src.size() - box_src_off[b];
-    const int64_t nchunks = (box_src_len[b] + kNearChunk - 1) / kNearChunk;
+    const int64_t nchunks = (box_src_len[b] + near_chunk - 1) / near_chunk;
     const int64_t wlen = t.list3f.start[b + 1] - t.list3f.start[b];
-    const int64_t fchunks = (wlen + kFarChunk - 1) / kFarChunk;
+    const int64_t fchunks = (wlen + far_chunk - 1) / far_chunk;
     base[b] = (int32_t)rows;
     nch[b] = (int32_t)(nchunks + fchunks);
     rows += (nchunks + fchunks) * nc;
@@ -170,17 +184,17 @@ gq_status upload_near_work(gq_ctx *ctx) {
       const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
       if (nc == 0 || ctx->box_pq[b] != pq) continue;
       const int64_t len = box_src_len[b];
-      const int64_t nchunks = (len + kNearChunk - 1) / kNearChunk;
+      const int64_t nchunks = (len + near_chunk - 1) / near_chunk;
       for (int64_t j = 0; j < nchunks; ++j) {
-        const int64_t c0 = j * kNearChunk, clen = std::min<int64_t>(kNearChunk, len - c0);
+        const int64_t c0 = j * near_chunk, clen = std::min<int64_t>(near_chunk, len - c0);
         emit(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
              pick_lg(nc, clen, 10.0 * pq));
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
-      for (int64_t j = 0; j * kFarChunk < wlen; ++j) {
-        const int64_t c0 = j * kFarChunk, clen = std::min<int64_t>(kFarChunk, wlen - c0);
+      for (int64_t j = 0; j * far_chunk < wlen; ++j) {
+        const int64_t c0 = j * far_chunk, clen = std::min<int64_t>(far_chunk, wlen - c0);
         emit(fitems, woff + c0, clen, t.ctr_begin[b], base[b] + (nchunks + j) * nc, nc,
-             pick_lg(nc, clen, 200.0 * pq));
+             far_lg(nc, clen, pq));
       }
       for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) clist.push_back((int32_t)c);
     }
@@ -297,6 +311,22 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.level_inv_side, iside.data(), iside.size()));
     GQ_TRY(upload(ctx, d.level_log_side, lside.data(), lside.size()));
   }
+  // depths that the upward and downward passes must cover
+  {
+    std::vector<int> depth(nb, 0);
+    for (int l = 0; l < t.n_levels; ++l)
+      for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) depth[b] = l;
+    int m2m_first = t.n_levels, l2l_first = t.n_levels;
+    for (int64_t b = 0; b < nb; ++b) {
+      for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e)
+        m2m_first = std::min(m2m_first, depth[t.list2.idx[e]]);
+      for (int64_t e = t.list3f.start[b]; e < t.list3f.start[b + 1]; ++e)
+        m2m_first = std::min(m2m_first, depth[t.list3f.idx[e]]);
+      if (t.list2.row_size(b) > 0 || t.list4f.row_size(b) > 0) l2l_first = std::min(l2l_first, depth[b]);
+    }
+    ctx->m2m_first_depth = m2m_first;
+    ctx->l2l_first_depth = l2l_first;
+  }
   // lists
   GQ_TRY(upload(ctx, d.v_start, to_i32(t.list2.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.v_idx, t.list2.idx.data(), t.list2.idx.size()));
@@ -363,9 +393,56 @@ bool finite_all(const std::vector<double> &v) {
   return true;
 }
 
+// The D half of GQ_S_AND_D: the same stages on a second stream pair, with every workspace
+// pointer moved past the first `slots` densities' workspace.
+gq_status launch_second_kind(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, double *out,
+                             int64_t ld_out, int nd, int slots, bool direct) {
+  if (!ctx->main2) {
+    GQ_HIP(ctx, hipStreamCreateWithFlags(&ctx->main2, hipStreamNonBlocking));
+    GQ_HIP(ctx, hipStreamCreateWithFlags(&ctx->side2, hipStreamNonBlocking));
+    GQ_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_pair_in, hipEventDisableTiming));
+    GQ_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_pair_out, hipEventDisableTiming));
+  }
+  GQ_HIP(ctx, hipEventRecord(ctx->ev_pair_in, ctx->stream));
+  GQ_HIP(ctx, hipStreamWaitEvent(ctx->main2, ctx->ev_pair_in, 0));
+  gq::DevBuffers saved = ctx->d;
+  const hipStream_t st = ctx->stream, side = ctx->side;
+  const int64_t P1 = ctx->params.p_fmm + 1, nb = ctx->tree.n_boxes();
+  ctx->d.sq += (int64_t)slots * ctx->ns;
+  ctx->d.sdip += (int64_t)slots * ctx->ns;
+  ctx->d.M += (int64_t)slots * nb * P1;
+  ctx->d.L += (int64_t)slots * nb * P1;
+  ctx->d.anear += (int64_t)slots * ctx->n_near_rows * (ctx->params.p_qbx + 1);
+  ctx->d.tv += (int64_t)slots * 2 * ctx->nt;
+  ctx->stream = ctx->main2;
+  ctx->side = ctx->side2;
+  hipError_t e = gq::run_eval(ctx, kind, d1, ld1, nullptr, 0, out, ld_out, nd, direct);
+  ctx->d = saved;
+  ctx->stream = st;
+  ctx->side = side;
+  if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  GQ_HIP(ctx, hipEventRecord(ctx->ev_pair_out, ctx->main2));
+  GQ_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_pair_out, 0));
+  return GQ_OK;
+}
+
 gq_status launch_batches(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
                          const double *dens2, int64_t ld2, double *out, int64_t ld_out,
                          bool direct) {
+  if (kind == GQ_S_AND_D) {
+    // S on the caller's stream and workspace slots [0, batch); D concurrently on the second
+    // stream pair and slots [batch, 2 batch)
+    const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch / 2);
+    for (int64_t j = 0; j < n_dens; j += batch) {
+      const int nd = (int)std::min<int64_t>(batch, n_dens - j);
+      GQ_TRY(launch_second_kind(ctx, GQ_D, dens1 + j * ld1, ld1, out + (n_dens + j) * ld_out,
+                                ld_out, nd, batch, direct));
+      hipError_t e = gq::run_eval(ctx, GQ_S, dens1 + j * ld1, ld1, nullptr, 0, out + j * ld_out,
+                                  ld_out, nd, direct);
+      if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return GQ_OK;
+  }
   const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
   for (int64_t j = 0; j < n_dens; j += batch) {
     const int nd = (int)std::min<int64_t>(batch, n_dens - j);
@@ -376,13 +453,19 @@ gq_status launch_batches(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
   return GQ_OK;
 }
 
+// Workspace slots an evaluation needs: one per density of a batch, two for GQ_S_AND_D.
+int workspace_batch(int kind, int64_t n_dens) {
+  if (kind == GQ_S_AND_D) return 2 * (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch / 2);
+  return (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
+}
+
 gq_status check_eval_args(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
                           int64_t ld1, const double *dens2, int64_t ld2, const double *out,
                           int64_t ld_out) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context cannot evaluate");
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_eval before a successful gq_build");
-  if (kind < GQ_S || kind > GQ_S_MINUS_D) return fail(ctx, GQ_EINVAL, "unknown kind");
+  if (kind < GQ_S || kind > GQ_S_AND_D) return fail(ctx, GQ_EINVAL, "unknown kind");
   if (n_dens < 0) return fail(ctx, GQ_EINVAL, "n_dens < 0");
   if (n_dens == 0) return GQ_OK;
   if (!dens1 || !out) return fail(ctx, GQ_EINVAL, "null density or output");
@@ -398,8 +481,7 @@ gq_status eval_common(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1
   GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
   if (n_dens == 0) return GQ_OK;
   GQ_HIP(ctx, hipSetDevice(ctx->device));
-  const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch);
-  GQ_TRY(ensure_workspace(ctx, batch));
+  GQ_TRY(ensure_workspace(ctx, workspace_batch(kind, n_dens)));
   return launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, direct);
 }
 
@@ -572,6 +654,9 @@ gq_status gq_default_params(gq_params *p) {
   p->precision = GQ_FP64;
   p->max_levels = 24;
   p->overlap = 1;
+  p->near_chunk = 0;
+  p->far_chunk = 0;
+  p->far_pairs_per_lane = 1;
   return GQ_OK;
 }
 
@@ -618,6 +703,8 @@ gq_status gq_destroy(gq_ctx *ctx) {
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->main2) (void)hipStreamSynchronize(ctx->main2);
+    if (ctx->side2) (void)hipStreamSynchronize(ctx->side2);
   }
   free_device(ctx);
   if (ctx->device >= 0) {
@@ -625,6 +712,10 @@ gq_status gq_destroy(gq_ctx *ctx) {
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->main2) (void)hipStreamDestroy(ctx->main2);
+    if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
+    if (ctx->ev_pair_in) (void)hipEventDestroy(ctx->ev_pair_in);
+    if (ctx->ev_pair_out) (void)hipEventDestroy(ctx->ev_pair_out);
   }
   delete ctx;
   return GQ_OK;
@@ -667,6 +758,9 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.count_mode != 0 && p.count_mode != 1) return fail(ctx, GQ_EINVAL, "count_mode must be 0 or 1");
   if (p.w3far_min_sources < 0) return fail(ctx, GQ_EINVAL, "w3far_min_sources must be >= 0");
   if (p.overlap != 0 && p.overlap != 1) return fail(ctx, GQ_EINVAL, "overlap must be 0 or 1");
+  if (p.near_chunk < 0 || p.near_chunk > (1 << 20) || p.far_chunk < 0 || p.far_chunk > 32 ||
+      p.far_pairs_per_lane < 0 || p.far_pairs_per_lane > 64)
+    return fail(ctx, GQ_EINVAL, "work-item shape out of range");
   free_device(ctx);
   ctx->params = p;
   ctx->pq_values.clear();
@@ -725,11 +819,14 @@ gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *d
   *graph = nullptr;
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (n_dens <= 0) return fail(ctx, GQ_EINVAL, "a graph needs n_dens >= 1");
+  if (kind == GQ_S_AND_D)
+    return fail(ctx, GQ_EUNSUP, "capture GQ_S and GQ_D as separate graphs (GQ_S_AND_D capture is "
+                                "not supported)");
   GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
   if (ctx->profiling) return fail(ctx, GQ_ESTATE, "disable stage profiling before capturing a graph");
   GQ_HIP(ctx, hipSetDevice(ctx->device));
   gq_status st = GQ_OK;
-  GQ_TRY(ensure_workspace(ctx, (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch)));
+  GQ_TRY(ensure_workspace(ctx, workspace_batch(kind, n_dens)));
   if (!ctx->capture) GQ_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
   // capture on the library's own stream (the caller's may be the null stream, which cannot be
   // captured); the side stream joins through the fork/join events

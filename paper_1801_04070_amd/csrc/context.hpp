@@ -108,6 +108,11 @@ struct gq_ctx {
   std::vector<void *> nw_allocations;    // direct / List 3 far work, re-uploaded on order changes
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
+  int far_chunk = 16;                // List 3 far boxes per work item (sizes k_m2qbxl's LDS)
+  // Shallowest depth whose multipoles are read (List 2 / List 3 far) and shallowest depth with a
+  // non-zero M2L/P2L local: M2M above the first and L2L out of depths above the second have no
+  // effect on any result and are not launched.
+  int m2m_first_depth = 0, l2l_first_depth = 0;
   gq::DevBuffers d;
   std::vector<void *> allocations;   // tree, list and table allocations, freed together
   std::vector<void *> ws_allocations;  // per-density workspace, sized for ws_batch densities
@@ -117,6 +122,9 @@ struct gq_ctx {
   // bumped whenever device buffers a captured graph refers to are freed or replaced
   uint64_t generation = 0;
   hipStream_t capture = nullptr;     // library stream used only to capture evaluation graphs
+  // second main/side stream pair and hand-over events for the concurrent half of GQ_S_AND_D
+  hipStream_t main2 = nullptr, side2 = nullptr;
+  hipEvent_t ev_pair_in = nullptr, ev_pair_out = nullptr;
 
   // stage profiling (HIP events on the context stream)
   bool profiling = false;

@@ -511,14 +511,13 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
                                            const double2 *__restrict__ bc,
                                            const int32_t *__restrict__ blevel,
                                            const double *__restrict__ level_side,
-                                           const E *__restrict__ M, int P1) {
+                                           const E *__restrict__ Md, int P1) {
   const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
   const double2 iy = cinv(y);
   const double sd = level_side[blevel[d]];
   const double2 w = cscale(iy, sd);
   const double2 iw = make_double2(y.x / sd, y.y / sd);
   const double2 u = cscale(iy, -r);
-  const E *Md = M + (int64_t)d * P1;
   const double a0 = Md[0].x;
   double2 S[PQ + 1];
 #pragma unroll
@@ -542,22 +541,30 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
 }
 
 // Work items for Stage 5b, same item layout and lane mapping as k_near, the slices striding over
-// the chunk's List 3 far boxes.
+// the chunk's List 3 far boxes. One wavefront per work-group; the chunk's multipoles are staged
+// in LDS first (dynamic LDS of far_chunk x P1 coefficients), so the serial recurrence over k
+// reads LDS instead of waiting on global memory at every step.
 template <int PQ, typename E>
-__global__ void __launch_bounds__(256) k_m2qbxl(
+__global__ void __launch_bounds__(64) k_m2qbxl(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_side, const E *__restrict__ M, int P1,
     double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st) {
-  const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (w >= n_items) return;  // uniform per wavefront
+  HIP_DYNAMIC_SHARED(unsigned char, m2q_lds)
+  E *Ms = reinterpret_cast<E *>(m2q_lds);
+  const int32_t w = (int32_t)blockIdx.x;
+  const int lane = threadIdx.x;
   M += (int64_t)blockIdx.y * box_st;
   anear += (int64_t)blockIdx.y * row_st;
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
   const int n_ctr = i1.x, lg = i1.y;
+  for (int i = lane; i < len * P1; i += 64) {
+    const int e = i / P1, k = i - e * P1;
+    Ms[i] = M[(int64_t)wf_idx[off + e] * P1 + k];
+  }
+  __syncthreads();
   const int nsl = 64 >> lg;
   const int cl = lane >> (6 - lg);
   const int sl = lane & (nsl - 1);
@@ -570,7 +577,7 @@ __global__ void __launch_bounds__(256) k_m2qbxl(
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   if (active)
     for (int32_t e = sl; e < len; e += nsl)
-      m2qbxl_add<PQ, E>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, M, P1);
+      m2qbxl_add<PQ, E>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, Ms + e * P1, P1);
   for (int o = nsl >> 1; o >= 1; o >>= 1) {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -809,8 +816,9 @@ void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                           const Strides &S, const E *M) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.far1 - bk.far0);
+  const size_t lds = sizeof(E) * (size_t)ctx->far_chunk * (ctx->params.p_fmm + 1);
   if (n > 0)
-    hipLaunchKernelGGL((k_m2qbxl<PQ, E>), dim3((n + 3) / 4, nd), dim3(256), 0, s, n,
+    hipLaunchKernelGGL((k_m2qbxl<PQ, E>), dim3(n, nd), dim3(64), lds, s, n,
                        d.far_items + 2 * bk.far0, d.wf_idx, d.cxy, d.cr, d.bc, d.blevel,
                        d.level_side, M, ctx->params.p_fmm + 1, d.anear, ctx->params.p_qbx + 1,
                        S.box, S.row);
@@ -867,7 +875,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    for (int l = t.n_levels - 2; l >= 0; --l) {
+    for (int l = t.n_levels - 2; l >= ctx->m2m_first_depth; --l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
         hipLaunchKernelGGL(k_m2m<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, X.m2m_rt, X.omega,
@@ -904,7 +912,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    for (int l = 1; l < t.n_levels; ++l) {
+    for (int l = std::max(1, ctx->l2l_first_depth + 1); l < t.n_levels; ++l) {
       const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
       if (nb > 0)
         hipLaunchKernelGGL(k_l2l<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad,

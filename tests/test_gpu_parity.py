@@ -366,3 +366,28 @@ def test_ragged_batch_matches_separate_contexts():
         q.build(**kw)
         np.testing.assert_array_equal(fb[c0:c0 + g.n_ctr], center_features(q).cpu().numpy())
         c0 += g.n_ctr
+
+
+def test_s_and_d_concurrent_matches_separate(c1):
+    """GQ_S_AND_D (S and D of the same densities, run concurrently on two stream pairs and two
+    workspace halves) equals separate S and D evaluations exactly, single and batched, also on
+    the direct path; graph capture of it is refused with an error."""
+    from paper_1801_04070_amd import GQ_S_AND_D
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=30)
+    dens = _dev(np.stack([gi.fourier_density(g, seed=s) for s in (1, 2, 3)]))
+    s_ref = q.eval(1, dens).cpu().numpy()
+    d_ref = q.eval(2, dens).cpu().numpy()
+    both = q.eval(GQ_S_AND_D, dens).cpu().numpy()
+    assert both.shape == (6, g.n_tgt)
+    assert np.array_equal(both[:3], s_ref) and np.array_equal(both[3:], d_ref)
+    one = q.eval(GQ_S_AND_D, dens[0]).cpu().numpy()
+    assert np.array_equal(one[0], s_ref[0]) and np.array_equal(one[1], d_ref[0])
+    # direct path too
+    bd = q.eval(GQ_S_AND_D, dens[:2], direct=True).cpu().numpy()
+    assert np.array_equal(bd[:2], q.eval(1, dens[:2], direct=True).cpu().numpy())
+    assert np.array_equal(bd[2:], q.eval(2, dens[:2], direct=True).cpu().numpy())
+    # capturing the combined kind is refused (the host capture crashed; capture S and D apart)
+    from paper_1801_04070_amd import GQError
+    with pytest.raises(GQError):
+        q.graph(GQ_S_AND_D, dens[1])
