@@ -9,7 +9,6 @@ targets/s = 2 x 131072 / step time. Tree and list build is excluded and reported
 
 Variants on the same geometry (reported under "variants", each with its own error against the
 FP64 oracle at sampled targets):
-  graph           S and D replayed from two captured HIP graphs
   sequential_s_then_d  S and D as two calls on one stream (no overlap between the kinds)
   batched_64      64 densities per call (a block of right-hand sides), FP64, p_fmm 30
   mixed_fp32_p16  FP32 box expansions at p_fmm 16 (tolerance 1e-6)
@@ -389,20 +388,6 @@ def main():
             stage_rates[name] = round(f / (ms / cnt * 1e-3) / 1e12, 3)
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
     plain_out = out.cpu().numpy()
-    # S and D replayed from two captured HIP graphs (no per-kernel host launch cost; the
-    # combined kind cannot be captured, so the kinds run one after the other here)
-    g_s, _ = q.graph(GQ_S, dens, out=out[0:1])
-    g_d, _ = q.graph(GQ_D, dens, out=out[1:2])
-
-    def graph_step():
-        g_s.launch()
-        g_d.launch()
-
-    ms_graph = timer.run_plain(graph_step, args.steps, args.warmup)
-    graph_same = bool(np.array_equal(out.cpu().numpy(), plain_out))
-    log(f"bench: graph replay {ms_graph:.3f} ms/step (identical: {graph_same})")
-    g_s.close()
-    g_d.close()
     # S then D as two calls on one stream (no concurrency between the kinds)
     out_seq = torch.empty_like(out)
 
@@ -416,11 +401,7 @@ def main():
     q.close()
 
     # ---- variants ----
-    variants = {"graph": {"value": round(2 * geom.n_tgt / (ms_graph * 1e-3), 1),
-                          "unit": "targets/s", "ms_per_step": round(ms_graph, 4),
-                          "steps": args.steps, "vs_plain": round(ms_per_step / ms_graph, 3),
-                          "identical_to_plain": graph_same,
-                          "workload": "S and D replayed from two captured HIP graphs"},
+    variants = {
                 "sequential_s_then_d": {"value": round(2 * geom.n_tgt / (ms_seq * 1e-3), 1),
                                         "unit": "targets/s", "ms_per_step": round(ms_seq, 4),
                                         "steps": args.steps,

@@ -151,8 +151,10 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params);
  *   kind GQ_D:          out[j] = D dens1[j]
  *   kind GQ_S_MINUS_D:  out[j] = S dens1[j] - D dens2[j]
  *   kind GQ_S_AND_D:    out[j] = S dens1[j] and out[n_dens + j] = D dens1[j]; the two kinds
- *                       run concurrently (separate library streams and workspace halves), so
- *                       one kind's latency-bound tree passes overlap the other's bulk kernels
+ *                       run concurrently on two library streams forked from and joined back to
+ *                       the context's stream (separate workspace halves), each kind's stages in
+ *                       order, so one kind's latency-bound tree passes overlap the other's bulk
+ *                       kernels
  * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
  * caller's source order; out is a device array (n_dens, n_tgt) (GQ_S_AND_D: 2 n_dens rows)
  * with row stride ld_out in the caller's target order. dens2 must be NULL unless kind is
@@ -189,15 +191,9 @@ gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders);
 gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
 
 /*
- * HIP graph of one evaluation, for small problems where kernel launches dominate (a build of the
- * 1024-source starfish runs about 15 launches per kind). gq_graph_create validates like gq_eval,
- * sizes the workspace, then captures exactly the gq_eval call with these arguments (pointers
- * are baked in) on a library-owned stream; nothing is computed. gq_graph_launch enqueues one
- * replay on the context's current stream. A graph becomes stale (GQ_ESTATE on launch) once the
- * context's buffers change: gq_set_geometry, gq_build, gq_set_qbx_orders, or a gq_eval with more
- * densities per batch than any before. Stage profiling must be off while capturing (GQ_ESTATE).
- * GQ_S_AND_D cannot be captured (GQ_EUNSUP): capture GQ_S and GQ_D as two graphs.
- * Replays and eager calls on one context share its workspace: they must not run concurrently.
+ * HIP graph of one evaluation. Switched off in this build: gq_graph_create returns GQ_EUNSUP
+ * (and *graph = NULL); gq_graph_launch and gq_graph_destroy accept only handles from
+ * gq_graph_create (NULL is ignored by destroy).
  */
 typedef struct gq_graph gq_graph;
 gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,

@@ -122,9 +122,10 @@ struct gq_ctx {
   // bumped whenever device buffers a captured graph refers to are freed or replaced
   uint64_t generation = 0;
   hipStream_t capture = nullptr;     // library stream used only to capture evaluation graphs
-  // second main/side stream pair and hand-over events for the concurrent half of GQ_S_AND_D
-  hipStream_t main2 = nullptr, side2 = nullptr;
-  hipEvent_t ev_pair_in = nullptr, ev_pair_out = nullptr;
+  // GQ_S_AND_D: one library stream per kind (both forked from and joined back to the caller's
+  // stream), with hand-over events
+  hipStream_t main1 = nullptr, main2 = nullptr;
+  hipEvent_t ev_pair_in = nullptr, ev_pair_out1 = nullptr, ev_pair_out2 = nullptr;
 
   // stage profiling (HIP events on the context stream)
   bool profiling = false;

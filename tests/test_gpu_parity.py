@@ -290,6 +290,8 @@ def test_point_targets_match_oracle(kind):
         assert e_pt < tol and e_q < tol
 
 
+@pytest.mark.skip(reason="graph capture is switched off: a capture whose forked library stream "
+                         "forked again crashed the host process, cause not established")
 @pytest.mark.parametrize("kind", [1, 3])
 def test_graph_replays_match_eager(c1, kind):
     """A captured evaluation replayed several times, with other eager evaluations (sharing the
@@ -387,7 +389,7 @@ def test_s_and_d_concurrent_matches_separate(c1):
     bd = q.eval(GQ_S_AND_D, dens[:2], direct=True).cpu().numpy()
     assert np.array_equal(bd[:2], q.eval(1, dens[:2], direct=True).cpu().numpy())
     assert np.array_equal(bd[2:], q.eval(2, dens[:2], direct=True).cpu().numpy())
-    # capturing the combined kind is refused (the host capture crashed; capture S and D apart)
+    # graph capture is switched off in this build: refused with an error
     from paper_1801_04070_amd import GQError
     with pytest.raises(GQError):
         q.graph(GQ_S_AND_D, dens[1])
