@@ -186,6 +186,19 @@ gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
  */
 gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders);
 
+/* Tune the work-item shapes (gq_params near_chunk, far_chunk, far_pairs_per_lane) for this
+ * built context: each of a fixed set of candidate shapes is timed over `reps` evaluations of
+ * kind GQ_S or GQ_D of dens1 (device, n_src, row stride ld1) with HIP events on the context's
+ * stream, and the context keeps the fastest (gq_get_params shows it; *best_ms, may be NULL,
+ * receives its time per evaluation). Synchronous; allocates a temporary output of n_tgt doubles
+ * and releases the evaluation workspace (the next gq_eval sizes it again). Results may differ
+ * from other shapes by summation order only. On an error the original shape is restored. */
+gq_status gq_autotune(gq_ctx *ctx, int kind, const double *dens1, int64_t ld1, int reps,
+                      double *best_ms);
+
+/* The parameters of the last gq_build (after gq_autotune: with the chosen shapes). */
+gq_status gq_get_params(gq_ctx *ctx, gq_params *out);
+
 /* Copy the QBX order used by each box (n_boxes int32, breadth-first box order) to host memory
  * `dst` (NULL to query the count, always written to *count). */
 gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);

@@ -187,6 +187,16 @@ class QBXFMM:
                  "list4c": _lib.GQ_LIST4C_START, "list4f": _lib.GQ_LIST4F_START}
         return {k: (self.tree_array(v), self.tree_array(v + 1)) for k, v in names.items()}
 
+    def autotune(self, kind: int, dens, reps: int = 5) -> tuple:
+        """Tune the work-item shapes on this context (gq_autotune); returns (params, ms)."""
+        d = dens.reshape(-1, dens.shape[-1])[0].contiguous()
+        ms = C.c_double()
+        self._check(self._L.gq_autotune(self._h, kind, _ptr(d), d.shape[0], reps, C.byref(ms)))
+        p = gq_params()
+        self._check(self._L.gq_get_params(self._h, C.byref(p)))
+        self.params = p
+        return p, ms.value
+
     def set_qbx_orders(self, orders):
         """Per-center QBX orders (caller order), or None for the uniform build order."""
         if orders is None:

@@ -49,7 +49,8 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_set_geometry_batch",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
-            "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_last_error"]
+            "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
+            "gq_get_params", "gq_last_error"]
 
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH):
     L.gq_graph_create.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64, C.POINTER(C.c_void_p)]
     L.gq_graph_launch.argtypes = [vp]
     L.gq_graph_destroy.argtypes = [vp]
+    L.gq_autotune.argtypes = [vp, i32, dp, i64, i32, C.POINTER(C.c_double)]
+    L.gq_get_params.argtypes = [vp, C.POINTER(gq_params)]
     L.gq_last_error.argtypes = [vp]
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:

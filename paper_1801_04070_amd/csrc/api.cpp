@@ -929,6 +929,75 @@ gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count) {
   return GQ_OK;
 }
 
+gq_status gq_autotune(gq_ctx *ctx, int kind, const double *dens1, int64_t ld1, int reps,
+                      double *best_ms) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (kind != GQ_S && kind != GQ_D) return fail(ctx, GQ_EINVAL, "autotune with GQ_S or GQ_D");
+  if (reps < 1 || reps > 1000) return fail(ctx, GQ_EINVAL, "reps must be in 1..1000");
+  GQ_TRY(check_eval_args(ctx, kind, 1, dens1, ld1, nullptr, 0, dens1, ctx->nt));
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  double *out = nullptr;
+  GQ_HIP(ctx, hipMalloc(&out, sizeof(double) * std::max<int64_t>(ctx->nt, 1)));
+  hipEvent_t a = nullptr, b = nullptr;
+  gq_status st = GQ_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    st = fail(ctx, GQ_EHIP, "hipEventCreate");
+  struct Shape { int near_chunk, far_chunk, far_ppl; };
+  const Shape cand[] = {{1024, 16, 1}, {512, 16, 1}, {2048, 16, 1}, {1024, 8, 1}, {1024, 16, 2},
+                        {1024, 32, 1}, {4096, 16, 1}};
+  const gq_params orig = ctx->params;
+  double best = 1e300;
+  Shape pick = {orig.near_chunk, orig.far_chunk, orig.far_pairs_per_lane};
+  for (const Shape &c : cand) {
+    if (st != GQ_OK) break;
+    ctx->params.near_chunk = c.near_chunk;
+    ctx->params.far_chunk = c.far_chunk;
+    ctx->params.far_pairs_per_lane = c.far_ppl;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    st = upload_near_work(ctx);
+    if (st != GQ_OK) break;
+    free_workspace(ctx);  // row counts may change with the shape
+    st = eval_common(ctx, kind, 1, dens1, ld1, nullptr, 0, out, ctx->nt, false);  // warm-up
+    if (st != GQ_OK) break;
+    hipError_t e = hipEventRecord(a, ctx->stream);
+    for (int r = 0; r < reps && e == hipSuccess && st == GQ_OK; ++r)
+      st = eval_common(ctx, kind, 1, dens1, ld1, nullptr, 0, out, ctx->nt, false);
+    if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) st = fail(ctx, GQ_EHIP, std::string("autotune timing: ") + hipGetErrorString(e));
+    if (st == GQ_OK && ms / reps < best) {
+      best = ms / reps;
+      pick = c;
+    }
+  }
+  // leave the context with the fastest shape (or the original one after an error)
+  const gq_status st_run = st;
+  ctx->params = orig;
+  if (st_run == GQ_OK) {
+    ctx->params.near_chunk = pick.near_chunk;
+    ctx->params.far_chunk = pick.far_chunk;
+    ctx->params.far_pairs_per_lane = pick.far_ppl;
+  }
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  gq_status st2 = upload_near_work(ctx);
+  free_workspace(ctx);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(out);
+  if (st_run != GQ_OK) return st_run;
+  if (st2 != GQ_OK) return st2;
+  if (best_ms) *best_ms = best;
+  return GQ_OK;
+}
+
+gq_status gq_get_params(gq_ctx *ctx, gq_params *out) {
+  if (!ctx || !out) return fail(ctx, GQ_EINVAL, "null argument");
+  *out = ctx->params;
+  return GQ_OK;
+}
+
 gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_set_qbx_orders before a successful gq_build");

@@ -393,3 +393,24 @@ def test_s_and_d_concurrent_matches_separate(c1):
     from paper_1801_04070_amd import GQError
     with pytest.raises(GQError):
         q.graph(GQ_S_AND_D, dens[1])
+
+
+def test_autotune_picks_a_candidate_shape_and_keeps_results():
+    """gq_autotune times candidate work-item shapes and keeps the fastest; the potentials stay
+    those of the oracle (shapes change only how the direct and List 3 far sums are split)."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    mu, _ = _densities(g, 3)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=30)
+    before = _run(q, 1, mu, None)
+    params, ms = q.autotune(1, _dev(mu), reps=2)
+    assert ms > 0
+    shape = (params.near_chunk, params.far_chunk, params.far_pairs_per_lane)
+    assert shape in {(1024, 16, 1), (512, 16, 1), (2048, 16, 1), (1024, 8, 1), (1024, 16, 2),
+                     (1024, 32, 1), (4096, 16, 1)}
+    after = _run(q, 1, mu, None)
+    assert _rel(after, before) < 1e-13
+    ref = oracle.qbx_eval(g, 1, mu, None, p_qbx=12)
+    assert _rel(after, ref) < 1e-10
+    from paper_1801_04070_amd import GQError
+    with pytest.raises(GQError):
+        q.autotune(3, _dev(mu))
