@@ -25,6 +25,15 @@ __host__ __device__ __forceinline__ double2 caxpy(double s, double2 b, double2 a
 __host__ __device__ __forceinline__ double2 cfma(double2 b, double2 c, double2 a) {
   return make_double2(fma(b.x, c.x, fma(-b.y, c.y, a.x)), fma(b.x, c.y, fma(b.y, c.x, a.y)));
 }
+// 1/x for finite non-zero x: the hardware reciprocal estimate refined by two Newton steps
+// (each doubles the correct bits), so the result is within an ulp or so of the division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
 __host__ __device__ __forceinline__ double2 cinv(double2 a) {
   double s = 1.0 / (a.x * a.x + a.y * a.y);
   return make_double2(a.x * s, -a.y * s);

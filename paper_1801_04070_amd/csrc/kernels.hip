@@ -137,6 +137,65 @@ __global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restr
   M[(int64_t)b * P1 + m] = out;
 }
 
+// One wavefront forms the M2M of box b from its children (as k_m2m), with a wave-private LDS
+// block X; no work-group barrier, so other waves of the work-group may be elsewhere.
+template <typename E>
+__device__ __forceinline__ void m2m_box_wave(int32_t b, int m, const int32_t *__restrict__ bchild,
+                                             const typename Scalar<E>::T *__restrict__ Rt,
+                                             const E *__restrict__ omega, int P1,
+                                             E *__restrict__ M, E (*X)[64]) {
+  const int32_t *ch = bchild + 4 * (int64_t)b;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    E x = mk2<E>(0.0, 0.0);
+    if (ch[q] >= 0 && m < P1) {
+      const E w = omega[q * 8 + (m & 7)];
+      x = cmul(M[(int64_t)ch[q] * P1 + m], mk2<E>(w.x, -w.y));
+    }
+    X[q][m] = x;
+  }
+  __builtin_amdgcn_wave_barrier();  // a wave's LDS writes precede its later reads
+  if (m < P1) {
+    E acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = mk2<E>(0.0, 0.0);
+    for (int k = 0; k <= m; ++k) {
+      const auto r = Rt[k * P1 + m];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q][k], acc[q]);
+    }
+    E out = mk2<E>(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
+    M[(int64_t)b * P1 + m] = out;
+  }
+  __builtin_amdgcn_wave_barrier();  // X may be rewritten by this wave next
+}
+
+// Two levels of Stage 2b in one launch: work-group = one box G of the upper level; wave q first
+// forms the M2M of G's child q (if that child has children), then, after the work-group barrier,
+// wave 0 forms G's own M2M from its children.
+template <typename E>
+__global__ void __launch_bounds__(256) k_m2m2(int32_t box0, const int32_t *__restrict__ bchild,
+                                              const typename Scalar<E>::T *__restrict__ Rt,
+                                              const E *__restrict__ omega, int P1,
+                                              E *__restrict__ M, int64_t box_st) {
+  __shared__ E X[4][4][64];
+  const int32_t g = box0 + blockIdx.x;
+  const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
+  M += (int64_t)blockIdx.y * box_st;
+  const int32_t *gch = bchild + 4 * (int64_t)g;
+  const bool g_leaf = gch[0] < 0 && gch[1] < 0 && gch[2] < 0 && gch[3] < 0;
+  const int32_t c = gch[w];
+  if (c >= 0) {
+    const int32_t *cch = bchild + 4 * (int64_t)c;
+    if (cch[0] >= 0 || cch[1] >= 0 || cch[2] >= 0 || cch[3] >= 0)
+      m2m_box_wave<E>(c, m, bchild, Rt, omega, P1, M, X[w]);
+  }
+  __syncthreads();
+  if (w == 0 && !g_leaf) m2m_box_wave<E>(g, m, bchild, Rt, omega, P1, M, X[0]);
+}
+
 // ------------------------------------------------------------------------------------------
 // Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One wavefront per
 // target-or-ancestor box.
@@ -336,6 +395,50 @@ __global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restr
   L[(int64_t)b * P1 + m] = cfma(mk2<E>(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
 }
 
+// One wavefront adds the L2L of parent p's local into child c's (as k_l2l), wave-private LDS.
+template <typename E>
+__device__ __forceinline__ void l2l_child_wave(int32_t p, int32_t c, int q, int m,
+                                               const typename Scalar<E>::T *__restrict__ Rt,
+                                               const E *__restrict__ omega, int P1,
+                                               E *__restrict__ L, E *X) {
+  if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
+  __builtin_amdgcn_wave_barrier();
+  if (m < P1) {
+    E acc = mk2<E>(0.0, 0.0);
+    for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
+    const E w = omega[q * 8 + (m & 7)];
+    L[(int64_t)c * P1 + m] = cfma(mk2<E>(w.x, -w.y), acc, L[(int64_t)c * P1 + m]);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Two levels of Stage 7 in one launch: work-group = one box P of the level above both, 16 waves.
+// Waves 0-3 take P's children through L2L from P; after the work-group barrier, wave 4 i + j
+// takes grandchild j of child i through L2L from that child. Only target-or-ancestor boxes
+// receive locals.
+template <typename E>
+__global__ void __launch_bounds__(1024) k_l2l2(int32_t box0, const int32_t *__restrict__ bchild,
+                                               const int8_t *__restrict__ bquad,
+                                               const int32_t *__restrict__ is_tbox,
+                                               const typename Scalar<E>::T *__restrict__ Rt,
+                                               const E *__restrict__ omega, int P1,
+                                               E *__restrict__ L, int64_t box_st) {
+  __shared__ E X[16][64];
+  const int32_t p = box0 + blockIdx.x;
+  const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
+  if (!is_tbox[p]) return;  // uniform per work-group
+  L += (int64_t)blockIdx.y * box_st;
+  if (w < 4) {
+    const int32_t c = bchild[4 * (int64_t)p + w];
+    if (c >= 0 && is_tbox[c]) l2l_child_wave<E>(p, c, bquad[c], m, Rt, omega, P1, L, X[w]);
+  }
+  __syncthreads();
+  const int32_t c = bchild[4 * (int64_t)p + (w >> 2)];
+  if (c < 0 || !is_tbox[c]) return;
+  const int32_t gc = bchild[4 * (int64_t)c + (w & 3)];
+  if (gc >= 0 && is_tbox[gc]) l2l_child_wave<E>(c, gc, bquad[gc], m, Rt, omega, P1, L, X[w]);
+}
+
 // ------------------------------------------------------------------------------------------
 // Near-field accumulation of one source into a center's QBX coefficients (P2QBXL).
 // z = (y - c)/r. Charge part accumulates acc_m = sum q z^-m (m >= 1), normalised by -1/m later.
@@ -352,7 +455,7 @@ struct NearAcc {
   }
   __device__ __forceinline__ void add(double2 z, double q, double2 dr) {
     const double r2 = z.x * z.x + z.y * z.y;
-    const double ir2 = 1.0 / r2;
+    const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND == 1) {
       logsum = fma(q, log(r2), logsum);
@@ -875,11 +978,22 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    for (int l = t.n_levels - 2; l >= ctx->m2m_first_depth; --l) {
-      const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-      if (nb > 0)
-        hipLaunchKernelGGL(k_m2m<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, X.m2m_rt, X.omega,
-                           P1, M, S.box);
+    // two levels per launch where two remain (a work-group per box of the upper one)
+    for (int l = t.n_levels - 2; l >= ctx->m2m_first_depth;) {
+      if (l - 1 >= ctx->m2m_first_depth) {
+        const int32_t b0 = (int32_t)t.level_start[l - 1];
+        const int32_t nb = (int32_t)(t.level_start[l] - b0);
+        if (nb > 0)
+          hipLaunchKernelGGL(k_m2m2<E>, dim3(nb, nd), dim3(256), 0, st, b0, d.bchild, X.m2m_rt,
+                             X.omega, P1, M, S.box);
+        l -= 2;
+      } else {
+        const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+        if (nb > 0)
+          hipLaunchKernelGGL(k_m2m<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, X.m2m_rt,
+                             X.omega, P1, M, S.box);
+        l -= 1;
+      }
     }
   }
   e = hipEventRecord(ctx->ev_up, st);
@@ -912,11 +1026,22 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    for (int l = std::max(1, ctx->l2l_first_depth + 1); l < t.n_levels; ++l) {
-      const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-      if (nb > 0)
-        hipLaunchKernelGGL(k_l2l<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad,
-                           d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
+    // two levels per launch where two remain (a work-group per box of the level above them)
+    for (int l = std::max(1, ctx->l2l_first_depth + 1); l < t.n_levels;) {
+      if (l + 1 < t.n_levels) {
+        const int32_t b0 = (int32_t)t.level_start[l - 1];
+        const int32_t nb = (int32_t)(t.level_start[l] - b0);
+        if (nb > 0)
+          hipLaunchKernelGGL(k_l2l2<E>, dim3(nb, nd), dim3(1024), 0, st, b0, d.bchild, d.bquad,
+                             d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
+        l += 2;
+      } else {
+        const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
+        if (nb > 0)
+          hipLaunchKernelGGL(k_l2l<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad,
+                             d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
+        l += 1;
+      }
     }
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
