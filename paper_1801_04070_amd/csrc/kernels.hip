@@ -458,7 +458,7 @@ struct NearAcc {
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND == 1) {
-      logsum = fma(q, log(r2), logsum);
+      logsum = fma(q, log_pos(r2), logsum);
       qsum += q;
       double2 pw = inv;
 #pragma unroll
@@ -474,7 +474,7 @@ struct NearAcc {
         if (m < PQ) pw = cmul(pw, inv);
       }
     } else {
-      logsum = fma(q, log(r2), logsum);
+      logsum = fma(q, log_pos(r2), logsum);
       qsum += q;
       const double2 e = cmul(dr, inv);
       a[0] = cadd(a[0], e);
