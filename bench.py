@@ -381,6 +381,24 @@ def main():
                 "algorithmic_bytes_per_launch": int(nbytes),
                 "achieved_hbm_gbs": round(nbytes / (avg_ms * 1e-3) / 1e9, 1)}
     roofline["traffic"], roofline["traffic_source"] = measured_traffic(KERNEL_OF_STAGE[dom])
+    # the same kernel with nothing else on the device: S then D, no side stream
+    q_iso, _ = context(overlap=0)
+    out_iso = torch.empty_like(out)
+
+    def iso_step():
+        q_iso.eval(GQ_S, dens, out=out_iso[0:1])
+        q_iso.eval(GQ_D, dens, out=out_iso[1:2])
+
+    _, st_iso = timer.run(q_iso, iso_step, args.steps, 1)
+    agg_iso, breakdown_iso = per_stage(st_iso, args.steps)
+    q_iso.close()
+    if dom in agg_iso:
+        ms_i, n_i = agg_iso[dom]
+        ach_i = flops / (ms_i / n_i * 1e-3) / 1e12
+        roofline["isolated"] = {"timed_region": f"{args.steps} profiled steps, S then D, no "
+                                                "side stream (one kernel at a time)",
+                                "avg_launch_ms": round(ms_i / n_i, 4),
+                                "achieved": round(ach_i, 3), "frac": round(ach_i / peak, 4)}
     stage_rates = {}
     for name, (ms, cnt) in agg.items():
         if name in work[GQ_S] and cnt:
@@ -463,6 +481,7 @@ def main():
                    "build_ms": round(stats["build_ms"], 1)},
         "variants": variants,
         "stage_ms_per_step": breakdown,
+        "stage_ms_per_step_isolated": breakdown_iso,
         "stage_tflops": stage_rates,
         "roofline": roofline,
     }

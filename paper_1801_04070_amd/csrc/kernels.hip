@@ -45,8 +45,11 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 2a, P2M for leaf boxes: one work-group per leaf, the leaf's sources staged in LDS, lane k
-// computes coefficient k.
+// Stage 2a, P2M for leaf boxes: one work-group (one wave) per leaf. For a batch of up to nb of the
+// leaf's sources (nb = 64, or 32 when P1 > 32, keeping LDS at P1 x nb x 16 B <= 32 KB), lane j
+// runs the powers of its own source, y_j^k (one complex multiply per order), and writes its
+// contribution to every coefficient into LDS; lane k then sums row k over the batch in source
+// order.
 template <int KIND, typename E>
 __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ bc,
@@ -59,43 +62,45 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
                                             const double2 *__restrict__ sdip, int P1,
                                             E *__restrict__ M, int64_t src_st,
                                             int64_t box_st) {
-  __shared__ double2 t_y[64];
-  __shared__ double t_q[(KIND & 1) ? 64 : 1];
-  __shared__ double2 t_d[(KIND & 2) ? 64 : 1];
+  HIP_DYNAMIC_SHARED(unsigned char, p2m_lds)
+  double2 *T = reinterpret_cast<double2 *>(p2m_lds);  // [k][nb]
+  __shared__ double invk[64];
+  const int nb = P1 > 32 ? 32 : 64;
   const int32_t b = leaves[blockIdx.x];
-  const int k = threadIdx.x;
+  const int lane = threadIdx.x;
   const int64_t jd = blockIdx.y;
   sq += jd * src_st;
   sdip += jd * src_st;
   M += jd * box_st;
+  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
   const double2 c = bc[b];
   const double is = level_inv_side[blevel[b]];
-  const double ik = k > 0 ? 1.0 / k : 0.0;
   double2 acc = make_double2(0.0, 0.0);
   const int32_t s0 = bsrc0[b], s1 = bsrc1[b];
-  for (int32_t base = s0; base < s1; base += 64) {
-    const int n = min(64, (int)(s1 - base));
-    __syncthreads();
-    if (k < n) {
-      const int32_t s = base + k;
-      t_y[k] = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-      if (KIND & 1) t_q[k] = sq[s];
-      if (KIND & 2) t_d[k] = cscale(sdip[s], -is);
-    }
-    __syncthreads();
-    if (k < P1) {
-      for (int j = 0; j < n; ++j) {
-        if (k == 0) {
-          if (KIND & 1) acc.x += t_q[j];
-          continue;
-        }
-        const double2 pk1 = cpowi(t_y[j], k - 1);
-        if (KIND & 1) acc = caxpy(-t_q[j] * ik, cmul(pk1, t_y[j]), acc);
-        if (KIND & 2) acc = cfma(t_d[j], pk1, acc);
+  for (int32_t base = s0; base < s1; base += nb) {
+    const int n = min(nb, (int)(s1 - base));
+    __syncthreads();  // invk ready; the previous batch's rows consumed
+    if (lane < n) {
+      const int32_t s = base + lane;
+      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+      const double q = (KIND & 1) ? sq[s] : 0.0;
+      const double2 d = (KIND & 2) ? cscale(sdip[s], -is) : make_double2(0.0, 0.0);
+      // coefficient 0: q;  coefficient k >= 1: -q y^k / k + d y^(k-1)
+      T[lane] = make_double2(q, 0.0);
+      double2 pw = make_double2(1.0, 0.0);  // y^(k-1)
+      for (int k = 1; k < P1; ++k) {
+        const double2 pk = cmul(pw, y);
+        double2 t = (KIND & 1) ? cscale(pk, -q * invk[k]) : make_double2(0.0, 0.0);
+        if (KIND & 2) t = cfma(d, pw, t);
+        T[k * nb + lane] = t;
+        pw = pk;
       }
     }
+    __syncthreads();
+    if (lane < P1)
+      for (int j = 0; j < n; ++j) acc = cadd(acc, T[lane * nb + j]);
   }
-  if (k < P1) M[(int64_t)b * P1 + k] = from_d2<E>(acc);
+  if (lane < P1) M[(int64_t)b * P1 + lane] = from_d2<E>(acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -351,7 +356,7 @@ __global__ void __launch_bounds__(64) k_far_local(
         // coefficient 0: q log|s y| + d/y;  coefficient k: -q y^-k / k + d y^-(k+1)
         double2 pw = inv;
         double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
-        if (KIND & 1) c0.x += q * (logs + 0.5 * log(y.x * y.x + y.y * y.y));
+        if (KIND & 1) c0.x += q * (logs + 0.5 * log_pos(y.x * y.x + y.y * y.y));
         Pc[lane][0] = c0;
         for (int k = 1; k < P1; ++k) {
           double2 ck = (KIND & 1) ? cscale(pw, -q / k) : make_double2(0.0, 0.0);
@@ -633,7 +638,7 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
     wk = cmul(wk, iw);
   }
   // alpha_0 += a_0 log|y| + V_0;  alpha_m += u^m (V_m - a_0/m)
-  alpha[0].x += a0 * 0.5 * log(y.x * y.x + y.y * y.y);
+  alpha[0].x += a0 * 0.5 * log_pos(y.x * y.x + y.y * y.y);
   alpha[0] = cadd(alpha[0], S[0]);
   double2 pm = u;
 #pragma unroll
@@ -972,7 +977,9 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64), 0, st, d.leaves, d.bc,
+    hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64),
+                       sizeof(double2) * (P1 > 32 ? 32 : 64) * P1,
+                       st, d.leaves, d.bc,
                        d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
                        S.src, S.box);
   }
