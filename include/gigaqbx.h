@@ -73,6 +73,9 @@ typedef struct {
   int far_chunk;          /* List 3 far boxes per work item (1..32), 0: 16                      */
   int far_pairs_per_lane; /* (center, List 3 far box) pairs per lane in an item (default 1);
                              0: a cost model of per-element and per-wave work                  */
+  int near_dens_group;    /* densities per direct-interaction work item when an evaluation has
+                             several (1, 2 or 4): the pair geometry is formed once per group;
+                             0: 2                                                              */
 } gq_params;
 
 #define GQ_MAX_P_QBX 20

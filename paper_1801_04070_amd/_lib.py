@@ -27,7 +27,8 @@ class gq_params(C.Structure):
     _fields_ = [("p_qbx", C.c_int), ("p_fmm", C.c_int), ("n_max", C.c_int),
                 ("count_mode", C.c_int), ("t_f", C.c_double), ("w3far_min_sources", C.c_int),
                 ("precision", C.c_int), ("max_levels", C.c_int), ("overlap", C.c_int),
-                ("near_chunk", C.c_int), ("far_chunk", C.c_int), ("far_pairs_per_lane", C.c_int)]
+                ("near_chunk", C.c_int), ("far_chunk", C.c_int), ("far_pairs_per_lane", C.c_int),
+                ("near_dens_group", C.c_int)]
 
 
 class gq_stats(C.Structure):

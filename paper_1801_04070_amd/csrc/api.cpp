@@ -670,6 +670,7 @@ gq_status gq_default_params(gq_params *p) {
   p->near_chunk = 0;
   p->far_chunk = 0;
   p->far_pairs_per_lane = 1;
+  p->near_dens_group = 0;
   return GQ_OK;
 }
 
@@ -775,6 +776,9 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.near_chunk < 0 || p.near_chunk > (1 << 20) || p.far_chunk < 0 || p.far_chunk > 32 ||
       p.far_pairs_per_lane < 0 || p.far_pairs_per_lane > 64)
     return fail(ctx, GQ_EINVAL, "work-item shape out of range");
+  if (p.near_dens_group != 0 && p.near_dens_group != 1 && p.near_dens_group != 2 &&
+      p.near_dens_group != 4)
+    return fail(ctx, GQ_EINVAL, "near_dens_group must be 0, 1, 2 or 4");
   free_device(ctx);
   ctx->params = p;
   ctx->pq_values.clear();

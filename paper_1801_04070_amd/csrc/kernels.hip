@@ -505,6 +505,85 @@ struct NearAcc {
   }
 };
 
+// The same P2QBXL accumulation for DG densities at once: the pair geometry (reciprocal, log,
+// powers of 1/z) is formed once and applied to every density's charge and dipole.
+template <int KIND, int PQ, int DG>
+struct NearAccMD {
+  double2 a[DG][PQ + 1];
+  double logsum[DG], qsum[DG];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int g = 0; g < DG; ++g) {
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) a[g][m] = make_double2(0.0, 0.0);
+      logsum[g] = 0.0;
+      qsum[g] = 0.0;
+    }
+  }
+  __device__ __forceinline__ void add(double2 z, const double *q, const double2 *dr) {
+    const double r2 = z.x * z.x + z.y * z.y;
+    const double ir2 = rcp_nr(r2);
+    const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
+    if (KIND & 1) {
+      const double lr = log_pos(r2);
+#pragma unroll
+      for (int g = 0; g < DG; ++g) {
+        logsum[g] = fma(q[g], lr, logsum[g]);
+        qsum[g] += q[g];
+      }
+    }
+    if (KIND == 1) {
+      double2 pw = inv;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+#pragma unroll
+        for (int g = 0; g < DG; ++g) a[g][m] = caxpy(q[g], pw, a[g][m]);
+        if (m < PQ) pw = cmul(pw, inv);
+      }
+    } else if (KIND == 2) {
+      // the running product dr / z^(m+1) per density, in the single-density order of operations
+      double2 pw[DG];
+#pragma unroll
+      for (int g = 0; g < DG; ++g) pw[g] = cmul(dr[g], inv);
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) {
+#pragma unroll
+        for (int g = 0; g < DG; ++g) {
+          a[g][m] = cadd(a[g][m], pw[g]);
+          if (m < PQ) pw[g] = cmul(pw[g], inv);
+        }
+      }
+    } else {
+      double2 e[DG];
+#pragma unroll
+      for (int g = 0; g < DG; ++g) {
+        e[g] = cmul(dr[g], inv);
+        a[g][0] = cadd(a[g][0], e[g]);
+      }
+      double2 pw = inv;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+#pragma unroll
+        for (int g = 0; g < DG; ++g) {
+          const double2 coef = make_double2(fma(-q[g], 1.0 / m, e[g].x), e[g].y);
+          a[g][m] = cfma(pw, coef, a[g][m]);
+        }
+        if (m < PQ) pw = cmul(pw, inv);
+      }
+    }
+  }
+  __device__ __forceinline__ void finish(int g, double2 *alpha, double logr) const {
+    if (KIND & 1) alpha[0].x += 0.5 * logsum[g] + qsum[g] * logr;
+    if (KIND == 1) {
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[g][m], alpha[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], a[g][m]);
+    }
+  }
+};
+
 // QBX expansion of a center evaluated at its targets (QBXL2P), written to the target slots.
 template <int PQ>
 __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, const double2 *alpha,
@@ -601,6 +680,94 @@ __global__ void __launch_bounds__(64) k_near(
     double2 *row = anear + (int64_t)(row_first + cl) * rs;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
+  }
+}
+
+// k_near for a block of DG densities per work-group (grid.y = density blocks): same items and
+// lanes, the sources' charges and dipoles of the DG densities staged together, one pair geometry
+// for all of them. Densities past n_dens (a last partial block) get zero strengths and no rows.
+template <int KIND, int PQ, int DG>
+__global__ void __launch_bounds__(64) k_near_md(
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, double2 *__restrict__ anear, int rs, int64_t src_st,
+    int64_t row_st, int n_dens) {
+  __shared__ double2 t_xy[kNearBatch];
+  __shared__ double t_q[(KIND & 1) ? DG : 1][(KIND & 1) ? kNearBatch : 1];
+  __shared__ double2 t_d[(KIND & 2) ? DG : 1][(KIND & 2) ? kNearBatch : 1];
+  const int32_t w = (int32_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  const int jd0 = (int)blockIdx.y * DG;
+  const int ng = min(DG, n_dens - jd0);
+  const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x, lg = i1.y;
+  const int nsl = 64 >> lg;
+  const int cl = lane >> (6 - lg);
+  const int sl = lane & (nsl - 1);
+  const bool active = cl < n_ctr;
+  const int32_t c = ctr_first + (active ? cl : 0);
+  const double2 cc = cxy[c];
+  const double r = cr[c];
+  const double ir = 1.0 / r;
+  NearAccMD<KIND, PQ, DG> acc;
+  acc.zero();
+  for (int32_t base = 0; base < len; base += kNearBatch) {
+    const int nb = min(kNearBatch, (int)(len - base));
+    __syncthreads();
+    for (int j = lane; j < nb; j += 64) {
+      const int32_t s = near_src[off + base + j];
+      t_xy[j] = sxy[s];
+#pragma unroll
+      for (int g = 0; g < DG; ++g) {
+        const int64_t o = (int64_t)(jd0 + g) * src_st + s;
+        if (KIND & 1) t_q[g][j] = g < ng ? sq[o] : 0.0;
+        if (KIND & 2) t_d[g][j] = g < ng ? sdip[o] : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < nb; j += nsl) {
+        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
+        double q[DG];
+        double2 dr[DG];
+#pragma unroll
+        for (int g = 0; g < DG; ++g) {
+          q[g] = (KIND & 1) ? t_q[g][j] : 0.0;
+          dr[g] = (KIND & 2) ? cscale(t_d[g][j], ir) : make_double2(0.0, 0.0);
+        }
+        acc.add(z, q, dr);
+      }
+    }
+  }
+  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int g = 0; g < DG; ++g) {
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) {
+        acc.a[g][m].x += __shfl_xor(acc.a[g][m].x, o, 64);
+        acc.a[g][m].y += __shfl_xor(acc.a[g][m].y, o, 64);
+      }
+      if (KIND & 1) {
+        acc.logsum[g] += __shfl_xor(acc.logsum[g], o, 64);
+        acc.qsum[g] += __shfl_xor(acc.qsum[g], o, 64);
+      }
+    }
+  }
+  if (active && sl == 0) {
+    const double logr = log(r);
+#pragma unroll
+    for (int g = 0; g < DG; ++g) {
+      if (g >= ng) break;
+      double2 alpha[PQ + 1];
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+      acc.finish(g, alpha, logr);
+      double2 *row = anear + (int64_t)(jd0 + g) * row_st + (int64_t)(row_first + cl) * rs;
+#pragma unroll
+      for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
+    }
   }
 }
 
@@ -913,7 +1080,18 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
                         const Strides &S) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
-  if (n > 0)
+  // Densities per work item: two by default. Four hold 4 (PQ + 1) complex accumulators per lane,
+  // which above order 6 leaves one or two waves per SIMD and runs slower than two.
+  const int dg = nd < 2 ? 1 : ctx->params.near_dens_group > 0 ? ctx->params.near_dens_group : 2;
+  if (n > 0 && dg == 4)
+    hipLaunchKernelGGL((k_near_md<KIND, PQ, 4>), dim3(n, (nd + 3) / 4), dim3(64), 0, s, n,
+                       d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip,
+                       d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
+  else if (n > 0 && dg == 2)
+    hipLaunchKernelGGL((k_near_md<KIND, PQ, 2>), dim3(n, (nd + 1) / 2), dim3(64), 0, s, n,
+                       d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip,
+                       d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
+  else if (n > 0)
     hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(n, nd), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
                        d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
                        ctx->params.p_qbx + 1, S.src, S.row);

@@ -195,6 +195,28 @@ def test_density_batches_match_single_evaluations(c1):
 
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
+def test_density_groups_match_one_density_per_item(c1, kind):
+    """The direct-interaction work items take 1, 2 or 4 densities at a time (shared pair geometry,
+    each density's sums in the single-density order): 7 densities, so the last group of 2 and of 4
+    is partial. Every group size gives the same rows bitwise; a size of 3 is rejected."""
+    from paper_1801_04070_amd import GQError
+    n = 7
+    rng = np.random.default_rng(11)
+    h1 = np.stack([gi.fourier_density(c1, seed=int(s)) for s in rng.integers(0, 10**6, n)])
+    h2 = np.stack([gi.fourier_density(c1, seed=int(s)) for s in rng.integers(0, 10**6, n)])
+    outs = {}
+    for dg in (1, 2, 4):
+        q, _ = _ctx(c1, p_qbx=12, p_fmm=30, near_dens_group=dg)
+        outs[dg] = q.eval(kind, _dev(h1), _dev(h2) if kind == 3 else None).cpu().numpy()
+        q.close()
+    assert np.array_equal(outs[1], outs[2]) and np.array_equal(outs[1], outs[4])
+    ref = oracle.qbx_eval(c1, kind, h1[n - 1], h2[n - 1] if kind == 3 else None, p_qbx=12)
+    assert _rel(outs[4][n - 1], ref) < 1e-10
+    with pytest.raises(GQError):
+        _ctx(c1, p_qbx=12, p_fmm=30, near_dens_group=3)
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
 def test_mixed_precision_c1(c1, kind):
     """FP32 box expansions (P2M, M2M, M2L on FP32 matrix cores, L2L) with power-of-two level
     scaling at p_fmm = 16 against the FP64 oracle: gate 1e-6."""
