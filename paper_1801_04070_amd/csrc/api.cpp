@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -43,6 +44,7 @@ void free_workspace(gq_ctx *ctx) {
   ctx->ws_allocations.clear();
   ctx->ws_batch = 0;
   ctx->d.sq = nullptr; ctx->d.sdip = nullptr; ctx->d.M = nullptr; ctx->d.L = nullptr;
+  ctx->d.Lf = nullptr;
   ctx->d.anear = nullptr; ctx->d.tv = nullptr;
 }
 
@@ -316,16 +318,44 @@ gq_status upload_all(gq_ctx *ctx) {
     std::vector<int> depth(nb, 0);
     for (int l = 0; l < t.n_levels; ++l)
       for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) depth[b] = l;
-    int m2m_first = t.n_levels, l2l_first = t.n_levels;
+    int m2m_first = t.n_levels;
     for (int64_t b = 0; b < nb; ++b) {
       for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e)
         m2m_first = std::min(m2m_first, depth[t.list2.idx[e]]);
       for (int64_t e = t.list3f.start[b]; e < t.list3f.start[b + 1]; ++e)
         m2m_first = std::min(m2m_first, depth[t.list3f.idx[e]]);
-      if (t.list2.row_size(b) > 0 || t.list4f.row_size(b) > 0) l2l_first = std::min(l2l_first, depth[b]);
     }
     ctx->m2m_first_depth = m2m_first;
-    ctx->l2l_first_depth = l2l_first;
+  }
+  // Stage 7 gather lists: every box owning centers, with its ancestors (top-down) that receive
+  // List 2 or List 4 far contributions of their own, and the two shift ratios of each pair
+  {
+    std::vector<int32_t> sink, anc, chain;
+    std::vector<double> tw;
+    std::vector<double> side = t.level_side_table;
+    if (side.empty())
+      for (int l = 0; l < t.n_levels; ++l) side.push_back(std::ldexp(t.side, -l));
+    for (int64_t b = 0; b < nb; ++b) {
+      if (t.ctr_end[b] <= t.ctr_begin[b]) continue;
+      chain.clear();
+      for (int32_t a = t.parent[b]; a >= 0; a = t.parent[a])
+        if (t.list2.row_size(a) > 0 || t.list4f.row_size(a) > 0) chain.push_back(a);
+      sink.insert(sink.end(), {(int32_t)b, (int32_t)anc.size(),
+                               (int32_t)(anc.size() + chain.size()), 0});
+      for (auto it = chain.rbegin(); it != chain.rend(); ++it) {
+        const int32_t a = *it;
+        const std::complex<double> dc(t.cx[b] - t.cx[a], t.cy[b] - t.cy[a]);
+        const std::complex<double> tt = dc / side[t.level[a]], w = side[t.level[b]] / dc;
+        tw.insert(tw.end(), {tt.real(), tt.imag(), w.real(), w.imag()});
+        anc.push_back(a);
+      }
+    }
+    ctx->n_l2g_sinks = (int64_t)sink.size() / 4;
+    if (!sink.empty()) {
+      GQ_TRY(upload(ctx, d.l2g_sink, sink.data(), sink.size() / 4));
+      GQ_TRY(upload(ctx, d.l2g_anc, anc.data(), anc.size()));
+      GQ_TRY(upload(ctx, d.l2g_tw, tw.data(), tw.size() / 4));
+    }
   }
   // lists
   GQ_TRY(upload(ctx, d.v_start, to_i32(t.list2.start).data(), nb + 1));
@@ -341,15 +371,13 @@ gq_status upload_all(gq_ctx *ctx) {
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->params.p_qbx;
   GQ_TRY(upload(ctx, d.m2m_rt, tb.m2m_rt.data(), tb.m2m_rt.size()));
-  GQ_TRY(upload(ctx, d.l2l_rt, tb.l2l_rt.data(), tb.l2l_rt.size()));
   GQ_TRY(upload(ctx, d.omega, tb.omega.data(), tb.omega.size() / 2));
   GQ_TRY(upload(ctx, d.m2l_bt, tb.m2l_bt.data(), tb.m2l_bt.size()));
   if (ctx->params.precision == GQ_MIXED_FP32) {
     auto f32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
-    const std::vector<float> rm = f32(tb.m2m_rt), rl = f32(tb.l2l_rt), bt = f32(tb.m2l_bt),
+    const std::vector<float> rm = f32(tb.m2m_rt), bt = f32(tb.m2l_bt),
                              om = f32(tb.omega), op = f32(tb.opow);
     GQ_TRY(upload(ctx, d.m2m_rt_f, rm.data(), rm.size()));
-    GQ_TRY(upload(ctx, d.l2l_rt_f, rl.data(), rl.size()));
     GQ_TRY(upload(ctx, d.m2l_bt_f, bt.data(), bt.size()));
     GQ_TRY(upload(ctx, d.omega_f, om.data(), om.size() / 2));
     GQ_TRY(upload(ctx, d.opow_f, op.data(), op.size() / 2));
@@ -365,6 +393,10 @@ gq_status upload_all(gq_ctx *ctx) {
     for (int m = 0; m <= PQ; ++m)
       for (int k = 0; k < P1; ++k) m2q[(size_t)m * P1 + k] = k == 0 ? 0.0 : C(m + k - 1, k - 1);
     GQ_TRY(upload(ctx, d.l2q_binom, l2q.data(), l2q.size()));
+    std::vector<double> bt((size_t)P1 * P1);
+    for (int k = 0; k < P1; ++k)
+      for (int m = 0; m < P1; ++m) bt[(size_t)k * P1 + m] = C(k, m);
+    GQ_TRY(upload(ctx, d.l2g_binom_t, bt.data(), bt.size()));
     GQ_TRY(upload(ctx, d.m2q_binom, m2q.data(), m2q.size()));
   }
   return GQ_OK;
@@ -381,6 +413,7 @@ gq_status ensure_workspace(gq_ctx *ctx, int nd) {
   GQ_TRY(alloc_ws(ctx, d.sdip, n * ctx->ns));
   GQ_TRY(alloc_ws(ctx, d.M, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.L, n * nb * P1));
+  GQ_TRY(alloc_ws(ctx, d.Lf, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1)));
   GQ_TRY(alloc_ws(ctx, d.tv, n * 2 * ctx->nt));
   ctx->ws_batch = nd;
@@ -405,6 +438,7 @@ gq_status launch_kind_on(gq_ctx *ctx, hipStream_t s, int kind, const double *d1,
   ctx->d.sdip += (int64_t)slot0 * ctx->ns;
   ctx->d.M += (int64_t)slot0 * nb * P1;
   ctx->d.L += (int64_t)slot0 * nb * P1;
+  ctx->d.Lf += (int64_t)slot0 * nb * P1;
   ctx->d.anear += (int64_t)slot0 * ctx->n_near_rows * (ctx->params.p_qbx + 1);
   ctx->d.tv += (int64_t)slot0 * 2 * ctx->nt;
   ctx->stream = s;

@@ -209,8 +209,8 @@ __global__ void __launch_bounds__(256) k_m2m2(int32_t box0, const int32_t *__res
 // (+ a_0 log|s o| in beta_0) on the matrix cores: the fixed real matrix B is the A operand of
 // v_mfma_f64_16x16x4f64 (RT row tiles x 4 RT k-steps, held in registers for the whole box), and a
 // batch of 8 List 2 pairs gives the 16 real columns (re/im of a_k o^-k per pair) of the B operand.
-// The 16 x 16 results are scaled by o^-m per pair and summed over the pairs with xor shuffles
-// inside each 16-lane group. Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane
+// The 16 x 16 results are scaled by o^-m per pair and written to LDS by pair and row, where lane m
+// sums row m over the batch (one LDS round trip instead of a shuffle tree per row). Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane
 // i + 16 k, B[k][j] in lane j + 16 k, D[g + 4 v][j] in element v of lane j + 16 g.
 typedef double gq_d4 __attribute__((ext_vector_type(4)));
 typedef float gq_f4 __attribute__((ext_vector_type(4)));
@@ -249,7 +249,6 @@ __global__ void __launch_bounds__(64) k_far_local(
   using R = typename Scalar<E>::T;
   using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
-  __shared__ double2 Ls[16 * RT];
   const int32_t b = tboxes[blockIdx.x];
   {
     const int64_t jd = blockIdx.y;
@@ -270,11 +269,9 @@ __global__ void __launch_bounds__(64) k_far_local(
       const int i = 16 * rt + c16, k = 4 * ks + g;
       A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
     }
-  double2 Lacc[RT][4];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Lacc[rt][v] = make_double2(0.0, 0.0);
+  // lane m sums coefficient m; a batch's rows, scaled per pair, are transposed through LDS
+  __shared__ double2 Pt[8][16 * RT];
+  double2 acc = make_double2(0.0, 0.0);
   double logsum0 = 0.0;
   const int pr = c16 >> 1, comp = c16 & 1;
   const int32_t v0 = v_start[b], v1 = v_start[b + 1];
@@ -310,15 +307,12 @@ __global__ void __launch_bounds__(64) k_far_local(
         const int m = 16 * rt + Mfma16<R>::row(g, v);
         const double y = C[rt][v];
         const double yo = __shfl_xor(y, 1, 64);
-        double2 contrib = make_double2(0.0, 0.0);
-        if (pv && !comp && m < P1) contrib = cmul(make_double2(y, yo), to_d2(op[m]));
-#pragma unroll
-        for (int o = 8; o >= 1; o >>= 1) {
-          contrib.x += __shfl_xor(contrib.x, o, 64);
-          contrib.y += __shfl_xor(contrib.y, o, 64);
-        }
-        Lacc[rt][v] = cadd(Lacc[rt][v], contrib);
+        if (pv && !comp && m < P1) Pt[pr][m] = cmul(make_double2(y, yo), to_d2(op[m]));
       }
+    __syncthreads();
+    if (lane < P1)
+      for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
+    __syncthreads();
     // a_0 log|s o| of pair `lane` of the batch
     if (lane < nbat)
       logsum0 += (double)M[(int64_t)v_idx[j0 + lane] * P1].x * (logs + ologabs[v_off[j0 + lane]]);
@@ -326,19 +320,11 @@ __global__ void __launch_bounds__(64) k_far_local(
   // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) logsum0 += __shfl_xor(logsum0, o, 64);
-  if (c16 == 0) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Ls[16 * rt + Mfma16<R>::row(g, v)] = Lacc[rt][v];
-  }
-  __syncthreads();
   // P2L (eq. (local) about c_b) for the sources of List 4 far boxes, 16 sources at a time: lane
   // j < 16 forms source j's contributions to every coefficient with a running power of 1/y and
   // stores them in LDS; lane m then sums column m.
   __shared__ double2 Pc[16][16 * RT];
   const int m = lane;
-  double2 acc = m < P1 ? Ls[m] : make_double2(0.0, 0.0);
   if (m == 0) acc.x += logsum0;
   const double2 c = bc[b];
   const double is = level_inv_side[lev];
@@ -375,73 +361,107 @@ __global__ void __launch_bounds__(64) k_far_local(
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 7, L2L for the target-or-ancestor boxes of one level (eq. (l2l), factored through the
-// real matrix Rl): child_m += w_q^-m sum_{k>=m} Rl[m][k] (w_q^k parent_k).
-template <typename E>
-__global__ void __launch_bounds__(64) k_l2l(int32_t box0, const int32_t *__restrict__ bparent,
-                                            const int8_t *__restrict__ bquad,
-                                            const int32_t *__restrict__ is_tbox,
-                                            const typename Scalar<E>::T *__restrict__ Rt,
-                                            const E *__restrict__ omega, int P1,
-                                            E *__restrict__ L, int64_t box_st) {
-  __shared__ E X[64];
-  const int32_t b = box0 + blockIdx.x;
-  const int m = threadIdx.x;
-  if (!is_tbox[b]) return;  // uniform per block
-  L += (int64_t)blockIdx.y * box_st;
-  const int32_t p = bparent[b];
-  const int q = bquad[b];
-  if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
-  __syncthreads();
-  if (m >= P1) return;
-  E acc = mk2<E>(0.0, 0.0);
-  for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
-  const E w = omega[q * 8 + (m & 7)];
-  L[(int64_t)b * P1 + m] = cfma(mk2<E>(w.x, -w.y), acc, L[(int64_t)b * P1 + m]);
-}
-
-// One wavefront adds the L2L of parent p's local into child c's (as k_l2l), wave-private LDS.
-template <typename E>
-__device__ __forceinline__ void l2l_child_wave(int32_t p, int32_t c, int q, int m,
-                                               const typename Scalar<E>::T *__restrict__ Rt,
-                                               const E *__restrict__ omega, int P1,
-                                               E *__restrict__ L, E *X) {
-  if (m < P1) X[m] = cmul(L[(int64_t)p * P1 + m], omega[q * 8 + (m & 7)]);
-  __builtin_amdgcn_wave_barrier();
-  if (m < P1) {
-    E acc = mk2<E>(0.0, 0.0);
-    for (int k = m; k < P1; ++k) acc = caxpy(Rt[k * P1 + m], X[k], acc);
-    const E w = omega[q * 8 + (m & 7)];
-    L[(int64_t)c * P1 + m] = cfma(mk2<E>(w.x, -w.y), acc, L[(int64_t)c * P1 + m]);
+// Stage 7 as one gather: the local of a box b that owns centers is its own local (M2L + P2L)
+// plus every ancestor a's own local shifted to c_b (eq. (l2l) applied across the level gap in
+// one step; translations compose, so this equals the level-by-level pass).
+//
+// With t = (c_b - c_a)/s_a, u = (c_b - c_a)/s_b and alpha the scaled coefficients of a,
+//   beta_m = sum_{j>=m} C(j,m) t^(j-m) (s_b/s_a)^m alpha_j = u^-m sum_{j>=m} C(j,m) (t^j alpha_j),
+// so the pair-dependent parts are diagonal and the fixed binomial matrix runs on the FP64 matrix
+// cores, 8 ancestors (16 real columns) per step, as in k_far_local. |t| < 2^-1/2 and |u| > 2^-1/2
+// for every ancestor: t^j only underflows where its term is negligible and u^-m < 2^(m/2).
+// One wavefront per box; arithmetic in FP64 whatever the storage type E.
+template <int RT, typename E>
+__global__ void __launch_bounds__(64) k_l2l_gather(
+    const int4 *__restrict__ sinks, const int32_t *__restrict__ anc_idx,
+    const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
+    const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st) {
+  constexpr int KS = 4 * RT;
+  __shared__ double2 Pt[8][16 * RT];  // one batch's shifted rows, per ancestor
+  const int4 sk = sinks[blockIdx.x];  // box, first pair, end of pairs
+  const int32_t b = sk.x, a0 = sk.y, a1 = sk.z;
+  {
+    const int64_t jd = blockIdx.y;
+    L += jd * box_st;
+    Lf += jd * box_st;
   }
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Two levels of Stage 7 in one launch: work-group = one box P of the level above both, 16 waves.
-// Waves 0-3 take P's children through L2L from P; after the work-group barrier, wave 4 i + j
-// takes grandchild j of child i through L2L from that child. Only target-or-ancestor boxes
-// receive locals.
-template <typename E>
-__global__ void __launch_bounds__(1024) k_l2l2(int32_t box0, const int32_t *__restrict__ bchild,
-                                               const int8_t *__restrict__ bquad,
-                                               const int32_t *__restrict__ is_tbox,
-                                               const typename Scalar<E>::T *__restrict__ Rt,
-                                               const E *__restrict__ omega, int P1,
-                                               E *__restrict__ L, int64_t box_st) {
-  __shared__ E X[16][64];
-  const int32_t p = box0 + blockIdx.x;
-  const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
-  if (!is_tbox[p]) return;  // uniform per work-group
-  L += (int64_t)blockIdx.y * box_st;
-  if (w < 4) {
-    const int32_t c = bchild[4 * (int64_t)p + w];
-    if (c >= 0 && is_tbox[c]) l2l_child_wave<E>(p, c, bquad[c], m, Rt, omega, P1, L, X[w]);
+  const int lane = threadIdx.x;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int pr = c16 >> 1, comp = c16 & 1;
+  // C(k, i) is zero below the diagonal: row tile rt only needs k-steps ks >= 4 rt
+  double A[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + c16, k = 4 * ks + g;
+      A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? binom_t[k * P1 + i] : 0.0;
+    }
+  double2 acc = make_double2(0.0, 0.0);  // lane m: coefficient m summed over the ancestors
+  // pair records of the first batch; each later batch's are fetched while the current one runs
+  const double4 unit = make_double4(0.0, 0.0, 1.0, 0.0);  // an idle column: t = 0, 1/u = 1
+  int32_t a = (a0 + pr < a1) ? anc_idx[a0 + pr] : -1;
+  double4 tw = (a0 + pr < a1) ? anc_tw[a0 + pr] : unit;
+  for (int32_t j0 = a0; j0 < a1; j0 += 8) {
+    const int nbat = min(8, (int)(a1 - j0));
+    const bool pv = a >= 0;
+    const E *La = L + (int64_t)(pv ? a : 0) * P1;
+    const int32_t jn = j0 + 8 + pr;
+    const int32_t a_next = jn < a1 ? anc_idx[jn] : -1;
+    const double4 tw_next = jn < a1 ? anc_tw[jn] : unit;
+    const double2 t = make_double2(tw.x, tw.y), w = make_double2(tw.z, tw.w);
+    // t^k alpha_k for k = g, g + 4, ...
+    double2 pw = make_double2(1.0, 0.0);
+    for (int e = 0; e < g; ++e) pw = cmul(pw, t);
+    const double2 t2 = cmul(t, t), t4 = cmul(t2, t2);
+    double Bf[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g;
+      double x = 0.0;
+      if (pv && k < P1) {
+        const double2 v = cmul(pw, to_d2(La[k]));
+        x = comp ? v.y : v.x;
+      }
+      Bf[ks] = x;
+      pw = cmul(pw, t4);
+    }
+    gq_d4 C[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      C[rt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 4 * rt; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
+    }
+    // row m = 16 rt + g + 4 v of column pair pr: times u^-m, into Pt[pr][m]
+    double2 wg = make_double2(1.0, 0.0);
+    for (int e = 0; e < g; ++e) wg = cmul(wg, w);
+    const double2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4), w16 = cmul(w8, w8);
+    double2 wr = wg;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      double2 wv = wr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + Mfma16<double>::row(g, v);
+        const double y = C[rt][v];
+        const double yo = __shfl_xor(y, 1, 64);
+        if (!comp) Pt[pr][m] = cmul(make_double2(y, yo), wv);
+        wv = cmul(wv, w4);
+      }
+      wr = cmul(wr, w16);
+    }
+    __syncthreads();
+    if (lane < P1)
+      for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
+    __syncthreads();
+    a = a_next;
+    tw = tw_next;
   }
-  __syncthreads();
-  const int32_t c = bchild[4 * (int64_t)p + (w >> 2)];
-  if (c < 0 || !is_tbox[c]) return;
-  const int32_t gc = bchild[4 * (int64_t)c + (w & 3)];
-  if (gc >= 0 && is_tbox[gc]) l2l_child_wave<E>(c, gc, bquad[gc], m, Rt, omega, P1, L, X[w]);
+  if (lane < P1) {
+    const double2 own = to_d2(L[(int64_t)b * P1 + lane]);
+    Lf[(int64_t)b * P1 + lane] = from_d2<E>(cadd(own, acc));
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1061,16 +1081,16 @@ hipError_t launch_gather(gq_ctx *ctx, const double *d1, int64_t ld1, const doubl
 // Translation tables in the expansion precision.
 template <typename E> struct ExpTables;
 template <> struct ExpTables<double2> {
-  const double *m2m_rt, *l2l_rt, *m2l_bt;
+  const double *m2m_rt, *m2l_bt;
   const double2 *omega, *opow;
   explicit ExpTables(const DevBuffers &d)
-      : m2m_rt(d.m2m_rt), l2l_rt(d.l2l_rt), m2l_bt(d.m2l_bt), omega(d.omega), opow(d.opow) {}
+      : m2m_rt(d.m2m_rt), m2l_bt(d.m2l_bt), omega(d.omega), opow(d.opow) {}
 };
 template <> struct ExpTables<float2> {
-  const float *m2m_rt, *l2l_rt, *m2l_bt;
+  const float *m2m_rt, *m2l_bt;
   const float2 *omega, *opow;
   explicit ExpTables(const DevBuffers &d)
-      : m2m_rt(d.m2m_rt_f), l2l_rt(d.l2l_rt_f), m2l_bt(d.m2l_bt_f), omega(d.omega_f),
+      : m2m_rt(d.m2m_rt_f), m2l_bt(d.m2l_bt_f), omega(d.omega_f),
         opow(d.opow_f) {}
 };
 
@@ -1130,6 +1150,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const ExpTables<E> X(d);
   E *M = reinterpret_cast<E *>(d.M);
   E *L = reinterpret_cast<E *>(d.L);
+  E *Lf = reinterpret_cast<E *>(d.Lf);
   const int P1 = ctx->params.p_fmm + 1;
   const hipStream_t st = ctx->stream;
   const Strides S = strides(ctx);
@@ -1209,25 +1230,12 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
                        d.xf_idx, d.bsrc0, d.bsrc1, M, X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq,
                        d.sdip, P1, L, S.src, S.box);
   }
-  {
+  if (ctx->n_l2g_sinks > 0) {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    // two levels per launch where two remain (a work-group per box of the level above them)
-    for (int l = std::max(1, ctx->l2l_first_depth + 1); l < t.n_levels;) {
-      if (l + 1 < t.n_levels) {
-        const int32_t b0 = (int32_t)t.level_start[l - 1];
-        const int32_t nb = (int32_t)(t.level_start[l] - b0);
-        if (nb > 0)
-          hipLaunchKernelGGL(k_l2l2<E>, dim3(nb, nd), dim3(1024), 0, st, b0, d.bchild, d.bquad,
-                             d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
-        l += 2;
-      } else {
-        const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-        if (nb > 0)
-          hipLaunchKernelGGL(k_l2l<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bparent, d.bquad,
-                             d.is_tbox, X.l2l_rt, X.omega, P1, L, S.box);
-        l += 1;
-      }
-    }
+    auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
+              : P1 <= 48 ? k_l2l_gather<3, E> : k_l2l_gather<4, E>;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_sinks, nd), dim3(64), 0, st, d.l2g_sink,
+                       d.l2g_anc, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;
@@ -1236,7 +1244,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_center_bucket<KIND, P, E>(ctx, bk, nd, st, S, L); break;
+  case P: launch_center_bucket<KIND, P, E>(ctx, bk, nd, st, S, Lf); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }

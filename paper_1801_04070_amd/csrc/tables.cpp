@@ -35,14 +35,12 @@ void build_tables(Tables &t, int p, int max_pq) {
   };
 
   t.m2m.assign((size_t)4 * P1 * P1 * 2, 0.0);
-  t.l2l.assign((size_t)4 * P1 * P1 * 2, 0.0);
   for (int q = 0; q < 4; ++q) {
     const long double sx = (q & 1) ? 0.5L : -0.5L, sy = (q & 2) ? 0.5L : -0.5L;
     // child center - parent center = s_child * u, u = (sx, sy)
     const cld u(sx, sy);
     const cld mv = u;  // -v with v = (parent - child)/s_child = -u
     double *M = &t.m2m[(size_t)q * P1 * P1 * 2];
-    double *L = &t.l2l[(size_t)q * P1 * P1 * 2];
     // M2M, eq. (m2m) with y = parent - child: alpha_m = -a_0 (-y)^m/m + sum_k C(m-1,k-1) a_k (-y)^(m-k)
     for (int m = 0; m <= p; ++m) {
       const long double s = std::pow(2.0L, -(long double)m);
@@ -55,20 +53,12 @@ void build_tables(Tables &t, int p, int max_pq) {
         M[((size_t)m * P1 + k) * 2 + 1] = (double)val.imag();
       }
     }
-    // L2L, eq. (l2l) with y = child - parent: beta_m = sum_{k>=m} C(k,m) b_k y^(k-m)
-    for (int m = 0; m <= p; ++m)
-      for (int k = m; k <= p; ++k) {
-        cld val = cpow(u, k - m) * (C(k, m) * std::pow(2.0L, -(long double)k));
-        L[((size_t)m * P1 + k) * 2] = (double)val.real();
-        L[((size_t)m * P1 + k) * 2 + 1] = (double)val.imag();
-      }
   }
 
   // factored shifts (see tables.hpp): |u| = 2^-1/2 for every quadrant
   {
     const long double au = std::sqrt(0.5L);
     t.m2m_rt.assign((size_t)P1 * P1, 0.0);
-    t.l2l_rt.assign((size_t)P1 * P1, 0.0);
     for (int m = 0; m <= p; ++m) {
       const long double s = std::pow(2.0L, -(long double)m);
       for (int k = 0; k <= m; ++k) {
@@ -78,9 +68,6 @@ void build_tables(Tables &t, int p, int max_pq) {
         else v = C(m - 1, k - 1) * std::pow(au, (long double)(m - k)) * s;
         t.m2m_rt[(size_t)k * P1 + m] = (double)v;
       }
-      for (int k = m; k <= p; ++k)
-        t.l2l_rt[(size_t)k * P1 + m] =
-            (double)(C(k, m) * std::pow(2.0L, -(long double)k) * std::pow(au, (long double)(k - m)));
     }
     t.omega.assign(4 * 8 * 2, 0.0);
     for (int q = 0; q < 4; ++q) {

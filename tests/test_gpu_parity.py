@@ -89,6 +89,21 @@ def test_fmm_matches_oracle_multi_curve(kind, count_mode):
     assert err < 1e-10
 
 
+@pytest.mark.parametrize("p_fmm", [40, 63])
+def test_fmm_deep_tree_high_order(p_fmm):
+    """A deep tree (n_max 8) at high FMM orders: the downward pass shifts locals across many
+    levels at once and runs the 3- and 4-tile forms of its matrix-core step."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=64, seed=21, box=12.0)
+    mu, mu2 = _densities(g, 5)
+    q, stats = _ctx(g, p_qbx=12, p_fmm=p_fmm, n_max=8)
+    assert stats["n_levels"] >= 9, stats["n_levels"]
+    gpu = _run(q, 3, mu, mu2)
+    ref = oracle.qbx_eval(g, 3, mu, mu2, p_qbx=12)
+    err = _rel(gpu, ref)
+    print(f"deep tree levels={stats['n_levels']} p_fmm={p_fmm} rel_err={err:.3e}")
+    assert err < 1e-12
+
+
 def test_fmm_green_identity_c2_sampled():
     """Full-size 131072-source workload: Green's formula S(du/dn) - D(u) vs the oracle at
     sampled targets (the oracle evaluates them one by one) and vs u/2."""
