@@ -733,6 +733,11 @@ gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
       gq_destroy(ctx);
       return fail(nullptr, GQ_EHIP, "stream/event creation failed");
     }
+    const hipError_t e = gq::upload_log_table();
+    if (e != hipSuccess) {
+      gq_destroy(ctx);
+      return fail(nullptr, GQ_EHIP, std::string("log table upload: ") + hipGetErrorString(e));
+    }
   }
   gq_default_params(&ctx->params);
   *out = ctx;

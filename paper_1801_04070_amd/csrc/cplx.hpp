@@ -34,33 +34,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y;
 }
 
-// Natural log of a positive normal double: x = m 2^e with m in [2^-1/2, 2^1/2), then
-// log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, by its odd series through s^21 (the
-// next term is below 1e-17 |s|), and e log 2 with log 2 split into a head with trailing zero bits
-// and a tail. Absolute error about 1e-16 (an ulp of values near 1).
-__device__ __forceinline__ double log_pos(double x) {
-  int e;
-  double m = frexp(x, &e);
-  const bool lo = m < 0.70710678118654752440;
-  m = lo ? 2.0 * m : m;
-  const double fe = (double)(lo ? e - 1 : e);
-  const double s = (m - 1.0) * rcp_nr(m + 1.0);
-  const double s2 = s * s;
-  double p = 1.0 / 21.0;
-  p = fma(p, s2, 1.0 / 19.0);
-  p = fma(p, s2, 1.0 / 17.0);
-  p = fma(p, s2, 1.0 / 15.0);
-  p = fma(p, s2, 1.0 / 13.0);
-  p = fma(p, s2, 1.0 / 11.0);
-  p = fma(p, s2, 1.0 / 9.0);
-  p = fma(p, s2, 1.0 / 7.0);
-  p = fma(p, s2, 1.0 / 5.0);
-  p = fma(p, s2, 1.0 / 3.0);
-  const double t = 2.0 * s;
-  const double lm = fma(t * s2, p, t);
-  return fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, lm));
-}
-
 __host__ __device__ __forceinline__ double2 cinv(double2 a) {
   double s = 1.0 / (a.x * a.x + a.y * a.y);
   return make_double2(a.x * s, -a.y * s);

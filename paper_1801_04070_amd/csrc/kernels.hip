@@ -18,6 +18,29 @@ namespace gq {
 
 namespace {
 
+// Natural log of a positive normal double by table lookup and a short series: x = M 2^(e-1) with
+// M in [1, 2); the top 7 bits of M pick j, c_j ~ 1/(1 + (j + 1/2)/128) and T_j = -log c_j (both
+// rounded to FP64 on the host, T_j from the rounded c_j), so log M = T_j + log1p(r) with
+// r = M c_j - 1 formed by one FMA, |r| <= 2^-8, and log1p(r) through r^7 (next term < 1e-20).
+// log 2 is split into a head with trailing zero bits and a tail. Absolute error about 1e-16.
+constexpr int kLogTab = 128;
+__device__ double2 g_log_tab[kLogTab];
+
+__device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ tab) {
+  int e;
+  const double M = 2.0 * frexp(x, &e);
+  const double2 ct = tab[(__double2hiint(M) >> 13) & (kLogTab - 1)];
+  const double r = fma(M, ct.x, -1.0);
+  double p = fma(r, 1.0 / 7.0, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -0.25);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  const double l1 = fma(r * r, p, r);
+  const double fe = (double)(e - 1);
+  return fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, ct.y) + l1);
+}
+
 constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 
 // ------------------------------------------------------------------------------------------
@@ -328,6 +351,7 @@ __global__ void __launch_bounds__(64) k_far_local(
   if (m == 0) acc.x += logsum0;
   const double2 c = bc[b];
   const double is = level_inv_side[lev];
+  const double2 *lt = g_log_tab;
   for (int32_t j = xf_start[b]; j < xf_start[b + 1]; ++j) {
     const int32_t dd = xf_idx[j];
     for (int32_t s0 = bsrc0[dd]; s0 < bsrc1[dd]; s0 += 16) {
@@ -342,7 +366,7 @@ __global__ void __launch_bounds__(64) k_far_local(
         // coefficient 0: q log|s y| + d/y;  coefficient k: -q y^-k / k + d y^-(k+1)
         double2 pw = inv;
         double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
-        if (KIND & 1) c0.x += q * (logs + 0.5 * log_pos(y.x * y.x + y.y * y.y));
+        if (KIND & 1) c0.x += q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt));
         Pc[lane][0] = c0;
         for (int k = 1; k < P1; ++k) {
           double2 ck = (KIND & 1) ? cscale(pw, -q / k) : make_double2(0.0, 0.0);
@@ -478,12 +502,12 @@ struct NearAcc {
     logsum = 0.0;
     qsum = 0.0;
   }
-  __device__ __forceinline__ void add(double2 z, double q, double2 dr) {
+  __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
     const double r2 = z.x * z.x + z.y * z.y;
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND == 1) {
-      logsum = fma(q, log_pos(r2), logsum);
+      logsum = fma(q, log_tab(r2, lt), logsum);
       qsum += q;
       double2 pw = inv;
 #pragma unroll
@@ -499,7 +523,7 @@ struct NearAcc {
         if (m < PQ) pw = cmul(pw, inv);
       }
     } else {
-      logsum = fma(q, log_pos(r2), logsum);
+      logsum = fma(q, log_tab(r2, lt), logsum);
       qsum += q;
       const double2 e = cmul(dr, inv);
       a[0] = cadd(a[0], e);
@@ -540,12 +564,13 @@ struct NearAccMD {
       qsum[g] = 0.0;
     }
   }
-  __device__ __forceinline__ void add(double2 z, const double *q, const double2 *dr) {
+  __device__ __forceinline__ void add(double2 z, const double *q, const double2 *dr,
+                                      const double2 *lt) {
     const double r2 = z.x * z.x + z.y * z.y;
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND & 1) {
-      const double lr = log_pos(r2);
+      const double lr = log_tab(r2, lt);
 #pragma unroll
       for (int g = 0; g < DG; ++g) {
         logsum[g] = fma(q[g], lr, logsum[g]);
@@ -658,6 +683,7 @@ __global__ void __launch_bounds__(64) k_near(
   const double2 cc = cxy[c];
   const double r = cr[c];
   const double ir = 1.0 / r;
+  const double2 *lt = g_log_tab;
   NearAcc<KIND, PQ> acc;
   acc.zero();
   for (int32_t base = 0; base < len; base += kNearBatch) {
@@ -677,7 +703,7 @@ __global__ void __launch_bounds__(64) k_near(
       for (int j = sl; j < nb; j += nsl) {
         const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
         acc.add(z, (KIND & 1) ? t_q[j] : 0.0,
-                (KIND & 2) ? cscale(t_d[j], ir) : make_double2(0.0, 0.0));
+                (KIND & 2) ? cscale(t_d[j], ir) : make_double2(0.0, 0.0), lt);
       }
     }
   }
@@ -731,6 +757,7 @@ __global__ void __launch_bounds__(64) k_near_md(
   const double2 cc = cxy[c];
   const double r = cr[c];
   const double ir = 1.0 / r;
+  const double2 *lt = g_log_tab;
   NearAccMD<KIND, PQ, DG> acc;
   acc.zero();
   for (int32_t base = 0; base < len; base += kNearBatch) {
@@ -757,7 +784,7 @@ __global__ void __launch_bounds__(64) k_near_md(
           q[g] = (KIND & 1) ? t_q[g][j] : 0.0;
           dr[g] = (KIND & 2) ? cscale(t_d[g][j], ir) : make_double2(0.0, 0.0);
         }
-        acc.add(z, q, dr);
+        acc.add(z, q, dr, lt);
       }
     }
   }
@@ -806,7 +833,8 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
                                            const double2 *__restrict__ bc,
                                            const int32_t *__restrict__ blevel,
                                            const double *__restrict__ level_side,
-                                           const E *__restrict__ Md, int P1) {
+                                           const E *__restrict__ Md, int P1,
+                                           const double2 *__restrict__ lt) {
   const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
   const double2 iy = cinv(y);
   const double sd = level_side[blevel[d]];
@@ -825,7 +853,7 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
     wk = cmul(wk, iw);
   }
   // alpha_0 += a_0 log|y| + V_0;  alpha_m += u^m (V_m - a_0/m)
-  alpha[0].x += a0 * 0.5 * log_pos(y.x * y.x + y.y * y.y);
+  alpha[0].x += a0 * 0.5 * log_tab(y.x * y.x + y.y * y.y, lt);
   alpha[0] = cadd(alpha[0], S[0]);
   double2 pm = u;
 #pragma unroll
@@ -849,6 +877,7 @@ __global__ void __launch_bounds__(64) k_m2qbxl(
   HIP_DYNAMIC_SHARED(unsigned char, m2q_lds)
   E *Ms = reinterpret_cast<E *>(m2q_lds);
   const int32_t w = (int32_t)blockIdx.x;
+  const double2 *lt = g_log_tab;
   const int lane = threadIdx.x;
   M += (int64_t)blockIdx.y * box_st;
   anear += (int64_t)blockIdx.y * row_st;
@@ -872,7 +901,8 @@ __global__ void __launch_bounds__(64) k_m2qbxl(
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   if (active)
     for (int32_t e = sl; e < len; e += nsl)
-      m2qbxl_add<PQ, E>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, Ms + e * P1, P1);
+      m2qbxl_add<PQ, E>(alpha, cc, r, wf_idx[off + e], bc, blevel, level_side, Ms + e * P1, P1,
+                        lt);
   for (int o = nsl >> 1; o >= 1; o >>= 1) {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -982,6 +1012,7 @@ __global__ void __launch_bounds__(256) k_direct(
   const double2 cc = active ? cxy[c] : make_double2(0.0, 0.0);
   const double r = active ? cr[c] : 1.0;
   const double ir = 1.0 / r;
+  const double2 *lt = g_log_tab;
   NearAcc<KIND, PQ> acc;
   acc.zero();
   for (int32_t base = 0; base < ns; base += 256) {
@@ -996,7 +1027,8 @@ __global__ void __launch_bounds__(256) k_direct(
     if (!active) continue;
     for (int32_t j = 0; j < n; ++j) {
       const double2 z = make_double2((ts[j].x - cc.x) * ir, (ts[j].y - cc.y) * ir);
-      acc.add(z, (KIND & 1) ? tq[j] : 0.0, (KIND & 2) ? cscale(td[j], ir) : make_double2(0.0, 0.0));
+      acc.add(z, (KIND & 1) ? tq[j] : 0.0, (KIND & 2) ? cscale(td[j], ir) : make_double2(0.0, 0.0),
+              lt);
     }
   }
   if (!active) return;
@@ -1305,6 +1337,16 @@ bool pq_supported(int pq) {
     return true;
   }
   return false;
+}
+
+hipError_t upload_log_table() {
+  double2 tab[kLogTab];
+  for (int j = 0; j < kLogTab; ++j) {
+    const long double mj = 1.0L + ((long double)j + 0.5L) / kLogTab;
+    const double c = (double)(1.0L / mj);
+    tab[j] = make_double2(c, (double)(-std::log((long double)c)));
+  }
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_log_tab), tab, sizeof(tab), 0, hipMemcpyHostToDevice);
 }
 
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
