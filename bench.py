@@ -4,7 +4,8 @@ Headline workload: 16 random star curves, 8192 panels x 16 Gauss-Legendre nodes 
 two QBX centers per node (radius = half the panel arclength), 131072 on-surface targets,
 p_qbx = 12, p_fmm = 30, n_max = 64, t_f = 0.9, FP64. One step evaluates the single-layer and the
 double-layer potential of a Fourier-mode density (all FMM stages, densities resident in HBM) with
-one gq_eval(GQ_S_AND_D) call, which runs the two kinds concurrently on two stream pairs;
+one gq_eval(GQ_S_AND_D) call (one expansion pipeline for both kinds, the direct interactions of
+both kinds in one pass);
 targets/s = 2 x 131072 / step time. Tree and list build is excluded and reported as build_ms.
 
 Variants on the same geometry (reported under "variants", each with its own error against the
@@ -44,9 +45,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QBX-FMM targets/s at 1e-10 rel err, plain vs batched/mixed/learned, 1 GPU"
 GATE = 1e-10
-KERNEL_OF_STAGE = {"near": "k_near", "m2qbxl": "k_m2qbxl", "qbx_center": "k_qbx_center",
-                   "m2l_p2l": "k_far_local", "m2m": "k_m2m", "l2l": "k_l2l", "p2m": "k_p2m",
-                   "gather": "k_gather", "finalize": "k_finalize"}
+# kernels of each stage in a GQ_S_AND_D evaluation of one density
+KERNEL_OF_STAGE = {"near": "k_near_sd", "m2qbxl": "k_m2qbxl", "qbx_center": "k_qbx_center",
+                   "m2l_p2l": "k_far_local", "m2m": "k_m2m", "l2l": "k_l2l_gather",
+                   "p2m": "k_p2m", "gather": "k_gather", "finalize": "k_finalize"}
 
 
 def log(msg):
@@ -364,15 +366,16 @@ def main():
     log(f"bench: with stage profiling {ms_profiled:.3f} ms/step")
     agg, breakdown = per_stage(stages, args.steps)
     n_slots = int((geom.tgt_ctr >= 0).sum())
-    work = {k: perfmodel.stage_work(stats, k, p_qbx, p_fmm, n_slots) for k in (GQ_S, GQ_D)}
+    # each stage interval of a GQ_S_AND_D step covers the work of both kinds (kind 4 below)
+    work = perfmodel.stage_work(stats, 4, p_qbx, p_fmm, n_slots)
     dom = max(agg, key=lambda n: agg[n][0])
     ms_dom, n_dom = agg[dom]
     avg_ms = ms_dom / n_dom
-    flops = (work[GQ_S][dom]["flops"] + work[GQ_D][dom]["flops"]) / 2
-    nbytes = (work[GQ_S][dom]["bytes"] + work[GQ_D][dom]["bytes"]) / 2
+    flops = work[dom]["flops"]
+    nbytes = work[dom]["bytes"]
     peak = perfmodel.MI355X_PEAKS["fp64_vector_tflops"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom] + " (S and D launches)",
+    roofline = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom] + " (S and D of one density)",
                 "timed_region": f"{args.steps} profiled steps (stage events on), "
                                 f"{ms_profiled:.4f} ms/step",
                 "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -381,29 +384,23 @@ def main():
                 "algorithmic_bytes_per_launch": int(nbytes),
                 "achieved_hbm_gbs": round(nbytes / (avg_ms * 1e-3) / 1e9, 1)}
     roofline["traffic"], roofline["traffic_source"] = measured_traffic(KERNEL_OF_STAGE[dom])
-    # the same kernel with nothing else on the device: S then D, no side stream
+    # the same kernels with nothing else on the device: no side stream, one kernel at a time
     q_iso, _ = context(overlap=0)
     out_iso = torch.empty_like(out)
-
-    def iso_step():
-        q_iso.eval(GQ_S, dens, out=out_iso[0:1])
-        q_iso.eval(GQ_D, dens, out=out_iso[1:2])
-
-    _, st_iso = timer.run(q_iso, iso_step, args.steps, 1)
+    _, st_iso = timer.run(q_iso, sd_step(q_iso, dens, out_iso), args.steps, 1)
     agg_iso, breakdown_iso = per_stage(st_iso, args.steps)
     q_iso.close()
     if dom in agg_iso:
         ms_i, n_i = agg_iso[dom]
         ach_i = flops / (ms_i / n_i * 1e-3) / 1e12
-        roofline["isolated"] = {"timed_region": f"{args.steps} profiled steps, S then D, no "
-                                                "side stream (one kernel at a time)",
+        roofline["isolated"] = {"timed_region": f"{args.steps} profiled steps, no side "
+                                                "stream (one kernel at a time)",
                                 "avg_launch_ms": round(ms_i / n_i, 4),
                                 "achieved": round(ach_i, 3), "frac": round(ach_i / peak, 4)}
     stage_rates = {}
     for name, (ms, cnt) in agg.items():
-        if name in work[GQ_S] and cnt:
-            f = (work[GQ_S][name]["flops"] + work[GQ_D][name]["flops"]) / 2
-            stage_rates[name] = round(f / (ms / cnt * 1e-3) / 1e12, 3)
+        if name in work and cnt:
+            stage_rates[name] = round(work[name]["flops"] / (ms / cnt * 1e-3) / 1e12, 3)
     value = 2 * geom.n_tgt / (ms_per_step * 1e-3)
     plain_out = out.cpu().numpy()
     # S then D as two calls on one stream (no concurrency between the kinds)
@@ -414,8 +411,9 @@ def main():
         q.eval(GQ_D, dens, out=out_seq[1:2])
 
     ms_seq = timer.run_plain(seq_step, args.steps, args.warmup)
-    seq_same = bool(np.array_equal(out_seq.cpu().numpy(), plain_out))
-    log(f"bench: S then D sequential {ms_seq:.3f} ms/step (identical: {seq_same})")
+    o_seq = out_seq.cpu().numpy()
+    seq_diff = float(np.abs(o_seq - plain_out).max() / np.abs(plain_out).max())
+    log(f"bench: S then D sequential {ms_seq:.3f} ms/step (max rel diff {seq_diff:.1e})")
     q.close()
 
     # ---- variants ----
@@ -424,7 +422,7 @@ def main():
                                         "unit": "targets/s", "ms_per_step": round(ms_seq, 4),
                                         "steps": args.steps,
                                         "vs_plain": round(ms_per_step / ms_seq, 3),
-                                        "identical_to_plain": seq_same,
+                                        "max_rel_diff_to_plain": seq_diff,
                                         "workload": "S then D as two calls on one stream"}}
     outputs = {}
     if not args.no_variants:

@@ -153,11 +153,13 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params);
  *   kind GQ_S:          out[j] = S dens1[j]
  *   kind GQ_D:          out[j] = D dens1[j]
  *   kind GQ_S_MINUS_D:  out[j] = S dens1[j] - D dens2[j]
- *   kind GQ_S_AND_D:    out[j] = S dens1[j] and out[n_dens + j] = D dens1[j]; the two kinds
- *                       run concurrently on two library streams forked from and joined back to
- *                       the context's stream (separate workspace halves), each kind's stages in
- *                       order, so one kind's latency-bound tree passes overlap the other's bulk
- *                       kernels
+ *   kind GQ_S_AND_D:    out[j] = S dens1[j] and out[n_dens + j] = D dens1[j]; one expansion
+ *                       pipeline over two workspace halves (S, D): the stages that only move
+ *                       expansions run once for both kinds, and for a single density the direct
+ *                       interactions of both kinds are one pass (pair geometry and powers of 1/z
+ *                       shared; its D rows agree with a GQ_D evaluation to rounding, its S rows
+ *                       exactly). The direct-QBX path (gq_eval_direct) runs the two kinds on two
+ *                       library streams forked from and joined back to the context's stream
  * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
  * caller's source order; out is a device array (n_dens, n_tgt) (GQ_S_AND_D: 2 n_dens rows)
  * with row stride ld_out in the caller's target order. dens2 must be NULL unless kind is
@@ -234,6 +236,8 @@ typedef struct {
   double root_side;
   double build_ms;               /* host time of the last gq_build                        */
   int64_t n_point_targets;       /* conventional targets (each with an internal center)   */
+  int64_t n_l2l_sinks;           /* boxes owning centers (they receive complete locals)   */
+  int64_t n_l2l_pairs;           /* (box, ancestor with its own local) shifts in Stage 7   */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);
@@ -263,7 +267,8 @@ gq_status gq_get_tree_array(gq_ctx *ctx, int what, void *dst, int64_t *count);
  * Per-stage device timing for profiling. When enabled, every evaluation records a HIP event pair
  * on the context's stream around each stage; gq_get_stage_times synchronises the stream, adds
  * the elapsed times since the last query into ms[(kind - 1) * GQ_N_STAGES + stage] (caller
- * arrays of 3 * GQ_N_STAGES doubles / int64 counts), and clears the records. Disabled by default.
+ * arrays of 3 * GQ_N_STAGES doubles / int64 counts), and clears the records. GQ_S_AND_D
+ * evaluations record under GQ_S (each stage interval covers both kinds). Disabled by default.
  */
 enum {
   GQ_STAGE_GATHER = 0,   /* densities -> per-source strengths in tree order                */

@@ -482,11 +482,19 @@ gq_status launch_batches(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
                          const double *dens2, int64_t ld2, double *out, int64_t ld_out,
                          bool direct) {
   if (kind == GQ_S_AND_D) {
+    // FMM: one expansion pipeline over 2 nd workspace slots (S in the first nd, D in the rest);
+    // direct QBX: the two kinds on two library streams
     const int batch = (int)std::min<int64_t>(n_dens, gq::kMaxDensBatch / 2);
     for (int64_t j = 0; j < n_dens; j += batch) {
       const int nd = (int)std::min<int64_t>(batch, n_dens - j);
-      GQ_TRY(launch_s_and_d(ctx, dens1 + j * ld1, ld1, out + j * ld_out,
-                            out + (n_dens + j) * ld_out, ld_out, nd, batch, direct));
+      if (direct) {
+        GQ_TRY(launch_s_and_d(ctx, dens1 + j * ld1, ld1, out + j * ld_out,
+                              out + (n_dens + j) * ld_out, ld_out, nd, batch, direct));
+        continue;
+      }
+      hipError_t e = gq::run_eval(ctx, 4, dens1 + j * ld1, ld1, nullptr, 0, out + j * ld_out,
+                                  ld_out, nd, false, out + (n_dens + j) * ld_out);
+      if (e != hipSuccess) return fail(ctx, GQ_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     }
     return GQ_OK;
   }
@@ -905,6 +913,12 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   std::memset(out, 0, sizeof(*out));
   out->n_src = ctx->ns; out->n_ctr = ctx->nc_user; out->n_tgt = ctx->nt;
   out->n_point_targets = ctx->n_pt;
+  for (int64_t b = 0; b < t.n_boxes(); ++b) {
+    if (t.ctr_end[b] <= t.ctr_begin[b]) continue;
+    out->n_l2l_sinks++;
+    for (int32_t a = t.parent[b]; a >= 0; a = t.parent[a])
+      if (t.list2.row_size(a) > 0 || t.list4f.row_size(a) > 0) out->n_l2l_pairs++;
+  }
   out->n_boxes = t.n_boxes(); out->n_levels = t.n_levels; out->n_leaves = t.n_leaves;
   out->n_target_boxes = t.n_target_boxes; out->n_suspended_centers = t.n_suspended;
   out->n_list1 = (int64_t)t.list1.idx.size(); out->n_list2 = (int64_t)t.list2.idx.size();

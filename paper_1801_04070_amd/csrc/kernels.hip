@@ -65,6 +65,11 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
     sq[i] = w * d1[o];
     sdip[i] = cscale(snrm[i], -w * d2[o]);
   }
+  if (KIND == 4) {  // S and D of the same density: charge and dipole from one value
+    const double v = w * d1[o];
+    sq[i] = v;
+    sdip[i] = cscale(snrm[i], v);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -124,6 +129,73 @@ __global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
       for (int j = 0; j < n; ++j) acc = cadd(acc, T[lane * nb + j]);
   }
   if (lane < P1) M[(int64_t)b * P1 + lane] = from_d2<E>(acc);
+}
+
+// k_p2m for S and D of the same density: one pass over the powers y^k writes the single-layer row
+// (-q y^k / k, and q at k = 0) and the double-layer row (d y^(k-1), and 0 at k = 0) of every
+// coefficient into LDS [kind][k][nb] with nb = 32 (16 when P1 > 32), so both kinds' sums run in
+// the order of k_p2m<1> and k_p2m<2>. Lane r sums row r of the 2 P1 rows (S rows first). The D
+// multipole goes d_off coefficients after the S one.
+template <typename E>
+__global__ void __launch_bounds__(64) k_p2m_sd(const int32_t *__restrict__ leaves,
+                                               const double2 *__restrict__ bc,
+                                               const int32_t *__restrict__ blevel,
+                                               const int32_t *__restrict__ bsrc0,
+                                               const int32_t *__restrict__ bsrc1,
+                                               const double *__restrict__ level_inv_side,
+                                               const double2 *__restrict__ sxy,
+                                               const double *__restrict__ sq,
+                                               const double2 *__restrict__ sdip, int P1,
+                                               E *__restrict__ M, int64_t src_st, int64_t box_st,
+                                               int64_t d_off) {
+  HIP_DYNAMIC_SHARED(unsigned char, p2m_lds)
+  double2 *T = reinterpret_cast<double2 *>(p2m_lds);  // [2][P1][nb]
+  __shared__ double invk[64];
+  const int nb = P1 > 32 ? 16 : 32;
+  const int32_t b = leaves[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int64_t jd = blockIdx.y;
+  sq += jd * src_st;
+  sdip += jd * src_st;
+  M += jd * box_st;
+  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
+  const double2 c = bc[b];
+  const double is = level_inv_side[blevel[b]];
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  double2 *TD = T + (int64_t)P1 * nb;
+  const int32_t s0 = bsrc0[b], s1 = bsrc1[b];
+  for (int32_t base = s0; base < s1; base += nb) {
+    const int n = min(nb, (int)(s1 - base));
+    __syncthreads();  // invk ready; the previous batch's rows consumed
+    if (lane < n) {
+      const int32_t s = base + lane;
+      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+      const double q = sq[s];
+      const double2 d = cscale(sdip[s], -is);
+      T[lane] = make_double2(q, 0.0);
+      TD[lane] = make_double2(0.0, 0.0);
+      double2 pw = make_double2(1.0, 0.0);  // y^(k-1)
+      for (int k = 1; k < P1; ++k) {
+        const double2 pk = cmul(pw, y);
+        T[k * nb + lane] = cscale(pk, -q * invk[k]);
+        TD[k * nb + lane] = cfma(d, pw, make_double2(0.0, 0.0));
+        pw = pk;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = lane + 64 * h;
+      if (r < 2 * P1)
+        for (int j = 0; j < n; ++j) acc[h] = cadd(acc[h], T[r * nb + j]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = lane + 64 * h;
+    if (r < P1) M[(int64_t)b * P1 + r] = from_d2<E>(acc[h]);
+    else if (r < 2 * P1) M[d_off + (int64_t)b * P1 + (r - P1)] = from_d2<E>(acc[h]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -729,6 +801,116 @@ __global__ void __launch_bounds__(64) k_near(
   }
 }
 
+// S and D of one density in one pass (the pair geometry, the log and the powers of 1/z formed
+// once): the single-layer sums as in NearAcc<1>, and the double-layer sums d z^-(m+1) taken from
+// the same powers, d z^-(m+1) = d (1/z)^(m+1) (NearAcc<2> runs its own product chain, so these D
+// rows agree with a GQ_D evaluation to rounding, not bitwise). Rows: S into the first slot, D into
+// the slot d_slot rows of row_st further.
+template <int PQ>
+struct NearAccSD {
+  double2 as[PQ + 1], ad[PQ + 1];
+  double logsum, qsum;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      as[m] = make_double2(0.0, 0.0);
+      ad[m] = make_double2(0.0, 0.0);
+    }
+    logsum = 0.0;
+    qsum = 0.0;
+  }
+  __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
+    const double r2 = z.x * z.x + z.y * z.y;
+    const double ir2 = rcp_nr(r2);
+    const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
+    logsum = fma(q, log_tab(r2, lt), logsum);
+    qsum += q;
+    double2 pw = inv;  // z^-(m+1) in step m: D coefficient m, S coefficient m + 1
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      ad[m] = cfma(dr, pw, ad[m]);
+      if (m < PQ) {
+        as[m + 1] = caxpy(q, pw, as[m + 1]);
+        pw = cmul(pw, inv);
+      }
+    }
+  }
+};
+
+template <int PQ>
+__global__ void __launch_bounds__(64) k_near_sd(
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, double2 *__restrict__ anear, int rs, int64_t src_st,
+    int64_t row_st, int64_t d_slot) {
+  __shared__ double2 t_xy[kNearBatch];
+  __shared__ double t_q[kNearBatch];
+  __shared__ double2 t_d[kNearBatch];
+  const int32_t w = (int32_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  {
+    const int64_t jd = blockIdx.y;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+    anear += jd * row_st;
+  }
+  const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x, lg = i1.y;
+  const int nsl = 64 >> lg;
+  const int cl = lane >> (6 - lg);
+  const int sl = lane & (nsl - 1);
+  const bool active = cl < n_ctr;
+  const int32_t c = ctr_first + (active ? cl : 0);
+  const double2 cc = cxy[c];
+  const double r = cr[c];
+  const double ir = 1.0 / r;
+  const double2 *lt = g_log_tab;
+  NearAccSD<PQ> acc;
+  acc.zero();
+  for (int32_t base = 0; base < len; base += kNearBatch) {
+    const int nb = min(kNearBatch, (int)(len - base));
+    __syncthreads();
+#pragma unroll
+    for (int j = lane; j < kNearBatch; j += 64) {
+      if (j < nb) {
+        const int32_t s = near_src[off + base + j];
+        t_xy[j] = sxy[s];
+        t_q[j] = sq[s];
+        t_d[j] = sdip[s];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < nb; j += nsl) {
+        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
+        acc.add(z, t_q[j], cscale(t_d[j], ir), lt);
+      }
+    }
+  }
+  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) {
+      acc.as[m].x += __shfl_xor(acc.as[m].x, o, 64);
+      acc.as[m].y += __shfl_xor(acc.as[m].y, o, 64);
+      acc.ad[m].x += __shfl_xor(acc.ad[m].x, o, 64);
+      acc.ad[m].y += __shfl_xor(acc.ad[m].y, o, 64);
+    }
+    acc.logsum += __shfl_xor(acc.logsum, o, 64);
+    acc.qsum += __shfl_xor(acc.qsum, o, 64);
+  }
+  if (active && sl == 0) {
+    double2 *row = anear + (int64_t)(row_first + cl) * rs;
+    row[0] = make_double2(0.5 * acc.logsum + acc.qsum * log(r), 0.0);
+#pragma unroll
+    for (int m = 1; m <= PQ; ++m) row[m] = caxpy(-1.0 / m, acc.as[m], make_double2(0.0, 0.0));
+    double2 *rowd = row + d_slot * row_st;
+#pragma unroll
+    for (int m = 0; m <= PQ; ++m) rowd[m] = acc.ad[m];
+  }
+}
+
 // k_near for a block of DG densities per work-group (grid.y = density blocks): same items and
 // lanes, the sources' charges and dipoles of the DG densities staged together, one pair geometry
 // for all of them. Densities past n_dens (a last partial block) get zero strengths and no rows.
@@ -1129,7 +1311,7 @@ template <> struct ExpTables<float2> {
 // The three per-order stages of one order bucket.
 template <int KIND, int PQ, typename E>
 void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
-                        const Strides &S) {
+                        const Strides &S, double2 *anear) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
   // Densities per work item: two by default. Four hold 4 (PQ + 1) complex accumulators per lane,
@@ -1138,15 +1320,33 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
   if (n > 0 && dg == 4)
     hipLaunchKernelGGL((k_near_md<KIND, PQ, 4>), dim3(n, (nd + 3) / 4), dim3(64), 0, s, n,
                        d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip,
-                       d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
+                       anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
   else if (n > 0 && dg == 2)
     hipLaunchKernelGGL((k_near_md<KIND, PQ, 2>), dim3(n, (nd + 1) / 2), dim3(64), 0, s, n,
                        d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip,
-                       d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
+                       anear, ctx->params.p_qbx + 1, S.src, S.row, nd);
   else if (n > 0)
     hipLaunchKernelGGL((k_near<KIND, PQ>), dim3(n, nd), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
-                       d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
+                       d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, anear,
                        ctx->params.p_qbx + 1, S.src, S.row);
+}
+
+// S and D of the same densities (nd of them): one fused pass for a single density, else the
+// per-kind launches (their density groups already share the pair geometry across densities).
+template <int PQ, typename E>
+void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
+                           const Strides &S) {
+  auto &d = ctx->d;
+  const int32_t n = (int32_t)(bk.near1 - bk.near0);
+  if (n <= 0) return;
+  if (nd == 1) {
+    hipLaunchKernelGGL((k_near_sd<PQ>), dim3(n, 1), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
+                       d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
+                       ctx->params.p_qbx + 1, S.src, S.row, (int64_t)1);
+    return;
+  }
+  launch_near_bucket<1, PQ, E>(ctx, bk, nd, s, S, d.anear);
+  launch_near_bucket<2, PQ, E>(ctx, bk, nd, s, S, d.anear + (int64_t)nd * S.row);
 }
 
 template <int PQ, typename E>
@@ -1177,6 +1377,12 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
 
 template <int KIND, typename E>
 hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
+  // KIND 4: S and D of nd densities; the charge and dipole strengths of density j sit in source
+  // slot j, and every expansion, row and target array holds S in slot j and D in slot nd + j.
+  // Stages that only move expansions run once over all 2 nd slots.
+  constexpr bool SD = KIND == 4;
+  const int slots = SD ? 2 * nd : nd;
+  constexpr int CK = SD ? 1 : KIND;  // the center stage does not depend on the kind
   auto &d = ctx->d;
   auto &t = ctx->tree;
   const ExpTables<E> X(d);
@@ -1198,8 +1404,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     StageTimer st_(ctx, GQ_STAGE_NEAR, side);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
-#define GQ_CASE(P) \
-  case P: launch_near_bucket<KIND, P, E>(ctx, bk, nd, side, S); break;
+#define GQ_CASE(P)                                                 \
+  case P:                                                          \
+    if constexpr (SD) launch_near_bucket_sd<P, E>(ctx, bk, nd, side, S); \
+    else launch_near_bucket<KIND, P, E>(ctx, bk, nd, side, S, d.anear); \
+    break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }
@@ -1208,11 +1417,17 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t nleaf = (int32_t)t.n_leaves;
   if (nleaf > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64),
-                       sizeof(double2) * (P1 > 32 ? 32 : 64) * P1,
-                       st, d.leaves, d.bc,
-                       d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
-                       S.src, S.box);
+    const size_t lds = sizeof(double2) * (P1 > 32 ? 32 : 64) * P1;
+    if constexpr (SD) {
+      const size_t lds2 = sizeof(double2) * 2 * (P1 > 32 ? 16 : 32) * P1;
+      hipLaunchKernelGGL((k_p2m_sd<E>), dim3(nleaf, nd), dim3(64), lds2, st, d.leaves, d.bc,
+                         d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
+                         S.src, S.box, (int64_t)nd * S.box);
+    } else {
+      hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64), lds, st, d.leaves, d.bc,
+                         d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
+                         S.src, S.box);
+    }
   }
   {
     StageTimer st_(ctx, GQ_STAGE_M2M);
@@ -1222,13 +1437,13 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
         const int32_t b0 = (int32_t)t.level_start[l - 1];
         const int32_t nb = (int32_t)(t.level_start[l] - b0);
         if (nb > 0)
-          hipLaunchKernelGGL(k_m2m2<E>, dim3(nb, nd), dim3(256), 0, st, b0, d.bchild, X.m2m_rt,
+          hipLaunchKernelGGL(k_m2m2<E>, dim3(nb, slots), dim3(256), 0, st, b0, d.bchild, X.m2m_rt,
                              X.omega, P1, M, S.box);
         l -= 2;
       } else {
         const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
         if (nb > 0)
-          hipLaunchKernelGGL(k_m2m<E>, dim3(nb, nd), dim3(64), 0, st, b0, d.bchild, X.m2m_rt,
+          hipLaunchKernelGGL(k_m2m<E>, dim3(nb, slots), dim3(64), 0, st, b0, d.bchild, X.m2m_rt,
                              X.omega, P1, M, S.box);
         l -= 1;
       }
@@ -1244,7 +1459,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_m2qbxl_bucket<P, E>(ctx, bk, nd, side, S, M); break;
+  case P: launch_m2qbxl_bucket<P, E>(ctx, bk, slots, side, S, M); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }
@@ -1255,18 +1470,31 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    auto kern = P1 <= 16 ? k_far_local<KIND, 1, E> : P1 <= 32 ? k_far_local<KIND, 2, E>
-              : P1 <= 48 ? k_far_local<KIND, 3, E> : k_far_local<KIND, 4, E>;
+    // (List 4 far P2L depends on the kind: for S and D, one launch per kind)
+    auto pick = [&](auto k1, auto k2, auto k3, auto k4) { return P1 <= 16 ? k1 : P1 <= 32 ? k2
+                                                                : P1 <= 48 ? k3 : k4; };
+    constexpr int K1 = SD ? 1 : KIND;
+    auto kern = pick(k_far_local<K1, 1, E>, k_far_local<K1, 2, E>, k_far_local<K1, 3, E>,
+                     k_far_local<K1, 4, E>);
     hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
                        d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
                        d.xf_idx, d.bsrc0, d.bsrc1, M, X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq,
                        d.sdip, P1, L, S.src, S.box);
+    if constexpr (SD) {
+      auto kern2 = pick(k_far_local<2, 1, E>, k_far_local<2, 2, E>, k_far_local<2, 3, E>,
+                        k_far_local<2, 4, E>);
+      hipLaunchKernelGGL(kern2, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
+                         d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off,
+                         d.xf_start, d.xf_idx, d.bsrc0, d.bsrc1, M + (int64_t)nd * S.box,
+                         X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq, d.sdip, P1,
+                         L + (int64_t)nd * S.box, S.src, S.box);
+    }
   }
   if (ctx->n_l2g_sinks > 0) {
     StageTimer st_(ctx, GQ_STAGE_L2L);
     auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
               : P1 <= 48 ? k_l2l_gather<3, E> : k_l2l_gather<4, E>;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_sinks, nd), dim3(64), 0, st, d.l2g_sink,
+    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_sinks, slots), dim3(64), 0, st, d.l2g_sink,
                        d.l2g_anc, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
@@ -1276,7 +1504,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_center_bucket<KIND, P, E>(ctx, bk, nd, st, S, Lf); break;
+  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }
@@ -1350,9 +1578,24 @@ hipError_t upload_log_table() {
 }
 
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
-                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct) {
+                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct, double *out2) {
   hipError_t e;
-  ctx->cur_kind = kind;
+  ctx->cur_kind = kind == 4 ? 1 : kind;
+  if (kind == 4) {  // S and D of the same densities through one expansion pipeline
+    if (direct || !out2) return hipErrorInvalidValue;
+    e = launch_gather<4>(ctx, d1, ld1, nullptr, 0, nd);
+    if (e != hipSuccess) return e;
+    e = launch_fmm<4>(ctx, nd);
+    if (e != hipSuccess) return e;
+    const int32_t nt = (int32_t)ctx->nt;
+    StageTimer st_(ctx, GQ_STAGE_FINALIZE);
+    hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
+                       ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out);
+    hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
+                       ctx->d.tctr, ctx->d.tv + (int64_t)nd * 2 * ctx->nt, out2, 2 * ctx->nt,
+                       ld_out);
+    return hipGetLastError();
+  }
   switch (kind) {
     case 1: e = launch_gather<1>(ctx, d1, ld1, d2, ld2, nd); break;
     case 2: e = launch_gather<2>(ctx, d1, ld1, d2, ld2, nd); break;

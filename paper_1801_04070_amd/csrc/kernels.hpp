@@ -21,13 +21,16 @@ const std::vector<int> &compiled_pq();
 // Maximum densities per launch (the batch dimension of every kernel's grid).
 constexpr int kMaxDensBatch = 64;
 
-// nd densities (rows of d1/d2 with strides ld1/ld2): gather strengths, run the FMM stages (or
-// direct QBX), write nd output rows of n_tgt values with stride ld_out.
 // Copies the natural-log table of the direct-interaction kernels to the current device; called
 // once per context, with its device current, before any evaluation.
 hipError_t upload_log_table();
 
+// nd densities (rows of d1/d2 with strides ld1/ld2): gather strengths, run the FMM stages (or
+// direct QBX), write nd output rows of n_tgt values with stride ld_out. Kind 4 (S and D of the
+// same densities, FMM only, 2 nd workspace slots) writes the S rows to out and the D rows to
+// out2, both with stride ld_out.
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
-                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct);
+                    int64_t ld2, double *out, int64_t ld_out, int nd, bool direct,
+                    double *out2 = nullptr);
 
 }  // namespace gq

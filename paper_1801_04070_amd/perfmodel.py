@@ -23,6 +23,10 @@ MI355X_PEAKS = {
 def _near_pair_flops(kind: int, q: int) -> int:
     # z = (y - c)/r (4), 1/z (6); charge: log|z| term (3), q-1 powers (6 each), q accumulations (4)
     f = 4 + 6
+    if kind == 4:
+        # S and D of one density in one pass: z, 1/z and the powers 1/z^m (m <= q+1) once;
+        # charge: log term (3), q accumulations (4); dipole: q+1 complex multiply-adds (8)
+        return f + 3 + 6 * q + 4 * q + 8 * (q + 1)
     if kind & 1:
         f += 3 + 6 * (q - 1) + 4 * q
     if kind & 2:
@@ -47,7 +51,20 @@ def _qbxl2p_flops(q: int) -> int:
 
 
 def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> dict:
-    """Algorithmic flops and HBM bytes of one launch of each stage for one density."""
+    """Algorithmic flops and HBM bytes of one launch of each stage for one density; kind 4 (S and
+    D of the same density, one pipeline) is the sum of the two kinds except for the direct
+    interactions, whose pair geometry is formed once."""
+    if kind == 4:
+        s = stage_work(stats, 1, p_qbx, p_fmm, n_slots)
+        d = stage_work(stats, 2, p_qbx, p_fmm, n_slots)
+        out = {k: {"flops": s[k]["flops"] + d[k]["flops"], "bytes": s[k]["bytes"] + d[k]["bytes"],
+                   "bound": s[k]["bound"]} for k in s}
+        row = (p_qbx + 1) * 16
+        out["near"] = {"flops": stats["near_pairs"] * _near_pair_flops(4, p_qbx),
+                       "bytes": stats["near_sources"] * (40 + 4) + stats["n_ctr"] * 24
+                                + 2 * stats["n_ctr"] * row,
+                       "bound": "alu"}
+        return out
     q, p = p_qbx, p_fmm
     P1, Q1 = p + 1, q + 1
     src_rec = {1: 24, 2: 32, 3: 40}[kind]
@@ -76,8 +93,12 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> 
     tri = P1 * (P1 + 1) // 2
     out["m2m"] = {"flops": (stats["n_boxes"] - 1) * tri * 8,
                   "bytes": 2 * stats["n_boxes"] * P1 * 16, "bound": "alu"}
-    out["l2l"] = {"flops": max(stats["n_local_boxes"] - 1, 0) * tri * 8,
-                  "bytes": 2 * stats["n_local_boxes"] * P1 * 16, "bound": "alu"}
+    # Stage 7 as a gather: per (box, ancestor) pair t^j a_j (6 per term), the binomial sum
+    # (real x complex multiply-add, 4 per term of the triangle), u^-m (6) and the sum (2)
+    out["l2l"] = {"flops": stats.get("n_l2l_pairs", 0) * (6 * P1 + 4 * tri + 8 * P1)
+                           + stats.get("n_l2l_sinks", 0) * 2 * P1,
+                  "bytes": stats.get("n_l2l_pairs", 0) * (P1 * 16 + 36)
+                           + 2 * stats.get("n_l2l_sinks", 0) * P1 * 16, "bound": "alu"}
     p2m = 4 + (10 * p if kind & 1 else 0) + (8 * p if kind & 2 else 0)
     out["p2m"] = {"flops": stats["n_src"] * p2m,
                   "bytes": stats["n_src"] * src_rec + stats["n_leaves"] * P1 * 16, "bound": "alu"}
