@@ -357,6 +357,24 @@ gq_status upload_all(gq_ctx *ctx) {
       GQ_TRY(upload(ctx, d.l2g_tw, tw.data(), tw.size() / 4));
     }
   }
+  // Stage 6b work: per box, the sources of its List 4 far boxes (tree order, box by box)
+  {
+    std::vector<int32_t> item, src;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int32_t first = (int32_t)src.size();
+      for (int64_t e = t.list4f.start[b]; e < t.list4f.start[b + 1]; ++e) {
+        const int32_t dd = t.list4f.idx[e];
+        for (int64_t s = t.src_begin[dd]; s < t.src_end[dd]; ++s) src.push_back((int32_t)s);
+      }
+      if ((int32_t)src.size() > first)
+        item.insert(item.end(), {(int32_t)b, first, (int32_t)src.size(), 0});
+    }
+    ctx->n_p2l_boxes = (int64_t)item.size() / 4;
+    if (!item.empty()) {
+      GQ_TRY(upload(ctx, d.p2l_item, item.data(), item.size() / 4));
+      GQ_TRY(upload(ctx, d.p2l_src, src.data(), src.size()));
+    }
+  }
   // lists
   GQ_TRY(upload(ctx, d.v_start, to_i32(t.list2.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.v_idx, t.list2.idx.data(), t.list2.idx.size()));

@@ -43,6 +43,9 @@ struct DevBuffers {
   int32_t *l2g_anc = nullptr;        // per pair: the ancestor
   double4 *l2g_tw = nullptr;         // per pair: t = (c_b - c_a)/s_a and 1/u, u = (c_b - c_a)/s_b
   double *l2g_binom_t = nullptr;     // [P1 (k)][P1 (m)]  C(k, m)
+  // Stage 6b: boxes with List 4 far sources (box, first, end) and the sources, flattened
+  int4 *p2l_item = nullptr;
+  int32_t *p2l_src = nullptr;
   double *level_side = nullptr, *level_inv_side = nullptr, *level_log_side = nullptr;
   // lists
   int32_t *v_start = nullptr, *v_idx = nullptr, *v_off = nullptr;
@@ -114,6 +117,7 @@ struct gq_ctx {
   std::vector<void *> nw_allocations;    // direct / List 3 far work, re-uploaded on order changes
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_l2g_sinks = 0;           // boxes owning centers (Stage 7 gather)
+  int64_t n_p2l_boxes = 0;           // boxes with List 4 far sources (Stage 6b)
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   int far_chunk = 16;                // List 3 far boxes per work item (sizes k_m2qbxl's LDS)
   // Shallowest depth whose multipoles are read (List 2 / List 3 far) and shallowest depth with a

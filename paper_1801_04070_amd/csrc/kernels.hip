@@ -328,18 +328,13 @@ template <> struct Mfma16<float> {
   static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
-template <int KIND, int RT, typename E>
-__global__ void __launch_bounds__(64) k_far_local(
-    const int32_t *__restrict__ tboxes, const double2 *__restrict__ bc,
-    const int32_t *__restrict__ blevel, const double *__restrict__ level_inv_side,
+template <int RT, typename E>
+__global__ void __launch_bounds__(64) k_m2l(
+    const int32_t *__restrict__ tboxes, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_log_side, const int32_t *__restrict__ v_start,
     const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
-    const int32_t *__restrict__ xf_start, const int32_t *__restrict__ xf_idx,
-    const int32_t *__restrict__ bsrc0, const int32_t *__restrict__ bsrc1,
     const E *__restrict__ M, const typename Scalar<E>::T *__restrict__ Bt,
-    const E *__restrict__ opow, const double *__restrict__ ologabs,
-    const double2 *__restrict__ sxy, const double *__restrict__ sq,
-    const double2 *__restrict__ sdip, int P1, E *__restrict__ L, int64_t src_st,
+    const E *__restrict__ opow, const double *__restrict__ ologabs, int P1, E *__restrict__ L,
     int64_t box_st) {
   using R = typename Scalar<E>::T;
   using Acc = typename Mfma16<R>::Acc;
@@ -349,8 +344,6 @@ __global__ void __launch_bounds__(64) k_far_local(
     const int64_t jd = blockIdx.y;
     M += jd * box_st;
     L += jd * box_st;
-    sq += jd * src_st;
-    sdip += jd * src_st;
   }
   const int lane = threadIdx.x;
   const int g = lane >> 4, c16 = lane & 15;
@@ -415,45 +408,100 @@ __global__ void __launch_bounds__(64) k_far_local(
   // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) logsum0 += __shfl_xor(logsum0, o, 64);
-  // P2L (eq. (local) about c_b) for the sources of List 4 far boxes, 16 sources at a time: lane
-  // j < 16 forms source j's contributions to every coefficient with a running power of 1/y and
-  // stores them in LDS; lane m then sums column m.
-  __shared__ double2 Pc[16][16 * RT];
   const int m = lane;
   if (m == 0) acc.x += logsum0;
-  const double2 c = bc[b];
-  const double is = level_inv_side[lev];
-  const double2 *lt = g_log_tab;
-  for (int32_t j = xf_start[b]; j < xf_start[b + 1]; ++j) {
-    const int32_t dd = xf_idx[j];
-    for (int32_t s0 = bsrc0[dd]; s0 < bsrc1[dd]; s0 += 16) {
-      const int n = min(16, (int)(bsrc1[dd] - s0));
-      __syncthreads();
-      if (lane < n) {
-        const int32_t s = s0 + lane;
-        const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-        const double2 inv = cinv(y);
-        const double q = (KIND & 1) ? sq[s] : 0.0;
-        const double2 dl = (KIND & 2) ? cscale(sdip[s], is) : make_double2(0.0, 0.0);
-        // coefficient 0: q log|s y| + d/y;  coefficient k: -q y^-k / k + d y^-(k+1)
-        double2 pw = inv;
-        double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
-        if (KIND & 1) c0.x += q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt));
-        Pc[lane][0] = c0;
-        for (int k = 1; k < P1; ++k) {
-          double2 ck = (KIND & 1) ? cscale(pw, -q / k) : make_double2(0.0, 0.0);
-          pw = cmul(pw, inv);
-          if (KIND & 2) ck = cfma(dl, pw, ck);
-          Pc[lane][k] = ck;
-        }
-      }
-      __syncthreads();
-      if (m < P1)
-        for (int jj = 0; jj < n; ++jj) acc = cadd(acc, Pc[jj][m]);
-    }
-  }
   if (m >= P1) return;
   L[(int64_t)b * P1 + m] = from_d2<E>(acc);
+}
+
+// ------------------------------------------------------------------------------------------
+// Stage 6b, P2L (eq. (local) about c_b) for the sources of a box's List 4 far boxes, added to the
+// box local that k_m2l wrote. One wavefront per box with such sources (their indices flattened
+// on the host); nb = 32 sources at a time (16 when P1 > 32): lane j forms source j's
+// contribution to every coefficient with a running power of 1/y and stores it in LDS; lane r
+// then sums row r over the batch in source order. KIND 4 (S and D of one density) forms both
+// kinds' rows from the same powers, S into the first P1 rows and D into the next P1, and adds the
+// D rows d_off coefficients further.
+//   coefficient 0: q log|s y| + d/y,  coefficient k >= 1: -q y^-k / k + d y^-(k+1)
+template <int KIND, typename E>
+__global__ void __launch_bounds__(64) k_p2l(
+    const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
+    const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
+    const double *__restrict__ level_inv_side, const double *__restrict__ level_log_side,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, int P1, E *__restrict__ L, int64_t src_st,
+    int64_t box_st, int64_t d_off) {
+  constexpr int NK = KIND == 4 ? 2 : 1;  // kinds formed per pass
+  HIP_DYNAMIC_SHARED(unsigned char, p2l_lds)
+  double2 *T = reinterpret_cast<double2 *>(p2l_lds);  // [NK][P1][nb]
+  __shared__ double invk[64];
+  const int nb = P1 > 32 ? 16 : 32;
+  const int4 it = items[blockIdx.x];  // box, first source, end of sources
+  const int32_t b = it.x;
+  const int lane = threadIdx.x;
+  {
+    const int64_t jd = blockIdx.y;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+    L += jd * box_st;
+  }
+  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
+  const int lev = blevel[b];
+  const double2 c = bc[b];
+  const double is = level_inv_side[lev];
+  const double logs = level_log_side[lev];
+  const double2 *lt = g_log_tab;
+  double2 *TD = T + (int64_t)P1 * nb;
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  for (int32_t base = it.y; base < it.z; base += nb) {
+    const int n = min(nb, (int)(it.z - base));
+    __syncthreads();  // invk ready; the previous batch's rows consumed
+    if (lane < n) {
+      const int32_t s = src_idx[base + lane];
+      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+      const double2 inv = cinv(y);
+      const double q = (KIND & 1) || KIND == 4 ? sq[s] : 0.0;
+      const double2 dl = (KIND & 2) || KIND == 4 ? cscale(sdip[s], is) : make_double2(0.0, 0.0);
+      double2 pw = inv;
+      if (KIND == 4) {
+        T[lane] = make_double2(q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt)), 0.0);
+        TD[lane] = cmul(dl, inv);
+        for (int k = 1; k < P1; ++k) {
+          T[k * nb + lane] = cscale(pw, -q * invk[k]);
+          pw = cmul(pw, inv);
+          TD[k * nb + lane] = cfma(dl, pw, make_double2(0.0, 0.0));
+        }
+      } else {
+        double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
+        if (KIND & 1) c0.x += q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt));
+        T[lane] = c0;
+        for (int k = 1; k < P1; ++k) {
+          double2 ck = (KIND & 1) ? cscale(pw, -q * invk[k]) : make_double2(0.0, 0.0);
+          pw = cmul(pw, inv);
+          if (KIND & 2) ck = cfma(dl, pw, ck);
+          T[k * nb + lane] = ck;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int r = lane + 64 * h;
+      if (r < NK * P1)
+        for (int j = 0; j < n; ++j) acc[h] = cadd(acc[h], T[r * nb + j]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = lane + 64 * h;
+    if (r < P1) {
+      E *o = L + (int64_t)b * P1 + r;
+      *o = from_d2<E>(cadd(to_d2(*o), acc[h]));
+    } else if (r < NK * P1) {
+      E *o = L + d_off + (int64_t)b * P1 + (r - P1);
+      *o = from_d2<E>(cadd(to_d2(*o), acc[h]));
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1470,24 +1518,18 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    // (List 4 far P2L depends on the kind: for S and D, one launch per kind)
-    auto pick = [&](auto k1, auto k2, auto k3, auto k4) { return P1 <= 16 ? k1 : P1 <= 32 ? k2
-                                                                : P1 <= 48 ? k3 : k4; };
-    constexpr int K1 = SD ? 1 : KIND;
-    auto kern = pick(k_far_local<K1, 1, E>, k_far_local<K1, 2, E>, k_far_local<K1, 3, E>,
-                     k_far_local<K1, 4, E>);
-    hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
-                       d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off, d.xf_start,
-                       d.xf_idx, d.bsrc0, d.bsrc1, M, X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq,
-                       d.sdip, P1, L, S.src, S.box);
-    if constexpr (SD) {
-      auto kern2 = pick(k_far_local<2, 1, E>, k_far_local<2, 2, E>, k_far_local<2, 3, E>,
-                        k_far_local<2, 4, E>);
-      hipLaunchKernelGGL(kern2, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.bc, d.blevel,
-                         d.level_inv_side, d.level_log_side, d.v_start, d.v_idx, d.v_off,
-                         d.xf_start, d.xf_idx, d.bsrc0, d.bsrc1, M + (int64_t)nd * S.box,
-                         X.m2l_bt, X.opow, d.ologabs, d.sxy, d.sq, d.sdip, P1,
-                         L + (int64_t)nd * S.box, S.src, S.box);
+    auto kern = P1 <= 16 ? k_m2l<1, E> : P1 <= 32 ? k_m2l<2, E>
+              : P1 <= 48 ? k_m2l<3, E> : k_m2l<4, E>;
+    hipLaunchKernelGGL(kern, dim3(ntb, slots), dim3(64), 0, st, d.tboxes, d.blevel,
+                       d.level_log_side, d.v_start, d.v_idx, d.v_off, M, X.m2l_bt, X.opow,
+                       d.ologabs, P1, L, S.box);
+    if (ctx->n_p2l_boxes > 0) {
+      const size_t lds = sizeof(double2) * (SD ? 2 : 1) * (P1 > 32 ? 16 : 32) * P1;
+      constexpr int PK = SD ? 4 : KIND;
+      hipLaunchKernelGGL((k_p2l<PK, E>), dim3((uint32_t)ctx->n_p2l_boxes, nd), dim3(64), lds, st,
+                         d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
+                         d.level_log_side, d.sxy, d.sq, d.sdip, P1, L, S.src, S.box,
+                         (int64_t)nd * S.box);
     }
   }
   if (ctx->n_l2g_sinks > 0) {
