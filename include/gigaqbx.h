@@ -238,6 +238,9 @@ typedef struct {
   int64_t n_point_targets;       /* conventional targets (each with an internal center)   */
   int64_t n_l2l_sinks;           /* boxes owning centers (they receive complete locals)   */
   int64_t n_l2l_pairs;           /* (box, ancestor with its own local) shifts in Stage 7   */
+  int64_t n_moment_boxes;        /* boxes whose multipole M2L or M2QBXL reads (Stage 2)   */
+  int64_t n_moment_pairs;        /* (box, subtree source) pairs of their moments          */
+  int64_t n_moment_parts;        /* partial moments of boxes split over several items     */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);

@@ -40,7 +40,8 @@ class gq_stats(C.Structure):
         "max_list2", "max_list4", "max_list4_close", "max_list4_far")] + [
         ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double),
         ("n_point_targets", C.c_int64), ("n_l2l_sinks", C.c_int64),
-        ("n_l2l_pairs", C.c_int64)]
+        ("n_l2l_pairs", C.c_int64), ("n_moment_boxes", C.c_int64),
+        ("n_moment_pairs", C.c_int64), ("n_moment_parts", C.c_int64)]
 
 
 GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",

@@ -44,7 +44,7 @@ void free_workspace(gq_ctx *ctx) {
   ctx->ws_allocations.clear();
   ctx->ws_batch = 0;
   ctx->d.sq = nullptr; ctx->d.sdip = nullptr; ctx->d.M = nullptr; ctx->d.L = nullptr;
-  ctx->d.Lf = nullptr;
+  ctx->d.Lf = nullptr; ctx->d.Mp = nullptr;
   ctx->d.anear = nullptr; ctx->d.tv = nullptr;
 }
 
@@ -108,6 +108,7 @@ std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
 // simple cost model (per-element work + slice reduction + fixed cost per wave). Each (center,
 // chunk) result goes to its own row; the rows of a box are laid out [chunk][center], direct
 // chunks first.
+constexpr int kMomentChunk = 512;  // sources per Stage 2 work item
 constexpr int kNearChunk = 1024;   // defaults of gq_params.near_chunk / far_chunk
 constexpr int kFarChunk = 16;
 
@@ -280,14 +281,11 @@ gq_status upload_all(gq_ctx *ctx) {
   // boxes
   {
     std::vector<double> bc(2 * nb);
-    std::vector<int8_t> quad(nb, 0);
-    std::vector<int32_t> s0(nb), s1(nb), leaves, tboxes, istb(nb, 0);
+    std::vector<int32_t> s0(nb), s1(nb), tboxes;
     for (int64_t b = 0; b < nb; ++b) {
       bc[2 * b] = t.cx[b]; bc[2 * b + 1] = t.cy[b];
-      quad[b] = (int8_t)((t.bi[b] & 1) + 2 * (t.bj[b] & 1));
       s0[b] = (int32_t)t.src_begin[b]; s1[b] = (int32_t)t.src_end[b];
-      if (t.is_leaf(b)) leaves.push_back((int32_t)b);
-      if (t.has_tgt[b]) { tboxes.push_back((int32_t)b); istb[b] = 1; }
+      if (t.has_tgt[b]) tboxes.push_back((int32_t)b);
     }
     ctx->n_tboxes = (int64_t)tboxes.size();
     GQ_TRY(upload(ctx, d.bc, bc.data(), nb));
@@ -296,10 +294,7 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.bchild, t.child.data(), 4 * nb));
     GQ_TRY(upload(ctx, d.bsrc0, s0.data(), nb));
     GQ_TRY(upload(ctx, d.bsrc1, s1.data(), nb));
-    GQ_TRY(upload(ctx, d.bquad, quad.data(), nb));
-    GQ_TRY(upload(ctx, d.leaves, leaves.data(), leaves.size()));
     GQ_TRY(upload(ctx, d.tboxes, tboxes.data(), tboxes.size()));
-    GQ_TRY(upload(ctx, d.is_tbox, istb.data(), nb));
     // box sides per level (a forest: per virtual level, one per tree and depth)
     std::vector<double> side = t.level_side_table;
     if (side.empty())
@@ -312,20 +307,6 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.level_side, side.data(), side.size()));
     GQ_TRY(upload(ctx, d.level_inv_side, iside.data(), iside.size()));
     GQ_TRY(upload(ctx, d.level_log_side, lside.data(), lside.size()));
-  }
-  // depths that the upward and downward passes must cover
-  {
-    std::vector<int> depth(nb, 0);
-    for (int l = 0; l < t.n_levels; ++l)
-      for (int64_t b = t.level_start[l]; b < t.level_start[l + 1]; ++b) depth[b] = l;
-    int m2m_first = t.n_levels;
-    for (int64_t b = 0; b < nb; ++b) {
-      for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e)
-        m2m_first = std::min(m2m_first, depth[t.list2.idx[e]]);
-      for (int64_t e = t.list3f.start[b]; e < t.list3f.start[b + 1]; ++e)
-        m2m_first = std::min(m2m_first, depth[t.list3f.idx[e]]);
-    }
-    ctx->m2m_first_depth = m2m_first;
   }
   // Stage 7 gather lists: every box owning centers, with its ancestors (top-down) that receive
   // List 2 or List 4 far contributions of their own, and the two shift ratios of each pair
@@ -356,6 +337,33 @@ gq_status upload_all(gq_ctx *ctx) {
       GQ_TRY(upload(ctx, d.l2g_anc, anc.data(), anc.size()));
       GQ_TRY(upload(ctx, d.l2g_tw, tw.data(), tw.size() / 4));
     }
+  }
+  // Stage 2 work: every box whose multipole M2L (List 2) or M2QBXL (List 3 far) reads, its
+  // subtree sources in items of at most kMomentChunk; split boxes first, each chunk writing a
+  // partial that k_m_reduce sums in order
+  {
+    std::vector<uint8_t> need(nb, 0);
+    for (int32_t x : t.list2.idx) need[x] = 1;
+    for (int32_t x : t.list3f.idx) need[x] = 1;
+    std::vector<int32_t> item, red;
+    int32_t parts = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int64_t s0 = t.src_begin[b], s1 = t.src_end[b];
+      if (!need[b] || s1 - s0 <= kMomentChunk) continue;
+      red.insert(red.end(), {(int32_t)b, parts, 0, 0});
+      for (int64_t c0 = s0; c0 < s1; c0 += kMomentChunk)
+        item.insert(item.end(), {(int32_t)b, (int32_t)c0,
+                                 (int32_t)std::min<int64_t>(s1, c0 + kMomentChunk), parts++});
+      red[red.size() - 2] = parts;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+      if (need[b] && t.src_end[b] - t.src_begin[b] <= kMomentChunk)
+        item.insert(item.end(), {(int32_t)b, (int32_t)t.src_begin[b], (int32_t)t.src_end[b], -1});
+    ctx->n_p2m_items = (int64_t)item.size() / 4;
+    ctx->n_p2m_red = (int64_t)red.size() / 4;
+    ctx->n_p2m_parts = parts;
+    if (!item.empty()) GQ_TRY(upload(ctx, d.p2m_item, item.data(), item.size() / 4));
+    if (!red.empty()) GQ_TRY(upload(ctx, d.p2m_red, red.data(), red.size() / 4));
   }
   // Stage 6b work: per box, the sources of its List 4 far boxes (tree order, box by box)
   {
@@ -388,16 +396,11 @@ gq_status upload_all(gq_ctx *ctx) {
   // tables
   const gq::Tables &tb = ctx->tables;
   const int P1 = ctx->params.p_fmm + 1, PQ = ctx->params.p_qbx;
-  GQ_TRY(upload(ctx, d.m2m_rt, tb.m2m_rt.data(), tb.m2m_rt.size()));
-  GQ_TRY(upload(ctx, d.omega, tb.omega.data(), tb.omega.size() / 2));
   GQ_TRY(upload(ctx, d.m2l_bt, tb.m2l_bt.data(), tb.m2l_bt.size()));
   if (ctx->params.precision == GQ_MIXED_FP32) {
     auto f32 = [](const std::vector<double> &v) { return std::vector<float>(v.begin(), v.end()); };
-    const std::vector<float> rm = f32(tb.m2m_rt), bt = f32(tb.m2l_bt),
-                             om = f32(tb.omega), op = f32(tb.opow);
-    GQ_TRY(upload(ctx, d.m2m_rt_f, rm.data(), rm.size()));
+    const std::vector<float> bt = f32(tb.m2l_bt), op = f32(tb.opow);
     GQ_TRY(upload(ctx, d.m2l_bt_f, bt.data(), bt.size()));
-    GQ_TRY(upload(ctx, d.omega_f, om.data(), om.size() / 2));
     GQ_TRY(upload(ctx, d.opow_f, op.data(), op.size() / 2));
   }
   GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
@@ -432,6 +435,7 @@ gq_status ensure_workspace(gq_ctx *ctx, int nd) {
   GQ_TRY(alloc_ws(ctx, d.M, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.L, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.Lf, n * nb * P1));
+  GQ_TRY(alloc_ws(ctx, d.Mp, n * (size_t)std::max<int64_t>(ctx->n_p2m_parts, 1) * 2 * P1));
   GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1)));
   GQ_TRY(alloc_ws(ctx, d.tv, n * 2 * ctx->nt));
   ctx->ws_batch = nd;
@@ -931,6 +935,18 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   std::memset(out, 0, sizeof(*out));
   out->n_src = ctx->ns; out->n_ctr = ctx->nc_user; out->n_tgt = ctx->nt;
   out->n_point_targets = ctx->n_pt;
+  {
+    std::vector<uint8_t> need(t.n_boxes(), 0);
+    for (int32_t x : t.list2.idx) need[x] = 1;
+    for (int32_t x : t.list3f.idx) need[x] = 1;
+    for (int64_t b = 0; b < t.n_boxes(); ++b) {
+      if (!need[b]) continue;
+      const int64_t n = t.src_end[b] - t.src_begin[b];
+      out->n_moment_boxes++;
+      out->n_moment_pairs += n;
+      if (n > kMomentChunk) out->n_moment_parts += (n + kMomentChunk - 1) / kMomentChunk;
+    }
+  }
   for (int64_t b = 0; b < t.n_boxes(); ++b) {
     if (t.ctr_end[b] <= t.ctr_begin[b]) continue;
     out->n_l2l_sinks++;

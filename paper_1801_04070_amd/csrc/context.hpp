@@ -34,15 +34,15 @@ struct DevBuffers {
   double2 *bc = nullptr;             // centers
   int32_t *blevel = nullptr, *bparent = nullptr, *bchild = nullptr;
   int32_t *bsrc0 = nullptr, *bsrc1 = nullptr;
-  int8_t *bquad = nullptr;           // quadrant of the box within its parent
-  int32_t *leaves = nullptr;         // leaf boxes
   int32_t *tboxes = nullptr;         // target-or-ancestor boxes
-  int32_t *is_tbox = nullptr;        // per box: 1 if target-or-ancestor
   // Stage 7 gather: boxes owning centers, and per box its ancestors with a nonzero own local
   int4 *l2g_sink = nullptr;          // (box, first pair, end of pairs, 0)
   int32_t *l2g_anc = nullptr;        // per pair: the ancestor
   double4 *l2g_tw = nullptr;         // per pair: t = (c_b - c_a)/s_a and 1/u, u = (c_b - c_a)/s_b
   double *l2g_binom_t = nullptr;     // [P1 (k)][P1 (m)]  C(k, m)
+  // Stage 2: moment items (box, first source, end, partial slot or -1) and the split boxes
+  // (box, first partial, end)
+  int4 *p2m_item = nullptr, *p2m_red = nullptr;
   // Stage 6b: boxes with List 4 far sources (box, first, end) and the sources, flattened
   int4 *p2l_item = nullptr;
   int32_t *p2l_src = nullptr;
@@ -61,11 +61,11 @@ struct DevBuffers {
   int32_t *ctr_list = nullptr;       // tree-order centers grouped by order
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
-  double2 *opow = nullptr, *omega = nullptr;
-  double *m2m_rt = nullptr, *m2l_bt = nullptr, *ologabs = nullptr;
+  double2 *opow = nullptr;
+  double *m2l_bt = nullptr, *ologabs = nullptr;
   // the same tables rounded to FP32 for the mixed-precision box expansions
-  float *m2m_rt_f = nullptr, *m2l_bt_f = nullptr;
-  float2 *omega_f = nullptr, *opow_f = nullptr;
+  float *m2l_bt_f = nullptr;
+  float2 *opow_f = nullptr;
   double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
   double *m2q_binom = nullptr;       // [PQB + 1][P1]  C(m + k - 1, k - 1)
   // workspace
@@ -73,6 +73,7 @@ struct DevBuffers {
   double2 *sdip = nullptr;           // per-source dipole  w * tau * n
   double2 *M = nullptr, *L = nullptr;
   double2 *Lf = nullptr;             // complete locals of the boxes owning centers (Stage 7)
+  double2 *Mp = nullptr;             // partial moments of split boxes: [slot][partial][2 P1]
   double *tv = nullptr;              // per target slot values
 };
 
@@ -118,12 +119,12 @@ struct gq_ctx {
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_l2g_sinks = 0;           // boxes owning centers (Stage 7 gather)
   int64_t n_p2l_boxes = 0;           // boxes with List 4 far sources (Stage 6b)
+  int64_t n_p2m_items = 0, n_p2m_red = 0, n_p2m_parts = 0;  // Stage 2 work
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   int far_chunk = 16;                // List 3 far boxes per work item (sizes k_m2qbxl's LDS)
   // Shallowest depth whose multipoles are read (List 2 / List 3 far) and shallowest depth with a
   // non-zero M2L/P2L local: M2M above the first and L2L out of depths above the second have no
   // effect on any result and are not launched.
-  int m2m_first_depth = 0;
   gq::DevBuffers d;
   std::vector<void *> allocations;   // tree, list and table allocations, freed together
   std::vector<void *> ws_allocations;  // per-density workspace, sized for ws_batch densities

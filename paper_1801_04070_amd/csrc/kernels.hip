@@ -73,227 +73,140 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 }
 
 // ------------------------------------------------------------------------------------------
-// Stage 2a, P2M for leaf boxes: one work-group (one wave) per leaf. For a batch of up to nb of the
-// leaf's sources (nb = 64, or 32 when P1 > 32, keeping LDS at P1 x nb x 16 B <= 32 KB), lane j
-// runs the powers of its own source, y_j^k (one complex multiply per order), and writes its
-// contribution to every coefficient into LDS; lane k then sums row k over the batch in source
-// order.
-template <int KIND, typename E>
-__global__ void __launch_bounds__(64) k_p2m(const int32_t *__restrict__ leaves,
-                                            const double2 *__restrict__ bc,
-                                            const int32_t *__restrict__ blevel,
-                                            const int32_t *__restrict__ bsrc0,
-                                            const int32_t *__restrict__ bsrc1,
-                                            const double *__restrict__ level_inv_side,
-                                            const double2 *__restrict__ sxy,
-                                            const double *__restrict__ sq,
-                                            const double2 *__restrict__ sdip, int P1,
-                                            E *__restrict__ M, int64_t src_st,
-                                            int64_t box_st) {
-  HIP_DYNAMIC_SHARED(unsigned char, p2m_lds)
-  double2 *T = reinterpret_cast<double2 *>(p2m_lds);  // [k][nb]
-  __shared__ double invk[64];
-  const int nb = P1 > 32 ? 32 : 64;
-  const int32_t b = leaves[blockIdx.x];
+// Stage 2 as direct moments: the multipole of every box that M2L or M2QBXL reads is formed from
+// the sources of its subtree (contiguous in tree order). In 2-D, M2M keeps the first p + 1
+// moments of a box exact (coefficient m of the parent depends only on the children's
+// coefficients k <= m), so these are the multipoles the level-by-level pass builds, up to
+// rounding. One work item = one box and up to 256 of its sources; a box with more sources is
+// split into several items whose partial sums k_m_reduce adds in item order.
+// Lanes: NBLK blocks of 8 consecutive orders (k = 8 kb + i) times 64 / NBLK source groups. A lane
+// walks the sources of its group, forms y^(8 kb) by repeated squaring and the block's powers by a
+// chain of complex multiplies, and accumulates A_k = sum q y^k and B_k = sum d y^k in registers;
+// a fixed xor tree then sums the groups. Coefficient k of the single layer is A_0 (k = 0) or
+// -A_k / k, of the double layer B_(k-1) (0 at k = 0). KIND 3 stores their sum (one expansion),
+// KIND 4 (S and D of one density) both, the D multipole d_off coefficients after the S one.
+// A split box's items write partial rows [S: P1][D: P1] to Mp for k_m_reduce.
+template <int KIND, int NBLK, typename E>
+__global__ void __launch_bounds__(64) k_p2m_all(
+    const int4 *__restrict__ items, const double2 *__restrict__ bc,
+    const int32_t *__restrict__ blevel, const double *__restrict__ level_inv_side,
+    const double2 *__restrict__ sxy, const double *__restrict__ sq,
+    const double2 *__restrict__ sdip, int P1, E *__restrict__ M, double2 *__restrict__ Mp,
+    int64_t src_st, int64_t box_st, int64_t part_st, int64_t d_off) {
+  constexpr bool HQ = (KIND & 1) || KIND == 4, HD = (KIND & 2) || KIND == 4;
+  constexpr int G = 64 / NBLK;
+  const int4 it = items[blockIdx.x];  // box, first source, end of sources, partial slot or -1
+  const int32_t b = it.x;
   const int lane = threadIdx.x;
-  const int64_t jd = blockIdx.y;
-  sq += jd * src_st;
-  sdip += jd * src_st;
-  M += jd * box_st;
-  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
+  const int kb = lane % NBLK, g = lane / NBLK;
+  {
+    const int64_t jd = blockIdx.y;
+    sq += jd * src_st;
+    sdip += jd * src_st;
+    M += jd * box_st;
+    Mp += jd * part_st;
+  }
   const double2 c = bc[b];
   const double is = level_inv_side[blevel[b]];
-  double2 acc = make_double2(0.0, 0.0);
-  const int32_t s0 = bsrc0[b], s1 = bsrc1[b];
-  for (int32_t base = s0; base < s1; base += nb) {
-    const int n = min(nb, (int)(s1 - base));
-    __syncthreads();  // invk ready; the previous batch's rows consumed
-    if (lane < n) {
-      const int32_t s = base + lane;
-      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-      const double q = (KIND & 1) ? sq[s] : 0.0;
-      const double2 d = (KIND & 2) ? cscale(sdip[s], -is) : make_double2(0.0, 0.0);
-      // coefficient 0: q;  coefficient k >= 1: -q y^k / k + d y^(k-1)
-      T[lane] = make_double2(q, 0.0);
-      double2 pw = make_double2(1.0, 0.0);  // y^(k-1)
-      for (int k = 1; k < P1; ++k) {
-        const double2 pk = cmul(pw, y);
-        double2 t = (KIND & 1) ? cscale(pk, -q * invk[k]) : make_double2(0.0, 0.0);
-        if (KIND & 2) t = cfma(d, pw, t);
-        T[k * nb + lane] = t;
-        pw = pk;
+  double2 A[8], B[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    A[i] = make_double2(0.0, 0.0);
+    B[i] = make_double2(0.0, 0.0);
+  }
+  for (int32_t s = it.y + g; s < it.z; s += G) {
+    const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+    const double q = HQ ? sq[s] : 0.0;
+    const double2 d = HD ? cscale(sdip[s], -is) : make_double2(0.0, 0.0);
+    // y^(8 kb)
+    double2 pw = make_double2(1.0, 0.0);
+    if (NBLK > 1) {
+      const double2 y2 = cmul(y, y), y4 = cmul(y2, y2), y8 = cmul(y4, y4);
+      if (kb & 1) pw = y8;
+      if (NBLK > 2) {
+        const double2 y16 = cmul(y8, y8);
+        if (kb & 2) pw = (kb & 1) ? cmul(y16, y8) : y16;
+        if (NBLK > 4) {
+          const double2 y32 = cmul(y16, y16);
+          if (kb & 4) pw = cmul(pw, y32);
+        }
       }
     }
-    __syncthreads();
-    if (lane < P1)
-      for (int j = 0; j < n; ++j) acc = cadd(acc, T[lane * nb + j]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (HQ) A[i] = caxpy(q, pw, A[i]);
+      if (HD) B[i] = cfma(d, pw, B[i]);
+      if (i < 7) pw = cmul(pw, y);
+    }
   }
-  if (lane < P1) M[(int64_t)b * P1 + lane] = from_d2<E>(acc);
+#pragma unroll
+  for (int o = 32; o >= NBLK; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (HQ) {
+        A[i].x += __shfl_xor(A[i].x, o, 64);
+        A[i].y += __shfl_xor(A[i].y, o, 64);
+      }
+      if (HD) {
+        B[i].x += __shfl_xor(B[i].x, o, 64);
+        B[i].y += __shfl_xor(B[i].y, o, 64);
+      }
+    }
+  }
+  // B_(8 kb - 1) from the lane of the previous block (lanes 0..NBLK-1 hold the sums)
+  double2 Bprev = make_double2(0.0, 0.0);
+  if (HD) {
+    Bprev.x = __shfl(B[7].x, lane - 1, 64);
+    Bprev.y = __shfl(B[7].y, lane - 1, 64);
+  }
+  if (g != 0) return;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = 8 * kb + i;
+    if (k >= P1) break;
+    double2 sv = make_double2(0.0, 0.0), dv = make_double2(0.0, 0.0);
+    if (HQ) sv = k == 0 ? A[0] : cscale(A[i], -1.0 / k);
+    if (HD) dv = i > 0 ? B[i - 1] : (kb > 0 ? Bprev : make_double2(0.0, 0.0));
+    if (it.w >= 0) {
+      double2 *o = Mp + (int64_t)it.w * 2 * P1;
+      if (KIND == 4) {
+        o[k] = sv;
+        o[P1 + k] = dv;
+      } else {
+        o[k] = cadd(sv, dv);
+      }
+    } else if (KIND == 4) {
+      M[(int64_t)b * P1 + k] = from_d2<E>(sv);
+      M[d_off + (int64_t)b * P1 + k] = from_d2<E>(dv);
+    } else {
+      M[(int64_t)b * P1 + k] = from_d2<E>(cadd(sv, dv));
+    }
+  }
 }
 
-// k_p2m for S and D of the same density: one pass over the powers y^k writes the single-layer row
-// (-q y^k / k, and q at k = 0) and the double-layer row (d y^(k-1), and 0 at k = 0) of every
-// coefficient into LDS [kind][k][nb] with nb = 32 (16 when P1 > 32), so both kinds' sums run in
-// the order of k_p2m<1> and k_p2m<2>. Lane r sums row r of the 2 P1 rows (S rows first). The D
-// multipole goes d_off coefficients after the S one.
-template <typename E>
-__global__ void __launch_bounds__(64) k_p2m_sd(const int32_t *__restrict__ leaves,
-                                               const double2 *__restrict__ bc,
-                                               const int32_t *__restrict__ blevel,
-                                               const int32_t *__restrict__ bsrc0,
-                                               const int32_t *__restrict__ bsrc1,
-                                               const double *__restrict__ level_inv_side,
-                                               const double2 *__restrict__ sxy,
-                                               const double *__restrict__ sq,
-                                               const double2 *__restrict__ sdip, int P1,
-                                               E *__restrict__ M, int64_t src_st, int64_t box_st,
-                                               int64_t d_off) {
-  HIP_DYNAMIC_SHARED(unsigned char, p2m_lds)
-  double2 *T = reinterpret_cast<double2 *>(p2m_lds);  // [2][P1][nb]
-  __shared__ double invk[64];
-  const int nb = P1 > 32 ? 16 : 32;
-  const int32_t b = leaves[blockIdx.x];
-  const int lane = threadIdx.x;
+// Sum of a split box's partial moments (one wavefront per box): four running sums over the
+// partials p = 0, 1, 2, 3 (mod 4), then combined in that order, so the result is deterministic.
+template <int NK, typename E>
+__global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
+                                                 const double2 *__restrict__ Mp, int P1,
+                                                 E *__restrict__ M, int64_t part_st,
+                                                 int64_t box_st, int64_t d_off) {
+  const int4 it = red[blockIdx.x];  // box, first partial, end of partials
   const int64_t jd = blockIdx.y;
-  sq += jd * src_st;
-  sdip += jd * src_st;
+  Mp += jd * part_st;
   M += jd * box_st;
-  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
-  const double2 c = bc[b];
-  const double is = level_inv_side[blevel[b]];
-  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-  double2 *TD = T + (int64_t)P1 * nb;
-  const int32_t s0 = bsrc0[b], s1 = bsrc1[b];
-  for (int32_t base = s0; base < s1; base += nb) {
-    const int n = min(nb, (int)(s1 - base));
-    __syncthreads();  // invk ready; the previous batch's rows consumed
-    if (lane < n) {
-      const int32_t s = base + lane;
-      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-      const double q = sq[s];
-      const double2 d = cscale(sdip[s], -is);
-      T[lane] = make_double2(q, 0.0);
-      TD[lane] = make_double2(0.0, 0.0);
-      double2 pw = make_double2(1.0, 0.0);  // y^(k-1)
-      for (int k = 1; k < P1; ++k) {
-        const double2 pk = cmul(pw, y);
-        T[k * nb + lane] = cscale(pk, -q * invk[k]);
-        TD[k * nb + lane] = cfma(d, pw, make_double2(0.0, 0.0));
-        pw = pk;
-      }
-    }
-    __syncthreads();
+  for (int r = threadIdx.x; r < NK * P1; r += 64) {
+    double2 a4[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                     make_double2(0.0, 0.0)};
+    int32_t p = it.y;
+    for (; p + 4 <= it.z; p += 4)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = lane + 64 * h;
-      if (r < 2 * P1)
-        for (int j = 0; j < n; ++j) acc[h] = cadd(acc[h], T[r * nb + j]);
-    }
+      for (int u = 0; u < 4; ++u) a4[u] = cadd(a4[u], Mp[(int64_t)(p + u) * 2 * P1 + r]);
+    for (int u = 0; p < it.z; ++p, ++u) a4[u] = cadd(a4[u], Mp[(int64_t)p * 2 * P1 + r]);
+    const double2 a = cadd(cadd(a4[0], a4[1]), cadd(a4[2], a4[3]));
+    if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(a);
+    else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(a);
   }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = lane + 64 * h;
-    if (r < P1) M[(int64_t)b * P1 + r] = from_d2<E>(acc[h]);
-    else if (r < 2 * P1) M[d_off + (int64_t)b * P1 + (r - P1)] = from_d2<E>(acc[h]);
-  }
-}
-
-// ------------------------------------------------------------------------------------------
-// Stage 2b, M2M for the non-leaf boxes of one level (eq. (m2m), factored through the real matrix
-// Rm, see tables.hpp): parent_m = sum_q w_q^m sum_k Rm[m][k] (w_q^-k child_q,k).
-template <typename E>
-__global__ void __launch_bounds__(64) k_m2m(int32_t box0, const int32_t *__restrict__ bchild,
-                                            const typename Scalar<E>::T *__restrict__ Rt,
-                                            const E *__restrict__ omega, int P1,
-                                            E *__restrict__ M, int64_t box_st) {
-  __shared__ E X[4][64];
-  const int32_t b = box0 + blockIdx.x;
-  const int m = threadIdx.x;
-  M += (int64_t)blockIdx.y * box_st;
-  const int32_t *ch = bchild + 4 * (int64_t)b;
-  if (ch[0] < 0 && ch[1] < 0 && ch[2] < 0 && ch[3] < 0) return;  // leaf (uniform per block)
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    E x = mk2<E>(0.0, 0.0);
-    if (ch[q] >= 0 && m < P1) {
-      const E w = omega[q * 8 + (m & 7)];
-      x = cmul(M[(int64_t)ch[q] * P1 + m], mk2<E>(w.x, -w.y));
-    }
-    X[q][m] = x;
-  }
-  __syncthreads();
-  if (m >= P1) return;
-  E acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = mk2<E>(0.0, 0.0);
-  for (int k = 0; k <= m; ++k) {
-    const auto r = Rt[k * P1 + m];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q][k], acc[q]);
-  }
-  E out = mk2<E>(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
-  M[(int64_t)b * P1 + m] = out;
-}
-
-// One wavefront forms the M2M of box b from its children (as k_m2m), with a wave-private LDS
-// block X; no work-group barrier, so other waves of the work-group may be elsewhere.
-template <typename E>
-__device__ __forceinline__ void m2m_box_wave(int32_t b, int m, const int32_t *__restrict__ bchild,
-                                             const typename Scalar<E>::T *__restrict__ Rt,
-                                             const E *__restrict__ omega, int P1,
-                                             E *__restrict__ M, E (*X)[64]) {
-  const int32_t *ch = bchild + 4 * (int64_t)b;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    E x = mk2<E>(0.0, 0.0);
-    if (ch[q] >= 0 && m < P1) {
-      const E w = omega[q * 8 + (m & 7)];
-      x = cmul(M[(int64_t)ch[q] * P1 + m], mk2<E>(w.x, -w.y));
-    }
-    X[q][m] = x;
-  }
-  __builtin_amdgcn_wave_barrier();  // a wave's LDS writes precede its later reads
-  if (m < P1) {
-    E acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = mk2<E>(0.0, 0.0);
-    for (int k = 0; k <= m; ++k) {
-      const auto r = Rt[k * P1 + m];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = caxpy(r, X[q][k], acc[q]);
-    }
-    E out = mk2<E>(0.0, 0.0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out = cfma(omega[q * 8 + (m & 7)], acc[q], out);
-    M[(int64_t)b * P1 + m] = out;
-  }
-  __builtin_amdgcn_wave_barrier();  // X may be rewritten by this wave next
-}
-
-// Two levels of Stage 2b in one launch: work-group = one box G of the upper level; wave q first
-// forms the M2M of G's child q (if that child has children), then, after the work-group barrier,
-// wave 0 forms G's own M2M from its children.
-template <typename E>
-__global__ void __launch_bounds__(256) k_m2m2(int32_t box0, const int32_t *__restrict__ bchild,
-                                              const typename Scalar<E>::T *__restrict__ Rt,
-                                              const E *__restrict__ omega, int P1,
-                                              E *__restrict__ M, int64_t box_st) {
-  __shared__ E X[4][4][64];
-  const int32_t g = box0 + blockIdx.x;
-  const int w = threadIdx.x >> 6, m = threadIdx.x & 63;
-  M += (int64_t)blockIdx.y * box_st;
-  const int32_t *gch = bchild + 4 * (int64_t)g;
-  const bool g_leaf = gch[0] < 0 && gch[1] < 0 && gch[2] < 0 && gch[3] < 0;
-  const int32_t c = gch[w];
-  if (c >= 0) {
-    const int32_t *cch = bchild + 4 * (int64_t)c;
-    if (cch[0] >= 0 || cch[1] >= 0 || cch[2] >= 0 || cch[3] >= 0)
-      m2m_box_wave<E>(c, m, bchild, Rt, omega, P1, M, X[w]);
-  }
-  __syncthreads();
-  if (w == 0 && !g_leaf) m2m_box_wave<E>(g, m, bchild, Rt, omega, P1, M, X[0]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1345,17 +1258,14 @@ hipError_t launch_gather(gq_ctx *ctx, const double *d1, int64_t ld1, const doubl
 // Translation tables in the expansion precision.
 template <typename E> struct ExpTables;
 template <> struct ExpTables<double2> {
-  const double *m2m_rt, *m2l_bt;
-  const double2 *omega, *opow;
-  explicit ExpTables(const DevBuffers &d)
-      : m2m_rt(d.m2m_rt), m2l_bt(d.m2l_bt), omega(d.omega), opow(d.opow) {}
+  const double *m2l_bt;
+  const double2 *opow;
+  explicit ExpTables(const DevBuffers &d) : m2l_bt(d.m2l_bt), opow(d.opow) {}
 };
 template <> struct ExpTables<float2> {
-  const float *m2m_rt, *m2l_bt;
-  const float2 *omega, *opow;
-  explicit ExpTables(const DevBuffers &d)
-      : m2m_rt(d.m2m_rt_f), m2l_bt(d.m2l_bt_f), omega(d.omega_f),
-        opow(d.opow_f) {}
+  const float *m2l_bt;
+  const float2 *opow;
+  explicit ExpTables(const DevBuffers &d) : m2l_bt(d.m2l_bt_f), opow(d.opow_f) {}
 };
 
 // The three per-order stages of one order bucket.
@@ -1464,40 +1374,21 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
       }
     }
   }
-  const int32_t nleaf = (int32_t)t.n_leaves;
-  if (nleaf > 0) {
+  constexpr int PK = SD ? 4 : KIND;
+  constexpr int NK = SD ? 2 : 1;
+  const int64_t part_st = ctx->n_p2m_parts * 2 * P1;
+  if (ctx->n_p2m_items > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    const size_t lds = sizeof(double2) * (P1 > 32 ? 32 : 64) * P1;
-    if constexpr (SD) {
-      const size_t lds2 = sizeof(double2) * 2 * (P1 > 32 ? 16 : 32) * P1;
-      hipLaunchKernelGGL((k_p2m_sd<E>), dim3(nleaf, nd), dim3(64), lds2, st, d.leaves, d.bc,
-                         d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
-                         S.src, S.box, (int64_t)nd * S.box);
-    } else {
-      hipLaunchKernelGGL((k_p2m<KIND, E>), dim3(nleaf, nd), dim3(64), lds, st, d.leaves, d.bc,
-                         d.blevel, d.bsrc0, d.bsrc1, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M,
-                         S.src, S.box);
-    }
+    auto kern = P1 <= 8 ? k_p2m_all<PK, 1, E> : P1 <= 16 ? k_p2m_all<PK, 2, E>
+              : P1 <= 32 ? k_p2m_all<PK, 4, E> : k_p2m_all<PK, 8, E>;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, nd), dim3(64), 0, st, d.p2m_item,
+                       d.bc, d.blevel, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M, d.Mp, S.src,
+                       S.box, part_st, (int64_t)nd * S.box);
   }
-  {
+  if (ctx->n_p2m_red > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    // two levels per launch where two remain (a work-group per box of the upper one)
-    for (int l = t.n_levels - 2; l >= ctx->m2m_first_depth;) {
-      if (l - 1 >= ctx->m2m_first_depth) {
-        const int32_t b0 = (int32_t)t.level_start[l - 1];
-        const int32_t nb = (int32_t)(t.level_start[l] - b0);
-        if (nb > 0)
-          hipLaunchKernelGGL(k_m2m2<E>, dim3(nb, slots), dim3(256), 0, st, b0, d.bchild, X.m2m_rt,
-                             X.omega, P1, M, S.box);
-        l -= 2;
-      } else {
-        const int32_t b0 = (int32_t)t.level_start[l], nb = (int32_t)(t.level_start[l + 1] - b0);
-        if (nb > 0)
-          hipLaunchKernelGGL(k_m2m<E>, dim3(nb, slots), dim3(64), 0, st, b0, d.bchild, X.m2m_rt,
-                             X.omega, P1, M, S.box);
-        l -= 1;
-      }
-    }
+    hipLaunchKernelGGL((k_m_reduce<NK, E>), dim3((uint32_t)ctx->n_p2m_red, nd), dim3(64), 0, st,
+                       d.p2m_red, d.Mp, P1, M, part_st, S.box, (int64_t)nd * S.box);
   }
   e = hipEventRecord(ctx->ev_up, st);
   if (e != hipSuccess) return e;

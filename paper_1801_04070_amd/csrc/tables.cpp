@@ -34,54 +34,6 @@ void build_tables(Tables &t, int p, int max_pq) {
     return r;
   };
 
-  t.m2m.assign((size_t)4 * P1 * P1 * 2, 0.0);
-  for (int q = 0; q < 4; ++q) {
-    const long double sx = (q & 1) ? 0.5L : -0.5L, sy = (q & 2) ? 0.5L : -0.5L;
-    // child center - parent center = s_child * u, u = (sx, sy)
-    const cld u(sx, sy);
-    const cld mv = u;  // -v with v = (parent - child)/s_child = -u
-    double *M = &t.m2m[(size_t)q * P1 * P1 * 2];
-    // M2M, eq. (m2m) with y = parent - child: alpha_m = -a_0 (-y)^m/m + sum_k C(m-1,k-1) a_k (-y)^(m-k)
-    for (int m = 0; m <= p; ++m) {
-      const long double s = std::pow(2.0L, -(long double)m);
-      for (int k = 0; k <= m; ++k) {
-        cld val;
-        if (m == 0) val = (k == 0) ? cld(1.0L) : cld(0.0L);
-        else if (k == 0) val = -cpow(mv, m) * (s / (long double)m);
-        else val = cpow(mv, m - k) * (C(m - 1, k - 1) * s);
-        M[((size_t)m * P1 + k) * 2] = (double)val.real();
-        M[((size_t)m * P1 + k) * 2 + 1] = (double)val.imag();
-      }
-    }
-  }
-
-  // factored shifts (see tables.hpp): |u| = 2^-1/2 for every quadrant
-  {
-    const long double au = std::sqrt(0.5L);
-    t.m2m_rt.assign((size_t)P1 * P1, 0.0);
-    for (int m = 0; m <= p; ++m) {
-      const long double s = std::pow(2.0L, -(long double)m);
-      for (int k = 0; k <= m; ++k) {
-        long double v;
-        if (m == 0) v = (k == 0) ? 1.0L : 0.0L;
-        else if (k == 0) v = -std::pow(au, (long double)m) * s / (long double)m;
-        else v = C(m - 1, k - 1) * std::pow(au, (long double)(m - k)) * s;
-        t.m2m_rt[(size_t)k * P1 + m] = (double)v;
-      }
-    }
-    t.omega.assign(4 * 8 * 2, 0.0);
-    for (int q = 0; q < 4; ++q) {
-      const cld u((q & 1) ? 0.5L : -0.5L, (q & 2) ? 0.5L : -0.5L);
-      const cld w = u / std::abs(u);
-      cld pw(1.0L);
-      for (int j = 0; j < 8; ++j) {
-        t.omega[(q * 8 + j) * 2] = (double)pw.real();
-        t.omega[(q * 8 + j) * 2 + 1] = (double)pw.imag();
-        pw *= w;
-      }
-    }
-  }
-
   // M2L factor B, eq. (m2l) with the corrected sign of the a_0 term
   t.m2l_b.assign((size_t)P1 * P1, 0.0);
   for (int m = 0; m <= p; ++m)

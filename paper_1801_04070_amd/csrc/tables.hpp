@@ -4,7 +4,8 @@
 //   multipole  M_b(z) = a_0 log(z - c_b) + sum_k a_k (z - c_b)^-k,   stored as  a_k / s^k
 //   local      L_b(z) = sum_k b_k (z - c_b)^k,                       stored as  b_k s^k
 // With this scaling the translations of Sec. 3.1 become level independent:
-//   M2M (eq. m2m), child -> parent: four fixed matrices, one per child quadrant;
+//   multipoles are formed directly from each box's subtree sources (the M2M of eq. (m2m) keeps
+//   the first p + 1 moments exact in 2-D, so no table is needed);
 //   L2L (eq. l2l) from an ancestor across any level gap: a fixed binomial matrix between
 //   diagonal factors of the shift (applied on the device);
 //   M2L (eq. m2l, with the sign of the a_0 term corrected, see below) between same-level boxes at
@@ -19,16 +20,9 @@
 
 namespace gq {
 
-// The child-parent offset u = (c_child - c_parent)/s_child = (+-1 +- i)/2 has modulus 2^-1/2 for
-// every quadrant q, so with w_q = u_q/|u_q| (a unit 8th root of unity) M2M factors through one
-// real matrix, exactly like M2L:
-//   M2M  parent_m += w_q^m  sum_k Rm[m][k] (w_q^-k child_k)
 // Real matrices are stored transposed ([k][m]) so that lanes indexed by m read consecutive words.
 struct Tables {
   int p = 0;                      // FMM order; arrays use P1 = p + 1 coefficients
-  std::vector<double> m2m;        // [4][P1][P1] complex interleaved: parent_m += T[q][m][k] child_k
-  std::vector<double> m2m_rt;     // [P1 (k)][P1 (m)] real Rm, transposed
-  std::vector<double> omega;      // [4][8] complex: w_q^j, j = 0..7
   std::vector<double> m2l_bt;     // [P1 (k)][P1 (m)] real B, transposed
   std::vector<double> m2l_b;      // [P1][P1] real B
   std::vector<double> opow;       // [121][P1] complex: o^-k for o = (i - 5) + (j - 5) i, index i*11+j

@@ -60,6 +60,10 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> 
         out = {k: {"flops": s[k]["flops"] + d[k]["flops"], "bytes": s[k]["bytes"] + d[k]["bytes"],
                    "bound": s[k]["bound"]} for k in s}
         row = (p_qbx + 1) * 16
+        P1 = p_fmm + 1
+        out["p2m"] = {"flops": stats.get("n_moment_pairs", 0) * (4 + 6 * p_fmm + 12 * P1),
+                      "bytes": stats.get("n_moment_pairs", 0) * 40
+                               + 2 * stats.get("n_moment_boxes", 0) * P1 * 16, "bound": "alu"}
         out["near"] = {"flops": stats["near_pairs"] * _near_pair_flops(4, p_qbx),
                        "bytes": stats["near_sources"] * (40 + 4) + stats["n_ctr"] * 24
                                 + 2 * stats["n_ctr"] * row,
@@ -91,17 +95,22 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int) -> 
         "bytes": stats["n_list2"] * (P1 * 16 + 8) + stats["n_local_boxes"] * P1 * 16,
         "bound": "alu"}
     tri = P1 * (P1 + 1) // 2
-    out["m2m"] = {"flops": (stats["n_boxes"] - 1) * tri * 8,
-                  "bytes": 2 * stats["n_boxes"] * P1 * 16, "bound": "alu"}
+    # Stage 2 as direct moments (k_p2m_all): per (box, subtree source) pair y (4), p powers (6
+    # each) and the accumulations (S: 4 per order, D: 8); "m2m" is the sum of split boxes' partials
+    nk = 2 if kind == 3 else 1
+    out["m2m"] = {"flops": stats.get("n_moment_parts", 0) * P1 * 2 * nk,
+                  "bytes": stats.get("n_moment_parts", 0) * P1 * 16 * nk
+                           + stats.get("n_moment_parts", 0) // 2 * P1 * 16, "bound": "latency"}
     # Stage 7 as a gather: per (box, ancestor) pair t^j a_j (6 per term), the binomial sum
     # (real x complex multiply-add, 4 per term of the triangle), u^-m (6) and the sum (2)
     out["l2l"] = {"flops": stats.get("n_l2l_pairs", 0) * (6 * P1 + 4 * tri + 8 * P1)
                            + stats.get("n_l2l_sinks", 0) * 2 * P1,
                   "bytes": stats.get("n_l2l_pairs", 0) * (P1 * 16 + 36)
                            + 2 * stats.get("n_l2l_sinks", 0) * P1 * 16, "bound": "alu"}
-    p2m = 4 + (10 * p if kind & 1 else 0) + (8 * p if kind & 2 else 0)
-    out["p2m"] = {"flops": stats["n_src"] * p2m,
-                  "bytes": stats["n_src"] * src_rec + stats["n_leaves"] * P1 * 16, "bound": "alu"}
+    p2m = 4 + 6 * p + (4 * P1 if kind & 1 else 0) + (8 * P1 if kind & 2 else 0)
+    out["p2m"] = {"flops": stats.get("n_moment_pairs", 0) * p2m,
+                  "bytes": stats.get("n_moment_pairs", 0) * src_rec
+                           + stats.get("n_moment_boxes", 0) * P1 * 16, "bound": "alu"}
     out["gather"] = {"flops": stats["n_src"] * 3, "bytes": stats["n_src"] * (8 + 8 + 16 + 4 + src_rec - 16),
                      "bound": "hbm"}
     out["finalize"] = {"flops": stats["n_tgt"] * 2, "bytes": stats["n_tgt"] * (16 + 8 + 8), "bound": "hbm"}
