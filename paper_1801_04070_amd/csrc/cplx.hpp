@@ -5,9 +5,14 @@
 
 namespace gq {
 
+// The fused multiply-adds are spelled out, so every kernel rounds a product the same way whatever
+// the compiler would contract in its context (results of different kernels stay comparable bit
+// for bit).
 __host__ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
+// |z|^2
+__host__ __device__ __forceinline__ double cnorm2(double2 z) { return fma(z.x, z.x, z.y * z.y); }
 __host__ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
@@ -35,7 +40,7 @@ __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 __host__ __device__ __forceinline__ double2 cinv(double2 a) {
-  double s = 1.0 / (a.x * a.x + a.y * a.y);
+  double s = 1.0 / cnorm2(a);
   return make_double2(a.x * s, -a.y * s);
 }
 // z^n for n >= 0 by binary powering

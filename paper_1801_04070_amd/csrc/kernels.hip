@@ -173,13 +173,13 @@ __global__ void __launch_bounds__(64) k_p2m_all(
         o[k] = sv;
         o[P1 + k] = dv;
       } else {
-        o[k] = cadd(sv, dv);
+        o[k] = KIND == 1 ? sv : KIND == 2 ? dv : cadd(sv, dv);
       }
     } else if (KIND == 4) {
       M[(int64_t)b * P1 + k] = from_d2<E>(sv);
       M[d_off + (int64_t)b * P1 + k] = from_d2<E>(dv);
     } else {
-      M[(int64_t)b * P1 + k] = from_d2<E>(cadd(sv, dv));
+      M[(int64_t)b * P1 + k] = from_d2<E>(KIND == 1 ? sv : KIND == 2 ? dv : cadd(sv, dv));
     }
   }
 }
@@ -330,13 +330,15 @@ __global__ void __launch_bounds__(64) k_m2l(
 // ------------------------------------------------------------------------------------------
 // Stage 6b, P2L (eq. (local) about c_b) for the sources of a box's List 4 far boxes, added to the
 // box local that k_m2l wrote. One wavefront per box with such sources (their indices flattened
-// on the host); nb = 32 sources at a time (16 when P1 > 32): lane j forms source j's
-// contribution to every coefficient with a running power of 1/y and stores it in LDS; lane r
-// then sums row r over the batch in source order. KIND 4 (S and D of one density) forms both
-// kinds' rows from the same powers, S into the first P1 rows and D into the next P1, and adds the
-// D rows d_off coefficients further.
-//   coefficient 0: q log|s y| + d/y,  coefficient k >= 1: -q y^-k / k + d y^-(k+1)
-template <int KIND, typename E>
+// on the host). With v = 1/y, coefficient 0 is q log|s y| + d v and coefficient k >= 1 is
+// -q v^k / k + d v^(k+1). Lanes: NBLK blocks of 8 consecutive powers (j = 8 kb + i, covering
+// j = 0..P1) times 64 / NBLK source groups; a lane forms v^(8 kb) by squaring and the block by a
+// multiply chain, accumulates A_j = sum q v^j and B_j = sum d v^j in registers (and the log sum
+// on the lanes of block 0), and a fixed xor tree adds the groups. Single layer row j = -A_j / j
+// (the log sum at j = 0), double layer row j = B_(j+1) (the next block's first power from the
+// neighbouring lane, or for the last block one extra power). KIND 4 (S and D of one density)
+// adds the D rows d_off coefficients further.
+template <int KIND, int NBLK, typename E>
 __global__ void __launch_bounds__(64) k_p2l(
     const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
@@ -344,75 +346,104 @@ __global__ void __launch_bounds__(64) k_p2l(
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, int P1, E *__restrict__ L, int64_t src_st,
     int64_t box_st, int64_t d_off) {
-  constexpr int NK = KIND == 4 ? 2 : 1;  // kinds formed per pass
-  HIP_DYNAMIC_SHARED(unsigned char, p2l_lds)
-  double2 *T = reinterpret_cast<double2 *>(p2l_lds);  // [NK][P1][nb]
-  __shared__ double invk[64];
-  const int nb = P1 > 32 ? 16 : 32;
+  constexpr bool HQ = (KIND & 1) || KIND == 4, HD = (KIND & 2) || KIND == 4;
+  constexpr int G = 64 / NBLK;
   const int4 it = items[blockIdx.x];  // box, first source, end of sources
   const int32_t b = it.x;
   const int lane = threadIdx.x;
+  const int kb = lane % NBLK, g = lane / NBLK;
   {
     const int64_t jd = blockIdx.y;
     sq += jd * src_st;
     sdip += jd * src_st;
     L += jd * box_st;
   }
-  invk[lane] = lane > 0 ? 1.0 / lane : 0.0;
   const int lev = blevel[b];
   const double2 c = bc[b];
   const double is = level_inv_side[lev];
   const double logs = level_log_side[lev];
   const double2 *lt = g_log_tab;
-  double2 *TD = T + (int64_t)P1 * nb;
-  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-  for (int32_t base = it.y; base < it.z; base += nb) {
-    const int n = min(nb, (int)(it.z - base));
-    __syncthreads();  // invk ready; the previous batch's rows consumed
-    if (lane < n) {
-      const int32_t s = src_idx[base + lane];
-      const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
-      const double2 inv = cinv(y);
-      const double q = (KIND & 1) || KIND == 4 ? sq[s] : 0.0;
-      const double2 dl = (KIND & 2) || KIND == 4 ? cscale(sdip[s], is) : make_double2(0.0, 0.0);
-      double2 pw = inv;
-      if (KIND == 4) {
-        T[lane] = make_double2(q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt)), 0.0);
-        TD[lane] = cmul(dl, inv);
-        for (int k = 1; k < P1; ++k) {
-          T[k * nb + lane] = cscale(pw, -q * invk[k]);
-          pw = cmul(pw, inv);
-          TD[k * nb + lane] = cfma(dl, pw, make_double2(0.0, 0.0));
-        }
-      } else {
-        double2 c0 = (KIND & 2) ? cmul(dl, inv) : make_double2(0.0, 0.0);
-        if (KIND & 1) c0.x += q * (logs + 0.5 * log_tab(y.x * y.x + y.y * y.y, lt));
-        T[lane] = c0;
-        for (int k = 1; k < P1; ++k) {
-          double2 ck = (KIND & 1) ? cscale(pw, -q * invk[k]) : make_double2(0.0, 0.0);
-          pw = cmul(pw, inv);
-          if (KIND & 2) ck = cfma(dl, pw, ck);
-          T[k * nb + lane] = ck;
+  double2 A[8], B[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    A[i] = make_double2(0.0, 0.0);
+    B[i] = make_double2(0.0, 0.0);
+  }
+  double lsum = 0.0;
+  double2 Bx = make_double2(0.0, 0.0);  // d v^(8 NBLK), on the last block's lanes
+  for (int32_t j = it.y + g; j < it.z; j += G) {
+    const int32_t s = src_idx[j];
+    const double2 y = make_double2((sxy[s].x - c.x) * is, (sxy[s].y - c.y) * is);
+    const double r2 = cnorm2(y);
+    const double ir2 = rcp_nr(r2);
+    const double2 v = make_double2(y.x * ir2, -y.y * ir2);
+    const double q = HQ ? sq[s] : 0.0;
+    const double2 d = HD ? cscale(sdip[s], is) : make_double2(0.0, 0.0);
+    if (HQ && kb == 0) lsum = fma(q, fma(0.5, log_tab(r2, lt), logs), lsum);
+    double2 pw = make_double2(1.0, 0.0);  // v^(8 kb)
+    if (NBLK > 1) {
+      const double2 v2 = cmul(v, v), v4 = cmul(v2, v2), v8 = cmul(v4, v4);
+      if (kb & 1) pw = v8;
+      if (NBLK > 2) {
+        const double2 v16 = cmul(v8, v8);
+        if (kb & 2) pw = (kb & 1) ? cmul(v16, v8) : v16;
+        if (NBLK > 4) {
+          const double2 v32 = cmul(v16, v16);
+          if (kb & 4) pw = cmul(pw, v32);
         }
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = lane + 64 * h;
-      if (r < NK * P1)
-        for (int j = 0; j < n; ++j) acc[h] = cadd(acc[h], T[r * nb + j]);
+    for (int i = 0; i < 8; ++i) {
+      if (HQ) A[i] = caxpy(q, pw, A[i]);
+      if (HD) B[i] = cfma(d, pw, B[i]);
+      if (i < 7) pw = cmul(pw, v);
     }
+    if (HD && kb == NBLK - 1) Bx = cfma(d, cmul(pw, v), Bx);
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = lane + 64 * h;
-    if (r < P1) {
-      E *o = L + (int64_t)b * P1 + r;
-      *o = from_d2<E>(cadd(to_d2(*o), acc[h]));
-    } else if (r < NK * P1) {
-      E *o = L + d_off + (int64_t)b * P1 + (r - P1);
-      *o = from_d2<E>(cadd(to_d2(*o), acc[h]));
+  for (int o = 32; o >= NBLK; o >>= 1) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (HQ) {
+        A[i].x += __shfl_xor(A[i].x, o, 64);
+        A[i].y += __shfl_xor(A[i].y, o, 64);
+      }
+      if (HD) {
+        B[i].x += __shfl_xor(B[i].x, o, 64);
+        B[i].y += __shfl_xor(B[i].y, o, 64);
+      }
+    }
+    if (HQ) lsum += __shfl_xor(lsum, o, 64);
+    if (HD) {
+      Bx.x += __shfl_xor(Bx.x, o, 64);
+      Bx.y += __shfl_xor(Bx.y, o, 64);
+    }
+  }
+  // B_(8 kb + 8) from the lane of the next block (lanes 0..NBLK-1 hold the sums)
+  double2 Bnext = make_double2(0.0, 0.0);
+  if (HD) {
+    Bnext.x = __shfl(B[0].x, lane + 1, 64);
+    Bnext.y = __shfl(B[0].y, lane + 1, 64);
+  }
+  if (g != 0) return;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = 8 * kb + i;
+    if (k >= P1) break;
+    double2 sv = make_double2(0.0, 0.0), dv = make_double2(0.0, 0.0);
+    if (HQ) sv = k == 0 ? make_double2(lsum, 0.0) : cscale(A[i], -1.0 / k);
+    if (HD) dv = i < 7 ? B[i + 1] : (kb + 1 < NBLK ? Bnext : Bx);
+    if (KIND == 4) {
+      E *o = L + (int64_t)b * P1 + k;
+      *o = from_d2<E>(cadd(to_d2(*o), sv));
+      E *od = L + d_off + (int64_t)b * P1 + k;
+      *od = from_d2<E>(cadd(to_d2(*od), dv));
+    } else {
+      // the same expression per kind as above, so each kind rounds as in KIND 4
+      E *o = L + (int64_t)b * P1 + k;
+      const double2 val = KIND == 1 ? sv : KIND == 2 ? dv : cadd(sv, dv);
+      *o = from_d2<E>(cadd(to_d2(*o), val));
     }
   }
 }
@@ -536,7 +567,7 @@ struct NearAcc {
     qsum = 0.0;
   }
   __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
-    const double r2 = z.x * z.x + z.y * z.y;
+    const double r2 = cnorm2(z);
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND == 1) {
@@ -571,7 +602,7 @@ struct NearAcc {
   }
   // Add the finished near-field coefficients into alpha (scaled by r^m), given log r.
   __device__ __forceinline__ void finish(double2 *alpha, double logr) const {
-    if (KIND & 1) alpha[0].x += 0.5 * logsum + qsum * logr;
+    if (KIND & 1) alpha[0].x += fma(qsum, logr, 0.5 * logsum);
     if (KIND == 1) {
 #pragma unroll
       for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[m], alpha[m]);
@@ -599,7 +630,7 @@ struct NearAccMD {
   }
   __device__ __forceinline__ void add(double2 z, const double *q, const double2 *dr,
                                       const double2 *lt) {
-    const double r2 = z.x * z.x + z.y * z.y;
+    const double r2 = cnorm2(z);
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND & 1) {
@@ -651,7 +682,7 @@ struct NearAccMD {
     }
   }
   __device__ __forceinline__ void finish(int g, double2 *alpha, double logr) const {
-    if (KIND & 1) alpha[0].x += 0.5 * logsum[g] + qsum[g] * logr;
+    if (KIND & 1) alpha[0].x += fma(qsum[g], logr, 0.5 * logsum[g]);
     if (KIND == 1) {
 #pragma unroll
       for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[g][m], alpha[m]);
@@ -781,7 +812,7 @@ struct NearAccSD {
     qsum = 0.0;
   }
   __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
-    const double r2 = z.x * z.x + z.y * z.y;
+    const double r2 = cnorm2(z);
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     logsum = fma(q, log_tab(r2, lt), logsum);
@@ -865,7 +896,7 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   }
   if (active && sl == 0) {
     double2 *row = anear + (int64_t)(row_first + cl) * rs;
-    row[0] = make_double2(0.5 * acc.logsum + acc.qsum * log(r), 0.0);
+    row[0] = make_double2(0.0 + fma(acc.qsum, log(r), 0.5 * acc.logsum), 0.0);
 #pragma unroll
     for (int m = 1; m <= PQ; ++m) row[m] = caxpy(-1.0 / m, acc.as[m], make_double2(0.0, 0.0));
     double2 *rowd = row + d_slot * row_st;
@@ -998,7 +1029,7 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
     wk = cmul(wk, iw);
   }
   // alpha_0 += a_0 log|y| + V_0;  alpha_m += u^m (V_m - a_0/m)
-  alpha[0].x += a0 * 0.5 * log_tab(y.x * y.x + y.y * y.y, lt);
+  alpha[0].x += a0 * 0.5 * log_tab(cnorm2(y), lt);
   alpha[0] = cadd(alpha[0], S[0]);
   double2 pm = u;
 #pragma unroll
@@ -1417,12 +1448,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
                        d.level_log_side, d.v_start, d.v_idx, d.v_off, M, X.m2l_bt, X.opow,
                        d.ologabs, P1, L, S.box);
     if (ctx->n_p2l_boxes > 0) {
-      const size_t lds = sizeof(double2) * (SD ? 2 : 1) * (P1 > 32 ? 16 : 32) * P1;
-      constexpr int PK = SD ? 4 : KIND;
-      hipLaunchKernelGGL((k_p2l<PK, E>), dim3((uint32_t)ctx->n_p2l_boxes, nd), dim3(64), lds, st,
-                         d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
-                         d.level_log_side, d.sxy, d.sq, d.sdip, P1, L, S.src, S.box,
-                         (int64_t)nd * S.box);
+      auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
+              : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
+      hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, nd), dim3(64), 0, st, d.p2l_item,
+                         d.p2l_src, d.bc, d.blevel, d.level_inv_side, d.level_log_side, d.sxy,
+                         d.sq, d.sdip, P1, L, S.src, S.box, (int64_t)nd * S.box);
     }
   }
   if (ctx->n_l2g_sinks > 0) {
