@@ -276,47 +276,60 @@ __global__ void __launch_bounds__(64) k_m2l(
   double logsum0 = 0.0;
   const int pr = c16 >> 1, comp = c16 & 1;
   const int32_t v0 = v_start[b], v1 = v_start[b + 1];
-  for (int32_t j0 = v0; j0 < v1; j0 += 8) {
-    const int nbat = min(8, (int)(v1 - j0));
-    const bool pv = pr < nbat;
-    const int32_t d = pv ? v_idx[j0 + pr] : 0;
-    const int32_t oi = pv ? v_off[j0 + pr] : 0;
-    const E *Md = M + (int64_t)d * P1;
-    const E *op = opow + (int64_t)oi * P1;
-    R Bf[KS];
+  for (int32_t e0 = v0; e0 < v1; e0 += 64) {
+    // up to 64 of the box's List 2 entries, one per lane, and each entry's a_0 log|s o| term
+    const int ne = min(64, (int)(v1 - e0));
+    const int32_t my_d = lane < ne ? v_idx[e0 + lane] : 0;
+    const int32_t my_o = lane < ne ? v_off[e0 + lane] : 0;
+    if (lane < ne) logsum0 += (double)M[(int64_t)my_d * P1].x * (logs + ologabs[my_o]);
+    for (int j0 = 0; j0 < ne; j0 += 8) {
+      const int nbat = min(8, ne - j0);
+      const bool pv = pr < nbat;
+      const int32_t d = __shfl(my_d, j0 + pr, 64);
+      const int32_t oi = __shfl(my_o, j0 + pr, 64);
+      const E *Md = M + (int64_t)d * P1;
+      const E *op = opow + (int64_t)oi * P1;
+      // this lane's output-row factors o^-m, loaded with the operands
+      E opm[RT][4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + g;
-      R x = R(0);
-      if (pv && k < P1) {
-        const E mk = Md[k], ok = op[k];
-        x = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rt + Mfma16<R>::row(g, v);
+          opm[rt][v] = (pv && !comp && m < P1) ? op[m] : mk2<E>(0.0, 0.0);
+        }
+      R Bf[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + g;
+        R x = R(0);
+        if (pv && k < P1) {
+          const E mk = Md[k], ok = op[k];
+          x = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
+        }
+        Bf[ks] = x;
       }
-      Bf[ks] = x;
-    }
-    Acc C[RT];
+      Acc C[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      C[rt] = Acc{R(0), R(0), R(0), R(0)};
+      for (int rt = 0; rt < RT; ++rt) {
+        C[rt] = Acc{R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
-    }
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = 16 * rt + Mfma16<R>::row(g, v);
-        const double y = C[rt][v];
-        const double yo = __shfl_xor(y, 1, 64);
-        if (pv && !comp && m < P1) Pt[pr][m] = cmul(make_double2(y, yo), to_d2(op[m]));
+        for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
       }
-    __syncthreads();
-    if (lane < P1)
-      for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
-    __syncthreads();
-    // a_0 log|s o| of pair `lane` of the batch
-    if (lane < nbat)
-      logsum0 += (double)M[(int64_t)v_idx[j0 + lane] * P1].x * (logs + ologabs[v_off[j0 + lane]]);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rt + Mfma16<R>::row(g, v);
+          const double y = C[rt][v];
+          const double yo = __shfl_xor(y, 1, 64);
+          if (pv && !comp && m < P1) Pt[pr][m] = cmul(make_double2(y, yo), to_d2(opm[rt][v]));
+        }
+      __syncthreads();
+      if (lane < P1)
+        for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
+      __syncthreads();
+    }
   }
   // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
 #pragma unroll
