@@ -241,14 +241,18 @@ template <> struct Mfma16<float> {
   static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
-template <int RT, typename E>
+// NSL = 2 (S and D of one density): one wavefront takes both slots of its box, 4 List 2 pairs x
+// 2 slots per batch (columns 0-7 slot 0, 8-15 slot 1), so the slots share the pair indices, the
+// factors o^-k and o^-m and the wavefront; slot 1 sits d_off coefficients after slot 0.
+template <int RT, int NSL, typename E>
 __global__ void __launch_bounds__(64) k_m2l(
     const int32_t *__restrict__ tboxes, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_log_side, const int32_t *__restrict__ v_start,
     const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
     const E *__restrict__ M, const typename Scalar<E>::T *__restrict__ Bt,
     const E *__restrict__ opow, const double *__restrict__ ologabs, int P1, E *__restrict__ L,
-    int64_t box_st) {
+    int64_t box_st, int64_t d_off) {
+  constexpr int PB = 8 / NSL;  // pairs per batch
   using R = typename Scalar<E>::T;
   using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
@@ -272,22 +276,34 @@ __global__ void __launch_bounds__(64) k_m2l(
     }
   // lane m sums coefficient m; a batch's rows, scaled per pair, are transposed through LDS
   __shared__ double2 Pt[8][16 * RT];
-  double2 acc = make_double2(0.0, 0.0);
-  double logsum0 = 0.0;
+  double2 acc[NSL];
+  double logsum0[NSL];
+#pragma unroll
+  for (int h = 0; h < NSL; ++h) {
+    acc[h] = make_double2(0.0, 0.0);
+    logsum0[h] = 0.0;
+  }
   const int pr = c16 >> 1, comp = c16 & 1;
+  const int slot = pr / PB, pp = pr % PB;  // column pair: slot and pair of the batch
+  const E *Ms = M + (slot ? d_off : 0);
   const int32_t v0 = v_start[b], v1 = v_start[b + 1];
   for (int32_t e0 = v0; e0 < v1; e0 += 64) {
     // up to 64 of the box's List 2 entries, one per lane, and each entry's a_0 log|s o| term
     const int ne = min(64, (int)(v1 - e0));
     const int32_t my_d = lane < ne ? v_idx[e0 + lane] : 0;
     const int32_t my_o = lane < ne ? v_off[e0 + lane] : 0;
-    if (lane < ne) logsum0 += (double)M[(int64_t)my_d * P1].x * (logs + ologabs[my_o]);
-    for (int j0 = 0; j0 < ne; j0 += 8) {
-      const int nbat = min(8, ne - j0);
-      const bool pv = pr < nbat;
-      const int32_t d = __shfl(my_d, j0 + pr, 64);
-      const int32_t oi = __shfl(my_o, j0 + pr, 64);
-      const E *Md = M + (int64_t)d * P1;
+    if (lane < ne) {
+      const double lo = logs + ologabs[my_o];
+#pragma unroll
+      for (int h = 0; h < NSL; ++h)
+        logsum0[h] += (double)M[(h ? d_off : 0) + (int64_t)my_d * P1].x * lo;
+    }
+    for (int j0 = 0; j0 < ne; j0 += PB) {
+      const int nbat = min(PB, ne - j0);
+      const bool pv = pp < nbat;
+      const int32_t d = __shfl(my_d, j0 + pp, 64);
+      const int32_t oi = __shfl(my_o, j0 + pp, 64);
+      const E *Md = Ms + (int64_t)d * P1;
       const E *op = opow + (int64_t)oi * P1;
       // this lane's output-row factors o^-m, loaded with the operands
       E opm[RT][4];
@@ -327,17 +343,25 @@ __global__ void __launch_bounds__(64) k_m2l(
         }
       __syncthreads();
       if (lane < P1)
-        for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
+#pragma unroll
+        for (int h = 0; h < NSL; ++h)
+          for (int p = 0; p < nbat; ++p) acc[h] = cadd(acc[h], Pt[h * PB + p][lane]);
       __syncthreads();
     }
   }
   // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) logsum0 += __shfl_xor(logsum0, o, 64);
+  for (int h = 0; h < NSL; ++h) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) logsum0[h] += __shfl_xor(logsum0[h], o, 64);
+  }
   const int m = lane;
-  if (m == 0) acc.x += logsum0;
   if (m >= P1) return;
-  L[(int64_t)b * P1 + m] = from_d2<E>(acc);
+#pragma unroll
+  for (int h = 0; h < NSL; ++h) {
+    if (m == 0) acc[h].x += logsum0[h];
+    L[(h ? d_off : 0) + (int64_t)b * P1 + m] = from_d2<E>(acc[h]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1455,11 +1479,13 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    auto kern = P1 <= 16 ? k_m2l<1, E> : P1 <= 32 ? k_m2l<2, E>
-              : P1 <= 48 ? k_m2l<3, E> : k_m2l<4, E>;
-    hipLaunchKernelGGL(kern, dim3(ntb, slots), dim3(64), 0, st, d.tboxes, d.blevel,
+    // S and D of one density: both slots in one wavefront
+    constexpr int NS = SD ? 2 : 1;
+    auto kern = P1 <= 16 ? k_m2l<1, NS, E> : P1 <= 32 ? k_m2l<2, NS, E>
+              : P1 <= 48 ? k_m2l<3, NS, E> : k_m2l<4, NS, E>;
+    hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.blevel,
                        d.level_log_side, d.v_start, d.v_idx, d.v_off, M, X.m2l_bt, X.opow,
-                       d.ologabs, P1, L, S.box);
+                       d.ologabs, P1, L, S.box, (int64_t)nd * S.box);
     if (ctx->n_p2l_boxes > 0) {
       auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
               : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
