@@ -386,3 +386,38 @@ def test_forest_matches_separate_trees():
                 got = sorted(key_f[e] for e in fi[fs[fbx]:fs[fbx + 1]])
                 exp = sorted(sb[e][1:] for e in si[ss[b]:ss[b + 1]])
                 assert got == exp, (name, k, b)
+
+
+@pytest.mark.parametrize("name", ["stars", "deep"])
+def test_stage_work_counts(name):
+    """The work the expansion stages are sized by, recomputed from the lists: direct moments for
+    every box M2L (List 2) or M2QBXL (List 3 far) reads, split into 512-source items; the
+    Stage 7 gather over every box owning centers and its ancestors with a List 2 or List 4 far
+    row of their own."""
+    if name == "stars":
+        g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+        q, T = _build(g, p_qbx=12, p_fmm=30)
+    else:
+        g = gi.random_stars(n_curves=3, panels_per_curve=64, seed=21, box=12.0)
+        q, T = _build(g, p_qbx=12, p_fmm=30, n_max=8)
+    st = T["stats"]
+    need = np.zeros(len(T["level"]), bool)
+    need[T["list2"][1]] = True
+    need[T["list3f"][1]] = True
+    n = T["src"][:, 1] - T["src"][:, 0]
+    assert st["n_moment_boxes"] == need.sum()
+    assert st["n_moment_pairs"] == n[need].sum()
+    big = need & (n > 512)
+    assert st["n_moment_parts"] == np.ceil(n[big] / 512).sum()
+    own = (np.diff(T["list2"][0]) > 0) | (np.diff(T["list4f"][0]) > 0)
+    sinks = np.nonzero(T["ctr"][:, 1] > T["ctr"][:, 0])[0]
+    pairs = 0
+    for b in sinks:
+        a = T["parent"][b]
+        while a >= 0:
+            pairs += own[a]
+            a = T["parent"][a]
+    assert st["n_l2l_sinks"] == len(sinks)
+    assert st["n_l2l_pairs"] == pairs
+    # every box read by M2L/M2QBXL has sources (its moments are not trivially zero)
+    assert (n[need] > 0).all()
