@@ -1169,6 +1169,7 @@ __global__ void __launch_bounds__(256) k_qbx_center(
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
     const E *Lb = L + (int64_t)b * P1;
+#pragma unroll 4
     for (int k = P1 - 1; k >= 0; --k) {
       const double2 bk = to_d2(Lb[k]);
       const double *Ck = l2q_binom + (int64_t)k * ls;
