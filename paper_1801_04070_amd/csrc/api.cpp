@@ -89,12 +89,6 @@ gq_status alloc_ws(gq_ctx *ctx, T *&dst, size_t count) {
   return GQ_OK;
 }
 
-std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
-  std::vector<int32_t> o(v.size());
-  for (size_t i = 0; i < v.size(); ++i) o[i] = (int32_t)v[i];
-  return o;
-}
-
 #define GQ_TRY(expr)                 \
   do {                               \
     gq_status s_ = (expr);           \
@@ -109,6 +103,7 @@ std::vector<int32_t> to_i32(const std::vector<int64_t> &v) {
 // chunk) result goes to its own row; the rows of a box are laid out [chunk][center], direct
 // chunks first.
 constexpr int kMomentChunk = 512;  // sources per Stage 2 work item
+constexpr int kM2LRun = 64;        // List 2 pairs per Stage 4 wavefront (whole boxes, at least)
 constexpr int kNearChunk = 1024;   // defaults of gq_params.near_chunk / far_chunk
 constexpr int kFarChunk = 16;
 
@@ -294,7 +289,6 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.bchild, t.child.data(), 4 * nb));
     GQ_TRY(upload(ctx, d.bsrc0, s0.data(), nb));
     GQ_TRY(upload(ctx, d.bsrc1, s1.data(), nb));
-    GQ_TRY(upload(ctx, d.tboxes, tboxes.data(), tboxes.size()));
     // box sides per level (a forest: per virtual level, one per tree and depth)
     std::vector<double> side = t.level_side_table;
     if (side.empty())
@@ -365,6 +359,43 @@ gq_status upload_all(gq_ctx *ctx) {
     if (!item.empty()) GQ_TRY(upload(ctx, d.p2m_item, item.data(), item.size() / 4));
     if (!red.empty()) GQ_TRY(upload(ctx, d.p2m_red, red.data(), red.size() / 4));
   }
+  // Stage 4 work: the List 2 pairs of the target-or-ancestor boxes in box order (a box without
+  // pairs gets one empty pair so that its local is written), cut after whole boxes into runs of
+  // at least kM2LRun pairs, one per wavefront
+  {
+    std::vector<double> side = t.level_side_table;
+    if (side.empty())
+      for (int l = 0; l < t.n_levels; ++l) side.push_back(std::ldexp(t.side, -l));
+    const std::vector<double> &olog = ctx->tables.ologabs;
+    std::vector<int32_t> pr, item;
+    std::vector<double> plog;
+    int32_t first = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      if (!t.has_tgt[b]) continue;
+      const double ls = std::log(side[t.level[b]]);
+      if (t.list2.row_size(b) == 0) {
+        pr.insert(pr.end(), {-1, 0, (int32_t)b, 0});
+        plog.push_back(0.0);
+      }
+      for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e) {
+        const int32_t o = t.list2_offset[e];
+        pr.insert(pr.end(), {t.list2.idx[e], o, (int32_t)b, 0});
+        plog.push_back(ls + olog[o]);
+      }
+      const int32_t n = (int32_t)plog.size();
+      if (n - first >= kM2LRun) {
+        item.insert(item.end(), {first, n});
+        first = n;
+      }
+    }
+    if ((int32_t)plog.size() > first) item.insert(item.end(), {first, (int32_t)plog.size()});
+    ctx->n_m2l_items = (int64_t)item.size() / 2;
+    if (!item.empty()) {
+      GQ_TRY(upload(ctx, d.m2l_item, item.data(), item.size() / 2));
+      GQ_TRY(upload(ctx, d.m2l_pr, pr.data(), pr.size() / 4));
+      GQ_TRY(upload(ctx, d.m2l_plog, plog.data(), plog.size()));
+    }
+  }
   // Stage 6b work: per box, the sources of its List 4 far boxes (tree order, box by box)
   {
     std::vector<int32_t> item, src;
@@ -384,13 +415,7 @@ gq_status upload_all(gq_ctx *ctx) {
     }
   }
   // lists
-  GQ_TRY(upload(ctx, d.v_start, to_i32(t.list2.start).data(), nb + 1));
-  GQ_TRY(upload(ctx, d.v_idx, t.list2.idx.data(), t.list2.idx.size()));
-  GQ_TRY(upload(ctx, d.v_off, t.list2_offset.data(), t.list2_offset.size()));
-  GQ_TRY(upload(ctx, d.wf_start, to_i32(t.list3f.start).data(), nb + 1));
   GQ_TRY(upload(ctx, d.wf_idx, t.list3f.idx.data(), t.list3f.idx.size()));
-  GQ_TRY(upload(ctx, d.xf_start, to_i32(t.list4f.start).data(), nb + 1));
-  GQ_TRY(upload(ctx, d.xf_idx, t.list4f.idx.data(), t.list4f.idx.size()));
   GQ_TRY(upload_near_work(ctx));
 
   // tables
@@ -404,21 +429,17 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.opow_f, op.data(), op.size() / 2));
   }
   GQ_TRY(upload(ctx, d.opow, tb.opow.data(), tb.opow.size() / 2));
-  GQ_TRY(upload(ctx, d.ologabs, tb.ologabs.data(), tb.ologabs.size()));
   {
     const int NB = tb.nbinom;
     auto C = [&](int n, int k) { return (k < 0 || k > n || n >= NB) ? 0.0 : tb.binom[(size_t)n * NB + k]; };
-    std::vector<double> l2q((size_t)P1 * (PQ + 1)), m2q((size_t)(PQ + 1) * P1);
+    std::vector<double> l2q((size_t)P1 * (PQ + 1));
     for (int k = 0; k < P1; ++k)
       for (int m = 0; m <= PQ; ++m) l2q[(size_t)k * (PQ + 1) + m] = C(k, m);
-    for (int m = 0; m <= PQ; ++m)
-      for (int k = 0; k < P1; ++k) m2q[(size_t)m * P1 + k] = k == 0 ? 0.0 : C(m + k - 1, k - 1);
     GQ_TRY(upload(ctx, d.l2q_binom, l2q.data(), l2q.size()));
     std::vector<double> bt((size_t)P1 * P1);
     for (int k = 0; k < P1; ++k)
       for (int m = 0; m < P1; ++m) bt[(size_t)k * P1 + m] = C(k, m);
     GQ_TRY(upload(ctx, d.l2g_binom_t, bt.data(), bt.size()));
-    GQ_TRY(upload(ctx, d.m2q_binom, m2q.data(), m2q.size()));
   }
   return GQ_OK;
 }

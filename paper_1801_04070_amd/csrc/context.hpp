@@ -34,7 +34,6 @@ struct DevBuffers {
   double2 *bc = nullptr;             // centers
   int32_t *blevel = nullptr, *bparent = nullptr, *bchild = nullptr;
   int32_t *bsrc0 = nullptr, *bsrc1 = nullptr;
-  int32_t *tboxes = nullptr;         // target-or-ancestor boxes
   // Stage 7 gather: boxes owning centers, and per box its ancestors with a nonzero own local
   int4 *l2g_sink = nullptr;          // (box, first pair, end of pairs, 0)
   int32_t *l2g_anc = nullptr;        // per pair: the ancestor
@@ -43,14 +42,17 @@ struct DevBuffers {
   // Stage 2: moment items (box, first source, end, partial slot or -1) and the split boxes
   // (box, first partial, end)
   int4 *p2m_item = nullptr, *p2m_red = nullptr;
+  // Stage 4 flat list: per wavefront (first pair, end), per pair (d, offset, box, 0) and
+  // log s_b + log|o|
+  int2 *m2l_item = nullptr;
+  int4 *m2l_pr = nullptr;
+  double *m2l_plog = nullptr;
   // Stage 6b: boxes with List 4 far sources (box, first, end) and the sources, flattened
   int4 *p2l_item = nullptr;
   int32_t *p2l_src = nullptr;
   double *level_side = nullptr, *level_inv_side = nullptr, *level_log_side = nullptr;
   // lists
-  int32_t *v_start = nullptr, *v_idx = nullptr, *v_off = nullptr;
-  int32_t *wf_start = nullptr, *wf_idx = nullptr;
-  int32_t *xf_start = nullptr, *xf_idx = nullptr;
+  int32_t *wf_idx = nullptr;         // List 3 far entries (indexed by the far work items)
   // direct (near-field) work: expanded source lists, balanced work items, partial-row layout
   int32_t *near_src = nullptr;       // per box owning centers: its direct sources (tree order)
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
@@ -62,12 +64,11 @@ struct DevBuffers {
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
   double2 *opow = nullptr;
-  double *m2l_bt = nullptr, *ologabs = nullptr;
+  double *m2l_bt = nullptr;
   // the same tables rounded to FP32 for the mixed-precision box expansions
   float *m2l_bt_f = nullptr;
   float2 *opow_f = nullptr;
   double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
-  double *m2q_binom = nullptr;       // [PQB + 1][P1]  C(m + k - 1, k - 1)
   // workspace
   double *sq = nullptr;              // per-source charge  w * sigma
   double2 *sdip = nullptr;           // per-source dipole  w * tau * n
@@ -119,6 +120,7 @@ struct gq_ctx {
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_l2g_sinks = 0;           // boxes owning centers (Stage 7 gather)
   int64_t n_p2l_boxes = 0;           // boxes with List 4 far sources (Stage 6b)
+  int64_t n_m2l_items = 0;           // Stage 4 wavefronts
   int64_t n_p2m_items = 0, n_p2m_red = 0, n_p2m_parts = 0;  // Stage 2 work
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   int far_chunk = 16;                // List 3 far boxes per work item (sizes k_m2qbxl's LDS)

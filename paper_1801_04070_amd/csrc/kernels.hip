@@ -210,16 +210,16 @@ __global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
 }
 
 // ------------------------------------------------------------------------------------------
-// Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far. One wavefront per
-// target-or-ancestor box.
+// Stages 4 and 6b: box local L_b = M2L over List 2 + P2L over List 4 far.
 //
 // M2L (eq. (m2l), corrected a_0 sign) in factored form beta_m = o^-m sum_k B[m][k] (a_k o^-k)
 // (+ a_0 log|s o| in beta_0) on the matrix cores: the fixed real matrix B is the A operand of
-// v_mfma_f64_16x16x4f64 (RT row tiles x 4 RT k-steps, held in registers for the whole box), and a
-// batch of 8 List 2 pairs gives the 16 real columns (re/im of a_k o^-k per pair) of the B operand.
-// The 16 x 16 results are scaled by o^-m per pair and written to LDS by pair and row, where lane m
-// sums row m over the batch (one LDS round trip instead of a shuffle tree per row). Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane
-// i + 16 k, B[k][j] in lane j + 16 k, D[g + 4 v][j] in element v of lane j + 16 g.
+// v_mfma_f64_16x16x4f64 (RT row tiles x 4 RT k-steps, held in registers for the whole wavefront),
+// and a batch of 8 List 2 pairs gives the 16 real columns (re/im of a_k o^-k per pair) of the B
+// operand. The 16 x 16 results are scaled by o^-m per pair and written to LDS by pair and row,
+// where lane m sums row m over the batch (one LDS round trip instead of a shuffle tree per row).
+// Operand layout of the FP64 16x16x4 instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k, D[g + 4 v][j] in element v of lane j + 16 g.
 typedef double gq_d4 __attribute__((ext_vector_type(4)));
 typedef float gq_f4 __attribute__((ext_vector_type(4)));
 
@@ -241,22 +241,27 @@ template <> struct Mfma16<float> {
   static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
 };
 
-// NSL = 2 (S and D of one density): one wavefront takes both slots of its box, 4 List 2 pairs x
-// 2 slots per batch (columns 0-7 slot 0, 8-15 slot 1), so the slots share the pair indices, the
-// factors o^-k and o^-m and the wavefront; slot 1 sits d_off coefficients after slot 0.
-template <int RT, int NSL, typename E>
-__global__ void __launch_bounds__(64) k_m2l(
-    const int32_t *__restrict__ tboxes, const int32_t *__restrict__ blevel,
-    const double *__restrict__ level_log_side, const int32_t *__restrict__ v_start,
-    const int32_t *__restrict__ v_idx, const int32_t *__restrict__ v_off,
-    const E *__restrict__ M, const typename Scalar<E>::T *__restrict__ Bt,
-    const E *__restrict__ opow, const double *__restrict__ ologabs, int P1, E *__restrict__ L,
-    int64_t box_st, int64_t d_off) {
-  constexpr int PB = 8 / NSL;  // pairs per batch
+// M2L over a flat list of List 2 pairs (one slot per grid row): a wavefront takes a run of whole
+// target boxes (about 64 pairs), in batches of 8 consecutive pairs that may span boxes (each
+// matrix-core column is its own pair). The next batch's pair records and multipole rows are
+// fetched while the current batch runs on the matrix cores; lane m then adds row m of each pair
+// in pair order and writes a box's local when the next box starts. Pair record: (source box d,
+// offset index, target box, 0), d = -1 for a target box without List 2 pairs (its local is 0);
+// plog = log s_b + log|o| for the a_0 term. For FP64 the row factors o^-m a lane needs are the
+// o^-k it loaded for its operands (row 16 rt + g + 4 v = order 4 ks + g with ks = 4 rt + v).
+template <int RT, typename E>
+__global__ void __launch_bounds__(64) k_m2l_mb(
+    const int2 *__restrict__ items, const int4 *__restrict__ prs,
+    const double *__restrict__ plog, const E *__restrict__ M,
+    const typename Scalar<E>::T *__restrict__ Bt, const E *__restrict__ opow, int P1,
+    E *__restrict__ L, int64_t box_st) {
   using R = typename Scalar<E>::T;
   using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
-  const int32_t b = tboxes[blockIdx.x];
+  constexpr bool F64 = sizeof(R) == 8;
+  __shared__ double2 Pt[8][16 * RT];
+  __shared__ int32_t Pb[8];
+  const int2 it = items[blockIdx.x];  // first pair, end of pairs
   {
     const int64_t jd = blockIdx.y;
     M += jd * box_st;
@@ -264,8 +269,7 @@ __global__ void __launch_bounds__(64) k_m2l(
   }
   const int lane = threadIdx.x;
   const int g = lane >> 4, c16 = lane & 15;
-  const int lev = blevel[b];
-  const double logs = level_log_side[lev];
+  const int pr = c16 >> 1, comp = c16 & 1;
   R A[RT][KS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -274,94 +278,83 @@ __global__ void __launch_bounds__(64) k_m2l(
       const int i = 16 * rt + c16, k = 4 * ks + g;
       A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
     }
-  // lane m sums coefficient m; a batch's rows, scaled per pair, are transposed through LDS
-  __shared__ double2 Pt[8][16 * RT];
-  double2 acc[NSL];
-  double logsum0[NSL];
+  // operands of the batch at j: pair record, a_0 log factor, M_d[k] and o^-k for this lane's k
+  int4 rec;
+  double pl;
+  E mdv[KS], opv[KS];
+  auto fetch = [&](int32_t j) {
+    const int32_t p = j + pr;
+    const bool in = p < it.y;
+    rec = in ? prs[p] : make_int4(-1, 0, -1, 0);
+    pl = in ? plog[p] : 0.0;
+    const bool pv = rec.x >= 0;
+    const E *Md = M + (int64_t)(pv ? rec.x : 0) * P1;
+    const E *op = opow + (int64_t)rec.y * P1;
 #pragma unroll
-  for (int h = 0; h < NSL; ++h) {
-    acc[h] = make_double2(0.0, 0.0);
-    logsum0[h] = 0.0;
-  }
-  const int pr = c16 >> 1, comp = c16 & 1;
-  const int slot = pr / PB, pp = pr % PB;  // column pair: slot and pair of the batch
-  const E *Ms = M + (slot ? d_off : 0);
-  const int32_t v0 = v_start[b], v1 = v_start[b + 1];
-  for (int32_t e0 = v0; e0 < v1; e0 += 64) {
-    // up to 64 of the box's List 2 entries, one per lane, and each entry's a_0 log|s o| term
-    const int ne = min(64, (int)(v1 - e0));
-    const int32_t my_d = lane < ne ? v_idx[e0 + lane] : 0;
-    const int32_t my_o = lane < ne ? v_off[e0 + lane] : 0;
-    if (lane < ne) {
-      const double lo = logs + ologabs[my_o];
-#pragma unroll
-      for (int h = 0; h < NSL; ++h)
-        logsum0[h] += (double)M[(h ? d_off : 0) + (int64_t)my_d * P1].x * lo;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g;
+      mdv[ks] = (pv && k < P1) ? Md[k] : mk2<E>(0.0, 0.0);
+      opv[ks] = k < P1 ? op[k] : mk2<E>(0.0, 0.0);
     }
-    for (int j0 = 0; j0 < ne; j0 += PB) {
-      const int nbat = min(PB, ne - j0);
-      const bool pv = pp < nbat;
-      const int32_t d = __shfl(my_d, j0 + pp, 64);
-      const int32_t oi = __shfl(my_o, j0 + pp, 64);
-      const E *Md = Ms + (int64_t)d * P1;
-      const E *op = opow + (int64_t)oi * P1;
-      // this lane's output-row factors o^-m, loaded with the operands
-      E opm[RT][4];
+  };
+  fetch(it.x);
+  double2 acc = make_double2(0.0, 0.0);
+  int32_t cur = -1;
+  for (int32_t j0 = it.x; j0 < it.y; j0 += 8) {
+    const int nbat = min(8, (int)(it.y - j0));
+    const int4 rc = rec;
+    const double plc = pl;
+    E mdc[KS], opc[KS];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = 16 * rt + Mfma16<R>::row(g, v);
-          opm[rt][v] = (pv && !comp && m < P1) ? op[m] : mk2<E>(0.0, 0.0);
-        }
-      R Bf[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + g;
-        R x = R(0);
-        if (pv && k < P1) {
-          const E mk = Md[k], ok = op[k];
-          x = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
-        }
-        Bf[ks] = x;
-      }
-      Acc C[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        C[rt] = Acc{R(0), R(0), R(0), R(0)};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
-      }
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = 16 * rt + Mfma16<R>::row(g, v);
-          const double y = C[rt][v];
-          const double yo = __shfl_xor(y, 1, 64);
-          if (pv && !comp && m < P1) Pt[pr][m] = cmul(make_double2(y, yo), to_d2(opm[rt][v]));
-        }
-      __syncthreads();
-      if (lane < P1)
-#pragma unroll
-        for (int h = 0; h < NSL; ++h)
-          for (int p = 0; p < nbat; ++p) acc[h] = cadd(acc[h], Pt[h * PB + p][lane]);
-      __syncthreads();
+    for (int ks = 0; ks < KS; ++ks) {
+      mdc[ks] = mdv[ks];
+      opc[ks] = opv[ks];
     }
-  }
-  // a_0 log|s o| terms: sum over lanes (each lane added its own pairs)
+    if (j0 + 8 < it.y) fetch(j0 + 8);  // in flight during this batch
+    R Bf[KS];
 #pragma unroll
-  for (int h = 0; h < NSL; ++h) {
+    for (int ks = 0; ks < KS; ++ks) {
+      const E mk = mdc[ks], ok = opc[ks];
+      Bf[ks] = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
+    }
+    Acc C[RT];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) logsum0[h] += __shfl_xor(logsum0[h], o, 64);
-  }
-  const int m = lane;
-  if (m >= P1) return;
+    for (int rt = 0; rt < RT; ++rt) {
+      C[rt] = Acc{R(0), R(0), R(0), R(0)};
 #pragma unroll
-  for (int h = 0; h < NSL; ++h) {
-    if (m == 0) acc[h].x += logsum0[h];
-    L[(h ? d_off : 0) + (int64_t)b * P1 + m] = from_d2<E>(acc[h]);
+      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
+    }
+    const E *opr = opow + (int64_t)rc.y * P1;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
+        const double y = C[rt][v];
+        const double yo = __shfl_xor(y, 1, 64);
+        if (!comp && m < P1) {
+          const E om = F64 ? opc[4 * rt + v] : opr[m];
+          double2 t = cmul(make_double2(y, yo), to_d2(om));
+          if (m == 0) t.x = fma((double)mdc[0].x, plc, t.x);  // a_0 log|s o| (lane g = 0)
+          Pt[pr][m] = t;
+        }
+      }
+    if (c16 == 2 * pr && g == 0 && !comp) Pb[pr] = rc.z;
+    __syncthreads();
+    if (lane < P1) {
+      for (int p = 0; p < nbat; ++p) {
+        const int32_t bx = Pb[p];
+        if (bx != cur) {
+          if (cur >= 0) L[(int64_t)cur * P1 + lane] = from_d2<E>(acc);
+          acc = make_double2(0.0, 0.0);
+          cur = bx;
+        }
+        acc = cadd(acc, Pt[p][lane]);
+      }
+    }
+    __syncthreads();
   }
+  if (lane < P1 && cur >= 0) L[(int64_t)cur * P1 + lane] = from_d2<E>(acc);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1480,13 +1473,10 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    // S and D of one density: both slots in one wavefront
-    constexpr int NS = SD ? 2 : 1;
-    auto kern = P1 <= 16 ? k_m2l<1, NS, E> : P1 <= 32 ? k_m2l<2, NS, E>
-              : P1 <= 48 ? k_m2l<3, NS, E> : k_m2l<4, NS, E>;
-    hipLaunchKernelGGL(kern, dim3(ntb, nd), dim3(64), 0, st, d.tboxes, d.blevel,
-                       d.level_log_side, d.v_start, d.v_idx, d.v_off, M, X.m2l_bt, X.opow,
-                       d.ologabs, P1, L, S.box, (int64_t)nd * S.box);
+    auto kern = P1 <= 16 ? k_m2l_mb<1, E> : P1 <= 32 ? k_m2l_mb<2, E>
+              : P1 <= 48 ? k_m2l_mb<3, E> : k_m2l_mb<4, E>;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2l_items, slots), dim3(64), 0, st,
+                       d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt, X.opow, P1, L, S.box);
     if (ctx->n_p2l_boxes > 0) {
       auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
               : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
