@@ -303,32 +303,46 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.level_log_side, lside.data(), lside.size()));
   }
   // Stage 7 gather lists: every box owning centers, with its ancestors (top-down) that receive
-  // List 2 or List 4 far contributions of their own, and the two shift ratios of each pair
+  // List 2 or List 4 far contributions of their own, and the two shift ratios of each pair; a box
+  // without such ancestors gets one empty pair. Cut after whole boxes into runs of at least
+  // kM2LRun pairs, one per wavefront.
   {
-    std::vector<int32_t> sink, anc, chain;
+    std::vector<int32_t> pr, item, chain;
     std::vector<double> tw;
     std::vector<double> side = t.level_side_table;
     if (side.empty())
       for (int l = 0; l < t.n_levels; ++l) side.push_back(std::ldexp(t.side, -l));
+    int64_t sinks = 0;
+    int32_t first = 0;
     for (int64_t b = 0; b < nb; ++b) {
       if (t.ctr_end[b] <= t.ctr_begin[b]) continue;
+      ++sinks;
       chain.clear();
       for (int32_t a = t.parent[b]; a >= 0; a = t.parent[a])
         if (t.list2.row_size(a) > 0 || t.list4f.row_size(a) > 0) chain.push_back(a);
-      sink.insert(sink.end(), {(int32_t)b, (int32_t)anc.size(),
-                               (int32_t)(anc.size() + chain.size()), 0});
+      if (chain.empty()) {
+        pr.insert(pr.end(), {-1, (int32_t)b});
+        tw.insert(tw.end(), {0.0, 0.0, 1.0, 0.0});
+      }
       for (auto it = chain.rbegin(); it != chain.rend(); ++it) {
         const int32_t a = *it;
         const std::complex<double> dc(t.cx[b] - t.cx[a], t.cy[b] - t.cy[a]);
         const std::complex<double> tt = dc / side[t.level[a]], w = side[t.level[b]] / dc;
         tw.insert(tw.end(), {tt.real(), tt.imag(), w.real(), w.imag()});
-        anc.push_back(a);
+        pr.insert(pr.end(), {a, (int32_t)b});
+      }
+      const int32_t n = (int32_t)pr.size() / 2;
+      if (n - first >= kM2LRun) {
+        item.insert(item.end(), {first, n});
+        first = n;
       }
     }
-    ctx->n_l2g_sinks = (int64_t)sink.size() / 4;
-    if (!sink.empty()) {
-      GQ_TRY(upload(ctx, d.l2g_sink, sink.data(), sink.size() / 4));
-      GQ_TRY(upload(ctx, d.l2g_anc, anc.data(), anc.size()));
+    if ((int32_t)pr.size() / 2 > first) item.insert(item.end(), {first, (int32_t)pr.size() / 2});
+    ctx->n_l2g_sinks = sinks;
+    ctx->n_l2g_items = (int64_t)item.size() / 2;
+    if (!item.empty()) {
+      GQ_TRY(upload(ctx, d.l2g_item, item.data(), item.size() / 2));
+      GQ_TRY(upload(ctx, d.l2g_pr, pr.data(), pr.size() / 2));
       GQ_TRY(upload(ctx, d.l2g_tw, tw.data(), tw.size() / 4));
     }
   }

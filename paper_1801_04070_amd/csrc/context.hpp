@@ -35,8 +35,8 @@ struct DevBuffers {
   int32_t *blevel = nullptr, *bparent = nullptr, *bchild = nullptr;
   int32_t *bsrc0 = nullptr, *bsrc1 = nullptr;
   // Stage 7 gather: boxes owning centers, and per box its ancestors with a nonzero own local
-  int4 *l2g_sink = nullptr;          // (box, first pair, end of pairs, 0)
-  int32_t *l2g_anc = nullptr;        // per pair: the ancestor
+  int2 *l2g_item = nullptr;          // per wavefront: (first pair, end of pairs), whole boxes
+  int2 *l2g_pr = nullptr;            // per pair: (ancestor or -1, box)
   double4 *l2g_tw = nullptr;         // per pair: t = (c_b - c_a)/s_a and 1/u, u = (c_b - c_a)/s_b
   double *l2g_binom_t = nullptr;     // [P1 (k)][P1 (m)]  C(k, m)
   // Stage 2: moment items (box, first source, end, partial slot or -1) and the split boxes
@@ -119,6 +119,7 @@ struct gq_ctx {
   std::vector<void *> nw_allocations;    // direct / List 3 far work, re-uploaded on order changes
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes
   int64_t n_l2g_sinks = 0;           // boxes owning centers (Stage 7 gather)
+  int64_t n_l2g_items = 0;           // Stage 7 wavefronts
   int64_t n_p2l_boxes = 0;           // boxes with List 4 far sources (Stage 6b)
   int64_t n_m2l_items = 0;           // Stage 4 wavefronts
   int64_t n_p2m_items = 0, n_p2m_red = 0, n_p2m_parts = 0;  // Stage 2 work

@@ -486,18 +486,24 @@ __global__ void __launch_bounds__(64) k_p2l(
 // With t = (c_b - c_a)/s_a, u = (c_b - c_a)/s_b and alpha the scaled coefficients of a,
 //   beta_m = sum_{j>=m} C(j,m) t^(j-m) (s_b/s_a)^m alpha_j = u^-m sum_{j>=m} C(j,m) (t^j alpha_j),
 // so the pair-dependent parts are diagonal and the fixed binomial matrix runs on the FP64 matrix
-// cores, 8 ancestors (16 real columns) per step, as in k_far_local. |t| < 2^-1/2 and |u| > 2^-1/2
-// for every ancestor: t^j only underflows where its term is negligible and u^-m < 2^(m/2).
-// One wavefront per box; arithmetic in FP64 whatever the storage type E.
+// cores, 8 pairs (16 real columns) per step, as in M2L. |t| < 2^-1/2 and |u| > 2^-1/2 for every
+// ancestor: t^j only underflows where its term is negligible and u^-m < 2^(m/2). Arithmetic in
+// FP64 whatever the storage type E.
+// The (box, ancestor) pairs of all boxes owning centers are one flat list in box order; a
+// wavefront takes a run of whole boxes (about 64 pairs) in batches of 8 consecutive pairs, which
+// may span boxes (each matrix-core column is its own pair), fetching the next batch's records and
+// coefficients during the current one. Lane m adds row m of each pair in pair order and, when the
+// next box starts, writes the finished box's own local plus its sum. Pair record: (ancestor, box),
+// ancestor -1 for a box without ancestors of its own local (one empty pair per such box).
 template <int RT, typename E>
 __global__ void __launch_bounds__(64) k_l2l_gather(
-    const int4 *__restrict__ sinks, const int32_t *__restrict__ anc_idx,
+    const int2 *__restrict__ items, const int2 *__restrict__ prs,
     const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
     const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st) {
   constexpr int KS = 4 * RT;
-  __shared__ double2 Pt[8][16 * RT];  // one batch's shifted rows, per ancestor
-  const int4 sk = sinks[blockIdx.x];  // box, first pair, end of pairs
-  const int32_t b = sk.x, a0 = sk.y, a1 = sk.z;
+  __shared__ double2 Pt[8][16 * RT];  // one batch's shifted rows, per pair
+  __shared__ int32_t Pb[8];
+  const int2 it = items[blockIdx.x];  // first pair, end of pairs
   {
     const int64_t jd = blockIdx.y;
     L += jd * box_st;
@@ -515,19 +521,35 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
       const int i = 16 * rt + c16, k = 4 * ks + g;
       A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? binom_t[k * P1 + i] : 0.0;
     }
-  double2 acc = make_double2(0.0, 0.0);  // lane m: coefficient m summed over the ancestors
-  // pair records of the first batch; each later batch's are fetched while the current one runs
+  int2 rec;
+  double4 tw;
+  double2 lav[KS];
   const double4 unit = make_double4(0.0, 0.0, 1.0, 0.0);  // an idle column: t = 0, 1/u = 1
-  int32_t a = (a0 + pr < a1) ? anc_idx[a0 + pr] : -1;
-  double4 tw = (a0 + pr < a1) ? anc_tw[a0 + pr] : unit;
-  for (int32_t j0 = a0; j0 < a1; j0 += 8) {
-    const int nbat = min(8, (int)(a1 - j0));
-    const bool pv = a >= 0;
-    const E *La = L + (int64_t)(pv ? a : 0) * P1;
-    const int32_t jn = j0 + 8 + pr;
-    const int32_t a_next = jn < a1 ? anc_idx[jn] : -1;
-    const double4 tw_next = jn < a1 ? anc_tw[jn] : unit;
-    const double2 t = make_double2(tw.x, tw.y), w = make_double2(tw.z, tw.w);
+  auto fetch = [&](int32_t j) {
+    const int32_t p = j + pr;
+    const bool in = p < it.y;
+    rec = in ? prs[p] : make_int2(-1, -1);
+    const bool pv = rec.x >= 0;
+    tw = pv ? anc_tw[p] : unit;
+    const E *La = L + (int64_t)(pv ? rec.x : 0) * P1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g;
+      lav[ks] = (pv && k < P1) ? to_d2(La[k]) : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(it.x);
+  double2 acc = make_double2(0.0, 0.0);  // lane m: coefficient m of the current box
+  int32_t cur = -1;
+  for (int32_t j0 = it.x; j0 < it.y; j0 += 8) {
+    const int nbat = min(8, (int)(it.y - j0));
+    const int2 rc = rec;
+    const double4 twc = tw;
+    double2 lac[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) lac[ks] = lav[ks];
+    if (j0 + 8 < it.y) fetch(j0 + 8);  // in flight during this batch
+    const double2 t = make_double2(twc.x, twc.y), w = make_double2(twc.z, twc.w);
     // t^k alpha_k for k = g, g + 4, ...
     double2 pw = make_double2(1.0, 0.0);
     for (int e = 0; e < g; ++e) pw = cmul(pw, t);
@@ -535,13 +557,8 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
     double Bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + g;
-      double x = 0.0;
-      if (pv && k < P1) {
-        const double2 v = cmul(pw, to_d2(La[k]));
-        x = comp ? v.y : v.x;
-      }
-      Bf[ks] = x;
+      const double2 v = cmul(pw, lac[ks]);
+      Bf[ks] = comp ? v.y : v.x;
       pw = cmul(pw, t4);
     }
     gq_d4 C[RT];
@@ -569,16 +586,27 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
       }
       wr = cmul(wr, w16);
     }
+    if (g == 0 && !comp) Pb[pr] = rc.y;
     __syncthreads();
-    if (lane < P1)
-      for (int p = 0; p < nbat; ++p) acc = cadd(acc, Pt[p][lane]);
+    if (lane < P1) {
+      for (int p = 0; p < nbat; ++p) {
+        const int32_t bx = Pb[p];
+        if (bx != cur) {
+          if (cur >= 0) {
+            const int64_t o = (int64_t)cur * P1 + lane;
+            Lf[o] = from_d2<E>(cadd(to_d2(L[o]), acc));
+          }
+          acc = make_double2(0.0, 0.0);
+          cur = bx;
+        }
+        acc = cadd(acc, Pt[p][lane]);
+      }
+    }
     __syncthreads();
-    a = a_next;
-    tw = tw_next;
   }
-  if (lane < P1) {
-    const double2 own = to_d2(L[(int64_t)b * P1 + lane]);
-    Lf[(int64_t)b * P1 + lane] = from_d2<E>(cadd(own, acc));
+  if (lane < P1 && cur >= 0) {
+    const int64_t o = (int64_t)cur * P1 + lane;
+    Lf[o] = from_d2<E>(cadd(to_d2(L[o]), acc));
   }
 }
 
@@ -1489,8 +1517,8 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     StageTimer st_(ctx, GQ_STAGE_L2L);
     auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
               : P1 <= 48 ? k_l2l_gather<3, E> : k_l2l_gather<4, E>;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_sinks, slots), dim3(64), 0, st, d.l2g_sink,
-                       d.l2g_anc, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_items, slots), dim3(64), 0, st,
+                       d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;
