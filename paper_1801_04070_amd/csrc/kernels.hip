@@ -611,18 +611,19 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
 }
 
 // ------------------------------------------------------------------------------------------
-// Near-field accumulation of one source into a center's QBX coefficients (P2QBXL).
-// z = (y - c)/r. Charge part accumulates acc_m = sum q z^-m (m >= 1), normalised by -1/m later.
+// Near-field accumulation of one source into a center's QBX coefficients (P2QBXL), in the
+// unscaled offset z = y - c and unscaled dipole d: the sums are taken in z^-m and multiplied by
+// r^m once per center (finish), which gives the coefficients in (x - c)/r; the log term
+// sum q log|z| needs no log r correction then. Charge part: a_m = sum q z^-m (m >= 1), normalised
+// by -1/m in finish.
 template <int KIND, int PQ>
 struct NearAcc {
-  double2 a[PQ + 1];   // KIND 1: a_m = sum q z^-m (m>=1); KIND 2/3: final scaled coefficients
-  double logsum;       // sum q log|z|
-  double qsum;         // sum q
+  double2 a[PQ + 1];   // KIND 1: a_m = sum q z^-m (m>=1); KIND 2/3: unscaled coefficients
+  double logsum;       // sum q log|z|^2
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) a[m] = make_double2(0.0, 0.0);
     logsum = 0.0;
-    qsum = 0.0;
   }
   __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
     const double r2 = cnorm2(z);
@@ -630,7 +631,6 @@ struct NearAcc {
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     if (KIND == 1) {
       logsum = fma(q, log_tab(r2, lt), logsum);
-      qsum += q;
       double2 pw = inv;
 #pragma unroll
       for (int m = 1; m <= PQ; ++m) {
@@ -646,7 +646,6 @@ struct NearAcc {
       }
     } else {
       logsum = fma(q, log_tab(r2, lt), logsum);
-      qsum += q;
       const double2 e = cmul(dr, inv);
       a[0] = cadd(a[0], e);
       double2 pw = inv;
@@ -658,15 +657,16 @@ struct NearAcc {
       }
     }
   }
-  // Add the finished near-field coefficients into alpha (scaled by r^m), given log r.
-  __device__ __forceinline__ void finish(double2 *alpha, double logr) const {
-    if (KIND & 1) alpha[0].x += fma(qsum, logr, 0.5 * logsum);
-    if (KIND == 1) {
+  // Add the finished near-field coefficients into alpha, scaled by r^m.
+  __device__ __forceinline__ void finish(double2 *alpha, double r) const {
+    if (KIND & 1) alpha[0].x += 0.5 * logsum;
+    if (KIND != 1) alpha[0] = cadd(alpha[0], a[0]);
+    double rp = 1.0;
 #pragma unroll
-      for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[m], alpha[m]);
-    } else {
-#pragma unroll
-      for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], a[m]);
+    for (int m = 1; m <= PQ; ++m) {
+      rp *= r;
+      if (KIND == 1) alpha[m] = caxpy(-(rp * (1.0 / m)), a[m], alpha[m]);
+      else alpha[m] = cadd(alpha[m], cscale(a[m], rp));
     }
   }
 };
@@ -676,14 +676,13 @@ struct NearAcc {
 template <int KIND, int PQ, int DG>
 struct NearAccMD {
   double2 a[DG][PQ + 1];
-  double logsum[DG], qsum[DG];
+  double logsum[DG];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int g = 0; g < DG; ++g) {
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) a[g][m] = make_double2(0.0, 0.0);
       logsum[g] = 0.0;
-      qsum[g] = 0.0;
     }
   }
   __device__ __forceinline__ void add(double2 z, const double *q, const double2 *dr,
@@ -694,10 +693,7 @@ struct NearAccMD {
     if (KIND & 1) {
       const double lr = log_tab(r2, lt);
 #pragma unroll
-      for (int g = 0; g < DG; ++g) {
-        logsum[g] = fma(q[g], lr, logsum[g]);
-        qsum[g] += q[g];
-      }
+      for (int g = 0; g < DG; ++g) logsum[g] = fma(q[g], lr, logsum[g]);
     }
     if (KIND == 1) {
       double2 pw = inv;
@@ -739,14 +735,15 @@ struct NearAccMD {
       }
     }
   }
-  __device__ __forceinline__ void finish(int g, double2 *alpha, double logr) const {
-    if (KIND & 1) alpha[0].x += fma(qsum[g], logr, 0.5 * logsum[g]);
-    if (KIND == 1) {
+  __device__ __forceinline__ void finish(int g, double2 *alpha, double r) const {
+    if (KIND & 1) alpha[0].x += 0.5 * logsum[g];
+    if (KIND != 1) alpha[0] = cadd(alpha[0], a[g][0]);
+    double rp = 1.0;
 #pragma unroll
-      for (int m = 1; m <= PQ; ++m) alpha[m] = caxpy(-1.0 / m, a[g][m], alpha[m]);
-    } else {
-#pragma unroll
-      for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], a[g][m]);
+    for (int m = 1; m <= PQ; ++m) {
+      rp *= r;
+      if (KIND == 1) alpha[m] = caxpy(-(rp * (1.0 / m)), a[g][m], alpha[m]);
+      else alpha[m] = cadd(alpha[m], cscale(a[g][m], rp));
     }
   }
 };
@@ -804,7 +801,6 @@ __global__ void __launch_bounds__(64) k_near(
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
   const double r = cr[c];
-  const double ir = 1.0 / r;
   const double2 *lt = g_log_tab;
   NearAcc<KIND, PQ> acc;
   acc.zero();
@@ -823,9 +819,8 @@ __global__ void __launch_bounds__(64) k_near(
     __syncthreads();
     if (active) {
       for (int j = sl; j < nb; j += nsl) {
-        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
-        acc.add(z, (KIND & 1) ? t_q[j] : 0.0,
-                (KIND & 2) ? cscale(t_d[j], ir) : make_double2(0.0, 0.0), lt);
+        const double2 z = make_double2(t_xy[j].x - cc.x, t_xy[j].y - cc.y);
+        acc.add(z, (KIND & 1) ? t_q[j] : 0.0, (KIND & 2) ? t_d[j] : make_double2(0.0, 0.0), lt);
       }
     }
   }
@@ -835,16 +830,13 @@ __global__ void __launch_bounds__(64) k_near(
       acc.a[m].x += __shfl_xor(acc.a[m].x, o, 64);
       acc.a[m].y += __shfl_xor(acc.a[m].y, o, 64);
     }
-    if (KIND & 1) {
-      acc.logsum += __shfl_xor(acc.logsum, o, 64);
-      acc.qsum += __shfl_xor(acc.qsum, o, 64);
-    }
+    if (KIND & 1) acc.logsum += __shfl_xor(acc.logsum, o, 64);
   }
   if (active && sl == 0) {
     double2 alpha[PQ + 1];
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
-    acc.finish(alpha, log(r));
+    acc.finish(alpha, r);
     double2 *row = anear + (int64_t)(row_first + cl) * rs;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
@@ -859,7 +851,7 @@ __global__ void __launch_bounds__(64) k_near(
 template <int PQ>
 struct NearAccSD {
   double2 as[PQ + 1], ad[PQ + 1];
-  double logsum, qsum;
+  double logsum;
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -867,14 +859,12 @@ struct NearAccSD {
       ad[m] = make_double2(0.0, 0.0);
     }
     logsum = 0.0;
-    qsum = 0.0;
   }
   __device__ __forceinline__ void add(double2 z, double q, double2 dr, const double2 *lt) {
     const double r2 = cnorm2(z);
     const double ir2 = rcp_nr(r2);
     const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
     logsum = fma(q, log_tab(r2, lt), logsum);
-    qsum += q;
     double2 pw = inv;  // z^-(m+1) in step m: D coefficient m, S coefficient m + 1
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
@@ -917,7 +907,6 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
   const double r = cr[c];
-  const double ir = 1.0 / r;
   const double2 *lt = g_log_tab;
   NearAccSD<PQ> acc;
   acc.zero();
@@ -936,8 +925,8 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
     __syncthreads();
     if (active) {
       for (int j = sl; j < nb; j += nsl) {
-        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
-        acc.add(z, t_q[j], cscale(t_d[j], ir), lt);
+        const double2 z = make_double2(t_xy[j].x - cc.x, t_xy[j].y - cc.y);
+        acc.add(z, t_q[j], t_d[j], lt);
       }
     }
   }
@@ -950,16 +939,20 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
       acc.ad[m].y += __shfl_xor(acc.ad[m].y, o, 64);
     }
     acc.logsum += __shfl_xor(acc.logsum, o, 64);
-    acc.qsum += __shfl_xor(acc.qsum, o, 64);
   }
   if (active && sl == 0) {
+    // the finish of NearAcc<1> and NearAcc<2> written out for both rows
     double2 *row = anear + (int64_t)(row_first + cl) * rs;
-    row[0] = make_double2(0.0 + fma(acc.qsum, log(r), 0.5 * acc.logsum), 0.0);
-#pragma unroll
-    for (int m = 1; m <= PQ; ++m) row[m] = caxpy(-1.0 / m, acc.as[m], make_double2(0.0, 0.0));
     double2 *rowd = row + d_slot * row_st;
+    row[0] = make_double2(0.0 + 0.5 * acc.logsum, 0.0);
+    rowd[0] = acc.ad[0];
+    double rp = 1.0;
 #pragma unroll
-    for (int m = 0; m <= PQ; ++m) rowd[m] = acc.ad[m];
+    for (int m = 1; m <= PQ; ++m) {
+      rp *= r;
+      row[m] = caxpy(-(rp * (1.0 / m)), acc.as[m], make_double2(0.0, 0.0));
+      rowd[m] = cscale(acc.ad[m], rp);
+    }
   }
 }
 
@@ -990,7 +983,6 @@ __global__ void __launch_bounds__(64) k_near_md(
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
   const double r = cr[c];
-  const double ir = 1.0 / r;
   const double2 *lt = g_log_tab;
   NearAccMD<KIND, PQ, DG> acc;
   acc.zero();
@@ -1010,13 +1002,13 @@ __global__ void __launch_bounds__(64) k_near_md(
     __syncthreads();
     if (active) {
       for (int j = sl; j < nb; j += nsl) {
-        const double2 z = make_double2((t_xy[j].x - cc.x) * ir, (t_xy[j].y - cc.y) * ir);
+        const double2 z = make_double2(t_xy[j].x - cc.x, t_xy[j].y - cc.y);
         double q[DG];
         double2 dr[DG];
 #pragma unroll
         for (int g = 0; g < DG; ++g) {
           q[g] = (KIND & 1) ? t_q[g][j] : 0.0;
-          dr[g] = (KIND & 2) ? cscale(t_d[g][j], ir) : make_double2(0.0, 0.0);
+          dr[g] = (KIND & 2) ? t_d[g][j] : make_double2(0.0, 0.0);
         }
         acc.add(z, q, dr, lt);
       }
@@ -1030,21 +1022,17 @@ __global__ void __launch_bounds__(64) k_near_md(
         acc.a[g][m].x += __shfl_xor(acc.a[g][m].x, o, 64);
         acc.a[g][m].y += __shfl_xor(acc.a[g][m].y, o, 64);
       }
-      if (KIND & 1) {
-        acc.logsum[g] += __shfl_xor(acc.logsum[g], o, 64);
-        acc.qsum[g] += __shfl_xor(acc.qsum[g], o, 64);
-      }
+      if (KIND & 1) acc.logsum[g] += __shfl_xor(acc.logsum[g], o, 64);
     }
   }
   if (active && sl == 0) {
-    const double logr = log(r);
 #pragma unroll
     for (int g = 0; g < DG; ++g) {
       if (g >= ng) break;
       double2 alpha[PQ + 1];
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
-      acc.finish(g, alpha, logr);
+      acc.finish(g, alpha, r);
       double2 *row = anear + (int64_t)(jd0 + g) * row_st + (int64_t)(row_first + cl) * rs;
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
@@ -1246,7 +1234,6 @@ __global__ void __launch_bounds__(256) k_direct(
   const int32_t c = active ? clist[i] : 0;
   const double2 cc = active ? cxy[c] : make_double2(0.0, 0.0);
   const double r = active ? cr[c] : 1.0;
-  const double ir = 1.0 / r;
   const double2 *lt = g_log_tab;
   NearAcc<KIND, PQ> acc;
   acc.zero();
@@ -1261,16 +1248,15 @@ __global__ void __launch_bounds__(256) k_direct(
     __syncthreads();
     if (!active) continue;
     for (int32_t j = 0; j < n; ++j) {
-      const double2 z = make_double2((ts[j].x - cc.x) * ir, (ts[j].y - cc.y) * ir);
-      acc.add(z, (KIND & 1) ? tq[j] : 0.0, (KIND & 2) ? cscale(td[j], ir) : make_double2(0.0, 0.0),
-              lt);
+      const double2 z = make_double2(ts[j].x - cc.x, ts[j].y - cc.y);
+      acc.add(z, (KIND & 1) ? tq[j] : 0.0, (KIND & 2) ? td[j] : make_double2(0.0, 0.0), lt);
     }
   }
   if (!active) return;
   double2 alpha[PQ + 1];
 #pragma unroll
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
-  acc.finish(alpha, log(r));
+  acc.finish(alpha, r);
   eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
 }
 

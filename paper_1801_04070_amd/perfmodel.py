@@ -21,8 +21,9 @@ MI355X_PEAKS = {
 
 
 def _near_pair_flops(kind: int, q: int) -> int:
-    # z = (y - c)/r (4), 1/z (6); charge: log|z| term (3), q-1 powers (6 each), q accumulations (4)
-    f = 4 + 6
+    # z = y - c (2; the sums run in z^-m and take the factor r^m once per center), 1/z (6);
+    # charge: log|z| term (3), q-1 powers (6 each), q accumulations (4)
+    f = 2 + 6
     if kind == 4:
         # S and D of one density in one pass: z, 1/z and the powers 1/z^m (m <= q+1) once;
         # charge: log term (3), q accumulations (4); dipole: q+1 complex multiply-adds (8)
