@@ -46,9 +46,9 @@ sys.path.insert(0, ROOT)
 METRIC = "QBX-FMM targets/s at 1e-10 rel err, plain vs batched/mixed/learned, 1 GPU"
 GATE = 1e-10
 # kernels of each stage in a GQ_S_AND_D evaluation of one density
-KERNEL_OF_STAGE = {"near": "k_near_sd", "m2qbxl": "k_m2qbxl", "qbx_center": "k_qbx_center",
-                   "m2l_p2l": "k_far_local", "m2m": "k_m2m", "l2l": "k_l2l_gather",
-                   "p2m": "k_p2m", "gather": "k_gather", "finalize": "k_finalize"}
+KERNEL_OF_STAGE = {"near": "k_near_sd", "m2qbxl": "k_m2qbxl_packed", "qbx_center": "k_qbx_center",
+                   "m2l_p2l": "k_m2l_mb", "m2m": "k_m_reduce", "l2l": "k_l2l_gather",
+                   "p2m": "k_p2m_all", "gather": "k_gather", "finalize": "k_finalize"}
 
 
 def log(msg):
@@ -314,7 +314,9 @@ def main():
                     help="run direct and List 3 far work on a second stream")
     ap.add_argument("--near-chunk", type=int, default=0, help="direct sources per work item")
     ap.add_argument("--far-chunk", type=int, default=0, help="List 3 far boxes per work item")
-    ap.add_argument("--far-ppl", type=int, default=0, help="List 3 far pairs per lane")
+    ap.add_argument("--far-ppl", type=int, default=None,
+                    help="List 3 far pairs per lane (gq_params.far_pairs_per_lane; default: the "
+                         "library's, 1 = pairs packed across boxes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -344,7 +346,9 @@ def main():
         q.set_geometry_from(geom)
         params = dict(p_qbx=p_qbx, p_fmm=p_fmm, n_max=64, count_mode=0, t_f=0.9,
                       w3far_min_sources=15, overlap=args.overlap, near_chunk=args.near_chunk,
-                      far_chunk=args.far_chunk, far_pairs_per_lane=args.far_ppl)
+                      far_chunk=args.far_chunk)
+        if args.far_ppl is not None:
+            params["far_pairs_per_lane"] = args.far_ppl
         params.update(kw)
         return q, q.build(**params)
 

@@ -71,8 +71,10 @@ typedef struct {
                              tree passes; 0: everything on the caller's stream                  */
   int near_chunk;         /* direct sources per work item (one wavefront), 0: 1024             */
   int far_chunk;          /* List 3 far boxes per work item (1..32), 0: 16                      */
-  int far_pairs_per_lane; /* (center, List 3 far box) pairs per lane in an item (default 1);
-                             0: a cost model of per-element and per-wave work                  */
+  int far_pairs_per_lane; /* 1 (default): one (center, List 3 far box) pair per lane, pairs of
+                             whole (center, far chunk) units packed across boxes; 2..64: items
+                             of one box's centers with at most that many pairs per lane;
+                             0: such items shaped by a cost model                              */
   int near_dens_group;    /* densities per direct-interaction work item when an evaluation has
                              several (1, 2 or 4): the pair geometry is formed once per group;
                              0: 2                                                              */
@@ -241,6 +243,10 @@ typedef struct {
   int64_t n_moment_boxes;        /* boxes whose multipole M2L or M2QBXL reads (Stage 2)   */
   int64_t n_moment_pairs;        /* (box, subtree source) pairs of their moments          */
   int64_t n_moment_parts;        /* partial moments of boxes split over several items     */
+  int64_t n_m2q_waves;           /* Stage 5b wavefronts of (center, List 3 far box) pairs
+                                    packed across boxes (far_pairs_per_lane 1; else 0)   */
+  int64_t n_m2q_pairs;           /* their pairs (list3_far_pairs when packed)             */
+  int64_t n_m2q_units;           /* their rows: (center, chunk of its List 3 far boxes)   */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);

@@ -41,7 +41,8 @@ class gq_stats(C.Structure):
         ("root_lo", C.c_double * 2), ("root_side", C.c_double), ("build_ms", C.c_double),
         ("n_point_targets", C.c_int64), ("n_l2l_sinks", C.c_int64),
         ("n_l2l_pairs", C.c_int64), ("n_moment_boxes", C.c_int64),
-        ("n_moment_pairs", C.c_int64), ("n_moment_parts", C.c_int64)]
+        ("n_moment_pairs", C.c_int64), ("n_moment_parts", C.c_int64),
+        ("n_m2q_waves", C.c_int64), ("n_m2q_pairs", C.c_int64), ("n_m2q_units", C.c_int64)]
 
 
 GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",

@@ -106,6 +106,7 @@ constexpr int kMomentChunk = 512;  // sources per Stage 2 work item
 constexpr int kM2LRun = 64;        // List 2 pairs per Stage 4 wavefront (whole boxes, at least)
 constexpr int kNearChunk = 1024;   // defaults of gq_params.near_chunk / far_chunk
 constexpr int kFarChunk = 16;
+constexpr int kM2qStageRows = 16;  // multipoles staged per packed Stage 5b wavefront (at least)
 
 int pick_lg(int64_t nc, int64_t len, double elem_cost) {
   int best_lg = 0;
@@ -121,8 +122,9 @@ int pick_lg(int64_t nc, int64_t len, double elem_cost) {
 
 // Work of the per-center stages grouped by QBX order: every box runs at its own order (the
 // largest order among its centers, default the build's p_qbx), and the items, rows and centers of
-// each compiled order form one contiguous range so that each order is one kernel launch.
-gq_status upload_near_work(gq_ctx *ctx) {
+// each compiled order form one contiguous range so that each order is one kernel launch. Device
+// contexts upload the lists; host-only contexts keep their counts (gq_get_stats).
+gq_status build_near_work(gq_ctx *ctx) {
   const gq::Tree &t = ctx->tree;
   auto &d = ctx->d;
   const int64_t nb = t.n_boxes();
@@ -130,12 +132,34 @@ gq_status upload_near_work(gq_ctx *ctx) {
   ctx->nw_allocations.clear();
   ctx->generation++;
   std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
+  std::vector<int32_t> qwave, qpair, qstage, qunit;
+  std::vector<double> qgeo;
+  std::vector<double> lside = t.level_side_table;
+  if (lside.empty())
+    for (int l = 0; l < t.n_levels; ++l) lside.push_back(std::ldexp(t.side, -l));
   std::vector<int64_t> box_src_off(nb, 0), box_src_len(nb, 0);
   int64_t rows = 0;
   const int64_t near_chunk = ctx->params.near_chunk > 0 ? ctx->params.near_chunk : kNearChunk;
   const int64_t far_chunk = ctx->params.far_chunk > 0 ? ctx->params.far_chunk : kFarChunk;
   ctx->far_chunk = (int)far_chunk;
   const int far_ppl = ctx->params.far_pairs_per_lane;
+  const bool packed = far_ppl == 1;
+  const int stage_rows = (int)std::max<int64_t>(kM2qStageRows, far_chunk);
+  ctx->m2q_stage_rows = stage_rows;
+  // Packed Stage 5b: units (center, chunk of its box's List 3 far boxes) in box order, whole
+  // units per wavefront, at most 64 pairs and stage_rows staged multipoles each (a chunk's boxes
+  // are staged once per wavefront and shared by the units of its centers)
+  int32_t q_pair0 = 0, q_stage0 = 0, q_unit0 = 0;
+  auto close_wave = [&]() {
+    const int32_t np = (int32_t)qpair.size() / 4 - q_pair0;
+    if (np == 0) return;
+    const int32_t w[8] = {q_pair0, np, q_stage0, (int32_t)qstage.size() - q_stage0,
+                          q_unit0, (int32_t)qunit.size() / 4 - q_unit0, 0, 0};
+    qwave.insert(qwave.end(), w, w + 8);
+    q_pair0 = (int32_t)qpair.size() / 4;
+    q_stage0 = (int32_t)qstage.size();
+    q_unit0 = (int32_t)qunit.size() / 4;
+  };
   // List 3 far items: with far_ppl > 0 the fewest slices that keep each lane at <= far_ppl
   // boxes (short serial chains, many waves); else the cost model
   auto far_lg = [&](int64_t nc, int64_t clen, int pq) {
@@ -177,6 +201,7 @@ gq_status upload_near_work(gq_ctx *ctx) {
     bk.pq = pq;
     bk.near0 = (int64_t)items.size() / 8;
     bk.far0 = (int64_t)fitems.size() / 8;
+    bk.m2q0 = (int64_t)qwave.size() / 8;
     bk.ctr0 = (int64_t)clist.size();
     for (int64_t b = 0; b < nb; ++b) {
       const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
@@ -191,19 +216,68 @@ gq_status upload_near_work(gq_ctx *ctx) {
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
       for (int64_t j = 0; j * far_chunk < wlen; ++j) {
         const int64_t c0 = j * far_chunk, clen = std::min<int64_t>(far_chunk, wlen - c0);
-        emit(fitems, woff + c0, clen, t.ctr_begin[b], base[b] + (nchunks + j) * nc, nc,
-             far_lg(nc, clen, pq));
+        if (!packed) {
+          emit(fitems, woff + c0, clen, t.ctr_begin[b], base[b] + (nchunks + j) * nc, nc,
+               far_lg(nc, clen, pq));
+          continue;
+        }
+        int32_t slot0 = -1;  // the chunk's first LDS slot in the current wavefront
+        for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) {
+          const int64_t np = (int64_t)qpair.size() / 4 - q_pair0;
+          const int64_t nst = (int64_t)qstage.size() - q_stage0;
+          if (np + clen > 64 || (slot0 < 0 && nst + clen > stage_rows)) {
+            close_wave();
+            slot0 = -1;
+          }
+          if (slot0 < 0) {
+            slot0 = (int32_t)qstage.size() - q_stage0;
+            for (int64_t e = 0; e < clen; ++e) qstage.push_back(t.list3f.idx[woff + c0 + e]);
+          }
+          const int32_t lane0 = (int32_t)qpair.size() / 4 - q_pair0;
+          const int32_t u[4] = {(int32_t)(base[b] + (nchunks + j) * nc + (c - t.ctr_begin[b])),
+                                lane0, (int32_t)clen, 0};
+          qunit.insert(qunit.end(), u, u + 4);
+          const int64_t co = t.ctr_order[c];
+          for (int64_t e = 0; e < clen; ++e) {
+            const int32_t fb = t.list3f.idx[woff + c0 + e];
+            const int32_t pr[4] = {(int32_t)c, fb, slot0 + (int32_t)e, 0};
+            qpair.insert(qpair.end(), pr, pr + 4);
+            qgeo.insert(qgeo.end(), {ctx->ctr_xy[2 * co] - t.cx[fb], ctx->ctr_xy[2 * co + 1] - t.cy[fb],
+                                     lside[t.level[fb]], ctx->ctr_r[co]});
+          }
+        }
       }
       for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) clist.push_back((int32_t)c);
     }
     bk.near1 = (int64_t)items.size() / 8;
+    close_wave();
     bk.far1 = (int64_t)fitems.size() / 8;
+    bk.m2q1 = (int64_t)qwave.size() / 8;
     bk.ctr1 = (int64_t)clist.size();
     if (bk.ctr1 > bk.ctr0) ctx->buckets.push_back(bk);
   }
   ctx->n_near_items = (int64_t)items.size() / 8;
   ctx->n_far_items = (int64_t)fitems.size() / 8;
+  ctx->n_m2q_waves = (int64_t)qwave.size() / 8;
+  // the packed Stage 5b lists must stay inside what k_m2qbxl_packed indexes: 64 lanes, the LDS
+  // slots it stages, the rows of the near-row layout
+  for (int64_t w = 0; w < ctx->n_m2q_waves; ++w) {
+    const int32_t *q = &qwave[8 * w];
+    bool ok = q[1] >= 1 && q[1] <= 64 && q[3] >= 1 && q[3] <= stage_rows && q[5] >= 1;
+    for (int32_t i = 0; ok && i < q[1]; ++i) {
+      const int32_t *pr = &qpair[4 * (q[0] + i)];
+      ok = pr[2] >= 0 && pr[2] < q[3] && qstage[q[2] + pr[2]] == pr[1];
+    }
+    for (int32_t i = 0; ok && i < q[5]; ++i) {
+      const int32_t *u = &qunit[4 * (q[4] + i)];
+      ok = u[0] >= 0 && u[0] < rows && u[1] >= 0 && u[2] >= 1 && u[1] + u[2] <= q[1];
+    }
+    if (!ok) return fail(ctx, GQ_EINVAL, "internal: packed List 3 far work list out of bounds");
+  }
   ctx->n_near_rows = rows;
+  ctx->n_m2q_pairs = (int64_t)qpair.size() / 4;
+  ctx->n_m2q_units = (int64_t)qunit.size() / 4;
+  if (ctx->device < 0) return GQ_OK;
   // these buffers live in nw_allocations (re-uploaded when the orders change)
   std::vector<void *> saved;
   saved.swap(ctx->allocations);
@@ -211,6 +285,11 @@ gq_status upload_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.near_src, src.data(), src.size());
   if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.m2q_wave, qwave.data(), qwave.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.m2q_pair, qpair.data(), qpair.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.m2q_geo, qgeo.data(), qgeo.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.m2q_stage, qstage.data(), qstage.size());
+  if (st == GQ_OK) st = upload(ctx, d.m2q_unit, qunit.data(), qunit.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.bctr0, bctr0.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.bctr1, bctr1.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.part_base, base.data(), nb);
@@ -430,7 +509,7 @@ gq_status upload_all(gq_ctx *ctx) {
   }
   // lists
   GQ_TRY(upload(ctx, d.wf_idx, t.list3f.idx.data(), t.list3f.idx.size()));
-  GQ_TRY(upload_near_work(ctx));
+  GQ_TRY(build_near_work(ctx));
 
   // tables
   const gq::Tables &tb = ctx->tables;
@@ -911,6 +990,8 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
       free_device(ctx);
       return st;
     }
+  } else {
+    GQ_TRY(build_near_work(ctx));
   }
   ctx->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   ctx->built = true;
@@ -994,6 +1075,9 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   out->n_list3_close = (int64_t)t.list3c.idx.size(); out->n_list3_far = (int64_t)t.list3f.idx.size();
   out->n_list4_close = (int64_t)t.list4c.idx.size(); out->n_list4_far = (int64_t)t.list4f.idx.size();
   out->near_pairs = t.near_pairs; out->list3_far_pairs = t.list3f_pairs;
+  out->n_m2q_waves = ctx->n_m2q_waves;
+  out->n_m2q_pairs = ctx->n_m2q_pairs;
+  out->n_m2q_units = ctx->n_m2q_units;
   out->list4_far_sources = t.list4f_sources;
   out->near_sources = t.near_sources;
   out->n_local_boxes = t.n_local_boxes;
@@ -1080,7 +1164,7 @@ gq_status gq_autotune(gq_ctx *ctx, int kind, const double *dens1, int64_t ld1, i
     ctx->params.far_chunk = c.far_chunk;
     ctx->params.far_pairs_per_lane = c.far_ppl;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    st = upload_near_work(ctx);
+    st = build_near_work(ctx);
     if (st != GQ_OK) break;
     free_workspace(ctx);  // row counts may change with the shape
     st = eval_common(ctx, kind, 1, dens1, ld1, nullptr, 0, out, ctx->nt, false);  // warm-up
@@ -1107,7 +1191,7 @@ gq_status gq_autotune(gq_ctx *ctx, int kind, const double *dens1, int64_t ld1, i
     ctx->params.far_pairs_per_lane = pick.far_ppl;
   }
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  gq_status st2 = upload_near_work(ctx);
+  gq_status st2 = build_near_work(ctx);
   free_workspace(ctx);
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
@@ -1154,7 +1238,7 @@ gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders) {
     GQ_HIP(ctx, hipSetDevice(ctx->device));
     if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->side) GQ_HIP(ctx, hipStreamSynchronize(ctx->side));
-    gq_status st = upload_near_work(ctx);
+    gq_status st = build_near_work(ctx);
     if (st != GQ_OK) return st;
   }
   return GQ_OK;

@@ -57,6 +57,15 @@ struct DevBuffers {
   int32_t *near_src = nullptr;       // per box owning centers: its direct sources (tree order)
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
   int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
+  // Stage 5b packed across boxes (far_pairs_per_lane 1): per wavefront 2 x int4 (first pair,
+  // pairs, first staged box, staged boxes), (first unit, units, 0, 0); per pair an int4 (center,
+  // List 3 far box, its LDS slot, 0) and a double4 (c - c_d, s_d, r); the staged boxes; per
+  // unit (one (center, far chunk) row) an int4 (row, first lane, lanes, 0)
+  int4 *m2q_wave = nullptr;
+  int4 *m2q_pair = nullptr;
+  double4 *m2q_geo = nullptr;
+  int32_t *m2q_stage = nullptr;
+  int4 *m2q_unit = nullptr;
   int32_t *bctr0 = nullptr, *bctr1 = nullptr;   // owned center range per box
   int32_t *part_base = nullptr;      // first near row of each box
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
@@ -82,6 +91,7 @@ struct DevBuffers {
 struct OrderBucket {
   int pq = 0;
   int64_t near0 = 0, near1 = 0, far0 = 0, far1 = 0, ctr0 = 0, ctr1 = 0;
+  int64_t m2q0 = 0, m2q1 = 0;        // packed Stage 5b wavefronts
 };
 
 }  // namespace gq
@@ -124,7 +134,10 @@ struct gq_ctx {
   int64_t n_m2l_items = 0;           // Stage 4 wavefronts
   int64_t n_p2m_items = 0, n_p2m_red = 0, n_p2m_parts = 0;  // Stage 2 work
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
+  int64_t n_m2q_waves = 0;           // packed Stage 5b wavefronts (0: per-box items)
+  int64_t n_m2q_pairs = 0, n_m2q_units = 0;
   int far_chunk = 16;                // List 3 far boxes per work item (sizes k_m2qbxl's LDS)
+  int m2q_stage_rows = 16;           // staged multipoles per packed Stage 5b wavefront
   // Shallowest depth whose multipoles are read (List 2 / List 3 far) and shallowest depth with a
   // non-zero M2L/P2L local: M2M above the first and L2L out of depths above the second have no
   // effect on any result and are not launched.

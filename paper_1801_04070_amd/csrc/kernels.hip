@@ -41,6 +41,11 @@ __device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ 
   return fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, ct.y) + l1);
 }
 
+// The moments, M2L, P2L and the Stage 7 gather run on the caller's stream and form the critical
+// path of an evaluation; their waves take issue priority over the direct pass's waves (side
+// stream) on a SIMD they share.
+__device__ __forceinline__ void critical_path_priority() { __builtin_amdgcn_s_setprio(1); }
+
 constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 
 // ------------------------------------------------------------------------------------------
@@ -93,6 +98,7 @@ __global__ void __launch_bounds__(64) k_p2m_all(
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, int P1, E *__restrict__ M, double2 *__restrict__ Mp,
     int64_t src_st, int64_t box_st, int64_t part_st, int64_t d_off) {
+  critical_path_priority();
   constexpr bool HQ = (KIND & 1) || KIND == 4, HD = (KIND & 2) || KIND == 4;
   constexpr int G = 64 / NBLK;
   const int4 it = items[blockIdx.x];  // box, first source, end of sources, partial slot or -1
@@ -191,6 +197,7 @@ __global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
                                                  const double2 *__restrict__ Mp, int P1,
                                                  E *__restrict__ M, int64_t part_st,
                                                  int64_t box_st, int64_t d_off) {
+  critical_path_priority();
   const int4 it = red[blockIdx.x];  // box, first partial, end of partials
   const int64_t jd = blockIdx.y;
   Mp += jd * part_st;
@@ -255,6 +262,7 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
     const double *__restrict__ plog, const E *__restrict__ M,
     const typename Scalar<E>::T *__restrict__ Bt, const E *__restrict__ opow, int P1,
     E *__restrict__ L, int64_t box_st) {
+  critical_path_priority();
   using R = typename Scalar<E>::T;
   using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
@@ -376,6 +384,7 @@ __global__ void __launch_bounds__(64) k_p2l(
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, int P1, E *__restrict__ L, int64_t src_st,
     int64_t box_st, int64_t d_off) {
+  critical_path_priority();
   constexpr bool HQ = (KIND & 1) || KIND == 4, HD = (KIND & 2) || KIND == 4;
   constexpr int G = 64 / NBLK;
   const int4 it = items[blockIdx.x];  // box, first source, end of sources
@@ -500,6 +509,7 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
     const int2 *__restrict__ items, const int2 *__restrict__ prs,
     const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
     const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st) {
+  critical_path_priority();
   constexpr int KS = 4 * RT;
   __shared__ double2 Pt[8][16 * RT];  // one batch's shifted rows, per pair
   __shared__ int32_t Pb[8];
@@ -1050,16 +1060,12 @@ __global__ void __launch_bounds__(64) k_near_md(
 // binomials: since C(m+k-1, m) = sum_{j<=k} C(m+j-2, m-1), V_m is the (m+1)-fold suffix sum of T.
 // Walking k downwards with running sums S_0 += T_k, S_1 += S_0, ..., S_PQ += S_{PQ-1} leaves
 // V_m = S_m. The powers w^k are produced downwards from w^p by multiplications with 1/w.
+// Pair geometry: y = c - c_d, the side s_d of box d and the radius r of center c.
 template <int PQ, typename E>
-__device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r, int32_t d,
-                                           const double2 *__restrict__ bc,
-                                           const int32_t *__restrict__ blevel,
-                                           const double *__restrict__ level_side,
-                                           const E *__restrict__ Md, int P1,
-                                           const double2 *__restrict__ lt) {
-  const double2 y = make_double2(cc.x - bc[d].x, cc.y - bc[d].y);
+__device__ __forceinline__ void m2qbxl_add_geo(double2 *alpha, double2 y, double sd, double r,
+                                               const E *__restrict__ Md, int P1,
+                                               const double2 *__restrict__ lt) {
   const double2 iy = cinv(y);
-  const double sd = level_side[blevel[d]];
   const double2 w = cscale(iy, sd);
   const double2 iw = make_double2(y.x / sd, y.y / sd);
   const double2 u = cscale(iy, -r);
@@ -1083,6 +1089,17 @@ __device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r,
     alpha[m] = cfma(pm, make_double2(S[m].x - a0 / m, S[m].y), alpha[m]);
     pm = cmul(pm, u);
   }
+}
+
+template <int PQ, typename E>
+__device__ __forceinline__ void m2qbxl_add(double2 *alpha, double2 cc, double r, int32_t d,
+                                           const double2 *__restrict__ bc,
+                                           const int32_t *__restrict__ blevel,
+                                           const double *__restrict__ level_side,
+                                           const E *__restrict__ Md, int P1,
+                                           const double2 *__restrict__ lt) {
+  m2qbxl_add_geo<PQ, E>(alpha, make_double2(cc.x - bc[d].x, cc.y - bc[d].y),
+                        level_side[blevel[d]], r, Md, P1, lt);
 }
 
 // Work items for Stage 5b, same item layout and lane mapping as k_near, the slices striding over
@@ -1136,6 +1153,65 @@ __global__ void __launch_bounds__(64) k_m2qbxl(
     double2 *row = anear + (int64_t)(row_first + cl) * rs;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) row[m] = alpha[m];
+  }
+}
+
+// Stage 5b over (center, List 3 far box) pairs packed across boxes, one pair per lane: a
+// wavefront holds whole units (a center and one chunk of its box's List 3 far boxes, one row),
+// so boxes with few centers or few far boxes no longer leave most lanes idle. The multipoles of
+// the wavefront's chunks and its unit records are staged in LDS, and each pair's geometry
+// (y = c - c_d, s_d, r; fixed by the build) comes as one record, so a lane waits on no chain of
+// dependent loads. Each lane forms its pair's coefficients, then the units' lanes are summed in
+// lane order through LDS, kM2qBlock coefficients per pass, and every unit writes its row.
+constexpr int kM2qBlock = 8;
+
+template <int PQ, typename E>
+__global__ void __launch_bounds__(64) k_m2qbxl_packed(
+    const int4 *__restrict__ waves, const int4 *__restrict__ pairs,
+    const double4 *__restrict__ geo, const int32_t *__restrict__ stage,
+    const int4 *__restrict__ units, const E *__restrict__ M, int P1,
+    double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st) {
+  HIP_DYNAMIC_SHARED(unsigned char, m2q_lds)
+  int4 *us = reinterpret_cast<int4 *>(m2q_lds);                       // [64] unit records
+  E *Ms = reinterpret_cast<E *>(m2q_lds + 64 * sizeof(int4));           // staged multipoles
+  double2 *red = reinterpret_cast<double2 *>(m2q_lds + 64 * sizeof(int4));  // then [kM2qBlock][64]
+  const double2 *lt = g_log_tab;
+  const int lane = threadIdx.x;
+  M += (int64_t)blockIdx.y * box_st;
+  anear += (int64_t)blockIdx.y * row_st;
+  const int4 w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
+  const int32_t pair0 = w0.x, npairs = w0.y, stage0 = w0.z, nstage = w0.w;
+  const int32_t unit0 = w1.x, nunits = w1.y;
+  if (lane < nunits) us[lane] = units[unit0 + lane];
+  for (int i = lane; i < nstage * P1; i += 64) {
+    const int e = i / P1, k = i - e * P1;
+    Ms[i] = M[(int64_t)stage[stage0 + e] * P1 + k];
+  }
+  __syncthreads();
+  double2 alpha[PQ + 1];
+#pragma unroll
+  for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
+  if (lane < npairs) {
+    const int slot = pairs[pair0 + lane].z;
+    const double4 g = geo[pair0 + lane];
+    m2qbxl_add_geo<PQ, E>(alpha, make_double2(g.x, g.y), g.z, g.w, Ms + slot * P1, P1, lt);
+  }
+#pragma unroll
+  for (int m0 = 0; m0 <= PQ; m0 += kM2qBlock) {
+    constexpr int kLast = PQ + 1;
+    const int mcount = kLast - m0 < kM2qBlock ? kLast - m0 : kM2qBlock;
+    __syncthreads();  // the staged multipoles / the previous block are no longer read
+#pragma unroll
+    for (int mm = 0; mm < kM2qBlock; ++mm)
+      if (mm < mcount) red[mm * 64 + lane] = alpha[m0 + mm];
+    __syncthreads();
+    for (int o = lane; o < nunits * mcount; o += 64) {
+      const int u = o / mcount, mm = o - u * mcount;
+      const int4 un = us[u];
+      double2 acc = red[mm * 64 + un.y];
+      for (int l = 1; l < un.z; ++l) acc = cadd(acc, red[mm * 64 + un.y + l]);
+      anear[(int64_t)un.x * rs + m0 + mm] = acc;
+    }
   }
 }
 
@@ -1389,6 +1465,15 @@ template <int PQ, typename E>
 void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
                           const Strides &S, const E *M) {
   auto &d = ctx->d;
+  const int32_t nw = (int32_t)(bk.m2q1 - bk.m2q0);
+  if (nw > 0) {
+    const size_t lds = 64 * sizeof(int4) +
+                       std::max(sizeof(E) * (size_t)ctx->m2q_stage_rows * (ctx->params.p_fmm + 1),
+                                sizeof(double2) * kM2qBlock * 64);
+    hipLaunchKernelGGL((k_m2qbxl_packed<PQ, E>), dim3(nw, nd), dim3(64), lds, s,
+                       d.m2q_wave + 2 * bk.m2q0, d.m2q_pair, d.m2q_geo, d.m2q_stage, d.m2q_unit,
+                       M, ctx->params.p_fmm + 1, d.anear, ctx->params.p_qbx + 1, S.box, S.row);
+  }
   const int32_t n = (int32_t)(bk.far1 - bk.far0);
   const size_t lds = sizeof(E) * (size_t)ctx->far_chunk * (ctx->params.p_fmm + 1);
   if (n > 0)
@@ -1471,7 +1556,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   // List 3 far multipoles -> centers on the side stream, once the upward pass is complete
   e = hipStreamWaitEvent(side, ctx->ev_up, 0);
   if (e != hipSuccess) return e;
-  if (ctx->n_far_items > 0) {
+  if (ctx->n_far_items > 0 || ctx->n_m2q_waves > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {

@@ -437,6 +437,33 @@ def test_s_and_d_concurrent_matches_separate(c1):
         q.graph(GQ_S_AND_D, dens[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_packed_list3_far_matches_per_box_items(precision):
+    """Stage 5b packed across boxes (far_pairs_per_lane 1) against the per-box items (2, and
+    the cost model 0): the same List 3 far sums in another order, so the potentials agree to
+    rounding; S, D and S_AND_D over three densities (two slots), and the oracle for FP64."""
+    from paper_1801_04070_amd import GQ_FP64, GQ_MIXED_FP32, GQ_S_AND_D
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    prec = GQ_FP64 if precision == "fp64" else GQ_MIXED_FP32
+    dens = _dev(np.stack([gi.fourier_density(g, seed=40 + j) for j in range(3)]))
+    res = {}
+    for ppl in (1, 2, 0):
+        q, st = _ctx(g, p_qbx=12, p_fmm=30 if precision == "fp64" else 16, precision=prec,
+                     far_pairs_per_lane=ppl, far_chunk=5)
+        assert (st["n_m2q_waves"] > 0) == (ppl == 1)
+        res[ppl] = (q.eval(1, dens).cpu().numpy(), q.eval(2, dens).cpu().numpy(),
+                    q.eval(GQ_S_AND_D, dens).cpu().numpy())
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for ppl in (2, 0):
+        for a, b in zip(res[1], res[ppl]):
+            assert _rel(a, b) < tol, ppl
+    assert np.array_equal(res[1][2][:3], res[1][0])
+    if precision == "fp64":
+        mu = gi.fourier_density(g, seed=40)
+        ref = oracle.qbx_eval(g, 1, mu, None, p_qbx=12)
+        assert _rel(res[1][0][0], ref) < 1e-10
+
+
 def test_autotune_picks_a_candidate_shape_and_keeps_results():
     """gq_autotune times candidate work-item shapes and keeps the fastest; the potentials stay
     those of the oracle (shapes change only how the direct and List 3 far sums are split)."""

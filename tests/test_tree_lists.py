@@ -421,3 +421,48 @@ def test_stage_work_counts(name):
     assert st["n_l2l_pairs"] == pairs
     # every box read by M2L/M2QBXL has sources (its moments are not trivially zero)
     assert (n[need] > 0).all()
+
+
+def _packed_far_waves(T, chunk=16, stage_rows=16):
+    """Greedy packing of (center, List 3 far chunk) units, written from the rule: box order,
+    whole units, at most 64 pairs and stage_rows staged far boxes per wavefront, a chunk staged
+    once per wavefront that holds any of its units."""
+    nc = T["ctr"][:, 1] - T["ctr"][:, 0]
+    W = np.diff(T["list3f"][0])
+    waves = units = 0
+    lanes = staged = 0
+    for b in np.nonzero(nc)[0]:
+        for c0 in range(0, W[b], chunk):
+            cl = min(chunk, W[b] - c0)
+            in_wave = False
+            for _ in range(nc[b]):
+                if lanes + cl > 64 or (not in_wave and staged + cl > stage_rows):
+                    waves += 1
+                    lanes = staged = 0
+                    in_wave = False
+                if not in_wave:
+                    staged += cl
+                    in_wave = True
+                lanes += cl
+                units += 1
+    return waves + (lanes > 0), units
+
+
+@pytest.mark.parametrize("far_chunk", [16, 3])
+def test_packed_list3_far_work(far_chunk):
+    """Stage 5b packed across boxes: every (center, List 3 far box) pair once, one row per
+    (center, far chunk), and the wavefront count of the packing rule, recomputed from the lists."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    q, T = _build(g, p_qbx=12, p_fmm=30, far_chunk=far_chunk)
+    st = T["stats"]
+    nc = T["ctr"][:, 1] - T["ctr"][:, 0]
+    W = np.diff(T["list3f"][0])
+    assert st["list3_far_pairs"] > 0
+    assert st["n_m2q_pairs"] == st["list3_far_pairs"] == (nc * W).sum()
+    waves, units = _packed_far_waves(T, chunk=far_chunk)
+    assert st["n_m2q_units"] == units == (nc * np.ceil(W / far_chunk)).sum()
+    assert st["n_m2q_waves"] == waves
+    assert waves >= np.ceil(st["n_m2q_pairs"] / 64)
+    # items of one box's centers instead: no packed work
+    q2, T2 = _build(g, p_qbx=12, p_fmm=30, far_chunk=far_chunk, far_pairs_per_lane=2)
+    assert T2["stats"]["n_m2q_waves"] == T2["stats"]["n_m2q_pairs"] == 0
