@@ -1246,28 +1246,58 @@ __global__ void __launch_bounds__(256) k_qbx_center(
   const int32_t b = cbox[c];
   double2 alpha[PQ + 1];
 
-  // L2QBXL: alpha_m = (r/s)^m sum_{k>=m} C(k,m) b_k t^(k-m), t = (c - c_b)/s  (Horner in t)
+  // L2QBXL: alpha_m = (r/s)^m sum_{k>=m} C(k,m) b_k t^(k-m), t = (c - c_b)/s.
+  // With a_k = b_k t^k the sums sum_k C(k,m) a_k are the coefficients of sum_k a_k (1+h)^k in h,
+  // formed by Horner in (1+h): per k (downwards) S_m += S_(m-1) for m = PQ..1, then S_0 += a_k,
+  // additions only; then alpha_m = S_m (r/(c - c_b))^m. The powers t^k run downwards from t^p by
+  // multiplications with 1/t. Where t^p could underflow (|t| below 2^(-900/p)), the plain Horner
+  // in t (a complex product per coefficient and step) is used instead.
   {
     const double s = level_side[blevel[b]];
     const double is = 1.0 / s;
-    const double2 t = make_double2((cc.x - bc[b].x) * is, (cc.y - bc[b].y) * is);
+    const double2 d = make_double2(cc.x - bc[b].x, cc.y - bc[b].y);
+    const double2 t = make_double2(d.x * is, d.y * is);
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
     const E *Lb = L + (int64_t)b * P1;
+    const double t2 = cnorm2(t);
+    const bool shift1 = t2 >= ldexp(1.0, -1800 / (P1 > 1 ? P1 - 1 : 1));
+    if (shift1) {
+      const double it2 = 1.0 / t2;
+      const double2 it = make_double2(t.x * it2, -t.y * it2);
+      double2 pw = cpowi(t, P1 - 1);
 #pragma unroll 4
-    for (int k = P1 - 1; k >= 0; --k) {
+      for (int k = P1 - 1; k >= 0; --k) {
+        const double2 a = cmul(to_d2(Lb[k]), pw);
+#pragma unroll
+        for (int m = PQ; m >= 1; --m) alpha[m] = cadd(alpha[m], alpha[m - 1]);
+        alpha[0] = cadd(alpha[0], a);
+        pw = cmul(pw, it);
+      }
+      const double2 rho = cscale(cinv(d), r);
+      double2 f = rho;
+#pragma unroll
+      for (int m = 1; m <= PQ; ++m) {
+        alpha[m] = cmul(alpha[m], f);
+        f = cmul(f, rho);
+      }
+    }
+#pragma unroll 4
+    for (int k = shift1 ? -1 : P1 - 1; k >= 0; --k) {
       const double2 bk = to_d2(Lb[k]);
       const double *Ck = l2q_binom + (int64_t)k * ls;
 #pragma unroll
       for (int m = 0; m <= PQ; ++m)
         if (m <= k) alpha[m] = caxpy(Ck[m], bk, cmul(alpha[m], t));
     }
-    const double rs = r * is;
-    double f = rs;
+    if (!shift1) {
+      const double rs = r * is;
+      double f = rs;
 #pragma unroll
-    for (int m = 1; m <= PQ; ++m) {
-      alpha[m] = cscale(alpha[m], f);
-      f *= rs;
+      for (int m = 1; m <= PQ; ++m) {
+        alpha[m] = cscale(alpha[m], f);
+        f *= rs;
+      }
     }
   }
 

@@ -43,8 +43,11 @@ def _m2qbxl_flops(q: int, p: int) -> int:
 
 
 def _l2qbxl_flops(q: int, p: int) -> int:
-    horner = sum(p - m for m in range(q + 1) if p - m > 0)
-    return 4 + 8 * horner + 8 * q
+    # t, 1/t, t^p (binary powers, ~2 log2 p products); per k: a_k = b_k t^k and the next power
+    # (2 complex products), q+1 complex adds of the Horner in (1 + h); r/(c - c_b) and its q powers
+    # applied to the q coefficients (2q products)
+    logp = max(p, 1).bit_length()
+    return 12 + 6 * 2 * logp + (p + 1) * (12 + 2 * (q + 1)) + 12 * q
 
 
 def _qbxl2p_flops(q: int) -> int:
