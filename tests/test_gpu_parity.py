@@ -327,6 +327,55 @@ def test_point_targets_match_oracle(kind):
         assert e_pt < tol and e_q < tol
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+def test_point_targets_at_leaf_centers(kind):
+    """Conventional targets placed exactly at the centers of sparse leaf boxes: each internal
+    center then sits at t = 0 of its box local, where the local-to-center shift takes its plain
+    Horner branch. Point values against the oracle's plain sums."""
+    from paper_1801_04070_amd import QBXFMM, _lib
+    g = gi.random_stars(n_curves=3, panels_per_curve=96, seed=21, box=10.0)
+    h = QBXFMM(device=-1)
+    h.set_geometry_from(g)
+    st = h.build(p_qbx=12, p_fmm=30)
+    level = h.tree_array(_lib.GQ_TREE_BOX_LEVEL)
+    child = h.tree_array(_lib.GQ_TREE_BOX_CHILD)
+    ij = h.tree_array(_lib.GQ_TREE_BOX_IJ)
+    src = h.tree_array(_lib.GQ_TREE_BOX_SRC_RANGE)
+    nsrc = src[:, 1] - src[:, 0]
+    lo, side = st["root_lo"], st["root_side"]
+    sz = side / 2.0 ** level  # box centers as the tree forms them
+    cen = np.stack([lo[0] + (ij[:, 0] + 0.5) * sz, lo[1] + (ij[:, 1] + 0.5) * sz], 1)
+    # inside the sources' bounding box (the root square stays the same) and few sources (the
+    # extra particle splits nothing)
+    inside = ((cen > g.src_xy.min(0)) & (cen < g.src_xy.max(0))).all(1)
+    leaves = np.nonzero((child < 0).all(1) & (nsrc >= 1) & (nsrc <= 16) & (level >= 2)
+                        & inside)[0][:40]
+    assert len(leaves) >= 10
+    pts = cen[leaves]
+    h.close()
+    e = copy.copy(g)
+    e.tgt_xy = np.concatenate([g.tgt_xy, pts])
+    e.tgt_ctr = np.concatenate([g.tgt_ctr, np.full((len(pts), 2), -1, np.int32)])
+    q, stats = _ctx(e, p_qbx=12, p_fmm=30)
+    assert stats["n_point_targets"] == len(pts)
+    # the same root and boxes, and every internal center is owned by the leaf it sits on
+    assert stats["root_lo"] == lo and stats["root_side"] == side
+    assert np.array_equal(q.tree_array(_lib.GQ_TREE_BOX_IJ), ij)
+    assert np.array_equal(q.tree_array(_lib.GQ_TREE_BOX_LEVEL), level)
+    ctr = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    order = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    for k, b in enumerate(leaves):
+        owned = order[ctr[b, 0]:ctr[b, 1]]
+        assert g.n_ctr + k in owned, (k, b)
+    mu, mu2 = _densities(g, 5)
+    gpu = _run(q, kind, mu, None)
+    ref_pt = oracle.point_potential(g, kind, mu, None, tgt_xy=pts)
+    err = _rel(gpu[g.n_tgt:], ref_pt)
+    print(f"points at leaf centers kind={kind} rel_err={err:.3e}")
+    assert err < 1e-10
+    assert _rel(gpu[:g.n_tgt], oracle.qbx_eval(g, kind, mu, None, p_qbx=12)) < 1e-10
+
+
 @pytest.mark.skip(reason="graph capture is switched off: a capture whose forked library stream "
                          "forked again crashed the host process, cause not established")
 @pytest.mark.parametrize("kind", [1, 3])
