@@ -293,16 +293,21 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
   auto fetch = [&](int32_t j) {
     const int32_t p = j + pr;
     const bool in = p < it.y;
-    rec = in ? prs[p] : make_int4(-1, 0, -1, 0);
-    pl = in ? plog[p] : 0.0;
+    const int32_t pc = in ? p : it.y - 1;  // in-bounds load, then select
+    const int4 rv = prs[pc];
+    const double lv = plog[pc];
+    rec = in ? rv : make_int4(-1, 0, -1, 0);
+    pl = in ? lv : 0.0;
     const bool pv = rec.x >= 0;
     const E *Md = M + (int64_t)(pv ? rec.x : 0) * P1;
     const E *op = opow + (int64_t)rec.y * P1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + g;
-      mdv[ks] = (pv && k < P1) ? Md[k] : mk2<E>(0.0, 0.0);
-      opv[ks] = k < P1 ? op[k] : mk2<E>(0.0, 0.0);
+      // loads from in-bounds addresses, then selects: no branch around each load
+      const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
+      const E mv = Md[kc], ov = op[kc];
+      mdv[ks] = (pv && k < P1) ? mv : mk2<E>(0.0, 0.0);
+      opv[ks] = k < P1 ? ov : mk2<E>(0.0, 0.0);
     }
   };
   fetch(it.x);
@@ -350,14 +355,23 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
     if (c16 == 2 * pr && g == 0 && !comp) Pb[pr] = rc.z;
     __syncthreads();
     if (lane < P1) {
-      for (int p = 0; p < nbat; ++p) {
-        const int32_t bx = Pb[p];
-        if (bx != cur) {
+      // the batch's rows and boxes read together, then summed in pair order
+      double2 v[8];
+      int32_t bxs[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        v[p] = Pt[p][lane];
+        bxs[p] = Pb[p];
+      }
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        if (p >= nbat) break;
+        if (bxs[p] != cur) {
           if (cur >= 0) L[(int64_t)cur * P1 + lane] = from_d2<E>(acc);
           acc = make_double2(0.0, 0.0);
-          cur = bx;
+          cur = bxs[p];
         }
-        acc = cadd(acc, Pt[p][lane]);
+        acc = cadd(acc, v[p]);
       }
     }
     __syncthreads();
@@ -538,18 +552,23 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
   auto fetch = [&](int32_t j) {
     const int32_t p = j + pr;
     const bool in = p < it.y;
-    rec = in ? prs[p] : make_int2(-1, -1);
+    const int32_t pc = in ? p : it.y - 1;  // in-bounds loads, then selects
+    const int2 rv = prs[pc];
+    const double4 tv = anc_tw[pc];
+    rec = in ? rv : make_int2(-1, -1);
     const bool pv = rec.x >= 0;
-    tw = pv ? anc_tw[p] : unit;
+    tw = pv ? tv : unit;
     const E *La = L + (int64_t)(pv ? rec.x : 0) * P1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + g;
-      lav[ks] = (pv && k < P1) ? to_d2(La[k]) : make_double2(0.0, 0.0);
+      const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;  // in-bounds load, then select
+      const double2 lv = to_d2(La[kc]);
+      lav[ks] = (pv && k < P1) ? lv : make_double2(0.0, 0.0);
     }
   };
   fetch(it.x);
   double2 acc = make_double2(0.0, 0.0);  // lane m: coefficient m of the current box
+  double2 own = make_double2(0.0, 0.0);  // lane m: coefficient m of that box's own local
   int32_t cur = -1;
   for (int32_t j0 = it.x; j0 < it.y; j0 += 8) {
     const int nbat = min(8, (int)(it.y - j0));
@@ -599,25 +618,30 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
     if (g == 0 && !comp) Pb[pr] = rc.y;
     __syncthreads();
     if (lane < P1) {
-      for (int p = 0; p < nbat; ++p) {
-        const int32_t bx = Pb[p];
-        if (bx != cur) {
-          if (cur >= 0) {
-            const int64_t o = (int64_t)cur * P1 + lane;
-            Lf[o] = from_d2<E>(cadd(to_d2(L[o]), acc));
-          }
+      // the batch's rows and boxes read together, then summed in pair order; a box's own local
+      // is loaded when its first pair arrives and added when the box is written
+      double2 v[8];
+      int32_t bxs[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        v[p] = Pt[p][lane];
+        bxs[p] = Pb[p];
+      }
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        if (p >= nbat) break;
+        if (bxs[p] != cur) {
+          if (cur >= 0) Lf[(int64_t)cur * P1 + lane] = from_d2<E>(cadd(own, acc));
           acc = make_double2(0.0, 0.0);
-          cur = bx;
+          cur = bxs[p];
+          own = to_d2(L[(int64_t)cur * P1 + lane]);
         }
-        acc = cadd(acc, Pt[p][lane]);
+        acc = cadd(acc, v[p]);
       }
     }
     __syncthreads();
   }
-  if (lane < P1 && cur >= 0) {
-    const int64_t o = (int64_t)cur * P1 + lane;
-    Lf[o] = from_d2<E>(cadd(to_d2(L[o]), acc));
-  }
+  if (lane < P1 && cur >= 0) Lf[(int64_t)cur * P1 + lane] = from_d2<E>(cadd(own, acc));
 }
 
 // ------------------------------------------------------------------------------------------
