@@ -95,11 +95,12 @@ gq_status alloc_ws(gq_ctx *ctx, T *&dst, size_t count) {
     if (s_ != GQ_OK) return s_;      \
   } while (0)
 
-// Direct-interaction work (Stages 3, 5a, 6a) and multipole-to-QBX-local work (Stage 5b) are split
-// into items of one wavefront each: a box, one chunk of its direct sources (at most kNearChunk)
-// or of its List 3 far boxes (at most kFarChunk), and a block of n_cl of its centers. The wave
-// runs n_cl centers x (64 / n_cl) slices over the chunk; n_cl is the power of two minimising a
-// simple cost model (per-element work + slice reduction + fixed cost per wave). Each (center,
+// Direct-interaction work (Stages 3, 5a, 6a) and the per-box form of the multipole-to-QBX-local
+// work (Stage 5b) are split into items of one wavefront each: a box, one chunk of its direct
+// sources (at most kNearChunk) or of its List 3 far boxes (at most kFarChunk), and a block of
+// n_cl of its centers. The wave runs n_cl centers x n_sl slices over the chunk (n_cl n_sl <= 64),
+// the shape minimising a simple cost model (per-element work + slice reduction + fixed cost per
+// wave): any n_sl for the direct items, powers of two for the List 3 far items. Each (center,
 // chunk) result goes to its own row; the rows of a box are laid out [chunk][center], direct
 // chunks first.
 constexpr int kMomentChunk = 512;  // sources per Stage 2 work item
@@ -118,6 +119,21 @@ int pick_lg(int64_t nc, int64_t len, double elem_cost) {
     if (cost <= best) { best = cost; best_lg = lg; }
   }
   return best_lg;
+}
+
+// Slices per center (1..64) of a direct item, n_cl = 64 / n_sl centers per wavefront.
+int pick_slices(int64_t nc, int64_t len, double elem_cost) {
+  int best_nsl = 1;
+  double best = 1e300;
+  for (int nsl = 64; nsl >= 1; --nsl) {
+    const int64_t ncl = 64 / nsl;
+    int steps = 0;
+    while ((1 << steps) < nsl) ++steps;  // reduction steps, ceil(log2 n_sl)
+    const double waves = (double)((nc + ncl - 1) / ncl);
+    const double cost = waves * ((double)((len + nsl - 1) / nsl) * elem_cost + steps * 60.0 + 150.0);
+    if (cost <= best) { best = cost; best_nsl = nsl; }
+  }
+  return best_nsl;
 }
 
 // Work of the per-center stages grouped by QBX order: every box runs at its own order (the
@@ -177,6 +193,16 @@ gq_status build_near_work(gq_ctx *ctx) {
       out.insert(out.end(), item, item + 8);
     }
   };
+  // direct items record their slice count, n_sl (List 3 far items: log2 of n_cl)
+  auto emit_near = [](std::vector<int32_t> &out, int64_t off, int64_t clen, int64_t ctr0,
+                      int64_t row0, int64_t nc, int nsl) {
+    const int64_t ncl = 64 / nsl;
+    for (int64_t cb = 0; cb < nc; cb += ncl) {
+      const int32_t item[8] = {(int32_t)off, (int32_t)clen, (int32_t)(ctr0 + cb), (int32_t)(row0 + cb),
+                               (int32_t)std::min<int64_t>(ncl, nc - cb), nsl, 0, 0};
+      out.insert(out.end(), item, item + 8);
+    }
+  };
   // direct source lists and row layout (independent of the orders)
   for (int64_t b = 0; b < nb; ++b) {
     bctr0[b] = (int32_t)t.ctr_begin[b];
@@ -210,8 +236,8 @@ gq_status build_near_work(gq_ctx *ctx) {
       const int64_t nchunks = (len + near_chunk - 1) / near_chunk;
       for (int64_t j = 0; j < nchunks; ++j) {
         const int64_t c0 = j * near_chunk, clen = std::min<int64_t>(near_chunk, len - c0);
-        emit(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
-             pick_lg(nc, clen, 10.0 * pq));
+        emit_near(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
+                  pick_slices(nc, clen, 10.0 * pq));
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
       for (int64_t j = 0; j * far_chunk < wlen; ++j) {

@@ -803,9 +803,19 @@ __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, co
 // ------------------------------------------------------------------------------------------
 // Stages 3, 5a, 6a: P2QBXL from the direct sources (List 1, List 3 close, List 4 close) of a box
 // into its centers. One wavefront per work item (box, source chunk, block of n_cl centers): lane
-// = (center, slice) with 64/n_cl slices striding over the chunk's sources, then a fixed-order
-// xor-shuffle reduction over the slices. The result row holds the scaled coefficients.
+// = (center, slice), n_sl slices per center (any n_sl <= 64, n_cl n_sl <= 64 lanes busy) striding
+// over the chunk's sources, then a fixed-order shuffle reduction over the slices (slice_add).
+// The result row holds the scaled coefficients.
 constexpr int kNearBatch = 128;  // sources staged in LDS per step
+
+// One step of the slice reduction over n_sl slices of a center (lanes cl n_sl + sl): at step o
+// (1, 2, 4, ...) slice sl adds slice sl + o when sl is a multiple of 2 o and sl + o < n_sl, so
+// after ceil(log2 n_sl) steps slice 0 holds the sum, in a fixed order. Every lane joins the
+// shuffle.
+__device__ __forceinline__ void slice_add(double &v, int o, bool take) {
+  const double t = __shfl_down(v, o, 64);
+  if (take) v += t;
+}
 
 template <int KIND, int PQ>
 __global__ void __launch_bounds__(64) k_near(
@@ -827,10 +837,9 @@ __global__ void __launch_bounds__(64) k_near(
   }
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
-  const int n_ctr = i1.x, lg = i1.y;
-  const int nsl = 64 >> lg;
-  const int cl = lane >> (6 - lg);
-  const int sl = lane & (nsl - 1);
+  const int n_ctr = i1.x, nsl = i1.y;  // centers, slices per center
+  const int cl = lane / nsl;
+  const int sl = lane - cl * nsl;
   const bool active = cl < n_ctr;
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
@@ -858,13 +867,14 @@ __global__ void __launch_bounds__(64) k_near(
       }
     }
   }
-  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+  for (int o = 1; o < nsl; o <<= 1) {
+    const bool take = (sl & (2 * o - 1)) == 0 && sl + o < nsl;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
-      acc.a[m].x += __shfl_xor(acc.a[m].x, o, 64);
-      acc.a[m].y += __shfl_xor(acc.a[m].y, o, 64);
+      slice_add(acc.a[m].x, o, take);
+      slice_add(acc.a[m].y, o, take);
     }
-    if (KIND & 1) acc.logsum += __shfl_xor(acc.logsum, o, 64);
+    if (KIND & 1) slice_add(acc.logsum, o, take);
   }
   if (active && sl == 0) {
     double2 alpha[PQ + 1];
@@ -933,10 +943,9 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   }
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
-  const int n_ctr = i1.x, lg = i1.y;
-  const int nsl = 64 >> lg;
-  const int cl = lane >> (6 - lg);
-  const int sl = lane & (nsl - 1);
+  const int n_ctr = i1.x, nsl = i1.y;  // centers, slices per center
+  const int cl = lane / nsl;
+  const int sl = lane - cl * nsl;
   const bool active = cl < n_ctr;
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
@@ -964,15 +973,16 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
       }
     }
   }
-  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+  for (int o = 1; o < nsl; o <<= 1) {
+    const bool take = (sl & (2 * o - 1)) == 0 && sl + o < nsl;
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) {
-      acc.as[m].x += __shfl_xor(acc.as[m].x, o, 64);
-      acc.as[m].y += __shfl_xor(acc.as[m].y, o, 64);
-      acc.ad[m].x += __shfl_xor(acc.ad[m].x, o, 64);
-      acc.ad[m].y += __shfl_xor(acc.ad[m].y, o, 64);
+      slice_add(acc.as[m].x, o, take);
+      slice_add(acc.as[m].y, o, take);
+      slice_add(acc.ad[m].x, o, take);
+      slice_add(acc.ad[m].y, o, take);
     }
-    acc.logsum += __shfl_xor(acc.logsum, o, 64);
+    slice_add(acc.logsum, o, take);
   }
   if (active && sl == 0) {
     // the finish of NearAcc<1> and NearAcc<2> written out for both rows
@@ -1009,10 +1019,9 @@ __global__ void __launch_bounds__(64) k_near_md(
   const int ng = min(DG, n_dens - jd0);
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
-  const int n_ctr = i1.x, lg = i1.y;
-  const int nsl = 64 >> lg;
-  const int cl = lane >> (6 - lg);
-  const int sl = lane & (nsl - 1);
+  const int n_ctr = i1.x, nsl = i1.y;  // centers, slices per center
+  const int cl = lane / nsl;
+  const int sl = lane - cl * nsl;
   const bool active = cl < n_ctr;
   const int32_t c = ctr_first + (active ? cl : 0);
   const double2 cc = cxy[c];
@@ -1048,15 +1057,16 @@ __global__ void __launch_bounds__(64) k_near_md(
       }
     }
   }
-  for (int o = nsl >> 1; o >= 1; o >>= 1) {
+  for (int o = 1; o < nsl; o <<= 1) {
+    const bool take = (sl & (2 * o - 1)) == 0 && sl + o < nsl;
 #pragma unroll
     for (int g = 0; g < DG; ++g) {
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) {
-        acc.a[g][m].x += __shfl_xor(acc.a[g][m].x, o, 64);
-        acc.a[g][m].y += __shfl_xor(acc.a[g][m].y, o, 64);
+        slice_add(acc.a[g][m].x, o, take);
+        slice_add(acc.a[g][m].y, o, take);
       }
-      if (KIND & 1) acc.logsum[g] += __shfl_xor(acc.logsum[g], o, 64);
+      if (KIND & 1) slice_add(acc.logsum[g], o, take);
     }
   }
   if (active && sl == 0) {
