@@ -190,8 +190,9 @@ __global__ void __launch_bounds__(64) k_p2m_all(
   }
 }
 
-// Sum of a split box's partial moments (one wavefront per box): four running sums over the
-// partials p = 0, 1, 2, 3 (mod 4), then combined in that order, so the result is deterministic.
+// Sum of a split box's partial moments (one wavefront per box): sixteen running sums over the
+// partials p = 0..15 (mod 16), their loads issued together (clamped to the last partial, extra
+// values unused), then combined by a fixed pairwise tree, so the result is deterministic.
 template <int NK, typename E>
 __global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
                                                  const double2 *__restrict__ Mp, int P1,
@@ -202,17 +203,25 @@ __global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
   const int64_t jd = blockIdx.y;
   Mp += jd * part_st;
   M += jd * box_st;
+  constexpr int U = 16;
   for (int r = threadIdx.x; r < NK * P1; r += 64) {
-    double2 a4[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
-                     make_double2(0.0, 0.0)};
-    int32_t p = it.y;
-    for (; p + 4 <= it.z; p += 4)
+    double2 a[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = cadd(a4[u], Mp[(int64_t)(p + u) * 2 * P1 + r]);
-    for (int u = 0; p < it.z; ++p, ++u) a4[u] = cadd(a4[u], Mp[(int64_t)p * 2 * P1 + r]);
-    const double2 a = cadd(cadd(a4[0], a4[1]), cadd(a4[2], a4[3]));
-    if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(a);
-    else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(a);
+    for (int u = 0; u < U; ++u) a[u] = make_double2(0.0, 0.0);
+    for (int32_t p = it.y; p < it.z; p += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t q = p + u;
+        const double2 v = Mp[(int64_t)(q < it.z ? q : it.z - 1) * 2 * P1 + r];
+        if (q < it.z) a[u] = cadd(a[u], v);
+      }
+    }
+#pragma unroll
+    for (int w = U / 2; w >= 1; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) a[u] = cadd(a[u], a[u + w]);
+    if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(a[0]);
+    else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(a[0]);
   }
 }
 
