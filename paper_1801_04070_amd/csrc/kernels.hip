@@ -815,7 +815,8 @@ __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, co
 // = (center, slice), n_sl slices per center (any n_sl <= 64, n_cl n_sl <= 64 lanes busy) striding
 // over the chunk's sources, then a fixed-order shuffle reduction over the slices (slice_add).
 // The result row holds the scaled coefficients.
-constexpr int kNearBatch = 128;  // sources staged in LDS per step
+constexpr int kNearBatch = 128;  // sources staged in LDS per step (two per lane)
+static_assert(kNearBatch == 128, "k_near_sd stages two sources per lane");
 
 // One step of the slice reduction over n_sl slices of a center (lanes cl n_sl + sl): at step o
 // (1, 2, 4, ...) slice sl adds slice sl + o when sl is a multiple of 2 o and sl + o < n_sl, so
@@ -962,18 +963,27 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   const double2 *lt = g_log_tab;
   NearAccSD<PQ> acc;
   acc.zero();
+  // the indices of a batch's sources are fetched during the previous batch's pairs (clamped to
+  // the item's last source, extra values unused)
+  const int32_t last = off + len - 1;
+  auto idx = [&](int32_t k) { return near_src[k < last ? k : last]; };
+  int32_t nx0 = idx(off + lane), nx1 = idx(off + lane + 64);
   for (int32_t base = 0; base < len; base += kNearBatch) {
     const int nb = min(kNearBatch, (int)(len - base));
+    const int32_t s0 = nx0, s1 = nx1;
     __syncthreads();
-#pragma unroll
-    for (int j = lane; j < kNearBatch; j += 64) {
-      if (j < nb) {
-        const int32_t s = near_src[off + base + j];
-        t_xy[j] = sxy[s];
-        t_q[j] = sq[s];
-        t_d[j] = sdip[s];
-      }
+    if (lane < nb) {
+      t_xy[lane] = sxy[s0];
+      t_q[lane] = sq[s0];
+      t_d[lane] = sdip[s0];
     }
+    if (lane + 64 < nb) {
+      t_xy[lane + 64] = sxy[s1];
+      t_q[lane + 64] = sq[s1];
+      t_d[lane + 64] = sdip[s1];
+    }
+    nx0 = idx(off + base + kNearBatch + lane);
+    nx1 = idx(off + base + kNearBatch + lane + 64);
     __syncthreads();
     if (active) {
       for (int j = sl; j < nb; j += nsl) {
