@@ -78,6 +78,27 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 }
 
 // ------------------------------------------------------------------------------------------
+// The value of lane + o (o = 1, 2, 4, ... 32) for the group sums below, which need their result
+// only in the lowest group of lanes: DPP row shifts within 16-lane rows for o < 16 (a lane past
+// its row's end reads 0), a shuffle across rows otherwise.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_shl(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_down(double v, int o) {
+  switch (o) {
+    case 1: return dpp_row_shl<0x101>(v);
+    case 2: return dpp_row_shl<0x102>(v);
+    case 4: return dpp_row_shl<0x104>(v);
+    case 8: return dpp_row_shl<0x108>(v);
+    default: return __shfl_down(v, o, 64);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Stage 2 as direct moments: the multipole of every box that M2L or M2QBXL reads is formed from
 // the sources of its subtree (contiguous in tree order). In 2-D, M2M keeps the first p + 1
 // moments of a box exact (coefficient m of the parent depends only on the children's
@@ -87,9 +108,10 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 // Lanes: NBLK blocks of 8 consecutive orders (k = 8 kb + i) times 64 / NBLK source groups. A lane
 // walks the sources of its group, forms y^(8 kb) by repeated squaring and the block's powers by a
 // chain of complex multiplies, and accumulates A_k = sum q y^k and B_k = sum d y^k in registers;
-// a fixed xor tree then sums the groups. Coefficient k of the single layer is A_0 (k = 0) or
-// -A_k / k, of the double layer B_(k-1) (0 at k = 0). KIND 3 stores their sum (one expansion),
-// KIND 4 (S and D of one density) both, the D multipole d_off coefficients after the S one.
+// a fixed shift-down tree (lane_down) then sums the groups into lanes 0..NBLK-1. Coefficient k
+// of the single layer is A_0 (k = 0) or -A_k / k, of the double layer B_(k-1) (0 at k = 0).
+// KIND 3 stores their sum (one expansion), KIND 4 (S and D of one density) both, the D
+// multipole d_off coefficients after the S one.
 // A split box's items write partial rows [S: P1][D: P1] to Mp for k_m_reduce.
 template <int KIND, int NBLK, typename E>
 __global__ void __launch_bounds__(64) k_p2m_all(
@@ -146,16 +168,16 @@ __global__ void __launch_bounds__(64) k_p2m_all(
     }
   }
 #pragma unroll
-  for (int o = 32; o >= NBLK; o >>= 1) {
+  for (int o = NBLK; o < 64; o <<= 1) {  // group g adds group g + o / NBLK: lanes 0..NBLK-1 sum
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (HQ) {
-        A[i].x += __shfl_xor(A[i].x, o, 64);
-        A[i].y += __shfl_xor(A[i].y, o, 64);
+        A[i].x += lane_down(A[i].x, o);
+        A[i].y += lane_down(A[i].y, o);
       }
       if (HD) {
-        B[i].x += __shfl_xor(B[i].x, o, 64);
-        B[i].y += __shfl_xor(B[i].y, o, 64);
+        B[i].x += lane_down(B[i].x, o);
+        B[i].y += lane_down(B[i].y, o);
       }
     }
   }
@@ -395,10 +417,10 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
 // -q v^k / k + d v^(k+1). Lanes: NBLK blocks of 8 consecutive powers (j = 8 kb + i, covering
 // j = 0..P1) times 64 / NBLK source groups; a lane forms v^(8 kb) by squaring and the block by a
 // multiply chain, accumulates A_j = sum q v^j and B_j = sum d v^j in registers (and the log sum
-// on the lanes of block 0), and a fixed xor tree adds the groups. Single layer row j = -A_j / j
-// (the log sum at j = 0), double layer row j = B_(j+1) (the next block's first power from the
-// neighbouring lane, or for the last block one extra power). KIND 4 (S and D of one density)
-// adds the D rows d_off coefficients further.
+// on the lanes of block 0), and a fixed shift-down tree (lane_down) adds the groups into lanes
+// 0..NBLK-1. Single layer row j = -A_j / j (the log sum at j = 0), double layer row
+// j = B_(j+1) (the next block's first power from the neighbouring lane, or for the last block
+// one extra power). KIND 4 (S and D of one density) adds the D rows d_off coefficients further.
 template <int KIND, int NBLK, typename E>
 __global__ void __launch_bounds__(64) k_p2l(
     const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
@@ -464,22 +486,22 @@ __global__ void __launch_bounds__(64) k_p2l(
     if (HD && kb == NBLK - 1) Bx = cfma(d, cmul(pw, v), Bx);
   }
 #pragma unroll
-  for (int o = 32; o >= NBLK; o >>= 1) {
+  for (int o = NBLK; o < 64; o <<= 1) {  // group g adds group g + o / NBLK: lanes 0..NBLK-1 sum
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if (HQ) {
-        A[i].x += __shfl_xor(A[i].x, o, 64);
-        A[i].y += __shfl_xor(A[i].y, o, 64);
+        A[i].x += lane_down(A[i].x, o);
+        A[i].y += lane_down(A[i].y, o);
       }
       if (HD) {
-        B[i].x += __shfl_xor(B[i].x, o, 64);
-        B[i].y += __shfl_xor(B[i].y, o, 64);
+        B[i].x += lane_down(B[i].x, o);
+        B[i].y += lane_down(B[i].y, o);
       }
     }
-    if (HQ) lsum += __shfl_xor(lsum, o, 64);
+    if (HQ) lsum += lane_down(lsum, o);
     if (HD) {
-      Bx.x += __shfl_xor(Bx.x, o, 64);
-      Bx.y += __shfl_xor(Bx.y, o, 64);
+      Bx.x += lane_down(Bx.x, o);
+      Bx.y += lane_down(Bx.y, o);
     }
   }
   // B_(8 kb + 8) from the lane of the next block (lanes 0..NBLK-1 hold the sums)
