@@ -78,25 +78,30 @@ __global__ void k_gather(int32_t ns, const int32_t *__restrict__ sperm, const do
 }
 
 // ------------------------------------------------------------------------------------------
-// The value of lane + o (o = 1, 2, 4, ... 32) for the group sums below, which need their result
-// only in the lowest group of lanes: DPP row shifts within 16-lane rows for o < 16 (a lane past
-// its row's end reads 0), a shuffle across rows otherwise.
+// A double moved between lanes by one DPP pattern (CTRL), both halves alike; a lane whose source
+// lies outside its row reads 0.
 template <int CTRL>
-__device__ __forceinline__ double dpp_row_shl(double v) {
+__device__ __forceinline__ double dpp_mov(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
+// The value of lane + o (o = 1, 2, 4, ... 32) for the group sums below, which need their result
+// only in the lowest group of lanes: DPP row shifts (row_shl) within 16-lane rows for o < 16, a
+// shuffle across rows otherwise.
 __device__ __forceinline__ double lane_down(double v, int o) {
   switch (o) {
-    case 1: return dpp_row_shl<0x101>(v);
-    case 2: return dpp_row_shl<0x102>(v);
-    case 4: return dpp_row_shl<0x104>(v);
-    case 8: return dpp_row_shl<0x108>(v);
+    case 1: return dpp_mov<0x101>(v);
+    case 2: return dpp_mov<0x102>(v);
+    case 4: return dpp_mov<0x104>(v);
+    case 8: return dpp_mov<0x108>(v);
     default: return __shfl_down(v, o, 64);
   }
 }
+
+// The value of lane ^ 1 (quad_perm 1, 0, 3, 2).
+__device__ __forceinline__ double lane_xor1(double v) { return dpp_mov<0xB1>(v); }
 
 // ------------------------------------------------------------------------------------------
 // Stage 2 as direct moments: the multipole of every box that M2L or M2QBXL reads is formed from
@@ -375,7 +380,7 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * rt + Mfma16<R>::row(g, v);
         const double y = C[rt][v];
-        const double yo = __shfl_xor(y, 1, 64);
+        const double yo = lane_xor1(y);
         if (!comp && m < P1) {
           const E om = F64 ? opc[4 * rt + v] : opr[m];
           double2 t = cmul(make_double2(y, yo), to_d2(om));
@@ -640,7 +645,7 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * rt + Mfma16<double>::row(g, v);
         const double y = C[rt][v];
-        const double yo = __shfl_xor(y, 1, 64);
+        const double yo = lane_xor1(y);
         if (!comp) Pt[pr][m] = cmul(make_double2(y, yo), wv);
         wv = cmul(wv, w4);
       }
