@@ -121,11 +121,17 @@ int pick_lg(int64_t nc, int64_t len, double elem_cost) {
   return best_lg;
 }
 
-// Slices per center (1..64) of a direct item, n_cl = 64 / n_sl centers per wavefront.
+// Slices per center (1..64) of a direct item, n_cl = 64 / n_sl centers per wavefront. A lane
+// takes at most kNearLaneSteps sources of the chunk (unless n_sl = 64): for a large box every
+// shape costs about the same in total, and without the cap the model picks one or two slices,
+// whose wavefronts then run far longer than the rest and set the kernel's length.
+constexpr int kNearLaneSteps = 64;
+
 int pick_slices(int64_t nc, int64_t len, double elem_cost) {
-  int best_nsl = 1;
+  int best_nsl = 64;
   double best = 1e300;
   for (int nsl = 64; nsl >= 1; --nsl) {
+    if (nsl < 64 && (len + nsl - 1) / nsl > kNearLaneSteps) continue;
     const int64_t ncl = 64 / nsl;
     int steps = 0;
     while ((1 << steps) < nsl) ++steps;  // reduction steps, ceil(log2 n_sl)
