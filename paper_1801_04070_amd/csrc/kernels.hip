@@ -1447,13 +1447,16 @@ __global__ void __launch_bounds__(256) k_direct(
 }
 
 // ------------------------------------------------------------------------------------------
-// Average the target slots into the caller's output row.
+// Average the target slots into the caller's output row: value row y of tv goes to row y of out,
+// or for y >= n_first to row y - n_first of out2 (S and D rows of one evaluation in one launch).
 __global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const double *__restrict__ tv,
-                           double *__restrict__ out, int64_t tv_st, int64_t ld_out) {
+                           double *__restrict__ out, int64_t tv_st, int64_t ld_out,
+                           double *__restrict__ out2, int32_t n_first) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
-  tv += (int64_t)blockIdx.y * tv_st;
-  out += (int64_t)blockIdx.y * ld_out;
+  const int32_t y = (int32_t)blockIdx.y;
+  tv += (int64_t)y * tv_st;
+  out = y < n_first ? out + (int64_t)y * ld_out : out2 + (int64_t)(y - n_first) * ld_out;
   double s = 0.0;
   int n = 0;
   if (tctr[2 * t] >= 0) { s += tv[2 * t]; n++; }
@@ -1793,11 +1796,8 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const 
     if (e != hipSuccess) return e;
     const int32_t nt = (int32_t)ctx->nt;
     StageTimer st_(ctx, GQ_STAGE_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
-                       ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out);
-    hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
-                       ctx->d.tctr, ctx->d.tv + (int64_t)nd * 2 * ctx->nt, out2, 2 * ctx->nt,
-                       ld_out);
+    hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, 2 * nd), dim3(256), 0, ctx->stream, nt,
+                       ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out, out2, nd);
     return hipGetLastError();
   }
   switch (kind) {
@@ -1826,7 +1826,7 @@ hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const 
   const int32_t nt = (int32_t)ctx->nt;
   StageTimer st_(ctx, GQ_STAGE_FINALIZE);
   hipLaunchKernelGGL(k_finalize, dim3((nt + 255) / 256, nd), dim3(256), 0, ctx->stream, nt,
-                     ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out);
+                     ctx->d.tctr, ctx->d.tv, out, 2 * ctx->nt, ld_out, nullptr, nd);
   return hipGetLastError();
 }
 
