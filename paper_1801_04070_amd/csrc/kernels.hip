@@ -1298,9 +1298,14 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
 // ------------------------------------------------------------------------------------------
 // Stage 8 per center: L2QBXL (box local -> center), plus the direct and List 3 far rows from
 // k_near and k_m2qbxl, then QBXL2P at its targets.
-// One thread per center (tree order, so a wave covers centers of a few neighbouring boxes).
+// One thread per center (tree order, so a wave covers centers of a few neighbouring boxes), one
+// wavefront per work-group: the complete locals of the wave's first kCenterStage boxes are
+// staged in LDS, so the serial shift loop reads its coefficients from LDS instead of waiting on
+// global memory at every step (a further box reads them from global memory).
+constexpr int kCenterStage = 8;
+
 template <int KIND, int PQ, typename E>
-__global__ void __launch_bounds__(256) k_qbx_center(
+__global__ void __launch_bounds__(64) k_qbx_center(
     int32_t nc, const int32_t *__restrict__ clist, int rs, int ls,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const int32_t *__restrict__ cbox, const double2 *__restrict__ bc,
@@ -1312,18 +1317,43 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
     int64_t tv_st) {
-  const int32_t ic = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ic >= nc) return;
-  const int32_t c = clist[ic];
+  HIP_DYNAMIC_SHARED(unsigned char, ctr_lds)
+  E *Ls = reinterpret_cast<E *>(ctr_lds);  // [kCenterStage][P1]
+  __shared__ int32_t sbox[kCenterStage];
+  const int lane = threadIdx.x;
+  const int32_t ic = blockIdx.x * 64 + lane;
+  const bool active = ic < nc;
+  const int32_t c = clist[active ? ic : nc - 1];
   {
     const int64_t jd = blockIdx.y;
     L += jd * box_st;
     anear += jd * row_st;
     tv += jd * tv_st;
   }
+  const int32_t b = cbox[c];
+  // runs of equal boxes across the wave's lanes; run j < kCenterStage is staged in LDS row j
+  const int32_t bprev = __shfl_up(b, 1, 64);
+  const uint64_t runs = __ballot(lane == 0 || bprev != b);
+  const int rank = __popcll(runs & (~0ull >> (63 - lane))) - 1;
+  const int nst = min(__popcll(runs), kCenterStage);
+  {
+    uint64_t m = runs;
+    for (int j = 0; j < nst; ++j) {
+      const int l = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const int32_t bx = __shfl(b, l, 64);
+      if (lane == 0) sbox[j] = bx;
+    }
+  }
+  __syncthreads();
+  for (int i = lane; i < nst * P1; i += 64) {
+    const int j = i / P1, k = i - j * P1;
+    Ls[i] = L[(int64_t)sbox[j] * P1 + k];
+  }
+  __syncthreads();
+  if (!active) return;
   const double2 cc = cxy[c];
   const double r = cr[c];
-  const int32_t b = cbox[c];
   double2 alpha[PQ + 1];
 
   // L2QBXL: alpha_m = (r/s)^m sum_{k>=m} C(k,m) b_k t^(k-m), t = (c - c_b)/s.
@@ -1339,7 +1369,7 @@ __global__ void __launch_bounds__(256) k_qbx_center(
     const double2 t = make_double2(d.x * is, d.y * is);
 #pragma unroll
     for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
-    const E *Lb = L + (int64_t)b * P1;
+    const E *Lb = rank < kCenterStage ? Ls + rank * P1 : L + (int64_t)b * P1;
     const double t2 = cnorm2(t);
     const bool shift1 = t2 >= ldexp(1.0, -1800 / (P1 > 1 ? P1 - 1 : 1));
     if (shift1) {
@@ -1602,7 +1632,8 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.ctr1 - bk.ctr0);
   if (n > 0)
-    hipLaunchKernelGGL((k_qbx_center<KIND, PQ, E>), dim3((n + 255) / 256, nd), dim3(256), 0, s, n,
+    hipLaunchKernelGGL((k_qbx_center<KIND, PQ, E>), dim3((n + 63) / 64, nd), dim3(64),
+                       sizeof(E) * kCenterStage * (ctx->params.p_fmm + 1), s, n,
                        d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
                        d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
                        d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear,
