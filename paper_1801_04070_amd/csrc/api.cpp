@@ -318,7 +318,9 @@ gq_status build_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_wave, qwave.data(), qwave.size() / 4);
-  if (st == GQ_OK) st = upload(ctx, d.m2q_pair, qpair.data(), qpair.size() / 4);
+  std::vector<int32_t> qslot(qpair.size() / 4);
+  for (size_t i = 0; i < qslot.size(); ++i) qslot[i] = qpair[4 * i + 2];
+  if (st == GQ_OK) st = upload(ctx, d.m2q_slot, qslot.data(), qslot.size());
   if (st == GQ_OK) st = upload(ctx, d.m2q_geo, qgeo.data(), qgeo.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_stage, qstage.data(), qstage.size());
   if (st == GQ_OK) st = upload(ctx, d.m2q_unit, qunit.data(), qunit.size() / 4);

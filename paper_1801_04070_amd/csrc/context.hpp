@@ -58,11 +58,11 @@ struct DevBuffers {
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
   int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
   // Stage 5b packed across boxes (far_pairs_per_lane 1): per wavefront 2 x int4 (first pair,
-  // pairs, first staged box, staged boxes), (first unit, units, 0, 0); per pair an int4 (center,
-  // List 3 far box, its LDS slot, 0) and a double4 (c - c_d, s_d, r); the staged boxes; per
-  // unit (one (center, far chunk) row) an int4 (row, first lane, lanes, 0)
+  // pairs, first staged box, staged boxes), (first unit, units, 0, 0); per pair the LDS slot of
+  // its List 3 far box and a double4 (c - c_d, s_d, r); the staged boxes; per unit (one
+  // (center, far chunk) row) an int4 (row, first lane, lanes, 0)
   int4 *m2q_wave = nullptr;
-  int4 *m2q_pair = nullptr;
+  int32_t *m2q_slot = nullptr;
   double4 *m2q_geo = nullptr;
   int32_t *m2q_stage = nullptr;
   int4 *m2q_unit = nullptr;

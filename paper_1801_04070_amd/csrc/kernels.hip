@@ -1247,7 +1247,7 @@ constexpr int kM2qBlock = 8;
 
 template <int PQ, typename E>
 __global__ void __launch_bounds__(64) k_m2qbxl_packed(
-    const int4 *__restrict__ waves, const int4 *__restrict__ pairs,
+    const int4 *__restrict__ waves, const int32_t *__restrict__ slots,
     const double4 *__restrict__ geo, const int32_t *__restrict__ stage,
     const int4 *__restrict__ units, const E *__restrict__ M, int P1,
     double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st) {
@@ -1272,7 +1272,7 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
 #pragma unroll
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   if (lane < npairs) {
-    const int slot = pairs[pair0 + lane].z;
+    const int slot = slots[pair0 + lane];
     const double4 g = geo[pair0 + lane];
     m2qbxl_add_geo<PQ, E>(alpha, make_double2(g.x, g.y), g.z, g.w, Ms + slot * P1, P1, lt);
   }
@@ -1614,7 +1614,7 @@ void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        std::max(sizeof(E) * (size_t)ctx->m2q_stage_rows * (ctx->params.p_fmm + 1),
                                 sizeof(double2) * kM2qBlock * 64);
     hipLaunchKernelGGL((k_m2qbxl_packed<PQ, E>), dim3(nw, nd), dim3(64), lds, s,
-                       d.m2q_wave + 2 * bk.m2q0, d.m2q_pair, d.m2q_geo, d.m2q_stage, d.m2q_unit,
+                       d.m2q_wave + 2 * bk.m2q0, d.m2q_slot, d.m2q_geo, d.m2q_stage, d.m2q_unit,
                        M, ctx->params.p_fmm + 1, d.anear, ctx->params.p_qbx + 1, S.box, S.row);
   }
   const int32_t n = (int32_t)(bk.far1 - bk.far0);
