@@ -466,3 +466,22 @@ def test_packed_list3_far_work(far_chunk):
     # items of one box's centers instead: no packed work
     q2, T2 = _build(g, p_qbx=12, p_fmm=30, far_chunk=far_chunk, far_pairs_per_lane=2)
     assert T2["stats"]["n_m2q_waves"] == T2["stats"]["n_m2q_pairs"] == 0
+
+
+def test_packed_list3_far_work_forest():
+    """The packed Stage 5b work of a ragged batch (one forest): every (center, List 3 far box)
+    pair of every geometry once, one row per (center, far chunk), and the packing rule's
+    wavefront count over the merged lists."""
+    from paper_1801_04070_amd import QBXFMM
+    geoms = gi.ragged_star_batch(n_geoms=4, seed=200)
+    q = QBXFMM(device=-1)
+    q.set_geometry_batch(geoms)
+    st = q.build(p_qbx=12, p_fmm=30)
+    T = {"ctr": q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)}
+    T.update(q.lists())
+    nc = T["ctr"][:, 1] - T["ctr"][:, 0]
+    W = np.diff(T["list3f"][0])
+    assert st["n_m2q_pairs"] == st["list3_far_pairs"] == (nc * W).sum() > 0
+    waves, units = _packed_far_waves(T)
+    assert st["n_m2q_units"] == units
+    assert st["n_m2q_waves"] == waves
