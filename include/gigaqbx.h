@@ -78,13 +78,17 @@ typedef struct {
   int near_dens_group;    /* densities per direct-interaction work item when an evaluation has
                              several (1, 2 or 4): the pair geometry is formed once per group;
                              0: 2                                                              */
+  double eps;             /* requested accuracy (Sec. 4.1 input (b)); used when p_fmm <= 0:
+                             the FMM error is of order (1/2)^(p_fmm + 1) (Theorem 1), so
+                             p_fmm = ceil(|log2 eps|), at most GQ_MAX_P_FMM. 0: unused       */
 } gq_params;
 
 #define GQ_MAX_P_QBX 20
 #define GQ_MAX_P_FMM 63
 
 /* Fill *p with the defaults: p_qbx 12, p_fmm 30, n_max 64, count_mode 0, t_f 0.9,
- * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1, work-item shapes 0 (defaults). */
+ * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1, work-item shapes 0 (defaults),
+ * eps 0. */
 gq_status gq_default_params(gq_params *p);
 
 /* Create a context on HIP device `device` (>= 0) using `hip_stream` (a hipStream_t, may be NULL for
@@ -145,7 +149,9 @@ gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int6
  * QBX disk; a center stays in a box when its disk does not fit the child's target confinement
  * region), sort particles into tree order, build Lists 1, 2, 3-close/far, 4-close/far, and upload
  * tree, lists and translation tables to the device. Synchronous. Invalid parameters give
- * GQ_EINVAL, orders above the compiled maxima GQ_EUNSUP.
+ * GQ_EINVAL, orders above the compiled maxima GQ_EUNSUP. With p_fmm <= 0 the FMM order is
+ * derived from params->eps (0 < eps < 1, else GQ_EINVAL) as described at gq_params.eps;
+ * gq_get_params then shows the order used.
  */
 gq_status gq_build(gq_ctx *ctx, const gq_params *params);
 
@@ -211,9 +217,18 @@ gq_status gq_get_params(gq_ctx *ctx, gq_params *out);
 gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
 
 /*
- * HIP graph of one evaluation. Switched off in this build: gq_graph_create returns GQ_EUNSUP
- * (and *graph = NULL); gq_graph_launch and gq_graph_destroy accept only handles from
- * gq_graph_create (NULL is ignored by destroy).
+ * HIP graph of one evaluation (the build-once / evaluate-many split of Sec. 4.6: the tree and lists
+ * are fixed, so the launches of an evaluation can be recorded once and replayed).
+ * gq_graph_create records gq_eval(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out) (the
+ * FMM path, any kind) into a graph without running it; gq_graph_launch replays it on the
+ * context's current stream, reading the densities at the recorded addresses and writing the
+ * recorded output. One density batch per graph: n_dens in 1..64 (1..32 for GQ_S_AND_D), else
+ * GQ_EUNSUP. Synchronous creation (it first sizes the workspace, then synchronises the
+ * context's streams); profiling must be off (GQ_ESTATE). The graph refers to the context's
+ * workspace: a later gq_eval with more densities, gq_build, gq_set_qbx_orders or gq_autotune
+ * replaces it, after which gq_graph_launch returns GQ_ESTATE. Replays and eager evaluations on
+ * one context share the workspace and must not overlap on the device (enqueue them on one
+ * stream). gq_graph_destroy accepts NULL.
  */
 typedef struct gq_graph gq_graph;
 gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
@@ -233,7 +248,10 @@ typedef struct {
   int64_t list4_far_sources;     /* (box, source) pairs formed into box locals            */
   int64_t near_sources;          /* sum over boxes owning centers of their direct sources  */
   int64_t n_local_boxes;         /* target-or-ancestor boxes (boxes with a local expansion) */
-  int64_t max_list2, max_list4, max_list4_close, max_list4_far;
+  int64_t max_list2, max_list4, max_list4_close, max_list4_far;  /* largest row of List 2, of
+                                    List 4 itself (Definition 7, before the close/far split),
+                                    of List 4 close and of List 4 far (Sec. 4.6 bounds them by
+                                    75, 21, 42 and 63)                                          */
   double root_lo[2];
   double root_side;
   double build_ms;               /* host time of the last gq_build                        */
@@ -247,6 +265,11 @@ typedef struct {
                                     packed across boxes (far_pairs_per_lane 1; else 0)   */
   int64_t n_m2q_pairs;           /* their pairs (list3_far_pairs when packed)             */
   int64_t n_m2q_units;           /* their rows: (center, chunk of its List 3 far boxes)   */
+  double m_c;                    /* M_C of Sec. 4.6.1: the mean over centers c of the number of
+                                    sources in the closed square of radius 8 r_c / t_f about c
+                                    (every source when t_f = 0); computed on the first
+                                    gq_get_stats after a build                                */
+  int64_t m_c_sum;               /* the sum behind m_c (N_C m_c)                            */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);
@@ -294,6 +317,15 @@ enum {
 };
 gq_status gq_set_profiling(gq_ctx *ctx, int enable);
 gq_status gq_get_stage_times(gq_ctx *ctx, double *ms, int64_t *count);
+
+/*
+ * Diagnostics: the device natural logarithm (GQ_MATH_LOG; x > 0 normal) and reciprocal
+ * (GQ_MATH_RCP; x finite, non-zero) that the direct-interaction (P2QBXL), P2L and M2QBXL kernels
+ * use, applied elementwise to n device doubles x, written to n device doubles out, enqueued on
+ * the context's stream. For testing their accuracy; other inputs give unspecified values.
+ */
+enum { GQ_MATH_LOG = 1, GQ_MATH_RCP = 2 };
+gq_status gq_device_math(gq_ctx *ctx, int fn, int64_t n, const double *x, double *out);
 
 /* Message describing the last failure on this context (or on creation, with ctx NULL). */
 const char *gq_last_error(gq_ctx *ctx);

@@ -152,7 +152,9 @@ class QBXFMM:
     def build(self, params: gq_params | None = None, **kw) -> dict:
         p = params if params is not None else default_params(**kw)
         self._check(self._L.gq_build(self._h, C.byref(p)))
-        self.params = p
+        got = gq_params()
+        self._check(self._L.gq_get_params(self._h, C.byref(got)))
+        self.params = got
         return self.stats()
 
     def stats(self) -> dict:
@@ -251,6 +253,15 @@ class QBXFMM:
                                             _ptr(d2), 0 if d2 is None else d2.stride(0),
                                             _ptr(out), out.stride(0), C.byref(h)))
         return EvalGraph(self, h, (d1, d2, out)), out
+
+    def device_math(self, fn: int, x):
+        """The library's device log (GQ_MATH_LOG) or reciprocal (GQ_MATH_RCP) of a float64 CUDA
+        tensor, elementwise (gq_device_math); returns a new tensor."""
+        import torch
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        self._check(self._L.gq_device_math(self._h, fn, x.numel(), _ptr(x), _ptr(out)))
+        return out
 
     def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
         """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or

@@ -12,6 +12,7 @@ GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D = 1, 2, 3, 4
 GQ_MEM_HOST, GQ_MEM_DEVICE = 0, 1
 GQ_FP64, GQ_MIXED_FP32 = 0, 1
 GQ_MAX_P_QBX, GQ_MAX_P_FMM = 20, 63
+GQ_MATH_LOG, GQ_MATH_RCP = 1, 2
 GQ_N_FEATURES = 8
 
 (GQ_TREE_BOX_LEVEL, GQ_TREE_BOX_PARENT, GQ_TREE_BOX_CHILD, GQ_TREE_BOX_IJ, GQ_TREE_BOX_SRC_RANGE,
@@ -28,7 +29,7 @@ class gq_params(C.Structure):
                 ("count_mode", C.c_int), ("t_f", C.c_double), ("w3far_min_sources", C.c_int),
                 ("precision", C.c_int), ("max_levels", C.c_int), ("overlap", C.c_int),
                 ("near_chunk", C.c_int), ("far_chunk", C.c_int), ("far_pairs_per_lane", C.c_int),
-                ("near_dens_group", C.c_int)]
+                ("near_dens_group", C.c_int), ("eps", C.c_double)]
 
 
 class gq_stats(C.Structure):
@@ -42,7 +43,8 @@ class gq_stats(C.Structure):
         ("n_point_targets", C.c_int64), ("n_l2l_sinks", C.c_int64),
         ("n_l2l_pairs", C.c_int64), ("n_moment_boxes", C.c_int64),
         ("n_moment_pairs", C.c_int64), ("n_moment_parts", C.c_int64),
-        ("n_m2q_waves", C.c_int64), ("n_m2q_pairs", C.c_int64), ("n_m2q_units", C.c_int64)]
+        ("n_m2q_waves", C.c_int64), ("n_m2q_pairs", C.c_int64), ("n_m2q_units", C.c_int64),
+        ("m_c", C.c_double), ("m_c_sum", C.c_int64)]
 
 
 GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",
@@ -54,7 +56,7 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
-            "gq_get_params", "gq_last_error"]
+            "gq_get_params", "gq_device_math", "gq_last_error"]
 
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
@@ -91,6 +93,7 @@ def load(path: str = LIB_PATH):
     L.gq_graph_destroy.argtypes = [vp]
     L.gq_autotune.argtypes = [vp, i32, dp, i64, i32, C.POINTER(C.c_double)]
     L.gq_get_params.argtypes = [vp, C.POINTER(gq_params)]
+    L.gq_device_math.argtypes = [vp, i32, i64, dp, dp]
     L.gq_last_error.argtypes = [vp]
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:

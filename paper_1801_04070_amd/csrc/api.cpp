@@ -883,6 +883,7 @@ gq_status gq_default_params(gq_params *p) {
   p->far_chunk = 0;
   p->far_pairs_per_lane = 1;
   p->near_dens_group = 0;
+  p->eps = 0.0;
   return GQ_OK;
 }
 
@@ -942,6 +943,9 @@ gq_status gq_destroy(gq_ctx *ctx) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_up) (void)hipEventDestroy(ctx->ev_up);
+    if (ctx->gev_fork) (void)hipEventDestroy(ctx->gev_fork);
+    if (ctx->gev_up) (void)hipEventDestroy(ctx->gev_up);
+    if (ctx->gev_join) (void)hipEventDestroy(ctx->gev_join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->main1) (void)hipStreamDestroy(ctx->main1);
     if (ctx->main2) (void)hipStreamDestroy(ctx->main2);
@@ -981,7 +985,13 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (!params) return fail(ctx, GQ_EINVAL, "null params");
   if (!ctx->have_geom) return fail(ctx, GQ_ESTATE, "gq_build before gq_set_geometry");
-  const gq_params &p = *params;
+  gq_params p = *params;
+  if (p.p_fmm <= 0) {
+    // Sec. 4.1: the FMM error is of order (1/2)^(p_fmm + 1), so p_fmm ~ |log2 eps|
+    if (!(p.eps > 0.0 && p.eps < 1.0))
+      return fail(ctx, GQ_EINVAL, "p_fmm <= 0 needs 0 < eps < 1 to derive the FMM order");
+    p.p_fmm = std::min(GQ_MAX_P_FMM, std::max(1, (int)std::ceil(-std::log2(p.eps) - 1e-9)));
+  }
   if (p.p_qbx < 0 || p.p_fmm < 1) return fail(ctx, GQ_EINVAL, "orders must satisfy p_qbx >= 0, p_fmm >= 1");
   if (p.p_fmm > GQ_MAX_P_FMM) return fail(ctx, GQ_EUNSUP, "p_fmm above GQ_MAX_P_FMM");
   if (!gq::pq_supported(p.p_qbx)) return fail(ctx, GQ_EUNSUP, "p_qbx has no compiled kernel in this build");
@@ -1028,6 +1038,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
     GQ_TRY(build_near_work(ctx));
   }
   ctx->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ctx->m_c_sum = -1;
   ctx->built = true;
   return GQ_OK;
 }
@@ -1052,11 +1063,67 @@ struct gq_graph {
 gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
                           const double *dens2, int64_t ld2, double *out, int64_t ld_out,
                           gq_graph **graph) {
-  (void)kind; (void)n_dens; (void)dens1; (void)ld1; (void)dens2; (void)ld2; (void)out; (void)ld_out;
-  if (graph) *graph = nullptr;
-  // Switched off: a capture whose forked stream forked again crashed the host process inside
-  // this call, and the cause is not established.
-  return fail(ctx, GQ_EUNSUP, "evaluation graph capture is disabled in this build");
+  if (!graph) return fail(ctx, GQ_EINVAL, "null graph output");
+  *graph = nullptr;
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
+  if (n_dens < 1) return fail(ctx, GQ_EINVAL, "a graph needs n_dens >= 1");
+  if (n_dens > (kind == GQ_S_AND_D ? gq::kMaxDensBatch / 2 : gq::kMaxDensBatch))
+    return fail(ctx, GQ_EUNSUP, "a graph captures one density batch (at most 64 densities, 32 for "
+                                "GQ_S_AND_D)");
+  if (ctx->profiling) return fail(ctx, GQ_ESTATE, "disable stage profiling before capturing a graph");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  // Everything the evaluation needs is allocated and created before the capture begins, so the
+  // captured calls are launches, event records and stream waits only: the workspace, a stream to
+  // capture on (the caller's may be the null stream, which cannot be captured) and fork/join
+  // events reserved for captures (the eager evaluations keep their own).
+  GQ_TRY(ensure_workspace(ctx, workspace_batch(kind, n_dens)));
+  if (!ctx->capture) GQ_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  for (hipEvent_t *e : {&ctx->gev_fork, &ctx->gev_up, &ctx->gev_join})
+    if (!*e) GQ_HIP(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
+  if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  GQ_HIP(ctx, hipStreamSynchronize(ctx->side));
+  const hipStream_t saved = ctx->stream;
+  const hipEvent_t ev[3] = {ctx->ev_fork, ctx->ev_up, ctx->ev_join};
+  ctx->stream = ctx->capture;
+  ctx->ev_fork = ctx->gev_fork;
+  ctx->ev_up = ctx->gev_up;
+  ctx->ev_join = ctx->gev_join;
+  hipGraph_t g = nullptr;
+  gq_status st = GQ_OK;
+  hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    // one density batch: one gq::run_eval, whose only fork is the side stream (joined back
+    // before the per-center stage)
+    st = launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, false);
+    // end the capture even after a failed launch, so the stream leaves capture mode
+    const hipError_t e2 = hipStreamEndCapture(ctx->capture, &g);
+    if (e2 != hipSuccess) e = e2;
+  }
+  ctx->stream = saved;
+  ctx->ev_fork = ev[0];
+  ctx->ev_up = ev[1];
+  ctx->ev_join = ev[2];
+  if (e != hipSuccess || st != GQ_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != GQ_OK ? st : fail(ctx, GQ_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  gq_graph *h = new (std::nothrow) gq_graph();
+  if (!h) {
+    (void)hipGraphDestroy(g);
+    return fail(ctx, GQ_ENOMEM, "graph handle");
+  }
+  h->ctx = ctx;
+  h->graph = g;
+  h->generation = ctx->generation;
+  e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete h;
+    return fail(ctx, GQ_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *graph = h;
+  return GQ_OK;
 }
 
 gq_status gq_graph_launch(gq_graph *graph) {
@@ -1120,7 +1187,12 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
     out->max_list4_close = std::max(out->max_list4_close, t.list4c.row_size(b));
     out->max_list4_far = std::max(out->max_list4_far, t.list4f.row_size(b));
   }
-  out->max_list4 = 0;
+  out->max_list4 = t.max_list4;
+  if (ctx->m_c_sum < 0)
+    ctx->m_c_sum = gq::sources_near_centers(t, ctx->src_xy.data(), ctx->ctr_xy.data(),
+                                            ctx->ctr_r.data(), ctx->nc_user, ctx->params.t_f);
+  out->m_c_sum = ctx->m_c_sum;
+  out->m_c = ctx->nc_user > 0 ? (double)ctx->m_c_sum / (double)ctx->nc_user : 0.0;
   out->root_lo[0] = t.lo[0]; out->root_lo[1] = t.lo[1]; out->root_side = t.side;
   out->build_ms = ctx->build_ms;
   return GQ_OK;
@@ -1314,6 +1386,18 @@ gq_status gq_get_stage_times(gq_ctx *ctx, double *ms, int64_t *count) {
   }
   ctx->prof.clear();
   return st;
+}
+
+gq_status gq_device_math(gq_ctx *ctx, int fn, int64_t n, const double *x, double *out) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context");
+  if (fn != GQ_MATH_LOG && fn != GQ_MATH_RCP) return fail(ctx, GQ_EINVAL, "unknown function");
+  if (n < 0 || n > (int64_t(1) << 38)) return fail(ctx, GQ_EINVAL, "n out of range");
+  if (n == 0) return GQ_OK;
+  if (!x || !out) return fail(ctx, GQ_EINVAL, "null array");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  GQ_HIP(ctx, gq::run_math(fn, n, x, out, ctx->stream));
+  return GQ_OK;
 }
 
 const char *gq_last_error(gq_ctx *ctx) {

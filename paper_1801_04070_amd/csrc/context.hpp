@@ -146,10 +146,12 @@ struct gq_ctx {
   std::vector<void *> ws_allocations;  // per-density workspace, sized for ws_batch densities
   int ws_batch = 0;
   double build_ms = 0;
+  int64_t m_c_sum = -1;              // N_C M_C (Sec. 4.6.1), computed on demand after a build
 
   // bumped whenever device buffers a captured graph refers to are freed or replaced
   uint64_t generation = 0;
   hipStream_t capture = nullptr;     // library stream used only to capture evaluation graphs
+  hipEvent_t gev_fork = nullptr, gev_up = nullptr, gev_join = nullptr;  // fork/join in captures
   // GQ_S_AND_D: one library stream per kind (both forked from and joined back to the caller's
   // stream), with hand-over events
   hipStream_t main1 = nullptr, main2 = nullptr;

@@ -18,12 +18,19 @@ namespace gq {
 
 namespace {
 
-// Natural log of a positive normal double by table lookup and a short series: x = M 2^(e-1) with
-// M in [1, 2); the top 7 bits of M pick j, c_j ~ 1/(1 + (j + 1/2)/128) and T_j = -log c_j (both
-// rounded to FP64 on the host, T_j from the rounded c_j), so log M = T_j + log1p(r) with
-// r = M c_j - 1 formed by one FMA, |r| <= 2^-8, and log1p(r) through r^7 (next term < 1e-20).
-// log 2 is split into a head with trailing zero bits and a tail. Absolute error about 1e-16.
+// Natural log of a positive normal double, table-driven in the manner of P. T. P. Tang, "Table-
+// driven implementation of the logarithm function in IEEE floating-point arithmetic" (ACM TOMS
+// 16(4), 1990): x = M 2^(e-1) with M in [1, 2); the top 7 bits of M pick j, c_j ~ 1/(1 + (j +
+// 1/2)/128) and T_j = -log c_j (both rounded to FP64 on the host in long double, T_j from the
+// rounded c_j), so log M = T_j + log1p(r) with r = M c_j - 1 formed by one FMA (exact),
+// |r| <= 2^-8, and log1p(r) by its Taylor series through r^7 (the next term is below 2^-64 r).
+// (e - 1) log 2 uses a two-part log 2: the head is log 2 rounded to a multiple of 2^-32 (32
+// significant bits, so (e - 1) times it is exact for any double exponent) and the tail the
+// remainder rounded to FP64; both were derived from a 60-digit value of log 2. Absolute error
+// about 1e-16 over the normal doubles (a GPU test sweeps the exponent range against numpy).
 constexpr int kLogTab = 128;
+constexpr double kLn2Head = 0x1.62e42ffp-1;                 // round(2^32 log 2) / 2^32
+constexpr double kLn2Tail = -0x1.718432a1b0e26p-35;          // log 2 - kLn2Head
 __device__ double2 g_log_tab[kLogTab];
 
 __device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ tab) {
@@ -38,7 +45,7 @@ __device__ __forceinline__ double log_tab(double x, const double2 *__restrict__ 
   p = fma(p, r, -0.5);
   const double l1 = fma(r * r, p, r);
   const double fe = (double)(e - 1);
-  return fma(fe, 6.93147180369123816490e-01, fma(fe, 1.90821492927058770002e-10, ct.y) + l1);
+  return fma(fe, kLn2Head, fma(fe, kLn2Tail, ct.y) + l1);
 }
 
 // The moments, M2L, P2L and the Stage 7 gather run on the caller's stream and form the critical
@@ -1477,6 +1484,15 @@ __global__ void __launch_bounds__(256) k_direct(
 }
 
 // ------------------------------------------------------------------------------------------
+// The device natural logarithm (log_tab) or reciprocal (rcp_nr) of the kernels above, elementwise,
+// so that their accuracy can be tested on their own.
+__global__ void k_math(int fn, int64_t n, const double *__restrict__ x, double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = fn == 1 ? log_tab(x[i], g_log_tab) : rcp_nr(x[i]);
+}
+
+// ------------------------------------------------------------------------------------------
 // Average the target slots into the caller's output row: value row y of tv goes to row y of out,
 // or for y >= n_first to row y - n_first of out2 (S and D rows of one evaluation in one launch).
 __global__ void k_finalize(int32_t nt, const int32_t *__restrict__ tctr, const double *__restrict__ tv,
@@ -1813,6 +1829,12 @@ hipError_t upload_log_table() {
     tab[j] = make_double2(c, (double)(-std::log((long double)c)));
   }
   return hipMemcpyToSymbol(HIP_SYMBOL(g_log_tab), tab, sizeof(tab), 0, hipMemcpyHostToDevice);
+}
+
+hipError_t run_math(int fn, int64_t n, const double *x, double *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_math, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, fn, n, x, out);
+  return hipGetLastError();
 }
 
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,

@@ -25,6 +25,9 @@ constexpr int kMaxDensBatch = 64;
 // once per context, with its device current, before any evaluation.
 hipError_t upload_log_table();
 
+// Elementwise device log (fn 1) or reciprocal (fn 2) of n values on stream s.
+hipError_t run_math(int fn, int64_t n, const double *x, double *out, hipStream_t s);
+
 // nd densities (rows of d1/d2 with strides ld1/ld2): gather strengths, run the FMM stages (or
 // direct QBX), write nd output rows of n_tgt values with stride ld_out. Kind 4 (S and D of the
 // same densities, FMM only, 2 nd workspace slots) writes the S rows to out and the D rows to

@@ -15,8 +15,10 @@
 #include "tree.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <thread>
 #include <unordered_map>
 
 namespace gq {
@@ -306,6 +308,7 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
       if (tcr_sep_box(b, d)) Xf[b].push_back(d);
       else Xc[b].push_back(d);
     };
+    t.max_list4 = std::max<int64_t>(t.max_list4, (int64_t)X.size());
     for (int32_t d : X) place4(d);
     if (pb >= 0)
       for (int32_t d : Xc[pb]) place4(d);
@@ -402,6 +405,64 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
     t.near_row[b + 1] = (int64_t)t.near_lo.size();
   }
   return "";
+}
+
+int64_t sources_near_centers(const Tree &t, const double *sxy, const double *cxy, const double *cr,
+                             int64_t n_user, double t_f) {
+  const int64_t nb = t.n_boxes(), nc = (int64_t)t.ctr_order.size();
+  auto half_of = [&](int64_t b) {
+    const double s = t.level_side_table.empty() ? std::ldexp(t.side, -t.level[b])
+                                                : t.level_side_table[t.level[b]];
+    return 0.5 * s;
+  };
+  std::atomic<int64_t> next{0}, total{0};
+  auto work = [&]() {
+    std::vector<int32_t> stk;
+    int64_t sum = 0;
+    for (int64_t k0; (k0 = next.fetch_add(1024)) < nc;) {
+      for (int64_t k = k0; k < std::min<int64_t>(nc, k0 + 1024); ++k) {
+        const int64_t c = t.ctr_order[k];
+        if (c >= n_user) continue;
+        int32_t root = t.ctr_box[k];
+        while (t.parent[root] >= 0) root = t.parent[root];
+        if (!(t_f > 0.0)) {
+          sum += t.n_src_subtree(root);
+          continue;
+        }
+        const double R = 8.0 * cr[c] / t_f, x = cxy[2 * c], y = cxy[2 * c + 1];
+        stk.assign(1, root);
+        while (!stk.empty()) {
+          const int32_t b = stk.back();
+          stk.pop_back();
+          if (t.src_end[b] <= t.src_begin[b]) continue;
+          const double h = half_of(b);
+          const double dx = std::fabs(t.cx[b] - x), dy = std::fabs(t.cy[b] - y);
+          if (dx - h > R || dy - h > R) continue;             // square and box disjoint
+          if (dx + h <= R && dy + h <= R) {                      // box inside the square
+            sum += t.n_src_subtree(b);
+            continue;
+          }
+          if (t.is_leaf(b)) {
+            for (int64_t i = t.src_begin[b]; i < t.src_end[b]; ++i) {
+              const int64_t s = t.src_order[i];
+              sum += std::max(std::fabs(sxy[2 * s] - x), std::fabs(sxy[2 * s + 1] - y)) <= R;
+            }
+            continue;
+          }
+          for (int q = 0; q < 4; ++q)
+            if (t.child[4 * b + q] >= 0) stk.push_back(t.child[4 * b + q]);
+        }
+      }
+    }
+    total += sum;
+  };
+  (void)nb;
+  const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int i = 1; i < nthr; ++i) pool.emplace_back(work);
+  work();
+  for (auto &th : pool) th.join();
+  return total.load();
 }
 
 void merge_forest(const std::vector<Tree> &trees, const std::vector<int64_t> &src_base,
@@ -507,6 +568,7 @@ void merge_forest(const std::vector<Tree> &trees, const std::vector<int64_t> &sr
     f.n_leaves += t.n_leaves; f.n_target_boxes += t.n_target_boxes; f.n_suspended += t.n_suspended;
     f.near_pairs += t.near_pairs; f.list3f_pairs += t.list3f_pairs;
     f.list4f_sources += t.list4f_sources; f.near_sources += t.near_sources;
+    f.max_list4 = std::max(f.max_list4, t.max_list4);
     f.n_local_boxes += t.n_local_boxes;
   }
 }

@@ -73,6 +73,7 @@ struct Tree {
   int64_t n_leaves = 0, n_target_boxes = 0, n_suspended = 0;
   int64_t near_pairs = 0, list3f_pairs = 0, list4f_sources = 0, near_sources = 0;
   int64_t n_local_boxes = 0;
+  int64_t max_list4 = 0;                        // largest List 4 (Definition 7) of any box
 
   int64_t n_boxes() const { return (int64_t)level.size(); }
   bool is_leaf(int64_t b) const {
@@ -86,6 +87,13 @@ struct Tree {
 // else an error message.
 std::string build_tree(Tree &t, int64_t ns, const double *src_xy, int64_t nc, const double *ctr_xy,
                        const double *ctr_r, const TreeParams &p);
+
+// Sum over the centers c with caller index < n_user of the number of sources y with
+// |y - c|_inf <= 8 r_c / t_f (every source of c's own tree when t_f = 0): N_C M_C of Sec. 4.6.1.
+// sxy, cxy, cr are in caller order; the square is answered by a walk down c's own tree that adds
+// whole subtrees inside it and tests sources only in leaves that straddle its edge.
+int64_t sources_near_centers(const Tree &t, const double *sxy, const double *cxy, const double *cr,
+                             int64_t n_user, double t_f);
 
 // Merge independent trees into one forest. Tree k's sources are the caller's sources
 // src_base[k] + (its local indices); its centers map through ctr_global[k] (local -> caller

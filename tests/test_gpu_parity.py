@@ -376,12 +376,13 @@ def test_point_targets_at_leaf_centers(kind):
     assert _rel(gpu[:g.n_tgt], oracle.qbx_eval(g, kind, mu, None, p_qbx=12)) < 1e-10
 
 
-@pytest.mark.skip(reason="graph capture is switched off: a capture whose forked library stream "
-                         "forked again crashed the host process, cause not established")
-@pytest.mark.parametrize("kind", [1, 3])
+@pytest.mark.parametrize("kind", [1, 3, 4])
 def test_graph_replays_match_eager(c1, kind):
     """A captured evaluation replayed several times, with other eager evaluations (sharing the
-    workspace) and host synchronisations between replays, reproduces the eager result exactly."""
+    workspace) and host synchronisations between replays, reproduces the eager result exactly;
+    the graph goes stale when the buffers change, and a capture of more than one density batch
+    is refused."""
+    from paper_1801_04070_amd import GQError, _lib
     mu, mu2 = _densities(c1, 4)
     q, _ = _ctx(c1, p_qbx=8, p_fmm=20)
     d1 = _dev(np.stack([mu, 2 * mu]))
@@ -399,10 +400,14 @@ def test_graph_replays_match_eager(c1, kind):
         torch.cuda.synchronize()
     # the graph goes stale when the buffers change
     q.set_qbx_orders(np.full(c1.n_ctr, 4, np.int32))
-    from paper_1801_04070_amd import GQError
-    with pytest.raises(GQError):
+    with pytest.raises(GQError) as e:
         g.launch()
+    assert e.value.status == _lib.GQ_ESTATE
     g.close()
+    big = _dev(np.tile(mu, (65, 1)))
+    with pytest.raises(GQError) as e:
+        q.graph(1, big)
+    assert e.value.status == _lib.GQ_EUNSUP
 
 
 def test_ragged_batch_matches_separate_contexts():
@@ -460,8 +465,8 @@ def test_s_and_d_concurrent_matches_separate(c1):
     """GQ_S_AND_D (S and D of the same densities through one expansion pipeline over two
     workspace halves) against separate S and D evaluations: S rows exactly; D rows exactly for a
     batch (per-kind direct interactions) and to rounding for one density (the fused direct pass
-    takes d z^-(m+1) from the shared powers of 1/z); the direct path exactly. Graph capture of it
-    is refused with an error."""
+    takes d z^-(m+1) from the shared powers of 1/z); the direct path exactly; a captured graph of
+    it replays to the eager rows."""
     from paper_1801_04070_amd import GQ_S_AND_D
     g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
     q, _ = _ctx(g, p_qbx=12, p_fmm=30)
@@ -480,10 +485,12 @@ def test_s_and_d_concurrent_matches_separate(c1):
     bd = q.eval(GQ_S_AND_D, dens[:2], direct=True).cpu().numpy()
     assert np.array_equal(bd[:2], q.eval(1, dens[:2], direct=True).cpu().numpy())
     assert np.array_equal(bd[2:], q.eval(2, dens[:2], direct=True).cpu().numpy())
-    # graph capture is switched off in this build: refused with an error
-    from paper_1801_04070_amd import GQError
-    with pytest.raises(GQError):
-        q.graph(GQ_S_AND_D, dens[1])
+    # a captured GQ_S_AND_D evaluation replays to the eager rows
+    gr, out = q.graph(GQ_S_AND_D, dens[1])
+    gr.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), q.eval(GQ_S_AND_D, dens[1]).cpu().numpy())
+    gr.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

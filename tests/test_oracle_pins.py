@@ -268,3 +268,28 @@ def test_compensated_sum_is_order_independent():
     gp.src_xy, gp.src_nrm, gp.src_w = g.src_xy[perm], g.src_nrm[perm], g.src_w[perm]
     u2 = oracle.qbx_eval(gp, oracle.S, mu[perm], p_qbx=8)
     assert np.abs(u1 - u2).max() <= 4e-16 * np.abs(u1).max() * 8
+
+
+def test_rough_m2l_estimate_order8():
+    """Sec. 2.4, eq. (rough-m2l-error): for boxes of side 1 one box apart, the furthest target of
+    the target box lies sqrt(2)/2 from its center and the closest source at least (4 - sqrt 2)/2,
+    so an order-8 local expansion errs by about (sqrt 2/(4 - sqrt 2))^9 = 4.4e-3. A unit charge on
+    the source box's circumscribed circle, nearest the target box, and a target at the corner
+    distance on the same ray are the worst case: the error of the oracle's order-8 local
+    expansion there (in units of log|x - y|) is the log series tail sum_{n>8} w^n/n with w the
+    distance ratio, below the paper's estimate and within a factor of ten of it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")) as f:
+        est = json.load(f)["rough_m2l_estimate_order8"]["value"]
+    s2 = math.sqrt(2.0)
+    w = s2 / (4 - s2)
+    assert abs(w ** 9 - est) < 5e-5  # the paper prints two digits
+    g = _single_source_geom(np.array([(4 - s2) / 2, 0.0]), np.array([1.0, 0.0]))
+    x = np.array([[s2 / 2, 0.0]])
+    b = oracle.local(g, oracle.S, np.ones(1), None, (0.0, 0.0), 8)
+    err = abs(oracle.eval_local(b, (0.0, 0.0), x)[0]
+              - oracle.point_potential(g, oracle.S, np.ones(1), tgt_xy=x)[0]) * 2 * math.pi
+    tail = -math.log1p(-w) - sum(w ** n / n for n in range(1, 9))
+    assert err == pytest.approx(tail, rel=1e-9)
+    assert est / 10 < err < est

@@ -485,3 +485,135 @@ def test_packed_list3_far_work_forest():
     waves, units = _packed_far_waves(T)
     assert st["n_m2q_units"] == units
     assert st["n_m2q_waves"] == waves
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _center_boxes(T):
+    """Owning box of every tree-order center position (centers are numbered in pre-order)."""
+    cbox = np.empty(T["ctr"][:, 1].max(), np.int64)
+    for b, (c0, c1) in enumerate(T["ctr"]):
+        cbox[c0:c1] = b
+    return cbox
+
+
+def _furthest_target(T, cxy, cr, cbox):
+    """Per box b: max over the centers c owned by b or a descendant of |c - c_b| + r_c."""
+    ft = np.zeros(len(T["level"]))
+    b = cbox.copy()
+    while (b >= 0).any():
+        ok = b >= 0
+        np.maximum.at(ft, b[ok], np.hypot(*(cxy[ok] - T["center"][b[ok]]).T) + cr[ok])
+        nxt = b.copy()
+        nxt[ok] = T["parent"][b[ok]]
+        b = nxt
+    return ft
+
+
+@pytest.fixture(scope="module")
+def c2_tree():
+    g = gi.config_geometry("c2")
+    q, T = _build(g, p_qbx=12, p_fmm=30)
+    return g, T
+
+
+def test_list_bounds_on_full_size_tree(c2_tree):
+    """The Sec. 4.6 list-size bounds on the 131072-source tree: |List 2| <= 75, |List 4| <= 21,
+    |List 4 close| <= 42, |List 4 far| <= 63 per box, and at most 64 List 3 far boxes per
+    center (Lemma for Stage 5)."""
+    g, T = c2_tree
+    const = _golden()
+    st = T["stats"]
+    assert st["max_list2"] <= const["max_list2"]["value"]
+    assert st["max_list4"] <= const["max_list4"]["value"]
+    assert st["max_list4_close"] <= const["max_list4_close"]["value"]
+    assert st["max_list4_far"] <= const["max_list4_far"]["value"]
+    for name, key in (("list2", "max_list2"), ("list4c", "max_list4_close"),
+                      ("list4f", "max_list4_far")):
+        assert np.diff(T[name][0]).max() == st[key]
+    owns = (T["ctr"][:, 1] - T["ctr"][:, 0]) > 0
+    assert np.diff(T["list3f"][0])[owns].max() <= const["list3_far_per_center"]["value"]
+
+
+def test_convergence_factors_on_full_size_tree(c2_tree):
+    """Theorem 1's convergence factors as the geometric ratios of the separation figures, over
+    every list entry of the 131072-source tree:
+      List 2 (b, d): furthest target of b over closest point of d's circumscribed disk, at most
+        alpha = (t_f + sqrt 2)/(6 - sqrt 2) (0.5046 at t_f = 0.9);
+      List 3 far (c, d): radius of d's circumscribed disk over the distance from c_d to c's QBX
+        disk, at most sqrt(2)/3;
+      List 4 far (b, d): furthest target of b over the closest source of d, at most sqrt(2)/3.
+    "Furthest target" is the largest |c - c_b| + r_c over the QBX centers below b."""
+    g, T = c2_tree
+    const = _golden()
+    alpha = const["list2_convergence_factor_tf09"]["value"]
+    far = const["list34_far_convergence_factor"]["value"]
+    assert abs(alpha - (0.9 + 2 ** 0.5) / (6 - 2 ** 0.5)) < 1e-6
+    cbox = _center_boxes(T)
+    cxy, cr = g.ctr_xy[T["ctr_order"]], g.ctr_r[T["ctr_order"]]
+    ft = _furthest_target(T, cxy, cr, cbox)
+    nb = len(T["level"])
+    cen, half = T["center"], T["half"]
+
+    def pairs(name):
+        st, ix = T[name]
+        return np.repeat(np.arange(nb), np.diff(st)), ix
+
+    b, d = pairs("list2")
+    r2 = ft[b] / (np.hypot(*(cen[b] - cen[d]).T) - np.sqrt(2) * half[d])
+    assert r2.max() <= alpha + 1e-9 and r2.max() > 0.45
+    st3 = T["list3f"][0]
+    n3 = np.diff(st3)[cbox]
+    ci = np.repeat(np.arange(len(cbox)), n3)
+    d3 = np.concatenate([T["list3f"][1][st3[x]:st3[x + 1]] for x in cbox])
+    r3 = np.sqrt(2) * half[d3] / (np.hypot(*(cxy[ci] - cen[d3]).T) - cr[ci])
+    assert len(r3) > 0 and r3.max() <= far + 1e-9
+    b, d = pairs("list4f")
+    ns = T["src"][d, 1] - T["src"][d, 0]
+    pid = np.repeat(np.arange(len(b)), ns)
+    src = np.concatenate([np.arange(T["src"][x, 0], T["src"][x, 1]) for x in d])
+    y = g.src_xy[T["src_order"][src]]
+    mind = np.full(len(b), np.inf)
+    np.minimum.at(mind, pid, np.hypot(*(y - cen[b[pid]]).T))
+    r4 = ft[b] / mind
+    assert len(r4) > 0 and r4.max() <= far + 1e-9
+
+
+@pytest.mark.parametrize("t_f", [0.9, 0.5, 0.0])
+def test_mean_sources_near_centers_brute_force(t_f):
+    """M_C (Sec. 4.6.1): the mean number of sources in the closed square of radius 8 r_c / t_f
+    about each center, from the library's tree walk, against counting every (center, source)
+    pair; t_f = 0 counts every source."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=40, seed=4, box=8.0)
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(g)
+    st = q.build(p_qbx=8, p_fmm=10, t_f=t_f)
+    total = 0
+    for c in range(g.n_ctr):
+        if t_f == 0.0:
+            total += g.n_src
+        else:
+            total += int((np.abs(g.src_xy - g.ctr_xy[c]).max(1) <= 8 * g.ctr_r[c] / t_f).sum())
+    assert st["m_c_sum"] == total
+    assert st["m_c"] == pytest.approx(total / g.n_ctr, rel=1e-15)
+
+
+def test_fmm_order_from_accuracy():
+    """Sec. 4.1: with p_fmm <= 0 the FMM order comes from the requested accuracy,
+    p_fmm = ceil(|log2 eps|); eps outside (0, 1) is rejected."""
+    from paper_1801_04070_amd import GQError
+    g = gi.starfish_c1()
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(g)
+    for eps, p in ((0.5, 1), (1e-6, 20), (1e-10, 34), (2.0 ** -30, 30), (1e-30, 63)):
+        q.build(p_qbx=8, p_fmm=0, eps=eps)
+        assert q.params.p_fmm == p, (eps, q.params.p_fmm)
+    q.build(p_qbx=8, p_fmm=15, eps=1e-10)
+    assert q.params.p_fmm == 15
+    for bad in (0.0, 1.0, -1e-3):
+        with pytest.raises(GQError) as e:
+            q.build(p_qbx=8, p_fmm=0, eps=bad)
+        assert e.value.status == _lib.GQ_EINVAL
