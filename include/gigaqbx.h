@@ -190,6 +190,24 @@ gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
                          int64_t ld_out);
 
 /*
+ * gq_eval without any device allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same contract and results as
+ * gq_eval (the same kernels in the same order; bitwise equal outputs), but the per-density
+ * workspace (strengths, box expansions, center rows, target slots) lives in a fixed scratch
+ * array of 256 MiB in device memory that the library holds on each device it runs on until the
+ * process ends (its address is taken when the first context is created on that device). An
+ * evaluation whose workspace for one density batch exceeds it (about 100 MB per density and kind
+ * for 131072 sources at p_fmm 30, p_qbx 12) gives GQ_EINVAL and launches nothing; stage profiling
+ * must be off (GQ_ESTATE). The call allocates no device or host memory. Every call on a device
+ * shares that device's scratch, so calls that can overlap on one device (on different streams or
+ * from different threads, from any context) race and must be ordered by the caller; the scratch
+ * keeps the last call's contents, none of which a later call reads.
+ */
+gq_status gq_eval_noalloc(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
+                          int64_t ld1, const double *dens2, int64_t ld2, double *out,
+                          int64_t ld_out);
+
+/*
  * Per-center QBX orders (the truncation order p of eq. (qbx) may differ between centers; Sec. 4.1
  * chooses it from the truncation error, which depends on the local geometry). orders[c] (n_ctr
  * int32, caller order, host or device memory per mem; NULL restores the uniform p_qbx) must lie in

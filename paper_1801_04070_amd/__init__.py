@@ -263,10 +263,12 @@ class QBXFMM:
         self._check(self._L.gq_device_math(self._h, fn, x.numel(), _ptr(x), _ptr(out)))
         return out
 
-    def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False):
+    def eval(self, kind: int, dens1, dens2=None, out=None, direct: bool = False,
+             noalloc: bool = False):
         """Evaluate on the device. dens1/dens2: torch float64 CUDA tensors (n_src,) or
         (n_dens, n_src); returns a tensor (n_tgt,) or (n_dens, n_tgt); for GQ_S_AND_D
-        (2 n_dens, n_tgt), the S rows first."""
+        (2 n_dens, n_tgt), the S rows first. direct: gq_eval_direct; noalloc: gq_eval_noalloc
+        (pass ``out`` as well to keep the call free of allocations)."""
         import torch
         squeeze = dens1.dim() == 1
 
@@ -281,7 +283,8 @@ class QBXFMM:
         if out is None:
             rows = n_dens * (2 if kind == GQ_S_AND_D else 1)
             out = torch.empty((rows, self.n_tgt), dtype=torch.float64, device=d1.device)
-        fn = self._L.gq_eval_direct if direct else self._L.gq_eval
+        fn = (self._L.gq_eval_direct if direct else
+              self._L.gq_eval_noalloc if noalloc else self._L.gq_eval)
         self._check(fn(self._h, kind, n_dens, _ptr(d1), d1.stride(0), _ptr(d2),
                        0 if d2 is None else d2.stride(0), _ptr(out), out.stride(0)))
         return out[0] if squeeze and kind != GQ_S_AND_D else out

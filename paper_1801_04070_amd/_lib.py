@@ -56,7 +56,7 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
-            "gq_get_params", "gq_device_math", "gq_last_error"]
+            "gq_get_params", "gq_device_math", "gq_eval_noalloc", "gq_last_error"]
 
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
     L.gq_build.argtypes = [vp, C.POINTER(gq_params)]
     L.gq_eval.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64]
     L.gq_eval_direct.argtypes = L.gq_eval.argtypes
+    L.gq_eval_noalloc.argtypes = L.gq_eval.argtypes
     L.gq_get_stats.argtypes = [vp, C.POINTER(gq_stats)]
     L.gq_get_tree_array.argtypes = [vp, i32, vp, C.POINTER(C.c_int64)]
     L.gq_set_qbx_orders.argtypes = [vp, i32, vp]

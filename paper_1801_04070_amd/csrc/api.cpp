@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -590,6 +591,68 @@ gq_status ensure_workspace(gq_ctx *ctx, int nd) {
   return GQ_OK;
 }
 
+// ---- scratch of the allocation-free evaluation (gq_eval_noalloc) ----
+// A file-scope device array: every GPU the library runs on holds its own copy, from the first
+// use of this code object on that device until the process ends. In host code the name
+// `scratch` is only a host-side stand-in; kernels get the device address of each GPU's copy,
+// taken once per device with hipGetSymbolAddress when a context is created there.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current: the address of its copy of `scratch`.
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+// Bytes of per-density workspace (strengths, box expansions, center rows, target slots) for
+// `slots` workspace slots, each buffer rounded up to 256 bytes.
+size_t workspace_bytes(const gq_ctx *ctx, int slots) {
+  const size_t n = (size_t)slots, P1 = ctx->params.p_fmm + 1, nb = ctx->tree.n_boxes();
+  auto r = [](size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; };
+  return r(n * ctx->ns * sizeof(double)) + r(n * ctx->ns * sizeof(double2)) +
+         3 * r(n * nb * P1 * sizeof(double2)) +
+         r(n * (size_t)std::max<int64_t>(ctx->n_p2m_parts, 1) * 2 * P1 * sizeof(double2)) +
+         r(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1) *
+           sizeof(double2)) +
+         r(n * 2 * ctx->nt * sizeof(double));
+}
+
+// Point the context's workspace at `base` (workspace_bytes(ctx, slots) bytes, 256-aligned), in
+// the order and sizes of workspace_bytes.
+void carve_workspace(gq_ctx *ctx, int slots, unsigned char *base) {
+  const size_t n = (size_t)slots, P1 = ctx->params.p_fmm + 1, nb = ctx->tree.n_boxes();
+  auto r = [](size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; };
+  auto take = [&](size_t bytes) {
+    unsigned char *p = base;
+    base += r(bytes);
+    return p;
+  };
+  auto &d = ctx->d;
+  d.sq = reinterpret_cast<double *>(take(n * ctx->ns * sizeof(double)));
+  d.sdip = reinterpret_cast<double2 *>(take(n * ctx->ns * sizeof(double2)));
+  d.M = reinterpret_cast<double2 *>(take(n * nb * P1 * sizeof(double2)));
+  d.L = reinterpret_cast<double2 *>(take(n * nb * P1 * sizeof(double2)));
+  d.Lf = reinterpret_cast<double2 *>(take(n * nb * P1 * sizeof(double2)));
+  d.Mp = reinterpret_cast<double2 *>(
+      take(n * (size_t)std::max<int64_t>(ctx->n_p2m_parts, 1) * 2 * P1 * sizeof(double2)));
+  d.anear = reinterpret_cast<double2 *>(
+      take(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1) *
+           sizeof(double2)));
+  d.tv = reinterpret_cast<double *>(take(n * 2 * ctx->nt * sizeof(double)));
+}
+
 bool finite_all(const std::vector<double> &v) {
   for (double x : v)
     if (!std::isfinite(x)) return false;
@@ -912,10 +975,16 @@ gq_status gq_create(gq_ctx **out, int device, void *hip_stream) {
       gq_destroy(ctx);
       return fail(nullptr, GQ_EHIP, "stream/event creation failed");
     }
-    const hipError_t e = gq::upload_log_table();
+    hipError_t e = gq::upload_log_table();
     if (e != hipSuccess) {
       gq_destroy(ctx);
       return fail(nullptr, GQ_EHIP, std::string("log table upload: ") + hipGetErrorString(e));
+    }
+    e = scratch_init(device);
+    if (e != hipSuccess) {
+      gq_destroy(ctx);
+      return fail(nullptr, GQ_EHIP, std::string("scratch address (hipGetSymbolAddress): ") +
+                                        hipGetErrorString(e));
     }
   }
   gq_default_params(&ctx->params);
@@ -1051,6 +1120,27 @@ gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, in
 gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
                          const double *dens2, int64_t ld2, double *out, int64_t ld_out) {
   return eval_common(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, true);
+}
+
+gq_status gq_eval_noalloc(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, int64_t ld1,
+                          const double *dens2, int64_t ld2, double *out, int64_t ld_out) {
+  GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
+  if (n_dens == 0) return GQ_OK;
+  if (ctx->profiling) return fail(ctx, GQ_ESTATE, "gq_eval_noalloc runs with stage profiling off");
+  if (ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device])
+    return fail(ctx, GQ_ESTATE, "no scratch address for this device");
+  const int slots = workspace_batch(kind, n_dens);
+  const size_t need = workspace_bytes(ctx, slots);
+  if (need > kScratchBytes)
+    return fail(ctx, GQ_EINVAL, "gq_eval_noalloc: this evaluation needs " + std::to_string(need) +
+                                    " bytes of workspace, more than the " +
+                                    std::to_string(kScratchBytes) + "-byte scratch");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  const gq::DevBuffers saved = ctx->d;
+  carve_workspace(ctx, slots, static_cast<unsigned char *>(g_scratch_ptr[ctx->device]));
+  const gq_status st = launch_batches(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out, false);
+  ctx->d = saved;
+  return st;
 }
 
 struct gq_graph {
