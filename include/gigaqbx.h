@@ -240,7 +240,7 @@ gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
  * gq_graph_create records gq_eval(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out) (the
  * FMM path, any kind) into a graph without running it; gq_graph_launch replays it on the
  * context's current stream, reading the densities at the recorded addresses and writing the
- * recorded output. One density batch per graph: n_dens in 1..64 (1..32 for GQ_S_AND_D), else
+ * recorded output. One density batch per graph: n_dens in 1..128 (1..64 for GQ_S_AND_D), else
  * GQ_EUNSUP. Synchronous creation (it first sizes the workspace, then synchronises the
  * context's streams); profiling must be off (GQ_ESTATE). The graph refers to the context's
  * workspace: a later gq_eval with more densities, gq_build, gq_set_qbx_orders or gq_autotune

@@ -155,6 +155,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   ctx->nw_allocations.clear();
   ctx->generation++;
   std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
+  std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
   std::vector<double> qgeo;
   std::vector<double> lside = t.level_side_table;
@@ -233,6 +234,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     gq::OrderBucket bk;
     bk.pq = pq;
     bk.near0 = (int64_t)items.size() / 8;
+    bk.nmf0 = (int64_t)mitems.size() / 8;
     bk.far0 = (int64_t)fitems.size() / 8;
     bk.m2q0 = (int64_t)qwave.size() / 8;
     bk.ctr0 = (int64_t)clist.size();
@@ -245,6 +247,12 @@ gq_status build_near_work(gq_ctx *ctx) {
         const int64_t c0 = j * near_chunk, clen = std::min<int64_t>(near_chunk, len - c0);
         emit_near(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
                   pick_slices(nc, clen, 10.0 * pq));
+        for (int64_t cb = 0; cb < nc; cb += 4) {
+          const int32_t it[8] = {(int32_t)(box_src_off[b] + c0), (int32_t)clen,
+                                 (int32_t)(t.ctr_begin[b] + cb), (int32_t)(base[b] + j * nc + cb),
+                                 (int32_t)std::min<int64_t>(4, nc - cb), 0, 0, 0};
+          mitems.insert(mitems.end(), it, it + 8);
+        }
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
       for (int64_t j = 0; j * far_chunk < wlen; ++j) {
@@ -283,6 +291,7 @@ gq_status build_near_work(gq_ctx *ctx) {
       for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) clist.push_back((int32_t)c);
     }
     bk.near1 = (int64_t)items.size() / 8;
+    bk.nmf1 = (int64_t)mitems.size() / 8;
     close_wave();
     bk.far1 = (int64_t)fitems.size() / 8;
     bk.m2q1 = (int64_t)qwave.size() / 8;
@@ -317,6 +326,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   gq_status st = GQ_OK;
   if (st == GQ_OK) st = upload(ctx, d.near_src, src.data(), src.size());
   if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.near_mitems, mitems.data(), mitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_wave, qwave.data(), qwave.size() / 4);
   std::vector<int32_t> qslot(qpair.size() / 4);
@@ -1159,8 +1169,8 @@ gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *d
   GQ_TRY(check_eval_args(ctx, kind, n_dens, dens1, ld1, dens2, ld2, out, ld_out));
   if (n_dens < 1) return fail(ctx, GQ_EINVAL, "a graph needs n_dens >= 1");
   if (n_dens > (kind == GQ_S_AND_D ? gq::kMaxDensBatch / 2 : gq::kMaxDensBatch))
-    return fail(ctx, GQ_EUNSUP, "a graph captures one density batch (at most 64 densities, 32 for "
-                                "GQ_S_AND_D)");
+    return fail(ctx, GQ_EUNSUP, "a graph captures one density batch (at most 128 densities, 64 "
+                                "for GQ_S_AND_D)");
   if (ctx->profiling) return fail(ctx, GQ_ESTATE, "disable stage profiling before capturing a graph");
   GQ_HIP(ctx, hipSetDevice(ctx->device));
   // Everything the evaluation needs is allocated and created before the capture begins, so the

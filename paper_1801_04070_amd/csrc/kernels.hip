@@ -423,6 +423,260 @@ __global__ void __launch_bounds__(64) k_m2l_mb(
 }
 
 // ------------------------------------------------------------------------------------------
+// M2L (Stage 4) and the Stage 7 gather over many workspace slots (a density batch, S and D): the
+// pair-dependent factors are diagonal, so every pair is one small GEMM whose columns are the
+// slots. A wavefront takes 8 slots (16 real columns: re/im of each), the fixed matrix T is the
+// A operand held in registers, and the pair's input rows scaled by the pre-factors f_k are the
+// B operand; the products, scaled by the post-factors g_m, accumulate in registers over the pairs
+// of a target box (all columns belong to the same pair), and a box's rows are written once, when
+// its last pair is done. A work-group takes 8 NW slots (NW wavefronts) of one run of whole boxes
+// of the flat pair lists that k_m2l_mb and k_l2l_gather walk.
+//   M2L:    f_k = o^-k, g_m = o^-m, T = B (the List 2 offset tables), plus a_0 log|s o| in beta_0;
+//   gather: f_k = t^k,  g_m = u^-m, T = C(k, m); a box's own local is added when it is written.
+// FP64 rows 16 rt + g + 4 v are the orders 4 (4 rt + v) + g, the orders 4 ks + g of the lane's
+// k-steps, so one set of per-lane factors serves both sides; FP32 rows (16 rt + 4 g + v) take
+// their post-factors separately. Arithmetic of the products in the expansion precision, of the
+// post-scaling and the sums in FP64.
+template <typename R>
+__device__ __forceinline__ double slot_post(double y, int comp, double2 gm) {
+  const double yo = lane_xor1(y);
+  const double yr = comp ? yo : y, yi = comp ? y : yo;
+  return comp ? fma(gm.x, yi, gm.y * yr) : fma(gm.x, yr, -(gm.y * yi));
+}
+
+template <int RT, typename E>
+__global__ void __launch_bounds__(256) k_m2l_slots(
+    const int2 *__restrict__ items, const int4 *__restrict__ prs,
+    const double *__restrict__ plog, const E *__restrict__ M,
+    const typename Scalar<E>::T *__restrict__ Bt, const E *__restrict__ opow, int P1,
+    E *__restrict__ L, int64_t box_st, int n_slots) {
+  critical_path_priority();
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
+  constexpr int KS = 4 * RT;
+  constexpr bool F64 = sizeof(R) == 8;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
+  if (slot0 >= n_slots) return;  // the whole wavefront past the last slot
+  const int2 it = items[blockIdx.x];  // first pair, end of pairs
+  const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
+  const int slot = slot0 + (c16 >> 1);
+  const bool sact = slot < n_slots;
+  M += (int64_t)(sact ? slot : slot0) * box_st;
+  L += (int64_t)(sact ? slot : slot0) * box_st;
+  R A[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + c16, k = 4 * ks + g;
+      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
+    }
+  int4 rec;
+  double pl;
+  E inv[KS], fv[KS], gv[F64 ? 1 : 4 * RT];
+  auto fetch = [&](int32_t j) {
+    rec = prs[j];
+    pl = plog[j];
+    const bool pv = rec.x >= 0;
+    const E *Md = M + (int64_t)(pv ? rec.x : 0) * P1;
+    const E *op = opow + (int64_t)rec.y * P1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
+      const E mv = Md[kc], ov = op[kc];
+      inv[ks] = (pv && k < P1) ? mv : mk2<E>(0.0, 0.0);
+      fv[ks] = k < P1 ? ov : mk2<E>(0.0, 0.0);
+    }
+    if (!F64) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rt + Mfma16<R>::row(g, v), mc = m < P1 ? m : P1 - 1;
+          gv[F64 ? 0 : 4 * rt + v] = op[mc];
+        }
+    }
+  };
+  double acc[RT][4];
+  auto flush = [&](int32_t b) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
+        if (sact && m < P1) reinterpret_cast<R *>(L + (int64_t)b * P1 + m)[comp] = (R)acc[rt][v];
+        acc[rt][v] = 0.0;
+      }
+  };
+  fetch(it.x);
+  int32_t cur = rec.z;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[rt][v] = 0.0;
+  for (int32_t j = it.x; j < it.y; ++j) {
+    const int4 rc = rec;
+    const double plc = pl;
+    E inc[KS], fc[KS], gc[F64 ? 1 : 4 * RT];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      inc[ks] = inv[ks];
+      fc[ks] = fv[ks];
+    }
+    if (!F64) {
+#pragma unroll
+      for (int q = 0; q < 4 * RT; ++q) gc[F64 ? 0 : q] = gv[F64 ? 0 : q];
+    }
+    if (j + 1 < it.y) fetch(j + 1);  // in flight during this pair's matrix-core work
+    if (rc.z != cur) {
+      flush(cur);
+      cur = rc.z;
+    }
+    if (rc.x < 0) continue;  // a box without List 2 pairs: its local is 0
+    R Bf[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const E mk = inc[ks], ok = fc[ks];
+      Bf[ks] = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
+    }
+    Acc C[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      C[rt] = Acc{R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
+        const double2 gm = to_d2(F64 ? fc[(4 * rt + v) % KS] : gc[F64 ? 0 : 4 * rt + v]);
+        double val = slot_post<R>((double)C[rt][v], comp, gm);
+        if (m == 0 && !comp) val = fma((double)inc[0].x, plc, val);  // a_0 log|s o|
+        acc[rt][v] += val;
+      }
+  }
+  flush(cur);
+}
+
+template <int RT, typename E>
+__global__ void __launch_bounds__(256) k_l2l_slots(
+    const int2 *__restrict__ items, const int2 *__restrict__ prs,
+    const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
+    const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st, int n_slots) {
+  critical_path_priority();
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
+  constexpr int KS = 4 * RT;
+  constexpr bool F64 = sizeof(R) == 8;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
+  if (slot0 >= n_slots) return;
+  const int2 it = items[blockIdx.x];
+  const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
+  const int slot = slot0 + (c16 >> 1);
+  const bool sact = slot < n_slots;
+  L += (int64_t)(sact ? slot : slot0) * box_st;
+  Lf += (int64_t)(sact ? slot : slot0) * box_st;
+  // C(k, i) vanishes below the diagonal: row tile rt needs only k-steps ks >= 4 rt
+  R A[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + c16, k = 4 * ks + g;
+      A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? (R)binom_t[k * P1 + i] : R(0);
+    }
+  int2 rec;
+  double4 tw;
+  E inv[KS];
+  auto fetch = [&](int32_t j) {
+    rec = prs[j];
+    tw = anc_tw[j];
+    const bool pv = rec.x >= 0;
+    const E *La = L + (int64_t)(pv ? rec.x : 0) * P1;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
+      const E lv = La[kc];
+      inv[ks] = (pv && k < P1) ? lv : mk2<E>(0.0, 0.0);
+    }
+  };
+  double acc[RT][4];
+  auto flush = [&](int32_t b) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
+        if (sact && m < P1) {
+          const int64_t o = (int64_t)b * P1 + m;
+          const double own = (double)reinterpret_cast<const R *>(L + o)[comp];
+          reinterpret_cast<R *>(Lf + o)[comp] = (R)(own + acc[rt][v]);
+        }
+        acc[rt][v] = 0.0;
+      }
+  };
+  fetch(it.x);
+  int32_t cur = rec.y;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[rt][v] = 0.0;
+  for (int32_t j = it.x; j < it.y; ++j) {
+    const int2 rc = rec;
+    const double4 twc = tw;
+    E inc[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) inc[ks] = inv[ks];
+    if (j + 1 < it.y) fetch(j + 1);
+    if (rc.y != cur) {
+      flush(cur);
+      cur = rc.y;
+    }
+    if (rc.x < 0) continue;  // no ancestor with a local of its own: Lf = L
+    const double2 t = make_double2(twc.x, twc.y), w = make_double2(twc.z, twc.w);
+    // pre-factors t^k, k = 4 ks + g
+    double2 pw = make_double2(1.0, 0.0);
+    for (int e = 0; e < g; ++e) pw = cmul(pw, t);
+    const double2 t2 = cmul(t, t), t4 = cmul(t2, t2);
+    R Bf[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const double2 x = cmul(pw, to_d2(inc[ks]));
+      Bf[ks] = (R)(comp ? x.y : x.x);
+      pw = cmul(pw, t4);
+    }
+    Acc C[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      C[rt] = Acc{R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int ks = 4 * rt; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
+    }
+    // post-factors u^-m for rows m = 16 rt + row(g, v)
+    const double2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4), w16 = cmul(w8, w8);
+    double2 wr = make_double2(1.0, 0.0);
+    const int g0 = F64 ? g : 4 * g;  // order of row (g, 0) in the first tile
+    for (int e = 0; e < g0; ++e) wr = cmul(wr, w);
+    const double2 wstep = F64 ? w4 : w;  // from row (g, v) to (g, v + 1)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      double2 wv2 = wr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[rt][v] += slot_post<R>((double)C[rt][v], comp, wv2);
+        wv2 = cmul(wv2, wstep);
+      }
+      wr = cmul(wr, w16);
+    }
+  }
+  flush(cur);
+}
+
+// ------------------------------------------------------------------------------------------
 // Stage 6b, P2L (eq. (local) about c_b) for the sources of a box's List 4 far boxes, added to the
 // box local that k_m2l wrote. One wavefront per box with such sources (their indices flattened
 // on the host). With v = 1/y, coefficient 0 is q log|s y| + d v and coefficient k >= 1 is
@@ -1053,6 +1307,168 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   }
 }
 
+// Stages 3, 5a, 6a for S and D of many densities (GQ_S_AND_D, a batch of nd densities) on the
+// matrix cores. For a center c and a source y of strength q^(j) = w mu^(j) in density j, the
+// charge part adds q z^-m (m >= 1) and q log|z|^2, the dipole part q n z^-(m+1) (the dipole is
+// the charge times the normal for S and D of one density), z = y - c. Over the sources of a chunk
+// and the densities this is one real GEMM per center: rows are the real and imaginary parts of
+// z^-m (S, m = 1..PQ, then log|z|^2) and of n z^-(m+1) (D, m = 0..PQ), the k dimension the
+// sources, the columns the densities. A work-group of four wavefronts takes up to four centers of
+// a box (one per wavefront) and one chunk of its direct sources; the chunk's positions, normals
+// and the strengths of 16 NT densities are staged in LDS 64 sources at a time (the next batch's
+// loads in flight during the current one), and each lane forms the pair's powers for its rows:
+// row 16 rt + i of either block is order 8 rt + i/2 + 1, so one chain of products serves both.
+// The finished rows are the scaled coefficients of k_near / k_near_sd (times r^m, S by -1/m),
+// written to the same (center, chunk) rows: S of density j in slot j, D in slot d_slot + j.
+template <int PQ, int NT>
+__global__ void __launch_bounds__(256, 2) k_near_mfma(
+    const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const double2 *__restrict__ sxy, const double2 *__restrict__ snrm,
+    const double *__restrict__ sq, double2 *__restrict__ anear, int rs, int64_t src_st,
+    int64_t row_st, int nd, int64_t d_slot) {
+  constexpr int RTS = (2 * PQ + 1 + 15) / 16, RTD = (2 * PQ + 2 + 15) / 16;
+  constexpr int RT = RTS > RTD ? RTS : RTD;
+  constexpr int LI = (2 * PQ) % 16, LRT = (2 * PQ) / 16;  // lane row and tile of the log row
+  constexpr int NDB = 16 * NT;                            // densities per work-group
+  constexpr int SB = 32;                                  // sources staged per batch
+  constexpr int SST = SB + 4;                             // LDS row stride (doubles)
+  __shared__ double t_q[NDB][SST];
+  __shared__ double2 t_y[SB], t_n[SB];
+  __shared__ double2 t_log[kLogTab];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int4 i0 = items[2 * blockIdx.x], i1 = items[2 * blockIdx.x + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x;
+  const int d0 = blockIdx.y * NDB;
+  const bool active = wv < n_ctr;
+  const int32_t c = ctr_first + (active ? wv : 0);
+  const double2 cc = cxy[c];
+  const double rad = cr[c];
+  if (tid < kLogTab) t_log[tid] = g_log_tab[tid];  // the log table from LDS in the loop
+  const double2 *lt = t_log;
+  const int i = lane & 15, kk = lane >> 4, h = i >> 1, comp = i & 1;
+  // staging: thread (source tid % SB, density rows tid / SB + 8 q) of an SB-source batch
+  const int ss = tid % SB, sd = tid / SB;
+  double rq[NDB / 8];
+  double2 ry = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+  auto load = [&](int32_t base) {
+    const int nb = min(SB, (int)(len - base));
+    const bool in = ss < nb;
+    const int32_t src = near_src[off + base + (in ? ss : 0)];
+    if (sd == 0) {
+      ry = sxy[src];
+      rn = snrm[src];
+    }
+#pragma unroll
+    for (int q = 0; q < NDB / 8; ++q) {
+      const int dj = d0 + sd + 8 * q;
+      const double v = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
+      rq[q] = (in && dj < nd) ? v : 0.0;
+    }
+  };
+  gq_d4 CS[RTS][NT], CD[RTD][NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+    for (int rt = 0; rt < RTS; ++rt) CS[rt][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rt = 0; rt < RTD; ++rt) CD[rt][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  load(0);
+  for (int32_t base = 0; base < len; base += SB) {
+    const int nb = min(SB, (int)(len - base));
+    __syncthreads();  // the previous batch is no longer read
+    if (sd == 0) {
+      t_y[ss] = ry;
+      t_n[ss] = rn;
+    }
+#pragma unroll
+    for (int q = 0; q < NDB / 8; ++q) t_q[sd + 8 * q][ss] = rq[q];
+    __syncthreads();
+    if (base + SB < len) load(base + SB);  // in flight during this batch
+    if (!active) continue;
+    const int nks = (nb + 3) >> 2;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int sl = 4 * ks + kk;
+      const bool valid = sl < nb;
+      const double2 y = t_y[sl], nv = t_n[sl];
+      const double2 z = make_double2(y.x - cc.x, y.y - cc.y);
+      const double r2 = valid ? cnorm2(z) : 1.0;
+      const double ir2 = rcp_nr(r2);
+      const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
+      const double2 i2 = cmul(inv, inv), i4 = cmul(i2, i2), i8 = cmul(i4, i4);
+      const int e = h + 1;  // 1..8
+      const double2 one = make_double2(1.0, 0.0);
+      double2 pw = cmul(cmul((e & 1) ? inv : one, (e & 2) ? i2 : one),
+                        cmul((e & 4) ? i4 : one, (e & 8) ? i8 : one));
+      double lg = 0.0;
+      if (i == LI) lg = log_tab(r2, lt);
+      double aS[RTS], aD[RTD];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int r = 16 * rt + i;
+        if (rt < RTS) {
+          double a = comp ? pw.y : pw.x;
+          if (r >= 2 * PQ) a = (rt == LRT && i == LI) ? lg : 0.0;
+          aS[rt < RTS ? rt : 0] = valid ? a : 0.0;
+        }
+        if (rt < RTD) {
+          const double2 w = cmul(nv, pw);
+          const double a = r < 2 * PQ + 2 ? (comp ? w.y : w.x) : 0.0;
+          aD[rt < RTD ? rt : 0] = valid ? a : 0.0;
+        }
+        if (rt + 1 < RT) pw = cmul(pw, i8);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double b = t_q[16 * nt + i][sl];  // B[kk][j]: column j = lane & 15 = i
+#pragma unroll
+        for (int rt = 0; rt < RTS; ++rt) CS[rt][nt] = mfma16(aS[rt], b, CS[rt][nt]);
+#pragma unroll
+        for (int rt = 0; rt < RTD; ++rt) CD[rt][nt] = mfma16(aD[rt], b, CD[rt][nt]);
+      }
+    }
+  }
+  if (!active) return;
+  // lane (column j = lane & 15, group g = lane >> 4) holds rows 16 rt + g + 4 v
+  const int g = kk, j = i;
+  const int64_t row = row_first + wv;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int dj = d0 + 16 * nt + j;
+    if (dj >= nd) continue;
+    double *os = reinterpret_cast<double *>(anear + (int64_t)dj * row_st + row * rs);
+    double *od = reinterpret_cast<double *>(anear + (d_slot + dj) * row_st + row * rs);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rt + g + 4 * v;
+        if (rt < RTS) {
+          const double y = CS[rt < RTS ? rt : 0][nt][v];
+          if (r < 2 * PQ) {
+            const int m = r / 2 + 1;
+            double rp = rad;
+            for (int q = 1; q < m; ++q) rp *= rad;
+            os[2 * m + (r & 1)] = -(rp * (1.0 / m)) * y;
+          } else if (r == 2 * PQ) {
+            os[0] = 0.5 * y;
+          } else if (r == 2 * PQ + 1) {
+            os[1] = 0.0;
+          }
+        }
+        if (rt < RTD && r < 2 * PQ + 2) {
+          const double y = CD[rt < RTD ? rt : 0][nt][v];
+          const int m = r / 2;
+          double rp = 1.0;
+          for (int q = 0; q < m; ++q) rp *= rad;
+          od[r] = rp * y;
+        }
+      }
+  }
+}
+
 // k_near for a block of DG densities per work-group (grid.y = density blocks): same items and
 // lanes, the sources' charges and dipoles of the DG densities staged together, one pair geometry
 // for all of them. Densities past n_dens (a last partial block) get zero strengths and no rows.
@@ -1544,6 +1960,13 @@ class StageTimer {
   hipEvent_t a_ = nullptr;
 };
 
+// Workspace slots from which M2L and the Stage 7 gather run as GEMMs over the slots (a full
+// column tile of 8 slots per wavefront); fewer slots keep the kernels that batch 8 pairs as the
+// columns of one slot.
+constexpr int kSlotGemmMin = 8;
+// Densities of a GQ_S_AND_D batch from which the direct interactions run on the matrix cores.
+constexpr int kNearMfmaMin = 8;
+
 // Per-density strides of the batched buffers (elements).
 struct Strides {
   int64_t src, box, row, tv;
@@ -1614,6 +2037,16 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
     hipLaunchKernelGGL((k_near_sd<PQ>), dim3(n, 1), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
                        d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
                        ctx->params.p_qbx + 1, S.src, S.row, (int64_t)1);
+    return;
+  }
+  const int32_t nm = (int32_t)(bk.nmf1 - bk.nmf0);
+  if (nd >= kNearMfmaMin && nm > 0) {
+    // one GEMM per center over the sources and a block of densities on the matrix cores
+    constexpr int NT = PQ <= 12 ? 4 : 2;
+    hipLaunchKernelGGL((k_near_mfma<PQ, NT>), dim3(nm, (nd + 16 * NT - 1) / (16 * NT)),
+                       dim3(256), 0, s, d.near_mitems + 2 * bk.nmf0, d.near_src, d.cxy, d.cr,
+                       d.sxy, d.snrm, d.sq, d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd,
+                       (int64_t)nd);
     return;
   }
   launch_near_bucket<1, PQ, E>(ctx, bk, nd, s, S, d.anear);
@@ -1732,10 +2165,20 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    auto kern = P1 <= 16 ? k_m2l_mb<1, E> : P1 <= 32 ? k_m2l_mb<2, E>
-              : P1 <= 48 ? k_m2l_mb<3, E> : k_m2l_mb<4, E>;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2l_items, slots), dim3(64), 0, st,
-                       d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt, X.opow, P1, L, S.box);
+    if (slots >= kSlotGemmMin) {
+      // a GEMM per List 2 pair over the slots (8 per wavefront)
+      const int nw = std::min(4, (slots + 7) / 8);
+      auto kern = P1 <= 16 ? k_m2l_slots<1, E> : P1 <= 32 ? k_m2l_slots<2, E>
+                : P1 <= 48 ? k_m2l_slots<3, E> : k_m2l_slots<4, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2l_items, (slots + 8 * nw - 1) / (8 * nw)),
+                         dim3(64 * nw), 0, st, d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt,
+                         X.opow, P1, L, S.box, slots);
+    } else {
+      auto kern = P1 <= 16 ? k_m2l_mb<1, E> : P1 <= 32 ? k_m2l_mb<2, E>
+                : P1 <= 48 ? k_m2l_mb<3, E> : k_m2l_mb<4, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2l_items, slots), dim3(64), 0, st,
+                         d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt, X.opow, P1, L, S.box);
+    }
     if (ctx->n_p2l_boxes > 0) {
       auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
               : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
@@ -1746,10 +2189,19 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   if (ctx->n_l2g_sinks > 0) {
     StageTimer st_(ctx, GQ_STAGE_L2L);
-    auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
-              : P1 <= 48 ? k_l2l_gather<3, E> : k_l2l_gather<4, E>;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_items, slots), dim3(64), 0, st,
-                       d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
+    if (slots >= kSlotGemmMin) {
+      const int nw = std::min(4, (slots + 7) / 8);
+      auto kern = P1 <= 16 ? k_l2l_slots<1, E> : P1 <= 32 ? k_l2l_slots<2, E>
+                : P1 <= 48 ? k_l2l_slots<3, E> : k_l2l_slots<4, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_items, (slots + 8 * nw - 1) / (8 * nw)),
+                         dim3(64 * nw), 0, st, d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1,
+                         L, Lf, S.box, slots);
+    } else {
+      auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
+                : P1 <= 48 ? k_l2l_gather<3, E> : k_l2l_gather<4, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_items, slots), dim3(64), 0, st,
+                         d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1, L, Lf, S.box);
+    }
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;

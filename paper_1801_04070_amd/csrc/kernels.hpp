@@ -19,7 +19,7 @@ const std::vector<int> &compiled_pq();
 
 
 // Maximum densities per launch (the batch dimension of every kernel's grid).
-constexpr int kMaxDensBatch = 64;
+constexpr int kMaxDensBatch = 128;
 
 // Copies the natural-log table of the direct-interaction kernels to the current device; called
 // once per context, with its device current, before any evaluation.

@@ -187,10 +187,13 @@ def test_empty_batch_and_errors(c1):
 
 
 def test_density_batches_match_single_evaluations(c1):
-    """70 densities (two launches of the batch dimension), padded row strides, S - D kind: each
-    row equals the single-density evaluation bitwise and the oracle within the gate."""
+    """134 densities (two launches of the batch dimension: 128, then 6), padded row strides, S - D
+    kind: each row equals the single-density evaluation to rounding (a batch of 8 or more slots
+    runs M2L and the Stage 7 gather as GEMMs over the slots, which sum in another order; a batch
+    of 6 runs the single-slot kernels, bitwise equal), the batch is bitwise reproducible, and the
+    last row matches the oracle within the gate."""
     q, _ = _ctx(c1, p_qbx=8, p_fmm=30)
-    n, pad = 70, 7
+    n, pad = 134, 7
     rng = np.random.default_rng(3)
     d1 = torch.zeros((n, c1.n_src + pad), dtype=torch.float64, device="cuda:0")
     d2 = torch.zeros((n, c1.n_src + pad), dtype=torch.float64, device="cuda:0")
@@ -202,11 +205,19 @@ def test_density_batches_match_single_evaluations(c1):
     q.eval(3, d1[:, :c1.n_src], d2[:, :c1.n_src], out=out[:, :c1.n_tgt])
     res = out.cpu().numpy()
     assert np.isnan(res[:, c1.n_tgt:]).all(), "wrote outside the output rows"
-    for j in (0, 33, 63, 64, 69):
+    for j in (0, 33, 127, 128, 133):
         single = q.eval(3, _dev(h1[j]), _dev(h2[j])).cpu().numpy()
-        assert np.array_equal(single, res[j, :c1.n_tgt])
-    ref = oracle.qbx_eval(c1, 3, h1[69], h2[69], p_qbx=8)
-    assert _rel(res[69, :c1.n_tgt], ref) < 1e-10
+        if j >= 128:
+            assert np.array_equal(single, res[j, :c1.n_tgt])
+        else:
+            assert _rel(res[j, :c1.n_tgt], single) < 1e-14
+    again = torch.full_like(out, np.nan)
+    q.eval(3, d1[:, :c1.n_src], d2[:, :c1.n_src], out=again[:, :c1.n_tgt])
+    assert np.array_equal(again.cpu().numpy()[:, :c1.n_tgt], res[:, :c1.n_tgt])
+    ref = oracle.qbx_eval(c1, 3, h1[133], h2[133], p_qbx=8)
+    assert _rel(res[133, :c1.n_tgt], ref) < 1e-10
+    ref = oracle.qbx_eval(c1, 3, h1[100], h2[100], p_qbx=8)
+    assert _rel(res[100, :c1.n_tgt], ref) < 1e-10
 
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
@@ -404,7 +415,7 @@ def test_graph_replays_match_eager(c1, kind):
         g.launch()
     assert e.value.status == _lib.GQ_ESTATE
     g.close()
-    big = _dev(np.tile(mu, (65, 1)))
+    big = _dev(np.tile(mu, (129, 1)))
     with pytest.raises(GQError) as e:
         q.graph(1, big)
     assert e.value.status == _lib.GQ_EUNSUP
@@ -539,3 +550,26 @@ def test_autotune_picks_a_candidate_shape_and_keeps_results():
     from paper_1801_04070_amd import GQError
     with pytest.raises(GQError):
         q.autotune(3, _dev(mu))
+
+
+@pytest.mark.parametrize("p_qbx", [8, 12, 16])
+def test_s_and_d_batch_on_matrix_cores(p_qbx):
+    """GQ_S_AND_D over 20 densities: the direct interactions run on the matrix cores (one GEMM
+    per center over its direct sources and a block of 64 densities, partly filled here) and M2L
+    and the Stage 7 gather as GEMMs over the 40 slots. Every S and D row matches the separate
+    single-kind evaluation to rounding, the last density the oracle within the gate."""
+    from paper_1801_04070_amd import GQ_S_AND_D
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    q, _ = _ctx(g, p_qbx=p_qbx, p_fmm=30)
+    n = 20
+    h = np.stack([gi.fourier_density(g, seed=300 + j) for j in range(n)])
+    both = q.eval(GQ_S_AND_D, _dev(h)).cpu().numpy()
+    assert both.shape == (2 * n, g.n_tgt)
+    for j in (0, 7, 19):
+        s = q.eval(1, _dev(h[j])).cpu().numpy()
+        d = q.eval(2, _dev(h[j])).cpu().numpy()
+        assert _rel(both[j], s) < 1e-13, j
+        assert _rel(both[n + j], d) < 1e-13, j
+    for kind, row in ((1, n - 1), (2, 2 * n - 1)):
+        ref = oracle.qbx_eval(g, kind, h[n - 1], None, p_qbx=p_qbx)
+        assert _rel(both[row], ref) < 1e-10, kind
