@@ -677,6 +677,189 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
 }
 
 // ------------------------------------------------------------------------------------------
+// Stage 2 (direct moments, MODE 0) and Stage 6b (P2L, MODE 1) for S and D of a batch of
+// densities on the matrix cores. For one box and its sources the coefficients of every density
+// are one real GEMM: rows are the real and imaginary parts of the powers of the scaled offset
+// (MODE 0: y^k for S, -n y^(k-1)/s for D; MODE 1: v^k with v = 1/y, log|s y| in row 0, for S and
+// n v^(k+1)/s for D; the dipole is the charge times the normal), the k dimension the sources and
+// the columns 64 densities; the charges q^(j) = w mu^(j) are the B operand for both kinds. The
+// S rows (RTS tiles of 16) and D rows (RTD tiles) are spread over the four wavefronts of a
+// work-group, TPW tiles each; the item's sources and the strengths of the 64 densities are
+// staged in LDS 32 sources at a time. Row 16 rt + i of either block is power 8 rt + i/2 (MODE 1
+// D: one more), so a lane forms x^(i/2) once per source and steps by x^8 between its tiles.
+// Coefficients as k_p2m_all / k_p2l write them: S a_0 = sum q, a_k = -A_k / k (MODE 0), the log
+// sum and -A_k / k (MODE 1); D from its rows directly. MODE 0 items of split boxes write partial
+// rows for k_m_reduce; MODE 1 adds to the box locals that M2L wrote.
+template <int MODE, int TPW>
+__global__ void __launch_bounds__(256, 2) k_p2x_mfma(
+    const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
+    const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
+    const double *__restrict__ level_inv_side, const double *__restrict__ level_log_side,
+    const double2 *__restrict__ sxy, const double2 *__restrict__ snrm,
+    const double *__restrict__ sq, int P1, double2 *__restrict__ Out,
+    double2 *__restrict__ Mp, int64_t src_st, int64_t box_st, int64_t part_st, int nd,
+    int64_t d_off) {
+  critical_path_priority();
+  constexpr int NT = 4, NDB = 64, SB = 32, SST = SB + 4;
+  __shared__ double t_q[NDB][SST];
+  __shared__ double2 t_y[SB], t_n[SB];
+  __shared__ double2 t_log[kLogTab];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int4 it = items[blockIdx.x];
+  const int32_t b = it.x;
+  const int d0 = blockIdx.y * NDB;
+  const int lev = blevel[b];
+  const double2 c = bc[b];
+  const double is = level_inv_side[lev];
+  const double logs = MODE == 1 ? level_log_side[lev] : 0.0;
+  if (MODE == 1 && tid < kLogTab) t_log[tid] = g_log_tab[tid];
+  const double2 *lt = t_log;
+  const int RTS = (2 * P1 + 15) / 16;
+  const int RTD = (2 * (MODE == 0 ? P1 - 1 : P1) + 15) / 16;
+  const int i = lane & 15, kk = lane >> 4, h = i >> 1, comp = i & 1;
+  const int ss = tid % SB, sd = tid / SB;
+  const int32_t len = it.z - it.y;
+  double rq[NDB / 8];
+  double2 ry = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+  auto load = [&](int32_t base) {
+    const int nb = min(SB, (int)(len - base));
+    const bool in = ss < nb;
+    const int32_t e = it.y + base + (in ? ss : 0);
+    const int32_t src = MODE == 0 ? e : src_idx[e];
+    if (sd == 0) {
+      ry = sxy[src];
+      rn = snrm[src];
+    }
+#pragma unroll
+    for (int q = 0; q < NDB / 8; ++q) {
+      const int dj = d0 + sd + 8 * q;
+      const double v = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
+      rq[q] = (in && dj < nd) ? v : 0.0;
+    }
+  };
+  // this wavefront's tiles: t = wv TPW + u; S tile t < RTS, else D tile t - RTS
+  int trt[TPW];
+  bool tis_d[TPW], tact[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int t = wv * TPW + u;
+    tis_d[u] = t >= RTS;
+    trt[u] = tis_d[u] ? t - RTS : t;
+    tact[u] = t < RTS + RTD;
+  }
+  gq_d4 C[TPW][NT];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) C[u][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int32_t base = 0; base < len; base += SB) {
+    const int nb = min(SB, (int)(len - base));
+    __syncthreads();
+    if (sd == 0) {
+      t_y[ss] = ry;
+      t_n[ss] = rn;
+    }
+#pragma unroll
+    for (int q = 0; q < NDB / 8; ++q) t_q[sd + 8 * q][ss] = rq[q];
+    __syncthreads();
+    if (base + SB < len) load(base + SB);
+    if (!tact[0]) continue;
+    const int nks = (nb + 3) >> 2;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int sl = 4 * ks + kk;
+      const bool valid = sl < nb;
+      const double2 yy = t_y[sl], nv = t_n[sl];
+      const double2 y = make_double2((yy.x - c.x) * is, (yy.y - c.y) * is);
+      double2 x = y;
+      double lg = 0.0;
+      if (MODE == 1) {
+        const double r2 = valid ? cnorm2(y) : 1.0;
+        const double ir2 = rcp_nr(r2);
+        x = make_double2(y.x * ir2, -y.y * ir2);
+        if (i == 0 && wv == 0) lg = fma(0.5, log_tab(r2, lt), logs);
+      }
+      const double2 one = make_double2(1.0, 0.0);
+      const double2 x2 = cmul(x, x), x4 = cmul(x2, x2), x8 = cmul(x4, x4);
+      const double2 xh = cmul(cmul((h & 1) ? x : one, (h & 2) ? x2 : one), (h & 4) ? x4 : one);
+      const double2 nd_s = make_double2(nv.x * is, nv.y * is);  // n / s
+      double a[TPW];
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        double2 p = xh;
+        for (int q = 0; q < trt[u]; ++q) p = cmul(p, x8);
+        const int k = 8 * trt[u] + h;
+        double val;
+        if (!tis_d[u]) {
+          val = comp ? p.y : p.x;
+          if (MODE == 1 && k == 0) val = comp ? 0.0 : lg;
+          if (k >= P1) val = 0.0;
+        } else {
+          // MODE 0: row k is coefficient k + 1, -n y^k / s; MODE 1: row k, n v^(k+1) / s
+          const double2 w = MODE == 0 ? cmul(make_double2(-nd_s.x, -nd_s.y), p)
+                                      : cmul(nd_s, cmul(p, x));
+          val = comp ? w.y : w.x;
+          if (k >= (MODE == 0 ? P1 - 1 : P1)) val = 0.0;
+        }
+        a[u] = (valid && tact[u]) ? val : 0.0;
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double bq = t_q[16 * nt + i][sl];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) C[u][nt] = mfma16(a[u], bq, C[u][nt]);
+      }
+    }
+  }
+  // lane (column j, group g) holds rows 16 rt + g + 4 v: order 8 rt + g/2 + 2 v, part g & 1
+  const int g = kk, j = i;
+  const int gc = g & 1;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int dj = d0 + 16 * nt + j;
+    if (dj >= nd) continue;
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      if (!tact[u]) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 8 * trt[u] + (g >> 1) + 2 * v;
+        const double y = C[u][nt][v];
+        int coef;
+        double val;
+        if (!tis_d[u]) {
+          if (k >= P1) continue;
+          coef = k;
+          val = k == 0 ? y : -y * (1.0 / k);
+        } else {
+          coef = MODE == 0 ? k + 1 : k;
+          if (coef >= P1) continue;
+          val = y;
+        }
+        if (MODE == 0) {
+          if (it.w >= 0) {
+            double *o = reinterpret_cast<double *>(Mp + (int64_t)dj * part_st +
+                                                   (int64_t)it.w * 2 * P1);
+            o[2 * ((tis_d[u] ? P1 : 0) + coef) + gc] = val;
+            if (!tis_d[u] && k == 0) o[2 * P1 + gc] = 0.0;  // D coefficient 0
+          } else {
+            double *o = reinterpret_cast<double *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
+                                                   (int64_t)b * P1);
+            o[2 * coef + gc] = val;
+            if (!tis_d[u] && k == 0)
+              reinterpret_cast<double *>(Out + (int64_t)dj * box_st + d_off + (int64_t)b * P1)[gc] = 0.0;
+          }
+        } else {
+          double *o = reinterpret_cast<double *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
+                                                 (int64_t)b * P1);
+          o[2 * coef + gc] += val;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Stage 6b, P2L (eq. (local) about c_b) for the sources of a box's List 4 far boxes, added to the
 // box local that k_m2l wrote. One wavefront per box with such sources (their indices flattened
 // on the host). With v = 1/y, coefficient 0 is q log|s y| + d v and coefficient k >= 1 is
@@ -1967,6 +2150,13 @@ constexpr int kSlotGemmMin = 8;
 // Densities of a GQ_S_AND_D batch from which the direct interactions run on the matrix cores.
 constexpr int kNearMfmaMin = 8;
 
+// The direct moments and P2L of a GQ_S_AND_D batch on the matrix cores (FP64 expansions, at least
+// kNearMfmaMin densities).
+template <int KIND, typename E>
+bool use_p2x_mfma(int nd) {
+  return KIND == 4 && sizeof(E) == sizeof(double2) && nd >= kNearMfmaMin;
+}
+
 // Per-density strides of the batched buffers (elements).
 struct Strides {
   int64_t src, box, row, tv;
@@ -2133,11 +2323,19 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int64_t part_st = ctx->n_p2m_parts * 2 * P1;
   if (ctx->n_p2m_items > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    auto kern = P1 <= 8 ? k_p2m_all<PK, 1, E> : P1 <= 16 ? k_p2m_all<PK, 2, E>
-              : P1 <= 32 ? k_p2m_all<PK, 4, E> : k_p2m_all<PK, 8, E>;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, nd), dim3(64), 0, st, d.p2m_item,
-                       d.bc, d.blevel, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M, d.Mp, S.src,
-                       S.box, part_st, (int64_t)nd * S.box);
+    if (use_p2x_mfma<KIND, E>(nd)) {
+      auto kern = P1 <= 32 ? k_p2x_mfma<0, 2> : k_p2x_mfma<0, 4>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, (nd + 63) / 64), dim3(256), 0, st,
+                         d.p2m_item, nullptr, d.bc, d.blevel, d.level_inv_side, d.level_log_side,
+                         d.sxy, d.snrm, d.sq, P1, reinterpret_cast<double2 *>(M), d.Mp, S.src,
+                         S.box, part_st, nd, (int64_t)nd * S.box);
+    } else {
+      auto kern = P1 <= 8 ? k_p2m_all<PK, 1, E> : P1 <= 16 ? k_p2m_all<PK, 2, E>
+                : P1 <= 32 ? k_p2m_all<PK, 4, E> : k_p2m_all<PK, 8, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, nd), dim3(64), 0, st, d.p2m_item,
+                         d.bc, d.blevel, d.level_inv_side, d.sxy, d.sq, d.sdip, P1, M, d.Mp, S.src,
+                         S.box, part_st, (int64_t)nd * S.box);
+    }
   }
   if (ctx->n_p2m_red > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2M);
@@ -2180,11 +2378,20 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
                          d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt, X.opow, P1, L, S.box);
     }
     if (ctx->n_p2l_boxes > 0) {
-      auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
-              : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
-      hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, nd), dim3(64), 0, st, d.p2l_item,
-                         d.p2l_src, d.bc, d.blevel, d.level_inv_side, d.level_log_side, d.sxy,
-                         d.sq, d.sdip, P1, L, S.src, S.box, (int64_t)nd * S.box);
+      if (use_p2x_mfma<KIND, E>(nd)) {
+        auto kp = P1 <= 32 ? k_p2x_mfma<1, 2> : k_p2x_mfma<1, 4>;
+        hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, (nd + 63) / 64), dim3(256), 0,
+                           st, d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
+                           d.level_log_side, d.sxy, d.snrm, d.sq, P1,
+                           reinterpret_cast<double2 *>(L), nullptr, S.src, S.box, (int64_t)0, nd,
+                           (int64_t)nd * S.box);
+      } else {
+        auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>
+                : P1 <= 32 ? k_p2l<PK, 4, E> : k_p2l<PK, 8, E>;
+        hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, nd), dim3(64), 0, st, d.p2l_item,
+                           d.p2l_src, d.bc, d.blevel, d.level_inv_side, d.level_log_side, d.sxy,
+                           d.sq, d.sdip, P1, L, S.src, S.box, (int64_t)nd * S.box);
+      }
     }
   }
   if (ctx->n_l2g_sinks > 0) {

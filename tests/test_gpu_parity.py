@@ -552,15 +552,16 @@ def test_autotune_picks_a_candidate_shape_and_keeps_results():
         q.autotune(3, _dev(mu))
 
 
-@pytest.mark.parametrize("p_qbx", [8, 12, 16])
-def test_s_and_d_batch_on_matrix_cores(p_qbx):
-    """GQ_S_AND_D over 20 densities: the direct interactions run on the matrix cores (one GEMM
-    per center over its direct sources and a block of 64 densities, partly filled here) and M2L
-    and the Stage 7 gather as GEMMs over the 40 slots. Every S and D row matches the separate
-    single-kind evaluation to rounding, the last density the oracle within the gate."""
+@pytest.mark.parametrize("p_qbx,p_fmm", [(8, 30), (12, 30), (16, 30), (12, 40), (12, 63)])
+def test_s_and_d_batch_on_matrix_cores(p_qbx, p_fmm):
+    """GQ_S_AND_D over 20 densities: the direct interactions, the moments and P2L run on the
+    matrix cores (one GEMM per center or box over its sources and a block of 64 densities, partly
+    filled here) and M2L and the Stage 7 gather as GEMMs over the 40 slots, at FMM orders that
+    take 2 to 4 row tiles per wavefront. Every S and D row matches the separate single-kind
+    evaluation to rounding, the last density the oracle within the gate."""
     from paper_1801_04070_amd import GQ_S_AND_D
     g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
-    q, _ = _ctx(g, p_qbx=p_qbx, p_fmm=30)
+    q, _ = _ctx(g, p_qbx=p_qbx, p_fmm=p_fmm)
     n = 20
     h = np.stack([gi.fourier_density(g, seed=300 + j) for j in range(n)])
     both = q.eval(GQ_S_AND_D, _dev(h)).cpu().numpy()
