@@ -55,6 +55,10 @@ __device__ __forceinline__ void critical_path_priority() { __builtin_amdgcn_s_se
 
 constexpr double kInv2Pi = 0.159154943091895335768883763372514362;
 
+
+
+
+
 // ------------------------------------------------------------------------------------------
 // Source strengths in tree order: q = w sigma, dipole d = w tau n (with the minus sign of S - D).
 template <int KIND>
@@ -446,7 +450,7 @@ __device__ __forceinline__ double slot_post(double y, int comp, double2 gm) {
 
 template <int RT, typename E>
 __global__ void __launch_bounds__(256) k_m2l_slots(
-    const int2 *__restrict__ items, const int4 *__restrict__ prs,
+    int32_t n_items, const int2 *__restrict__ items, const int4 *__restrict__ prs,
     const double *__restrict__ plog, const E *__restrict__ M,
     const typename Scalar<E>::T *__restrict__ Bt, const E *__restrict__ opow, int P1,
     E *__restrict__ L, int64_t box_st, int n_slots) {
@@ -457,6 +461,7 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
   constexpr bool F64 = sizeof(R) == 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
+  (void)n_items;
   if (slot0 >= n_slots) return;  // the whole wavefront past the last slot
   const int2 it = items[blockIdx.x];  // first pair, end of pairs
   const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
 
 template <int RT, typename E>
 __global__ void __launch_bounds__(256) k_l2l_slots(
-    const int2 *__restrict__ items, const int2 *__restrict__ prs,
+    int32_t n_items, const int2 *__restrict__ items, const int2 *__restrict__ prs,
     const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
     const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st, int n_slots) {
   critical_path_priority();
@@ -573,6 +578,7 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
   constexpr bool F64 = sizeof(R) == 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
+  (void)n_items;
   if (slot0 >= n_slots) return;
   const int2 it = items[blockIdx.x];
   const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
@@ -692,7 +698,7 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
 // rows for k_m_reduce; MODE 1 adds to the box locals that M2L wrote.
 template <int MODE, int TPW>
 __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
-    const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_inv_side, const double *__restrict__ level_log_side,
     const double2 *__restrict__ sxy, const double2 *__restrict__ snrm,
@@ -705,6 +711,7 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
   __shared__ double2 t_y[SB], t_n[SB];
   __shared__ double2 t_log[kLogTab];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  (void)n_items;
   const int4 it = items[blockIdx.x];
   const int32_t b = it.x;
   const int d0 = blockIdx.y * NDB;
@@ -1505,7 +1512,7 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
 // written to the same (center, chunk) rows: S of density j in slot j, D in slot d_slot + j.
 template <int PQ, int NT>
 __global__ void __launch_bounds__(256, 2) k_near_mfma(
-    const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double *__restrict__ cr,
     const double2 *__restrict__ sxy, const double2 *__restrict__ snrm,
     const double *__restrict__ sq, double2 *__restrict__ anear, int rs, int64_t src_st,
@@ -1519,7 +1526,10 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
   __shared__ double t_q[NDB][SST];
   __shared__ double2 t_y[SB], t_n[SB];
   __shared__ double2 t_log[kLogTab];
+  __shared__ double2 t_pw[4][SB][8];  // per wavefront (center): z^-1 .. z^-8 of the batch
+  __shared__ double t_lg[4][SB];      // and log|z|^2
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  (void)n_items;
   const int4 i0 = items[2 * blockIdx.x], i1 = items[2 * blockIdx.x + 1];
   const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
   const int n_ctr = i1.x;
@@ -1570,38 +1580,49 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
     for (int q = 0; q < NDB / 8; ++q) t_q[sd + 8 * q][ss] = rq[q];
     __syncthreads();
     if (base + SB < len) load(base + SB);  // in flight during this batch
+    if (active) {
+      // the pair geometry of the batch, once per (center, source): lane l takes source l % 32
+      // and powers 1..4 (l < 32, with the log) or 5..8 of 1/z; zeros past the batch
+      const int sa = lane & 31, half = lane >> 5;
+      const bool va = sa < nb;
+      const double2 ya = t_y[sa];
+      const double2 za = make_double2(ya.x - cc.x, ya.y - cc.y);
+      const double r2 = va ? cnorm2(za) : 1.0;
+      const double ir2 = rcp_nr(r2);
+      const double2 inv = make_double2(za.x * ir2, -za.y * ir2);
+      const double2 i2 = cmul(inv, inv), i3 = cmul(i2, inv), i4 = cmul(i2, i2);
+      const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+      const double2 b4 = half ? i4 : one;  // z^-(4 half)
+      double2 *pw = &t_pw[wv][sa][4 * half];
+      pw[0] = va ? cmul(b4, inv) : zero;
+      pw[1] = va ? cmul(b4, i2) : zero;
+      pw[2] = va ? cmul(b4, i3) : zero;
+      pw[3] = va ? cmul(b4, i4) : zero;
+      if (half == 0) t_lg[wv][sa] = va ? log_tab(r2, lt) : 0.0;
+    }
+    __syncthreads();
     if (!active) continue;
     const int nks = (nb + 3) >> 2;
     for (int ks = 0; ks < nks; ++ks) {
       const int sl = 4 * ks + kk;
-      const bool valid = sl < nb;
-      const double2 y = t_y[sl], nv = t_n[sl];
-      const double2 z = make_double2(y.x - cc.x, y.y - cc.y);
-      const double r2 = valid ? cnorm2(z) : 1.0;
-      const double ir2 = rcp_nr(r2);
-      const double2 inv = make_double2(z.x * ir2, -z.y * ir2);
-      const double2 i2 = cmul(inv, inv), i4 = cmul(i2, i2), i8 = cmul(i4, i4);
-      const int e = h + 1;  // 1..8
-      const double2 one = make_double2(1.0, 0.0);
-      double2 pw = cmul(cmul((e & 1) ? inv : one, (e & 2) ? i2 : one),
-                        cmul((e & 4) ? i4 : one, (e & 8) ? i8 : one));
-      double lg = 0.0;
-      if (i == LI) lg = log_tab(r2, lt);
+      const double2 nv = t_n[sl];
+      double2 pwr = t_pw[wv][sl][h];         // z^-(h + 1)
+      const double2 i8 = t_pw[wv][sl][7];   // z^-8
+      const double lg = t_lg[wv][sl];
       double aS[RTS], aD[RTD];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int r = 16 * rt + i;
         if (rt < RTS) {
-          double a = comp ? pw.y : pw.x;
+          double a = comp ? pwr.y : pwr.x;
           if (r >= 2 * PQ) a = (rt == LRT && i == LI) ? lg : 0.0;
-          aS[rt < RTS ? rt : 0] = valid ? a : 0.0;
+          aS[rt < RTS ? rt : 0] = a;
         }
         if (rt < RTD) {
-          const double2 w = cmul(nv, pw);
-          const double a = r < 2 * PQ + 2 ? (comp ? w.y : w.x) : 0.0;
-          aD[rt < RTD ? rt : 0] = valid ? a : 0.0;
+          const double2 w = cmul(nv, pwr);
+          aD[rt < RTD ? rt : 0] = r < 2 * PQ + 2 ? (comp ? w.y : w.x) : 0.0;
         }
-        if (rt + 1 < RT) pw = cmul(pw, i8);
+        if (rt + 1 < RT) pwr = cmul(pwr, i8);
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -2233,8 +2254,8 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   if (nd >= kNearMfmaMin && nm > 0) {
     // one GEMM per center over the sources and a block of densities on the matrix cores
     constexpr int NT = PQ <= 12 ? 4 : 2;
-    hipLaunchKernelGGL((k_near_mfma<PQ, NT>), dim3(nm, (nd + 16 * NT - 1) / (16 * NT)),
-                       dim3(256), 0, s, d.near_mitems + 2 * bk.nmf0, d.near_src, d.cxy, d.cr,
+    hipLaunchKernelGGL((k_near_mfma<PQ, NT>), dim3((uint32_t)nm, (nd + 16 * NT - 1) / (16 * NT)),
+                       dim3(256), 0, s, nm, d.near_mitems + 2 * bk.nmf0, d.near_src, d.cxy, d.cr,
                        d.sxy, d.snrm, d.sq, d.anear, ctx->params.p_qbx + 1, S.src, S.row, nd,
                        (int64_t)nd);
     return;
@@ -2326,7 +2347,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     if (use_p2x_mfma<KIND, E>(nd)) {
       auto kern = P1 <= 32 ? k_p2x_mfma<0, 2> : k_p2x_mfma<0, 4>;
       hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, (nd + 63) / 64), dim3(256), 0, st,
-                         d.p2m_item, nullptr, d.bc, d.blevel, d.level_inv_side, d.level_log_side,
+                         (int32_t)ctx->n_p2m_items, d.p2m_item, nullptr, d.bc, d.blevel, d.level_inv_side, d.level_log_side,
                          d.sxy, d.snrm, d.sq, P1, reinterpret_cast<double2 *>(M), d.Mp, S.src,
                          S.box, part_st, nd, (int64_t)nd * S.box);
     } else {
@@ -2369,7 +2390,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
       auto kern = P1 <= 16 ? k_m2l_slots<1, E> : P1 <= 32 ? k_m2l_slots<2, E>
                 : P1 <= 48 ? k_m2l_slots<3, E> : k_m2l_slots<4, E>;
       hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2l_items, (slots + 8 * nw - 1) / (8 * nw)),
-                         dim3(64 * nw), 0, st, d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt,
+                         dim3(64 * nw), 0, st, (int32_t)ctx->n_m2l_items, d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt,
                          X.opow, P1, L, S.box, slots);
     } else {
       auto kern = P1 <= 16 ? k_m2l_mb<1, E> : P1 <= 32 ? k_m2l_mb<2, E>
@@ -2381,7 +2402,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
       if (use_p2x_mfma<KIND, E>(nd)) {
         auto kp = P1 <= 32 ? k_p2x_mfma<1, 2> : k_p2x_mfma<1, 4>;
         hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, (nd + 63) / 64), dim3(256), 0,
-                           st, d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
+                           st, (int32_t)ctx->n_p2l_boxes, d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
                            d.level_log_side, d.sxy, d.snrm, d.sq, P1,
                            reinterpret_cast<double2 *>(L), nullptr, S.src, S.box, (int64_t)0, nd,
                            (int64_t)nd * S.box);
@@ -2401,7 +2422,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
       auto kern = P1 <= 16 ? k_l2l_slots<1, E> : P1 <= 32 ? k_l2l_slots<2, E>
                 : P1 <= 48 ? k_l2l_slots<3, E> : k_l2l_slots<4, E>;
       hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_l2g_items, (slots + 8 * nw - 1) / (8 * nw)),
-                         dim3(64 * nw), 0, st, d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1,
+                         dim3(64 * nw), 0, st, (int32_t)ctx->n_l2g_items, d.l2g_item, d.l2g_pr, d.l2g_tw, d.l2g_binom_t, P1,
                          L, Lf, S.box, slots);
     } else {
       auto kern = P1 <= 16 ? k_l2l_gather<1, E> : P1 <= 32 ? k_l2l_gather<2, E>
