@@ -696,16 +696,19 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
 // Coefficients as k_p2m_all / k_p2l write them: S a_0 = sum q, a_k = -A_k / k (MODE 0), the log
 // sum and -A_k / k (MODE 1); D from its rows directly. MODE 0 items of split boxes write partial
 // rows for k_m_reduce; MODE 1 adds to the box locals that M2L wrote.
-template <int MODE, int TPW>
+template <int MODE, int TPW, typename E>
 __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ src_idx,
     const double2 *__restrict__ bc, const int32_t *__restrict__ blevel,
     const double *__restrict__ level_inv_side, const double *__restrict__ level_log_side,
     const double2 *__restrict__ sxy, const double2 *__restrict__ snrm,
-    const double *__restrict__ sq, int P1, double2 *__restrict__ Out,
+    const double *__restrict__ sq, int P1, E *__restrict__ Out,
     double2 *__restrict__ Mp, int64_t src_st, int64_t box_st, int64_t part_st, int nd,
     int64_t d_off) {
   critical_path_priority();
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
+  constexpr bool F64 = sizeof(R) == 8;
   constexpr int NT = 4, NDB = 64, SB = 32, SST = SB + 4;
   __shared__ double t_q[NDB][SST];
   __shared__ double2 t_y[SB], t_n[SB];
@@ -754,11 +757,18 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
     trt[u] = tis_d[u] ? t - RTS : t;
     tact[u] = t < RTS + RTD;
   }
-  gq_d4 C[TPW][NT];
+  // FP32 products are summed over one batch on the matrix cores, then into FP64 sums
+  Acc C[TPW][NT];
+  double Cd[F64 ? 1 : TPW][F64 ? 1 : NT][4];
 #pragma unroll
   for (int u = 0; u < TPW; ++u)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) C[u][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+    for (int nt = 0; nt < NT; ++nt) {
+      C[u][nt] = Acc{R(0), R(0), R(0), R(0)};
+      if (!F64)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Cd[F64 ? 0 : u][F64 ? 0 : nt][v] = 0.0;
+    }
   load(0);
   for (int32_t base = 0; base < len; base += SB) {
     const int nb = min(SB, (int)(len - base));
@@ -790,7 +800,7 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
       const double2 x2 = cmul(x, x), x4 = cmul(x2, x2), x8 = cmul(x4, x4);
       const double2 xh = cmul(cmul((h & 1) ? x : one, (h & 2) ? x2 : one), (h & 4) ? x4 : one);
       const double2 nd_s = make_double2(nv.x * is, nv.y * is);  // n / s
-      double a[TPW];
+      R a[TPW];
 #pragma unroll
       for (int u = 0; u < TPW; ++u) {
         double2 p = xh;
@@ -808,19 +818,28 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
           val = comp ? w.y : w.x;
           if (k >= (MODE == 0 ? P1 - 1 : P1)) val = 0.0;
         }
-        a[u] = (valid && tact[u]) ? val : 0.0;
+        a[u] = (R)((valid && tact[u]) ? val : 0.0);
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const double bq = t_q[16 * nt + i][sl];
+        const R bq = (R)t_q[16 * nt + i][sl];
 #pragma unroll
         for (int u = 0; u < TPW; ++u) C[u][nt] = mfma16(a[u], bq, C[u][nt]);
       }
     }
+    if (!F64) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cd[F64 ? 0 : u][F64 ? 0 : nt][v] += (double)C[u][nt][v];
+          C[u][nt] = Acc{R(0), R(0), R(0), R(0)};
+        }
+    }
   }
-  // lane (column j, group g) holds rows 16 rt + g + 4 v: order 8 rt + g/2 + 2 v, part g & 1
+  // lane (column j, group g) holds rows 16 rt + row(g, v): order 8 rt + row/2, part row & 1
   const int g = kk, j = i;
-  const int gc = g & 1;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int dj = d0 + 16 * nt + j;
@@ -830,8 +849,9 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
       if (!tact[u]) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int k = 8 * trt[u] + (g >> 1) + 2 * v;
-        const double y = C[u][nt][v];
+        const int rin = Mfma16<R>::row(g, v);
+        const int k = 8 * trt[u] + (rin >> 1), gc = rin & 1;
+        const double y = F64 ? (double)C[u][nt][v] : Cd[F64 ? 0 : u][F64 ? 0 : nt][v];
         int coef;
         double val;
         if (!tis_d[u]) {
@@ -850,16 +870,16 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
             o[2 * ((tis_d[u] ? P1 : 0) + coef) + gc] = val;
             if (!tis_d[u] && k == 0) o[2 * P1 + gc] = 0.0;  // D coefficient 0
           } else {
-            double *o = reinterpret_cast<double *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
-                                                   (int64_t)b * P1);
-            o[2 * coef + gc] = val;
+            R *o = reinterpret_cast<R *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
+                                         (int64_t)b * P1);
+            o[2 * coef + gc] = (R)val;
             if (!tis_d[u] && k == 0)
-              reinterpret_cast<double *>(Out + (int64_t)dj * box_st + d_off + (int64_t)b * P1)[gc] = 0.0;
+              reinterpret_cast<R *>(Out + (int64_t)dj * box_st + d_off + (int64_t)b * P1)[gc] = R(0);
           }
         } else {
-          double *o = reinterpret_cast<double *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
-                                                 (int64_t)b * P1);
-          o[2 * coef + gc] += val;
+          R *o = reinterpret_cast<R *>(Out + (int64_t)dj * box_st + (tis_d[u] ? d_off : 0) +
+                                       (int64_t)b * P1);
+          o[2 * coef + gc] = (R)((double)o[2 * coef + gc] + val);
         }
       }
     }
@@ -997,8 +1017,9 @@ __global__ void __launch_bounds__(64) k_p2l(
 //   beta_m = sum_{j>=m} C(j,m) t^(j-m) (s_b/s_a)^m alpha_j = u^-m sum_{j>=m} C(j,m) (t^j alpha_j),
 // so the pair-dependent parts are diagonal and the fixed binomial matrix runs on the FP64 matrix
 // cores, 8 pairs (16 real columns) per step, as in M2L. |t| < 2^-1/2 and |u| > 2^-1/2 for every
-// ancestor: t^j only underflows where its term is negligible and u^-m < 2^(m/2). Arithmetic in
-// FP64 whatever the storage type E.
+// ancestor: t^j only underflows where its term is negligible and u^-m < 2^(m/2). The products run
+// on the matrix cores in the expansion precision (FP32 for mixed-precision expansions), the
+// diagonal factors and the sums in FP64.
 // The (box, ancestor) pairs of all boxes owning centers are one flat list in box order; a
 // wavefront takes a run of whole boxes (about 64 pairs) in batches of 8 consecutive pairs, which
 // may span boxes (each matrix-core column is its own pair), fetching the next batch's records and
@@ -1011,7 +1032,10 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
     const double4 *__restrict__ anc_tw, const double *__restrict__ binom_t, int P1,
     const E *__restrict__ L, E *__restrict__ Lf, int64_t box_st) {
   critical_path_priority();
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
   constexpr int KS = 4 * RT;
+  constexpr bool F64 = sizeof(R) == 8;
   __shared__ double2 Pt[8][16 * RT];  // one batch's shifted rows, per pair
   __shared__ int32_t Pb[8];
   const int2 it = items[blockIdx.x];  // first pair, end of pairs
@@ -1024,13 +1048,13 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
   const int g = lane >> 4, c16 = lane & 15;
   const int pr = c16 >> 1, comp = c16 & 1;
   // C(k, i) is zero below the diagonal: row tile rt only needs k-steps ks >= 4 rt
-  double A[RT][KS];
+  R A[RT][KS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int i = 16 * rt + c16, k = 4 * ks + g;
-      A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? binom_t[k * P1 + i] : 0.0;
+      A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? (R)binom_t[k * P1 + i] : R(0);
     }
   int2 rec;
   double4 tw;
@@ -1070,35 +1094,37 @@ __global__ void __launch_bounds__(64) k_l2l_gather(
     double2 pw = make_double2(1.0, 0.0);
     for (int e = 0; e < g; ++e) pw = cmul(pw, t);
     const double2 t2 = cmul(t, t), t4 = cmul(t2, t2);
-    double Bf[KS];
+    R Bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const double2 v = cmul(pw, lac[ks]);
-      Bf[ks] = comp ? v.y : v.x;
+      Bf[ks] = (R)(comp ? v.y : v.x);
       pw = cmul(pw, t4);
     }
-    gq_d4 C[RT];
+    Acc C[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      C[rt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+      C[rt] = Acc{R(0), R(0), R(0), R(0)};
 #pragma unroll
       for (int ks = 4 * rt; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
     }
     // row m = 16 rt + g + 4 v of column pair pr: times u^-m, into Pt[pr][m]
+    // FP64 rows 16 rt + g + 4 v, FP32 rows 16 rt + 4 g + v: u^-m from u^-(row of v = 0)
     double2 wg = make_double2(1.0, 0.0);
-    for (int e = 0; e < g; ++e) wg = cmul(wg, w);
+    for (int e = 0; e < (F64 ? g : 4 * g); ++e) wg = cmul(wg, w);
     const double2 w2 = cmul(w, w), w4 = cmul(w2, w2), w8 = cmul(w4, w4), w16 = cmul(w8, w8);
+    const double2 wstep = F64 ? w4 : w;
     double2 wr = wg;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       double2 wv = wr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = 16 * rt + Mfma16<double>::row(g, v);
-        const double y = C[rt][v];
+        const int m = 16 * rt + Mfma16<R>::row(g, v);
+        const double y = (double)C[rt][v];
         const double yo = lane_xor1(y);
         if (!comp) Pt[pr][m] = cmul(make_double2(y, yo), wv);
-        wv = cmul(wv, w4);
+        wv = cmul(wv, wstep);
       }
       wr = cmul(wr, w16);
     }
@@ -2171,11 +2197,17 @@ constexpr int kSlotGemmMin = 8;
 // Densities of a GQ_S_AND_D batch from which the direct interactions run on the matrix cores.
 constexpr int kNearMfmaMin = 8;
 
-// The direct moments and P2L of a GQ_S_AND_D batch on the matrix cores (FP64 expansions, at least
-// kNearMfmaMin densities).
+// The direct moments and P2L of a GQ_S_AND_D batch on the matrix cores (in the expansion
+// precision), from kNearMfmaMin densities.
+// FP32 expansions up to 32 coefficients (two row tiles per wavefront, no spills).
 template <int KIND, typename E>
-bool use_p2x_mfma(int nd) {
-  return KIND == 4 && sizeof(E) == sizeof(double2) && nd >= kNearMfmaMin;
+bool use_p2x_mfma(int nd, int P1) {
+  return KIND == 4 && nd >= kNearMfmaMin && (sizeof(E) == sizeof(double2) || P1 <= 32);
+}
+template <int MODE, typename E>
+auto p2x_kernel(int P1) {
+  if constexpr (sizeof(E) == sizeof(double2)) return P1 <= 32 ? k_p2x_mfma<MODE, 2, E> : k_p2x_mfma<MODE, 4, E>;
+  else return k_p2x_mfma<MODE, 2, E>;
 }
 
 // Per-density strides of the batched buffers (elements).
@@ -2344,11 +2376,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int64_t part_st = ctx->n_p2m_parts * 2 * P1;
   if (ctx->n_p2m_items > 0) {
     StageTimer st_(ctx, GQ_STAGE_P2M);
-    if (use_p2x_mfma<KIND, E>(nd)) {
-      auto kern = P1 <= 32 ? k_p2x_mfma<0, 2> : k_p2x_mfma<0, 4>;
+    if (use_p2x_mfma<KIND, E>(nd, P1)) {
+      auto kern = p2x_kernel<0, E>(P1);
       hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_p2m_items, (nd + 63) / 64), dim3(256), 0, st,
                          (int32_t)ctx->n_p2m_items, d.p2m_item, nullptr, d.bc, d.blevel, d.level_inv_side, d.level_log_side,
-                         d.sxy, d.snrm, d.sq, P1, reinterpret_cast<double2 *>(M), d.Mp, S.src,
+                         d.sxy, d.snrm, d.sq, P1, M, d.Mp, S.src,
                          S.box, part_st, nd, (int64_t)nd * S.box);
     } else {
       auto kern = P1 <= 8 ? k_p2m_all<PK, 1, E> : P1 <= 16 ? k_p2m_all<PK, 2, E>
@@ -2399,12 +2431,12 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
                          d.m2l_item, d.m2l_pr, d.m2l_plog, M, X.m2l_bt, X.opow, P1, L, S.box);
     }
     if (ctx->n_p2l_boxes > 0) {
-      if (use_p2x_mfma<KIND, E>(nd)) {
-        auto kp = P1 <= 32 ? k_p2x_mfma<1, 2> : k_p2x_mfma<1, 4>;
+      if (use_p2x_mfma<KIND, E>(nd, P1)) {
+        auto kp = p2x_kernel<1, E>(P1);
         hipLaunchKernelGGL(kp, dim3((uint32_t)ctx->n_p2l_boxes, (nd + 63) / 64), dim3(256), 0,
                            st, (int32_t)ctx->n_p2l_boxes, d.p2l_item, d.p2l_src, d.bc, d.blevel, d.level_inv_side,
-                           d.level_log_side, d.sxy, d.snrm, d.sq, P1,
-                           reinterpret_cast<double2 *>(L), nullptr, S.src, S.box, (int64_t)0, nd,
+                           d.level_log_side, d.sxy, d.snrm, d.sq, P1, L, nullptr, S.src, S.box,
+                           (int64_t)0, nd,
                            (int64_t)nd * S.box);
       } else {
         auto kp = P1 <= 8 ? k_p2l<PK, 1, E> : P1 <= 16 ? k_p2l<PK, 2, E>

@@ -574,3 +574,23 @@ def test_s_and_d_batch_on_matrix_cores(p_qbx, p_fmm):
     for kind, row in ((1, n - 1), (2, 2 * n - 1)):
         ref = oracle.qbx_eval(g, kind, h[n - 1], None, p_qbx=p_qbx)
         assert _rel(both[row], ref) < 1e-10, kind
+
+
+def test_s_and_d_batch_mixed_precision():
+    """FP32 box expansions for a batch of 20 densities of S and D: moments, P2L, M2L and the
+    Stage 7 gather on the FP32 matrix cores (per-batch FP32 products summed in FP64), the direct
+    pass on the FP64 matrix cores; against the oracle at the mixed-precision gate 1e-6, and the
+    single-density mixed evaluation (vector-unit moments and P2L, FP32 matrix-core M2L and
+    gather) to the same gate."""
+    from paper_1801_04070_amd import GQ_MIXED_FP32, GQ_S_AND_D
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=16, precision=GQ_MIXED_FP32)
+    n = 20
+    h = np.stack([gi.fourier_density(g, seed=500 + j) for j in range(n)])
+    both = q.eval(GQ_S_AND_D, _dev(h)).cpu().numpy()
+    one = q.eval(GQ_S_AND_D, _dev(h[n - 1])).cpu().numpy()
+    for kind, row, orow in ((1, n - 1, 0), (2, 2 * n - 1, 1)):
+        ref = oracle.qbx_eval(g, kind, h[n - 1], None, p_qbx=12)
+        e_b, e_1 = _rel(both[row], ref), _rel(one[orow], ref)
+        print(f"mixed S_AND_D kind={kind}: batch {e_b:.3e} single {e_1:.3e}")
+        assert e_b < 1e-6 and e_1 < 1e-6
