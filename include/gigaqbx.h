@@ -145,6 +145,28 @@ gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int6
                                 int64_t n_tgt, const double *tgt_xy, const int32_t *tgt_ctr);
 
 /*
+ * Target-to-center association for targets anywhere in the plane (Sec. 2.2.2: identify the
+ * targets too close to the curve for plain quadrature and find a QBX center for each). Host
+ * arrays, no context. For each of the n_tgt targets, with rho = min over centers of
+ * |x - c| / r_c (ties to the lowest center index):
+ *   rho <= 1 + slack:           QBX target of that center: tgt_ctr[t] = (c, -1) (one-sided value
+ *                               at the center's side of the curve); slack 0.2 is the 20 % the
+ *                               paper reports as harmless, 0 admits only targets in a disk;
+ *   1 + slack < rho < far_factor: in a coverage gap next to the curve (the paper refines the
+ *                               geometry there): tgt_ctr[t] = (-1, -1) like a far target, and
+ *                               counted in *n_gap (may be NULL) so the caller can refine;
+ *   rho >= far_factor:          conventional target: tgt_ctr[t] = (-1, -1).
+ * The output feeds gq_set_geometry's tgt_ctr (centers in the same order). Needs slack >= 0 and a
+ * finite far_factor >= 1 + slack, finite coordinates and positive radii (else GQ_EINVAL; message
+ * from gq_associate_last_error()). Runs on host threads; the query is an area query on a grid
+ * whose cells hold the centers whose disks of radius far_factor r_c they overlap.
+ */
+gq_status gq_associate_targets(int64_t n_ctr, const double *ctr_xy, const double *ctr_r,
+                               int64_t n_tgt, const double *tgt_xy, double slack,
+                               double far_factor, int32_t *tgt_ctr, int64_t *n_gap);
+const char *gq_associate_last_error(void);
+
+/*
  * Stage 1 and Sec. 4.3: build the quadtree (root square covering every particle and every whole
  * QBX disk; a center stays in a box when its disk does not fit the child's target confinement
  * region), sort particles into tree order, build Lists 1, 2, 3-close/far, 4-close/far, and upload

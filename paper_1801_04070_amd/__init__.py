@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64,
                    GQ_MIXED_FP32, gq_params, gq_stats)
 
-__all__ = ["QBXFMM", "GQError", "library", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "GQ_S_AND_D",
+__all__ = ["QBXFMM", "GQError", "library", "associate_targets", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "GQ_S_AND_D",
            "default_params"]
 
 _L = None
@@ -41,6 +41,21 @@ def __getattr__(name):
     if name in _lib.EXPORTED or name in _lib.EXPORTED_MLP:
         return getattr(library(), name)
     raise AttributeError(name)
+
+
+def associate_targets(ctr_xy, ctr_r, tgt_xy, slack: float = 0.2, far_factor: float = 3.0):
+    """gq_associate_targets on host arrays: returns (tgt_ctr (n_tgt, 2) int32, n_gap)."""
+    L = library()
+    c = np.ascontiguousarray(ctr_xy, dtype=np.float64).reshape(-1, 2)
+    r = np.ascontiguousarray(ctr_r, dtype=np.float64)
+    t = np.ascontiguousarray(tgt_xy, dtype=np.float64).reshape(-1, 2)
+    out = np.empty((t.shape[0], 2), dtype=np.int32)
+    gap = C.c_int64()
+    st = L.gq_associate_targets(len(r), c.ctypes.data, r.ctypes.data, t.shape[0], t.ctypes.data,
+                                float(slack), float(far_factor), out.ctypes.data, C.byref(gap))
+    if st != 0:
+        raise GQError(st, L.gq_associate_last_error().decode())
+    return out, gap.value
 
 
 class GQError(RuntimeError):

@@ -56,7 +56,8 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
-            "gq_get_params", "gq_device_math", "gq_eval_noalloc", "gq_last_error"]
+            "gq_get_params", "gq_device_math", "gq_eval_noalloc", "gq_associate_targets",
+            "gq_associate_last_error", "gq_last_error"]
 
 
 EXPORTED_MLP = ["gq_mlp_create", "gq_mlp_destroy", "gq_mlp_param_count", "gq_mlp_set_params",
@@ -95,10 +96,14 @@ def load(path: str = LIB_PATH):
     L.gq_autotune.argtypes = [vp, i32, dp, i64, i32, C.POINTER(C.c_double)]
     L.gq_get_params.argtypes = [vp, C.POINTER(gq_params)]
     L.gq_device_math.argtypes = [vp, i32, i64, dp, dp]
+    L.gq_associate_targets.argtypes = [i64, dp, dp, i64, dp, C.c_double, C.c_double, ip,
+                                       C.POINTER(C.c_int64)]
+    L.gq_associate_last_error.argtypes = []
+    L.gq_associate_last_error.restype = C.c_char_p
     L.gq_last_error.argtypes = [vp]
     L.gq_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name != "gq_last_error":
+        if name not in ("gq_last_error", "gq_associate_last_error"):
             getattr(L, name).restype = C.c_int
     # include/gigaqbx_mlp.h
     L.gq_mlp_create.argtypes = [C.POINTER(C.c_void_p), i32, vp, i32, i32, i32, C.c_uint64]

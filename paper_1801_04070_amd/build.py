@@ -24,7 +24,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 
 HIP_SOURCES = ["kernels.hip", "api.cpp", "mlp.hip", "orders.hip"]
-CXX_SOURCES = ["tree.cpp", "tables.cpp"]
+CXX_SOURCES = ["tree.cpp", "tables.cpp", "assoc.cpp"]
 
 
 def _run(cmd, verbose):

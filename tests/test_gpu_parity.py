@@ -594,3 +594,35 @@ def test_s_and_d_batch_mixed_precision():
         e_b, e_1 = _rel(both[row], ref), _rel(one[orow], ref)
         print(f"mixed S_AND_D kind={kind}: batch {e_b:.3e} single {e_1:.3e}")
         assert e_b < 1e-6 and e_1 < 1e-6
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_off_surface_targets_by_association(kind):
+    """Targets anywhere in the plane (Sec. 2.2.2): pushed off the curve by up to 2.2 center radii
+    along the normal, plus points all over the bounding box. gq_associate_targets gives each a
+    center (inside its disk or within the 20 % slack) or leaves it to the conventional paths
+    (point value: direct sum, multipole-to-point, local-to-point). One evaluation for all of them
+    against the oracle's one-sided QBX at the associated centers and its plain point sums."""
+    from paper_1801_04070_amd import associate_targets
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    rng = np.random.default_rng(40 + kind)
+    i = rng.integers(0, g.n_src, 3000)
+    near = g.src_xy[i] + rng.uniform(-2.2, 2.2, 3000)[:, None] * g.ctr_r[2 * i][:, None] * g.src_nrm[i]
+    lo, hi = g.src_xy.min(0) - 1.0, g.src_xy.max(0) + 1.0
+    tgt = np.concatenate([near, rng.uniform(lo, hi, (2000, 2))])
+    tc, n_gap = associate_targets(g.ctr_xy, g.ctr_r, tgt, slack=0.2, far_factor=3.0)
+    qbx = tc[:, 0] >= 0
+    assert qbx.sum() > 1500 and (~qbx).sum() > 1500
+    e = copy.copy(g)
+    e.tgt_xy, e.tgt_ctr = tgt, tc
+    q, stats = _ctx(e, p_qbx=12, p_fmm=30)
+    assert stats["n_point_targets"] == (~qbx).sum()
+    mu, mu2 = _densities(g, 8)
+    d2 = mu2 if kind == 3 else None
+    gpu = _run(q, kind, mu, mu2)
+    ref_q = oracle.qbx_eval(g, kind, mu, d2, p_qbx=12, tgt_xy=tgt[qbx], tgt_ctr=tc[qbx])
+    ref_p = oracle.point_potential(g, kind, mu, d2, tgt_xy=tgt[~qbx])
+    e_q, e_p = _rel(gpu[qbx], ref_q), _rel(gpu[~qbx], ref_p)
+    print(f"off-surface kind={kind}: qbx {qbx.sum()} ({e_q:.2e}), conventional {(~qbx).sum()} "
+          f"({e_p:.2e}), gaps {n_gap}")
+    assert e_q < 1e-10 and e_p < 1e-10
