@@ -184,7 +184,9 @@ def ragged_variant(timer, steps, warmup, n_geoms=32, p_qbx=12, p_fmm=30):
 
 
 def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192):
-    """Learned per-center QBX orders against the smallest uniform order meeting the tolerance.
+    """Learned per-center QBX orders against the smallest uniform order meeting the tolerance
+    (found by trying the candidates against the exact solution) and against the configured
+    uniform order p_qbx 12.
 
     Workload: 8 x 8 lattice of wavy curves (seed 300) whose neighbours nearly touch (gap of four
     expansion radii), `panels` panels x 16 nodes per curve (192: 196608 on-surface targets and
@@ -234,6 +236,11 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192)
         return {"status": "no uniform candidate order meets the tolerance", "uniform": uniform}
     ms_u = timer.run_plain(step, steps, warmup)
     _, st_u = timer.run(q, step, steps, 1)
+    # the configured uniform order of the method (p_qbx 12, as in the 16-star workload), which a
+    # user without the network runs; the smallest uniform order above needs the exact solution
+    q.set_qbx_orders(np.full(g.n_ctr, 12, np.int32))
+    e_12 = round(log10_err(), 2)
+    ms_12 = timer.run_plain(step, steps, warmup)
     t0 = time.perf_counter()
     orders = learned.choose_orders(q, log10_tol, model)
     torch.cuda.synchronize()
@@ -250,12 +257,16 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192)
     return {"value": round(v_l, 1), "unit": "targets/s", "ms_per_step": round(ms_l, 4),
             "uniform_value": round(v_u, 1), "uniform_ms_per_step": round(ms_u, 4),
             "speedup_vs_uniform": round(v_l / v_u, 3), "log10_tol": log10_tol,
+            "configured_order_value": round(g.n_tgt / (ms_12 * 1e-3), 1),
+            "configured_order_ms_per_step": round(ms_12, 4), "configured_order_log10_err": e_12,
+            "speedup_vs_configured_order": round(ms_12 / ms_l, 3),
             "p_uniform": p_u, "uniform_log10_err": uniform, "learned_log10_err": e_l,
             "status": "ok" if e_l <= log10_tol else "FAILED",
             "learned_order_histogram": {int(p): int(hist[p]) for p in model.candidates},
             "choose_orders_s": round(choose_s, 3), "build_s": round(build_s, 1),
             "stage_ms_per_step_uniform": bd_u, "stage_ms_per_step_learned": bd_l,
             "steps": steps, "p_fmm": p_fmm,
+            "learned_mean_order": round(float(orders.float().mean()), 3),
             "workload": f"8x8 wavy lattice (gap 4 radii), {panels} panels per curve, "
                         f"{g.n_tgt} targets, {g.n_ctr} centers, {g.n_src} upsampled sources, "
                         "Green's formula, FP64"}
@@ -558,6 +569,13 @@ def main():
             variants[name] = learned_variant(timer, max(2, args.steps // 4), max(1, args.warmup),
                                              log10_tol=tol)
             log(f"bench: {name}: {variants[name].get('speedup_vs_uniform')}x")
+        # the learned-order workload as specified: 8 x 8 wavy curves, 1024 panels each
+        # (1048576 targets, 2097152 centers, 4194304 upsampled sources), tolerance 1e-8
+        log("bench: learned orders, 1048576-target wavy lattice, tolerance 1e-8")
+        variants["learned_orders_1e-8_1m"] = learned_variant(timer, 3, 1, log10_tol=-8.0,
+                                                             panels=1024)
+        log(f"bench: learned_orders_1e-8_1m: "
+            f"{variants['learned_orders_1e-8_1m'].get('speedup_vs_uniform')}x")
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,

@@ -204,7 +204,7 @@ gq_status gq_eval(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1, in
  * Same contract as gq_eval, computed by unaccelerated QBX on the GPU: every center's expansion
  * (eq. (qbx)) is formed from all sources directly, without tree or lists (needs only
  * gq_set_geometry and gq_build for the orders). Each center uses the same order as in gq_eval
- * (its box's order after gq_set_qbx_orders). O(n_ctr n_src) work; for checking and small
+ * (gq_get_center_orders). O(n_ctr n_src) work; for checking and small
  * problems.
  */
 gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *dens1,
@@ -233,11 +233,16 @@ gq_status gq_eval_noalloc(gq_ctx *ctx, int kind, int64_t n_dens, const double *d
  * Per-center QBX orders (the truncation order p of eq. (qbx) may differ between centers; Sec. 4.1
  * chooses it from the truncation error, which depends on the local geometry). orders[c] (n_ctr
  * int32, caller order, host or device memory per mem; NULL restores the uniform p_qbx) must lie in
- * 0..p_qbx of the last gq_build. Every box then runs at the smallest compiled order that is at
- * least the largest order of its centers, and the direct, List 3 far and center work is regrouped
- * by order. Synchronous. Call after gq_build; a new gq_build resets to the uniform order.
+ * 0..p_qbx of the last gq_build. Every center then runs at the smallest compiled order that is at
+ * least its own (gq_get_center_orders): the centers inside each box are regrouped by that order
+ * (GQ_TREE_CTR_ORDER changes accordingly) and the direct, List 3 far and per-center work of each
+ * group runs at the group's order. Results per center do not depend on the regrouping.
+ * Synchronous. Call after gq_build; a new gq_build resets to the uniform order.
  */
 gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders);
+
+/* The compiled QBX order each center runs at (n_ctr int32, caller order, host memory `dst`). */
+gq_status gq_get_center_orders(gq_ctx *ctx, int32_t *dst);
 
 /* Tune the work-item shapes (gq_params near_chunk, far_chunk, far_pairs_per_lane) for this
  * built context: each of a fixed set of candidate shapes is timed over `reps` evaluations of
@@ -252,8 +257,9 @@ gq_status gq_autotune(gq_ctx *ctx, int kind, const double *dens1, int64_t ld1, i
 /* The parameters of the last gq_build (after gq_autotune: with the chosen shapes). */
 gq_status gq_get_params(gq_ctx *ctx, gq_params *out);
 
-/* Copy the QBX order used by each box (n_boxes int32, breadth-first box order) to host memory
- * `dst` (NULL to query the count, always written to *count). */
+/* Copy the largest QBX order run in each box (n_boxes int32, breadth-first box order; the
+ * smallest compiled order for a box without centers) to host memory `dst` (NULL to query the
+ * count, always written to *count). */
 gq_status gq_get_box_orders(gq_ctx *ctx, int32_t *dst, int64_t *count);
 
 /*

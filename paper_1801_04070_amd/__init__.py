@@ -227,6 +227,12 @@ class QBXFMM:
             o = orders.to(torch.int32).contiguous()
             self._check(self._L.gq_set_qbx_orders(self._h, GQ_MEM_DEVICE, o.data_ptr()))
 
+    def center_orders(self) -> np.ndarray:
+        """The compiled QBX order each center runs at (caller order)."""
+        out = np.empty(self.n_ctr, dtype=np.int32)
+        self._check(self._L.gq_get_center_orders(self._h, out.ctypes.data))
+        return out
+
     def box_orders(self) -> np.ndarray:
         n = C.c_int64()
         self._check(self._L.gq_get_box_orders(self._h, None, C.byref(n)))

@@ -54,7 +54,8 @@ GQ_N_STAGES = len(GQ_STAGE_NAMES)
 EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq_set_geometry",
             "gq_set_geometry_batch",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
-            "gq_set_qbx_orders", "gq_get_box_orders", "gq_set_profiling", "gq_get_stage_times",
+            "gq_set_qbx_orders", "gq_get_box_orders", "gq_get_center_orders",
+            "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
             "gq_get_params", "gq_device_math", "gq_eval_noalloc", "gq_associate_targets",
             "gq_associate_last_error", "gq_last_error"]
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
     L.gq_get_tree_array.argtypes = [vp, i32, vp, C.POINTER(C.c_int64)]
     L.gq_set_qbx_orders.argtypes = [vp, i32, vp]
     L.gq_get_box_orders.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    L.gq_get_center_orders.argtypes = [vp, vp]
     L.gq_set_profiling.argtypes = [vp, i32]
     L.gq_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.gq_graph_create.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64, C.POINTER(C.c_void_p)]

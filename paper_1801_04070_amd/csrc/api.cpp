@@ -240,17 +240,29 @@ gq_status build_near_work(gq_ctx *ctx) {
     bk.ctr0 = (int64_t)clist.size();
     for (int64_t b = 0; b < nb; ++b) {
       const int64_t nc = t.ctr_end[b] - t.ctr_begin[b];
-      if (nc == 0 || ctx->box_pq[b] != pq) continue;
+      if (nc == 0) continue;
+      // the box's centers of this order: one contiguous group (centers are ordered by QBX order
+      // within each box); rows stay those of the whole box, [chunk][center of the box]
+      int64_t g0 = t.ctr_begin[b], g1 = t.ctr_end[b];
+      if (!ctx->ctr_pq.empty()) {
+        while (g0 < g1 && ctx->ctr_pq[g0] != pq) ++g0;
+        g1 = g0;
+        while (g1 < t.ctr_end[b] && ctx->ctr_pq[g1] == pq) ++g1;
+      } else if (ctx->params.p_qbx != pq) {
+        continue;
+      }
+      const int64_t ng = g1 - g0, gl = g0 - t.ctr_begin[b];
+      if (ng == 0) continue;
       const int64_t len = box_src_len[b];
       const int64_t nchunks = (len + near_chunk - 1) / near_chunk;
       for (int64_t j = 0; j < nchunks; ++j) {
         const int64_t c0 = j * near_chunk, clen = std::min<int64_t>(near_chunk, len - c0);
-        emit_near(items, box_src_off[b] + c0, clen, t.ctr_begin[b], base[b] + j * nc, nc,
-                  pick_slices(nc, clen, 10.0 * pq));
-        for (int64_t cb = 0; cb < nc; cb += 4) {
-          const int32_t it[8] = {(int32_t)(box_src_off[b] + c0), (int32_t)clen,
-                                 (int32_t)(t.ctr_begin[b] + cb), (int32_t)(base[b] + j * nc + cb),
-                                 (int32_t)std::min<int64_t>(4, nc - cb), 0, 0, 0};
+        emit_near(items, box_src_off[b] + c0, clen, g0, base[b] + j * nc + gl, ng,
+                  pick_slices(ng, clen, 10.0 * pq));
+        for (int64_t cb = 0; cb < ng; cb += 4) {
+          const int32_t it[8] = {(int32_t)(box_src_off[b] + c0), (int32_t)clen, (int32_t)(g0 + cb),
+                                 (int32_t)(base[b] + j * nc + gl + cb),
+                                 (int32_t)std::min<int64_t>(4, ng - cb), 0, 0, 0};
           mitems.insert(mitems.end(), it, it + 8);
         }
       }
@@ -258,12 +270,12 @@ gq_status build_near_work(gq_ctx *ctx) {
       for (int64_t j = 0; j * far_chunk < wlen; ++j) {
         const int64_t c0 = j * far_chunk, clen = std::min<int64_t>(far_chunk, wlen - c0);
         if (!packed) {
-          emit(fitems, woff + c0, clen, t.ctr_begin[b], base[b] + (nchunks + j) * nc, nc,
-               far_lg(nc, clen, pq));
+          emit(fitems, woff + c0, clen, g0, base[b] + (nchunks + j) * nc + gl, ng,
+               far_lg(ng, clen, pq));
           continue;
         }
         int32_t slot0 = -1;  // the chunk's first LDS slot in the current wavefront
-        for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) {
+        for (int64_t c = g0; c < g1; ++c) {
           const int64_t np = (int64_t)qpair.size() / 4 - q_pair0;
           const int64_t nst = (int64_t)qstage.size() - q_stage0;
           if (np + clen > 64 || (slot0 < 0 && nst + clen > stage_rows)) {
@@ -288,7 +300,7 @@ gq_status build_near_work(gq_ctx *ctx) {
           }
         }
       }
-      for (int64_t c = t.ctr_begin[b]; c < t.ctr_end[b]; ++c) clist.push_back((int32_t)c);
+      for (int64_t c = g0; c < g1; ++c) clist.push_back((int32_t)c);
     }
     bk.near1 = (int64_t)items.size() / 8;
     bk.nmf1 = (int64_t)mitems.size() / 8;
@@ -345,6 +357,41 @@ gq_status build_near_work(gq_ctx *ctx) {
   return st;
 }
 
+// Center arrays in tree order (positions, radii, caller index) and the CSR map from each center
+// to its target slots (slot = 2 target + column).
+struct CenterArrays {
+  std::vector<double> xy, r;
+  std::vector<int32_t> cperm, start, slot;
+};
+
+void center_arrays(const gq_ctx *ctx, CenterArrays &a) {
+  const gq::Tree &t = ctx->tree;
+  const int64_t nc = ctx->nc, nt = ctx->nt;
+  a.xy.resize(2 * nc);
+  a.r.resize(nc);
+  a.cperm.resize(nc);
+  std::vector<int64_t> inv(nc);
+  for (int64_t k = 0; k < nc; ++k) {
+    const int64_t o = t.ctr_order[k];
+    inv[o] = k;
+    a.cperm[k] = (int32_t)o;
+    a.xy[2 * k] = ctx->ctr_xy[2 * o];
+    a.xy[2 * k + 1] = ctx->ctr_xy[2 * o + 1];
+    a.r[k] = ctx->ctr_r[o];
+  }
+  a.start.assign(nc + 1, 0);
+  for (int64_t tg = 0; tg < nt; ++tg)
+    for (int s = 0; s < 2; ++s)
+      if (ctx->tgt_ctr[2 * tg + s] >= 0) a.start[inv[ctx->tgt_ctr[2 * tg + s]] + 1]++;
+  for (int64_t k = 0; k < nc; ++k) a.start[k + 1] += a.start[k];
+  a.slot.assign(a.start[nc], 0);
+  std::vector<int32_t> fill(a.start.begin(), a.start.end() - 1);
+  for (int64_t tg = 0; tg < nt; ++tg)
+    for (int s = 0; s < 2; ++s)
+      if (ctx->tgt_ctr[2 * tg + s] >= 0)
+        a.slot[fill[inv[ctx->tgt_ctr[2 * tg + s]]]++] = (int32_t)(2 * tg + s);
+}
+
 gq_status upload_all(gq_ctx *ctx) {
   const gq::Tree &t = ctx->tree;
   auto &d = ctx->d;
@@ -367,33 +414,14 @@ gq_status upload_all(gq_ctx *ctx) {
   }
   // centers in tree order, center -> target slots
   {
-    std::vector<double> xy(2 * nc), r(nc);
-    std::vector<int64_t> inv(nc);
-    std::vector<int32_t> cperm(nc);
-    for (int64_t k = 0; k < nc; ++k) {
-      int64_t o = t.ctr_order[k];
-      inv[o] = k;
-      cperm[k] = (int32_t)o;
-      xy[2 * k] = ctx->ctr_xy[2 * o]; xy[2 * k + 1] = ctx->ctr_xy[2 * o + 1];
-      r[k] = ctx->ctr_r[o];
-    }
-    std::vector<int32_t> start(nc + 1, 0), slot;
-    for (int64_t tg = 0; tg < nt; ++tg)
-      for (int s = 0; s < 2; ++s)
-        if (ctx->tgt_ctr[2 * tg + s] >= 0) start[inv[ctx->tgt_ctr[2 * tg + s]] + 1]++;
-    for (int64_t k = 0; k < nc; ++k) start[k + 1] += start[k];
-    slot.assign(start[nc], 0);
-    std::vector<int32_t> fill(start.begin(), start.end() - 1);
-    for (int64_t tg = 0; tg < nt; ++tg)
-      for (int s = 0; s < 2; ++s)
-        if (ctx->tgt_ctr[2 * tg + s] >= 0)
-          slot[fill[inv[ctx->tgt_ctr[2 * tg + s]]]++] = (int32_t)(2 * tg + s);
-    GQ_TRY(upload(ctx, d.cxy, xy.data(), nc));
-    GQ_TRY(upload(ctx, d.cr, r.data(), nc));
-    GQ_TRY(upload(ctx, d.cperm, cperm.data(), nc));
+    CenterArrays ca;
+    center_arrays(ctx, ca);
+    GQ_TRY(upload(ctx, d.cxy, ca.xy.data(), nc));
+    GQ_TRY(upload(ctx, d.cr, ca.r.data(), nc));
+    GQ_TRY(upload(ctx, d.cperm, ca.cperm.data(), nc));
     GQ_TRY(upload(ctx, d.cbox, t.ctr_box.data(), nc));
-    GQ_TRY(upload(ctx, d.c2t_start, start.data(), nc + 1));
-    GQ_TRY(upload(ctx, d.c2t_slot, slot.data(), slot.size()));
+    GQ_TRY(upload(ctx, d.c2t_start, ca.start.data(), nc + 1));
+    GQ_TRY(upload(ctx, d.c2t_slot, ca.slot.data(), ca.slot.size()));
     GQ_TRY(upload(ctx, d.txy, ctx->tgt_xy.data(), nt));
     GQ_TRY(upload(ctx, d.tctr, ctx->tgt_ctr.data(), 2 * nt));
   }
@@ -1106,6 +1134,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (!msg.empty()) return fail(ctx, GQ_EINVAL, msg);
   gq::build_tables(ctx->tables, p.p_fmm, p.p_qbx);
   ctx->box_pq.assign(ctx->tree.n_boxes(), p.p_qbx);
+  ctx->ctr_pq.clear();
   if (ctx->device >= 0) {
     GQ_HIP(ctx, hipSetDevice(ctx->device));
     gq_status st = upload_all(ctx);
@@ -1419,33 +1448,72 @@ gq_status gq_set_qbx_orders(gq_ctx *ctx, int mem, const int32_t *orders) {
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_set_qbx_orders before a successful gq_build");
   if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "bad mem");
   if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
-  const gq::Tree &t = ctx->tree;
-  std::vector<int32_t> ord(ctx->nc, ctx->params.p_qbx);
+  gq::Tree &t = ctx->tree;
+  const int64_t nc = ctx->nc, nb = t.n_boxes();
+  std::vector<int32_t> ord(nc, ctx->params.p_qbx);
   if (orders) {
     if (mem == GQ_MEM_HOST) std::memcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc_user);
     else GQ_HIP(ctx, hipMemcpy(ord.data(), orders, sizeof(int32_t) * ctx->nc_user, hipMemcpyDeviceToHost));
   }
-  // point targets need only the constant term: lowest compiled order, never raising a box's
-  for (int64_t c = ctx->nc_user; c < ctx->nc; ++c) ord[c] = ctx->pq_values.front();
-  std::vector<int32_t> bp(t.n_boxes(), -1);
-  for (int64_t k = 0; k < ctx->nc; ++k) {
-    const int32_t q = ord[t.ctr_order[k]];
-    if (q < 0 || q > ctx->params.p_qbx) return fail(ctx, GQ_EINVAL, "order outside 0..p_qbx");
-    bp[t.ctr_box[k]] = std::max(bp[t.ctr_box[k]], q);
-  }
-  for (int64_t b = 0; b < t.n_boxes(); ++b) {
-    int q = ctx->params.p_qbx;  // smallest compiled order >= the box's largest center order
+  for (int64_t c = 0; c < ctx->nc_user; ++c)
+    if (ord[c] < 0 || ord[c] > ctx->params.p_qbx) return fail(ctx, GQ_EINVAL, "order outside 0..p_qbx");
+  // point targets need only the constant term: the lowest compiled order
+  for (int64_t c = ctx->nc_user; c < nc; ++c) ord[c] = ctx->pq_values.front();
+  // every center runs at the smallest compiled order at least its own; within each box the
+  // centers are regrouped by that order (stable), so each order's centers of a box are one
+  // contiguous group of tree positions
+  auto eff = [&](int q) {
     for (int c : ctx->pq_values)
-      if (c >= bp[b]) { q = c; break; }
-    bp[b] = q;
+      if (c >= q) return c;
+    return ctx->params.p_qbx;
+  };
+  std::vector<int32_t> cpq(nc), bp(nb, -1);
+  std::vector<std::pair<int32_t, int64_t>> grp;
+  for (int64_t b = 0; b < nb; ++b) {
+    grp.clear();
+    for (int64_t k = t.ctr_begin[b]; k < t.ctr_end[b]; ++k)
+      grp.push_back({(int32_t)eff(ord[t.ctr_order[k]]), t.ctr_order[k]});
+    std::stable_sort(grp.begin(), grp.end(),
+                     [](const std::pair<int32_t, int64_t> &a, const std::pair<int32_t, int64_t> &b2) {
+                       return a.first < b2.first;
+                     });
+    for (size_t i = 0; i < grp.size(); ++i) {
+      const int64_t k = t.ctr_begin[b] + (int64_t)i;
+      t.ctr_order[k] = grp[i].second;
+      cpq[k] = grp[i].first;
+      bp[b] = std::max(bp[b], grp[i].first);
+    }
+    if (bp[b] < 0) bp[b] = eff(0);
   }
   ctx->box_pq = bp;
+  if (orders) ctx->ctr_pq = cpq;
+  else ctx->ctr_pq.clear();
   if (ctx->device >= 0) {
     GQ_HIP(ctx, hipSetDevice(ctx->device));
     if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->side) GQ_HIP(ctx, hipStreamSynchronize(ctx->side));
-    gq_status st = build_near_work(ctx);
-    if (st != GQ_OK) return st;
+    // the center arrays in the new tree order (same sizes, copied into the same buffers)
+    CenterArrays ca;
+    center_arrays(ctx, ca);
+    auto &d = ctx->d;
+    GQ_HIP(ctx, hipMemcpy(d.cxy, ca.xy.data(), sizeof(double) * ca.xy.size(), hipMemcpyHostToDevice));
+    GQ_HIP(ctx, hipMemcpy(d.cr, ca.r.data(), sizeof(double) * ca.r.size(), hipMemcpyHostToDevice));
+    GQ_HIP(ctx, hipMemcpy(d.cperm, ca.cperm.data(), sizeof(int32_t) * ca.cperm.size(), hipMemcpyHostToDevice));
+    GQ_HIP(ctx, hipMemcpy(d.c2t_start, ca.start.data(), sizeof(int32_t) * ca.start.size(), hipMemcpyHostToDevice));
+    if (!ca.slot.empty())
+      GQ_HIP(ctx, hipMemcpy(d.c2t_slot, ca.slot.data(), sizeof(int32_t) * ca.slot.size(), hipMemcpyHostToDevice));
+  }
+  return build_near_work(ctx);
+}
+
+gq_status gq_get_center_orders(gq_ctx *ctx, int32_t *dst) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!ctx->built) return fail(ctx, GQ_ESTATE, "no tree built");
+  if (!dst) return fail(ctx, GQ_EINVAL, "null output");
+  const gq::Tree &t = ctx->tree;
+  for (int64_t k = 0; k < ctx->nc; ++k) {
+    const int64_t c = t.ctr_order[k];
+    if (c < ctx->nc_user) dst[c] = ctx->ctr_pq.empty() ? ctx->params.p_qbx : ctx->ctr_pq[k];
   }
   return GQ_OK;
 }

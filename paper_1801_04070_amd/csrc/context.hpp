@@ -128,6 +128,8 @@ struct gq_ctx {
   gq::Tables tables;
   std::vector<int> pq_values;        // compiled QBX orders <= params.p_qbx, ascending
   std::vector<int32_t> box_pq;       // QBX order of each box (largest order of its centers)
+  std::vector<int32_t> ctr_pq;       // compiled QBX order of each tree-order center (empty: the
+                                     // uniform build order)
   std::vector<gq::OrderBucket> buckets;  // per order: item and center ranges
   std::vector<void *> nw_allocations;    // direct / List 3 far work, re-uploaded on order changes
   int64_t n_tboxes = 0;              // number of target-or-ancestor boxes

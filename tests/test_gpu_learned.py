@@ -7,7 +7,8 @@ at each on-surface target (average of the two one-sided limits) is u / 2. Errors
 max |u| over the targets, FMM at p_fmm 30 (its own error is far below the tolerance).
 
 The gain: the learned orders meet the tolerance while their mean effective order (each center
-runs at its box's order) is below the smallest uniform order that meets it.
+runs at the smallest compiled order covering its own) is below the smallest uniform order that
+meets it.
 """
 import numpy as np
 import pytest
@@ -42,14 +43,7 @@ def _err(q, d1, d2, u):
 
 
 def _effective_orders(q):
-    from paper_1801_04070_amd import _lib
-    bo = q.box_orders()
-    rng = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
-    order = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
-    eff = np.empty(len(order), np.int64)
-    for b, (c0, c1) in enumerate(rng):
-        eff[order[c0:c1]] = bo[b]
-    return eff
+    return q.center_orders()
 
 
 @pytest.mark.parametrize("log10_tol", LOG10_TOLS)
@@ -89,3 +83,46 @@ def test_fallback_to_uniform_orders(case):
     from paper_1801_04070_amd import _lib
     rng = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
     assert (q.box_orders()[rng[:, 1] > rng[:, 0]] == 16).all()
+
+
+def _ms_per_eval(q, d1, d2, reps=10):
+    import torch
+    for _ in range(2):
+        q.eval(3, d1, d2)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        q.eval(3, d1, d2)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def test_learned_orders_gain_targets_per_second():
+    """Throughput on the 8 x 8 wavy lattice (192 panels per curve, 196608 targets, sources
+    upsampled to 64 nodes per panel): the learned orders at tolerance 1e-10 meet it and evaluate
+    at least 1.1 times as many targets per second as the method at its configured uniform order
+    p_qbx 12 (what runs without the network), with every center at its own order."""
+    import torch
+    from paper_1801_04070_amd import QBXFMM, learned
+    g = gi.wavy_lattice(nx=8, ny=8, panels_per_curve=192, seed=300, gap_in_radii=4.0, src_order=64)
+    lo, hi = g.src_xy.min(0), g.src_xy.max(0)
+    x0 = np.array([lo[0] - 0.7, 0.3 * lo[1] + 0.7 * hi[1]])
+    sig, tau, u = gi.green_test_field(g, x0)
+    q = QBXFMM(0)
+    q.set_geometry_from(g)
+    q.build(p_qbx=16, p_fmm=30)
+    d1, d2 = torch.from_numpy(sig).cuda(), torch.from_numpy(tau).cuda()
+    q.set_qbx_orders(np.full(g.n_ctr, 12, np.int32))
+    e12 = _err(q, d1, d2, u)
+    ms12 = _ms_per_eval(q, d1, d2)
+    model = learned.load_default()
+    learned.choose_orders(q, -10.0, model)
+    el = _err(q, d1, d2, u)
+    msl = _ms_per_eval(q, d1, d2)
+    print(f"uniform 12: {ms12:.3f} ms (log10 err {e12:.2f}); learned: {msl:.3f} ms "
+          f"(log10 err {el:.2f}, mean order {q.center_orders().mean():.2f}); "
+          f"{ms12 / msl:.2f}x targets/s")
+    assert el <= -10.0
+    assert ms12 / msl >= 1.1

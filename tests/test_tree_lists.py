@@ -255,6 +255,33 @@ def test_box_orders_from_center_orders():
         q.set_qbx_orders(np.full(g.n_ctr, 13, np.int32))
 
 
+def test_center_orders_regroup_centers_within_boxes():
+    """Per-center orders: every center runs at the smallest compiled order >= its own; inside each
+    box the centers are regrouped by that order (ascending, ties in their previous order), the
+    set of centers per box and every list stay as built, and NULL restores the uniform order."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=40, seed=4, box=8.0)
+    q = QBXFMM(device=-1)
+    q.set_geometry_from(g)
+    q.build(p_qbx=12, p_fmm=10)
+    rng_c = q.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE)
+    before = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    lists = q.lists()
+    orders = np.random.default_rng(2).integers(0, 13, size=g.n_ctr).astype(np.int32)
+    q.set_qbx_orders(orders)
+    compiled = np.array([4, 6, 8, 10, 12])
+    eff = compiled[np.searchsorted(compiled, orders)]
+    np.testing.assert_array_equal(q.center_orders(), eff)
+    after = q.tree_array(_lib.GQ_TREE_CTR_ORDER)
+    for c0, c1 in rng_c:
+        assert sorted(before[c0:c1]) == sorted(after[c0:c1])
+        e = eff[after[c0:c1]]
+        assert (np.diff(e) >= 0).all()
+    for k, (st, ix) in q.lists().items():
+        assert np.array_equal(st, lists[k][0]) and np.array_equal(ix, lists[k][1]), k
+    q.set_qbx_orders(None)
+    assert (q.center_orders() == 12).all()
+
+
 def _with_point_targets(g, n_pt=300, seed=4):
     """Add conventional targets (both center slots -1) off the curve and around it."""
     rng = np.random.default_rng(seed)
