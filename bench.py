@@ -557,6 +557,10 @@ def main():
         variant("fp64_p16", "all FP64, p_fmm 16 (equal-accuracy reference for mixed_fp32_p16)",
                 p_fmm=16)
         variant("fp64_p40", "all FP64, p_fmm 40, tolerance 1e-12", p_fmm=40)
+        variant("level_restricted", "the tree refined until no leaf has an adjacent source leaf "
+                "two levels coarser (Remark 2), S and D, FP64, p_fmm 30", level_restrict=1)
+        variant("disk_tcr", "disk-shaped target confinement regions (the corrigendum's first "
+                "experiments), S and D, FP64, p_fmm 30", tcr_shape=1)
         log("bench: off-surface targets")
         variants["offsurface"] = offsurface_variant(timer, geom, dens_h, args)
         log(f"bench: offsurface: {variants['offsurface']['ms_per_step']} ms/step")
@@ -613,7 +617,8 @@ def main():
         if max(par["S"], par["D"]) > GATE:
             par["status"] = "FAILED"
         result["parity"] = par
-        gates = {"mixed_fp32_p16": 1e-6, "fp64_p16": 1e-6, "fp64_p40": 1e-12}
+        gates = {"mixed_fp32_p16": 1e-6, "fp64_p16": 1e-6, "fp64_p40": 1e-12,
+                 "level_restricted": GATE, "disk_tcr": GATE}
         for name, gate in gates.items():
             if name in outputs:
                 e = rel_errors(smp, outputs[name][0], outputs[name][1])

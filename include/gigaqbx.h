@@ -81,6 +81,13 @@ typedef struct {
   double eps;             /* requested accuracy (Sec. 4.1 input (b)); used when p_fmm <= 0:
                              the FMM error is of order (1/2)^(p_fmm + 1) (Theorem 1), so
                              p_fmm = ceil(|log2 eps|), at most GQ_MAX_P_FMM. 0: unused       */
+  int tcr_shape;          /* target confinement region: 0 (default) the closed square of
+                             radius |b|(1 + t_f) (Sec. 4.3, Definition 1); 1 the closed disk of
+                             that radius, the shape the paper's corrigendum reports its first
+                             experiments used; the separation relations of Definition 1 then
+                             take the l-inf distance to the disk                              */
+  int level_restrict;     /* 1: refine the tree until adjacent leaves differ by at most one
+                             level (Remark 2, level-restricted quadtree); 0 (default): as built */
 } gq_params;
 
 #define GQ_MAX_P_QBX 20
@@ -88,7 +95,7 @@ typedef struct {
 
 /* Fill *p with the defaults: p_qbx 12, p_fmm 30, n_max 64, count_mode 0, t_f 0.9,
  * w3far_min_sources 15, GQ_FP64, max_levels 24, overlap 1, work-item shapes 0 (defaults),
- * eps 0. */
+ * eps 0, tcr_shape 0, level_restrict 0. */
 gq_status gq_default_params(gq_params *p);
 
 /* Create a context on HIP device `device` (>= 0) using `hip_stream` (a hipStream_t, may be NULL for

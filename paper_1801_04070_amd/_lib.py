@@ -29,7 +29,8 @@ class gq_params(C.Structure):
                 ("count_mode", C.c_int), ("t_f", C.c_double), ("w3far_min_sources", C.c_int),
                 ("precision", C.c_int), ("max_levels", C.c_int), ("overlap", C.c_int),
                 ("near_chunk", C.c_int), ("far_chunk", C.c_int), ("far_pairs_per_lane", C.c_int),
-                ("near_dens_group", C.c_int), ("eps", C.c_double)]
+                ("near_dens_group", C.c_int), ("eps", C.c_double), ("tcr_shape", C.c_int),
+                ("level_restrict", C.c_int)]
 
 
 class gq_stats(C.Structure):

@@ -985,6 +985,8 @@ gq_status gq_default_params(gq_params *p) {
   p->far_pairs_per_lane = 1;
   p->near_dens_group = 0;
   p->eps = 0.0;
+  p->tcr_shape = 0;
+  p->level_restrict = 0;
   return GQ_OK;
 }
 
@@ -1107,6 +1109,9 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   if (p.count_mode != 0 && p.count_mode != 1) return fail(ctx, GQ_EINVAL, "count_mode must be 0 or 1");
   if (p.w3far_min_sources < 0) return fail(ctx, GQ_EINVAL, "w3far_min_sources must be >= 0");
   if (p.overlap != 0 && p.overlap != 1) return fail(ctx, GQ_EINVAL, "overlap must be 0 or 1");
+  if (p.tcr_shape != 0 && p.tcr_shape != 1) return fail(ctx, GQ_EINVAL, "tcr_shape must be 0 or 1");
+  if (p.level_restrict != 0 && p.level_restrict != 1)
+    return fail(ctx, GQ_EINVAL, "level_restrict must be 0 or 1");
   if (p.near_chunk < 0 || p.near_chunk > (1 << 20) || p.far_chunk < 0 || p.far_chunk > 32 ||
       p.far_pairs_per_lane < 0 || p.far_pairs_per_lane > 64)
     return fail(ctx, GQ_EINVAL, "work-item shape out of range");
@@ -1121,6 +1126,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params) {
   gq::TreeParams tp;
   tp.n_max = p.n_max; tp.count_mode = p.count_mode; tp.t_f = p.t_f;
   tp.w3far_min_sources = p.w3far_min_sources; tp.max_levels = p.max_levels;
+  tp.tcr_shape = p.tcr_shape; tp.level_restrict = p.level_restrict;
   std::string msg;
   try {
     if (ctx->n_geom > 1)

@@ -96,8 +96,11 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
     for (int64_t c = 0; c < nc; ++c) root.ctr[c] = (int32_t)c;
     bx.push_back(std::move(root));
   }
-  for (size_t b = 0; b < bx.size(); ++b) {
-    if (bx[b].level >= p.max_levels - 1) continue;
+  // Split box b into its non-empty quadrants (sources by quadrant, centers whose disk fits the
+  // child's TCR; the others stay, suspended). force: split whatever the count of eligible
+  // particles. Returns whether children were made.
+  auto subdivide = [&](size_t b, bool force) {
+    if (bx[b].level >= p.max_levels - 1) return false;
     const int lev = bx[b].level;
     const double h = 0.5 * side / (double)(int64_t(1) << lev);  // |b|
     const double ccx = t.lo[0] + (bx[b].i + 0.5) * 2 * h, ccy = t.lo[1] + (bx[b].j + 0.5) * 2 * h;
@@ -110,13 +113,14 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
       double x = cxy[2 * c], y = cxy[2 * c + 1];
       int q = quad(x, y);
       double chx = ccx + ((q & 1) ? hc : -hc), chy = ccy + ((q & 2) ? hc : -hc);
-      double dist = std::max(std::fabs(x - chx), std::fabs(y - chy));
+      const double dist = p.tcr_shape == 1 ? std::hypot(x - chx, y - chy)
+                                            : std::max(std::fabs(x - chx), std::fabs(y - chy));
       bool fits = dist + cr[c] <= hc * (1.0 + p.t_f);
       cq[k] = fits ? (int8_t)q : (int8_t)-1;
       n_elig_ctr += fits;
     }
     int64_t count = (int64_t)bx[b].src.size() + (p.count_mode == 0 ? n_elig_ctr : 0);
-    if (count <= p.n_max) continue;
+    if (!force && count <= p.n_max) return false;
     std::vector<int32_t> csrc[4], cctr[4], keep;
     for (int32_t s : bx[b].src) csrc[quad(sxy[2 * s], sxy[2 * s + 1])].push_back(s);
     for (size_t k = 0; k < bx[b].ctr.size(); ++k) {
@@ -137,6 +141,72 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
       bx[b].src.shrink_to_fit();
       bx[b].ctr = std::move(keep);
     }
+    return any;
+  };
+  for (size_t b = 0; b < bx.size(); ++b) subdivide(b, false);
+
+  // ---- level restriction (Remark 2, optional): split source leaves until no leaf has an
+  // adjacent source leaf two or more levels coarser (adjacent: the closed squares touch, corners
+  // included). Leaves that hold only centers own no sources for any list and are not split (their
+  // centers may not fit a child's TCR). A leaf b at level l looks at the cells of its 8
+  // same-level neighbours; the deepest box covering such a cell, if a source leaf two or more
+  // levels coarser, is split (empty quadrants stay absent), and the new leaves are checked in
+  // turn. Boxes are then renumbered level-major again.
+  if (p.level_restrict) {
+    std::unordered_map<uint64_t, int32_t> at;
+    at.reserve(bx.size() * 2);
+    for (size_t b = 0; b < bx.size(); ++b) at[box_key(bx[b].level, bx[b].i, bx[b].j)] = (int32_t)b;
+    auto leaf = [&](int32_t b) {
+      return bx[b].child[0] < 0 && bx[b].child[1] < 0 && bx[b].child[2] < 0 && bx[b].child[3] < 0;
+    };
+    auto cover = [&](int l, int64_t i, int64_t j) -> int32_t {
+      if (i < 0 || j < 0 || i >= (int64_t(1) << l) || j >= (int64_t(1) << l)) return -1;
+      for (; l >= 0; --l, i >>= 1, j >>= 1) {
+        auto it = at.find(box_key(l, i, j));
+        if (it != at.end()) return it->second;
+      }
+      return -1;
+    };
+    std::vector<int32_t> work;
+    for (size_t b = 0; b < bx.size(); ++b)
+      if (leaf((int32_t)b)) work.push_back((int32_t)b);
+    while (!work.empty()) {
+      const int32_t b = work.back();
+      work.pop_back();
+      if (!leaf(b)) continue;
+      const int l = bx[b].level;
+      bool again = false;
+      for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (!di && !dj) continue;
+          const int32_t e = cover(l, bx[b].i + di, bx[b].j + dj);
+          if (e < 0 || !leaf(e) || bx[e].level >= l - 1 || bx[e].src.empty()) continue;
+          const size_t first = bx.size();
+          if (!subdivide((size_t)e, true)) continue;
+          for (size_t k = first; k < bx.size(); ++k) {
+            at[box_key(bx[k].level, bx[k].i, bx[k].j)] = (int32_t)k;
+            work.push_back((int32_t)k);
+          }
+          again = true;
+        }
+      if (again) work.push_back(b);  // the covering boxes may still be too coarse
+    }
+    std::vector<int32_t> perm(bx.size());
+    for (size_t k = 0; k < perm.size(); ++k) perm[k] = (int32_t)k;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t a, int32_t b2) { return bx[a].level < bx[b2].level; });
+    std::vector<int32_t> inv(bx.size());
+    for (size_t k = 0; k < perm.size(); ++k) inv[perm[k]] = (int32_t)k;
+    std::vector<BuildBox> nbx;
+    nbx.reserve(bx.size());
+    for (int32_t o : perm) {
+      BuildBox bb = std::move(bx[o]);
+      if (bb.parent >= 0) bb.parent = inv[bb.parent];
+      for (int q = 0; q < 4; ++q)
+        if (bb.child[q] >= 0) bb.child[q] = inv[bb.child[q]];
+      nbx.push_back(std::move(bb));
+    }
+    bx.swap(nbx);
   }
 
   const int64_t nb = (int64_t)bx.size();
@@ -227,10 +297,27 @@ std::string build_tree(Tree &t, int64_t ns, const double *sxy, int64_t nc, const
     return std::max(std::fabs(t.cx[a] - t.cx[b]), std::fabs(t.cy[a] - t.cy[b]));
   };
   const double tf1 = 1.0 + p.t_f;
-  // d < TCR(b): l-inf distance of centers at least 3|d| + |b|(1 + t_f)   (Definition 1)
-  auto box_sep_tcr = [&](int32_t d, int32_t b) { return linf(d, b) >= 3 * t.half(d) + t.half(b) * tf1; };
-  // TCR(b) < d: l-inf distance of centers at least 3|b|(1 + t_f) + |d|  (Definition 1)
-  auto tcr_sep_box = [&](int32_t b, int32_t d) { return linf(d, b) >= 3 * t.half(b) * tf1 + t.half(d); };
+  // Euclidean distance from the center of box a to the closed square of radius s about the
+  // center of box e
+  auto dist2_sq = [&](int32_t a, int32_t e, double s) {
+    const double dx = std::max(std::fabs(t.cx[a] - t.cx[e]) - s, 0.0);
+    const double dy = std::max(std::fabs(t.cy[a] - t.cy[e]) - s, 0.0);
+    return std::hypot(dx, dy);
+  };
+  // d < TCR(b): l-inf distance of d and TCR(b) at least 2|d| (Definition 1): for the square TCR,
+  // l-inf distance of the centers at least 3|d| + |b|(1 + t_f); for the disk TCR (radius
+  // |b|(1 + t_f) about c_b), the disk does not reach into the square of radius 3|d| about c_d
+  auto box_sep_tcr = [&](int32_t d, int32_t b) {
+    if (p.tcr_shape == 1) return dist2_sq(b, d, 3 * t.half(d)) >= t.half(b) * tf1;
+    return linf(d, b) >= 3 * t.half(d) + t.half(b) * tf1;
+  };
+  // TCR(b) < d: l-inf distance of TCR(b) and d at least 2|b|(1 + t_f): square TCR, centers at
+  // least 3|b|(1 + t_f) + |d| apart in l-inf; disk TCR, the disk outside the square of radius
+  // |d| + 2|b|(1 + t_f) about c_d
+  auto tcr_sep_box = [&](int32_t b, int32_t d) {
+    if (p.tcr_shape == 1) return dist2_sq(b, d, t.half(d) + 2 * t.half(b) * tf1) >= t.half(b) * tf1;
+    return linf(d, b) >= 3 * t.half(b) * tf1 + t.half(d);
+  };
 
   // Leaves with sources at levels <= level(b) whose squares touch b's square.
   auto coarse_adjacent_leaves = [&](int32_t b, std::vector<int32_t> &out) {

@@ -17,6 +17,8 @@ struct TreeParams {
   double t_f = 0.9;
   int w3far_min_sources = 15;  // Remark 1 threshold, 0 disables
   int max_levels = 24;
+  int tcr_shape = 0;           // 0: l-inf square (Definition 1); 1: l2 disk of the same radius
+  int level_restrict = 0;      // 1: refine until adjacent leaves differ by at most one level
 };
 
 // Compressed sparse rows: entries of row b are idx[start[b] .. start[b+1]).

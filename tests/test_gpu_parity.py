@@ -623,3 +623,18 @@ def test_off_surface_targets_by_association(kind):
     print(f"off-surface kind={kind}: qbx {qbx.sum()} ({e_q:.2e}), conventional {(~qbx).sum()} "
           f"({e_p:.2e}), gaps {n_gap}")
     assert e_q < 1e-10 and e_p < 1e-10
+
+
+@pytest.mark.parametrize("tcr_shape,level_restrict", [(1, 0), (0, 1), (1, 1)])
+def test_tree_variants_match_oracle(tcr_shape, level_restrict):
+    """The disk-shaped TCR and the level-restricted tree give other lists; the potentials still
+    match the oracle within the gate (S, D and S_AND_D, one and several densities)."""
+    from paper_1801_04070_amd import GQ_S_AND_D
+    g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
+    q, _ = _ctx(g, p_qbx=12, p_fmm=30, tcr_shape=tcr_shape, level_restrict=level_restrict)
+    h = np.stack([gi.fourier_density(g, seed=700 + j) for j in range(10)])
+    both = q.eval(GQ_S_AND_D, _dev(h)).cpu().numpy()
+    one = q.eval(GQ_S_AND_D, _dev(h[9])).cpu().numpy()
+    for kind, rows in ((1, (9, 0)), (2, (19, 1))):
+        ref = oracle.qbx_eval(g, kind, h[9], None, p_qbx=12)
+        assert _rel(both[rows[0]], ref) < 1e-10 and _rel(one[rows[1]], ref) < 1e-10, kind

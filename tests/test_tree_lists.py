@@ -75,9 +75,32 @@ GEOMS = {
 }
 
 
-def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15):
+def _dist2_sq(p, c, s):
+    """Euclidean distance from point p to the closed square of radius s about c."""
+    d = np.maximum(np.abs(np.asarray(p) - np.asarray(c)) - s, 0.0)
+    return float(np.hypot(d[..., 0], d[..., 1]))
+
+
+def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15, tcr_shape=0, level_restrict=0):
     q, T = _build(geom, p_qbx=8, p_fmm=10, t_f=t_f, n_max=n_max, count_mode=count_mode,
-                  w3far_min_sources=w3)
+                  w3far_min_sources=w3, tcr_shape=tcr_shape, level_restrict=level_restrict)
+    disk = tcr_shape == 1
+
+    def dnorm(v):  # the TCR's norm of center offsets
+        return np.hypot(v[..., 0], v[..., 1]) if disk else np.abs(v).max(axis=-1)
+
+    def sep_d_tcr(d, b):  # d < TCR(b) (Definition 1 with the TCR's shape)
+        if disk:
+            return _dist2_sq(T["center"][b], T["center"][d], 3 * T["half"][d]) >= \
+                T["half"][b] * (1 + t_f) * (1 - 1e-12)
+        return _linf(T, d, b) >= (3 * T["half"][d] + T["half"][b] * (1 + t_f)) * (1 - 1e-12)
+
+    def sep_tcr_d(b, d):  # TCR(b) < d
+        if disk:
+            return _dist2_sq(T["center"][b], T["center"][d],
+                             T["half"][d] + 2 * T["half"][b] * (1 + t_f)) >= \
+                T["half"][b] * (1 + t_f) * (1 - 1e-12)
+        return _linf(T, d, b) >= (3 * T["half"][b] * (1 + t_f) + T["half"][d]) * (1 - 1e-12)
     nb = len(T["level"])
     ns = geom.n_src
     src = T["src"]
@@ -101,7 +124,7 @@ def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15):
             assert d <= T["half"][b] * (1 + 1e-12)
         c0, c1 = T["ctr"][b]
         if c1 > c0 and b != 0:
-            reach = np.abs(cxy[c0:c1] - T["center"][b]).max(axis=1) + cr[c0:c1]
+            reach = dnorm(cxy[c0:c1] - T["center"][b]) + cr[c0:c1]
             assert (reach <= T["half"][b] * (1 + t_f) * (1 + 1e-12)).all()
     # subdivision rule: a leaf owns at most n_max particles eligible for children (sources, and
     # centers whose disk would fit the TCR of the child containing them), unless at max depth
@@ -111,9 +134,18 @@ def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15):
             hc = 0.5 * T["half"][b]
             quad = (cxy[c0:c1] >= T["center"][b]).astype(float) * 2 - 1
             chc = T["center"][b] + quad * hc
-            elig = (np.abs(cxy[c0:c1] - chc).max(axis=1) + cr[c0:c1] <= hc * (1 + t_f)).sum()
+            elig = (dnorm(cxy[c0:c1] - chc) + cr[c0:c1] <= hc * (1 + t_f)).sum()
             cnt = (src[b, 1] - src[b, 0]) + (elig if count_mode == 0 else 0)
             assert cnt <= n_max or T["level"][b] == T["stats"]["n_levels"] - 1
+    if level_restrict:
+        # Remark 2: no leaf has an adjacent source leaf (closed squares touching) two or more
+        # levels coarser
+        leaves = np.nonzero(T["leaf"])[0]
+        sleaves = leaves[src[leaves, 1] > src[leaves, 0]]
+        for a in leaves:
+            near = sleaves[(np.abs(T["center"][sleaves] - T["center"][a]).max(axis=1)
+                            <= (T["half"][sleaves] + T["half"][a]) * (1 + 1e-12))]
+            assert (T["level"][near] >= T["level"][a] - 1).all(), a
     # ---- exact-once coverage and predicates for every box owning centers ----
     tf1 = 1 + t_f
     counts = {"list2": 0, "list4c": 0, "list4f": 0}
@@ -142,20 +174,20 @@ def _check_tree(geom, t_f=0.9, n_max=64, count_mode=0, w3=15):
         for d in _row(T, "list1", b):
             assert _adjacent(T, b, d)
         for d in _row(T, "list3f", b):
-            assert _linf(T, d, b) >= 3 * T["half"][d] + T["half"][b] * tf1 * (1 - 1e-12)
+            assert sep_d_tcr(d, b)
             assert not _adjacent(T, b, d) and T["level"][d] > T["level"][b]
         if w3 == 0:
             for d in _row(T, "list3c", b):
-                assert _linf(T, d, b) < 3 * T["half"][d] + T["half"][b] * tf1
+                assert not sep_d_tcr(d, b)
                 assert not _adjacent(T, b, d)
         for d in _row(T, "list4c", b):
-            assert _linf(T, d, b) < 3 * T["half"][b] * tf1 + T["half"][d]
+            assert not sep_tcr_d(b, d)
     for b in range(nb):
         for d in _row(T, "list2", b):
             assert T["level"][d] == T["level"][b]
             assert np.abs(T["ij"][d] - T["ij"][b]).max() in (3, 4, 5)  # 2-well-separated
         for d in _row(T, "list4f", b):
-            assert _linf(T, d, b) >= 3 * T["half"][b] * tf1 + T["half"][d] * (1 - 1e-12)
+            assert sep_tcr_d(b, d)
             assert T["leaf"][d] and T["level"][d] <= T["level"][b]
             assert not _adjacent(T, b, d)
     return T, counts
@@ -173,6 +205,36 @@ def test_lists_partition_deep_trees(t_f, n_max):
     # small n_max forces deep adaptive trees with many suspended centers
     _check_tree(gi.random_stars(n_curves=2, panels_per_curve=24, seed=9, box=6.0), t_f=t_f,
                 n_max=n_max, w3=0)
+
+
+@pytest.mark.parametrize("tcr_shape,level_restrict", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("n_max", [8, 64])
+def test_tree_variants_partition_sources(tcr_shape, level_restrict, n_max):
+    """The disk-shaped TCR and the level-restricted tree (Remark 2) keep the exact-once partition
+    of the sources for every center, every list entry satisfies its relation for that TCR shape,
+    and in the level-restricted tree no leaf has an adjacent source leaf two levels coarser."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=40, seed=4, box=8.0)
+    T, counts = _check_tree(g, n_max=n_max, tcr_shape=tcr_shape, level_restrict=level_restrict)
+    const = _golden()
+    assert counts["list2"] <= const["max_list2"]["value"]
+    assert counts["list4c"] <= const["max_list4_close"]["value"]
+    assert counts["list4f"] <= const["max_list4_far"]["value"]
+
+
+def test_level_restriction_on_full_size_tree(c2_tree):
+    """Remark 2 on the 131072-source tree: the level-restricted tree has more boxes, and fewer
+    direct (center, source) pairs and List 3 far pairs than the tree as built; the lists still
+    meet the Sec. 4.6 size bounds."""
+    g, T = c2_tree
+    _, R = _build(g, p_qbx=12, p_fmm=30, level_restrict=1)
+    a, b = T["stats"], R["stats"]
+    assert b["n_boxes"] > a["n_boxes"]
+    assert b["near_pairs"] < a["near_pairs"] and b["list3_far_pairs"] < a["list3_far_pairs"]
+    const = _golden()
+    assert b["max_list2"] <= const["max_list2"]["value"]
+    assert b["max_list4"] <= const["max_list4"]["value"]
+    assert b["max_list4_close"] <= const["max_list4_close"]["value"]
+    assert b["max_list4_far"] <= const["max_list4_far"]["value"]
 
 
 def test_remark1_demotion_keeps_partition():
