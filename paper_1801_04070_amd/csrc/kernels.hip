@@ -462,21 +462,23 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
   (void)n_items;
-  if (slot0 >= n_slots) return;  // the whole wavefront past the last slot
-  const int2 it = items[blockIdx.x];  // first pair, end of pairs
   const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
   const int slot = slot0 + (c16 >> 1);
   const bool sact = slot < n_slots;
   M += (int64_t)(sact ? slot : slot0) * box_st;
   L += (int64_t)(sact ? slot : slot0) * box_st;
-  R A[RT][KS];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int i = 16 * rt + c16, k = 4 * ks + g;
-      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
-    }
+  // the fixed matrix in LDS, in the A-operand order of each (row tile, k-step): one read per
+  // matrix-core step instead of RT KS registers per lane
+  __shared__ R As[RT][KS][64];
+  for (int e = threadIdx.x; e < RT * KS * 64; e += blockDim.x) {
+    const int l = e & 63, ks = (e >> 6) % KS, rt = (e >> 6) / KS;
+    const int i = 16 * rt + (l & 15), k = 4 * ks + (l >> 4);
+    As[rt][ks][l] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
+  }
+  __syncthreads();
+  // every thread of the work-group has filled the matrix; a wavefront past the last slot stops
+  if (slot0 >= n_slots) return;
+  const int2 it = items[blockIdx.x];  // first pair, end of pairs
   int4 rec;
   double pl;
   E inv[KS], fv[KS], gv[F64 ? 1 : 4 * RT];
@@ -521,13 +523,18 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[rt][v] = 0.0;
   for (int32_t j = it.x; j < it.y; ++j) {
+    // the B operand and the factors this pair needs are taken before the next pair's loads are
+    // issued into the same registers
     const int4 rc = rec;
     const double plc = pl;
-    E inc[KS], fc[KS], gc[F64 ? 1 : 4 * RT];
+    const double a0 = (double)inv[0].x;
+    R Bf[KS];
+    E fc[F64 ? KS : 1], gc[F64 ? 1 : 4 * RT];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      inc[ks] = inv[ks];
-      fc[ks] = fv[ks];
+      const E mk = inv[ks], ok = fv[ks];
+      Bf[ks] = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
+      if (F64) fc[F64 ? ks : 0] = ok;
     }
     if (!F64) {
 #pragma unroll
@@ -539,27 +546,21 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
       cur = rc.z;
     }
     if (rc.x < 0) continue;  // a box without List 2 pairs: its local is 0
-    R Bf[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const E mk = inc[ks], ok = fc[ks];
-      Bf[ks] = comp ? mk.x * ok.y + mk.y * ok.x : mk.x * ok.x - mk.y * ok.y;
-    }
     Acc C[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       C[rt] = Acc{R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(A[rt][ks], Bf[ks], C[rt]);
+      for (int ks = 0; ks < KS; ++ks) C[rt] = mfma16(As[rt][ks][lane], Bf[ks], C[rt]);
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = 16 * rt + Mfma16<R>::row(g, v);
-        const double2 gm = to_d2(F64 ? fc[(4 * rt + v) % KS] : gc[F64 ? 0 : 4 * rt + v]);
+        const double2 gm = to_d2(F64 ? fc[F64 ? (4 * rt + v) % KS : 0] : gc[F64 ? 0 : 4 * rt + v]);
         double val = slot_post<R>((double)C[rt][v], comp, gm);
-        if (m == 0 && !comp) val = fma((double)inc[0].x, plc, val);  // a_0 log|s o|
+        if (m == 0 && !comp) val = fma(a0, plc, val);  // a_0 log|s o|
         acc[rt][v] += val;
       }
   }
