@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -158,6 +159,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
   std::vector<double> qgeo;
+
   std::vector<double> lside = t.level_side_table;
   if (lside.empty())
     for (int l = 0; l < t.n_levels; ++l) lside.push_back(std::ldexp(t.side, -l));
@@ -560,6 +562,87 @@ gq_status upload_all(gq_ctx *ctx) {
       GQ_TRY(upload(ctx, d.m2l_item, item.data(), item.size() / 2));
       GQ_TRY(upload(ctx, d.m2l_pr, pr.data(), pr.size() / 4));
       GQ_TRY(upload(ctx, d.m2l_plog, plog.data(), plog.size()));
+    }
+    // The same pairs for density batches, grouped by target parent: siblings share most of
+    // their List 2 boxes, so every group record is one source box with the offset of each member
+    // that lists it (a byte, 0xFF: none), and a source multipole is read once for up to four
+    // targets. The offsets are renumbered to the ones List 2 uses (a compact o^-k table).
+    std::vector<int32_t> cmap(121, -1), used;
+    for (int32_t o : t.list2_offset)
+      if (cmap[o] < 0) {
+        cmap[o] = (int32_t)used.size();
+        used.push_back(o);
+      }
+    std::vector<int32_t> gkey(nb + 1, -1), grp, rec, gitem;
+    std::vector<double> gplog;
+    for (int64_t b = 0; b < nb; ++b) {
+      if (!t.has_tgt[b]) continue;
+      const int64_t key = t.parent[b] >= 0 ? t.parent[b] : nb;
+      if (gkey[key] < 0 || grp[4 * gkey[key] + 3] >= 0) {
+        gkey[key] = (int32_t)grp.size() / 4;
+        grp.insert(grp.end(), {-1, -1, -1, -1});
+      }
+      int32_t *gm = &grp[4 * gkey[key]];
+      int q = 0;
+      while (gm[q] >= 0) ++q;
+      gm[q] = (int32_t)b;
+    }
+    const int32_t ngrp = (int32_t)grp.size() / 4;
+    std::vector<std::array<int32_t, 3>> ent;  // (d, member, compact offset)
+    int32_t gfirst = 0, work = 0;
+    for (int32_t gi = 0; gi < ngrp; ++gi) {
+      ent.clear();
+      for (int q = 0; q < 4; ++q) {
+        const int32_t b = grp[4 * gi + q];
+        if (b < 0) continue;
+        for (int64_t e = t.list2.start[b]; e < t.list2.start[b + 1]; ++e)
+          ent.push_back({t.list2.idx[e], q, cmap[t.list2_offset[e]]});
+      }
+      std::stable_sort(ent.begin(), ent.end(),
+                       [](const auto &x, const auto &y) { return x[0] < y[0]; });
+      const double ls = std::log(side[t.level[grp[4 * gi]]]);
+      if (ent.empty()) {
+        rec.insert(rec.end(), {-1, -1, gi, 0});
+        gplog.insert(gplog.end(), {0.0, 0.0, 0.0, 0.0});
+      }
+      for (size_t e0 = 0; e0 < ent.size();) {
+        size_t e1 = e0;
+        uint32_t packed = 0xFFFFFFFFu;
+        double pl[4] = {0.0, 0.0, 0.0, 0.0};
+        for (; e1 < ent.size() && ent[e1][0] == ent[e0][0]; ++e1) {
+          const int q = ent[e1][1];
+          packed = (packed & ~(0xFFu << (8 * q))) | ((uint32_t)ent[e1][2] << (8 * q));
+          pl[q] = ls + olog[used[ent[e1][2]]];
+        }
+        rec.insert(rec.end(), {ent[e0][0], (int32_t)packed, gi, 0});
+        gplog.insert(gplog.end(), pl, pl + 4);
+        e0 = e1;
+      }
+      work += std::max<int32_t>(1, (int32_t)ent.size());
+      if (work >= kM2LRun) {
+        gitem.insert(gitem.end(), {gfirst, (int32_t)rec.size() / 4});
+        gfirst = (int32_t)rec.size() / 4;
+        work = 0;
+      }
+    }
+    if ((int32_t)rec.size() / 4 > gfirst) gitem.insert(gitem.end(), {gfirst, (int32_t)rec.size() / 4});
+    ctx->n_m2g_items = (int64_t)gitem.size() / 2;
+    ctx->m2g_n_off = (int32_t)used.size();
+    if (!gitem.empty()) {
+      const int P1 = ctx->params.p_fmm + 1;
+      std::vector<double> op((size_t)used.size() * P1 * 2);
+      for (size_t u = 0; u < used.size(); ++u)
+        std::copy_n(ctx->tables.opow.begin() + (size_t)used[u] * P1 * 2, (size_t)P1 * 2,
+                    op.begin() + u * P1 * 2);
+      GQ_TRY(upload(ctx, d.m2g_item, gitem.data(), gitem.size() / 2));
+      GQ_TRY(upload(ctx, d.m2g_rec, rec.data(), rec.size() / 4));
+      GQ_TRY(upload(ctx, d.m2g_plog, gplog.data(), gplog.size() / 4));
+      GQ_TRY(upload(ctx, d.m2g_grp, grp.data(), grp.size() / 4));
+      GQ_TRY(upload(ctx, d.m2g_opow, op.data(), op.size() / 2));
+      if (ctx->params.precision == GQ_MIXED_FP32) {
+        const std::vector<float> opf(op.begin(), op.end());
+        GQ_TRY(upload(ctx, d.m2g_opow_f, opf.data(), opf.size() / 2));
+      }
     }
   }
   // Stage 6b work: per box, the sources of its List 4 far boxes (tree order, box by box)

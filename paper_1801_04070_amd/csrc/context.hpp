@@ -47,6 +47,16 @@ struct DevBuffers {
   int2 *m2l_item = nullptr;
   int4 *m2l_pr = nullptr;
   double *m2l_plog = nullptr;
+  // Stage 4 for density batches: target boxes grouped by parent; per group record one source box
+  // (or -1), the compact offset of each member that lists it (4 bytes, 0xFF: none), the group;
+  // per record log s_b + log|o| of each member; per group its member boxes (-1: none); o^-k of
+  // the offsets List 2 uses
+  int2 *m2g_item = nullptr;          // per work-group: (first record, end), whole groups
+  int4 *m2g_rec = nullptr;
+  double4 *m2g_plog = nullptr;
+  int4 *m2g_grp = nullptr;
+  double2 *m2g_opow = nullptr;
+  float2 *m2g_opow_f = nullptr;
   // Stage 6b: boxes with List 4 far sources (box, first, end) and the sources, flattened
   int4 *p2l_item = nullptr;
   int32_t *p2l_src = nullptr;
@@ -137,6 +147,8 @@ struct gq_ctx {
   int64_t n_l2g_items = 0;           // Stage 7 wavefronts
   int64_t n_p2l_boxes = 0;           // boxes with List 4 far sources (Stage 6b)
   int64_t n_m2l_items = 0;           // Stage 4 wavefronts
+  int64_t n_m2g_items = 0;           // Stage 4 work-groups of grouped records (density batches)
+  int32_t m2g_n_off = 0;             // distinct List 2 offsets
   int64_t n_p2m_items = 0, n_p2m_red = 0, n_p2m_parts = 0;  // Stage 2 work
   int64_t n_near_items = 0, n_far_items = 0, n_near_rows = 0;
   int64_t n_m2q_waves = 0;           // packed Stage 5b wavefronts (0: per-box items)

@@ -491,9 +491,10 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
-      const E mv = Md[kc], ov = op[kc];
-      inv[ks] = (pv && k < P1) ? mv : mk2<E>(0.0, 0.0);
-      fv[ks] = k < P1 ? ov : mk2<E>(0.0, 0.0);
+      // raw loads (a select here would wait for them at once): orders k >= P1 meet zero columns
+      // of the fixed matrix, and a pair without a source box is skipped
+      inv[ks] = Md[kc];
+      fv[ks] = op[kc];
     }
     if (!F64) {
 #pragma unroll
@@ -567,6 +568,168 @@ __global__ void __launch_bounds__(256) k_m2l_slots(
   flush(cur);
 }
 
+// Direct load from global memory into LDS: every active lane moves N bytes from its own address
+// to lds + N * lane (lds is the same for the whole wavefront); counted by vmcnt.
+template <int N>
+__device__ __forceinline__ void load_to_lds(const void *src, void *lds) {
+  static_assert(N == 4 || N == 16, "4 or 16 bytes per lane");
+  auto *l = (__attribute__((address_space(3))) void *)lds;
+  if constexpr (N == 16)
+    __builtin_amdgcn_global_load_lds(src, l, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(src, l, 4, 0, 0);
+}
+
+// M2L over a density batch with the target boxes grouped by parent: a record is one source box
+// and the offsets of the (up to four) sibling targets that list it, so its multipole rows are
+// loaded once and serve every member; each member has its own accumulators, written when the
+// group ends. The fixed matrix is held in registers in A-operand order, the o^-k rows of the
+// offsets in use sit in LDS, and the next record's multipole rows travel from memory straight
+// into a per-wavefront LDS buffer (no registers held while they are in flight). A lane of a real
+// column keeps (Re M_k, -Im M_k) and a lane of an imaginary column (Im M_k, Re M_k), so the
+// pre-scaled operand is Re or Im of o^-k M_k with one product and one fma; the post-factor o^-m
+// enters the same way, with Im o^-m signed by the column.
+template <int RT, typename E>
+__global__ void __launch_bounds__(256) k_m2l_grp(
+    const int2 *__restrict__ items, const int4 *__restrict__ recs,
+    const double4 *__restrict__ plog, const int4 *__restrict__ grp, const E *__restrict__ M,
+    const typename Scalar<E>::T *__restrict__ Bt, const E *__restrict__ opow, int n_off, int P1,
+    E *__restrict__ L, int64_t box_st, int n_slots) {
+  critical_path_priority();
+  using R = typename Scalar<E>::T;
+  using Acc = typename Mfma16<R>::Acc;
+  constexpr int KS = 4 * RT;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot0 = (blockIdx.y * (blockDim.x >> 6) + wv) * 8;
+  const int g = lane >> 4, c16 = lane & 15, comp = c16 & 1;
+  const int slot = slot0 + (c16 >> 1);
+  const bool sact = slot < n_slots;
+  const R sgn = comp ? R(1) : R(-1);
+  L += (int64_t)(sact ? slot : slot0) * box_st;
+  // LDS: the o^-k table [n_off][P1], then per wavefront the staged rows of one record, entry
+  // (ks, g, s) = 32 ks + 8 g + s holding M_(4 ks + g) of slot slot0 + s (zero where k >= P1)
+  extern __shared__ unsigned char dyn_lds[];
+  E *Os = reinterpret_cast<E *>(dyn_lds);
+  E *Mb = Os + ((n_off * P1 + 1) & ~1) + wv * (KS * 32);
+  for (int e = threadIdx.x; e < n_off * P1; e += blockDim.x) Os[e] = opow[e];
+  for (int e = lane; e < KS * 32; e += 64) Mb[e] = mk2<E>(0.0, 0.0);
+  __syncthreads();
+  // every thread of the work-group has filled the tables; a wavefront past the last slot stops
+  if (slot0 >= n_slots) return;
+  R A[RT][KS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + c16, k = 4 * ks + g;
+      A[rt][ks] = (i < P1 && k < P1) ? Bt[k * P1 + i] : R(0);
+    }
+  // the loader lanes: a direct load moves U bytes per lane (a whole FP64 entry, or half of an FP32
+  // one), so instruction h fills the EPI entries from EPI h on; entry e is k-step e / 32, order
+  // 4 (e / 32) + (e / 8) % 4, slot slot0 + e % 8
+  constexpr int U = sizeof(E) == 16 ? 16 : 4, EPI = 64 * U / (int)sizeof(E), NI = KS * 32 / EPI;
+  const int le = U == 16 ? lane : lane >> 1, ls = le & 7, lg = (le >> 3) & 3;
+  const bool lact = slot0 + ls < n_slots;
+  const char *Ml = reinterpret_cast<const char *>(M + (int64_t)(lact ? slot0 + ls : slot0) * box_st) +
+                   (U == 16 ? 0 : 4 * (lane & 1));
+  auto stage = [&](int32_t src) {  // rows of box src into this wavefront's buffer
+    if (src < 0) return;
+#pragma unroll
+    for (int h = 0; h < NI; ++h) {
+      const int k = 4 * ((EPI * h + le) >> 5) + lg;
+      if (lact && k < P1)
+        load_to_lds<U>(Ml + ((int64_t)src * P1 + k) * (int64_t)sizeof(E),
+                       reinterpret_cast<char *>(Mb) + 64 * U * h);
+    }
+  };
+  const int2 it = items[blockIdx.x];  // first record, end of records
+  // the records are read two ahead, so that staging the next record's rows waits for nothing
+  int4 rec = recs[it.x], rnx = recs[it.x + 1 < it.y ? it.x + 1 : it.x];
+  stage(rec.x);
+  int32_t cur = rec.z;
+  int4 tg = grp[rec.z];
+  double acc[4][RT][4];
+  auto flush = [&](const int4 &t4) {
+    const int32_t tb[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rt + Mfma16<R>::row(g, v);
+          if (tb[q] >= 0 && sact && m < P1)
+            reinterpret_cast<R *>(L + (int64_t)tb[q] * P1 + m)[comp] = (R)acc[q][rt][v];
+          acc[q][rt][v] = 0.0;
+        }
+  };
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[q][rt][v] = 0.0;
+  const R *Mr = reinterpret_cast<const R *>(Mb + 8 * g + (c16 >> 1));
+  for (int32_t j = it.x; j < it.y; ++j) {
+    const int4 rc = rec;
+    const double4 plc = plog[j];
+    // this record's rows have landed (and the stores of a finished group are out)
+    __builtin_amdgcn_s_waitcnt(0);
+    R m0[KS], m1[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      m0[ks] = Mr[64 * ks + comp];
+      const R o1 = Mr[64 * ks + 1 - comp];
+      m1[ks] = comp ? o1 : -o1;
+    }
+    // the reads are complete before the buffer is filled again with the next record's rows
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    if (j + 1 < it.y) {
+      rec = rnx;
+      stage(rec.x);
+      if (j + 2 < it.y) rnx = recs[j + 2];
+    }
+    if (rc.z != cur) {
+      flush(tg);
+      cur = rc.z;
+      tg = grp[rc.z];
+    }
+    if (rc.x < 0) continue;  // a group without List 2 pairs: its locals are 0
+    const double a0 = (double)m0[0];  // Re M_0 on the real columns of lanes g = 0
+    const double plq[4] = {plc.x, plc.y, plc.z, plc.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = ((uint32_t)rc.y >> (8 * q)) & 0xFF;
+      if (o == 0xFF) continue;
+      const E *op = Os + o * P1;
+      Acc C[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) C[rt] = Acc{R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
+        const E ok = op[kc];
+        const R bf = fma(m0[ks], ok.x, m1[ks] * ok.y);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) C[rt] = mfma16(A[rt][ks], bf, C[rt]);
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * rt + Mfma16<R>::row(g, v);
+          const double y = (double)C[rt][v], yo = lane_xor1(y);
+          const E om = op[m < P1 ? m : P1 - 1];
+          const double px = (double)om.x, py = (double)(sgn * om.y);
+          double a = fma(px, y, acc[q][rt][v]);
+          if (m == 0 && !comp) a = fma(a0, plq[q], a);  // a_0 log|s o|
+          acc[q][rt][v] = fma(py, yo, a);
+        }
+    }
+  }
+  flush(tg);
+}
+
 template <int RT, typename E>
 __global__ void __launch_bounds__(256) k_l2l_slots(
     int32_t n_items, const int2 *__restrict__ items, const int2 *__restrict__ prs,
@@ -596,19 +759,18 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
       const int i = 16 * rt + c16, k = 4 * ks + g;
       A[rt][ks] = (ks >= 4 * rt && i < P1 && k < P1) ? (R)binom_t[k * P1 + i] : R(0);
     }
-  int2 rec;
+  // the pairs are read two ahead, so that the loads of the next pair's rows wait for nothing
+  int2 rec = prs[it.x], rnx = prs[it.x + 1 < it.y ? it.x + 1 : it.x];
   double4 tw;
   E inv[KS];
   auto fetch = [&](int32_t j) {
-    rec = prs[j];
     tw = anc_tw[j];
     const bool pv = rec.x >= 0;
     const E *La = L + (int64_t)(pv ? rec.x : 0) * P1;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + g, kc = k < P1 ? k : P1 - 1;
-      const E lv = La[kc];
-      inv[ks] = (pv && k < P1) ? lv : mk2<E>(0.0, 0.0);
+      inv[ks] = La[kc];  // raw: orders k >= P1 meet zero columns, a pair without ancestor is skipped
     }
   };
   double acc[RT][4];
@@ -638,7 +800,11 @@ __global__ void __launch_bounds__(256) k_l2l_slots(
     E inc[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) inc[ks] = inv[ks];
-    if (j + 1 < it.y) fetch(j + 1);
+    if (j + 1 < it.y) {
+      rec = rnx;
+      fetch(j + 1);
+      if (j + 2 < it.y) rnx = prs[j + 2];
+    }
     if (rc.y != cur) {
       flush(cur);
       cur = rc.y;
@@ -732,11 +898,14 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
   const int32_t len = it.z - it.y;
   double rq[NDB / 8];
   double2 ry = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
-  auto load = [&](int32_t base) {
+  // a batch's source indices are read one batch ahead of its strengths, and the strengths are
+  // kept raw until they are written to LDS (a select at the load would wait for it at once)
+  auto index = [&](int32_t base) {
     const int nb = min(SB, (int)(len - base));
-    const bool in = ss < nb;
-    const int32_t e = it.y + base + (in ? ss : 0);
-    const int32_t src = MODE == 0 ? e : src_idx[e];
+    const int32_t e = it.y + base + (ss < nb ? ss : 0);
+    return MODE == 0 ? e : src_idx[e];
+  };
+  auto load = [&](int32_t src) {
     if (sd == 0) {
       ry = sxy[src];
       rn = snrm[src];
@@ -744,8 +913,7 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
 #pragma unroll
     for (int q = 0; q < NDB / 8; ++q) {
       const int dj = d0 + sd + 8 * q;
-      const double v = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
-      rq[q] = (in && dj < nd) ? v : 0.0;
+      rq[q] = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
     }
   };
   // this wavefront's tiles: t = wv TPW + u; S tile t < RTS, else D tile t - RTS
@@ -770,7 +938,8 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
 #pragma unroll
         for (int v = 0; v < 4; ++v) Cd[F64 ? 0 : u][F64 ? 0 : nt][v] = 0.0;
     }
-  load(0);
+  load(index(0));
+  int32_t snx = SB < len ? index(SB) : 0;
   for (int32_t base = 0; base < len; base += SB) {
     const int nb = min(SB, (int)(len - base));
     __syncthreads();
@@ -779,9 +948,13 @@ __global__ void __launch_bounds__(256, 2) k_p2x_mfma(
       t_n[ss] = rn;
     }
 #pragma unroll
-    for (int q = 0; q < NDB / 8; ++q) t_q[sd + 8 * q][ss] = rq[q];
+    for (int q = 0; q < NDB / 8; ++q)
+      t_q[sd + 8 * q][ss] = (ss < nb && d0 + sd + 8 * q < nd) ? rq[q] : 0.0;
     __syncthreads();
-    if (base + SB < len) load(base + SB);
+    if (base + SB < len) {
+      load(snx);
+      if (base + 2 * SB < len) snx = index(base + 2 * SB);
+    }
     if (!tact[0]) continue;
     const int nks = (nb + 3) >> 2;
     for (int ks = 0; ks < nks; ++ks) {
@@ -1549,11 +1722,13 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
   constexpr int LI = (2 * PQ) % 16, LRT = (2 * PQ) / 16;  // lane row and tile of the log row
   constexpr int NDB = 16 * NT;                            // densities per work-group
   constexpr int SB = 32;                                  // sources staged per batch
-  constexpr int SST = SB + 4;                             // LDS row stride (doubles)
-  __shared__ double t_q[NDB][SST];
+  // LDS strides chosen so that the k-step reads (4 sources x 16 columns) hit distinct banks
+  constexpr int QST = NDB + 1;  // strengths: source-major rows of the batch's densities
+  constexpr int PST = 9;        // powers: 8 per source and one pad
+  __shared__ double t_q[SB][QST];
   __shared__ double2 t_y[SB], t_n[SB];
   __shared__ double2 t_log[kLogTab];
-  __shared__ double2 t_pw[4][SB][8];  // per wavefront (center): z^-1 .. z^-8 of the batch
+  __shared__ double2 t_pw[4][SB][PST];  // per wavefront (center): z^-1 .. z^-8 of the batch
   __shared__ double t_lg[4][SB];      // and log|z|^2
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   (void)n_items;
@@ -1572,10 +1747,13 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
   const int ss = tid % SB, sd = tid / SB;
   double rq[NDB / 8];
   double2 ry = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
-  auto load = [&](int32_t base) {
+  // a batch's source indices are read one batch ahead of its strengths, and the strengths are
+  // kept raw until they are written to LDS (a select at the load would wait for it at once)
+  auto index = [&](int32_t base) {
     const int nb = min(SB, (int)(len - base));
-    const bool in = ss < nb;
-    const int32_t src = near_src[off + base + (in ? ss : 0)];
+    return near_src[off + base + (ss < nb ? ss : 0)];
+  };
+  auto load = [&](int32_t src) {
     if (sd == 0) {
       ry = sxy[src];
       rn = snrm[src];
@@ -1583,8 +1761,7 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
 #pragma unroll
     for (int q = 0; q < NDB / 8; ++q) {
       const int dj = d0 + sd + 8 * q;
-      const double v = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
-      rq[q] = (in && dj < nd) ? v : 0.0;
+      rq[q] = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
     }
   };
   gq_d4 CS[RTS][NT], CD[RTD][NT];
@@ -1595,7 +1772,8 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
 #pragma unroll
     for (int rt = 0; rt < RTD; ++rt) CD[rt][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
   }
-  load(0);
+  load(index(0));
+  int32_t snx = SB < len ? index(SB) : 0;
   for (int32_t base = 0; base < len; base += SB) {
     const int nb = min(SB, (int)(len - base));
     __syncthreads();  // the previous batch is no longer read
@@ -1604,9 +1782,13 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
       t_n[ss] = rn;
     }
 #pragma unroll
-    for (int q = 0; q < NDB / 8; ++q) t_q[sd + 8 * q][ss] = rq[q];
+    for (int q = 0; q < NDB / 8; ++q)
+      t_q[ss][sd + 8 * q] = (ss < nb && d0 + sd + 8 * q < nd) ? rq[q] : 0.0;
     __syncthreads();
-    if (base + SB < len) load(base + SB);  // in flight during this batch
+    if (base + SB < len) {  // in flight during this batch
+      load(snx);
+      if (base + 2 * SB < len) snx = index(base + 2 * SB);
+    }
     if (active) {
       // the pair geometry of the batch, once per (center, source): lane l takes source l % 32
       // and powers 1..4 (l < 32, with the log) or 5..8 of 1/z; zeros past the batch
@@ -1653,7 +1835,7 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const double b = t_q[16 * nt + i][sl];  // B[kk][j]: column j = lane & 15 = i
+        const double b = t_q[sl][16 * nt + i];  // B[kk][j]: column j = lane & 15 = i
 #pragma unroll
         for (int rt = 0; rt < RTS; ++rt) CS[rt][nt] = mfma16(aS[rt], b, CS[rt][nt]);
 #pragma unroll
@@ -2195,6 +2377,8 @@ class StageTimer {
 // column tile of 8 slots per wavefront); fewer slots keep the kernels that batch 8 pairs as the
 // columns of one slot.
 constexpr int kSlotGemmMin = 8;
+// dynamic LDS of the grouped M2L: the o^-k rows of the List 2 offsets in use
+constexpr size_t kM2gLdsMax = 64 * 1024;
 // Densities of a GQ_S_AND_D batch from which the direct interactions run on the matrix cores.
 constexpr int kNearMfmaMin = 8;
 
@@ -2237,13 +2421,14 @@ hipError_t launch_gather(gq_ctx *ctx, const double *d1, int64_t ld1, const doubl
 template <typename E> struct ExpTables;
 template <> struct ExpTables<double2> {
   const double *m2l_bt;
-  const double2 *opow;
-  explicit ExpTables(const DevBuffers &d) : m2l_bt(d.m2l_bt), opow(d.opow) {}
+  const double2 *opow, *m2g_opow;
+  explicit ExpTables(const DevBuffers &d) : m2l_bt(d.m2l_bt), opow(d.opow), m2g_opow(d.m2g_opow) {}
 };
 template <> struct ExpTables<float2> {
   const float *m2l_bt;
-  const float2 *opow;
-  explicit ExpTables(const DevBuffers &d) : m2l_bt(d.m2l_bt_f), opow(d.opow_f) {}
+  const float2 *opow, *m2g_opow;
+  explicit ExpTables(const DevBuffers &d)
+      : m2l_bt(d.m2l_bt_f), opow(d.opow_f), m2g_opow(d.m2g_opow_f) {}
 };
 
 // The three per-order stages of one order bucket.
@@ -2417,7 +2602,17 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   const int32_t ntb = (int32_t)ctx->n_tboxes;
   if (ntb > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2L_P2L);
-    if (slots >= kSlotGemmMin) {
+    // the o^-k table, then 4 wavefronts x (8 slots x 16 RT orders) staged multipole rows
+    const size_t m2g_lds = (((size_t)ctx->m2g_n_off * P1 + 1) & ~(size_t)1) * sizeof(E) +
+                           (size_t)4 * (P1 <= 16 ? 4 : 8) * 32 * sizeof(E);
+    if (slots >= kSlotGemmMin && P1 <= 32 && ctx->n_m2g_items > 0 && m2g_lds <= kM2gLdsMax) {
+      // sibling groups: a GEMM per (record, member) over the slots (8 per wavefront)
+      const int nw = std::min(4, (slots + 7) / 8);
+      auto kern = P1 <= 16 ? k_m2l_grp<1, E> : k_m2l_grp<2, E>;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)ctx->n_m2g_items, (slots + 8 * nw - 1) / (8 * nw)),
+                         dim3(64 * nw), m2g_lds, st, d.m2g_item, d.m2g_rec, d.m2g_plog, d.m2g_grp,
+                         M, X.m2l_bt, X.m2g_opow, ctx->m2g_n_off, P1, L, S.box, slots);
+    } else if (slots >= kSlotGemmMin) {
       // a GEMM per List 2 pair over the slots (8 per wavefront)
       const int nw = std::min(4, (slots + 7) / 8);
       auto kern = P1 <= 16 ? k_m2l_slots<1, E> : P1 <= 32 ? k_m2l_slots<2, E>
