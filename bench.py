@@ -391,6 +391,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--only", default="", help="comma-separated variant names: run only these")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--batch", type=int, default=64, help="densities of the batched variant")
@@ -514,7 +515,12 @@ def main():
                                         "workload": "S then D as two calls on one stream"}}
     outputs = {}
     if not args.no_variants:
+        def want(name):
+            return not args.only or name in args.only.split(",")
+
         def variant(name, workload, nd=1, graph=False, **kw):
+            if not want(name):
+                return
             qv, _ = context(**kw)
             if nd == 1:
                 dv = dens
@@ -561,25 +567,30 @@ def main():
                 "two levels coarser (Remark 2), S and D, FP64, p_fmm 30", level_restrict=1)
         variant("disk_tcr", "disk-shaped target confinement regions (the corrigendum's first "
                 "experiments), S and D, FP64, p_fmm 30", tcr_shape=1)
-        log("bench: off-surface targets")
-        variants["offsurface"] = offsurface_variant(timer, geom, dens_h, args)
-        log(f"bench: offsurface: {variants['offsurface']['ms_per_step']} ms/step")
-        log("bench: ragged batch of 32 geometries")
-        variants["ragged_32"] = ragged_variant(timer, args.steps, args.warmup)
-        log(f"bench: ragged batch: {variants['ragged_32']['speedup_vs_separate']}x vs separate")
+        if want("offsurface"):
+            log("bench: off-surface targets")
+            variants["offsurface"] = offsurface_variant(timer, geom, dens_h, args)
+            log(f"bench: offsurface: {variants['offsurface']['ms_per_step']} ms/step")
+        if want("ragged_32"):
+            log("bench: ragged batch of 32 geometries")
+            variants["ragged_32"] = ragged_variant(timer, args.steps, args.warmup)
+            log(f"bench: ragged batch: {variants['ragged_32']['speedup_vs_separate']}x vs separate")
         for tol in (-10.0, -12.0):
             name = f"learned_orders_1e{int(tol)}"
+            if not want(name):
+                continue
             log(f"bench: learned orders on the wavy lattice, tolerance 1e{int(tol)}")
             variants[name] = learned_variant(timer, max(2, args.steps // 4), max(1, args.warmup),
                                              log10_tol=tol)
             log(f"bench: {name}: {variants[name].get('speedup_vs_uniform')}x")
         # the learned-order workload as specified: 8 x 8 wavy curves, 1024 panels each
         # (1048576 targets, 2097152 centers, 4194304 upsampled sources), tolerance 1e-8
-        log("bench: learned orders, 1048576-target wavy lattice, tolerance 1e-8")
-        variants["learned_orders_1e-8_1m"] = learned_variant(timer, 3, 1, log10_tol=-8.0,
-                                                             panels=1024)
-        log(f"bench: learned_orders_1e-8_1m: "
-            f"{variants['learned_orders_1e-8_1m'].get('speedup_vs_uniform')}x")
+        if want("learned_orders_1e-8_1m"):
+            log("bench: learned orders, 1048576-target wavy lattice, tolerance 1e-8")
+            variants["learned_orders_1e-8_1m"] = learned_variant(timer, 3, 1, log10_tol=-8.0,
+                                                                 panels=1024)
+            log(f"bench: learned_orders_1e-8_1m: "
+                f"{variants['learned_orders_1e-8_1m'].get('speedup_vs_uniform')}x")
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "targets/s", "n_gpus": 1,

@@ -5,6 +5,14 @@ Usage (after the profiling runs, from the repo root):
   python -m paper_1801_04070_amd.profsummary pmc    <counter_collection.csv> [--top 20]
   python -m paper_1801_04070_amd.profsummary traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-mib 256 --out traffic.json
+  python -m paper_1801_04070_amd.profsummary mfma --trace <kernel_trace.csv> \
+        --pmc <counter_collection.csv> [--after KERNEL]
+  python -m paper_1801_04070_amd.profsummary window <kernel_trace.csv> --after KERNEL [--top 20]
+
+``mfma`` reads SQ_INSTS_VALU_MFMA_MOPS_F64 / _F32 (units of 512 flops) per dispatch from one run
+and the launch durations from a kernel trace of the same workload in another, and prints the
+executed matrix-core flops and rate of every kernel that has them. With --after, only the
+dispatches after the last one of KERNEL count in either file (a later phase of the run).
 
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch. ``traffic`` calibrates them with a plain
 device copy of known size (bytes read = bytes written = copy size): the factors are
@@ -114,6 +122,42 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_mib):
             "kernel_sources_sha256": sources_sha256(), "kernels": kernels}
 
 
+PEAK_TFLOPS = {"SQ_INSTS_VALU_MFMA_MOPS_F64": 78.6, "SQ_INSTS_VALU_MFMA_MOPS_F32": 157.3}
+
+
+def _after(rows, kernel, key):
+    """Rows whose key (dispatch id or start time) follows the last dispatch of ``kernel``."""
+    if not kernel:
+        return rows
+    last = max((int(_col(r, key)) for r in rows if short_name(_col(r, "Kernel_Name")) == kernel),
+               default=-1)
+    return [r for r in rows if int(_col(r, key)) > last]
+
+
+def mfma_rates(trace, pmc, after=None):
+    tr = _after(_rows(trace), after, "Start_Timestamp")
+    dur = defaultdict(list)
+    for r in tr:
+        dur[short_name(_col(r, "Kernel_Name"))].append(
+            (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) * 1e-9)
+    per = defaultdict(lambda: defaultdict(float))
+    for r in _after(_rows(pmc), after, "Dispatch_Id"):
+        cn = _col(r, "Counter_Name")
+        if cn in PEAK_TFLOPS:
+            per[(short_name(_col(r, "Kernel_Name")), cn)][_col(r, "Dispatch_Id")] += \
+                float(_col(r, "Counter_Value"))
+    out = []
+    for (k, cn), v in per.items():
+        fl = sum(v.values()) / len(v) * 512.0
+        if fl == 0 or not dur.get(k):
+            continue
+        d = sum(dur[k]) / len(dur[k])
+        out.append({"kernel": k, "counter": cn, "launches": len(dur[k]), "avg_ms": d * 1e3,
+                    "gflop": fl / 1e9, "tflops": fl / d / 1e12,
+                    "frac": fl / d / 1e12 / PEAK_TFLOPS[cn]})
+    return sorted(out, key=lambda x: -x["gflop"] * x["launches"])
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -128,6 +172,14 @@ def main(argv=None):
     for n in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
         c.add_argument(n, required=True)
     c.add_argument("--copy-mib", type=int, required=True)
+    wdw = sub.add_parser("window")
+    wdw.add_argument("csv")
+    wdw.add_argument("--after", required=True)
+    wdw.add_argument("--top", type=int, default=25)
+    m = sub.add_parser("mfma")
+    m.add_argument("--trace", required=True)
+    m.add_argument("--pmc", required=True)
+    m.add_argument("--after", default=None)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         rows = kernel_stats(args.csv)
@@ -142,6 +194,23 @@ def main(argv=None):
             print(f"== {cn} (mean per dispatch)")
             for k, (v, n) in sorted(d.items(), key=lambda kv: -kv[1][0] * kv[1][1])[:args.top]:
                 print(f"{k[:58]:58s} {v:14.1f} x{n}")
+    elif args.cmd == "window":
+        per = defaultdict(list)
+        for r in _after(_rows(args.csv), args.after, "Start_Timestamp"):
+            per[short_name(_col(r, "Kernel_Name"))].append(
+                (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) * 1e-6)
+        tot = sum(sum(v) for v in per.values())
+        print(f"{'kernel':58s} {'calls':>6s} {'total ms':>10s} {'avg us':>9s} {'%':>6s}")
+        for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:args.top]:
+            print(f"{k[:58]:58s} {len(v):6d} {sum(v):10.3f} {sum(v) / len(v) * 1e3:9.2f} "
+                  f"{100 * sum(v) / tot:6.2f}")
+    elif args.cmd == "mfma":
+        print(f"{'kernel':50s} {'launches':>8s} {'avg ms':>8s} {'GFLOP':>8s} {'TF/s':>7s} "
+              f"{'of peak':>7s}")
+        for d in mfma_rates(args.trace, args.pmc, args.after):
+            prec = "f64" if d["counter"].endswith("F64") else "f32"
+            print(f"{d['kernel'][:46]:46s} {prec} {d['launches']:8d} {d['avg_ms']:8.3f} "
+                  f"{d['gflop']:8.2f} {d['tflops']:7.1f} {d['frac']:7.3f}")
     else:
         t = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_mib)
         with open(args.out, "w") as f:
