@@ -49,11 +49,15 @@ enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3, GQ_S_AND_D = 4 };
 /* Where the geometry arrays passed to gq_set_geometry live. */
 enum { GQ_MEM_HOST = 0, GQ_MEM_DEVICE = 1 };
 
-/* Arithmetic of the box expansions. GQ_MIXED_FP32 stores box multipoles and locals in FP32 and
- * runs M2M, M2L (on the FP32 matrix cores) and L2L in FP32; every coefficient is scaled by a power of
- * two per tree level (the box side), so the scaling itself is exact. P2M/P2L sums, the
- * source-to-center (P2QBXL), multipole-to-center (M2QBXL), local-to-center (L2QBXL) steps and the
- * evaluation at the targets stay in FP64. Intended for tolerances around 1e-6. */
+/* Arithmetic of the box expansions. GQ_MIXED_FP32 stores box multipoles and locals in FP32; every
+ * coefficient is scaled by a power of two per tree level (the box side), so the scaling itself is
+ * exact. M2L and the downward pass (L2L as the Stage 7 gather) run on the FP32 matrix cores. For
+ * density batches (8 or more expansion slots) the moments (P2M; M2M is not launched, the moments
+ * are the multipoles it would build) and P2L run on the FP32 matrix cores too, with FP32 products
+ * per batch of sources summed in FP64; one density forms them in FP64 and rounds them to FP32.
+ * The source-to-center (P2QBXL), multipole-to-center (M2QBXL) and local-to-center (L2QBXL) steps,
+ * the pair powers and the evaluation at the targets stay in FP64. Intended for tolerances around
+ * 1e-6. */
 enum { GQ_FP64 = 0, GQ_MIXED_FP32 = 1 };
 
 typedef struct {

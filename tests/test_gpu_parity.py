@@ -244,8 +244,9 @@ def test_density_groups_match_one_density_per_item(c1, kind):
 
 @pytest.mark.parametrize("kind", [1, 2, 3])
 def test_mixed_precision_c1(c1, kind):
-    """FP32 box expansions (P2M, M2M, M2L on FP32 matrix cores, L2L) with power-of-two level
-    scaling at p_fmm = 16 against the FP64 oracle: gate 1e-6."""
+    """FP32 box expansions with power-of-two level scaling at p_fmm = 16 (one density: moments and
+    P2L formed in FP64 and stored in FP32, M2L and the Stage 7 gather on the FP32 matrix cores)
+    against the FP64 oracle: gate 1e-6."""
     from paper_1801_04070_amd import GQ_MIXED_FP32
     mu, mu2 = _densities(c1, 0)
     q, _ = _ctx(c1, p_qbx=8, p_fmm=16, precision=GQ_MIXED_FP32)
