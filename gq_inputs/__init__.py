@@ -327,6 +327,34 @@ def green_test_field(geom: Geometry, x0):
     return dudn, u, 0.5 * np.log(np.einsum("ij,ij->i", d, d))
 
 
+def neumann_test_problem(geom: Geometry, n_charges: int = 25, seed: int = 5,
+                         inner: float = 0.5, outer: float = 1.5):
+    """A manufactured exterior Neumann problem in the manner of Table 5: for every curve of the
+    geometry, n_charges point charges ~ N(0, 1) (seeded) at radius inner x R about its center at
+    angles pi/2 + 2 pi i / n_charges, and as many check points at radius outer x R on the
+    opposite rays. With u(x) = -1/(2 pi) sum_j q_j log|x - z_j|, returns (g, x_check, u_check):
+    g = n . grad u at the nodes (the Neumann data), the check points and u there."""
+    rng = np.random.default_rng(seed)
+    zs, qs, xs = [], [], []
+    al = np.pi / 2 + 2 * np.pi * np.arange(n_charges) / n_charges
+    for c in geom.curves:
+        zs.append(np.stack([c.cx + inner * c.R * np.cos(al), c.cy + inner * c.R * np.sin(al)], 1))
+        qs.append(rng.standard_normal(n_charges))
+        xs.append(np.stack([c.cx + outer * c.R * np.cos(np.pi + al),
+                            c.cy + outer * c.R * np.sin(np.pi + al)], 1))
+    z, q, xc = np.concatenate(zs), np.concatenate(qs), np.concatenate(xs)
+
+    def field(x, nrm=None):
+        d = x[:, None, :] - z[None, :, :]
+        r2 = d[..., 0] ** 2 + d[..., 1] ** 2
+        if nrm is None:
+            return -(0.5 / np.pi) * (q[None, :] * 0.5 * np.log(r2)).sum(1)
+        dn = (nrm[:, None, 0] * d[..., 0] + nrm[:, None, 1] * d[..., 1]) / r2
+        return -(0.5 / np.pi) * (q[None, :] * dn).sum(1)
+
+    return field(geom.src_xy, geom.src_nrm), xc, field(xc)
+
+
 def config_geometry(name: str) -> Geometry:
     """Named workloads: 'c1' starfish (1024 sources), 'c2' 16 random stars (131072 sources)."""
     if name == "c1":

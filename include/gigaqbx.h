@@ -43,8 +43,12 @@ typedef enum {
 
 /* Layer-potential kinds. GQ_S_MINUS_D evaluates S(dens1) - D(dens2), the left side of Green's
  * formula used as the accuracy test in Sec. 5.1. GQ_S_AND_D evaluates both S(dens1) and
- * D(dens1) (two output rows per density). */
-enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3, GQ_S_AND_D = 4 };
+ * D(dens1) (two output rows per density). GQ_SP evaluates S'(dens1) = n(x) . grad_x S(dens1)(x),
+ * the normal derivative of the single layer potential at the targets (the operator of the
+ * exterior Neumann integral equation of Sec. 1, eq. (ext-neumann-ie)), with the target normals
+ * of gq_set_target_normals: the same expansions as GQ_S, differentiated where they are evaluated;
+ * a target with two centers takes the average of the two one-sided limits (the principal value). */
+enum { GQ_S = 1, GQ_D = 2, GQ_S_MINUS_D = 3, GQ_S_AND_D = 4, GQ_SP = 5 };
 
 /* Where the geometry arrays passed to gq_set_geometry live. */
 enum { GQ_MEM_HOST = 0, GQ_MEM_DEVICE = 1 };
@@ -189,6 +193,14 @@ const char *gq_associate_last_error(void);
 gq_status gq_build(gq_ctx *ctx, const gq_params *params);
 
 /*
+ * Unit normals n(x) of the n_tgt targets for GQ_SP: (n_tgt x 2), (x, y) interleaved, in the
+ * caller's target order, host or device memory as mem says; the library copies them. n_tgt must
+ * be the geometry's target count (else GQ_EINVAL; non-finite values: GQ_EINVAL). A later call
+ * replaces them; gq_set_geometry drops them. Before gq_set_geometry: GQ_ESTATE.
+ */
+gq_status gq_set_target_normals(gq_ctx *ctx, int mem, int64_t n_tgt, const double *tgt_nrm);
+
+/*
  * Evaluate, by the GIGAQBX FMM (Algorithm Stages 2-8 plus evaluation of the QBX expansions at
  * the targets), n_dens independent potentials:
  *   kind GQ_S:          out[j] = S dens1[j]
@@ -201,6 +213,7 @@ gq_status gq_build(gq_ctx *ctx, const gq_params *params);
  *                       shared; its D rows agree with a GQ_D evaluation to rounding, its S rows
  *                       exactly). The direct-QBX path (gq_eval_direct) runs the two kinds on two
  *                       library streams forked from and joined back to the context's stream
+ *   kind GQ_SP:         out[j] = S' dens1[j] (needs gq_set_target_normals, else GQ_ESTATE)
  * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
  * caller's source order; out is a device array (n_dens, n_tgt) (GQ_S_AND_D: 2 n_dens rows)
  * with row stride ld_out in the caller's target order. dens2 must be NULL unless kind is

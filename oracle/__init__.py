@@ -27,6 +27,8 @@ def load(path: str):
     L.oracle_qbx_eval.argtypes = [i32, i64, dp, dp, dp, dp, dp, i64, dp, i32, i64, dp,
                                   C.POINTER(C.c_int32), dp]
     L.oracle_point_potential.argtypes = [i32, i64, dp, dp, dp, dp, dp, i64, dp, dp]
+    L.oracle_qbx_normal_derivative.argtypes = [i64, dp, dp, dp, dp, i64, dp, i32, i64, dp, dp,
+                                               C.POINTER(C.c_int32), dp]
     L.oracle_multipole.argtypes = [i32, i64, dp, dp, dp, dp, dp, C.c_double, C.c_double, i32,
                                    dp]
     L.oracle_local.argtypes = L.oracle_multipole.argtypes
@@ -95,6 +97,25 @@ def qbx_coeffs(geom, kind, dens1, dens2=None, p_qbx=8, ctr_xy=None):
     if rc != 0:
         raise RuntimeError(f"oracle_qbx_coeffs failed ({rc})")
     return out[..., 0] + 1j * out[..., 1]
+
+
+def qbx_normal_derivative(geom, dens, p_qbx=8, tgt_xy=None, tgt_nrm=None, tgt_ctr=None):
+    """S' dens (the single layer potential's normal derivative along the target normals) by
+    direct QBX at the geometry's targets (or the given ones); on-surface targets with two
+    centers average the one-sided limits."""
+    (sxy, snrm, sw), d1, _ = _sources(geom, dens, None)
+    cxy = _f64(geom.ctr_xy)
+    txy = _f64(geom.tgt_xy if tgt_xy is None else tgt_xy).reshape(-1, 2)
+    tn = _f64(geom.tgt_nrm if tgt_nrm is None else tgt_nrm).reshape(-1, 2)
+    tc = np.ascontiguousarray(geom.tgt_ctr if tgt_ctr is None else tgt_ctr, dtype=np.int32)
+    out = np.empty(txy.shape[0])
+    rc = lib().oracle_qbx_normal_derivative(sxy.shape[0], _d(sxy), _d(snrm), _d(sw), _d(d1),
+                                            cxy.shape[0], _d(cxy), p_qbx, txy.shape[0], _d(txy),
+                                            _d(tn), tc.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            _d(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_qbx_normal_derivative failed ({rc})")
+    return out
 
 
 def point_potential(geom, kind, dens1, dens2=None, tgt_xy=None):

@@ -14,10 +14,10 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64,
+from ._lib import (GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D, GQ_SP, GQ_MEM_HOST, GQ_MEM_DEVICE, GQ_FP64,
                    GQ_MIXED_FP32, gq_params, gq_stats)
 
-__all__ = ["QBXFMM", "GQError", "library", "associate_targets", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "GQ_S_AND_D",
+__all__ = ["QBXFMM", "GQError", "library", "associate_targets", "GQ_S", "GQ_D", "GQ_S_MINUS_D", "GQ_S_AND_D", "GQ_SP",
            "default_params"]
 
 _L = None
@@ -226,6 +226,19 @@ class QBXFMM:
             import torch
             o = orders.to(torch.int32).contiguous()
             self._check(self._L.gq_set_qbx_orders(self._h, GQ_MEM_DEVICE, o.data_ptr()))
+
+    def set_target_normals(self, tgt_nrm):
+        """Unit normals of the targets for GQ_SP: host numpy (n_tgt, 2) or a device tensor."""
+        if isinstance(tgt_nrm, np.ndarray):
+            a = np.ascontiguousarray(tgt_nrm, dtype=np.float64).reshape(-1, 2)
+            self._nrm_keep = a
+            self._check(self._L.gq_set_target_normals(self._h, GQ_MEM_HOST, a.shape[0],
+                                                      a.ctypes.data))
+        else:
+            a = tgt_nrm.contiguous()
+            self._nrm_keep = a
+            self._check(self._L.gq_set_target_normals(self._h, GQ_MEM_DEVICE, a.shape[0],
+                                                      a.data_ptr()))
 
     def center_orders(self) -> np.ndarray:
         """The compiled QBX order each center runs at (caller order)."""

@@ -50,6 +50,15 @@ void free_workspace(gq_ctx *ctx) {
   ctx->d.anear = nullptr; ctx->d.tv = nullptr;
 }
 
+void drop_target_normals(gq_ctx *ctx) {
+  if (ctx->tnrm_dev && ctx->device >= 0) {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->tnrm_dev);
+  }
+  ctx->tnrm_dev = nullptr;
+  ctx->tgt_nrm.clear();
+}
+
 void free_device(gq_ctx *ctx) {
   free_workspace(ctx);
   ctx->generation++;
@@ -874,7 +883,9 @@ gq_status check_eval_args(gq_ctx *ctx, int kind, int64_t n_dens, const double *d
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (ctx->device < 0) return fail(ctx, GQ_ESTATE, "host-only context cannot evaluate");
   if (!ctx->built) return fail(ctx, GQ_ESTATE, "gq_eval before a successful gq_build");
-  if (kind < GQ_S || kind > GQ_S_AND_D) return fail(ctx, GQ_EINVAL, "unknown kind");
+  if (kind < GQ_S || kind > GQ_SP) return fail(ctx, GQ_EINVAL, "unknown kind");
+  if (kind == GQ_SP && !ctx->tnrm_dev)
+    return fail(ctx, GQ_ESTATE, "GQ_SP needs the target normals (gq_set_target_normals)");
   if (n_dens < 0) return fail(ctx, GQ_EINVAL, "n_dens < 0");
   if (n_dens == 0) return GQ_OK;
   if (!dens1 || !out) return fail(ctx, GQ_EINVAL, "null density or output");
@@ -923,6 +934,7 @@ gq_status set_geometry_impl(gq_ctx *ctx, int mem, int64_t n_geom, const int64_t 
         return fail(ctx, GQ_EINVAL, "offsets must increase (every geometry needs a source)");
   }
   free_device(ctx);
+  drop_target_normals(ctx);
   ctx->have_geom = false;
   ctx->ns = n_src; ctx->nc = n_ctr; ctx->nt = n_tgt;
   ctx->nc_user = n_ctr; ctx->n_pt = 0;
@@ -1131,6 +1143,7 @@ gq_status gq_destroy(gq_ctx *ctx) {
     if (ctx->main2) (void)hipStreamSynchronize(ctx->main2);
   }
   free_device(ctx);
+  drop_target_normals(ctx);
   if (ctx->device >= 0) {
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
@@ -1171,6 +1184,35 @@ gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int6
   if (!src_off) return fail(ctx, GQ_EINVAL, "null offsets");
   return set_geometry_impl(ctx, mem, n_geom, src_off, ctr_off, tgt_off, n_src, src_xy, src_nrm,
                            src_w, n_ctr, ctr_xy, ctr_r, n_tgt, tgt_xy, tgt_ctr);
+}
+
+gq_status gq_set_target_normals(gq_ctx *ctx, int mem, int64_t n_tgt, const double *tgt_nrm) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!ctx->have_geom) return fail(ctx, GQ_ESTATE, "gq_set_target_normals before gq_set_geometry");
+  if (mem != GQ_MEM_HOST && mem != GQ_MEM_DEVICE) return fail(ctx, GQ_EINVAL, "mem must be GQ_MEM_HOST or GQ_MEM_DEVICE");
+  if (mem == GQ_MEM_DEVICE && ctx->device < 0) return fail(ctx, GQ_ESTATE, "device memory on a host-only context");
+  if (n_tgt != ctx->nt) return fail(ctx, GQ_EINVAL, "n_tgt differs from the geometry's target count");
+  if (n_tgt > 0 && !tgt_nrm) return fail(ctx, GQ_EINVAL, "null target normals");
+  std::vector<double> h((size_t)2 * n_tgt);
+  if (n_tgt > 0) {
+    if (mem == GQ_MEM_HOST) std::memcpy(h.data(), tgt_nrm, sizeof(double) * h.size());
+    else GQ_HIP(ctx, hipMemcpy(h.data(), tgt_nrm, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+  }
+  if (!finite_all(h)) return fail(ctx, GQ_EINVAL, "non-finite target normal");
+  if (ctx->device >= 0) {
+    GQ_HIP(ctx, hipSetDevice(ctx->device));
+    if (!ctx->tnrm_dev) {
+      void *p = nullptr;
+      hipError_t e = hipMalloc(&p, std::max<size_t>(h.size(), 2) * sizeof(double));
+      if (e != hipSuccess) return fail(ctx, GQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      ctx->tnrm_dev = static_cast<double2 *>(p);
+    }
+    if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (n_tgt > 0)
+      GQ_HIP(ctx, hipMemcpy(ctx->tnrm_dev, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  }
+  ctx->tgt_nrm.swap(h);
+  return GQ_OK;
 }
 
 gq_status gq_build(gq_ctx *ctx, const gq_params *params) {

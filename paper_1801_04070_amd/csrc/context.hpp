@@ -132,6 +132,11 @@ struct gq_ctx {
   std::vector<double> src_xy, src_nrm, src_w, ctr_xy, ctr_r, tgt_xy;
   std::vector<int32_t> tgt_ctr;
   bool have_geom = false, built = false;
+  // target normals for GQ_SP (caller order, host copy and its device copy) and the flag that
+  // makes the stages of an evaluation of GQ_SP differentiate at the targets
+  std::vector<double> tgt_nrm;
+  double2 *tnrm_dev = nullptr;
+  bool eval_sp = false;
 
   gq_params params{};
   gq::Tree tree;

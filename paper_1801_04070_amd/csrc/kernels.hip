@@ -1470,16 +1470,28 @@ struct NearAccMD {
 };
 
 // QBX expansion of a center evaluated at its targets (QBXL2P), written to the target slots.
+// With target normals (tnrm, the normal derivative S' of GQ_SP): u = Re F with F analytic, so
+// n . grad u = Re(F'(x) nu), nu = n_x + i n_y; the scaled expansion sum_m a_m z^m, z = (x - c)/r,
+// has F' = (1/r) sum_{m>=1} m a_m z^(m-1), formed by the same Horner.
 template <int PQ>
 __device__ __forceinline__ void eval_targets(int32_t c, double2 cc, double r, const double2 *alpha,
                                              const int32_t *__restrict__ c2t_start,
                                              const int32_t *__restrict__ c2t_slot,
-                                             const double2 *__restrict__ txy, double *__restrict__ tv) {
+                                             const double2 *__restrict__ txy, double *__restrict__ tv,
+                                             const double2 *__restrict__ tnrm) {
   const double ir = 1.0 / r;
   for (int32_t g = c2t_start[c]; g < c2t_start[c + 1]; ++g) {
     const int32_t slot = c2t_slot[g];
     const double2 x = txy[slot >> 1];
     const double2 z = make_double2((x.x - cc.x) * ir, (x.y - cc.y) * ir);
+    if (tnrm) {
+      double2 s = cscale(alpha[PQ], (double)PQ);
+#pragma unroll
+      for (int m = PQ - 1; m >= 1; --m) s = cfma(s, z, cscale(alpha[m], (double)m));
+      const double2 d = cmul(s, tnrm[slot >> 1]);
+      tv[slot] = -kInv2Pi * ir * d.x;
+      continue;
+    }
     double2 s = alpha[PQ];
 #pragma unroll
     for (int m = PQ - 1; m >= 0; --m) s = cfma(s, z, alpha[m]);
@@ -2152,7 +2164,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
     const double2 *__restrict__ anear,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
-    int64_t tv_st) {
+    int64_t tv_st, const double2 *__restrict__ tnrm) {
   HIP_DYNAMIC_SHARED(unsigned char, ctr_lds)
   E *Ls = reinterpret_cast<E *>(ctr_lds);  // [kCenterStage][P1]
   __shared__ int32_t sbox[kCenterStage];
@@ -2258,7 +2270,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
       for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], row[m]);
     }
   }
-  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
+  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv, tnrm);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2271,7 +2283,7 @@ __global__ void __launch_bounds__(256) k_direct(
     const double2 *__restrict__ sxy, const double *__restrict__ sq,
     const double2 *__restrict__ sdip, const int32_t *__restrict__ c2t_start,
     const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
-    double *__restrict__ tv, int64_t src_st, int64_t tv_st) {
+    double *__restrict__ tv, int64_t src_st, int64_t tv_st, const double2 *__restrict__ tnrm) {
   __shared__ double2 ts[256];
   {
     const int64_t jd = blockIdx.y;
@@ -2309,7 +2321,7 @@ __global__ void __launch_bounds__(256) k_direct(
 #pragma unroll
   for (int m = 0; m <= PQ; ++m) alpha[m] = make_double2(0.0, 0.0);
   acc.finish(alpha, r);
-  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv);
+  eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv, tnrm);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2515,7 +2527,8 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
                        d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
                        d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear,
-                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv);
+                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv,
+                       ctx->eval_sp ? ctx->tnrm_dev : nullptr);
 }
 
 template <int KIND, typename E>
@@ -2688,7 +2701,8 @@ void launch_direct(gq_ctx *ctx, const OrderBucket &bk, int nd, const Strides &S)
   if (n > 0)
     hipLaunchKernelGGL((k_direct<KIND, PQ>), dim3((n + 255) / 256, nd), dim3(256), 0, ctx->stream,
                        n, d.ctr_list + bk.ctr0, d.cxy, d.cr, (int32_t)ctx->ns, d.sxy, d.sq, d.sdip,
-                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.src, S.tv);
+                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.src, S.tv,
+                       ctx->eval_sp ? ctx->tnrm_dev : nullptr);
 }
 
 // Direct QBX at each center's box order (the same effective orders as the FMM path).
@@ -2748,6 +2762,13 @@ hipError_t run_math(int fn, int64_t n, const double *x, double *out, hipStream_t
 hipError_t run_eval(gq_ctx *ctx, int kind, const double *d1, int64_t ld1, const double *d2,
                     int64_t ld2, double *out, int64_t ld_out, int nd, bool direct, double *out2) {
   hipError_t e;
+  // GQ_SP: the expansions of S, differentiated along the target normals where they are evaluated
+  struct SpFlag {
+    gq_ctx *c;
+    ~SpFlag() { c->eval_sp = false; }
+  } sp_{ctx};
+  ctx->eval_sp = kind == 5;
+  if (kind == 5) kind = 1;
   ctx->cur_kind = kind == 4 ? 1 : kind;
   if (kind == 4) {  // S and D of the same densities through one expansion pipeline
     if (direct || !out2) return hipErrorInvalidValue;

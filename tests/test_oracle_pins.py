@@ -293,3 +293,74 @@ def test_rough_m2l_estimate_order8():
     tail = -math.log1p(-w) - sum(w ** n / n for n in range(1, 9))
     assert err == pytest.approx(tail, rel=1e-9)
     assert est / 10 < err < est
+
+
+# ---- S' (normal derivative of the single layer potential, Sec. 1 eq. (ext-neumann-ie)) ----
+
+def _sp(g, mu, p, side=0):
+    gg = g if side == 0 else g.one_sided(side)
+    return oracle.qbx_normal_derivative(gg, mu, p_qbx=p, tgt_nrm=g.src_nrm)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_circle_normal_derivative_one_sided_limits(k):
+    """Unit circle, density cos k t: S mu = r^k cos(k t)/(2k) inside and r^-k cos(k t)/(2k)
+    outside, so the radial derivative at r = 1 is +cos(k t)/2 from inside (a polynomial: exact
+    for p >= k) and -cos(k t)/2 from outside (converging in p); the average (the principal value
+    S' mu) is 0. Beyond p ~ 12 the quadrature error of the high coefficients (centers at half a
+    panel length, amplified by the factor m of the derivative) takes over, so p stays <= 12."""
+    g = gi.unit_circle(64, order=32)
+    mu = np.cos(k * g.theta)
+    half = 0.5 * np.cos(k * g.theta)
+    assert np.abs(_sp(g, mu, 8, -1) - half).max() < 1e-13
+    errs = [np.abs(_sp(g, mu, p, +1) + half).max() for p in (4, 8, 12)]
+    assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1))
+    assert errs[-1] < 1e-11
+    assert np.abs(_sp(g, mu, 12)).max() < 1e-11
+
+
+def test_circle_normal_derivative_of_constant():
+    """S 1 = 0 inside the unit circle and -log r outside: S' 1 is 0 from inside, -1 from outside,
+    -1/2 on the curve."""
+    g = gi.unit_circle(64, order=32)
+    one = np.ones(g.n_src)
+    assert np.abs(_sp(g, one, 8, -1)).max() < 1e-13
+    assert np.abs(_sp(g, one, 12, +1) + 1.0).max() < 1e-11
+    assert np.abs(_sp(g, one, 12) + 0.5).max() < 1e-11
+
+
+def test_starfish_normal_derivative_jump_and_adjoint_identity():
+    """On a starfish with a smooth density: the one-sided limits differ by the density (the jump
+    of the single layer's normal derivative), and sum_i w_i S' mu(x_i) = -1/2 sum_i w_i mu_i,
+    since S' is the adjoint of the double layer operator and D 1 = -1/2 on the curve (Gauss)."""
+    g = gi.discretize([gi.StarCurve(amp=0.25, arms=5)], 256, order=32)
+    mu = 1.0 + 0.3 * np.cos(2 * g.theta) - 0.2 * np.sin(5 * g.theta)
+    inner, outer = _sp(g, mu, 12, -1), _sp(g, mu, 12, +1)
+    assert np.abs((inner - outer) - mu).max() < 1e-9
+    avg = _sp(g, mu, 12)
+    assert abs(np.sum(g.src_w * avg) + 0.5 * np.sum(g.src_w * mu)) < 1e-12 * np.sum(g.src_w)
+
+
+def test_normal_derivative_matches_finite_differences():
+    """Both branches against central differences of the oracle's potentials along the normal:
+    a point target with no center (plain quadrature) and an off-surface target with one
+    center (the differentiated expansion against the expansion's own values)."""
+    g = gi.discretize([gi.StarCurve(amp=0.25, arms=5)], 32, order=16)
+    mu = np.cos(3 * g.theta)
+    x = np.array([[2.1, 0.7]])
+    nu = np.array([[0.6, 0.8]])
+    h = 1e-5
+    none = np.full((1, 2), -1, dtype=np.int32)
+    got = oracle.qbx_normal_derivative(g, mu, p_qbx=8, tgt_xy=x, tgt_nrm=nu, tgt_ctr=none)
+    up = oracle.point_potential(g, oracle.S, mu, tgt_xy=x + h * nu)
+    dn = oracle.point_potential(g, oracle.S, mu, tgt_xy=x - h * nu)
+    assert abs(got[0] - (up[0] - dn[0]) / (2 * h)) < 1e-8
+    j = 7  # an exterior center; a target inside its disk
+    c, r = g.ctr_xy[2 * j + 1], g.ctr_r[2 * j + 1]
+    xt = (c + 0.5 * r * np.array([0.8, -0.6]))[None, :]
+    one = np.array([[2 * j + 1, -1]], dtype=np.int32)
+    got = oracle.qbx_normal_derivative(g, mu, p_qbx=10, tgt_xy=xt, tgt_nrm=nu, tgt_ctr=one)
+    hh = 1e-6 * r
+    up = oracle.qbx_eval(g, oracle.S, mu, p_qbx=10, tgt_xy=xt + hh * nu, tgt_ctr=one)
+    dn = oracle.qbx_eval(g, oracle.S, mu, p_qbx=10, tgt_xy=xt - hh * nu, tgt_ctr=one)
+    assert abs(got[0] - (up[0] - dn[0]) / (2 * hh)) < 1e-6 * max(1.0, abs(got[0]))
