@@ -272,6 +272,52 @@ def learned_variant(timer, steps, warmup, log10_tol=-10.0, p_fmm=30, panels=192)
                         "Green's formula, FP64"}
 
 
+def neumann_variant(timer, geom, n_rhs=8, p_qbx=12, p_fmm=30, tol=1e-10):
+    """The exterior Neumann integral equation of Sec. 1 (-mu/2 + S' mu = g) on the 16-star
+    workload: n_rhs manufactured problems (25 point charges inside every star, seeds 20..,
+    Table 5's construction) solved together by GMRES, each iteration one batched GQ_SP
+    evaluation of all right-hand sides; then S mu at the check points outside every star (a
+    second context, point targets) against the manufactured field. Timed: the whole solve."""
+    import copy as _copy
+    import numpy as np
+    import torch
+    import gq_inputs as gi
+    from paper_1801_04070_amd import GQ_S, QBXFMM
+    from paper_1801_04070_amd.bie import gmres, neumann_operator
+    probs = [gi.neumann_test_problem(geom, seed=20 + j) for j in range(n_rhs)]
+    rhs = torch.as_tensor(np.stack([p[0] for p in probs]), device="cuda:0")
+    q = QBXFMM(0)
+    q.set_geometry_from(geom)
+    q.build(p_qbx=p_qbx, p_fmm=p_fmm)
+    q.set_target_normals(geom.src_nrm)
+    op = neumann_operator(q)
+    gmres(op, rhs, tol=tol, maxiter=3)  # warm-up (workspace, first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, its, res = gmres(op, rhs, tol=tol, maxiter=60)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ev = _copy.copy(geom)
+    ev.tgt_xy = probs[0][1]
+    ev.tgt_ctr = np.full((len(ev.tgt_xy), 2), -1, dtype=np.int32)
+    qe = QBXFMM(0)
+    qe.set_geometry_from(ev)
+    qe.build(p_qbx=p_qbx, p_fmm=p_fmm)
+    u = qe.eval(GQ_S, x).cpu().numpy()
+    errs = [float(np.abs(u[j] - probs[j][2]).max() / np.abs(probs[j][2]).max())
+            for j in range(n_rhs)]
+    n_it = int(its.max())
+    q.close()
+    qe.close()
+    return {"value": round(n_rhs * n_it * geom.n_tgt / sec, 1), "unit": "targets/s",
+            "ms_per_solve": round(sec * 1e3, 2), "n_rhs": n_rhs,
+            "gmres_iterations": [int(i) for i in its], "final_residuals": [float(r) for r in res],
+            "bvp_rel_errors": errs, "n_check_points": int(len(ev.tgt_xy)),
+            "workload": f"exterior Neumann equation, {n_rhs} right-hand sides by batched GMRES "
+                        f"to {tol:g}, S' by GQ_SP (p_qbx {p_qbx}, p_fmm {p_fmm}); value = "
+                        "right-hand sides x iterations x targets / solve time"}
+
+
 def offsurface_variant(timer, geom, dens_h, args, n_side=384, p_qbx=12, p_fmm=30):
     """Targets on a regular grid over the 16-star workload's bounding box (n_side^2 points)
     instead of on the curves: gq_associate_targets (Sec. 2.2.2, 20 % slack, conventional beyond
@@ -571,6 +617,11 @@ def main():
             log("bench: off-surface targets")
             variants["offsurface"] = offsurface_variant(timer, geom, dens_h, args)
             log(f"bench: offsurface: {variants['offsurface']['ms_per_step']} ms/step")
+        if want("neumann_bie"):
+            log("bench: exterior Neumann equation by batched GMRES")
+            variants["neumann_bie"] = neumann_variant(timer, geom)
+            log(f"bench: neumann_bie: {variants['neumann_bie']['ms_per_solve']} ms per solve, "
+                f"{max(variants['neumann_bie']['gmres_iterations'])} iterations")
         if want("ragged_32"):
             log("bench: ragged batch of 32 geometries")
             variants["ragged_32"] = ragged_variant(timer, args.steps, args.warmup)
