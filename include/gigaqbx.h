@@ -193,6 +193,23 @@ const char *gq_associate_last_error(void);
 gq_status gq_build(gq_ctx *ctx, const gq_params *params);
 
 /*
+ * The box expansions of the last evaluation, for operator-level tests: what = GQ_EXP_MULTIPOLE
+ * (every box's multipole, Stage 2), GQ_EXP_LOCAL (every target-or-ancestor box's own local: List 2
+ * by M2L plus List 4 far by P2L, Stages 4 and 6b) or GQ_EXP_LOCAL_COMPLETE (the complete local of
+ * every box owning centers after the downward pass, Stage 7; other boxes' rows are not written).
+ * Layout: n_boxes x (p_fmm + 1) complex values, (re, im) interleaved, boxes in the order of the
+ * tree arrays, coefficients scaled by the box side s: a_k / s^k (multipoles, the expansion
+ * a_0 log(z - c) + sum_k a_k (z - c)^-k) and b_k s^k (locals, sum_k b_k (z - c)^k). slot selects
+ * the density slot of the evaluation (0 for one density; GQ_S_AND_D of n densities uses slots
+ * 0..n-1 for S and n..2n-1 for D). *count receives the number of complex values; dst NULL asks
+ * for the count only; else dst (host) receives them, after the context's streams have finished.
+ * Errors: GQ_ESTATE before a build or an evaluation that filled the slot; GQ_EUNSUP for
+ * GQ_MIXED_FP32 contexts (FP32 storage); GQ_EINVAL for an unknown what or a null count.
+ */
+enum { GQ_EXP_MULTIPOLE = 1, GQ_EXP_LOCAL = 2, GQ_EXP_LOCAL_COMPLETE = 3 };
+gq_status gq_get_expansions(gq_ctx *ctx, int what, int64_t slot, double *dst, int64_t *count);
+
+/*
  * Unit normals n(x) of the n_tgt targets for GQ_SP: (n_tgt x 2), (x, y) interleaved, in the
  * caller's target order, host or device memory as mem says; the library copies them. n_tgt must
  * be the geometry's target count (else GQ_EINVAL; non-finite values: GQ_EINVAL). A later call

@@ -240,6 +240,16 @@ class QBXFMM:
             self._check(self._L.gq_set_target_normals(self._h, GQ_MEM_DEVICE, a.shape[0],
                                                       a.data_ptr()))
 
+    def expansions(self, what: int, slot: int = 0) -> np.ndarray:
+        """Box expansions of the last evaluation (gq_get_expansions): (n_boxes, p_fmm + 1)
+        complex, scaled by the box side (a_k / s^k, b_k s^k)."""
+        n = C.c_int64()
+        self._check(self._L.gq_get_expansions(self._h, what, slot, None, C.byref(n)))
+        out = np.empty(2 * n.value, dtype=np.float64)
+        self._check(self._L.gq_get_expansions(self._h, what, slot, out.ctypes.data, C.byref(n)))
+        c = out[0::2] + 1j * out[1::2]
+        return c.reshape(-1, self.params.p_fmm + 1)
+
     def center_orders(self) -> np.ndarray:
         """The compiled QBX order each center runs at (caller order)."""
         out = np.empty(self.n_ctr, dtype=np.int32)

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libgigaqbx.so")
 
 GQ_OK, GQ_EINVAL, GQ_ENOMEM, GQ_EHIP, GQ_ESTATE, GQ_EUNSUP = 0, -1, -2, -3, -4, -5
 GQ_S, GQ_D, GQ_S_MINUS_D, GQ_S_AND_D, GQ_SP = 1, 2, 3, 4, 5
+GQ_EXP_MULTIPOLE, GQ_EXP_LOCAL, GQ_EXP_LOCAL_COMPLETE = 1, 2, 3
 GQ_MEM_HOST, GQ_MEM_DEVICE = 0, 1
 GQ_FP64, GQ_MIXED_FP32 = 0, 1
 GQ_MAX_P_QBX, GQ_MAX_P_FMM = 20, 63
@@ -56,7 +57,7 @@ EXPORTED = ["gq_default_params", "gq_create", "gq_destroy", "gq_set_stream", "gq
             "gq_set_geometry_batch",
             "gq_build", "gq_eval", "gq_eval_direct", "gq_get_stats", "gq_get_tree_array",
             "gq_set_qbx_orders", "gq_get_box_orders", "gq_get_center_orders",
-            "gq_set_target_normals",
+            "gq_set_target_normals", "gq_get_expansions",
             "gq_set_profiling", "gq_get_stage_times",
             "gq_graph_create", "gq_graph_launch", "gq_graph_destroy", "gq_autotune",
             "gq_get_params", "gq_device_math", "gq_eval_noalloc", "gq_associate_targets",
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
     L.gq_get_box_orders.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.gq_get_center_orders.argtypes = [vp, vp]
     L.gq_set_target_normals.argtypes = [vp, i32, i64, dp]
+    L.gq_get_expansions.argtypes = [vp, i32, i64, dp, C.POINTER(C.c_int64)]
     L.gq_set_profiling.argtypes = [vp, i32]
     L.gq_get_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.gq_graph_create.argtypes = [vp, i32, i64, dp, i64, dp, i64, dp, i64, C.POINTER(C.c_void_p)]

@@ -1186,6 +1186,31 @@ gq_status gq_set_geometry_batch(gq_ctx *ctx, int mem, int64_t n_geom, const int6
                            src_w, n_ctr, ctr_xy, ctr_r, n_tgt, tgt_xy, tgt_ctr);
 }
 
+gq_status gq_get_expansions(gq_ctx *ctx, int what, int64_t slot, double *dst, int64_t *count) {
+  if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
+  if (!count) return fail(ctx, GQ_EINVAL, "null count");
+  if (!ctx->built || ctx->device < 0) return fail(ctx, GQ_ESTATE, "no tree built on a device");
+  const int64_t n = ctx->tree.n_boxes() * (ctx->params.p_fmm + 1);
+  const double2 *src = nullptr;
+  switch (what) {
+    case GQ_EXP_MULTIPOLE: src = ctx->d.M; break;
+    case GQ_EXP_LOCAL: src = ctx->d.L; break;
+    case GQ_EXP_LOCAL_COMPLETE: src = ctx->d.Lf; break;
+    default: return fail(ctx, GQ_EINVAL, "unknown expansion kind");
+  }
+  *count = n;
+  if (!dst) return GQ_OK;
+  if (ctx->params.precision != GQ_FP64)
+    return fail(ctx, GQ_EUNSUP, "expansions are read back from FP64 contexts only");
+  if (!src || slot < 0 || slot >= ctx->ws_batch)
+    return fail(ctx, GQ_ESTATE, "no evaluation has filled this workspace slot");
+  GQ_HIP(ctx, hipSetDevice(ctx->device));
+  if (ctx->stream) GQ_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->side) GQ_HIP(ctx, hipStreamSynchronize(ctx->side));
+  GQ_HIP(ctx, hipMemcpy(dst, src + slot * n, sizeof(double2) * n, hipMemcpyDeviceToHost));
+  return GQ_OK;
+}
+
 gq_status gq_set_target_normals(gq_ctx *ctx, int mem, int64_t n_tgt, const double *tgt_nrm) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (!ctx->have_geom) return fail(ctx, GQ_ESTATE, "gq_set_target_normals before gq_set_geometry");
