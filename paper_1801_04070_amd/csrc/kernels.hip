@@ -1621,8 +1621,8 @@ struct NearAccSD {
   }
 };
 
-// Up to order 12 the accumulators fit three waves per SIMD with a spill of a few bytes, which
-// measured 10 % faster than two waves without one; higher orders keep two.
+// Up to order 12 the accumulators fit three waves per SIMD (168 registers, no spill), which
+// measured 10 % faster than two; higher orders keep two.
 template <int PQ>
 __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
