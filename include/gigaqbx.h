@@ -324,6 +324,30 @@ gq_status gq_graph_create(gq_ctx *ctx, int kind, int64_t n_dens, const double *d
 gq_status gq_graph_launch(gq_graph *graph);
 gq_status gq_graph_destroy(gq_graph *graph);
 
+/*
+ * Modeled operation counts (Sec. 4.6 and the per-list-entry cost model of Sec. 5): an expansion
+ * of order p costs p to form from one source or to evaluate, a translation between orders p and
+ * p' costs p p'. With n_s the sources of a source box, n_t the QBX centers owned by a target box
+ * (each at its own QBX order p_c, so n_t p_QBX reads as the sum of p_c over them) and N_S the
+ * sources, one evaluation of one density is modeled as
+ *   GQ_OP_MULTIPOLES  N_S p_FMM                      (Stage 2, forming leaf multipoles)
+ *   GQ_OP_M2M         p_FMM^2 per upward shift       (Stage 2: boxes with sources and a parent)
+ *   GQ_OP_LIST1       p_QBX n_s n_t per List 1 entry (Stage 3)
+ *   GQ_OP_LIST2       p_FMM^2 per List 2 entry       (Stage 4)
+ *   GQ_OP_LIST3_CLOSE p_QBX n_s n_t per entry        (Stage 5a)
+ *   GQ_OP_LIST3_FAR   p_FMM p_QBX n_t per entry      (Stage 5b)
+ *   GQ_OP_LIST4_CLOSE p_QBX n_s n_t per entry        (Stage 6a)
+ *   GQ_OP_LIST4_FAR   p_FMM n_s per entry            (Stage 6b)
+ *   GQ_OP_L2L         p_FMM^2 per downward shift     (Stage 7: boxes with a local and a parent)
+ *   GQ_OP_L2QBXL      p_FMM p_QBX per QBX center     (Stage 8)
+ * Conventional (non-QBX) targets and their internal centers are not in the model. The counts
+ * describe the method, not the kernels (which form multipoles from whole subtrees, for one).
+ */
+enum {
+  GQ_OP_MULTIPOLES = 0, GQ_OP_M2M, GQ_OP_LIST1, GQ_OP_LIST2, GQ_OP_LIST3_CLOSE, GQ_OP_LIST3_FAR,
+  GQ_OP_LIST4_CLOSE, GQ_OP_LIST4_FAR, GQ_OP_L2L, GQ_OP_L2QBXL, GQ_N_OPS
+};
+
 /* Sizes of the tree and lists after gq_build (Sec. 4.3, and the stage costs of Table 2). */
 typedef struct {
   int64_t n_src, n_ctr, n_tgt;
@@ -357,6 +381,9 @@ typedef struct {
                                     (every source when t_f = 0); computed on the first
                                     gq_get_stats after a build                                */
   int64_t m_c_sum;               /* the sum behind m_c (N_C m_c)                            */
+  int64_t model_ops[GQ_N_OPS];   /* modeled operation counts per GQ_OP_* stage (above), for the
+                                    current QBX orders; computed on each gq_get_stats        */
+  int64_t model_ops_total;       /* their sum                                               */
 } gq_stats;
 
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out);

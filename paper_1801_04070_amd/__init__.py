@@ -177,6 +177,7 @@ class QBXFMM:
         self._check(self._L.gq_get_stats(self._h, C.byref(s)))
         d = {name: getattr(s, name) for name, _ in gq_stats._fields_}
         d["root_lo"] = tuple(s.root_lo)
+        d["model_ops"] = dict(zip(_lib.GQ_OP_NAMES, list(s.model_ops)))
         return d
 
     _TREE_TYPES = {

@@ -34,6 +34,11 @@ class gq_params(C.Structure):
                 ("level_restrict", C.c_int)]
 
 
+GQ_OP_NAMES = ["multipoles", "m2m", "list1", "list2", "list3_close", "list3_far", "list4_close",
+               "list4_far", "l2l", "l2qbxl"]
+GQ_N_OPS = len(GQ_OP_NAMES)
+
+
 class gq_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "n_src", "n_ctr", "n_tgt", "n_boxes", "n_levels", "n_leaves", "n_target_boxes",
@@ -46,7 +51,9 @@ class gq_stats(C.Structure):
         ("n_l2l_pairs", C.c_int64), ("n_moment_boxes", C.c_int64),
         ("n_moment_pairs", C.c_int64), ("n_moment_parts", C.c_int64),
         ("n_m2q_waves", C.c_int64), ("n_m2q_pairs", C.c_int64), ("n_m2q_units", C.c_int64),
-        ("m_c", C.c_double), ("m_c_sum", C.c_int64)]
+        ("m_c", C.c_double), ("m_c_sum", C.c_int64),
+        ("model_ops", C.c_int64 * GQ_N_OPS), ("model_ops_total", C.c_int64)]
+
 
 
 GQ_STAGE_NAMES = ["gather", "p2m", "m2m", "m2l_p2l", "l2l", "near", "m2qbxl", "qbx_center",

@@ -1429,6 +1429,36 @@ gq_status gq_graph_destroy(gq_graph *graph) {
   return GQ_OK;
 }
 
+// Modeled operation counts per GQ_OP_* stage (the per-list-entry cost model): every QBX center
+// at its own order, the box sums weighted by the orders of the user centers a box owns.
+static void model_ops(const gq_ctx *ctx, int64_t *ops) {
+  const gq::Tree &t = ctx->tree;
+  const int64_t pf = ctx->params.p_fmm, nb = t.n_boxes();
+  auto ns = [&](int32_t d) { return t.n_src_subtree(d); };
+  auto sum_src = [&](const gq::Csr &l, int64_t b) {
+    int64_t n = 0;
+    for (int64_t i = l.start[b]; i < l.start[b + 1]; ++i) n += ns(l.idx[i]);
+    return n;
+  };
+  for (int k = 0; k < GQ_N_OPS; ++k) ops[k] = 0;
+  ops[GQ_OP_MULTIPOLES] = pf * ctx->ns;
+  for (int64_t b = 0; b < nb; ++b) {
+    if (t.parent[b] >= 0 && ns((int32_t)b) > 0) ops[GQ_OP_M2M] += pf * pf;
+    if (t.parent[b] >= 0 && t.has_tgt[b]) ops[GQ_OP_L2L] += pf * pf;
+    ops[GQ_OP_LIST2] += pf * pf * t.list2.row_size(b);
+    ops[GQ_OP_LIST4_FAR] += pf * sum_src(t.list4f, b);
+    int64_t pq = 0;  // sum of the QBX orders of the user centers box b owns
+    for (int64_t k = t.ctr_begin[b]; k < t.ctr_end[b]; ++k)
+      if (t.ctr_order[k] < ctx->nc_user) pq += ctx->ctr_pq.empty() ? ctx->params.p_qbx : ctx->ctr_pq[k];
+    if (pq == 0) continue;
+    ops[GQ_OP_LIST1] += pq * sum_src(t.list1, b);
+    ops[GQ_OP_LIST3_CLOSE] += pq * sum_src(t.list3c, b);
+    ops[GQ_OP_LIST4_CLOSE] += pq * sum_src(t.list4c, b);
+    ops[GQ_OP_LIST3_FAR] += pf * pq * t.list3f.row_size(b);
+    ops[GQ_OP_L2QBXL] += pf * pq;
+  }
+}
+
 gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   if (!ctx) return fail(nullptr, GQ_EINVAL, "null context");
   if (!out) return fail(ctx, GQ_EINVAL, "null output");
@@ -1480,6 +1510,8 @@ gq_status gq_get_stats(gq_ctx *ctx, gq_stats *out) {
   out->m_c = ctx->nc_user > 0 ? (double)ctx->m_c_sum / (double)ctx->nc_user : 0.0;
   out->root_lo[0] = t.lo[0]; out->root_lo[1] = t.lo[1]; out->root_side = t.side;
   out->build_ms = ctx->build_ms;
+  model_ops(ctx, out->model_ops);
+  for (int k = 0; k < GQ_N_OPS; ++k) out->model_ops_total += out->model_ops[k];
   return GQ_OK;
 }
 

@@ -706,3 +706,81 @@ def test_fmm_order_from_accuracy():
         with pytest.raises(GQError) as e:
             q.build(p_qbx=8, p_fmm=0, eps=bad)
         assert e.value.status == _lib.GQ_EINVAL
+
+
+def _model_ops_from_lists(T, orders, n_user, p_fmm, n_src):
+    """The per-list-entry cost model, center by center from the exported tree and lists: a QBX
+    center of order p in box b costs p per source of List 1, List 3 close and List 4 close of b,
+    p_FMM p per List 3 far box and p_FMM p for its own local (Stage 8); List 2 entries cost
+    p_FMM^2, List 4 far entries p_FMM per source; forming multipoles p_FMM per source, and each
+    upward (downward) shift p_FMM^2 for a non-root box with sources (with centers below it)."""
+    ops = dict.fromkeys(_lib.GQ_OP_NAMES, 0)
+    ns = T["src"][:, 1] - T["src"][:, 0]
+    nb = len(T["level"])
+    has_ctr = np.zeros(nb, bool)
+    for b in range(nb):
+        if T["ctr"][b, 1] > T["ctr"][b, 0]:
+            a = b
+            while a >= 0 and not has_ctr[a]:
+                has_ctr[a] = True
+                a = T["parent"][a]
+    ops["multipoles"] = p_fmm * n_src
+    for b in range(nb):
+        if T["parent"][b] >= 0:
+            ops["m2m"] += p_fmm ** 2 * (ns[b] > 0)
+            ops["l2l"] += p_fmm ** 2 * has_ctr[b]
+        ops["list2"] += p_fmm ** 2 * len(_row(T, "list2", b))
+        ops["list4_far"] += p_fmm * int(ns[_row(T, "list4f", b)].sum())
+        for k in range(T["ctr"][b, 0], T["ctr"][b, 1]):
+            c = T["ctr_order"][k]
+            if c >= n_user:
+                continue
+            p = int(orders[c])
+            ops["list1"] += p * int(ns[_row(T, "list1", b)].sum())
+            ops["list3_close"] += p * int(ns[_row(T, "list3c", b)].sum())
+            ops["list4_close"] += p * int(ns[_row(T, "list4c", b)].sum())
+            ops["list3_far"] += p_fmm * p * len(_row(T, "list3f", b))
+            ops["l2qbxl"] += p_fmm * p
+    return ops
+
+
+def test_modeled_operation_counts():
+    """gq_stats.model_ops against the cost model evaluated center by center from the exported
+    lists, at the uniform order, after per-center orders, and with conventional targets (whose
+    internal centers the model leaves out); under the uniform order the direct and far terms
+    also equal the orders times the pair counts the stats report."""
+    g = gi.random_stars(n_curves=3, panels_per_curve=64, seed=21, box=12.0)
+    q, T = _build(g, p_qbx=12, p_fmm=30, n_max=8)
+    st = T["stats"]
+    exp = _model_ops_from_lists(T, np.full(g.n_ctr, 12), g.n_ctr, 30, g.n_src)
+    assert st["model_ops"] == exp
+    assert st["model_ops_total"] == sum(exp.values())
+    near = exp["list1"] + exp["list3_close"] + exp["list4_close"]
+    assert near == 12 * st["near_pairs"]
+    assert exp["list3_far"] == 30 * 12 * st["list3_far_pairs"]
+    assert exp["list4_far"] == 30 * st["list4_far_sources"]
+    assert exp["list2"] == 30 ** 2 * st["n_list2"]
+    assert exp["l2qbxl"] == 30 * 12 * g.n_ctr
+    # Table 2's bounds: Stage 4 <= 75 N_B p_FMM^2, Stage 7 <= 4 N_B p_FMM^2 (one shift per box)
+    assert exp["list2"] <= 75 * st["n_boxes"] * 30 ** 2
+    assert exp["l2l"] <= st["n_boxes"] * 30 ** 2 and exp["m2m"] <= st["n_boxes"] * 30 ** 2
+
+    orders = np.random.default_rng(3).integers(0, 13, size=g.n_ctr).astype(np.int32)
+    q.set_qbx_orders(orders)
+    got = q.stats()["model_ops"]
+    assert got == _model_ops_from_lists(T, q.center_orders(), g.n_ctr, 30, g.n_src)
+    assert got["list2"] == exp["list2"] and got["list1"] < exp["list1"]
+
+    pts, tgt_xy, tgt_ctr = _with_point_targets(g)
+    q2 = QBXFMM(device=-1)
+    q2.set_geometry(g.src_xy, g.src_nrm, g.src_w, g.ctr_xy, g.ctr_r, tgt_xy, tgt_ctr)
+    s2 = q2.build(p_qbx=8, p_fmm=10, n_max=16)
+    T2 = {"level": q2.tree_array(_lib.GQ_TREE_BOX_LEVEL),
+          "parent": q2.tree_array(_lib.GQ_TREE_BOX_PARENT),
+          "src": q2.tree_array(_lib.GQ_TREE_BOX_SRC_RANGE),
+          "ctr": q2.tree_array(_lib.GQ_TREE_BOX_CTR_RANGE),
+          "ctr_order": q2.tree_array(_lib.GQ_TREE_CTR_ORDER)}
+    T2.update(q2.lists())
+    exp2 = _model_ops_from_lists(T2, np.full(g.n_ctr, 8), g.n_ctr, 10, g.n_src)
+    assert s2["model_ops"] == exp2
+    assert exp2["l2qbxl"] == 10 * 8 * g.n_ctr
