@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QBX-FMM targets/s at 1e-10 rel err, plain vs batched/mixed/learned, 1 GPU"
 GATE = 1e-10
 # kernels of each stage in a GQ_S_AND_D evaluation of one density
-KERNEL_OF_STAGE = {"near": "k_near_sd", "m2qbxl": "k_m2qbxl_packed", "qbx_center": "k_qbx_center",
+KERNEL_OF_STAGE = {"near": "k_near_sd_t", "m2qbxl": "k_m2qbxl_packed", "qbx_center": "k_qbx_center",
                    "m2l_p2l": "k_m2l_mb", "m2m": "k_m_reduce", "l2l": "k_l2l_gather",
                    "p2m": "k_p2m_all", "gather": "k_gather", "finalize": "k_finalize"}
 
@@ -502,7 +502,9 @@ def main():
     agg, breakdown = per_stage(stages, args.steps)
     n_slots = int((geom.tgt_ctr >= 0).sum())
     # each stage interval of a GQ_S_AND_D step covers the work of both kinds (kind 4 below)
-    work = perfmodel.stage_work(stats, 4, p_qbx, p_fmm, n_slots)
+    used = geom.tgt_ctr[geom.tgt_ctr >= 0]
+    one_target = used.size == 0 or int(np.bincount(used).max()) <= 1
+    work = perfmodel.stage_work(stats, 4, p_qbx, p_fmm, n_slots, near_values=one_target)
     dom = max(agg, key=lambda n: agg[n][0])
     ms_dom, n_dom = agg[dom]
     avg_ms = ms_dom / n_dom

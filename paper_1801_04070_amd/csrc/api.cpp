@@ -164,7 +164,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   for (void *p : ctx->nw_allocations) (void)hipFree(p);
   ctx->nw_allocations.clear();
   ctx->generation++;
-  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), items, fitems, clist;
+  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), nnear(nb, 0), items, fitems, clist;
   std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
   std::vector<double> qgeo;
@@ -237,6 +237,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     const int64_t fchunks = (wlen + far_chunk - 1) / far_chunk;
     base[b] = (int32_t)rows;
     nch[b] = (int32_t)(nchunks + fchunks);
+    nnear[b] = (int32_t)nchunks;
     rows += (nchunks + fchunks) * nc;
   }
   // items and centers, grouped by order
@@ -362,6 +363,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.bctr1, bctr1.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.part_base, base.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.n_chunks, nch.data(), nb);
+  if (st == GQ_OK) st = upload(ctx, d.n_near_chunks, nnear.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.ctr_list, clist.data(), clist.size());
   ctx->nw_allocations.swap(ctx->allocations);
   ctx->allocations.swap(saved);
@@ -433,6 +435,9 @@ gq_status upload_all(gq_ctx *ctx) {
     GQ_TRY(upload(ctx, d.cbox, t.ctr_box.data(), nc));
     GQ_TRY(upload(ctx, d.c2t_start, ca.start.data(), nc + 1));
     GQ_TRY(upload(ctx, d.c2t_slot, ca.slot.data(), ca.slot.size()));
+    ctx->one_target_per_center = true;
+    for (int64_t k = 0; k < nc; ++k)
+      if (ca.start[k + 1] - ca.start[k] > 1) ctx->one_target_per_center = false;
     GQ_TRY(upload(ctx, d.txy, ctx->tgt_xy.data(), nt));
     GQ_TRY(upload(ctx, d.tctr, ctx->tgt_ctr.data(), 2 * nt));
   }

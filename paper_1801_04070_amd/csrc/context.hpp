@@ -81,6 +81,7 @@ struct DevBuffers {
   int32_t *bctr0 = nullptr, *bctr1 = nullptr;   // owned center range per box
   int32_t *part_base = nullptr;      // first near row of each box
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box
+  int32_t *n_near_chunks = nullptr;  // of them direct-source chunks (the first ones)
   int32_t *ctr_list = nullptr;       // tree-order centers grouped by order
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
   // tables
@@ -137,6 +138,9 @@ struct gq_ctx {
   std::vector<double> tgt_nrm;
   double2 *tnrm_dev = nullptr;
   bool eval_sp = false;
+  // every center (caller's and internal) serves at most one target slot: the fused S and D
+  // direct pass of one density then sums at the targets (set at upload)
+  bool one_target_per_center = false;
 
   gq_params params{};
   gq::Tree tree;

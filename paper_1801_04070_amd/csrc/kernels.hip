@@ -1709,6 +1709,118 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   }
 }
 
+// S and D of one density evaluated at the centers' own targets, for geometries in which every
+// center serves at most one target (a target on the curve takes one center on each side). The
+// direct part of a center's expansion is then needed at one point only, x, and is summed there:
+// for a source y of charge q and dipole strength d, with z = y - c and rho = (x - c)/z,
+//   S: q (log|z| - Re sum_{k=1..p} rho^k / k),   D: Re((d / z) sum_{k=0..p} rho^k),
+// the truncated series of the coefficient rows of k_near_sd, summed in another order. Both
+// polynomials have real coefficients, so each is evaluated at the complex point rho by the
+// second-order recurrence for real polynomials at a complex argument (Knuth, The Art of
+// Computer Programming, vol. 2, Sec. 4.6.4): with r1 = 2 Re rho and s = |rho|^2,
+// b_k = a_k + r1 b_(k+1) - s b_(k+2) downwards from b_p = a_p, and P(rho) = b_1 rho + a_0 - s b_2;
+// two fused multiply-adds per order and polynomial, against a complex product and a complex
+// accumulation per order for the coefficients. Each (center, chunk) row gets the value in the
+// real part of its order-0 entry (S; D d_off entries further), which the center stage adds to the
+// constant term of the center's expansion; the row's other entries are neither written nor read.
+template <int PQ>
+__global__ void __launch_bounds__(64) k_near_sd_t(
+    int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double2 *__restrict__ sxy,
+    const double *__restrict__ sq, const double2 *__restrict__ sdip,
+    const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
+    const double2 *__restrict__ txy, double2 *__restrict__ anear, int rs, int64_t d_off) {
+  static_assert(PQ >= 2, "the recurrences start at b_p and b_(p-1)");
+  __shared__ double2 t_xy[kNearBatch];
+  __shared__ double t_q[kNearBatch];
+  __shared__ double2 t_d[kNearBatch];
+  const int32_t w = (int32_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x, nsl = i1.y;  // centers, slices per center
+  const int cl = lane / nsl;
+  const int sl = lane - cl * nsl;
+  const bool active = cl < n_ctr;
+  const int32_t c = ctr_first + (active ? cl : 0);
+  const double2 cc = cxy[c];
+  // x - c for the center's target (zero for a center without one: rho = 0, value unused)
+  double2 tz = make_double2(0.0, 0.0);
+  {
+    const int32_t g = c2t_start[c];
+    if (c2t_start[c + 1] > g) {
+      const double2 x = txy[c2t_slot[g] >> 1];
+      tz = make_double2(x.x - cc.x, x.y - cc.y);
+    }
+  }
+  const double tz2 = cnorm2(tz);
+  const double2 *lt = g_log_tab;
+  double logsum = 0.0, fsum = 0.0, dsum = 0.0;
+  const int32_t last = off + len - 1;
+  auto idx = [&](int32_t k) { return near_src[k < last ? k : last]; };
+  int32_t nx0 = idx(off + lane), nx1 = idx(off + lane + 64);
+  for (int32_t base = 0; base < len; base += kNearBatch) {
+    const int nb = min(kNearBatch, (int)(len - base));
+    const int32_t s0 = nx0, s1 = nx1;
+    __syncthreads();
+    if (lane < nb) {
+      t_xy[lane] = sxy[s0];
+      t_q[lane] = sq[s0];
+      t_d[lane] = sdip[s0];
+    }
+    if (lane + 64 < nb) {
+      t_xy[lane + 64] = sxy[s1];
+      t_q[lane + 64] = sq[s1];
+      t_d[lane + 64] = sdip[s1];
+    }
+    nx0 = idx(off + base + kNearBatch + lane);
+    nx1 = idx(off + base + kNearBatch + lane + 64);
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < nb; j += nsl) {
+        const double2 y = t_xy[j];
+        const double q = t_q[j];
+        const double dx = y.x - cc.x, dy = y.y - cc.y;
+        const double n2 = fma(dx, dx, dy * dy);
+        const double ir2 = rcp_nr(n2);
+        logsum = fma(q, log_tab(n2, lt), logsum);
+        // rho = (x - c) conj(z) / |z|^2
+        const double ux = fma(tz.x, dx, tz.y * dy) * ir2;
+        const double uy = fma(tz.y, dx, -(tz.x * dy)) * ir2;
+        const double r1 = 2.0 * ux, s = tz2 * ir2;
+        double b2 = 1.0 / PQ, b1 = fma(r1, b2, 1.0 / (PQ - 1));  // S: a_k = 1/k, a_0 = 0
+        double e2 = 1.0, e1 = 1.0 + r1;                           // D: a_k = 1
+#pragma unroll
+        for (int k = PQ - 2; k >= 1; --k) {
+          const double b0 = fma(r1, b1, fma(-s, b2, 1.0 / k));
+          const double e0 = fma(r1, e1, fma(-s, e2, 1.0));
+          b2 = b1;
+          b1 = b0;
+          e2 = e1;
+          e1 = e0;
+        }
+        fsum = fma(q, fma(b1, ux, -(s * b2)), fsum);
+        const double gx = fma(e1, ux, fma(-s, e2, 1.0)), gy = e1 * uy;
+        // Re(d conj(z) g) / |z|^2
+        const double hx = fma(dx, gx, dy * gy), hy = fma(dx, gy, -(dy * gx));
+        const double2 dr = t_d[j];
+        dsum = fma(ir2, fma(dr.x, hx, -(dr.y * hy)), dsum);
+      }
+    }
+  }
+  double vs = fma(0.5, logsum, -fsum);
+  for (int o = 1; o < nsl; o <<= 1) {
+    const bool take = (sl & (2 * o - 1)) == 0 && sl + o < nsl;
+    slice_add(vs, o, take);
+    slice_add(dsum, o, take);
+  }
+  if (active && sl == 0) {
+    double2 *row = anear + (int64_t)(row_first + cl) * rs;
+    row[0] = make_double2(vs, 0.0);
+    row[d_off] = make_double2(dsum, 0.0);
+  }
+}
+
 // Stages 3, 5a, 6a for S and D of many densities (GQ_S_AND_D, a batch of nd densities) on the
 // matrix cores. For a center c and a source y of strength q^(j) = w mu^(j) in density j, the
 // charge part adds q z^-m (m >= 1) and q log|z|^2, the dipole part q n z^-(m+1) (the dipole is
@@ -2161,7 +2273,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
     const E *__restrict__ L, int P1, const double *__restrict__ l2q_binom,
     const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
     const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_chunks,
-    const double2 *__restrict__ anear,
+    const int32_t *__restrict__ n_val_chunks, const double2 *__restrict__ anear,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
     int64_t tv_st, const double2 *__restrict__ tnrm) {
@@ -2259,13 +2371,20 @@ __global__ void __launch_bounds__(64) k_qbx_center(
     }
   }
 
-  // direct (P2QBXL) and List 3 far (M2QBXL) rows of this center, in chunk order
+  // direct (P2QBXL) and List 3 far (M2QBXL) rows of this center, in chunk order; with
+  // n_val_chunks the box's first n_val_chunks[b] (direct) rows hold the value at the center's
+  // target in the real part of their order-0 entry (k_near_sd_t)
   {
     const int32_t nbc = bctr1[b] - bctr0[b];
     const int32_t loc = c - bctr0[b];
     const int32_t nch = n_chunks[b];
+    const int32_t nval = n_val_chunks ? n_val_chunks[b] : 0;
     for (int32_t j = 0; j < nch; ++j) {
       const double2 *row = anear + (int64_t)(part_base[b] + j * nbc + loc) * rs;
+      if (j < nval) {
+        alpha[0].x += row[0].x;
+        continue;
+      }
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], row[m]);
     }
@@ -2466,6 +2585,12 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
                        ctx->params.p_qbx + 1, S.src, S.row);
 }
 
+// Whether the fused S and D direct pass of nd densities sums at the centers' targets
+// (k_near_sd_t): one density, every center serving at most one target.
+inline bool near_at_targets(const gq_ctx *ctx, int nd) {
+  return nd == 1 && ctx->one_target_per_center && ctx->d.n_near_chunks != nullptr;
+}
+
 // S and D of the same densities (nd of them): one fused pass for a single density, else the
 // per-kind launches (their density groups already share the pair geometry across densities).
 template <int PQ, typename E>
@@ -2474,6 +2599,12 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
   if (n <= 0) return;
+  if (near_at_targets(ctx, nd)) {
+    hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64), 0, s, n,
+                       d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
+                       d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1, S.row);
+    return;
+  }
   if (nd == 1) {
     hipLaunchKernelGGL((k_near_sd<PQ>), dim3(n, 1), dim3(64), 0, s, n, d.near_items + 2 * bk.near0,
                        d.near_src, d.cxy, d.cr, d.sxy, d.sq, d.sdip, d.anear,
@@ -2518,7 +2649,7 @@ void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
 
 template <int KIND, int PQ, typename E>
 void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
-                          const Strides &S, const E *L) {
+                          const Strides &S, const E *L, bool near_values) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.ctr1 - bk.ctr0);
   if (n > 0)
@@ -2526,7 +2657,8 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        sizeof(E) * kCenterStage * (ctx->params.p_fmm + 1), s, n,
                        d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
                        d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
-                       d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks, d.anear,
+                       d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
+                       near_values ? d.n_near_chunks : nullptr, d.anear,
                        d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv,
                        ctx->eval_sp ? ctx->tnrm_dev : nullptr);
 }
@@ -2676,10 +2808,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   if (e != hipSuccess) return e;
   {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
+    const bool near_values = SD && near_at_targets(ctx, nd);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf); break;
+  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf, near_values); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }

@@ -472,10 +472,11 @@ def test_ragged_batch_matches_separate_contexts():
 
 def test_s_and_d_concurrent_matches_separate(c1):
     """GQ_S_AND_D (S and D of the same densities through one expansion pipeline over two
-    workspace halves) against separate S and D evaluations: S rows exactly; D rows exactly for a
-    batch (per-kind direct interactions) and to rounding for one density (the fused direct pass
-    takes d z^-(m+1) from the shared powers of 1/z); the direct path exactly; a captured graph of
-    it replays to the eager rows."""
+    workspace halves) against separate S and D evaluations: S and D rows exactly for a batch
+    (per-kind direct interactions); for one density the fused direct pass sums the direct part
+    at each center's target (every center here serves one target) by the real-coefficient
+    recurrence, so both rows agree to rounding; the direct path exactly; a captured graph of it
+    replays to the eager rows."""
     from paper_1801_04070_amd import GQ_S_AND_D
     g = gi.random_stars(n_curves=3, panels_per_curve=128, seed=12, box=12.0)
     q, _ = _ctx(g, p_qbx=12, p_fmm=30)
@@ -486,8 +487,9 @@ def test_s_and_d_concurrent_matches_separate(c1):
     assert both.shape == (6, g.n_tgt)
     assert np.array_equal(both[:3], s_ref) and np.array_equal(both[3:], d_ref)
     one = q.eval(GQ_S_AND_D, dens[0]).cpu().numpy()
-    assert np.array_equal(one[0], s_ref[0])
-    assert _rel(one[1], d_ref[0]) < 1e-14
+    es, ed = _rel(one[0], s_ref[0]), _rel(one[1], d_ref[0])
+    print(f"one density S and D against GQ_S / GQ_D: S {es:.2e} D {ed:.2e}")
+    assert es < 1e-13 and ed < 1e-13
     ref = oracle.qbx_eval(g, 2, dens[0].cpu().numpy(), None, p_qbx=12)
     assert _rel(one[1], ref) < 1e-10
     # direct path too
