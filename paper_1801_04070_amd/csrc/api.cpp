@@ -164,7 +164,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   for (void *p : ctx->nw_allocations) (void)hipFree(p);
   ctx->nw_allocations.clear();
   ctx->generation++;
-  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), nnear(nb, 0), items, fitems, clist;
+  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), nnear(nb, 0), items, fitems, clist, vitems;
   std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
   std::vector<double> qgeo;
@@ -247,6 +247,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     bk.pq = pq;
     bk.near0 = (int64_t)items.size() / 8;
     bk.nmf0 = (int64_t)mitems.size() / 8;
+    bk.nvf0 = (int64_t)vitems.size() / 8;
     bk.far0 = (int64_t)fitems.size() / 8;
     bk.m2q0 = (int64_t)qwave.size() / 8;
     bk.ctr0 = (int64_t)clist.size();
@@ -276,6 +277,12 @@ gq_status build_near_work(gq_ctx *ctx) {
                                  (int32_t)(base[b] + j * nc + gl + cb),
                                  (int32_t)std::min<int64_t>(4, ng - cb), 0, 0, 0};
           mitems.insert(mitems.end(), it, it + 8);
+        }
+        for (int64_t cb = 0; cb < ng; cb += 16) {
+          const int32_t it[8] = {(int32_t)(box_src_off[b] + c0), (int32_t)clen, (int32_t)(g0 + cb),
+                                 (int32_t)(base[b] + j * nc + gl + cb),
+                                 (int32_t)std::min<int64_t>(16, ng - cb), 0, 0, 0};
+          vitems.insert(vitems.end(), it, it + 8);
         }
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
@@ -316,6 +323,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     }
     bk.near1 = (int64_t)items.size() / 8;
     bk.nmf1 = (int64_t)mitems.size() / 8;
+    bk.nvf1 = (int64_t)vitems.size() / 8;
     close_wave();
     bk.far1 = (int64_t)fitems.size() / 8;
     bk.m2q1 = (int64_t)qwave.size() / 8;
@@ -351,6 +359,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.near_src, src.data(), src.size());
   if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.near_mitems, mitems.data(), mitems.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.near_vitems, vitems.data(), vitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_wave, qwave.data(), qwave.size() / 4);
   std::vector<int32_t> qslot(qpair.size() / 4);

@@ -67,6 +67,7 @@ struct DevBuffers {
   int32_t *near_src = nullptr;       // per box owning centers: its direct sources (tree order)
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
   int4 *near_mitems = nullptr;       // 2 x int4 per item: a chunk and up to 4 of its box's centers
+  int4 *near_vitems = nullptr;       // the same with up to 16 centers (values at the targets)
                                      // (the matrix-core direct pass of S and D batches)
   int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
   // Stage 5b packed across boxes (far_pairs_per_lane 1): per wavefront 2 x int4 (first pair,
@@ -106,6 +107,7 @@ struct OrderBucket {
   int64_t near0 = 0, near1 = 0, far0 = 0, far1 = 0, ctr0 = 0, ctr1 = 0;
   int64_t m2q0 = 0, m2q1 = 0;        // packed Stage 5b wavefronts
   int64_t nmf0 = 0, nmf1 = 0;        // matrix-core direct items
+  int64_t nvf0 = 0, nvf1 = 0;        // matrix-core direct items summed at the targets
 };
 
 }  // namespace gq

@@ -2006,6 +2006,176 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
   }
 }
 
+// S and D of a batch of densities at the centers' own targets (every center serving at most one
+// target) on the matrix cores. At a center's target x the direct part of its expansion is, for
+// density j, sum_y q_y^(j) A(c, y) (S) and sum_y q_y^(j) B(c, y) (D), the dipole being the charge
+// times the normal: with z = y - c and rho = (x - c)/z,
+//   A = log|z| - Re sum_{k=1..p} rho^k / k,   B = Re(n conj(z) sum_{k=0..p} rho^k) / |z|^2,
+// pair weights that do not depend on the density (the polynomials by the recurrence of
+// k_near_sd_t). Over a chunk of a box's sources this is one real GEMM per block of 16 centers:
+// rows the centers, k the sources, columns the densities, S and D two accumulators. A work-group
+// of four wavefronts takes one (chunk, block of up to 16 centers) item and 16 NT densities; the
+// chunk is staged 64 sources at a time (positions, normals and the strengths of the densities,
+// the next batch's loads in flight during the current one), each wavefront takes 16 of them
+// (four k-steps, lane (row i, k kk) forming the weights of one pair), and the four partial
+// products are summed through LDS at the end. Values go to the order-0 entry of the (center,
+// chunk) rows as in k_near_sd_t: S of density j in slot j, D in slot d_slot + j.
+template <int PQ, int NT>
+__global__ void __launch_bounds__(256, 2) k_near_val_mfma(
+    const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
+    const double2 *__restrict__ cxy, const double2 *__restrict__ sxy,
+    const double2 *__restrict__ snrm, const double *__restrict__ sq,
+    const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
+    const double2 *__restrict__ txy, double2 *__restrict__ anear, int rs, int64_t src_st,
+    int64_t row_st, int nd, int64_t d_slot) {
+  static_assert(PQ >= 2, "the recurrences start at b_p and b_(p-1)");
+  constexpr int NDB = 16 * NT;  // densities per work-group
+  constexpr int SB = 64;        // sources staged per batch, 16 per wavefront
+  constexpr int QST = NDB + 1;  // strengths: source-major rows of the batch's densities (padded)
+  constexpr int NQ = NDB / 4;   // strengths staged per thread and batch
+  constexpr int RED = 3 * 64 * 4 * NT;  // one accumulator set of waves 1..3 (doubles)
+  static_assert(RED <= SB * QST, "the wave reduction reuses the strength buffer");
+  __shared__ double t_q[SB * QST];
+  __shared__ double2 t_y[SB], t_n[SB];
+  __shared__ double2 t_log[kLogTab];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int4 i0 = items[2 * blockIdx.x], i1 = items[2 * blockIdx.x + 1];
+  const int32_t off = i0.x, len = i0.y, ctr_first = i0.z, row_first = i0.w;
+  const int n_ctr = i1.x;
+  const int d0 = blockIdx.y * NDB;
+  if (tid < kLogTab) t_log[tid] = g_log_tab[tid];
+  const int i = lane & 15, kk = lane >> 4;
+  // the A-operand row of this lane: center i of the block and the offset of its target
+  const bool row_on = i < n_ctr;
+  const int32_t c = ctr_first + (row_on ? i : 0);
+  const double2 cc = cxy[c];
+  double2 tz = make_double2(0.0, 0.0);
+  {
+    const int32_t g = c2t_start[c];
+    if (c2t_start[c + 1] > g) {
+      const double2 x = txy[c2t_slot[g] >> 1];
+      tz = make_double2(x.x - cc.x, x.y - cc.y);
+    }
+  }
+  const double tz2 = cnorm2(tz);
+  // staging: thread (source tid % SB, densities tid / SB + 4 q) of a batch
+  const int ss = tid % SB, sd = tid / SB;
+  double rq[NQ];
+  double2 ry = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+  auto index = [&](int32_t base) {
+    const int nb = min(SB, (int)(len - base));
+    return near_src[off + base + (ss < nb ? ss : 0)];
+  };
+  auto load = [&](int32_t src) {
+    if (sd == 0) {
+      ry = sxy[src];
+      rn = snrm[src];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int dj = d0 + sd + 4 * q;
+      rq[q] = sq[(int64_t)(dj < nd ? dj : 0) * src_st + src];
+    }
+  };
+  gq_d4 CS[NT], CD[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    CS[nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+    CD[nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+  }
+  load(index(0));
+  int32_t snx = SB < len ? index(SB) : 0;
+  for (int32_t base = 0; base < len; base += SB) {
+    const int nb = min(SB, (int)(len - base));
+    __syncthreads();  // the previous batch is no longer read
+    if (sd == 0) {
+      t_y[ss] = ry;
+      t_n[ss] = rn;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      t_q[ss * QST + sd + 4 * q] = (ss < nb && d0 + sd + 4 * q < nd) ? rq[q] : 0.0;
+    __syncthreads();
+    if (base + SB < len) {  // in flight during this batch
+      load(snx);
+      if (base + 2 * SB < len) snx = index(base + 2 * SB);
+    }
+#pragma unroll 1
+    for (int ks = 0; ks < 4; ++ks) {
+      const int sl = 16 * wv + 4 * ks + kk;
+      if (16 * wv + 4 * ks >= nb) break;  // uniform over the wavefront
+      const double2 y = t_y[sl], nv = t_n[sl];
+      const double dx = y.x - cc.x, dy = y.y - cc.y;
+      const bool on = row_on && sl < nb;
+      const double n2 = on ? fma(dx, dx, dy * dy) : 1.0;
+      const double ir2 = rcp_nr(n2);
+      const double lg = log_tab(n2, t_log);
+      const double ux = fma(tz.x, dx, tz.y * dy) * ir2;
+      const double uy = fma(tz.y, dx, -(tz.x * dy)) * ir2;
+      const double r1 = 2.0 * ux, s = tz2 * ir2;
+      double b2 = 1.0 / PQ, b1 = fma(r1, b2, 1.0 / (PQ - 1));
+      double e2 = 1.0, e1 = 1.0 + r1;
+#pragma unroll
+      for (int k = PQ - 2; k >= 1; --k) {
+        const double b0 = fma(r1, b1, fma(-s, b2, 1.0 / k));
+        const double e0 = fma(r1, e1, fma(-s, e2, 1.0));
+        b2 = b1;
+        b1 = b0;
+        e2 = e1;
+        e1 = e0;
+      }
+      const double gx = fma(e1, ux, fma(-s, e2, 1.0)), gy = e1 * uy;
+      const double hx = fma(dx, gx, dy * gy), hy = fma(dx, gy, -(dy * gx));
+      const double aS = on ? fma(0.5, lg, -fma(b1, ux, -(s * b2))) : 0.0;
+      const double aD = on ? ir2 * fma(nv.x, hx, -(nv.y * hy)) : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const double b = t_q[sl * QST + 16 * nt + i];  // B[kk][j]: column j = lane & 15 = i
+        CS[nt] = mfma16(aS, b, CS[nt]);
+        CD[nt] = mfma16(aD, b, CD[nt]);
+      }
+    }
+  }
+  // sum the four wavefronts' products (S, then D) in wavefront 0 through the strength buffer
+  double *red = t_q;
+  auto reduce = [&](gq_d4 (&C)[NT]) {
+    __syncthreads();
+    if (wv > 0) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(((wv - 1) * NT + nt) * 4 + v) * 64 + lane] = C[nt][v];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) C[nt][v] += red[((w * NT + nt) * 4 + v) * 64 + lane];
+    }
+  };
+  reduce(CS);
+  reduce(CD);
+  if (wv != 0) return;
+  // lane (column j = lane & 15, group g = lane >> 4) holds rows (centers) g + 4 v
+  const int g = kk, j = i;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int dj = d0 + 16 * nt + j;
+    if (dj >= nd) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ci = g + 4 * v;
+      if (ci >= n_ctr) continue;
+      const int64_t row = (int64_t)(row_first + ci) * rs;
+      anear[(int64_t)dj * row_st + row] = make_double2(CS[nt][v], 0.0);
+      anear[(d_slot + dj) * row_st + row] = make_double2(CD[nt][v], 0.0);
+    }
+  }
+}
+
 // k_near for a block of DG densities per work-group (grid.y = density blocks): same items and
 // lanes, the sources' charges and dipoles of the DG densities staged together, one pair geometry
 // for all of them. Densities past n_dens (a last partial block) get zero strengths and no rows.
@@ -2585,10 +2755,21 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
                        ctx->params.p_qbx + 1, S.src, S.row);
 }
 
-// Whether the fused S and D direct pass of nd densities sums at the centers' targets
-// (k_near_sd_t): one density, every center serving at most one target.
+// Whether the S and D direct pass of nd densities sums at the centers' targets (k_near_sd_t for
+// one density, k_near_val_mfma for a batch): every center serves at most one target.
 inline bool near_at_targets(const gq_ctx *ctx, int nd) {
-  return nd == 1 && ctx->one_target_per_center && ctx->d.n_near_chunks != nullptr;
+  return nd >= 1 && ctx->one_target_per_center && ctx->d.n_near_chunks != nullptr;
+}
+
+template <int PQ, int NT>
+void launch_near_val_mfma(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
+                          const Strides &S) {
+  auto &d = ctx->d;
+  const int32_t nv = (int32_t)(bk.nvf1 - bk.nvf0);
+  hipLaunchKernelGGL((k_near_val_mfma<PQ, NT>), dim3((uint32_t)nv, (nd + 16 * NT - 1) / (16 * NT)),
+                     dim3(256), 0, s, d.near_vitems + 2 * bk.nvf0, d.near_src, d.cxy, d.sxy,
+                     d.snrm, d.sq, d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1,
+                     S.src, S.row, nd, (int64_t)nd);
 }
 
 // S and D of the same densities (nd of them): one fused pass for a single density, else the
@@ -2600,9 +2781,16 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
   if (n <= 0) return;
   if (near_at_targets(ctx, nd)) {
-    hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64), 0, s, n,
-                       d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
-                       d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1, S.row);
+    if (nd == 1)
+      hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64), 0, s, n,
+                         d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
+                         d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1, S.row);
+    else if (bk.nvf1 > bk.nvf0 && nd <= 16)
+      launch_near_val_mfma<PQ, 1>(ctx, bk, nd, s, S);
+    else if (bk.nvf1 > bk.nvf0 && nd <= 32)
+      launch_near_val_mfma<PQ, 2>(ctx, bk, nd, s, S);
+    else if (bk.nvf1 > bk.nvf0)
+      launch_near_val_mfma<PQ, 4>(ctx, bk, nd, s, S);
     return;
   }
   if (nd == 1) {
