@@ -164,7 +164,8 @@ gq_status build_near_work(gq_ctx *ctx) {
   for (void *p : ctx->nw_allocations) (void)hipFree(p);
   ctx->nw_allocations.clear();
   ctx->generation++;
-  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), nnear(nb, 0), items, fitems, clist, vitems;
+  std::vector<int32_t> src, bctr0(nb), bctr1(nb), base(nb, 0), nch(nb, 0), nnear(nb, 0), items, fitems, clist, vitems,
+      citems;
   std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
   std::vector<double> qgeo;
@@ -248,6 +249,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     bk.near0 = (int64_t)items.size() / 8;
     bk.nmf0 = (int64_t)mitems.size() / 8;
     bk.nvf0 = (int64_t)vitems.size() / 8;
+    bk.cv0 = (int64_t)citems.size() / 8;
     bk.far0 = (int64_t)fitems.size() / 8;
     bk.m2q0 = (int64_t)qwave.size() / 8;
     bk.ctr0 = (int64_t)clist.size();
@@ -286,6 +288,11 @@ gq_status build_near_work(gq_ctx *ctx) {
         }
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
+      for (int64_t cb = 0; cb < ng; cb += 16) {
+        const int32_t it[8] = {(int32_t)b, (int32_t)(g0 + cb), (int32_t)std::min<int64_t>(16, ng - cb),
+                               (int32_t)woff, (int32_t)wlen, 0, 0, 0};
+        citems.insert(citems.end(), it, it + 8);
+      }
       for (int64_t j = 0; j * far_chunk < wlen; ++j) {
         const int64_t c0 = j * far_chunk, clen = std::min<int64_t>(far_chunk, wlen - c0);
         if (!packed) {
@@ -324,6 +331,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     bk.near1 = (int64_t)items.size() / 8;
     bk.nmf1 = (int64_t)mitems.size() / 8;
     bk.nvf1 = (int64_t)vitems.size() / 8;
+    bk.cv1 = (int64_t)citems.size() / 8;
     close_wave();
     bk.far1 = (int64_t)fitems.size() / 8;
     bk.m2q1 = (int64_t)qwave.size() / 8;
@@ -360,6 +368,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.near_items, items.data(), items.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.near_mitems, mitems.data(), mitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.near_vitems, vitems.data(), vitems.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.cval_items, citems.data(), citems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.far_items, fitems.data(), fitems.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_wave, qwave.data(), qwave.size() / 4);
   std::vector<int32_t> qslot(qpair.size() / 4);
@@ -708,6 +717,10 @@ gq_status upload_all(gq_ctx *ctx) {
     for (int k = 0; k < P1; ++k)
       for (int m = 0; m <= PQ; ++m) l2q[(size_t)k * (PQ + 1) + m] = C(k, m);
     GQ_TRY(upload(ctx, d.l2q_binom, l2q.data(), l2q.size()));
+    std::vector<double> m2q((size_t)P1 * (PQ + 1), 0.0);
+    for (int k = 1; k < P1; ++k)
+      for (int m = 0; m <= PQ; ++m) m2q[(size_t)k * (PQ + 1) + m] = C(k + m - 1, m);
+    GQ_TRY(upload(ctx, d.m2q_binom, m2q.data(), m2q.size()));
     std::vector<double> bt((size_t)P1 * P1);
     for (int k = 0; k < P1; ++k)
       for (int m = 0; m < P1; ++m) bt[(size_t)k * P1 + m] = C(k, m);

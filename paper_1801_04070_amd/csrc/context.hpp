@@ -68,6 +68,7 @@ struct DevBuffers {
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
   int4 *near_mitems = nullptr;       // 2 x int4 per item: a chunk and up to 4 of its box's centers
   int4 *near_vitems = nullptr;       // the same with up to 16 centers (values at the targets)
+  int4 *cval_items = nullptr;        // 2 x int4: (box, first center, n <= 16, List 3 far start), (n far)
                                      // (the matrix-core direct pass of S and D batches)
   int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
   // Stage 5b packed across boxes (far_pairs_per_lane 1): per wavefront 2 x int4 (first pair,
@@ -92,6 +93,7 @@ struct DevBuffers {
   float *m2l_bt_f = nullptr;
   float2 *opow_f = nullptr;
   double *l2q_binom = nullptr;       // [P1][PQB + 1]  C(k, m)
+  double *m2q_binom = nullptr;       // [P1][PQB + 1]  C(k + m - 1, m)
   // workspace
   double *sq = nullptr;              // per-source charge  w * sigma
   double2 *sdip = nullptr;           // per-source dipole  w * tau * n
@@ -108,6 +110,7 @@ struct OrderBucket {
   int64_t m2q0 = 0, m2q1 = 0;        // packed Stage 5b wavefronts
   int64_t nmf0 = 0, nmf1 = 0;        // matrix-core direct items
   int64_t nvf0 = 0, nvf1 = 0;        // matrix-core direct items summed at the targets
+  int64_t cv0 = 0, cv1 = 0;          // center-stage items summed at the targets (k_ctr_val)
 };
 
 }  // namespace gq

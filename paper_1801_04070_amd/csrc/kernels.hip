@@ -2562,6 +2562,230 @@ __global__ void __launch_bounds__(64) k_qbx_center(
   eval_targets<PQ>(c, cc, r, alpha, c2t_start, c2t_slot, txy, tv, tnrm);
 }
 
+// Stage 8 and the List 3 far part of Stage 5 summed at the centers' targets, for centers that
+// serve at most one target (with the direct values of k_near_sd_t / k_near_val_mfma). For a
+// center c of box b with target x, zeta = x - c, the box parts of its QBX expansion at x are:
+//   L2QBXL: Re sum_k b_k U_k, U_k = sum_{m <= min(k, p)} C(k, m) t^(k-m) w^m, t = (c - c_b)/s_b,
+//     w = zeta/s_b: the box local (a series in (x - c_b)/s_b) shifted to c and truncated at the
+//     QBX order p, by U_0 = 1, U_k = (t + w) U_(k-1) - [k > p] C(k-1, p) t^(k-1-p) w^(p+1);
+//   M2QBXL from a List 3 far box d: a_0 (log|y| - Re sum_{m=1..p} rho^m / m)
+//     + Re sum_{k>=1} M_k (s_d/y)^k P_k(rho), y = c - c_d, rho = -zeta/y,
+//     P_k(rho) = sum_{m<=p} C(k+m-1, m) rho^m: the multipole's Taylor series about c truncated
+//     at p, evaluated at x.
+// These are the coefficient forms of k_qbx_center and k_m2qbxl evaluated at x, summed in another
+// order. The weights U_k, W_k do not depend on the density: one wavefront per (box, block of up
+// to 16 centers) forms them for one segment at a time (the box local, then each List 3 far box)
+// in LDS and contracts them with the segment's expansion over the slots on the matrix cores: rows
+// the centers, k the real and imaginary parts of the coefficients (Re(b U) = b.x U.x - b.y U.y),
+// columns 16 NT slots. Then the center's direct rows are added and its target written.
+template <int PQ, int NT, typename E>
+__global__ void __launch_bounds__(64) k_ctr_val(
+    const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
+    const double2 *__restrict__ cxy, const double2 *__restrict__ bc,
+    const int32_t *__restrict__ blevel, const double *__restrict__ level_side,
+    const E *__restrict__ M, const E *__restrict__ L, int P1,
+    const double *__restrict__ m2q_binom, int ls,
+    const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
+    const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_near_chunks,
+    const double2 *__restrict__ anear, int rs, const int32_t *__restrict__ c2t_start,
+    const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
+    double *__restrict__ tv, int64_t box_st, int64_t row_st, int64_t tv_st, int nslots) {
+  HIP_DYNAMIC_SHARED(unsigned char, cv_lds)
+  // k order of a segment: coefficient k = 4 j + r sits at entry 8 j + r (real part, k-step 2 j,
+  // B row r) and 8 j + 4 + r (imaginary part, k-step 2 j + 1), so that lane r of a B column loads
+  // coefficient 4 j + r whole and uses its two parts in consecutive k-steps
+  const int nks = 2 * ((P1 + 3) >> 2);  // k-steps of one segment
+  const int ke = 4 * nks;               // real entries of a segment (zero-padded)
+  constexpr int RS = 17;              // LDS row stride of the weights, [entry][center]
+  double *As = reinterpret_cast<double *>(cv_lds);  // [ke][RS]
+  double *Cb = As + ke * RS;                         // [P1][PQ + 1] C(k+m-1, m)
+  constexpr int kFarStage = 64;                      // List 3 far boxes staged per item
+  __shared__ double4 fgeo[kFarStage];                // center, side of each far box
+  __shared__ int32_t fidx[kFarStage];
+  const int lane = threadIdx.x;
+  const int4 i0 = items[2 * blockIdx.x], i1 = items[2 * blockIdx.x + 1];
+  const int32_t b = i0.x, cfirst = i0.y, n_ctr = i0.z, far0 = i0.w, nfar = i1.x;
+  const int d0 = blockIdx.y * 16 * NT;
+  for (int e = lane; e < ke * RS; e += 64) As[e] = 0.0;
+  for (int e = lane; e < P1 * (PQ + 1); e += 64) Cb[e] = m2q_binom[(e / (PQ + 1)) * ls + e % (PQ + 1)];
+  if (lane < nfar && lane < kFarStage) {
+    const int32_t d = wf_idx[far0 + lane];
+    fidx[lane] = d;
+    fgeo[lane] = make_double4(bc[d].x, bc[d].y, level_side[blevel[d]], 0.0);
+  }
+  // the geometry of far box f (staged for the first kFarStage)
+  auto far_box = [&](int f, int32_t &d, double2 &cd, double &sd) {
+    if (f < kFarStage) {
+      d = fidx[f];
+      const double4 g4 = fgeo[f];
+      cd = make_double2(g4.x, g4.y);
+      sd = g4.z;
+    } else {
+      d = wf_idx[far0 + f];
+      cd = bc[d];
+      sd = level_side[blevel[d]];
+    }
+  };
+  const int i = lane & 15, q = lane >> 4;
+  // the weight rows: center i of the block and the offset of its target
+  const bool row_on = i < n_ctr;
+  const int32_t c = cfirst + (row_on ? i : 0);
+  const double2 cc = cxy[c];
+  double2 tz = make_double2(0.0, 0.0);
+  {
+    const int32_t g = c2t_start[c];
+    if (c2t_start[c + 1] > g) {
+      const double2 x = txy[c2t_slot[g] >> 1];
+      tz = make_double2(x.x - cc.x, x.y - cc.y);
+    }
+  }
+  gq_d4 C[NT];
+  // this lane's B-operand columns: offsets of its slots (-1: past the last slot)
+  int64_t so[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    C[nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+    const int sl = d0 + 16 * nt + i;
+    so[nt] = sl < nslots ? (int64_t)sl * box_st : -1;
+  }
+  auto ent = [](int k) { return 8 * (k >> 2) + (k & 3); };  // entry of the real part
+  const int kq = (P1 + 3) >> 2;  // coefficients per lane group q in a far segment
+  // B operands in groups of 2 GH k-steps (GH coefficients per column and lane, 16 values in
+  // flight), the next group (or the next segment's first) loaded while the current one is on
+  // the matrix cores
+  constexpr int GH = 8 / NT;
+  const int ngr = (nks / 2 + GH - 1) / GH;
+  double2 bcur[GH][NT], bnext[GH][NT];
+  auto seg_ptr = [&](int32_t bx, bool local) { return (local ? L : M) + (int64_t)bx * P1; };
+  auto load_group = [&](const E *X, int gi, double2 (&bv)[GH][NT]) {
+#pragma unroll
+    for (int jj = 0; jj < GH; ++jj) {
+      const int k = 4 * (gi * GH + jj) + q;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        bv[jj][nt] = (k < P1 && so[nt] >= 0) ? to_d2(X[so[nt] + k]) : make_double2(0.0, 0.0);
+    }
+  };
+  const E *X = seg_ptr(b, true);
+  load_group(X, 0, bcur);
+  __syncthreads();  // the staged far boxes
+  for (int sg = 0; sg <= nfar; ++sg) {
+    __syncthreads();  // the previous segment's weights are no longer read
+    if (sg == 0) {
+      if (q == 0) {
+        const double is = 1.0 / level_side[blevel[b]];
+        const double2 t = make_double2((cc.x - bc[b].x) * is, (cc.y - bc[b].y) * is);
+        const double2 w = make_double2(tz.x * is, tz.y * is);
+        const double2 tw = cadd(t, w);
+        double2 u = make_double2(1.0, 0.0);
+        double2 tp = make_double2(1.0, 0.0);    // t^(k-1-p)
+        double cb = 1.0;                        // C(k-1, p), exact integers
+        const double2 wp1 = cpowi(w, PQ + 1);
+        for (int k = 0; k < P1; ++k) {
+          if (k > 0) {
+            u = cmul(tw, u);
+            if (k > PQ) {
+              if (k > PQ + 1) cb = cb * (double)(k - 1) / (double)(k - 1 - PQ);
+              u = csub(u, cscale(cmul(tp, wp1), cb));
+              tp = cmul(tp, t);
+            }
+          }
+          As[ent(k) * RS + i] = row_on ? u.x : 0.0;
+          As[(ent(k) + 4) * RS + i] = row_on ? -u.y : 0.0;
+        }
+      }
+    } else {
+      int32_t box;
+      double2 cd;
+      double sd;
+      far_box(sg - 1, box, cd, sd);
+      const double2 y = make_double2(cc.x - cd.x, cc.y - cd.y);
+      const double2 iy = cinv(y);
+      const double2 w = cscale(iy, sd);
+      const double2 rho = make_double2(-(tz.x * iy.x - tz.y * iy.y), -(tz.x * iy.y + tz.y * iy.x));
+      const int k0 = q * kq, k1 = min(P1, k0 + kq);
+      if (q == 0) {
+        // a_0 weight: log|y| - Re sum_{m=1..p} rho^m / m
+        const double r1 = 2.0 * rho.x, s2 = cnorm2(rho);
+        double b2 = 1.0 / PQ, b1 = fma(r1, b2, 1.0 / (PQ - 1));
+#pragma unroll
+        for (int m = PQ - 2; m >= 1; --m) {
+          const double b0 = fma(r1, b1, fma(-s2, b2, 1.0 / m));
+          b2 = b1;
+          b1 = b0;
+        }
+        const double a0w = 0.5 * log_tab(cnorm2(y), g_log_tab) - fma(b1, rho.x, -(s2 * b2));
+        As[ent(0) * RS + i] = row_on ? a0w : 0.0;
+        As[(ent(0) + 4) * RS + i] = 0.0;
+      }
+      double2 wk = cpowi(w, k0 > 1 ? k0 : 1);
+      for (int k = k0 > 1 ? k0 : 1; k < k1; ++k) {
+        const double *ck = Cb + k * (PQ + 1);
+        double2 h = make_double2(ck[PQ], 0.0);
+#pragma unroll
+        for (int m = PQ - 1; m >= 0; --m)
+          h = make_double2(fma(h.x, rho.x, fma(-h.y, rho.y, ck[m])), fma(h.x, rho.y, h.y * rho.x));
+        const double2 wv = cmul(wk, h);
+        As[ent(k) * RS + i] = row_on ? wv.x : 0.0;
+        As[(ent(k) + 4) * RS + i] = row_on ? -wv.y : 0.0;
+        wk = cmul(wk, w);
+      }
+    }
+    __syncthreads();
+    for (int gi = 0; gi < ngr; ++gi) {
+      if (gi + 1 < ngr) {
+        load_group(X, gi + 1, bnext);
+      } else if (sg < nfar) {
+        int32_t nb2;
+        double2 cd2;
+        double sd2;
+        far_box(sg, nb2, cd2, sd2);
+        X = seg_ptr(nb2, false);
+        load_group(X, 0, bnext);
+      }
+#pragma unroll
+      for (int jj = 0; jj < GH; ++jj) {
+        const int ks = 2 * (gi * GH + jj);
+        if (ks < nks) {
+          const double are = As[(4 * ks + q) * RS + i];  // A row i, entries 4 ks + q, + 4
+          const double aim = As[(4 * ks + 4 + q) * RS + i];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(are, bcur[jj][nt].x, C[nt]);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(aim, bcur[jj][nt].y, C[nt]);
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < GH; ++jj)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bcur[jj][nt] = bnext[jj][nt];
+    }
+  }
+  // lane (column j = lane & 15, group g = lane >> 4) holds rows (centers) g + 4 v
+  const int g = q, j = i;
+  const int32_t nbc = bctr1[b] - bctr0[b];
+  const int32_t nnear = n_near_chunks[b];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int ci = g + 4 * v;
+    if (ci >= n_ctr) continue;
+    const int32_t cv = cfirst + ci;
+    const int32_t t0 = c2t_start[cv];
+    if (c2t_start[cv + 1] <= t0) continue;
+    const int32_t tslot = c2t_slot[t0];
+    const int64_t row0 = (int64_t)part_base[b] + (cv - bctr0[b]);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int sl = d0 + 16 * nt + j;
+      if (sl >= nslots) continue;
+      double val = C[nt][v];
+      for (int32_t ch = 0; ch < nnear; ++ch)
+        val += anear[(int64_t)sl * row_st + (row0 + (int64_t)ch * nbc) * rs].x;
+      tv[(int64_t)sl * tv_st + tslot] = -kInv2Pi * val;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Direct (unaccelerated) QBX: every center of one order bucket (clist, n) takes every source,
 // staged through LDS tiles.
@@ -2851,6 +3075,38 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        ctx->eval_sp ? ctx->tnrm_dev : nullptr);
 }
 
+// The center stage summed at the targets (k_ctr_val), which also takes the List 3 far
+// multipoles: with the direct values of a S and D evaluation of kNearMfmaMin or more densities
+// (the weights are formed once for all slots; for fewer slots the coefficient kernels are faster).
+inline bool center_at_targets(const gq_ctx *ctx, int nd, bool sd) {
+  return sd && nd >= kNearMfmaMin && near_at_targets(ctx, nd) && ctx->d.cval_items != nullptr;
+}
+
+template <int PQ, int NT, typename E>
+void launch_ctr_val(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStream_t s, const Strides &S,
+                    const E *M, const E *L) {
+  auto &d = ctx->d;
+  const int32_t n = (int32_t)(bk.cv1 - bk.cv0);
+  if (n <= 0) return;
+  const int P1 = ctx->params.p_fmm + 1;
+  const int ke = 4 * ((2 * P1 + 3) / 4);
+  const size_t lds = sizeof(double) * ((size_t)ke * 17 + (size_t)P1 * (PQ + 1));
+  hipLaunchKernelGGL((k_ctr_val<PQ, NT, E>), dim3((uint32_t)n, (slots + 16 * NT - 1) / (16 * NT)),
+                     dim3(64), lds, s, d.cval_items + 2 * bk.cv0, d.wf_idx, d.cxy, d.bc, d.blevel,
+                     d.level_side, M, L, P1, d.m2q_binom, ctx->params.p_qbx + 1,
+                     d.bctr0, d.bctr1, d.part_base, d.n_near_chunks, d.anear, ctx->params.p_qbx + 1,
+                     d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv, slots);
+}
+
+template <int PQ, typename E>
+void launch_ctr_val_bucket(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStream_t s,
+                           const Strides &S, const E *M, const E *L) {
+  if (slots <= 16) launch_ctr_val<PQ, 1, E>(ctx, bk, slots, s, S, M, L);
+  else if (slots <= 32) launch_ctr_val<PQ, 2, E>(ctx, bk, slots, s, S, M, L);
+  else if (slots <= 64) launch_ctr_val<PQ, 4, E>(ctx, bk, slots, s, S, M, L);
+  else launch_ctr_val<PQ, 8, E>(ctx, bk, slots, s, S, M, L);
+}
+
 template <int KIND, typename E>
 hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   // KIND 4: S and D of nd densities; the charge and dipole strengths of density j sit in source
@@ -2919,7 +3175,8 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   // List 3 far multipoles -> centers on the side stream, once the upward pass is complete
   e = hipStreamWaitEvent(side, ctx->ev_up, 0);
   if (e != hipSuccess) return e;
-  if (ctx->n_far_items > 0 || ctx->n_m2q_waves > 0) {
+  const bool ctr_vals = center_at_targets(ctx, nd, SD);
+  if ((ctx->n_far_items > 0 || ctx->n_m2q_waves > 0) && !ctr_vals) {
     StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
@@ -2994,7 +3251,17 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   e = hipStreamWaitEvent(st, ctx->ev_join, 0);
   if (e != hipSuccess) return e;
-  {
+  if (ctr_vals) {
+    StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
+    for (const OrderBucket &bk : ctx->buckets) {
+      switch (bk.pq) {
+#define GQ_CASE(P) \
+  case P: launch_ctr_val_bucket<P, E>(ctx, bk, slots, st, S, M, Lf); break;
+        GQ_PQ_LIST(GQ_CASE)
+#undef GQ_CASE
+      }
+    }
+  } else {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
     const bool near_values = SD && near_at_targets(ctx, nd);
     for (const OrderBucket &bk : ctx->buckets) {

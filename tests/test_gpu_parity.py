@@ -631,13 +631,14 @@ def test_off_surface_targets_by_association(kind):
     assert e_q < 1e-10 and e_p < 1e-10
 
 
-@pytest.mark.parametrize("nd", [1, 20])
-def test_s_and_d_values_and_coefficient_paths(nd):
+@pytest.mark.parametrize("nd,orders", [(1, False), (20, False), (20, True)])
+def test_s_and_d_values_and_coefficient_paths(nd, orders):
     """GQ_S_AND_D sums the direct part at the targets only when every center serves at most one
-    target. The on-surface geometry (one target per center, value path) and the same geometry
-    with off-surface targets added to its centers (several targets per center: the coefficient
-    rows of the fused pass, or of the matrix-core pass for the batch) agree with GQ_S and GQ_D at
-    their common targets to rounding, and the latter with the oracle within the gate."""
+    target, and for a batch of 8 or more densities also the box parts (L2QBXL, M2QBXL). The
+    on-surface geometry (one target per center, value path) and the same geometry with
+    off-surface targets added to its centers (several targets per center: the coefficient rows)
+    agree with GQ_S and GQ_D at their common targets to rounding, and the latter with the oracle
+    within the gate; also with per-center QBX orders (one pass per order group)."""
     from paper_1801_04070_amd import GQ_S_AND_D
     g = gi.random_stars(n_curves=3, panels_per_curve=64, seed=14, box=12.0)
     rng = np.random.default_rng(77)
@@ -650,8 +651,11 @@ def test_s_and_d_values_and_coefficient_paths(nd):
     dens = np.stack([gi.fourier_density(g, seed=300 + j) for j in range(nd)])
     dd = _dev(dens if nd > 1 else dens[0])
     rows = {}
+    po = np.random.default_rng(5).choice([4, 6, 8, 12], size=g.n_ctr).astype(np.int32)
     for name, geom in (("values", g), ("coefficients", e)):
         q, _ = _ctx(geom, p_qbx=12, p_fmm=30)
+        if orders:
+            q.set_qbx_orders(po)
         both = q.eval(GQ_S_AND_D, dd).cpu().numpy().reshape(2, nd, -1)
         s_ref = q.eval(1, dd).cpu().numpy().reshape(nd, -1)
         d_ref = q.eval(2, dd).cpu().numpy().reshape(nd, -1)
@@ -661,6 +665,8 @@ def test_s_and_d_values_and_coefficient_paths(nd):
         rows[name] = both
     n = g.n_tgt
     assert _rel(rows["coefficients"][:, :, :n], rows["values"]) < 1e-13
+    if orders:
+        return  # the oracle runs one uniform order; GQ_S / GQ_D above hold the same orders
     j = nd - 1
     for kind in (1, 2):
         ref = oracle.qbx_eval(e, kind, dens[j], None, p_qbx=12)
