@@ -2652,18 +2652,21 @@ __global__ void __launch_bounds__(64) k_ctr_val(
   const int kq = (P1 + 3) >> 2;  // coefficients per lane group q in a far segment
   // B operands in groups of 2 GH k-steps (GH coefficients per column and lane, 16 values in
   // flight), the next group (or the next segment's first) loaded while the current one is on
-  // the matrix cores
+  // the matrix cores; kept in the storage type until used (a conversion at the load would wait
+  // for it at once)
   constexpr int GH = 8 / NT;
   const int ngr = (nks / 2 + GH - 1) / GH;
-  double2 bcur[GH][NT], bnext[GH][NT];
+  E bcur[GH][NT], bnext[GH][NT];
   auto seg_ptr = [&](int32_t bx, bool local) { return (local ? L : M) + (int64_t)bx * P1; };
-  auto load_group = [&](const E *X, int gi, double2 (&bv)[GH][NT]) {
+  auto load_group = [&](const E *X, int gi, E (&bv)[GH][NT]) {
 #pragma unroll
     for (int jj = 0; jj < GH; ++jj) {
       const int k = 4 * (gi * GH + jj) + q;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        bv[jj][nt] = (k < P1 && so[nt] >= 0) ? to_d2(X[so[nt] + k]) : make_double2(0.0, 0.0);
+      for (int nt = 0; nt < NT; ++nt) {
+        const int64_t o = so[nt] + (k < P1 ? k : 0);
+        bv[jj][nt] = X[o < 0 ? 0 : o];  // masked at use
+      }
     }
   };
   const E *X = seg_ptr(b, true);
@@ -2749,10 +2752,15 @@ __global__ void __launch_bounds__(64) k_ctr_val(
         if (ks < nks) {
           const double are = As[(4 * ks + q) * RS + i];  // A row i, entries 4 ks + q, + 4
           const double aim = As[(4 * ks + 4 + q) * RS + i];
+          const bool kon = 2 * ks + q < P1;  // this lane's coefficient 4 (ks / 2) + q exists
+          double2 bb[NT];
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(are, bcur[jj][nt].x, C[nt]);
+          for (int nt = 0; nt < NT; ++nt)
+            bb[nt] = (kon && so[nt] >= 0) ? to_d2(bcur[jj][nt]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(aim, bcur[jj][nt].y, C[nt]);
+          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(are, bb[nt].x, C[nt]);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(aim, bb[nt].y, C[nt]);
         }
       }
 #pragma unroll
