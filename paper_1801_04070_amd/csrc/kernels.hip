@@ -2987,6 +2987,13 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
                        ctx->params.p_qbx + 1, S.src, S.row);
 }
 
+// Unused LDS requested by the one-density direct pass when it runs on the side stream beside the
+// tree passes: 10 KB per work-group caps it at four waves per SIMD (seven by its registers
+// alone), which leaves wave slots to the moments, M2L and the Stage 7 gather on the critical
+// path. Per step of the 16-star workload: 0.410-0.413 ms against 0.443 uncapped, 0.413 at three
+// waves per SIMD and 0.419 at five.
+constexpr size_t kNearSideLds = 5120;
+
 // Whether the S and D direct pass of nd densities sums at the centers' targets (k_near_sd_t for
 // one density, k_near_val_mfma for a batch): every center serves at most one target.
 inline bool near_at_targets(const gq_ctx *ctx, int nd) {
@@ -3014,7 +3021,8 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   if (n <= 0) return;
   if (near_at_targets(ctx, nd)) {
     if (nd == 1)
-      hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64), 0, s, n,
+      hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64),
+                         ctx->params.overlap ? kNearSideLds : 0, s, n,
                          d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
                          d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1, S.row);
     else if (bk.nvf1 > bk.nvf0 && nd <= 16)
