@@ -29,7 +29,7 @@ The JSON line also carries:
   cpu_baseline  the CPU oracle (direct QBX, FP64) timed on a bounded sample of the same targets
                 on this host; the same oracle values give the GPU-vs-oracle error of this run.
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-variants]
+Usage: python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--no-cpu-baseline] [--no-variants]
        python bench.py --copy-mib 256      (plain copy kernel, for HBM counter calibration)
 """
 from __future__ import annotations
@@ -433,8 +433,10 @@ def rel_errors(sample, out_s, out_d):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the device reaches its steady clock only after some tens of steps: 20 untimed steps, then
+    # 100 timed ones (about 40 ms)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--only", default="", help="comma-separated variant names: run only these")
