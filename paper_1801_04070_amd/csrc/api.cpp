@@ -288,8 +288,8 @@ gq_status build_near_work(gq_ctx *ctx) {
         }
       }
       const int64_t woff = t.list3f.start[b], wlen = t.list3f.start[b + 1] - woff;
-      for (int64_t cb = 0; cb < ng; cb += 16) {
-        const int32_t it[8] = {(int32_t)b, (int32_t)(g0 + cb), (int32_t)std::min<int64_t>(16, ng - cb),
+      for (int64_t cb = 0; cb < ng; cb += 32) {  // k_ctr_val: two row tiles of 16 centers
+        const int32_t it[8] = {(int32_t)b, (int32_t)(g0 + cb), (int32_t)std::min<int64_t>(32, ng - cb),
                                (int32_t)woff, (int32_t)wlen, 0, 0, 0};
         citems.insert(citems.end(), it, it + 8);
       }

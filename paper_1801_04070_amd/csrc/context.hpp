@@ -68,7 +68,7 @@ struct DevBuffers {
   int4 *near_items = nullptr;        // 2 x int4 per item: direct-source chunks (see api.cpp)
   int4 *near_mitems = nullptr;       // 2 x int4 per item: a chunk and up to 4 of its box's centers
   int4 *near_vitems = nullptr;       // the same with up to 16 centers (values at the targets)
-  int4 *cval_items = nullptr;        // 2 x int4: (box, first center, n <= 16, List 3 far start), (n far)
+  int4 *cval_items = nullptr;        // 2 x int4: (box, first center, n <= 32, List 3 far start), (n far)
                                      // (the matrix-core direct pass of S and D batches)
   int4 *far_items = nullptr;         // 2 x int4 per item: List 3 far chunks
   // Stage 5b packed across boxes (far_pairs_per_lane 1): per wavefront 2 x int4 (first pair,

@@ -2574,11 +2574,12 @@ __global__ void __launch_bounds__(64) k_qbx_center(
 //     at p, evaluated at x.
 // These are the coefficient forms of k_qbx_center and k_m2qbxl evaluated at x, summed in another
 // order. The weights U_k, W_k do not depend on the density: one wavefront per (box, block of up
-// to 16 centers) forms them for one segment at a time (the box local, then each List 3 far box)
-// in LDS and contracts them with the segment's expansion over the slots on the matrix cores: rows
-// the centers, k the real and imaginary parts of the coefficients (Re(b U) = b.x U.x - b.y U.y),
-// columns 16 NT slots. Then the center's direct rows are added and its target written.
-template <int PQ, int NT, typename E>
+// to 16 RT centers) forms them for one segment at a time (the box local, then each List 3 far
+// box) in LDS and contracts them with the segment's expansion over the slots on the matrix cores:
+// rows the centers (RT tiles of 16, each B operand serving all of them), k the real and imaginary
+// parts of the coefficients (Re(b U) = b.x U.x - b.y U.y), columns 16 NT slots. Then the center's
+// direct rows are added and its target written.
+template <int PQ, int NT, int RT, typename E>
 __global__ void __launch_bounds__(64) k_ctr_val(
     const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
     const double2 *__restrict__ cxy, const double2 *__restrict__ bc,
@@ -2596,7 +2597,7 @@ __global__ void __launch_bounds__(64) k_ctr_val(
   // coefficient 4 j + r whole and uses its two parts in consecutive k-steps
   const int nks = 2 * ((P1 + 3) >> 2);  // k-steps of one segment
   const int ke = 4 * nks;               // real entries of a segment (zero-padded)
-  constexpr int RS = 17;              // LDS row stride of the weights, [entry][center]
+  constexpr int RS = 16 * RT + 1;       // LDS row stride of the weights, [entry][center]
   double *As = reinterpret_cast<double *>(cv_lds);  // [ke][RS]
   double *Cb = As + ke * RS;                         // [P1][PQ + 1] C(k+m-1, m)
   constexpr int kFarStage = 64;                      // List 3 far boxes staged per item
@@ -2606,6 +2607,7 @@ __global__ void __launch_bounds__(64) k_ctr_val(
   const int4 i0 = items[2 * blockIdx.x], i1 = items[2 * blockIdx.x + 1];
   const int32_t b = i0.x, cfirst = i0.y, n_ctr = i0.z, far0 = i0.w, nfar = i1.x;
   const int d0 = blockIdx.y * 16 * NT;
+  const int nrt = (n_ctr + 15) >> 4;  // row tiles in use (uniform)
   for (int e = lane; e < ke * RS; e += 64) As[e] = 0.0;
   for (int e = lane; e < P1 * (PQ + 1); e += 64) Cb[e] = m2q_binom[(e / (PQ + 1)) * ls + e % (PQ + 1)];
   if (lane < nfar && lane < kFarStage) {
@@ -2627,24 +2629,28 @@ __global__ void __launch_bounds__(64) k_ctr_val(
     }
   };
   const int i = lane & 15, q = lane >> 4;
-  // the weight rows: center i of the block and the offset of its target
-  const bool row_on = i < n_ctr;
-  const int32_t c = cfirst + (row_on ? i : 0);
-  const double2 cc = cxy[c];
-  double2 tz = make_double2(0.0, 0.0);
-  {
+  // the weight rows of this lane: center 16 r + i of the block (row tile r) and its target offset
+  bool row_on[RT];
+  double2 cc[RT], tz[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    row_on[r] = 16 * r + i < n_ctr;
+    const int32_t c = cfirst + (row_on[r] ? 16 * r + i : 0);
+    cc[r] = cxy[c];
+    tz[r] = make_double2(0.0, 0.0);
     const int32_t g = c2t_start[c];
     if (c2t_start[c + 1] > g) {
       const double2 x = txy[c2t_slot[g] >> 1];
-      tz = make_double2(x.x - cc.x, x.y - cc.y);
+      tz[r] = make_double2(x.x - cc[r].x, x.y - cc[r].y);
     }
   }
-  gq_d4 C[NT];
+  gq_d4 C[RT][NT];
   // this lane's B-operand columns: offsets of its slots (-1: past the last slot)
   int64_t so[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    C[nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < RT; ++r) C[r][nt] = gq_d4{0.0, 0.0, 0.0, 0.0};
     const int sl = d0 + 16 * nt + i;
     so[nt] = sl < nslots ? (int64_t)sl * box_st : -1;
   }
@@ -2653,7 +2659,7 @@ __global__ void __launch_bounds__(64) k_ctr_val(
   // B operands in groups of 2 GH k-steps (GH coefficients per column and lane, 16 values in
   // flight), the next group (or the next segment's first) loaded while the current one is on
   // the matrix cores; kept in the storage type until used (a conversion at the load would wait
-  // for it at once)
+  // for it at once). One B load serves the RT row tiles.
   constexpr int GH = 8 / NT;
   const int ngr = (nks / 2 + GH - 1) / GH;
   E bcur[GH][NT], bnext[GH][NT];
@@ -2675,10 +2681,13 @@ __global__ void __launch_bounds__(64) k_ctr_val(
   for (int sg = 0; sg <= nfar; ++sg) {
     __syncthreads();  // the previous segment's weights are no longer read
     if (sg == 0) {
-      if (q == 0) {
+      // lane group q < RT forms the local weights of row tile q
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        if (q != r || r >= nrt) continue;
         const double is = 1.0 / level_side[blevel[b]];
-        const double2 t = make_double2((cc.x - bc[b].x) * is, (cc.y - bc[b].y) * is);
-        const double2 w = make_double2(tz.x * is, tz.y * is);
+        const double2 t = make_double2((cc[r].x - bc[b].x) * is, (cc[r].y - bc[b].y) * is);
+        const double2 w = make_double2(tz[r].x * is, tz[r].y * is);
         const double2 tw = cadd(t, w);
         double2 u = make_double2(1.0, 0.0);
         double2 tp = make_double2(1.0, 0.0);    // t^(k-1-p)
@@ -2693,8 +2702,8 @@ __global__ void __launch_bounds__(64) k_ctr_val(
               tp = cmul(tp, t);
             }
           }
-          As[ent(k) * RS + i] = row_on ? u.x : 0.0;
-          As[(ent(k) + 4) * RS + i] = row_on ? -u.y : 0.0;
+          As[ent(k) * RS + 16 * r + i] = row_on[r] ? u.x : 0.0;
+          As[(ent(k) + 4) * RS + 16 * r + i] = row_on[r] ? -u.y : 0.0;
         }
       }
     } else {
@@ -2702,36 +2711,41 @@ __global__ void __launch_bounds__(64) k_ctr_val(
       double2 cd;
       double sd;
       far_box(sg - 1, box, cd, sd);
-      const double2 y = make_double2(cc.x - cd.x, cc.y - cd.y);
-      const double2 iy = cinv(y);
-      const double2 w = cscale(iy, sd);
-      const double2 rho = make_double2(-(tz.x * iy.x - tz.y * iy.y), -(tz.x * iy.y + tz.y * iy.x));
       const int k0 = q * kq, k1 = min(P1, k0 + kq);
-      if (q == 0) {
-        // a_0 weight: log|y| - Re sum_{m=1..p} rho^m / m
-        const double r1 = 2.0 * rho.x, s2 = cnorm2(rho);
-        double b2 = 1.0 / PQ, b1 = fma(r1, b2, 1.0 / (PQ - 1));
 #pragma unroll
-        for (int m = PQ - 2; m >= 1; --m) {
-          const double b0 = fma(r1, b1, fma(-s2, b2, 1.0 / m));
-          b2 = b1;
-          b1 = b0;
+      for (int r = 0; r < RT; ++r) {
+        if (r >= nrt) continue;
+        const double2 y = make_double2(cc[r].x - cd.x, cc[r].y - cd.y);
+        const double2 iy = cinv(y);
+        const double2 w = cscale(iy, sd);
+        const double2 rho = make_double2(-(tz[r].x * iy.x - tz[r].y * iy.y),
+                                         -(tz[r].x * iy.y + tz[r].y * iy.x));
+        if (q == 0) {
+          // a_0 weight: log|y| - Re sum_{m=1..p} rho^m / m
+          const double r1 = 2.0 * rho.x, s2 = cnorm2(rho);
+          double b2 = 1.0 / PQ, b1 = fma(r1, b2, 1.0 / (PQ - 1));
+#pragma unroll
+          for (int m = PQ - 2; m >= 1; --m) {
+            const double b0 = fma(r1, b1, fma(-s2, b2, 1.0 / m));
+            b2 = b1;
+            b1 = b0;
+          }
+          const double a0w = 0.5 * log_tab(cnorm2(y), g_log_tab) - fma(b1, rho.x, -(s2 * b2));
+          As[ent(0) * RS + 16 * r + i] = row_on[r] ? a0w : 0.0;
+          As[(ent(0) + 4) * RS + 16 * r + i] = 0.0;
         }
-        const double a0w = 0.5 * log_tab(cnorm2(y), g_log_tab) - fma(b1, rho.x, -(s2 * b2));
-        As[ent(0) * RS + i] = row_on ? a0w : 0.0;
-        As[(ent(0) + 4) * RS + i] = 0.0;
-      }
-      double2 wk = cpowi(w, k0 > 1 ? k0 : 1);
-      for (int k = k0 > 1 ? k0 : 1; k < k1; ++k) {
-        const double *ck = Cb + k * (PQ + 1);
-        double2 h = make_double2(ck[PQ], 0.0);
+        double2 wk = cpowi(w, k0 > 1 ? k0 : 1);
+        for (int k = k0 > 1 ? k0 : 1; k < k1; ++k) {
+          const double *ck = Cb + k * (PQ + 1);
+          double2 h = make_double2(ck[PQ], 0.0);
 #pragma unroll
-        for (int m = PQ - 1; m >= 0; --m)
-          h = make_double2(fma(h.x, rho.x, fma(-h.y, rho.y, ck[m])), fma(h.x, rho.y, h.y * rho.x));
-        const double2 wv = cmul(wk, h);
-        As[ent(k) * RS + i] = row_on ? wv.x : 0.0;
-        As[(ent(k) + 4) * RS + i] = row_on ? -wv.y : 0.0;
-        wk = cmul(wk, w);
+          for (int m = PQ - 1; m >= 0; --m)
+            h = make_double2(fma(h.x, rho.x, fma(-h.y, rho.y, ck[m])), fma(h.x, rho.y, h.y * rho.x));
+          const double2 wv = cmul(wk, h);
+          As[ent(k) * RS + 16 * r + i] = row_on[r] ? wv.x : 0.0;
+          As[(ent(k) + 4) * RS + 16 * r + i] = row_on[r] ? -wv.y : 0.0;
+          wk = cmul(wk, w);
+        }
       }
     }
     __syncthreads();
@@ -2750,17 +2764,21 @@ __global__ void __launch_bounds__(64) k_ctr_val(
       for (int jj = 0; jj < GH; ++jj) {
         const int ks = 2 * (gi * GH + jj);
         if (ks < nks) {
-          const double are = As[(4 * ks + q) * RS + i];  // A row i, entries 4 ks + q, + 4
-          const double aim = As[(4 * ks + 4 + q) * RS + i];
           const bool kon = 2 * ks + q < P1;  // this lane's coefficient 4 (ks / 2) + q exists
           double2 bb[NT];
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt)
             bb[nt] = (kon && so[nt] >= 0) ? to_d2(bcur[jj][nt]) : make_double2(0.0, 0.0);
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(are, bb[nt].x, C[nt]);
+          for (int r = 0; r < RT; ++r) {
+            if (r >= nrt) continue;
+            const double are = As[(4 * ks + q) * RS + 16 * r + i];  // A row i of tile r
+            const double aim = As[(4 * ks + 4 + q) * RS + 16 * r + i];
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) C[nt] = mfma16(aim, bb[nt].y, C[nt]);
+            for (int nt = 0; nt < NT; ++nt) C[r][nt] = mfma16(are, bb[nt].x, C[r][nt]);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) C[r][nt] = mfma16(aim, bb[nt].y, C[r][nt]);
+          }
         }
       }
 #pragma unroll
@@ -2769,27 +2787,30 @@ __global__ void __launch_bounds__(64) k_ctr_val(
         for (int nt = 0; nt < NT; ++nt) bcur[jj][nt] = bnext[jj][nt];
     }
   }
-  // lane (column j = lane & 15, group g = lane >> 4) holds rows (centers) g + 4 v
+  // lane (column j = lane & 15, group g = lane >> 4) holds rows (centers) 16 r + g + 4 v
   const int g = q, j = i;
   const int32_t nbc = bctr1[b] - bctr0[b];
   const int32_t nnear = n_near_chunks[b];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int ci = g + 4 * v;
-    if (ci >= n_ctr) continue;
-    const int32_t cv = cfirst + ci;
-    const int32_t t0 = c2t_start[cv];
-    if (c2t_start[cv + 1] <= t0) continue;
-    const int32_t tslot = c2t_slot[t0];
-    const int64_t row0 = (int64_t)part_base[b] + (cv - bctr0[b]);
+  for (int r = 0; r < RT; ++r) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int sl = d0 + 16 * nt + j;
-      if (sl >= nslots) continue;
-      double val = C[nt][v];
-      for (int32_t ch = 0; ch < nnear; ++ch)
-        val += anear[(int64_t)sl * row_st + (row0 + (int64_t)ch * nbc) * rs].x;
-      tv[(int64_t)sl * tv_st + tslot] = -kInv2Pi * val;
+    for (int v = 0; v < 4; ++v) {
+      const int ci = 16 * r + g + 4 * v;
+      if (ci >= n_ctr) continue;
+      const int32_t cv = cfirst + ci;
+      const int32_t t0 = c2t_start[cv];
+      if (c2t_start[cv + 1] <= t0) continue;
+      const int32_t tslot = c2t_slot[t0];
+      const int64_t row0 = (int64_t)part_base[b] + (cv - bctr0[b]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int sl = d0 + 16 * nt + j;
+        if (sl >= nslots) continue;
+        double val = C[r][nt][v];
+        for (int32_t ch = 0; ch < nnear; ++ch)
+          val += anear[(int64_t)sl * row_st + (row0 + (int64_t)ch * nbc) * rs].x;
+        tv[(int64_t)sl * tv_st + tslot] = -kInv2Pi * val;
+      }
     }
   }
 }
@@ -3098,6 +3119,10 @@ inline bool center_at_targets(const gq_ctx *ctx, int nd, bool sd) {
   return sd && nd >= kNearMfmaMin && near_at_targets(ctx, nd) && ctx->d.cval_items != nullptr;
 }
 
+// Centers per k_ctr_val item: two row tiles of 16 (the box's expansions read once for up to 32
+// of its centers).
+constexpr int kCtrValRT = 2;
+
 template <int PQ, int NT, typename E>
 void launch_ctr_val(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStream_t s, const Strides &S,
                     const E *M, const E *L) {
@@ -3105,9 +3130,11 @@ void launch_ctr_val(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStream_t s
   const int32_t n = (int32_t)(bk.cv1 - bk.cv0);
   if (n <= 0) return;
   const int P1 = ctx->params.p_fmm + 1;
-  const int ke = 4 * ((2 * P1 + 3) / 4);
-  const size_t lds = sizeof(double) * ((size_t)ke * 17 + (size_t)P1 * (PQ + 1));
-  hipLaunchKernelGGL((k_ctr_val<PQ, NT, E>), dim3((uint32_t)n, (slots + 16 * NT - 1) / (16 * NT)),
+  const int ke = 8 * ((P1 + 3) / 4);
+  const size_t lds =
+      sizeof(double) * ((size_t)ke * (16 * kCtrValRT + 1) + (size_t)P1 * (PQ + 1));
+  hipLaunchKernelGGL((k_ctr_val<PQ, NT, kCtrValRT, E>),
+                     dim3((uint32_t)n, (slots + 16 * NT - 1) / (16 * NT)),
                      dim3(64), lds, s, d.cval_items + 2 * bk.cv0, d.wf_idx, d.cxy, d.bc, d.blevel,
                      d.level_side, M, L, P1, d.m2q_binom, ctx->params.p_qbx + 1,
                      d.bctr0, d.bctr1, d.part_base, d.n_near_chunks, d.anear, ctx->params.p_qbx + 1,
@@ -3119,8 +3146,7 @@ void launch_ctr_val_bucket(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStr
                            const Strides &S, const E *M, const E *L) {
   if (slots <= 16) launch_ctr_val<PQ, 1, E>(ctx, bk, slots, s, S, M, L);
   else if (slots <= 32) launch_ctr_val<PQ, 2, E>(ctx, bk, slots, s, S, M, L);
-  else if (slots <= 64) launch_ctr_val<PQ, 4, E>(ctx, bk, slots, s, S, M, L);
-  else launch_ctr_val<PQ, 8, E>(ctx, bk, slots, s, S, M, L);
+  else launch_ctr_val<PQ, 4, E>(ctx, bk, slots, s, S, M, L);
 }
 
 template <int KIND, typename E>
