@@ -47,7 +47,7 @@ void free_workspace(gq_ctx *ctx) {
   ctx->ws_batch = 0;
   ctx->d.sq = nullptr; ctx->d.sdip = nullptr; ctx->d.M = nullptr; ctx->d.L = nullptr;
   ctx->d.Lf = nullptr; ctx->d.Mp = nullptr;
-  ctx->d.anear = nullptr; ctx->d.tv = nullptr;
+  ctx->d.anear = nullptr; ctx->d.nval = nullptr; ctx->d.tv = nullptr;
 }
 
 void drop_target_normals(gq_ctx *ctx) {
@@ -743,6 +743,7 @@ gq_status ensure_workspace(gq_ctx *ctx, int nd) {
   GQ_TRY(alloc_ws(ctx, d.Lf, n * nb * P1));
   GQ_TRY(alloc_ws(ctx, d.Mp, n * (size_t)std::max<int64_t>(ctx->n_p2m_parts, 1) * 2 * P1));
   GQ_TRY(alloc_ws(ctx, d.anear, n * std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1)));
+  GQ_TRY(alloc_ws(ctx, d.nval, n * std::max<int64_t>(ctx->n_near_rows, 1)));
   GQ_TRY(alloc_ws(ctx, d.tv, n * 2 * ctx->nt));
   ctx->ws_batch = nd;
   return GQ_OK;
@@ -783,6 +784,7 @@ size_t workspace_bytes(const gq_ctx *ctx, int slots) {
          r(n * (size_t)std::max<int64_t>(ctx->n_p2m_parts, 1) * 2 * P1 * sizeof(double2)) +
          r(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1) *
            sizeof(double2)) +
+         r(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * sizeof(double)) +
          r(n * 2 * ctx->nt * sizeof(double));
 }
 
@@ -807,6 +809,8 @@ void carve_workspace(gq_ctx *ctx, int slots, unsigned char *base) {
   d.anear = reinterpret_cast<double2 *>(
       take(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * (ctx->params.p_qbx + 1) *
            sizeof(double2)));
+  d.nval = reinterpret_cast<double *>(
+      take(n * (size_t)std::max<int64_t>(ctx->n_near_rows, 1) * sizeof(double)));
   d.tv = reinterpret_cast<double *>(take(n * 2 * ctx->nt * sizeof(double)));
 }
 

@@ -86,6 +86,7 @@ struct DevBuffers {
   int32_t *n_near_chunks = nullptr;  // of them direct-source chunks (the first ones)
   int32_t *ctr_list = nullptr;       // tree-order centers grouped by order
   double2 *anear = nullptr;          // near rows: [row][p_qbx + 1] scaled coefficients
+  double *nval = nullptr;            // direct values at the targets, one per near row (R38 paths)
   // tables
   double2 *opow = nullptr;
   double *m2l_bt = nullptr;

@@ -1720,16 +1720,16 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
 // Computer Programming, vol. 2, Sec. 4.6.4): with r1 = 2 Re rho and s = |rho|^2,
 // b_k = a_k + r1 b_(k+1) - s b_(k+2) downwards from b_p = a_p, and P(rho) = b_1 rho + a_0 - s b_2;
 // two fused multiply-adds per order and polynomial, against a complex product and a complex
-// accumulation per order for the coefficients. Each (center, chunk) row gets the value in the
-// real part of its order-0 entry (S; D d_off entries further), which the center stage adds to the
-// constant term of the center's expansion; the row's other entries are neither written nor read.
+// accumulation per order for the coefficients. Each (center, chunk) row's value goes to the dense
+// value array nval (S; D d_off entries further, one slot on), which the center stage adds to the
+// constant term of the center's expansion.
 template <int PQ>
 __global__ void __launch_bounds__(64) k_near_sd_t(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double2 *__restrict__ sxy,
     const double *__restrict__ sq, const double2 *__restrict__ sdip,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
-    const double2 *__restrict__ txy, double2 *__restrict__ anear, int rs, int64_t d_off) {
+    const double2 *__restrict__ txy, double *__restrict__ nval, int64_t d_off) {
   static_assert(PQ >= 2, "the recurrences start at b_p and b_(p-1)");
   __shared__ double2 t_xy[kNearBatch];
   __shared__ double t_q[kNearBatch];
@@ -1815,9 +1815,8 @@ __global__ void __launch_bounds__(64) k_near_sd_t(
     slice_add(dsum, o, take);
   }
   if (active && sl == 0) {
-    double2 *row = anear + (int64_t)(row_first + cl) * rs;
-    row[0] = make_double2(vs, 0.0);
-    row[d_off] = make_double2(dsum, 0.0);
+    nval[row_first + cl] = vs;
+    nval[d_off + row_first + cl] = dsum;
   }
 }
 
@@ -2018,16 +2017,16 @@ __global__ void __launch_bounds__(256, 2) k_near_mfma(
 // chunk is staged 64 sources at a time (positions, normals and the strengths of the densities,
 // the next batch's loads in flight during the current one), each wavefront takes 16 of them
 // (four k-steps, lane (row i, k kk) forming the weights of one pair), and the four partial
-// products are summed through LDS at the end. Values go to the order-0 entry of the (center,
-// chunk) rows as in k_near_sd_t: S of density j in slot j, D in slot d_slot + j.
+// products are summed through LDS at the end. Values go to the dense value array as in
+// k_near_sd_t: S of density j in slot j, D in slot d_slot + j.
 template <int PQ, int NT>
 __global__ void __launch_bounds__(256, 2) k_near_val_mfma(
     const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double2 *__restrict__ sxy,
     const double2 *__restrict__ snrm, const double *__restrict__ sq,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
-    const double2 *__restrict__ txy, double2 *__restrict__ anear, int rs, int64_t src_st,
-    int64_t row_st, int nd, int64_t d_slot) {
+    const double2 *__restrict__ txy, double *__restrict__ nval, int64_t src_st, int64_t nv_st,
+    int nd, int64_t d_slot) {
   static_assert(PQ >= 2, "the recurrences start at b_p and b_(p-1)");
   constexpr int NDB = 16 * NT;  // densities per work-group
   constexpr int SB = 64;        // sources staged per batch, 16 per wavefront
@@ -2169,9 +2168,9 @@ __global__ void __launch_bounds__(256, 2) k_near_val_mfma(
     for (int v = 0; v < 4; ++v) {
       const int ci = g + 4 * v;
       if (ci >= n_ctr) continue;
-      const int64_t row = (int64_t)(row_first + ci) * rs;
-      anear[(int64_t)dj * row_st + row] = make_double2(CS[nt][v], 0.0);
-      anear[(d_slot + dj) * row_st + row] = make_double2(CD[nt][v], 0.0);
+      const int64_t row = row_first + ci;
+      nval[(int64_t)dj * nv_st + row] = CS[nt][v];
+      nval[(d_slot + dj) * nv_st + row] = CD[nt][v];
     }
   }
 }
@@ -2443,10 +2442,11 @@ __global__ void __launch_bounds__(64) k_qbx_center(
     const E *__restrict__ L, int P1, const double *__restrict__ l2q_binom,
     const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
     const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_chunks,
-    const int32_t *__restrict__ n_val_chunks, const double2 *__restrict__ anear,
+    const int32_t *__restrict__ n_val_chunks, const double *__restrict__ nval,
+    const double2 *__restrict__ anear,
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ tv, int64_t box_st, int64_t row_st,
-    int64_t tv_st, const double2 *__restrict__ tnrm) {
+    int64_t tv_st, const double2 *__restrict__ tnrm, int64_t nv_st) {
   HIP_DYNAMIC_SHARED(unsigned char, ctr_lds)
   E *Ls = reinterpret_cast<E *>(ctr_lds);  // [kCenterStage][P1]
   __shared__ int32_t sbox[kCenterStage];
@@ -2459,6 +2459,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
     L += jd * box_st;
     anear += jd * row_st;
     tv += jd * tv_st;
+    if (nval) nval += jd * nv_st;
   }
   const int32_t b = cbox[c];
   // runs of equal boxes across the wave's lanes; run j < kCenterStage is staged in LDS row j
@@ -2542,19 +2543,20 @@ __global__ void __launch_bounds__(64) k_qbx_center(
   }
 
   // direct (P2QBXL) and List 3 far (M2QBXL) rows of this center, in chunk order; with
-  // n_val_chunks the box's first n_val_chunks[b] (direct) rows hold the value at the center's
-  // target in the real part of their order-0 entry (k_near_sd_t)
+  // n_val_chunks the box's first n_val_chunks[b] (direct) rows are values at the center's target
+  // in nval (k_near_sd_t)
   {
     const int32_t nbc = bctr1[b] - bctr0[b];
     const int32_t loc = c - bctr0[b];
     const int32_t nch = n_chunks[b];
-    const int32_t nval = n_val_chunks ? n_val_chunks[b] : 0;
+    const int32_t nvc = n_val_chunks ? n_val_chunks[b] : 0;
     for (int32_t j = 0; j < nch; ++j) {
-      const double2 *row = anear + (int64_t)(part_base[b] + j * nbc + loc) * rs;
-      if (j < nval) {
-        alpha[0].x += row[0].x;
+      const int64_t r = (int64_t)part_base[b] + j * nbc + loc;
+      if (j < nvc) {
+        alpha[0].x += nval[r];
         continue;
       }
+      const double2 *row = anear + r * rs;
 #pragma unroll
       for (int m = 0; m <= PQ; ++m) alpha[m] = cadd(alpha[m], row[m]);
     }
@@ -2588,9 +2590,9 @@ __global__ void __launch_bounds__(64) k_ctr_val(
     const double *__restrict__ m2q_binom, int ls,
     const int32_t *__restrict__ bctr0, const int32_t *__restrict__ bctr1,
     const int32_t *__restrict__ part_base, const int32_t *__restrict__ n_near_chunks,
-    const double2 *__restrict__ anear, int rs, const int32_t *__restrict__ c2t_start,
+    const double *__restrict__ nval, const int32_t *__restrict__ c2t_start,
     const int32_t *__restrict__ c2t_slot, const double2 *__restrict__ txy,
-    double *__restrict__ tv, int64_t box_st, int64_t row_st, int64_t tv_st, int nslots) {
+    double *__restrict__ tv, int64_t box_st, int64_t nv_st, int64_t tv_st, int nslots) {
   HIP_DYNAMIC_SHARED(unsigned char, cv_lds)
   // k order of a segment: coefficient k = 4 j + r sits at entry 8 j + r (real part, k-step 2 j,
   // B row r) and 8 j + 4 + r (imaginary part, k-step 2 j + 1), so that lane r of a B column loads
@@ -2808,7 +2810,7 @@ __global__ void __launch_bounds__(64) k_ctr_val(
         if (sl >= nslots) continue;
         double val = C[r][nt][v];
         for (int32_t ch = 0; ch < nnear; ++ch)
-          val += anear[(int64_t)sl * row_st + (row0 + (int64_t)ch * nbc) * rs].x;
+          val += nval[(int64_t)sl * nv_st + row0 + (int64_t)ch * nbc];
         tv[(int64_t)sl * tv_st + tslot] = -kInv2Pi * val;
       }
     }
@@ -2951,13 +2953,13 @@ auto p2x_kernel(int P1) {
 
 // Per-density strides of the batched buffers (elements).
 struct Strides {
-  int64_t src, box, row, tv;
+  int64_t src, box, row, tv, nv;
 };
 
 Strides strides(const gq_ctx *ctx) {
   const int64_t P1 = ctx->params.p_fmm + 1;
   return {ctx->ns, ctx->tree.n_boxes() * P1, ctx->n_near_rows * (ctx->params.p_qbx + 1),
-          2 * ctx->nt};
+          2 * ctx->nt, std::max<int64_t>(ctx->n_near_rows, 1)};
 }
 
 template <int KIND>
@@ -3028,8 +3030,8 @@ void launch_near_val_mfma(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
   const int32_t nv = (int32_t)(bk.nvf1 - bk.nvf0);
   hipLaunchKernelGGL((k_near_val_mfma<PQ, NT>), dim3((uint32_t)nv, (nd + 16 * NT - 1) / (16 * NT)),
                      dim3(256), 0, s, d.near_vitems + 2 * bk.nvf0, d.near_src, d.cxy, d.sxy,
-                     d.snrm, d.sq, d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1,
-                     S.src, S.row, nd, (int64_t)nd);
+                     d.snrm, d.sq, d.c2t_start, d.c2t_slot, d.txy, d.nval, S.src, S.nv, nd,
+                     (int64_t)nd);
 }
 
 // S and D of the same densities (nd of them): one fused pass for a single density, else the
@@ -3045,7 +3047,7 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
       hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64),
                          ctx->params.overlap ? kNearSideLds : 0, s, n,
                          d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
-                         d.c2t_start, d.c2t_slot, d.txy, d.anear, ctx->params.p_qbx + 1, S.row);
+                         d.c2t_start, d.c2t_slot, d.txy, d.nval, S.nv);
     else if (bk.nvf1 > bk.nvf0 && nd <= 16)
       launch_near_val_mfma<PQ, 1>(ctx, bk, nd, s, S);
     else if (bk.nvf1 > bk.nvf0 && nd <= 32)
@@ -3107,9 +3109,9 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
                        d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
                        d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
-                       near_values ? d.n_near_chunks : nullptr, d.anear,
-                       d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv,
-                       ctx->eval_sp ? ctx->tnrm_dev : nullptr);
+                       near_values ? d.n_near_chunks : nullptr, near_values ? d.nval : nullptr,
+                       d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv,
+                       ctx->eval_sp ? ctx->tnrm_dev : nullptr, S.nv);
 }
 
 // The center stage summed at the targets (k_ctr_val), which also takes the List 3 far
@@ -3137,8 +3139,8 @@ void launch_ctr_val(gq_ctx *ctx, const OrderBucket &bk, int slots, hipStream_t s
                      dim3((uint32_t)n, (slots + 16 * NT - 1) / (16 * NT)),
                      dim3(64), lds, s, d.cval_items + 2 * bk.cv0, d.wf_idx, d.cxy, d.bc, d.blevel,
                      d.level_side, M, L, P1, d.m2q_binom, ctx->params.p_qbx + 1,
-                     d.bctr0, d.bctr1, d.part_base, d.n_near_chunks, d.anear, ctx->params.p_qbx + 1,
-                     d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv, slots);
+                     d.bctr0, d.bctr1, d.part_base, d.n_near_chunks, d.nval, d.c2t_start,
+                     d.c2t_slot, d.txy, d.tv, S.box, S.nv, S.tv, slots);
 }
 
 template <int PQ, typename E>
