@@ -60,7 +60,7 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int,
     D of the same density, one pipeline) is the sum of the two kinds except for the direct
     interactions, whose pair geometry is formed once. The flops are the method's (coefficient
     formation and evaluation) whatever the kernel's formulation; near_values: the direct pass
-    writes one value per (center, chunk) row and kind instead of the coefficient row (every
+    writes one double per (center, chunk) row and kind instead of the coefficient row (every
     center serving one target)."""
     if kind == 4:
         s = stage_work(stats, 1, p_qbx, p_fmm, n_slots)
@@ -74,7 +74,7 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int,
                                + 2 * stats.get("n_moment_boxes", 0) * P1 * 16, "bound": "alu"}
         out["near"] = {"flops": stats["near_pairs"] * _near_pair_flops(4, p_qbx),
                        "bytes": stats["near_sources"] * (40 + 4) + stats["n_ctr"] * 24
-                                + 2 * stats["n_ctr"] * (16 if near_values else row),
+                                + 2 * stats["n_ctr"] * (8 if near_values else row),
                        "bound": "alu"}
         return out
     q, p = p_qbx, p_fmm
