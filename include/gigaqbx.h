@@ -225,11 +225,14 @@ gq_status gq_set_target_normals(gq_ctx *ctx, int mem, int64_t n_tgt, const doubl
  *   kind GQ_S_MINUS_D:  out[j] = S dens1[j] - D dens2[j]
  *   kind GQ_S_AND_D:    out[j] = S dens1[j] and out[n_dens + j] = D dens1[j]; one expansion
  *                       pipeline over two workspace halves (S, D): the stages that only move
- *                       expansions run once for both kinds, and for a single density the direct
- *                       interactions of both kinds are one pass (pair geometry and powers of 1/z
- *                       shared; its D rows agree with a GQ_D evaluation to rounding, its S rows
- *                       exactly). The direct-QBX path (gq_eval_direct) runs the two kinds on two
- *                       library streams forked from and joined back to the context's stream
+ *                       expansions run once for both kinds, and the direct interactions of both
+ *                       kinds share their pair geometry. When every center serves at most one
+ *                       target, the direct part of each center's expansion (and, for 8 or more
+ *                       densities, its box parts L2QBXL and M2QBXL) is summed at that target
+ *                       instead of formed as coefficients: the same truncated series in another
+ *                       order, so S and D agree with GQ_S and GQ_D to rounding (about 1e-14),
+ *                       not bitwise. The direct-QBX path (gq_eval_direct) runs the two kinds on
+ *                       two library streams forked from and joined back to the context's stream
  *   kind GQ_SP:         out[j] = S' dens1[j] (needs gq_set_target_normals, else GQ_ESTATE)
  * dens1/dens2 are device arrays (n_dens, n_src) with row stride ld1/ld2 (>= n_src) in the
  * caller's source order; out is a device array (n_dens, n_tgt) (GQ_S_AND_D: 2 n_dens rows)
@@ -259,7 +262,7 @@ gq_status gq_eval_direct(gq_ctx *ctx, int kind, int64_t n_dens, const double *de
  * workspace (strengths, box expansions, center rows, target slots) lives in a fixed scratch
  * array of 256 MiB in device memory that the library holds on each device it runs on until the
  * process ends (its address is taken when the first context is created on that device). An
- * evaluation whose workspace for one density batch exceeds it (about 100 MB per density and kind
+ * evaluation whose workspace for one density batch exceeds it (about 105 MB per density and kind
  * for 131072 sources at p_fmm 30, p_qbx 12) gives GQ_EINVAL and launches nothing; stage profiling
  * must be off (GQ_ESTATE). The call allocates no device or host memory. Every call on a device
  * shares that device's scratch, so calls that can overlap on one device (on different streams or
