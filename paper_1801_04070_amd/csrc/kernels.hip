@@ -1709,8 +1709,9 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
   }
 }
 
-// S and D of one density evaluated at the centers' own targets, for geometries in which every
-// center serves at most one target (a target on the curve takes one center on each side). The
+// The direct part of one density evaluated at the centers' own targets (KIND 4: S and D, two
+// values; 1, 2, 3: S, D or S - D, one value), for geometries in which every center serves at
+// most one target (a target on the curve takes one center on each side). The
 // direct part of a center's expansion is then needed at one point only, x, and is summed there:
 // for a source y of charge q and dipole strength d, with z = y - c and rho = (x - c)/z,
 //   S: q (log|z| - Re sum_{k=1..p} rho^k / k),   D: Re((d / z) sum_{k=0..p} rho^k),
@@ -1723,7 +1724,7 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
 // accumulation per order for the coefficients. Each (center, chunk) row's value goes to the dense
 // value array nval (S; D d_off entries further, one slot on), which the center stage adds to the
 // constant term of the center's expansion.
-template <int PQ>
+template <int KIND, int PQ>
 __global__ void __launch_bounds__(64) k_near_sd_t(
     int32_t n_items, const int4 *__restrict__ items, const int32_t *__restrict__ near_src,
     const double2 *__restrict__ cxy, const double2 *__restrict__ sxy,
@@ -1731,9 +1732,10 @@ __global__ void __launch_bounds__(64) k_near_sd_t(
     const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
     const double2 *__restrict__ txy, double *__restrict__ nval, int64_t d_off) {
   static_assert(PQ >= 2, "the recurrences start at b_p and b_(p-1)");
+  constexpr bool HS = KIND != 2, HD = KIND != 1;  // single / double layer terms
   __shared__ double2 t_xy[kNearBatch];
-  __shared__ double t_q[kNearBatch];
-  __shared__ double2 t_d[kNearBatch];
+  __shared__ double t_q[HS ? kNearBatch : 1];
+  __shared__ double2 t_d[HD ? kNearBatch : 1];
   const int32_t w = (int32_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int4 i0 = items[2 * w], i1 = items[2 * w + 1];
@@ -1765,13 +1767,13 @@ __global__ void __launch_bounds__(64) k_near_sd_t(
     __syncthreads();
     if (lane < nb) {
       t_xy[lane] = sxy[s0];
-      t_q[lane] = sq[s0];
-      t_d[lane] = sdip[s0];
+      if (HS) t_q[lane] = sq[s0];
+      if (HD) t_d[lane] = sdip[s0];
     }
     if (lane + 64 < nb) {
       t_xy[lane + 64] = sxy[s1];
-      t_q[lane + 64] = sq[s1];
-      t_d[lane + 64] = sdip[s1];
+      if (HS) t_q[lane + 64] = sq[s1];
+      if (HD) t_d[lane + 64] = sdip[s1];
     }
     nx0 = idx(off + base + kNearBatch + lane);
     nx1 = idx(off + base + kNearBatch + lane + 64);
@@ -1779,11 +1781,9 @@ __global__ void __launch_bounds__(64) k_near_sd_t(
     if (active) {
       for (int j = sl; j < nb; j += nsl) {
         const double2 y = t_xy[j];
-        const double q = t_q[j];
         const double dx = y.x - cc.x, dy = y.y - cc.y;
         const double n2 = fma(dx, dx, dy * dy);
         const double ir2 = rcp_nr(n2);
-        logsum = fma(q, log_tab(n2, lt), logsum);
         // rho = (x - c) conj(z) / |z|^2
         const double ux = fma(tz.x, dx, tz.y * dy) * ir2;
         const double uy = fma(tz.y, dx, -(tz.x * dy)) * ir2;
@@ -1792,31 +1792,44 @@ __global__ void __launch_bounds__(64) k_near_sd_t(
         double e2 = 1.0, e1 = 1.0 + r1;                           // D: a_k = 1
 #pragma unroll
         for (int k = PQ - 2; k >= 1; --k) {
-          const double b0 = fma(r1, b1, fma(-s, b2, 1.0 / k));
-          const double e0 = fma(r1, e1, fma(-s, e2, 1.0));
-          b2 = b1;
-          b1 = b0;
-          e2 = e1;
-          e1 = e0;
+          if (HS) {
+            const double b0 = fma(r1, b1, fma(-s, b2, 1.0 / k));
+            b2 = b1;
+            b1 = b0;
+          }
+          if (HD) {
+            const double e0 = fma(r1, e1, fma(-s, e2, 1.0));
+            e2 = e1;
+            e1 = e0;
+          }
         }
-        fsum = fma(q, fma(b1, ux, -(s * b2)), fsum);
-        const double gx = fma(e1, ux, fma(-s, e2, 1.0)), gy = e1 * uy;
-        // Re(d conj(z) g) / |z|^2
-        const double hx = fma(dx, gx, dy * gy), hy = fma(dx, gy, -(dy * gx));
-        const double2 dr = t_d[j];
-        dsum = fma(ir2, fma(dr.x, hx, -(dr.y * hy)), dsum);
+        if (HS) {
+          const double q = t_q[j];
+          logsum = fma(q, log_tab(n2, lt), logsum);
+          fsum = fma(q, fma(b1, ux, -(s * b2)), fsum);
+        }
+        if (HD) {
+          const double gx = fma(e1, ux, fma(-s, e2, 1.0)), gy = e1 * uy;
+          // Re(d conj(z) g) / |z|^2
+          const double hx = fma(dx, gx, dy * gy), hy = fma(dx, gy, -(dy * gx));
+          const double2 dr = t_d[j];
+          dsum = fma(ir2, fma(dr.x, hx, -(dr.y * hy)), dsum);
+        }
       }
     }
   }
+  // S and D of one density: two values (D d_off further); one kind, or S - D (the dipoles carry
+  // the sign): one value
   double vs = fma(0.5, logsum, -fsum);
+  if (KIND != 4) vs += dsum;
   for (int o = 1; o < nsl; o <<= 1) {
     const bool take = (sl & (2 * o - 1)) == 0 && sl + o < nsl;
     slice_add(vs, o, take);
-    slice_add(dsum, o, take);
+    if (KIND == 4) slice_add(dsum, o, take);
   }
   if (active && sl == 0) {
     nval[row_first + cl] = vs;
-    nval[d_off + row_first + cl] = dsum;
+    if (KIND == 4) nval[d_off + row_first + cl] = dsum;
   }
 }
 
@@ -2987,12 +3000,35 @@ template <> struct ExpTables<float2> {
       : m2l_bt(d.m2l_bt_f), opow(d.opow_f), m2g_opow(d.m2g_opow_f) {}
 };
 
+// Unused LDS requested by the one-density direct pass when it runs on the side stream beside the
+// tree passes: 10 KB per work-group caps it at four waves per SIMD (seven by its registers
+// alone), which leaves wave slots to the moments, M2L and the Stage 7 gather on the critical
+// path. Per step of the 16-star workload: 0.410-0.413 ms against 0.443 uncapped, 0.413 at three
+// waves per SIMD and 0.419 at five.
+constexpr size_t kNearSideLds = 5120;
+
+// Whether the direct pass of nd densities of a kind sums at the centers' targets (dense values
+// instead of coefficient rows): every center serves at most one target, the expansions are not
+// differentiated at the targets (GQ_SP), and either one density (k_near_sd_t) or S and D of a
+// batch (k_near_val_mfma).
+inline bool near_values(const gq_ctx *ctx, int nd, int kind) {
+  return nd >= 1 && ctx->one_target_per_center && ctx->d.n_near_chunks != nullptr &&
+         !ctx->eval_sp && (kind == 4 || nd == 1);
+}
+
 // The three per-order stages of one order bucket.
 template <int KIND, int PQ, typename E>
 void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
                         const Strides &S, double2 *anear) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
+  if (n > 0 && near_values(ctx, nd, KIND)) {  // one density, summed at the targets
+    hipLaunchKernelGGL((k_near_sd_t<KIND, PQ>), dim3(n, 1), dim3(64),
+                       ctx->params.overlap ? kNearSideLds : 0, s, n, d.near_items + 2 * bk.near0,
+                       d.near_src, d.cxy, d.sxy, d.sq, d.sdip, d.c2t_start, d.c2t_slot, d.txy,
+                       d.nval, S.nv);
+    return;
+  }
   // Densities per work item: two by default. Four hold 4 (PQ + 1) complex accumulators per lane,
   // which above order 6 leaves one or two waves per SIMD and runs slower than two.
   const int dg = nd < 2 ? 1 : ctx->params.near_dens_group > 0 ? ctx->params.near_dens_group : 2;
@@ -3010,18 +3046,7 @@ void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t 
                        ctx->params.p_qbx + 1, S.src, S.row);
 }
 
-// Unused LDS requested by the one-density direct pass when it runs on the side stream beside the
-// tree passes: 10 KB per work-group caps it at four waves per SIMD (seven by its registers
-// alone), which leaves wave slots to the moments, M2L and the Stage 7 gather on the critical
-// path. Per step of the 16-star workload: 0.410-0.413 ms against 0.443 uncapped, 0.413 at three
-// waves per SIMD and 0.419 at five.
-constexpr size_t kNearSideLds = 5120;
 
-// Whether the S and D direct pass of nd densities sums at the centers' targets (k_near_sd_t for
-// one density, k_near_val_mfma for a batch): every center serves at most one target.
-inline bool near_at_targets(const gq_ctx *ctx, int nd) {
-  return nd >= 1 && ctx->one_target_per_center && ctx->d.n_near_chunks != nullptr;
-}
 
 template <int PQ, int NT>
 void launch_near_val_mfma(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
@@ -3042,9 +3067,9 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.near1 - bk.near0);
   if (n <= 0) return;
-  if (near_at_targets(ctx, nd)) {
+  if (near_values(ctx, nd, 4)) {
     if (nd == 1)
-      hipLaunchKernelGGL((k_near_sd_t<PQ>), dim3(n, 1), dim3(64),
+      hipLaunchKernelGGL((k_near_sd_t<4, PQ>), dim3(n, 1), dim3(64),
                          ctx->params.overlap ? kNearSideLds : 0, s, n,
                          d.near_items + 2 * bk.near0, d.near_src, d.cxy, d.sxy, d.sq, d.sdip,
                          d.c2t_start, d.c2t_slot, d.txy, d.nval, S.nv);
@@ -3118,7 +3143,7 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
 // multipoles: with the direct values of a S and D evaluation of kNearMfmaMin or more densities
 // (the weights are formed once for all slots; for fewer slots the coefficient kernels are faster).
 inline bool center_at_targets(const gq_ctx *ctx, int nd, bool sd) {
-  return sd && nd >= kNearMfmaMin && near_at_targets(ctx, nd) && ctx->d.cval_items != nullptr;
+  return sd && nd >= kNearMfmaMin && near_values(ctx, nd, 4) && ctx->d.cval_items != nullptr;
 }
 
 // Centers per k_ctr_val item: two row tiles of 16 (the box's expansions read once for up to 32
@@ -3307,11 +3332,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     }
   } else {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
-    const bool near_values = SD && near_at_targets(ctx, nd);
+    const bool nvals = near_values(ctx, nd, KIND);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf, near_values); break;
+  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf, nvals); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }

@@ -136,6 +136,9 @@ def test_fmm_c2_sampled(kind):
 
 
 def test_multi_density_and_determinism(c1):
+    """Four densities in one call are bitwise reproducible and each row matches the oracle; a
+    single density sums its direct part at the targets (every center here serves one target)
+    while the 4-density call forms coefficient rows, so they agree to rounding."""
     q, _ = _ctx(c1, p_qbx=8, p_fmm=30)
     dens = np.stack([gi.fourier_density(c1, seed=s) for s in range(4)])
     out = q.eval(1, _dev(dens)).cpu().numpy()
@@ -143,7 +146,8 @@ def test_multi_density_and_determinism(c1):
     assert np.array_equal(out, again), "evaluation is not bitwise deterministic"
     for j in range(4):
         single = q.eval(1, _dev(dens[j])).cpu().numpy()
-        assert np.array_equal(single, out[j])
+        assert np.array_equal(single, q.eval(1, _dev(dens[j])).cpu().numpy())
+        assert _rel(single, out[j]) < 1e-13
         ref = oracle.qbx_eval(c1, 1, dens[j], p_qbx=8)
         assert _rel(out[j], ref) < 1e-10
 
@@ -189,9 +193,9 @@ def test_empty_batch_and_errors(c1):
 def test_density_batches_match_single_evaluations(c1):
     """134 densities (two launches of the batch dimension: 128, then 6), padded row strides, S - D
     kind: each row equals the single-density evaluation to rounding (a batch of 8 or more slots
-    runs M2L and the Stage 7 gather as GEMMs over the slots, which sum in another order; a batch
-    of 6 runs the single-slot kernels, bitwise equal), the batch is bitwise reproducible, and the
-    last row matches the oracle within the gate."""
+    runs M2L and the Stage 7 gather as GEMMs over the slots, which sum in another order; a
+    single density sums its direct part at the targets, the batches form coefficient rows), the
+    batch is bitwise reproducible, and the last row matches the oracle within the gate."""
     q, _ = _ctx(c1, p_qbx=8, p_fmm=30)
     n, pad = 134, 7
     rng = np.random.default_rng(3)
@@ -207,10 +211,7 @@ def test_density_batches_match_single_evaluations(c1):
     assert np.isnan(res[:, c1.n_tgt:]).all(), "wrote outside the output rows"
     for j in (0, 33, 127, 128, 133):
         single = q.eval(3, _dev(h1[j]), _dev(h2[j])).cpu().numpy()
-        if j >= 128:
-            assert np.array_equal(single, res[j, :c1.n_tgt])
-        else:
-            assert _rel(res[j, :c1.n_tgt], single) < 1e-14
+        assert _rel(res[j, :c1.n_tgt], single) < 1e-13
     again = torch.full_like(out, np.nan)
     q.eval(3, d1[:, :c1.n_src], d2[:, :c1.n_src], out=again[:, :c1.n_tgt])
     assert np.array_equal(again.cpu().numpy()[:, :c1.n_tgt], res[:, :c1.n_tgt])
