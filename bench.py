@@ -46,7 +46,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QBX-FMM targets/s at 1e-10 rel err, plain vs batched/mixed/learned, 1 GPU"
 GATE = 1e-10
 # kernels of each stage in a GQ_S_AND_D evaluation of one density
-KERNEL_OF_STAGE = {"near": "k_near_sd_t", "m2qbxl": "k_m2qbxl_packed", "qbx_center": "k_qbx_center",
+KERNEL_OF_STAGE = {"near": "k_near_sd_t<4, 12>", "m2qbxl": "k_m2qbxl_packed", "qbx_center": "k_qbx_center",
                    "m2l_p2l": "k_m2l_mb", "m2m": "k_m_reduce", "l2l": "k_l2l_gather",
                    "p2m": "k_p2m_all", "gather": "k_gather", "finalize": "k_finalize"}
 
