@@ -1715,7 +1715,7 @@ __global__ void __launch_bounds__(64, PQ <= 12 ? 3 : 2) k_near_sd(
 // direct part of a center's expansion is then needed at one point only, x, and is summed there:
 // for a source y of charge q and dipole strength d, with z = y - c and rho = (x - c)/z,
 //   S: q (log|z| - Re sum_{k=1..p} rho^k / k),   D: Re((d / z) sum_{k=0..p} rho^k),
-// the truncated series of the coefficient rows of k_near_sd, summed in another order. Both
+// the truncated series of the coefficient rows of k_near / k_near_sd, summed in another order. Both
 // polynomials have real coefficients, so each is evaluated at the complex point rho by the
 // second-order recurrence for real polynomials at a complex argument (Knuth, The Art of
 // Computer Programming, vol. 2, Sec. 4.6.4): with r1 = 2 Re rho and s = |rho|^2,
@@ -2584,7 +2584,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
 //     w = zeta/s_b: the box local (a series in (x - c_b)/s_b) shifted to c and truncated at the
 //     QBX order p, by U_0 = 1, U_k = (t + w) U_(k-1) - [k > p] C(k-1, p) t^(k-1-p) w^(p+1);
 //   M2QBXL from a List 3 far box d: a_0 (log|y| - Re sum_{m=1..p} rho^m / m)
-//     + Re sum_{k>=1} M_k (s_d/y)^k P_k(rho), y = c - c_d, rho = -zeta/y,
+//     + Re sum_{k>=1} M_k W_k, W_k = (s_d/y)^k P_k(rho), y = c - c_d, rho = -zeta/y,
 //     P_k(rho) = sum_{m<=p} C(k+m-1, m) rho^m: the multipole's Taylor series about c truncated
 //     at p, evaluated at x.
 // These are the coefficient forms of k_qbx_center and k_m2qbxl evaluated at x, summed in another
@@ -2593,7 +2593,7 @@ __global__ void __launch_bounds__(64) k_qbx_center(
 // box) in LDS and contracts them with the segment's expansion over the slots on the matrix cores:
 // rows the centers (RT tiles of 16, each B operand serving all of them), k the real and imaginary
 // parts of the coefficients (Re(b U) = b.x U.x - b.y U.y), columns 16 NT slots. Then the center's
-// direct rows are added and its target written.
+// direct values (nval) are added and its target written.
 template <int PQ, int NT, int RT, typename E>
 __global__ void __launch_bounds__(64) k_ctr_val(
     const int4 *__restrict__ items, const int32_t *__restrict__ wf_idx,
