@@ -471,6 +471,46 @@ def test_ragged_batch_matches_separate_contexts():
         c0 += g.n_ctr
 
 
+@pytest.mark.parametrize("nd", [1, 8])
+def test_forest_value_paths_match_separate_contexts(nd):
+    """S and D summed at the targets on a forest: three star geometries in one context (one
+    target per center, plus conventional targets with internal centers in one of them) against
+    a context per geometry, for one density (the one-density value pass) and for 8 (the batched
+    value passes, k_near_val_mfma and k_ctr_val): the same trees and work items, so the rows
+    agree to rounding; and the first geometry against the oracle."""
+    from paper_1801_04070_amd import GQ_S_AND_D, QBXFMM
+    geoms = gi.ragged_star_batch(n_geoms=3, seed=300, min_nodes=512, max_nodes=4096)
+    g1 = copy.copy(geoms[1])
+    pts = np.array([[0.2, 0.1], [2.5, -1.5], [-0.4, 0.9]])
+    g1.tgt_xy = np.concatenate([g1.tgt_xy, pts])
+    g1.tgt_ctr = np.concatenate([g1.tgt_ctr, np.full((3, 2), -1, np.int32)])
+    geoms[1] = g1
+    kw = dict(p_qbx=12, p_fmm=30)
+    qb = QBXFMM(0)
+    qb.set_geometry_batch(geoms)
+    qb.build(**kw)
+    dens = [np.stack([gi.fourier_density(g, seed=70 + 10 * i + j) for j in range(nd)])
+            for i, g in enumerate(geoms)]
+    db = _dev(np.concatenate(dens, axis=1))
+    out = qb.eval(GQ_S_AND_D, db if nd > 1 else db[0]).cpu().numpy().reshape(2, nd, -1)
+    t0 = 0
+    for i, g in enumerate(geoms):
+        q = QBXFMM(0)
+        q.set_geometry_from(g)
+        q.build(**kw)
+        ref = q.eval(GQ_S_AND_D, _dev(dens[i]) if nd > 1 else _dev(dens[i][0]))
+        ref = ref.cpu().numpy().reshape(2, nd, -1)
+        part = out[:, :, t0:t0 + g.n_tgt]
+        err = np.abs(part - ref).max() / np.abs(ref).max()
+        print(f"forest S_AND_D nd={nd} geometry {i}: {err:.2e} against its own context")
+        assert err <= 1e-13, (i, err)
+        if i == 0:
+            for kind in (1, 2):
+                o = oracle.qbx_eval(g, kind, dens[0][nd - 1], None, p_qbx=12)
+                assert _rel(part[kind - 1, nd - 1], o) < 1e-10, kind
+        t0 += g.n_tgt
+
+
 def test_s_and_d_concurrent_matches_separate(c1):
     """GQ_S_AND_D (S and D of the same densities through one expansion pipeline over two
     workspace halves) against separate S and D evaluations: every center here serves one
