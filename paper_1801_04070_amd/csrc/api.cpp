@@ -314,7 +314,7 @@ gq_status build_near_work(gq_ctx *ctx) {
           }
           const int32_t lane0 = (int32_t)qpair.size() / 4 - q_pair0;
           const int32_t u[4] = {(int32_t)(base[b] + (nchunks + j) * nc + (c - t.ctr_begin[b])),
-                                lane0, (int32_t)clen, 0};
+                                lane0, (int32_t)clen, (int32_t)c};
           qunit.insert(qunit.end(), u, u + 4);
           const int64_t co = t.ctr_order[c];
           for (int64_t e = 0; e < clen; ++e) {
@@ -352,7 +352,8 @@ gq_status build_near_work(gq_ctx *ctx) {
     }
     for (int32_t i = 0; ok && i < q[5]; ++i) {
       const int32_t *u = &qunit[4 * (q[4] + i)];
-      ok = u[0] >= 0 && u[0] < rows && u[1] >= 0 && u[2] >= 1 && u[1] + u[2] <= q[1];
+      ok = u[0] >= 0 && u[0] < rows && u[1] >= 0 && u[2] >= 1 && u[1] + u[2] <= q[1] &&
+           u[3] >= 0 && u[3] < (int32_t)ctx->nc;
     }
     if (!ok) return fail(ctx, GQ_EINVAL, "internal: packed List 3 far work list out of bounds");
   }
@@ -834,6 +835,7 @@ gq_status launch_kind_on(gq_ctx *ctx, hipStream_t s, int kind, const double *d1,
   ctx->d.L += (int64_t)slot0 * nb * P1;
   ctx->d.Lf += (int64_t)slot0 * nb * P1;
   ctx->d.anear += (int64_t)slot0 * ctx->n_near_rows * (ctx->params.p_qbx + 1);
+  ctx->d.nval += (int64_t)slot0 * ctx->n_near_rows;
   ctx->d.tv += (int64_t)slot0 * 2 * ctx->nt;
   ctx->stream = s;
   ctx->params.overlap = 0;

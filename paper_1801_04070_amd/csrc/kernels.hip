@@ -2385,18 +2385,27 @@ __global__ void __launch_bounds__(64) k_m2qbxl(
 // (y = c - c_d, s_d, r; fixed by the build) comes as one record, so a lane waits on no chain of
 // dependent loads. Each lane forms its pair's coefficients, then the units' lanes are summed in
 // lane order through LDS, kM2qBlock coefficients per pass, and every unit writes its row.
+// VAL (every center serves at most one target, no derivative at the targets): each lane
+// evaluates its pair's coefficients at the center's target instead (Horner in (x - c)/r, the
+// series k_qbx_center evaluates), and every unit writes the sum of its lanes' values, in lane
+// order, to nval: one double per (center, far chunk) row instead of p + 1 complex coefficients.
 constexpr int kM2qBlock = 8;
 
-template <int PQ, typename E>
+template <int PQ, typename E, bool VAL>
 __global__ void __launch_bounds__(64) k_m2qbxl_packed(
     const int4 *__restrict__ waves, const int32_t *__restrict__ slots,
     const double4 *__restrict__ geo, const int32_t *__restrict__ stage,
     const int4 *__restrict__ units, const E *__restrict__ M, int P1,
-    double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st) {
+    double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st,
+    const double2 *__restrict__ cxy, const double *__restrict__ cr,
+    const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
+    const double2 *__restrict__ txy, double *__restrict__ nval, int64_t nv_st) {
   HIP_DYNAMIC_SHARED(unsigned char, m2q_lds)
   int4 *us = reinterpret_cast<int4 *>(m2q_lds);                       // [64] unit records
-  E *Ms = reinterpret_cast<E *>(m2q_lds + 64 * sizeof(int4));           // staged multipoles
-  double2 *red = reinterpret_cast<double2 *>(m2q_lds + 64 * sizeof(int4));  // then [kM2qBlock][64]
+  double2 *zl = reinterpret_cast<double2 *>(m2q_lds + 64 * sizeof(int4));  // VAL: [64] per lane
+  unsigned char *body = m2q_lds + 64 * sizeof(int4) + (VAL ? 64 * sizeof(double2) : 0);
+  E *Ms = reinterpret_cast<E *>(body);                                // staged multipoles
+  double2 *red = reinterpret_cast<double2 *>(body);                   // then [kM2qBlock][64]
   const double2 *lt = g_log_tab;
   const int lane = threadIdx.x;
   M += (int64_t)blockIdx.y * box_st;
@@ -2404,7 +2413,21 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
   const int4 w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
   const int32_t pair0 = w0.x, npairs = w0.y, stage0 = w0.z, nstage = w0.w;
   const int32_t unit0 = w1.x, nunits = w1.y;
-  if (lane < nunits) us[lane] = units[unit0 + lane];
+  if (lane < nunits) {
+    const int4 un = units[unit0 + lane];
+    us[lane] = un;
+    if constexpr (VAL) {
+      // the unit's center (un.w) and its target: the point at which the unit's lanes evaluate
+      const int32_t c = un.w, g = c2t_start[c];
+      double2 z = make_double2(0.0, 0.0);
+      if (c2t_start[c + 1] > g) {
+        const double2 x = txy[c2t_slot[g] >> 1], cc = cxy[c];
+        const double ir = 1.0 / cr[c];
+        z = make_double2((x.x - cc.x) * ir, (x.y - cc.y) * ir);
+      }
+      for (int l = 0; l < un.z; ++l) zl[un.y + l] = z;
+    }
+  }
   for (int i = lane; i < nstage * P1; i += 64) {
     const int e = i / P1, k = i - e * P1;
     Ms[i] = M[(int64_t)stage[stage0 + e] * P1 + k];
@@ -2417,6 +2440,27 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
     const int slot = slots[pair0 + lane];
     const double4 g = geo[pair0 + lane];
     m2qbxl_add_geo<PQ, E>(alpha, make_double2(g.x, g.y), g.z, g.w, Ms + slot * P1, P1, lt);
+  }
+  if constexpr (VAL) {
+    double v = 0.0;
+    if (lane < npairs) {
+      const double2 z = zl[lane];
+      double2 sv = alpha[PQ];
+#pragma unroll
+      for (int m = PQ - 1; m >= 0; --m) sv = cfma(sv, z, alpha[m]);
+      v = sv.x;
+    }
+    double *rv = reinterpret_cast<double *>(body);
+    __syncthreads();  // the staged multipoles are no longer read
+    rv[lane] = v;
+    __syncthreads();
+    if (lane < nunits) {
+      const int4 un = us[lane];
+      double acc = rv[un.y];
+      for (int l = 1; l < un.z; ++l) acc += rv[un.y + l];
+      nval[(int64_t)blockIdx.y * nv_st + un.x] = acc;
+    }
+    return;
   }
 #pragma unroll
   for (int m0 = 0; m0 <= PQ; m0 += kM2qBlock) {
@@ -2556,8 +2600,8 @@ __global__ void __launch_bounds__(64) k_qbx_center(
   }
 
   // direct (P2QBXL) and List 3 far (M2QBXL) rows of this center, in chunk order; with
-  // n_val_chunks the box's first n_val_chunks[b] (direct) rows are values at the center's target
-  // in nval (k_near_sd_t)
+  // n_val_chunks the box's first n_val_chunks[b] rows are values at the center's target in nval:
+  // the direct rows (k_near_sd_t), or every row (the far ones from k_m2qbxl_packed, VAL)
   {
     const int32_t nbc = bctr1[b] - bctr0[b];
     const int32_t loc = c - bctr0[b];
@@ -3016,6 +3060,13 @@ inline bool near_values(const gq_ctx *ctx, int nd, int kind) {
          !ctx->eval_sp && (kind == 4 || nd == 1);
 }
 
+// Whether the List 3 far part is summed at the centers' targets too (k_m2qbxl_packed, VAL): the
+// direct pass is, and every List 3 far chunk is a packed unit (no k_m2qbxl items). The center
+// stage then reads one value per row, direct and far alike.
+inline bool m2q_values(const gq_ctx *ctx, int nd, int kind) {
+  return near_values(ctx, nd, kind) && ctx->n_far_items == 0;
+}
+
 // The three per-order stages of one order bucket.
 template <int KIND, int PQ, typename E>
 void launch_near_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
@@ -3101,18 +3152,21 @@ void launch_near_bucket_sd(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream
   launch_near_bucket<2, PQ, E>(ctx, bk, nd, s, S, d.anear + (int64_t)nd * S.row);
 }
 
+// vals: the packed List 3 far units as values at the centers' targets (m2q_values)
 template <int PQ, typename E>
 void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
-                          const Strides &S, const E *M) {
+                          const Strides &S, const E *M, bool vals) {
   auto &d = ctx->d;
   const int32_t nw = (int32_t)(bk.m2q1 - bk.m2q0);
   if (nw > 0) {
-    const size_t lds = 64 * sizeof(int4) +
+    const size_t lds = 64 * sizeof(int4) + (vals ? 64 * sizeof(double2) : 0) +
                        std::max(sizeof(E) * (size_t)ctx->m2q_stage_rows * (ctx->params.p_fmm + 1),
                                 sizeof(double2) * kM2qBlock * 64);
-    hipLaunchKernelGGL((k_m2qbxl_packed<PQ, E>), dim3(nw, nd), dim3(64), lds, s,
-                       d.m2q_wave + 2 * bk.m2q0, d.m2q_slot, d.m2q_geo, d.m2q_stage, d.m2q_unit,
-                       M, ctx->params.p_fmm + 1, d.anear, ctx->params.p_qbx + 1, S.box, S.row);
+    hipLaunchKernelGGL((vals ? k_m2qbxl_packed<PQ, E, true> : k_m2qbxl_packed<PQ, E, false>),
+                       dim3(nw, nd), dim3(64), lds, s, d.m2q_wave + 2 * bk.m2q0, d.m2q_slot,
+                       d.m2q_geo, d.m2q_stage, d.m2q_unit, M, ctx->params.p_fmm + 1, d.anear,
+                       ctx->params.p_qbx + 1, S.box, S.row, d.cxy, d.cr, d.c2t_start, d.c2t_slot,
+                       d.txy, d.nval, S.nv);
   }
   const int32_t n = (int32_t)(bk.far1 - bk.far0);
   const size_t lds = sizeof(E) * (size_t)ctx->far_chunk * (ctx->params.p_fmm + 1);
@@ -3123,9 +3177,11 @@ void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        S.box, S.row);
 }
 
+// n_val_chunks: per box, how many of its leading rows are values at the centers' targets
+// (nullptr: none)
 template <int KIND, int PQ, typename E>
 void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_t s,
-                          const Strides &S, const E *L, bool near_values) {
+                          const Strides &S, const E *L, const int32_t *n_val_chunks) {
   auto &d = ctx->d;
   const int32_t n = (int32_t)(bk.ctr1 - bk.ctr0);
   if (n > 0)
@@ -3134,7 +3190,7 @@ void launch_center_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
                        d.ctr_list + bk.ctr0, ctx->params.p_qbx + 1, ctx->params.p_qbx + 1, d.cxy,
                        d.cr, d.cbox, d.bc, d.blevel, d.level_side, L, ctx->params.p_fmm + 1,
                        d.l2q_binom, d.bctr0, d.bctr1, d.part_base, d.n_chunks,
-                       near_values ? d.n_near_chunks : nullptr, near_values ? d.nval : nullptr,
+                       n_val_chunks, n_val_chunks ? d.nval : nullptr,
                        d.anear, d.c2t_start, d.c2t_slot, d.txy, d.tv, S.box, S.row, S.tv,
                        ctx->eval_sp ? ctx->tnrm_dev : nullptr, S.nv);
 }
@@ -3245,12 +3301,13 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   e = hipStreamWaitEvent(side, ctx->ev_up, 0);
   if (e != hipSuccess) return e;
   const bool ctr_vals = center_at_targets(ctx, nd, SD);
+  const bool qvals = m2q_values(ctx, nd, KIND);
   if ((ctx->n_far_items > 0 || ctx->n_m2q_waves > 0) && !ctr_vals) {
     StageTimer st_(ctx, GQ_STAGE_M2QBXL, side);
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_m2qbxl_bucket<P, E>(ctx, bk, slots, side, S, M); break;
+  case P: launch_m2qbxl_bucket<P, E>(ctx, bk, slots, side, S, M, qvals); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }
@@ -3332,11 +3389,11 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
     }
   } else {
     StageTimer st_(ctx, GQ_STAGE_QBX_CENTER);
-    const bool nvals = near_values(ctx, nd, KIND);
+    const int32_t *nvc = qvals ? d.n_chunks : near_values(ctx, nd, KIND) ? d.n_near_chunks : nullptr;
     for (const OrderBucket &bk : ctx->buckets) {
       switch (bk.pq) {
 #define GQ_CASE(P) \
-  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf, nvals); break;
+  case P: launch_center_bucket<CK, P, E>(ctx, bk, slots, st, S, Lf, nvc); break;
         GQ_PQ_LIST(GQ_CASE)
 #undef GQ_CASE
       }

@@ -59,12 +59,12 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int,
     """Algorithmic flops and HBM bytes of one launch of each stage for one density; kind 4 (S and
     D of the same density, one pipeline) is the sum of the two kinds except for the direct
     interactions, whose pair geometry is formed once. The flops are the method's (coefficient
-    formation and evaluation) whatever the kernel's formulation; near_values: the direct pass
-    writes one double per (center, chunk) row and kind instead of the coefficient row (every
-    center serving one target)."""
+    formation and evaluation) whatever the kernel's formulation; near_values: the direct pass and
+    the List 3 far pass write one double per (center, chunk) row and kind instead of the
+    coefficient row, and the center stage reads those (every center serving one target)."""
     if kind == 4:
-        s = stage_work(stats, 1, p_qbx, p_fmm, n_slots)
-        d = stage_work(stats, 2, p_qbx, p_fmm, n_slots)
+        s = stage_work(stats, 1, p_qbx, p_fmm, n_slots, near_values)
+        d = stage_work(stats, 2, p_qbx, p_fmm, n_slots, near_values)
         out = {k: {"flops": s[k]["flops"] + d[k]["flops"], "bytes": s[k]["bytes"] + d[k]["bytes"],
                    "bound": s[k]["bound"]} for k in s}
         row = (p_qbx + 1) * 16
@@ -80,7 +80,7 @@ def stage_work(stats: dict, kind: int, p_qbx: int, p_fmm: int, n_slots: int,
     q, p = p_qbx, p_fmm
     P1, Q1 = p + 1, q + 1
     src_rec = {1: 24, 2: 32, 3: 40}[kind]
-    row = Q1 * 16
+    row = 8 if near_values else Q1 * 16  # a row: one value at the target, or the coefficients
     n_rows_near = stats["n_ctr"]  # at least one direct row per center
     out = {}
     out["near"] = {
