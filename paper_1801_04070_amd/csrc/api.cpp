@@ -168,7 +168,13 @@ gq_status build_near_work(gq_ctx *ctx) {
       citems;
   std::vector<int32_t> mitems;  // matrix-core direct items: (off, len, first center, first row), (n_ctr <= 4)
   std::vector<int32_t> qwave, qpair, qstage, qunit;
-  std::vector<double> qgeo;
+  std::vector<double> qgeo, quz;
+  // each center's first target (caller order): a packed unit carries (x - c)/r of its center's
+  // target, at which k_m2qbxl_packed evaluates when every center serves at most one target
+  std::vector<int64_t> first_tgt(ctx->nc, -1);
+  for (int64_t tg = ctx->nt - 1; tg >= 0; --tg)
+    for (int sd = 1; sd >= 0; --sd)
+      if (ctx->tgt_ctr[2 * tg + sd] >= 0) first_tgt[ctx->tgt_ctr[2 * tg + sd]] = tg;
 
   std::vector<double> lside = t.level_side_table;
   if (lside.empty())
@@ -314,9 +320,17 @@ gq_status build_near_work(gq_ctx *ctx) {
           }
           const int32_t lane0 = (int32_t)qpair.size() / 4 - q_pair0;
           const int32_t u[4] = {(int32_t)(base[b] + (nchunks + j) * nc + (c - t.ctr_begin[b])),
-                                lane0, (int32_t)clen, (int32_t)c};
+                                lane0, (int32_t)clen, 0};
           qunit.insert(qunit.end(), u, u + 4);
           const int64_t co = t.ctr_order[c];
+          double zx = 0.0, zy = 0.0;
+          if (first_tgt[co] >= 0) {
+            const int64_t tg = first_tgt[co];
+            const double ir = 1.0 / ctx->ctr_r[co];
+            zx = (ctx->tgt_xy[2 * tg] - ctx->ctr_xy[2 * co]) * ir;
+            zy = (ctx->tgt_xy[2 * tg + 1] - ctx->ctr_xy[2 * co + 1]) * ir;
+          }
+          quz.insert(quz.end(), {zx, zy});
           for (int64_t e = 0; e < clen; ++e) {
             const int32_t fb = t.list3f.idx[woff + c0 + e];
             const int32_t pr[4] = {(int32_t)c, fb, slot0 + (int32_t)e, 0};
@@ -352,8 +366,7 @@ gq_status build_near_work(gq_ctx *ctx) {
     }
     for (int32_t i = 0; ok && i < q[5]; ++i) {
       const int32_t *u = &qunit[4 * (q[4] + i)];
-      ok = u[0] >= 0 && u[0] < rows && u[1] >= 0 && u[2] >= 1 && u[1] + u[2] <= q[1] &&
-           u[3] >= 0 && u[3] < (int32_t)ctx->nc;
+      ok = u[0] >= 0 && u[0] < rows && u[1] >= 0 && u[2] >= 1 && u[1] + u[2] <= q[1];
     }
     if (!ok) return fail(ctx, GQ_EINVAL, "internal: packed List 3 far work list out of bounds");
   }
@@ -378,6 +391,7 @@ gq_status build_near_work(gq_ctx *ctx) {
   if (st == GQ_OK) st = upload(ctx, d.m2q_geo, qgeo.data(), qgeo.size() / 4);
   if (st == GQ_OK) st = upload(ctx, d.m2q_stage, qstage.data(), qstage.size());
   if (st == GQ_OK) st = upload(ctx, d.m2q_unit, qunit.data(), qunit.size() / 4);
+  if (st == GQ_OK) st = upload(ctx, d.m2q_uz, quz.data(), quz.size() / 2);
   if (st == GQ_OK) st = upload(ctx, d.bctr0, bctr0.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.bctr1, bctr1.data(), nb);
   if (st == GQ_OK) st = upload(ctx, d.part_base, base.data(), nb);

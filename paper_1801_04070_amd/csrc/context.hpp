@@ -80,6 +80,7 @@ struct DevBuffers {
   double4 *m2q_geo = nullptr;
   int32_t *m2q_stage = nullptr;
   int4 *m2q_unit = nullptr;
+  double2 *m2q_uz = nullptr;  // per packed unit: (x - c)/r of its center's target
   int32_t *bctr0 = nullptr, *bctr1 = nullptr;   // owned center range per box
   int32_t *part_base = nullptr;      // first near row of each box
   int32_t *n_chunks = nullptr;       // source chunks (rows per center) of each box

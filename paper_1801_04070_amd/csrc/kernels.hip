@@ -2397,9 +2397,7 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
     const double4 *__restrict__ geo, const int32_t *__restrict__ stage,
     const int4 *__restrict__ units, const E *__restrict__ M, int P1,
     double2 *__restrict__ anear, int rs, int64_t box_st, int64_t row_st,
-    const double2 *__restrict__ cxy, const double *__restrict__ cr,
-    const int32_t *__restrict__ c2t_start, const int32_t *__restrict__ c2t_slot,
-    const double2 *__restrict__ txy, double *__restrict__ nval, int64_t nv_st) {
+    const double2 *__restrict__ uz, double *__restrict__ nval, int64_t nv_st) {
   HIP_DYNAMIC_SHARED(unsigned char, m2q_lds)
   int4 *us = reinterpret_cast<int4 *>(m2q_lds);                       // [64] unit records
   double2 *zl = reinterpret_cast<double2 *>(m2q_lds + 64 * sizeof(int4));  // VAL: [64] per lane
@@ -2417,14 +2415,8 @@ __global__ void __launch_bounds__(64) k_m2qbxl_packed(
     const int4 un = units[unit0 + lane];
     us[lane] = un;
     if constexpr (VAL) {
-      // the unit's center (un.w) and its target: the point at which the unit's lanes evaluate
-      const int32_t c = un.w, g = c2t_start[c];
-      double2 z = make_double2(0.0, 0.0);
-      if (c2t_start[c + 1] > g) {
-        const double2 x = txy[c2t_slot[g] >> 1], cc = cxy[c];
-        const double ir = 1.0 / cr[c];
-        z = make_double2((x.x - cc.x) * ir, (x.y - cc.y) * ir);
-      }
+      // (x - c)/r of the unit's center's target (fixed by the build): where its lanes evaluate
+      const double2 z = uz[unit0 + lane];
       for (int l = 0; l < un.z; ++l) zl[un.y + l] = z;
     }
   }
@@ -3165,8 +3157,7 @@ void launch_m2qbxl_bucket(gq_ctx *ctx, const OrderBucket &bk, int nd, hipStream_
     hipLaunchKernelGGL((vals ? k_m2qbxl_packed<PQ, E, true> : k_m2qbxl_packed<PQ, E, false>),
                        dim3(nw, nd), dim3(64), lds, s, d.m2q_wave + 2 * bk.m2q0, d.m2q_slot,
                        d.m2q_geo, d.m2q_stage, d.m2q_unit, M, ctx->params.p_fmm + 1, d.anear,
-                       ctx->params.p_qbx + 1, S.box, S.row, d.cxy, d.cr, d.c2t_start, d.c2t_slot,
-                       d.txy, d.nval, S.nv);
+                       ctx->params.p_qbx + 1, S.box, S.row, d.m2q_uz, d.nval, S.nv);
   }
   const int32_t n = (int32_t)(bk.far1 - bk.far0);
   const size_t lds = sizeof(E) * (size_t)ctx->far_chunk * (ctx->params.p_fmm + 1);
