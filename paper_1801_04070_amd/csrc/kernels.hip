@@ -119,8 +119,8 @@ __device__ __forceinline__ double lane_xor1(double v) { return dpp_mov<0xB1>(v);
 // the sources of its subtree (contiguous in tree order). In 2-D, M2M keeps the first p + 1
 // moments of a box exact (coefficient m of the parent depends only on the children's
 // coefficients k <= m), so these are the multipoles the level-by-level pass builds, up to
-// rounding. One work item = one box and up to 256 of its sources; a box with more sources is
-// split into several items whose partial sums k_m_reduce adds in item order.
+// rounding. One work item = one box and up to 512 of its sources; a box with more sources is
+// split into several items whose partial sums k_m_reduce adds in a fixed order.
 // Lanes: NBLK blocks of 8 consecutive orders (k = 8 kb + i) times 64 / NBLK source groups. A lane
 // walks the sources of its group, forms y^(8 kb) by repeated squaring and the block's powers by a
 // chain of complex multiplies, and accumulates A_k = sum q y^k and B_k = sum d y^k in registers;
@@ -228,38 +228,56 @@ __global__ void __launch_bounds__(64) k_p2m_all(
   }
 }
 
-// Sum of a split box's partial moments (one wavefront per box): sixteen running sums over the
-// partials p = 0..15 (mod 16), their loads issued together (clamped to the last partial, extra
-// values unused), then combined by a fixed pairwise tree, so the result is deterministic.
+// Sum of a split box's partial moments, one work-group of kRedWaves wavefronts per box: the
+// partials are taken in chunks of 16 (chunk c by wavefront c mod kRedWaves), each lane holding
+// sixteen running sums of one coefficient (one per position in a chunk, their loads issued
+// together, clamped to the last partial, extra values unused); the sixteen are combined by a
+// fixed pairwise tree and the wavefronts' sums in wavefront order through LDS, so the result is
+// deterministic, and the largest box waits on a quarter of the dependent loads of one wavefront.
+constexpr int kRedWaves = 4;
+
 template <int NK, typename E>
-__global__ void __launch_bounds__(64) k_m_reduce(const int4 *__restrict__ red,
-                                                 const double2 *__restrict__ Mp, int P1,
-                                                 E *__restrict__ M, int64_t part_st,
-                                                 int64_t box_st, int64_t d_off) {
+__global__ void __launch_bounds__(64 * kRedWaves) k_m_reduce(const int4 *__restrict__ red,
+                                                            const double2 *__restrict__ Mp,
+                                                            int P1, E *__restrict__ M,
+                                                            int64_t part_st, int64_t box_st,
+                                                            int64_t d_off) {
   critical_path_priority();
+  __shared__ double2 wsum[kRedWaves][64];
   const int4 it = red[blockIdx.x];  // box, first partial, end of partials
   const int64_t jd = blockIdx.y;
   Mp += jd * part_st;
   M += jd * box_st;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int U = 16;
-  for (int r = threadIdx.x; r < NK * P1; r += 64) {
+  for (int r0 = 0; r0 < NK * P1; r0 += 64) {
+    const int r = r0 + lane;
     double2 a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) a[u] = make_double2(0.0, 0.0);
-    for (int32_t p = it.y; p < it.z; p += U) {
+    if (r < NK * P1)
+      for (int32_t p = it.y + U * wv; p < it.z; p += U * kRedWaves) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t q = p + u;
-        const double2 v = Mp[(int64_t)(q < it.z ? q : it.z - 1) * 2 * P1 + r];
-        if (q < it.z) a[u] = cadd(a[u], v);
+        for (int u = 0; u < U; ++u) {
+          const int32_t q = p + u;
+          const double2 v = Mp[(int64_t)(q < it.z ? q : it.z - 1) * 2 * P1 + r];
+          if (q < it.z) a[u] = cadd(a[u], v);
+        }
       }
-    }
 #pragma unroll
     for (int w = U / 2; w >= 1; w >>= 1)
 #pragma unroll
       for (int u = 0; u < w; ++u) a[u] = cadd(a[u], a[u + w]);
-    if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(a[0]);
-    else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(a[0]);
+    wsum[wv][lane] = a[0];
+    __syncthreads();
+    if (wv == 0 && r < NK * P1) {
+      double2 sum = wsum[0][lane];
+#pragma unroll
+      for (int w = 1; w < kRedWaves; ++w) sum = cadd(sum, wsum[w][lane]);
+      if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(sum);
+      else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(sum);
+    }
+    __syncthreads();  // wsum is written again for the next 64 coefficients
   }
 }
 
@@ -3283,7 +3301,7 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   if (ctx->n_p2m_red > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    hipLaunchKernelGGL((k_m_reduce<NK, E>), dim3((uint32_t)ctx->n_p2m_red, nd), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_m_reduce<NK, E>), dim3((uint32_t)ctx->n_p2m_red, nd), dim3(64 * kRedWaves), 0, st,
                        d.p2m_red, d.Mp, P1, M, part_st, S.box, (int64_t)nd * S.box);
   }
   e = hipEventRecord(ctx->ev_up, st);
