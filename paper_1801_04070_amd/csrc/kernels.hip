@@ -228,22 +228,21 @@ __global__ void __launch_bounds__(64) k_p2m_all(
   }
 }
 
-// Sum of a split box's partial moments, one work-group of kRedWaves wavefronts per box: the
-// partials are taken in chunks of 16 (chunk c by wavefront c mod kRedWaves), each lane holding
-// sixteen running sums of one coefficient (one per position in a chunk, their loads issued
-// together, clamped to the last partial, extra values unused); the sixteen are combined by a
-// fixed pairwise tree and the wavefronts' sums in wavefront order through LDS, so the result is
-// deterministic, and the largest box waits on a quarter of the dependent loads of one wavefront.
-constexpr int kRedWaves = 4;
-
-template <int NK, typename E>
-__global__ void __launch_bounds__(64 * kRedWaves) k_m_reduce(const int4 *__restrict__ red,
+// Sum of a split box's partial moments, one work-group of W wavefronts per box: the partials are
+// taken in chunks of 16 (chunk c by wavefront c mod W), each lane holding sixteen running sums of
+// one coefficient (one per position in a chunk, their loads issued together, clamped to the last
+// partial, extra values unused); the sixteen are combined by a fixed pairwise tree and the
+// wavefronts' sums in wavefront order through LDS, so the result is deterministic. W = 4 for one
+// density (the largest box waits on a quarter of the dependent loads of one wavefront), 1 for
+// batches (grid.y already holds the densities, and most split boxes have few partials).
+template <int NK, int W, typename E>
+__global__ void __launch_bounds__(64 * W) k_m_reduce(const int4 *__restrict__ red,
                                                             const double2 *__restrict__ Mp,
                                                             int P1, E *__restrict__ M,
                                                             int64_t part_st, int64_t box_st,
                                                             int64_t d_off) {
   critical_path_priority();
-  __shared__ double2 wsum[kRedWaves][64];
+  __shared__ double2 wsum[W][64];
   const int4 it = red[blockIdx.x];  // box, first partial, end of partials
   const int64_t jd = blockIdx.y;
   Mp += jd * part_st;
@@ -256,7 +255,7 @@ __global__ void __launch_bounds__(64 * kRedWaves) k_m_reduce(const int4 *__restr
 #pragma unroll
     for (int u = 0; u < U; ++u) a[u] = make_double2(0.0, 0.0);
     if (r < NK * P1)
-      for (int32_t p = it.y + U * wv; p < it.z; p += U * kRedWaves) {
+      for (int32_t p = it.y + U * wv; p < it.z; p += U * W) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t q = p + u;
@@ -273,7 +272,7 @@ __global__ void __launch_bounds__(64 * kRedWaves) k_m_reduce(const int4 *__restr
     if (wv == 0 && r < NK * P1) {
       double2 sum = wsum[0][lane];
 #pragma unroll
-      for (int w = 1; w < kRedWaves; ++w) sum = cadd(sum, wsum[w][lane]);
+      for (int w = 1; w < W; ++w) sum = cadd(sum, wsum[w][lane]);
       if (r < P1) M[(int64_t)it.x * P1 + r] = from_d2<E>(sum);
       else M[d_off + (int64_t)it.x * P1 + (r - P1)] = from_d2<E>(sum);
     }
@@ -3301,7 +3300,9 @@ hipError_t launch_fmm_t(gq_ctx *ctx, int nd) {
   }
   if (ctx->n_p2m_red > 0) {
     StageTimer st_(ctx, GQ_STAGE_M2M);
-    hipLaunchKernelGGL((k_m_reduce<NK, E>), dim3((uint32_t)ctx->n_p2m_red, nd), dim3(64 * kRedWaves), 0, st,
+    const bool few = nd < kNearMfmaMin;
+    hipLaunchKernelGGL((few ? k_m_reduce<NK, 4, E> : k_m_reduce<NK, 1, E>),
+                       dim3((uint32_t)ctx->n_p2m_red, nd), dim3(few ? 256 : 64), 0, st,
                        d.p2m_red, d.Mp, P1, M, part_st, S.box, (int64_t)nd * S.box);
   }
   e = hipEventRecord(ctx->ev_up, st);
