@@ -227,9 +227,10 @@ gq_status gq_set_target_normals(gq_ctx *ctx, int mem, int64_t n_tgt, const doubl
  *                       pipeline over two workspace halves (S, D): the stages that only move
  *                       expansions run once for both kinds, and the direct interactions of both
  *                       kinds share their pair geometry. When every center serves at most one
- *                       target, the direct part of each center's expansion (and, for 8 or more
- *                       densities, its box parts L2QBXL and M2QBXL) is summed at that target
- *                       instead of formed as coefficients: the same truncated series in another
+ *                       target, the direct and List 3 far (M2QBXL) parts of each center's
+ *                       expansion (and, for 8 or more densities, its box local, L2QBXL) are
+ *                       summed at that target instead of formed as coefficients (GQ_S and GQ_D
+ *                       of one density likewise): the same truncated series in another
  *                       order, so S and D agree with GQ_S and GQ_D to rounding (about 1e-14),
  *                       not bitwise. The direct-QBX path (gq_eval_direct) runs the two kinds on
  *                       two library streams forked from and joined back to the context's stream
